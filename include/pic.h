@@ -1,0 +1,247 @@
+/*
+ * pic.h -- C ABI of the MI355X laser-dielectric particle-in-cell hot path.
+ *
+ * The library advances the particle-in-cell method of arXiv 2502.13695
+ * ("A Fully Three-Dimensional Kinetic Particle-In-Cell Framework for Modeling
+ * Laser-Dielectric Interactions: Few-Cycle Pulse Damage") on one AMD MI355X:
+ * Yee field solve with a spatially varying permittivity (Sec. 2.3), shape-
+ * function gather, relativistic Boris push, Esirkepov current deposit,
+ * one-cycle rolling field-amplitude window and Keldysh photoionization with
+ * Monte-Carlo single ionization of neutral molecule macroparticles (Sec. 2.1),
+ * driven by a laser entering through the x_min boundary (Sec. 3).
+ *
+ * Conventions for every call:
+ *  - Return value: PIC_OK (0) or a negative pic_status.  No exception or
+ *    signal crosses the ABI.  A NULL pointer where one is required gives
+ *    PIC_E_INVAL.
+ *  - Host pointers are plain host memory owned by the caller; the library
+ *    copies what it needs before returning.  Device memory is owned by the
+ *    library (through the allocator callbacks of pic_config when given, else
+ *    hipMalloc) and released by pic_destroy.
+ *  - A context is bound to one HIP stream (pic_config.stream, NULL = the
+ *    default stream) and must be used from one host thread at a time.
+ *  - Work is enqueued asynchronously; pic_diag synchronises the stream.
+ *  - Errors latch: after PIC_E_NUMERIC or PIC_E_CAPACITY only pic_diag and
+ *    pic_destroy are accepted.
+ *  - Units are SI unless stated.  The propagation axis is x (index 0); the
+ *    laser enters at x = 0.  Transverse axes are y, z.
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PIC_ABI_VERSION 1u
+
+typedef enum {
+  PIC_OK = 0,
+  PIC_E_INVAL = -1,     /* bad argument or configuration */
+  PIC_E_NOMEM = -2,     /* device allocation failed */
+  PIC_E_DEVICE = -3,    /* HIP runtime error */
+  PIC_E_STATE = -4,     /* call not valid in the current state (latched error) */
+  PIC_E_NUMERIC = -5,   /* non-finite field or particle value detected */
+  PIC_E_CAPACITY = -6,  /* charged-particle buffer full */
+  PIC_E_VERSION = -7    /* struct_size / abi_version mismatch */
+} pic_status;
+
+typedef struct pic_ctx pic_ctx;
+typedef struct pic_batch pic_batch;
+
+/* One dielectric (paper Table 1): band gap [eV], linear refractive index n
+ * (eps_r = n^2, Sec. 2.3), mass density [g/cm^3], molar mass [g/mol] (gives the
+ * molecular density n0 = rho N_A / M), effective hole and electron masses in
+ * units of m_e (reduced mass m* = 1/(1/m_e* + 1/m_h*), Sec. 3.2).  Ionized
+ * electrons carry m_e* (Sec. 3.2).  pos_mass_kg: mass of the positive carrier
+ * born with each electron; 0 selects the molecule mass M / N_A. */
+typedef struct {
+  double gap_eV, n_index, density_gcc, molar_mass_gmol, me_star, mh_star, pos_mass_kg;
+} pic_material;
+
+/* Optical region (Sec. 2.3): material `material` fills lo_m <= x < hi_m across
+ * the whole transverse extent.  The first matching layer wins; no layer means
+ * vacuum.  The same predicate places the neutral molecules (at cell centres)
+ * and the permittivity (at each E component's own staggered position). */
+typedef struct {
+  int32_t material;
+  int32_t reserved;
+  double lo_m, hi_m;
+} pic_layer;
+
+enum { PIC_ENV_GAUSS = 0, PIC_ENV_SIN2 = 1 };
+
+/* Laser pulse entering at x = 0 (Sec. 3).  Field at the boundary:
+ *   E(t) = E0 env(t) cos(omega (t - t_peak) + cep)  x  exp(-r^2 / waist^2)
+ * with env = exp(-2 ln2 (t - t_peak)^2 / fwhm^2) (PIC_ENV_GAUSS) or sin^2 with
+ * intensity FWHM fwhm (PIC_ENV_SIN2, Sec. 3).  Peak intensity I0 from
+ * peak_Wcm2, or from fluence_Jcm2 > 0 as I0 = F / int(env^2 dt) (peak on-axis
+ * fluence F = 2 E_las / (pi w0^2), Sec. 3); E0 = sqrt(2 I0 / (c eps0)).
+ * t_peak_s = 0 selects 3 fwhm (Gaussian) or the sin^2 centre.  waist_m = 0 is
+ * a plane wave.  pol_axis: 1 = y, 2 = z. */
+typedef struct {
+  double lambda_m, fwhm_s, peak_Wcm2, fluence_Jcm2, waist_m, t_peak_s, cep_rad;
+  int32_t envelope, pol_axis;
+} pic_laser;
+
+enum { PIC_BC_OUTFLOW = 0, PIC_BC_PERIODIC = 1 };
+
+/* Run configuration.  Copied by pic_init; the caller keeps ownership. */
+typedef struct {
+  uint32_t struct_size;        /* sizeof(pic_config) */
+  uint32_t abi_version;        /* PIC_ABI_VERSION */
+  int32_t ndim;                /* 1, 2 or 3 */
+  int32_t transverse_bc;       /* PIC_BC_OUTFLOW (Sec. 3.1) or PIC_BC_PERIODIC */
+  int64_t n[3];                /* cells per axis (unused axes ignored) */
+  double dx_m[3];              /* cell size per axis [m] */
+  double cfl;                  /* fraction of the CFL limit (Sec. 3.1: 0.95) */
+  int64_t nsteps;              /* planned steps (sizes the laser source table) */
+  int32_t nmat, nlayer;
+  const pic_material* mats;
+  const pic_layer* layers;
+  int32_t ppc;                 /* neutral macroparticles per material cell (Sec. 3.1) */
+  int32_t shape_order;         /* 1 or 2 (B-spline order of the particle shape) */
+  double T_K;                  /* neutral temperature (Sec. 3.1: 300 K) */
+  int32_t keldysh_terms;       /* terms of the Eq. (3) series (Sec. 2.1: 500) */
+  int32_t reserved0;
+  uint64_t seed;               /* Philox key */
+  pic_laser laser;
+  int64_t particle_capacity;   /* charged-particle slots; 0 = 2 x neutrals + 4096 */
+  double preionize_eV;         /* >0: every neutral starts ionized, carriers thermal at
+                                  this temperature (charged-loop stress variant) */
+  void* stream;                /* hipStream_t, or NULL for the default stream */
+  void* (*alloc)(size_t bytes, void* user);   /* optional device allocator */
+  void (*free)(void* ptr, void* user);
+  void* alloc_user;
+} pic_config;
+
+/* Canonical discrete problem derived from a configuration (host-only query).
+ * dt is the largest value with c dt / dx_0 an FP32 number not above the
+ * requested fraction of the CFL limit (Sec. 3.1); Cd[d] = c dt / dx_d and
+ * kmur[d] = (Cd - 1)/(Cd + 1) are FP32 numbers; ie[m] = 1/n_m^2 as FP32;
+ * nwin = ceil(lambda / (c dt)) samples make one laser cycle (Sec. 2.1). */
+typedef struct {
+  double dt;
+  double Cd[3];
+  double kmur[3];
+  double ie[8];
+  int64_t nwin;
+  double E0;                   /* peak boundary field [V/m] */
+  double t_peak;               /* envelope centre [s] */
+  double amp_cut[8];           /* per material: amplitudes below cannot ionize [V/m] */
+  double amp_sat[8];           /* per material: amplitudes above ionize with P = 1 */
+  int64_t n_neutral;           /* neutral macroparticles loaded */
+  int64_t capacity;            /* charged slots */
+} pic_params;
+
+/* Diagnostic kinds for pic_diag.  Grids are FP64 unless stated, on the
+ * positions inside the box, x fastest. */
+enum {
+  PIC_DIAG_SCALARS = 0,   /* double[16], see PIC_SC_* */
+  PIC_DIAG_FIELDS = 1,    /* double: Ex, Ey, Ez, bx, by, bz (b = cB) on their own
+                             staggered positions; per component the shape is
+                             n_d (half-integer or periodic axis) or n_d + 1 */
+  PIC_DIAG_NE_GRID = 2,   /* electron number density at nodes [m^-3] (Sec. 4.1) */
+  PIC_DIAG_UE_GRID = 3,   /* electron kinetic energy density at nodes [J/m^3] (Sec. 4.2) */
+  PIC_DIAG_EVENTS = 4,    /* int64 pairs (neutral id, step) of every ionization so far */
+  PIC_DIAG_PARTICLES = 5, /* pic_particle records of live charged particles */
+  PIC_DIAG_PARAMS = 6,    /* one pic_params */
+  PIC_DIAG_AMP = 7,       /* float: windowed amplitude A at nodes [V/m] */
+  PIC_DIAG_TIMERS = 8     /* double[8]: ms spent in the step phases (if timing on) */
+};
+
+/* PIC_DIAG_SCALARS layout (all double). */
+enum {
+  PIC_SC_STEP = 0, PIC_SC_TIME = 1, PIC_SC_N_NEUTRAL = 2, PIC_SC_N_E = 3, PIC_SC_N_POS = 4,
+  PIC_SC_EVENTS = 5, PIC_SC_U_FIELD = 6, PIC_SC_KE_E = 7, PIC_SC_KE_POS = 8,
+  PIC_SC_E_GAP = 9, PIC_SC_E_ABS = 10, PIC_SC_GAUSS_MAX = 11, PIC_SC_RHO_MAX = 12,
+  PIC_SC_HEALTH = 13, PIC_SC_SLOTS = 14, PIC_SC_COUNT = 16
+};
+
+/* A charged macroparticle: cell indices, FP32 offsets in [0, 1) (position =
+ * cell + offset, in cells), u = gamma v / c, kind = 2 * material (electron) or
+ * 2 * material + 1 (positive carrier). */
+typedef struct {
+  int32_t cell[3];
+  int32_t kind;
+  float off[3];
+  float u[3];
+} pic_particle;
+
+/* State written by pic_set_state: E and b (FP32, layout of PIC_DIAG_FIELDS),
+ * the charged particles, and the step index.  Neutrals and the amplitude
+ * window keep their values unless reset_window != 0 (window cleared). */
+typedef struct {
+  int64_t step;
+  const float* E[3];
+  const float* b[3];
+  int64_t n_particles;
+  const pic_particle* particles;
+  int32_t reset_window;
+  int32_t reserved;
+} pic_state;
+
+/* Create a context: canonicalise the configuration, build the FP64 Keldysh
+ * rate table per material (Sec. 2.1, Eq. 1-3), allocate device state, load the
+ * neutrals (Sec. 3.1).  Returns PIC_E_VERSION on a struct_size/abi_version
+ * mismatch, PIC_E_INVAL on a bad configuration, PIC_E_NOMEM / PIC_E_DEVICE. */
+pic_status pic_init(const pic_config* cfg, pic_ctx** out);
+
+/* Enqueue nsteps time steps (Sec. 1-2 loop: gather, push, deposit, field
+ * update, amplitude window, ionization).  Asynchronous on the context stream. */
+pic_status pic_step(pic_ctx* c, int64_t nsteps);
+
+/* Copy a diagnostic into host_out (out_bytes available); *written gets the
+ * byte count.  host_out == NULL queries the size only.  Synchronous.
+ * Returns PIC_E_INVAL if out_bytes is too small. */
+pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size_t* written);
+
+/* Overwrite fields, charged particles and step index (parity tests, restarts). */
+pic_status pic_set_state(pic_ctx* c, const pic_state* s);
+
+/* Device bytes pic_init would allocate for this configuration (admission
+ * control).  Host-only. */
+pic_status pic_footprint(const pic_config* cfg, size_t* bytes);
+
+/* Canonical parameters of a configuration without creating a context.
+ * Host-only (no GPU needed). */
+pic_status pic_canonical(const pic_config* cfg, pic_params* out);
+
+/* FP64 Keldysh rate W(A) [m^-3 s^-1] of Eq. (2)-(3) for n amplitudes A [V/m]
+ * with `terms` series terms, as the table builder evaluates it.  Host-only. */
+pic_status pic_keldysh_rate(const pic_material* m, double lambda_m, int32_t terms,
+                            const double* A, int64_t n, double* W_out);
+
+/* Per-step ionization probability P(A) = 1 - exp(-W dt / n0) for material
+ * `mat` of `cfg`, looked up in the FP32 table exactly as the device does, for
+ * n FP32 amplitudes.  Host-only (builds the table on the host). */
+pic_status pic_table_probe(const pic_config* cfg, int32_t mat, const float* A, int64_t n,
+                           float* P_out);
+
+/* The same lookup executed on the device of context c (host in/out buffers). */
+pic_status pic_table_probe_device(pic_ctx* c, int32_t mat, const float* A, int64_t n,
+                                  float* P_out);
+
+/* Batching of independent instances (fluence scans): one launch per phase
+ * advances every member.  Members keep their own step counters; a member
+ * added with pic_batch_add joins at the next step boundary. */
+pic_status pic_batch_create(pic_ctx* const* members, int32_t n, pic_batch** out);
+pic_status pic_batch_step(pic_batch* b, int64_t nsteps);
+pic_status pic_batch_add(pic_batch* b, pic_ctx* c);
+pic_status pic_batch_remove(pic_batch* b, pic_ctx* c);
+void pic_batch_destroy(pic_batch* b);
+
+/* Per-step device time of the phases (hip events), off by default. */
+pic_status pic_set_timing(pic_ctx* c, int32_t on);
+
+void pic_destroy(pic_ctx* c);
+const char* pic_status_str(pic_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIC_H */

@@ -1,0 +1,50 @@
+// Host-side FP64 math of the PIC library: canonical discrete problem, laser
+// source, Keldysh rate (Sec. 2.1, Eq. 1-3) and its FP32 lookup table.
+#pragma once
+
+#include <vector>
+
+#include "pic.h"
+#include "pic_common.h"
+
+namespace pic {
+
+struct MatC {
+  double gap_eV, n_index, n0, mred, mol_kg, e_kg, p_kg;
+  float ie;
+};
+
+struct Canon {
+  int D;
+  int64_t n[3];
+  double dx[3];
+  bool per[3];
+  double dt;
+  float C[3], kmur[3];
+  int nwin;
+  int nmat;
+  MatC mats[MAXMAT];
+  double vcell;
+  int ppc;
+  // laser
+  double lam, omega, fwhm, t0, T, waist, cep, I0, E0, env2;
+  int env, pol;
+  std::vector<signed char> mat_cell;   // per cell x index
+  std::vector<signed char> mat_node;   // per node x index
+};
+
+pic_status canonicalize(const pic_config* cfg, Canon* out);
+double laser_field(const Canon& c, double t);
+double transverse_profile(const Canon& c, double y, double z);
+
+// Keldysh volumetric rate W(A) [m^-3 s^-1], FP64, `terms` terms of Eq. (3).
+double keldysh_W(const MatC& m, double lam, int terms, double A);
+
+struct TableHost {
+  std::vector<unsigned char> bytes;   // TabHdr, TabSeg[], coefficients
+  float acut = 0.f, asat = 0.f;
+};
+// Table of P(A) = 1 - exp(-W dt / n0) for material `mat`.
+pic_status build_table(const Canon& c, int mat, int terms, TableHost* out);
+
+}  // namespace pic

@@ -1,0 +1,161 @@
+// Shared definitions of the MI355X PIC library: the per-instance parameter
+// block the kernels read, the Philox4x32-10 generator and the FP32 Keldysh
+// table lookup (both usable on host and device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pic {
+
+constexpr int G = 3;             // guard layers per side of every present axis
+constexpr int MAXMAT = 8;
+constexpr int MAXKIND = 2 * MAXMAT;
+constexpr uint8_t DEAD = 0xFF;   // kind of an empty charged slot
+
+// Health bits (latched in device memory, read by the diagnostics)
+constexpr unsigned HEALTH_CAPACITY = 1u;
+constexpr unsigned HEALTH_NONFINITE = 2u;
+
+// Philox draw purposes (fourth counter word)
+constexpr uint32_t PURPOSE_POS = 1, PURPOSE_VEL = 2, PURPOSE_IONIZE = 3,
+                   PURPOSE_STRESS_E = 4, PURPOSE_STRESS_P = 5;
+
+// ---------------------------------------------------------------- Philox
+// Philox4x32-10 (Salmon et al., SC'11): counter (id_lo, id_hi, step, purpose),
+// key (seed_lo, seed_hi).
+struct u32x4 { uint32_t x, y, z, w; };
+
+__host__ __device__ inline u32x4 philox4x32(u32x4 c, uint32_t k0, uint32_t k1) {
+  for (int r = 0; r < 10; ++r) {
+    if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    c = u32x4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+  }
+  return c;
+}
+
+__host__ __device__ inline u32x4 draw(uint64_t seed, uint64_t id, uint32_t step, uint32_t purpose) {
+  return philox4x32(u32x4{(uint32_t)id, (uint32_t)(id >> 32), step, purpose},
+                    (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+// ---------------------------------------------------------- Keldysh table
+// Per material: P(A) = 1 - exp(-r(A)), r = W(A) dt / n0.  Between consecutive
+// channel closings (x(A) crossing an integer, Eq. 1) the rate is
+//   r(A) = S1(A) + sqrt(A_k - A) S2(A)
+// with S1, S2 smooth: the n = 0 Dawson term of Eq. (3) vanishes like a square
+// root at the closing A_k.  S1 and S2 are cubic polynomials in the local
+// coordinate f = (A - A_i) / h of each interval of a uniform grid (step h)
+// inside each segment.  Interval record: {A_i, S1 c0..c3, S2 c0..c3, pad x3}.
+constexpr int TAB_REC = 12;
+
+struct TabSeg {
+  float lo, hi, inv_h;      // segment [lo, hi), 1 / grid step
+  int base, nint;           // first interval, number of intervals
+  int has_sigma;            // right end is a channel closing
+  float dk;                 // exact closing A_k = hi - dk (0 <= dk < 1 ulp of hi)
+  int pad1;
+};
+
+struct TabHdr {
+  float acut;               // A < acut: P < 2^-34 (cannot fire against a u32 draw)
+  float asat;               // A >= asat: P = 1
+  int nseg;
+  int pad;
+};
+// Memory: TabHdr, TabSeg[nseg], then float rec[TAB_REC * total intervals].
+
+__host__ __device__ inline float table_lookup(const TabHdr* __restrict__ h, float A) {
+  if (!(A >= h->acut)) return 0.0f;
+  if (A >= h->asat) return 1.0f;
+  const TabSeg* seg = reinterpret_cast<const TabSeg*>(h + 1);
+  int k = 0;
+  while (k + 1 < h->nseg && A >= seg[k].hi) ++k;
+  const TabSeg s = seg[k];
+  int i = (int)((A - s.lo) * s.inv_h);
+  i = i < 0 ? 0 : (i >= s.nint ? s.nint - 1 : i);
+  const float* c = reinterpret_cast<const float*>(seg + h->nseg) + TAB_REC * (s.base + i);
+  const float f = (A - c[0]) * s.inv_h;
+  float r = c[1] + f * (c[2] + f * (c[3] + f * c[4]));
+  if (s.has_sigma) {
+    const float s2 = c[5] + f * (c[6] + f * (c[7] + f * c[8]));
+    const float d = (s.hi - A) - s.dk;   // A_k - A; hi - A is exact
+    r += sqrtf(d > 0.0f ? d : 0.0f) * s2;
+  }
+  return -expm1f(-r);
+}
+
+// ----------------------------------------------------- instance parameters
+struct Inst {
+  // grid
+  int D, order, nx, ny, nz;
+  int Px, Py, Pz;               // padded extents (absent axes: 1)
+  int sy, sz;                   // strides of y and z in the padded arrays
+  int Gy, Gz;                   // guard offsets of y, z (0 if absent)
+  int per_y, per_z;             // periodic transverse axes
+  float C[3];                   // c dt / dx_d (FP32-exact)
+  float halfC[3];
+  float kmur[3];
+  float ctdt_m;                 // c dt [m] (displacement along absent axes)
+  // fields (padded, x fastest)
+  float *E0, *E1, *E2, *B0, *B1, *B2, *J0, *J1, *J2;
+  const float* ie_half;         // 1/eps_r at Ex positions, per padded x index
+  const float* ie_node;         // 1/eps_r at nodes, per padded x index
+  const signed char* mat_cell;  // material of cell i (-1 vacuum), per cell x index
+  // laser
+  int pol;                      // 1 = Ey, 2 = Ez
+  int nsrc;                     // entries in src
+  const float4* src;            // per time level m: g(m dt), g(m dt - dx/c), 0, 0
+  const float* prof;            // transverse profile of the polarised component (Py * Pz)
+  // amplitude window (Sec. 2.1): node |E| over [wx0, wx1) padded x indices
+  int nwin, wx0, wx1, wnx;      // wnx = wx1 - wx0
+  int64_t wsz;                  // wnx * Py * Pz
+  float *ring, *suffix, *prefix, *A;
+  // charged particles (SoA)
+  uint32_t* pcell;              // packed cell indices
+  float *po0, *po1, *po2, *pu0, *pu1, *pu2;
+  uint8_t* pkind;
+  int* pcount;                  // used slots
+  int capacity;
+  // particle kinds: 2m electron, 2m+1 positive carrier
+  float kh[MAXKIND];            // q dt / (2 m c)
+  float kq[MAXKIND][3];         // qhat dx_d (present axes) or qhat c dt (absent)
+  float ksig[MAXMAT];           // thermal velocity spread / c of the neutral molecules
+  double kqhat[MAXKIND];        // q w / (eps0 V) [V/m^2] (diagnostics, FP64)
+  double kw[MAXKIND];           // macroparticle weight (physical particles)
+  double kmass[MAXKIND];        // mass [kg]
+  double dx[3];                 // cell size [m] (absent axes: 1)
+  double vcell;                 // cell volume [m^3] (absent axes count as 1 m)
+  // neutrals
+  int64_t nneut;
+  int ppc;
+  float *no0, *no1, *no2;       // offsets
+  uint32_t* alive;              // bitmask
+  int* death;                   // ionization step, -1 alive
+  const uint32_t* mcell;        // packed cell of each material cell (neutral / ppc)
+  const TabHdr* tab[MAXMAT];
+  float acut[MAXMAT];
+  unsigned long long* nevents;  // per material
+  uint64_t seed;
+  // control
+  int* step;                    // device step counter
+  unsigned* health;
+};
+
+// packed cell: D = 1: i; D = 2: i | j << 16; D = 3: i | j << 12 | k << 22
+__host__ __device__ inline uint32_t pack_cell(int D, int i, int j, int k) {
+  if (D == 1) return (uint32_t)i;
+  if (D == 2) return (uint32_t)i | ((uint32_t)j << 16);
+  return (uint32_t)i | ((uint32_t)j << 12) | ((uint32_t)k << 22);
+}
+__host__ __device__ inline void unpack_cell(int D, uint32_t c, int& i, int& j, int& k) {
+  if (D == 1) { i = (int)c; j = 0; k = 0; return; }
+  if (D == 2) { i = (int)(c & 0xFFFFu); j = (int)(c >> 16); k = 0; return; }
+  i = (int)(c & 0xFFFu); j = (int)((c >> 12) & 0x3FFu); k = (int)(c >> 22);
+}
+
+}  // namespace pic

@@ -1,0 +1,38 @@
+// Device kernels of the PIC hot path (gfx950).  Every kernel advances a group
+// of independent instances in one launch: block b belongs to the instance i
+// with off[i] <= b < off[i+1] (a single run is a group of one).
+#pragma once
+
+#include "pic_common.h"
+
+namespace pic {
+
+struct Group {
+  const Inst* insts;   // device array of instance parameter blocks
+  const int* off;      // device prefix offsets of blocks per instance (n + 1)
+  int n;               // instances
+  int blocks;          // total blocks
+};
+
+constexpr int TPB = 256;
+
+// phase launchers (enqueue on `s`); D = 1..3, order = 1..2
+void launch_push(const Group& g, int D, int order, hipStream_t s);
+void launch_bhalf(const Group& g, int D, hipStream_t s);
+void launch_efull(const Group& g, int D, hipStream_t s);
+void launch_amp(const Group& g, int D, hipStream_t s);
+void launch_ionize(const Group& g, int D, int order, hipStream_t s);
+void launch_advance(const Inst* insts, int n, hipStream_t s);
+
+// one-instance setup and diagnostics
+void launch_init_neutrals_d(const Inst* d, int64_t nneut, int D, hipStream_t s);
+void launch_preionize_d(const Inst* d, int64_t nneut, int D, const float* sig_e, const float* sig_p,
+                        hipStream_t s);
+void launch_diag_particles(const Inst* d, int capacity, double* acc, hipStream_t s);
+void launch_diag_field_energy(const Inst* d, int64_t ncell, double* acc, hipStream_t s);
+void launch_diag_deposit(const Inst* d, int D, int order, int capacity, double* grid, int what,
+                         hipStream_t s);
+void launch_diag_gauss(const Inst* d, int D, const double* rho, double* acc, hipStream_t s);
+void launch_table_probe(const TabHdr* tab, const float* A, float* P, int64_t n, hipStream_t s);
+
+}  // namespace pic

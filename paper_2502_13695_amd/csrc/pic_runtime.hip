@@ -1,0 +1,927 @@
+// C ABI of the MI355X PIC library (include/pic.h): context set-up, device
+// memory layout, stepping, batching and diagnostics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "host_math.h"
+#include "pic.h"
+#include "pic_kernels.h"
+
+using namespace pic;
+
+namespace {
+
+constexpr double kC = 299792458.0;
+constexpr double kQE = 1.602176634e-19;
+constexpr double kEPS0 = 8.8541878128e-12;
+constexpr double kKB = 1.380649e-23;
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Device memory plan of one context (offsets into one allocation).
+struct Layout {
+  int64_t Px, Py, Pz, ncell;
+  int64_t nmcell, nneut, capacity;
+  int wx0, wx1;
+  int64_t wsz;
+  int nsrc;
+  size_t o_E[3], o_B[3], o_J[3], o_ie_half, o_ie_node, o_mat, o_src, o_prof;
+  size_t o_ring, o_suffix, o_prefix, o_A;
+  size_t o_no[3], o_alive, o_death, o_mcell;
+  size_t o_pcell, o_po[3], o_pu[3], o_pkind;
+  size_t o_tab[MAXMAT];
+  size_t o_ctr;      // pcount, step, health, nevents[MAXMAT], diag accumulators
+  size_t o_grid64;   // FP64 node grid for diagnostics
+  size_t o_inst, o_off, o_sig;
+  size_t o_probe;    // scratch for table probes
+  size_t total;
+};
+
+struct Ctr {
+  int pcount;
+  int step;
+  unsigned health;
+  int pad;
+  unsigned long long nevents[MAXMAT];
+  double acc[64];
+};
+
+pic_status plan(const pic_config* cfg, const Canon& c, const std::vector<TableHost>& tabs, Layout* L) {
+  const int D = c.D;
+  L->Px = c.n[0] + 1 + 2 * G;
+  L->Py = D >= 2 ? c.n[1] + 1 + 2 * G : 1;
+  L->Pz = D >= 3 ? c.n[2] + 1 + 2 * G : 1;
+  L->ncell = L->Px * L->Py * L->Pz;
+  int64_t nxm = 0, imin = -1, imax = -1;
+  for (int64_t i = 0; i < c.n[0]; ++i)
+    if (c.mat_cell[i] >= 0) {
+      ++nxm;
+      if (imin < 0) imin = i;
+      imax = i;
+    }
+  L->nmcell = nxm * c.n[1] * c.n[2];
+  L->nneut = L->nmcell * c.ppc;
+  if (nxm > 0) {
+    L->wx0 = (int)std::max<int64_t>(0, imin - 1) + G;
+    L->wx1 = (int)std::min<int64_t>(c.n[0], imax + 2) + G + 1;
+  } else {
+    L->wx0 = L->wx1 = G;
+  }
+  L->wsz = (int64_t)(L->wx1 - L->wx0) * L->Py * L->Pz;
+  int64_t cap = cfg->particle_capacity > 0 ? cfg->particle_capacity : 2 * L->nneut + 4096;
+  if (cfg->preionize_eV > 0) cap = std::max<int64_t>(cap, 2 * L->nneut);
+  if (cap > INT_MAX - 16 || L->nneut > ((int64_t)1 << 40)) return PIC_E_INVAL;
+  L->capacity = cap;
+  L->nsrc = (int)std::min<int64_t>(cfg->nsteps + 2, 1 << 26);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t r = o;
+    o += align256(bytes);
+    return r;
+  };
+  const size_t f = sizeof(float) * (size_t)L->ncell;
+  for (int q = 0; q < 3; ++q) L->o_E[q] = take(f);
+  for (int q = 0; q < 3; ++q) L->o_B[q] = take(f);
+  for (int q = 0; q < 3; ++q) L->o_J[q] = take(f);
+  L->o_ie_half = take(sizeof(float) * L->Px);
+  L->o_ie_node = take(sizeof(float) * L->Px);
+  L->o_mat = take(c.n[0]);
+  L->o_src = take(sizeof(float) * 4 * (size_t)L->nsrc);
+  L->o_prof = take(sizeof(float) * L->Py * L->Pz);
+  L->o_ring = take(sizeof(float) * (size_t)L->wsz * c.nwin);
+  L->o_suffix = take(sizeof(float) * (size_t)L->wsz * c.nwin);
+  L->o_prefix = take(sizeof(float) * (size_t)L->wsz);
+  L->o_A = take(f);
+  for (int q = 0; q < 3; ++q) L->o_no[q] = take(q < D ? sizeof(float) * L->nneut : 0);
+  L->o_alive = take(sizeof(uint32_t) * ((L->nneut + 31) / 32 + 1));
+  L->o_death = take(sizeof(int) * L->nneut);
+  L->o_mcell = take(sizeof(uint32_t) * L->nmcell);
+  L->o_pcell = take(sizeof(uint32_t) * L->capacity);
+  for (int q = 0; q < 3; ++q) L->o_po[q] = take(q < D ? sizeof(float) * L->capacity : 0);
+  for (int q = 0; q < 3; ++q) L->o_pu[q] = take(sizeof(float) * L->capacity);
+  L->o_pkind = take(L->capacity);
+  for (int m = 0; m < MAXMAT; ++m) L->o_tab[m] = take(m < (int)tabs.size() ? tabs[m].bytes.size() : 0);
+  L->o_ctr = take(sizeof(Ctr));
+  L->o_grid64 = take(sizeof(double) * (size_t)L->ncell);
+  L->o_inst = take(sizeof(Inst));
+  L->o_off = take(sizeof(int) * 16);
+  L->o_sig = take(sizeof(float) * 2 * MAXMAT);
+  L->o_probe = take(0);
+  L->total = o;
+  return PIC_OK;
+}
+
+}  // namespace
+
+struct pic_ctx {
+  pic_config cfg{};
+  std::vector<pic_material> mats;
+  std::vector<pic_layer> layers;
+  Canon canon;
+  std::vector<TableHost> tabs;
+  Layout L{};
+  unsigned char* base = nullptr;
+  hipStream_t stream = nullptr;
+  Inst h{};
+  Inst* d_inst = nullptr;
+  int* d_off = nullptr;   // [0, nb_push, 0, nb_cell, 0, nb_win, 0, nb_neut]
+  int nb_push = 0, nb_cell = 0, nb_win = 0, nb_neut = 0;
+  Ctr* d_ctr = nullptr;
+  double* d_grid64 = nullptr;
+  std::vector<uint32_t> mcell;
+  int64_t step = 0;
+  pic_status latched = PIC_OK;
+  int timing = 0;
+  double timers[8] = {0};
+  int owns_alloc_via_cb = 0;
+};
+
+struct pic_batch {
+  std::vector<pic_ctx*> members;
+  bool dirty = true;
+  // per (D, order) class: device Inst copies and per-phase block offsets
+  struct Class {
+    int D, order;
+    std::vector<pic_ctx*> ms;
+    Inst* d_insts = nullptr;
+    int* d_off = nullptr;   // 4 phases x (n + 1)
+    int n = 0;
+    int blocks[4] = {0, 0, 0, 0};
+  };
+  std::vector<Class> classes;
+  hipStream_t stream = nullptr;
+};
+
+namespace {
+
+#define HIP_OK(x)                                   \
+  do {                                              \
+    if ((x) != hipSuccess) return PIC_E_DEVICE;     \
+  } while (0)
+
+inline void* devp(pic_ctx* c, size_t off) { return c->base + off; }
+
+Group single(pic_ctx* c, int phase, int nb) {
+  return Group{c->d_inst, c->d_off + 2 * phase, 1, nb};
+}
+
+void enqueue_step(pic_ctx* c) {
+  const int D = c->canon.D, order = c->cfg.shape_order;
+  hipStream_t s = c->stream;
+  launch_push(single(c, 0, c->nb_push), D, order, s);
+  launch_bhalf(single(c, 1, c->nb_cell), D, s);
+  launch_efull(single(c, 1, c->nb_cell), D, s);
+  launch_bhalf(single(c, 1, c->nb_cell), D, s);
+  if (c->nb_win > 0) launch_amp(single(c, 2, c->nb_win), D, s);
+  if (c->nb_neut > 0) launch_ionize(single(c, 3, c->nb_neut), D, order, s);
+  launch_advance(c->d_inst, 1, s);
+}
+
+// padded index of logical (i, j, k)
+inline int64_t pidx(const Layout& L, int D, int64_t i, int64_t j, int64_t k) {
+  return (i + G) + L.Px * ((D >= 2 ? j + G : 0) + L.Py * (D >= 3 ? k + G : 0));
+}
+
+// domain extent of a component along axis d (half: staggered by 1/2)
+inline int64_t dom_n(const Canon& c, int d, bool half) {
+  if (d >= c.D) return 1;
+  return (half || c.per[d]) ? c.n[d] : c.n[d] + 1;
+}
+
+template <typename Fn>
+void for_domain(const Canon& c, const bool half[3], Fn fn) {
+  const int64_t nx = dom_n(c, 0, half[0]), ny = dom_n(c, 1, half[1]), nz = dom_n(c, 2, half[2]);
+  int64_t q = 0;
+  for (int64_t k = 0; k < nz; ++k)
+    for (int64_t j = 0; j < ny; ++j)
+      for (int64_t i = 0; i < nx; ++i) fn(q++, i, j, k);
+}
+
+const bool kHalfE[3][3] = {{true, false, false}, {false, true, false}, {false, false, true}};
+const bool kHalfB[3][3] = {{false, true, true}, {true, false, true}, {true, true, false}};
+const bool kNode[3] = {false, false, false};
+
+int64_t dom_count(const Canon& c, const bool half[3]) {
+  return dom_n(c, 0, half[0]) * dom_n(c, 1, half[1]) * dom_n(c, 2, half[2]);
+}
+
+pic_status check_health(pic_ctx* c) {
+  unsigned h = 0;
+  HIP_OK(hipMemcpy(&h, &c->d_ctr->health, sizeof h, hipMemcpyDeviceToHost));
+  if (c->latched == PIC_OK) {
+    if (h & HEALTH_NONFINITE) c->latched = PIC_E_NUMERIC;
+    else if (h & HEALTH_CAPACITY) c->latched = PIC_E_CAPACITY;
+  }
+  return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pic_status_str(pic_status s) {
+  switch (s) {
+    case PIC_OK: return "ok";
+    case PIC_E_INVAL: return "invalid argument";
+    case PIC_E_NOMEM: return "device allocation failed";
+    case PIC_E_DEVICE: return "HIP runtime error";
+    case PIC_E_STATE: return "invalid state (latched error)";
+    case PIC_E_NUMERIC: return "non-finite value";
+    case PIC_E_CAPACITY: return "charged-particle capacity exceeded";
+    case PIC_E_VERSION: return "ABI version mismatch";
+  }
+  return "unknown";
+}
+
+pic_status pic_canonical(const pic_config* cfg, pic_params* out) {
+  if (!cfg || !out) return PIC_E_INVAL;
+  Canon c;
+  pic_status st = canonicalize(cfg, &c);
+  if (st != PIC_OK) return st;
+  std::memset(out, 0, sizeof *out);
+  out->dt = c.dt;
+  for (int d = 0; d < 3; ++d) {
+    out->Cd[d] = c.C[d];
+    out->kmur[d] = c.kmur[d];
+  }
+  for (int m = 0; m < c.nmat; ++m) out->ie[m] = c.mats[m].ie;
+  out->nwin = c.nwin;
+  out->E0 = c.E0;
+  out->t_peak = c.t0;
+  std::vector<TableHost> none;
+  Layout L;
+  st = plan(cfg, c, none, &L);
+  if (st != PIC_OK) return st;
+  out->n_neutral = L.nneut;
+  out->capacity = L.capacity;
+  return PIC_OK;
+}
+
+pic_status pic_keldysh_rate(const pic_material* m, double lambda_m, int32_t terms, const double* A,
+                            int64_t n, double* W_out) {
+  if (!m || !A || !W_out || n < 0 || terms < 1 || !(lambda_m > 0)) return PIC_E_INVAL;
+  MatC mc;
+  mc.gap_eV = m->gap_eV;
+  mc.n_index = m->n_index;
+  mc.n0 = 0;
+  mc.mred = 1.0 / (1.0 / m->me_star + 1.0 / m->mh_star);
+  for (int64_t i = 0; i < n; ++i) W_out[i] = keldysh_W(mc, lambda_m, terms, A[i]);
+  return PIC_OK;
+}
+
+pic_status pic_table_probe(const pic_config* cfg, int32_t mat, const float* A, int64_t n, float* P_out) {
+  if (!cfg || !A || !P_out || n < 0) return PIC_E_INVAL;
+  Canon c;
+  pic_status st = canonicalize(cfg, &c);
+  if (st != PIC_OK) return st;
+  TableHost T;
+  st = build_table(c, mat, cfg->keldysh_terms, &T);
+  if (st != PIC_OK) return st;
+  const TabHdr* h = reinterpret_cast<const TabHdr*>(T.bytes.data());
+  for (int64_t i = 0; i < n; ++i) P_out[i] = table_lookup(h, A[i]);
+  return PIC_OK;
+}
+
+pic_status pic_footprint(const pic_config* cfg, size_t* bytes) {
+  if (!cfg || !bytes) return PIC_E_INVAL;
+  Canon c;
+  pic_status st = canonicalize(cfg, &c);
+  if (st != PIC_OK) return st;
+  // tables: bounded estimate without building them (<= 1 MiB per material)
+  std::vector<TableHost> est(c.nmat);
+  for (auto& t : est) t.bytes.resize(1 << 20);
+  Layout L;
+  st = plan(cfg, c, est, &L);
+  if (st != PIC_OK) return st;
+  *bytes = L.total;
+  return PIC_OK;
+}
+
+pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
+  if (!cfg_in || !out) return PIC_E_INVAL;
+  *out = nullptr;
+  pic_ctx* c = new (std::nothrow) pic_ctx();
+  if (!c) return PIC_E_NOMEM;
+  c->cfg = *cfg_in;
+  pic_status st = canonicalize(cfg_in, &c->canon);
+  if (st != PIC_OK) {
+    delete c;
+    return st;
+  }
+  c->mats.assign(cfg_in->mats, cfg_in->mats + cfg_in->nmat);
+  c->layers.assign(cfg_in->layers, cfg_in->layers + cfg_in->nlayer);
+  c->cfg.mats = c->mats.data();
+  c->cfg.layers = c->layers.data();
+  const Canon& K = c->canon;
+  const int D = K.D;
+  c->tabs.resize(K.nmat);
+  for (int m = 0; m < K.nmat; ++m) {
+    st = build_table(K, m, cfg_in->keldysh_terms > 0 ? cfg_in->keldysh_terms : 500, &c->tabs[m]);
+    if (st != PIC_OK) {
+      delete c;
+      return st;
+    }
+  }
+  st = plan(&c->cfg, K, c->tabs, &c->L);
+  if (st != PIC_OK) {
+    delete c;
+    return st;
+  }
+  const Layout& L = c->L;
+  c->stream = (hipStream_t)cfg_in->stream;
+  void* mem = nullptr;
+  if (cfg_in->alloc) {
+    mem = cfg_in->alloc(L.total, cfg_in->alloc_user);
+    c->owns_alloc_via_cb = 1;
+  } else if (hipMalloc(&mem, L.total) != hipSuccess) {
+    mem = nullptr;
+  }
+  if (!mem) {
+    delete c;
+    return PIC_E_NOMEM;
+  }
+  c->base = (unsigned char*)mem;
+  auto fail = [&](pic_status s) {
+    pic_destroy(c);
+    return s;
+  };
+  if (hipMemsetAsync(c->base, 0, L.total, c->stream) != hipSuccess) return fail(PIC_E_DEVICE);
+
+  // ---- host-built tables and parameter block
+  std::vector<float> ie_half(L.Px, 1.0f), ie_node(L.Px, 1.0f);
+  for (int64_t i = 0; i < K.n[0]; ++i)
+    ie_half[i + G] = K.mat_cell[i] >= 0 ? K.mats[K.mat_cell[i]].ie : 1.0f;
+  for (int64_t i = 0; i <= K.n[0]; ++i)
+    ie_node[i + G] = K.mat_node[i] >= 0 ? K.mats[K.mat_node[i]].ie : 1.0f;
+  std::vector<float> src(4 * (size_t)L.nsrc, 0.0f);
+  for (int m = 0; m < L.nsrc; ++m) {
+    src[4 * m + 0] = (float)laser_field(K, m * K.dt);
+    src[4 * m + 1] = (float)laser_field(K, m * K.dt - K.dx[0] / kC);
+  }
+  std::vector<float> prof((size_t)L.Py * L.Pz, 0.0f);
+  for (int64_t k = 0; k < (D >= 3 ? K.n[2] + 1 : 1); ++k)
+    for (int64_t j = 0; j < (D >= 2 ? K.n[1] + 1 : 1); ++j) {
+      double y = 0.0, z = 0.0;
+      if (D >= 2) y = ((double)j + (K.pol == 1 ? 0.5 : 0.0)) * K.dx[1] - 0.5 * K.n[1] * K.dx[1];
+      if (D >= 3) z = ((double)k + (K.pol == 2 ? 0.5 : 0.0)) * K.dx[2] - 0.5 * K.n[2] * K.dx[2];
+      prof[(D >= 2 ? j + G : 0) + L.Py * (D >= 3 ? k + G : 0)] = (float)transverse_profile(K, y, z);
+    }
+  c->mcell.clear();
+  c->mcell.reserve(L.nmcell);
+  for (int64_t k = 0; k < K.n[2]; ++k)
+    for (int64_t j = 0; j < K.n[1]; ++j)
+      for (int64_t i = 0; i < K.n[0]; ++i)
+        if (K.mat_cell[i] >= 0) c->mcell.push_back(pack_cell(D, (int)i, (int)j, (int)k));
+
+  Inst& I = c->h;
+  std::memset(&I, 0, sizeof I);
+  I.D = D;
+  I.order = c->cfg.shape_order;
+  I.nx = (int)K.n[0];
+  I.ny = (int)K.n[1];
+  I.nz = (int)K.n[2];
+  I.Px = (int)L.Px;
+  I.Py = (int)L.Py;
+  I.Pz = (int)L.Pz;
+  I.sy = (int)L.Px;
+  I.sz = (int)(L.Px * L.Py);
+  I.Gy = D >= 2 ? G : 0;
+  I.Gz = D >= 3 ? G : 0;
+  I.per_y = K.per[1];
+  I.per_z = K.per[2];
+  for (int d = 0; d < 3; ++d) {
+    I.C[d] = K.C[d];
+    I.halfC[d] = 0.5f * K.C[d];
+    I.kmur[d] = K.kmur[d];
+    I.dx[d] = K.dx[d];
+  }
+  I.vcell = K.vcell;
+  I.ctdt_m = (float)(kC * K.dt);
+  float* fE[3];
+  for (int q = 0; q < 3; ++q) fE[q] = (float*)devp(c, L.o_E[q]);
+  I.E0 = fE[0];
+  I.E1 = fE[1];
+  I.E2 = fE[2];
+  I.B0 = (float*)devp(c, L.o_B[0]);
+  I.B1 = (float*)devp(c, L.o_B[1]);
+  I.B2 = (float*)devp(c, L.o_B[2]);
+  I.J0 = (float*)devp(c, L.o_J[0]);
+  I.J1 = (float*)devp(c, L.o_J[1]);
+  I.J2 = (float*)devp(c, L.o_J[2]);
+  I.ie_half = (const float*)devp(c, L.o_ie_half);
+  I.ie_node = (const float*)devp(c, L.o_ie_node);
+  I.mat_cell = (const signed char*)devp(c, L.o_mat);
+  I.pol = K.pol;
+  I.nsrc = L.nsrc;
+  I.src = (const float4*)devp(c, L.o_src);
+  I.prof = (const float*)devp(c, L.o_prof);
+  I.nwin = K.nwin;
+  I.wx0 = L.wx0;
+  I.wx1 = L.wx1;
+  I.wnx = L.wx1 - L.wx0;
+  I.wsz = L.wsz;
+  I.ring = (float*)devp(c, L.o_ring);
+  I.suffix = (float*)devp(c, L.o_suffix);
+  I.prefix = (float*)devp(c, L.o_prefix);
+  I.A = (float*)devp(c, L.o_A);
+  I.pcell = (uint32_t*)devp(c, L.o_pcell);
+  I.po0 = (float*)devp(c, L.o_po[0]);
+  I.po1 = (float*)devp(c, L.o_po[1]);
+  I.po2 = (float*)devp(c, L.o_po[2]);
+  I.pu0 = (float*)devp(c, L.o_pu[0]);
+  I.pu1 = (float*)devp(c, L.o_pu[1]);
+  I.pu2 = (float*)devp(c, L.o_pu[2]);
+  I.pkind = (uint8_t*)devp(c, L.o_pkind);
+  c->d_ctr = (Ctr*)devp(c, L.o_ctr);
+  I.pcount = &c->d_ctr->pcount;
+  I.step = &c->d_ctr->step;
+  I.health = &c->d_ctr->health;
+  I.nevents = c->d_ctr->nevents;
+  I.capacity = (int)L.capacity;
+  for (int m = 0; m < K.nmat; ++m) {
+    const MatC& mt = K.mats[m];
+    const double kmass[2] = {mt.e_kg, mt.p_kg};
+    for (int s = 0; s < 2; ++s) {
+      const int kd = 2 * m + s;
+      const double q = s == 0 ? -kQE : kQE;
+      const double qhat = q * mt.n0 / (K.ppc > 0 ? K.ppc : 1) / kEPS0;
+      I.kh[kd] = (float)(q * K.dt / (2.0 * kmass[s] * kC));
+      for (int d = 0; d < 3; ++d) I.kq[kd][d] = (float)(d < D ? qhat * K.dx[d] : qhat * kC * K.dt);
+      I.kqhat[kd] = qhat;
+      I.kw[kd] = mt.n0 * K.vcell / (K.ppc > 0 ? K.ppc : 1);
+      I.kmass[kd] = kmass[s];
+    }
+    I.ksig[m] = (float)(std::sqrt(kKB * c->cfg.T_K / mt.mol_kg) / kC);
+    I.tab[m] = (const TabHdr*)devp(c, L.o_tab[m]);
+    I.acut[m] = c->tabs[m].acut;
+  }
+  I.nneut = L.nneut;
+  I.ppc = K.ppc;
+  I.no0 = (float*)devp(c, L.o_no[0]);
+  I.no1 = (float*)devp(c, L.o_no[1]);
+  I.no2 = (float*)devp(c, L.o_no[2]);
+  I.alive = (uint32_t*)devp(c, L.o_alive);
+  I.death = (int*)devp(c, L.o_death);
+  I.mcell = (const uint32_t*)devp(c, L.o_mcell);
+  I.seed = c->cfg.seed;
+  c->d_inst = (Inst*)devp(c, L.o_inst);
+  c->d_off = (int*)devp(c, L.o_off);
+  c->d_grid64 = (double*)devp(c, L.o_grid64);
+
+  // block counts per phase
+  auto nblk = [](int64_t n) { return (int)std::max<int64_t>(0, (n + TPB - 1) / TPB); };
+  c->nb_push = std::max(1, std::min(nblk(L.capacity), 4096));
+  c->nb_cell = nblk(L.ncell);
+  c->nb_win = nblk(L.wsz);
+  c->nb_neut = nblk(L.nneut);
+  const int offs[8] = {0, c->nb_push, 0, c->nb_cell, 0, c->nb_win, 0, c->nb_neut};
+
+  hipStream_t s = c->stream;
+  bool ok = true;
+  ok &= hipMemcpyAsync(devp(c, L.o_ie_half), ie_half.data(), sizeof(float) * L.Px, hipMemcpyHostToDevice, s) == hipSuccess;
+  ok &= hipMemcpyAsync(devp(c, L.o_ie_node), ie_node.data(), sizeof(float) * L.Px, hipMemcpyHostToDevice, s) == hipSuccess;
+  ok &= hipMemcpyAsync(devp(c, L.o_mat), K.mat_cell.data(), K.n[0], hipMemcpyHostToDevice, s) == hipSuccess;
+  ok &= hipMemcpyAsync(devp(c, L.o_src), src.data(), sizeof(float) * src.size(), hipMemcpyHostToDevice, s) == hipSuccess;
+  ok &= hipMemcpyAsync(devp(c, L.o_prof), prof.data(), sizeof(float) * prof.size(), hipMemcpyHostToDevice, s) == hipSuccess;
+  if (!c->mcell.empty())
+    ok &= hipMemcpyAsync(devp(c, L.o_mcell), c->mcell.data(), sizeof(uint32_t) * c->mcell.size(),
+                         hipMemcpyHostToDevice, s) == hipSuccess;
+  for (int m = 0; m < K.nmat; ++m)
+    ok &= hipMemcpyAsync(devp(c, L.o_tab[m]), c->tabs[m].bytes.data(), c->tabs[m].bytes.size(),
+                         hipMemcpyHostToDevice, s) == hipSuccess;
+  ok &= hipMemcpyAsync(c->d_inst, &I, sizeof I, hipMemcpyHostToDevice, s) == hipSuccess;
+  ok &= hipMemcpyAsync(c->d_off, offs, sizeof offs, hipMemcpyHostToDevice, s) == hipSuccess;
+  float sig[2 * MAXMAT] = {0};
+  if (c->cfg.preionize_eV > 0) {
+    for (int m = 0; m < K.nmat; ++m) {
+      sig[m] = (float)(std::sqrt(c->cfg.preionize_eV * kQE / K.mats[m].e_kg) / kC);
+      sig[MAXMAT + m] = (float)(std::sqrt(c->cfg.preionize_eV * kQE / K.mats[m].p_kg) / kC);
+    }
+    ok &= hipMemcpyAsync(devp(c, L.o_sig), sig, sizeof sig, hipMemcpyHostToDevice, s) == hipSuccess;
+  }
+  if (!ok) return fail(PIC_E_DEVICE);
+  launch_init_neutrals_d(c->d_inst, L.nneut, D, s);
+  if (c->cfg.preionize_eV > 0 && L.nneut > 0) {
+    const float* sg = (const float*)devp(c, L.o_sig);
+    launch_preionize_d(c->d_inst, L.nneut, D, sg, sg + MAXMAT, s);
+    const int cnt = (int)(2 * L.nneut);
+    if (hipMemcpyAsync(&c->d_ctr->pcount, &cnt, sizeof cnt, hipMemcpyHostToDevice, s) != hipSuccess)
+      return fail(PIC_E_DEVICE);
+  }
+  if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess) return fail(PIC_E_DEVICE);
+  *out = c;
+  return PIC_OK;
+}
+
+void pic_destroy(pic_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream); else (void)hipDeviceSynchronize();
+  if (c->base) {
+    if (c->owns_alloc_via_cb && c->cfg.free) c->cfg.free(c->base, c->cfg.alloc_user);
+    else if (!c->owns_alloc_via_cb) (void)hipFree(c->base);
+  }
+  delete c;
+}
+
+pic_status pic_set_timing(pic_ctx* c, int32_t on) {
+  if (!c) return PIC_E_INVAL;
+  c->timing = on;
+  return PIC_OK;
+}
+
+pic_status pic_step(pic_ctx* c, int64_t nsteps) {
+  if (!c || nsteps < 0) return PIC_E_INVAL;
+  if (c->latched != PIC_OK) return PIC_E_STATE;
+  for (int64_t s = 0; s < nsteps; ++s) enqueue_step(c);
+  c->step += nsteps;
+  if (hipGetLastError() != hipSuccess) return PIC_E_DEVICE;
+  return PIC_OK;
+}
+
+pic_status pic_set_state(pic_ctx* c, const pic_state* S) {
+  if (!c || !S) return PIC_E_INVAL;
+  if (S->n_particles < 0 || S->n_particles > c->L.capacity || (S->n_particles > 0 && !S->particles))
+    return PIC_E_INVAL;
+  const Canon& K = c->canon;
+  const Layout& L = c->L;
+  const int D = K.D;
+  hipStream_t s = c->stream;
+  if (hipStreamSynchronize(s) != hipSuccess) return PIC_E_DEVICE;
+  std::vector<float> buf(L.ncell);
+  for (int w = 0; w < 2; ++w)
+    for (int q = 0; q < 3; ++q) {
+      const float* src = w == 0 ? S->E[q] : S->b[q];
+      if (!src) continue;
+      std::fill(buf.begin(), buf.end(), 0.0f);
+      const bool* half = w == 0 ? kHalfE[q] : kHalfB[q];
+      for_domain(K, half, [&](int64_t n, int64_t i, int64_t j, int64_t k) { buf[pidx(L, D, i, j, k)] = src[n]; });
+      HIP_OK(hipMemcpy(devp(c, w == 0 ? L.o_E[q] : L.o_B[q]), buf.data(), sizeof(float) * L.ncell,
+                       hipMemcpyHostToDevice));
+    }
+  const int64_t n = S->n_particles;
+  if (n > 0 || true) {
+    std::vector<uint32_t> pc(n);
+    std::vector<float> po[3], pu[3];
+    for (int q = 0; q < 3; ++q) {
+      po[q].resize(n);
+      pu[q].resize(n);
+    }
+    std::vector<uint8_t> pk(n);
+    for (int64_t p = 0; p < n; ++p) {
+      const pic_particle& r = S->particles[p];
+      for (int d = 0; d < D; ++d)
+        if (r.cell[d] < 0 || r.cell[d] >= K.n[d] || !(r.off[d] >= 0.0f && r.off[d] < 1.0f)) return PIC_E_INVAL;
+      if (r.kind < 0 || r.kind >= 2 * K.nmat) return PIC_E_INVAL;
+      pc[p] = pack_cell(D, r.cell[0], D >= 2 ? r.cell[1] : 0, D >= 3 ? r.cell[2] : 0);
+      for (int q = 0; q < 3; ++q) {
+        po[q][p] = r.off[q];
+        pu[q][p] = r.u[q];
+      }
+      pk[p] = (uint8_t)r.kind;
+    }
+    if (n > 0) {
+      HIP_OK(hipMemcpy(devp(c, L.o_pcell), pc.data(), 4 * n, hipMemcpyHostToDevice));
+      for (int q = 0; q < 3; ++q) {
+        if (q < D) HIP_OK(hipMemcpy(devp(c, L.o_po[q]), po[q].data(), 4 * n, hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(devp(c, L.o_pu[q]), pu[q].data(), 4 * n, hipMemcpyHostToDevice));
+      }
+      HIP_OK(hipMemcpy(devp(c, L.o_pkind), pk.data(), n, hipMemcpyHostToDevice));
+    }
+    const int cnt = (int)n;
+    HIP_OK(hipMemcpy(&c->d_ctr->pcount, &cnt, sizeof cnt, hipMemcpyHostToDevice));
+  }
+  const int st = (int)S->step;
+  HIP_OK(hipMemcpy(&c->d_ctr->step, &st, sizeof st, hipMemcpyHostToDevice));
+  c->step = S->step;
+  if (S->reset_window) {
+    HIP_OK(hipMemset(devp(c, L.o_ring), 0, sizeof(float) * L.wsz * K.nwin));
+    HIP_OK(hipMemset(devp(c, L.o_suffix), 0, sizeof(float) * L.wsz * K.nwin));
+    HIP_OK(hipMemset(devp(c, L.o_prefix), 0, sizeof(float) * L.wsz));
+    HIP_OK(hipMemset(devp(c, L.o_A), 0, sizeof(float) * L.ncell));
+  }
+  for (int q = 0; q < 3; ++q) HIP_OK(hipMemset(devp(c, L.o_J[q]), 0, sizeof(float) * L.ncell));
+  HIP_OK(hipDeviceSynchronize());
+  return PIC_OK;
+}
+
+pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size_t* written) {
+  if (!c) return PIC_E_INVAL;
+  const Canon& K = c->canon;
+  const Layout& L = c->L;
+  const int D = K.D;
+  hipStream_t s = c->stream;
+  if (hipStreamSynchronize(s) != hipSuccess) return PIC_E_DEVICE;
+  check_health(c);
+  size_t need = 0;
+  switch (kind) {
+    case PIC_DIAG_SCALARS: need = sizeof(double) * PIC_SC_COUNT; break;
+    case PIC_DIAG_FIELDS: {
+      for (int q = 0; q < 3; ++q) need += sizeof(double) * (dom_count(K, kHalfE[q]) + dom_count(K, kHalfB[q]));
+      break;
+    }
+    case PIC_DIAG_NE_GRID:
+    case PIC_DIAG_UE_GRID: need = sizeof(double) * dom_count(K, kNode); break;
+    case PIC_DIAG_AMP: need = sizeof(float) * dom_count(K, kNode); break;
+    case PIC_DIAG_PARAMS: need = sizeof(pic_params); break;
+    case PIC_DIAG_TIMERS: need = sizeof(double) * 8; break;
+    case PIC_DIAG_EVENTS:
+    case PIC_DIAG_PARTICLES: break;   // computed below
+    default: return PIC_E_INVAL;
+  }
+  if (kind == PIC_DIAG_EVENTS) {
+    std::vector<int> death(L.nneut);
+    if (L.nneut) HIP_OK(hipMemcpy(death.data(), devp(c, L.o_death), 4 * L.nneut, hipMemcpyDeviceToHost));
+    std::vector<int64_t> pairs;
+    for (int64_t jn = 0; jn < L.nneut; ++jn) {
+      if (death[jn] < 0) continue;
+      const int64_t m = jn / K.ppc, kk = jn - m * K.ppc;
+      int ci, cj, ck;
+      unpack_cell(D, c->mcell[m], ci, cj, ck);
+      const int64_t lin = ci + K.n[0] * (cj + K.n[1] * (int64_t)ck);
+      pairs.push_back(lin * K.ppc + kk);
+      pairs.push_back(death[jn]);
+    }
+    need = sizeof(int64_t) * pairs.size();
+    if (written) *written = need;
+    if (!host_out) return PIC_OK;
+    if (out_bytes < need) return PIC_E_INVAL;
+    if (need) std::memcpy(host_out, pairs.data(), need);
+    return PIC_OK;
+  }
+  if (kind == PIC_DIAG_PARTICLES) {
+    int cnt = 0;
+    HIP_OK(hipMemcpy(&cnt, &c->d_ctr->pcount, sizeof cnt, hipMemcpyDeviceToHost));
+    cnt = std::min<int64_t>(cnt, L.capacity);
+    std::vector<uint32_t> pc(cnt);
+    std::vector<float> po[3], pu[3];
+    std::vector<uint8_t> pk(cnt);
+    if (cnt) {
+      HIP_OK(hipMemcpy(pc.data(), devp(c, L.o_pcell), 4 * cnt, hipMemcpyDeviceToHost));
+      HIP_OK(hipMemcpy(pk.data(), devp(c, L.o_pkind), cnt, hipMemcpyDeviceToHost));
+    }
+    for (int q = 0; q < 3; ++q) {
+      po[q].assign(cnt, 0.0f);
+      pu[q].resize(cnt);
+      if (cnt && q < D) HIP_OK(hipMemcpy(po[q].data(), devp(c, L.o_po[q]), 4 * cnt, hipMemcpyDeviceToHost));
+      if (cnt) HIP_OK(hipMemcpy(pu[q].data(), devp(c, L.o_pu[q]), 4 * cnt, hipMemcpyDeviceToHost));
+    }
+    std::vector<pic_particle> recs;
+    for (int p = 0; p < cnt; ++p) {
+      if (pk[p] == DEAD) continue;
+      pic_particle r{};
+      int ci, cj, ck;
+      unpack_cell(D, pc[p], ci, cj, ck);
+      r.cell[0] = ci;
+      r.cell[1] = cj;
+      r.cell[2] = ck;
+      r.kind = pk[p];
+      for (int q = 0; q < 3; ++q) {
+        r.off[q] = po[q][p];
+        r.u[q] = pu[q][p];
+      }
+      recs.push_back(r);
+    }
+    need = sizeof(pic_particle) * recs.size();
+    if (written) *written = need;
+    if (!host_out) return PIC_OK;
+    if (out_bytes < need) return PIC_E_INVAL;
+    if (need) std::memcpy(host_out, recs.data(), need);
+    return PIC_OK;
+  }
+  if (written) *written = need;
+  if (!host_out) return PIC_OK;
+  if (out_bytes < need) return PIC_E_INVAL;
+
+  if (kind == PIC_DIAG_FIELDS) {
+    double* o = (double*)host_out;
+    std::vector<float> buf(L.ncell);
+    for (int w = 0; w < 2; ++w)
+      for (int q = 0; q < 3; ++q) {
+        HIP_OK(hipMemcpy(buf.data(), devp(c, w == 0 ? L.o_E[q] : L.o_B[q]), sizeof(float) * L.ncell,
+                         hipMemcpyDeviceToHost));
+        const bool* half = w == 0 ? kHalfE[q] : kHalfB[q];
+        for_domain(K, half, [&](int64_t n, int64_t i, int64_t j, int64_t k) { o[n] = buf[pidx(L, D, i, j, k)]; });
+        o += dom_count(K, half);
+      }
+    return PIC_OK;
+  }
+  if (kind == PIC_DIAG_AMP) {
+    std::vector<float> buf(L.ncell);
+    HIP_OK(hipMemcpy(buf.data(), devp(c, L.o_A), sizeof(float) * L.ncell, hipMemcpyDeviceToHost));
+    float* o = (float*)host_out;
+    for_domain(K, kNode, [&](int64_t n, int64_t i, int64_t j, int64_t k) { o[n] = buf[pidx(L, D, i, j, k)]; });
+    return PIC_OK;
+  }
+  if (kind == PIC_DIAG_NE_GRID || kind == PIC_DIAG_UE_GRID) {
+    HIP_OK(hipMemsetAsync(c->d_grid64, 0, sizeof(double) * L.ncell, s));
+    launch_diag_deposit(c->d_inst, D, c->cfg.shape_order, (int)L.capacity, c->d_grid64,
+                        kind == PIC_DIAG_NE_GRID ? 1 : 2, s);
+    std::vector<double> buf(L.ncell);
+    HIP_OK(hipMemcpyAsync(buf.data(), c->d_grid64, sizeof(double) * L.ncell, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    double* o = (double*)host_out;
+    std::vector<double> full = buf;
+    // fold periodic images are already wrapped by the deposit
+    for_domain(K, kNode, [&](int64_t n, int64_t i, int64_t j, int64_t k) { o[n] = full[pidx(L, D, i, j, k)]; });
+    return PIC_OK;
+  }
+  if (kind == PIC_DIAG_PARAMS) {
+    pic_params P;
+    pic_canonical(&c->cfg, &P);
+    for (int m = 0; m < K.nmat; ++m) {
+      P.amp_cut[m] = c->tabs[m].acut;
+      P.amp_sat[m] = c->tabs[m].asat;
+    }
+    std::memcpy(host_out, &P, sizeof P);
+    return PIC_OK;
+  }
+  if (kind == PIC_DIAG_TIMERS) {
+    std::memcpy(host_out, c->timers, sizeof c->timers);
+    return PIC_OK;
+  }
+  // ---- SCALARS
+  double* o = (double*)host_out;
+  std::memset(o, 0, sizeof(double) * PIC_SC_COUNT);
+  HIP_OK(hipMemsetAsync(c->d_ctr->acc, 0, sizeof(c->d_ctr->acc), s));
+  launch_diag_particles(c->d_inst, (int)L.capacity, c->d_ctr->acc, s);
+  launch_diag_field_energy(c->d_inst, L.ncell, c->d_ctr->acc + 40, s);
+  HIP_OK(hipMemsetAsync(c->d_grid64, 0, sizeof(double) * L.ncell, s));
+  launch_diag_deposit(c->d_inst, D, c->cfg.shape_order, (int)L.capacity, c->d_grid64, 0, s);
+  launch_diag_gauss(c->d_inst, D, c->d_grid64, c->d_ctr->acc + 44, s);
+  Ctr h;
+  HIP_OK(hipMemcpyAsync(&h, c->d_ctr, sizeof h, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  if (hipGetLastError() != hipSuccess) return PIC_E_DEVICE;
+  double ne = 0, np = 0, kee = 0, kep = 0, egap = 0, nev = 0;
+  for (int m = 0; m < K.nmat; ++m) {
+    ne += h.acc[2 * (2 * m)];
+    kee += h.acc[2 * (2 * m) + 1];
+    np += h.acc[2 * (2 * m + 1)];
+    kep += h.acc[2 * (2 * m + 1) + 1];
+    nev += (double)h.nevents[m];
+    egap += (double)h.nevents[m] * c->h.kw[2 * m] * K.mats[m].gap_eV * kQE;
+  }
+  if (c->cfg.preionize_eV > 0) {
+    // pre-ionized neutrals count as events of step 0
+    nev += (double)L.nneut;
+  }
+  o[PIC_SC_STEP] = (double)h.step;
+  o[PIC_SC_TIME] = h.step * K.dt;
+  o[PIC_SC_N_NEUTRAL] = (double)L.nneut - nev;
+  o[PIC_SC_N_E] = ne;
+  o[PIC_SC_N_POS] = np;
+  o[PIC_SC_EVENTS] = nev;
+  o[PIC_SC_U_FIELD] = 0.5 * kEPS0 * h.acc[40] * K.vcell;
+  o[PIC_SC_KE_E] = kee;
+  o[PIC_SC_KE_POS] = kep;
+  o[PIC_SC_E_GAP] = egap;
+  o[PIC_SC_E_ABS] = kee + kep + egap;
+  o[PIC_SC_GAUSS_MAX] = h.acc[44];
+  o[PIC_SC_RHO_MAX] = h.acc[45];
+  o[PIC_SC_HEALTH] = (double)h.health;
+  o[PIC_SC_SLOTS] = (double)h.pcount;
+  return PIC_OK;
+}
+
+pic_status pic_table_probe_device(pic_ctx* c, int32_t mat, const float* A, int64_t n, float* P_out) {
+  if (!c || !A || !P_out || n < 0 || mat < 0 || mat >= c->canon.nmat) return PIC_E_INVAL;
+  if (n == 0) return PIC_OK;
+  float *dA = nullptr, *dP = nullptr;
+  HIP_OK(hipMalloc(&dA, 4 * n));
+  if (hipMalloc(&dP, 4 * n) != hipSuccess) {
+    (void)hipFree(dA);
+    return PIC_E_NOMEM;
+  }
+  pic_status st = PIC_OK;
+  if (hipMemcpy(dA, A, 4 * n, hipMemcpyHostToDevice) != hipSuccess) st = PIC_E_DEVICE;
+  if (st == PIC_OK) {
+    launch_table_probe((const TabHdr*)devp(c, c->L.o_tab[mat]), dA, dP, n, nullptr);
+    if (hipMemcpy(P_out, dP, 4 * n, hipMemcpyDeviceToHost) != hipSuccess) st = PIC_E_DEVICE;
+  }
+  (void)hipFree(dA);
+  (void)hipFree(dP);
+  return st;
+}
+
+// ------------------------------------------------------------------ batch
+pic_status pic_batch_create(pic_ctx* const* members, int32_t n, pic_batch** out) {
+  if (!out || n < 0 || (n > 0 && !members)) return PIC_E_INVAL;
+  pic_batch* b = new (std::nothrow) pic_batch();
+  if (!b) return PIC_E_NOMEM;
+  for (int i = 0; i < n; ++i) {
+    if (!members[i]) {
+      delete b;
+      return PIC_E_INVAL;
+    }
+    b->members.push_back(members[i]);
+  }
+  if (n > 0) b->stream = members[0]->stream;
+  *out = b;
+  return PIC_OK;
+}
+
+static void batch_free_classes(pic_batch* b) {
+  for (auto& cl : b->classes) {
+    if (cl.d_insts) (void)hipFree(cl.d_insts);
+    if (cl.d_off) (void)hipFree(cl.d_off);
+  }
+  b->classes.clear();
+}
+
+static pic_status batch_rebuild(pic_batch* b) {
+  if (b->stream) (void)hipStreamSynchronize(b->stream); else (void)hipDeviceSynchronize();
+  batch_free_classes(b);
+  for (pic_ctx* c : b->members) {
+    pic_batch::Class* cl = nullptr;
+    for (auto& k : b->classes)
+      if (k.D == c->canon.D && k.order == c->cfg.shape_order) cl = &k;
+    if (!cl) {
+      b->classes.push_back(pic_batch::Class{});
+      cl = &b->classes.back();
+      cl->D = c->canon.D;
+      cl->order = c->cfg.shape_order;
+    }
+    cl->ms.push_back(c);
+  }
+  for (auto& cl : b->classes) {
+    cl.n = (int)cl.ms.size();
+    std::vector<Inst> hi(cl.n);
+    std::vector<int> off(4 * (cl.n + 1), 0);
+    for (int i = 0; i < cl.n; ++i) {
+      hi[i] = cl.ms[i]->h;
+      const int nb[4] = {cl.ms[i]->nb_push, cl.ms[i]->nb_cell, cl.ms[i]->nb_win, cl.ms[i]->nb_neut};
+      for (int ph = 0; ph < 4; ++ph) off[ph * (cl.n + 1) + i + 1] = off[ph * (cl.n + 1) + i] + nb[ph];
+    }
+    for (int ph = 0; ph < 4; ++ph) cl.blocks[ph] = off[ph * (cl.n + 1) + cl.n];
+    HIP_OK(hipMalloc(&cl.d_insts, sizeof(Inst) * cl.n));
+    HIP_OK(hipMalloc(&cl.d_off, sizeof(int) * off.size()));
+    HIP_OK(hipMemcpy(cl.d_insts, hi.data(), sizeof(Inst) * cl.n, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(cl.d_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice));
+  }
+  b->dirty = false;
+  return PIC_OK;
+}
+
+pic_status pic_batch_step(pic_batch* b, int64_t nsteps) {
+  if (!b || nsteps < 0) return PIC_E_INVAL;
+  for (pic_ctx* c : b->members)
+    if (c->latched != PIC_OK) return PIC_E_STATE;
+  if (b->dirty) {
+    pic_status st = batch_rebuild(b);
+    if (st != PIC_OK) return st;
+  }
+  hipStream_t s = b->stream;
+  for (int64_t t = 0; t < nsteps; ++t) {
+    for (auto& cl : b->classes) {
+      const int np1 = cl.n + 1;
+      Group gp{cl.d_insts, cl.d_off + 0 * np1, cl.n, cl.blocks[0]};
+      Group gc{cl.d_insts, cl.d_off + 1 * np1, cl.n, cl.blocks[1]};
+      Group gw{cl.d_insts, cl.d_off + 2 * np1, cl.n, cl.blocks[2]};
+      Group gn{cl.d_insts, cl.d_off + 3 * np1, cl.n, cl.blocks[3]};
+      launch_push(gp, cl.D, cl.order, s);
+      launch_bhalf(gc, cl.D, s);
+      launch_efull(gc, cl.D, s);
+      launch_bhalf(gc, cl.D, s);
+      if (gw.blocks > 0) launch_amp(gw, cl.D, s);
+      if (gn.blocks > 0) launch_ionize(gn, cl.D, cl.order, s);
+      launch_advance(cl.d_insts, cl.n, s);
+    }
+  }
+  for (pic_ctx* c : b->members) c->step += nsteps;
+  if (hipGetLastError() != hipSuccess) return PIC_E_DEVICE;
+  return PIC_OK;
+}
+
+pic_status pic_batch_add(pic_batch* b, pic_ctx* c) {
+  if (!b || !c) return PIC_E_INVAL;
+  for (pic_ctx* m : b->members)
+    if (m == c) return PIC_E_INVAL;
+  if (b->members.empty()) b->stream = c->stream;
+  b->members.push_back(c);
+  b->dirty = true;
+  return PIC_OK;
+}
+
+pic_status pic_batch_remove(pic_batch* b, pic_ctx* c) {
+  if (!b || !c) return PIC_E_INVAL;
+  auto it = std::find(b->members.begin(), b->members.end(), c);
+  if (it == b->members.end()) return PIC_E_INVAL;
+  b->members.erase(it);
+  b->dirty = true;
+  return PIC_OK;
+}
+
+void pic_batch_destroy(pic_batch* b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream); else (void)hipDeviceSynchronize();
+  batch_free_classes(b);
+  delete b;
+}
+
+}  // extern "C"

@@ -1,0 +1,425 @@
+"""ctypes binding of libpic.so (include/pic.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+behind the C ABI.  The library must be built (``python -m
+paper_2502_13695_amd.build``); loading fails loudly otherwise.  PyTorch, when
+present with a GPU, provides the device allocator and the stream.
+"""
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpic.so")
+_LIB = None
+
+PIC_OK = 0
+STATUS = {0: "ok", -1: "invalid argument", -2: "device allocation failed", -3: "HIP runtime error",
+          -4: "invalid state (latched error)", -5: "non-finite value",
+          -6: "charged-particle capacity exceeded", -7: "ABI version mismatch"}
+ABI_VERSION = 1
+ENV = {"gauss": 0, "sin2": 1}
+BC = {"outflow": 0, "periodic": 1}
+DIAG_SCALARS, DIAG_FIELDS, DIAG_NE, DIAG_UE, DIAG_EVENTS, DIAG_PARTICLES, DIAG_PARAMS, DIAG_AMP, \
+    DIAG_TIMERS = range(9)
+SC = dict(step=0, time=1, n_neutral=2, n_e=3, n_pos=4, events=5, u_field=6, ke_e=7, ke_pos=8,
+          e_gap=9, e_abs=10, gauss_max=11, rho_max=12, health=13, slots=14)
+
+
+class PicError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {STATUS.get(code, code)} ({code})")
+        self.code = code
+
+
+class Material(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("gap_eV", "n_index", "density_gcc", "molar_mass_gmol",
+                                            "me_star", "mh_star", "pos_mass_kg")]
+
+
+class Layer(C.Structure):
+    _fields_ = [("material", C.c_int32), ("reserved", C.c_int32), ("lo_m", C.c_double),
+                ("hi_m", C.c_double)]
+
+
+class Laser(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("lambda_m", "fwhm_s", "peak_Wcm2", "fluence_Jcm2",
+                                            "waist_m", "t_peak_s", "cep_rad")] + \
+               [("envelope", C.c_int32), ("pol_axis", C.c_int32)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class Config(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("abi_version", C.c_uint32), ("ndim", C.c_int32),
+                ("transverse_bc", C.c_int32), ("n", C.c_int64 * 3), ("dx_m", C.c_double * 3),
+                ("cfl", C.c_double), ("nsteps", C.c_int64), ("nmat", C.c_int32),
+                ("nlayer", C.c_int32), ("mats", C.POINTER(Material)), ("layers", C.POINTER(Layer)),
+                ("ppc", C.c_int32), ("shape_order", C.c_int32), ("T_K", C.c_double),
+                ("keldysh_terms", C.c_int32), ("reserved0", C.c_int32), ("seed", C.c_uint64),
+                ("laser", Laser), ("particle_capacity", C.c_int64), ("preionize_eV", C.c_double),
+                ("stream", C.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN),
+                ("alloc_user", C.c_void_p)]
+
+
+class Params(C.Structure):
+    _fields_ = [("dt", C.c_double), ("Cd", C.c_double * 3), ("kmur", C.c_double * 3),
+                ("ie", C.c_double * 8), ("nwin", C.c_int64), ("E0", C.c_double),
+                ("t_peak", C.c_double), ("amp_cut", C.c_double * 8), ("amp_sat", C.c_double * 8),
+                ("n_neutral", C.c_int64), ("capacity", C.c_int64)]
+
+
+class Particle(C.Structure):
+    _fields_ = [("cell", C.c_int32 * 3), ("kind", C.c_int32), ("off", C.c_float * 3),
+                ("u", C.c_float * 3)]
+
+
+PARTICLE_DTYPE = np.dtype([("cell", "<i4", 3), ("kind", "<i4"), ("off", "<f4", 3), ("u", "<f4", 3)])
+assert PARTICLE_DTYPE.itemsize == C.sizeof(Particle)
+
+
+class State(C.Structure):
+    _fields_ = [("step", C.c_int64), ("E", C.POINTER(C.c_float) * 3), ("b", C.POINTER(C.c_float) * 3),
+                ("n_particles", C.c_int64), ("particles", C.POINTER(Particle)),
+                ("reset_window", C.c_int32), ("reserved", C.c_int32)]
+
+
+SYMBOLS = ["pic_init", "pic_step", "pic_diag", "pic_set_state", "pic_footprint", "pic_canonical",
+           "pic_keldysh_rate", "pic_table_probe", "pic_table_probe_device", "pic_batch_create",
+           "pic_batch_step", "pic_batch_add", "pic_batch_remove", "pic_batch_destroy",
+           "pic_set_timing", "pic_destroy", "pic_status_str"]
+
+
+def lib():
+    """Load libpic.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2502_13695_amd.build")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        sig = {
+            "pic_init": ([C.POINTER(Config), C.POINTER(vp)], C.c_int),
+            "pic_step": ([vp, i64], C.c_int),
+            "pic_diag": ([vp, C.c_int, vp, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
+            "pic_set_state": ([vp, C.POINTER(State)], C.c_int),
+            "pic_footprint": ([C.POINTER(Config), C.POINTER(C.c_size_t)], C.c_int),
+            "pic_canonical": ([C.POINTER(Config), C.POINTER(Params)], C.c_int),
+            "pic_keldysh_rate": ([C.POINTER(Material), C.c_double, i32, C.POINTER(C.c_double), i64,
+                                  C.POINTER(C.c_double)], C.c_int),
+            "pic_table_probe": ([C.POINTER(Config), i32, C.POINTER(C.c_float), i64,
+                                 C.POINTER(C.c_float)], C.c_int),
+            "pic_table_probe_device": ([vp, i32, C.POINTER(C.c_float), i64, C.POINTER(C.c_float)],
+                                       C.c_int),
+            "pic_batch_create": ([C.POINTER(vp), i32, C.POINTER(vp)], C.c_int),
+            "pic_batch_step": ([vp, i64], C.c_int),
+            "pic_batch_add": ([vp, vp], C.c_int),
+            "pic_batch_remove": ([vp, vp], C.c_int),
+            "pic_batch_destroy": ([vp], None),
+            "pic_set_timing": ([vp, i32], C.c_int),
+            "pic_destroy": ([vp], None),
+            "pic_status_str": ([C.c_int], C.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _LIB = L
+    return _LIB
+
+
+def _check(code, what):
+    if code != PIC_OK:
+        raise PicError(code, what)
+
+
+def make_config(cfg, stream=None, alloc=None, free=None):
+    """Marshal a workload dictionary into a pic_config.  Returns (Config, keepalive)."""
+    mats = (Material * max(1, len(cfg["materials"])))()
+    for i, m in enumerate(cfg["materials"]):
+        for k in ("gap_eV", "n_index", "density_gcc", "molar_mass_gmol", "me_star", "mh_star"):
+            setattr(mats[i], k, float(m[k]))
+        mats[i].pos_mass_kg = float(m.get("pos_mass_kg", 0.0))
+    layers = (Layer * max(1, len(cfg["layers"])))()
+    for i, (m, lo, hi) in enumerate(cfg["layers"]):
+        layers[i].material = int(m)
+        layers[i].lo_m = float(lo)
+        layers[i].hi_m = float(hi)
+    c = Config()
+    c.struct_size = C.sizeof(Config)
+    c.abi_version = ABI_VERSION
+    c.ndim = int(cfg["ndim"])
+    c.transverse_bc = BC[cfg.get("transverse_bc", "outflow")]
+    for d in range(c.ndim):
+        c.n[d] = int(cfg["n"][d])
+        c.dx_m[d] = float(cfg["dx"][d])
+    c.cfl = float(cfg["cfl"])
+    c.nsteps = int(cfg["nsteps"])
+    c.nmat = len(cfg["materials"])
+    c.nlayer = len(cfg["layers"])
+    c.mats = mats
+    c.layers = layers
+    c.ppc = int(cfg["ppc"])
+    c.shape_order = int(cfg.get("shape_order", 2))
+    c.T_K = float(cfg.get("T_K", 300.0))
+    c.keldysh_terms = int(cfg.get("keldysh_terms", 500))
+    c.seed = int(cfg["seed"])
+    L = cfg["laser"]
+    for k in ("lambda_m", "fwhm_s", "cep_rad", "waist_m", "t_peak_s"):
+        setattr(c.laser, k, float(L.get(k, 0.0)))
+    c.laser.peak_Wcm2 = float(L.get("peak_Wcm2", 0.0))
+    c.laser.fluence_Jcm2 = float(L.get("fluence_Jcm2", 0.0))
+    c.laser.envelope = ENV[L.get("envelope", "gauss")]
+    c.laser.pol_axis = int(L.get("pol_axis", 1))
+    c.particle_capacity = int(cfg.get("particle_capacity", 0))
+    c.preionize_eV = float(cfg.get("preionize_eV", 0.0))
+    c.stream = stream
+    if alloc is not None:
+        c.alloc = alloc
+        c.free = free
+    return c, (mats, layers, alloc, free)
+
+
+def _torch_allocator():
+    """Device allocator callbacks backed by torch's caching allocator."""
+    import torch
+    dev = torch.cuda.current_device()
+
+    def _a(nbytes, user):
+        try:
+            return int(torch.cuda.caching_allocator_alloc(int(nbytes), dev))
+        except Exception:
+            return None
+
+    def _f(ptr, user):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return ALLOC_FN(_a), FREE_FN(_f)
+
+
+def domain_shape(ndim, n, periodic_t, which, comp):
+    out = []
+    for d in range(3):
+        if d >= ndim:
+            out.append(1)
+            continue
+        half = (d == comp) if which == "E" else (d != comp)
+        out.append(n[d] if (half or (periodic_t and d > 0)) else n[d] + 1)
+    return tuple(out)
+
+
+class Context:
+    """One run (pic_init .. pic_destroy)."""
+
+    def __init__(self, cfg, use_torch=True):
+        L = lib()
+        self.cfg = cfg
+        self._keep = []
+        stream = None
+        alloc = free = None
+        if use_torch:
+            try:
+                import torch
+                if torch.cuda.is_available():
+                    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+                    alloc, free = _torch_allocator()
+            except ImportError:
+                pass
+        c, keep = make_config(cfg, stream=stream, alloc=alloc, free=free)
+        self._config = c
+        self._keep.append(keep)
+        h = C.c_void_p()
+        _check(L.pic_init(C.byref(c), C.byref(h)), "pic_init")
+        self.h = h
+        self.ndim = int(cfg["ndim"])
+        self.n = [int(cfg["n"][d]) if d < self.ndim else 1 for d in range(3)]
+        self.periodic_t = cfg.get("transverse_bc", "outflow") == "periodic"
+
+    # -------------------------------------------------------------- control
+    def step(self, n=1):
+        _check(lib().pic_step(self.h, int(n)), "pic_step")
+
+    def set_timing(self, on):
+        _check(lib().pic_set_timing(self.h, int(on)), "pic_set_timing")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pic_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------- diagnostics
+    def _diag_bytes(self, kind):
+        n = C.c_size_t()
+        _check(lib().pic_diag(self.h, kind, None, 0, C.byref(n)), "pic_diag(size)")
+        return n.value
+
+    def _diag(self, kind, dtype):
+        nb = self._diag_bytes(kind)
+        buf = np.zeros(max(1, nb // np.dtype(dtype).itemsize), dtype=dtype)
+        w = C.c_size_t()
+        _check(lib().pic_diag(self.h, kind, buf.ctypes.data_as(C.c_void_p), buf.nbytes, C.byref(w)),
+               "pic_diag")
+        return buf[: w.value // np.dtype(dtype).itemsize]
+
+    def scalars(self):
+        v = self._diag(DIAG_SCALARS, np.float64)
+        return {k: float(v[i]) for k, i in SC.items()}
+
+    def _split(self, flat, which_list):
+        out = []
+        o = 0
+        for which, comp in which_list:
+            shp = domain_shape(self.ndim, self.n, self.periodic_t, which, comp)
+            cnt = shp[0] * shp[1] * shp[2]
+            out.append(flat[o:o + cnt].reshape(shp[::-1]).transpose(2, 1, 0))
+            o += cnt
+        return out
+
+    def fields(self):
+        """(E, b): lists of 3 FP64 arrays indexed [i, j, k] on their own positions."""
+        flat = self._diag(DIAG_FIELDS, np.float64)
+        arrs = self._split(flat, [("E", 0), ("E", 1), ("E", 2), ("b", 0), ("b", 1), ("b", 2)])
+        return arrs[:3], arrs[3:]
+
+    def _node_grid(self, kind, dtype):
+        flat = self._diag(kind, dtype)
+        shp = domain_shape(self.ndim, self.n, self.periodic_t, "node", -1)
+        shp = tuple(self.n[d] + (0 if (self.periodic_t and d > 0) else 1) if d < self.ndim else 1
+                    for d in range(3))
+        return flat.reshape(shp[::-1]).transpose(2, 1, 0)
+
+    def ne_grid(self):
+        return self._node_grid(DIAG_NE, np.float64)
+
+    def ue_grid(self):
+        return self._node_grid(DIAG_UE, np.float64)
+
+    def amp(self):
+        return self._node_grid(DIAG_AMP, np.float32)
+
+    def events(self):
+        v = self._diag(DIAG_EVENTS, np.int64)
+        return v.reshape(-1, 2)
+
+    def particles(self):
+        nb = self._diag_bytes(DIAG_PARTICLES)
+        buf = np.zeros(nb // PARTICLE_DTYPE.itemsize, dtype=PARTICLE_DTYPE)
+        w = C.c_size_t()
+        if nb:
+            _check(lib().pic_diag(self.h, DIAG_PARTICLES, buf.ctypes.data_as(C.c_void_p), buf.nbytes,
+                                  C.byref(w)), "pic_diag(particles)")
+        return buf
+
+    def params(self):
+        p = Params()
+        w = C.c_size_t()
+        _check(lib().pic_diag(self.h, DIAG_PARAMS, C.byref(p), C.sizeof(p), C.byref(w)), "pic_diag(params)")
+        return p
+
+    def timers(self):
+        return self._diag(DIAG_TIMERS, np.float64)
+
+    def set_state(self, step, E=None, b=None, particles=None, reset_window=True):
+        """Overwrite fields ([i, j, k] arrays on their own positions), charged
+        particles (PARTICLE_DTYPE records) and the step index."""
+        S = State()
+        S.step = int(step)
+        keep = []
+        for q in range(3):
+            for arrs, name in ((E, "E"), (b, "b")):
+                if arrs is None:
+                    continue
+                a = np.ascontiguousarray(np.asarray(arrs[q], dtype=np.float32).transpose(2, 1, 0)).ravel()
+                keep.append(a)
+                getattr(S, name)[q] = a.ctypes.data_as(C.POINTER(C.c_float))
+        if particles is not None and len(particles):
+            p = np.ascontiguousarray(particles, dtype=PARTICLE_DTYPE)
+            keep.append(p)
+            S.n_particles = len(p)
+            S.particles = p.ctypes.data_as(C.POINTER(Particle))
+        S.reset_window = int(bool(reset_window))
+        _check(lib().pic_set_state(self.h, C.byref(S)), "pic_set_state")
+
+    def table_probe_device(self, mat, A):
+        A = np.ascontiguousarray(A, dtype=np.float32)
+        P = np.zeros_like(A)
+        _check(lib().pic_table_probe_device(self.h, int(mat), A.ctypes.data_as(C.POINTER(C.c_float)),
+                                            len(A), P.ctypes.data_as(C.POINTER(C.c_float))),
+               "pic_table_probe_device")
+        return P
+
+
+class Batch:
+    """Independent instances advanced together, one launch per phase."""
+
+    def __init__(self, contexts=()):
+        arr = (C.c_void_p * max(1, len(contexts)))(*[c.h for c in contexts])
+        h = C.c_void_p()
+        _check(lib().pic_batch_create(arr, len(contexts), C.byref(h)), "pic_batch_create")
+        self.h = h
+
+    def step(self, n=1):
+        _check(lib().pic_batch_step(self.h, int(n)), "pic_batch_step")
+
+    def add(self, ctx):
+        _check(lib().pic_batch_add(self.h, ctx.h), "pic_batch_add")
+
+    def remove(self, ctx):
+        _check(lib().pic_batch_remove(self.h, ctx.h), "pic_batch_remove")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pic_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------ host-only calls
+def canonical(cfg):
+    c, keep = make_config(cfg)
+    p = Params()
+    _check(lib().pic_canonical(C.byref(c), C.byref(p)), "pic_canonical")
+    return p
+
+
+def footprint(cfg):
+    c, keep = make_config(cfg)
+    n = C.c_size_t()
+    _check(lib().pic_footprint(C.byref(c), C.byref(n)), "pic_footprint")
+    return n.value
+
+
+def keldysh_rate(material, lam, A, terms=500):
+    m = Material()
+    for k in ("gap_eV", "n_index", "density_gcc", "molar_mass_gmol", "me_star", "mh_star"):
+        setattr(m, k, float(material[k]))
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    W = np.zeros_like(A)
+    _check(lib().pic_keldysh_rate(C.byref(m), float(lam), int(terms),
+                                  A.ctypes.data_as(C.POINTER(C.c_double)), len(A),
+                                  W.ctypes.data_as(C.POINTER(C.c_double))), "pic_keldysh_rate")
+    return W
+
+
+def table_probe(cfg, mat, A):
+    c, keep = make_config(cfg)
+    A = np.ascontiguousarray(A, dtype=np.float32)
+    P = np.zeros_like(A)
+    _check(lib().pic_table_probe(C.byref(c), int(mat), A.ctypes.data_as(C.POINTER(C.c_float)), len(A),
+                                 P.ctypes.data_as(C.POINTER(C.c_float))), "pic_table_probe")
+    return P

@@ -1,0 +1,249 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+* one step from a seeded random state (fields, relativistic particles) in
+  1D / 2D / 3D, shape order 1 and 2, outflow and periodic transverse
+  boundaries: fields and every particle element by element;
+* the device rate table against the oracle's in-situ Keldysh probability;
+* whole runs (laser through a slab, ionization births): fields (relative L2),
+  ionization events (id, step), electron count and absorbed energy, the
+  windowed amplitude, the Gauss law;
+* the pre-ionized stress variant and batched instances against single runs.
+
+Tolerances follow from FP32 arithmetic (the kernel's precision) against FP64:
+one step ~1e-6 relative; whole-run fields relative L2 <= 1e-5; electron count
+and absorbed energy within 0.5 %; events identical except where the FP32
+probability sits within its own rounding of the draw.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import pic as OP
+from oracle import keldysh as K
+from oracle.problem import Problem
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_2502_13695_amd import pic
+    pic.lib()
+    return pic
+
+
+def _to_oracle_state(sim, st):
+    for c in range(3):
+        sim.E[c][sim._domain_slices(sim.stE[c])] = st["E"][c]
+        sim.b[c][sim._domain_slices(sim.stB[c])] = st["b"][c]
+    pos = st["cell"].astype(np.float64) + st["off"].astype(np.float64)
+    sim.px = pos
+    sim.pu = st["u"].astype(np.float32).astype(np.float64)
+    sim.pk = st["kind"].astype(np.int64)
+
+
+def _records(P, st, ndim):
+    rec = np.zeros(len(st["kind"]), dtype=P.PARTICLE_DTYPE)
+    rec["cell"][:, :ndim] = st["cell"][:, :ndim]
+    rec["off"] = st["off"]
+    rec["u"] = st["u"].astype(np.float32)
+    rec["kind"] = st["kind"]
+    return rec
+
+
+def _state_f32(st):
+    st = dict(st)
+    st["E"] = [a.astype(np.float32).astype(np.float64) for a in st["E"]]
+    st["b"] = [a.astype(np.float32).astype(np.float64) for a in st["b"]]
+    return st
+
+
+CASES = [
+    (1, 2, "outflow"), (1, 1, "outflow"),
+    (2, 2, "outflow"), (2, 1, "outflow"), (2, 2, "periodic"),
+    (3, 2, "periodic"), (3, 2, "outflow"), (3, 1, "periodic"),
+]
+
+
+@pytest.mark.parametrize("ndim,order,bc", CASES)
+def test_one_step_fields_and_particles(P, ndim, order, bc):
+    n = {1: [200], 2: [40, 24], 3: [20, 12, 10]}[ndim]
+    dx = W.LAMBDA / 30
+    cfg = dict(ndim=ndim, n=n, dx=[dx] * ndim, cfl=0.95, nsteps=10, transverse_bc=bc,
+               # two indices (1.45, 2.1) with a 9 eV gap: these fields ionize nothing
+               materials=[W.silica_like(), dict(W.high_index(), gap_eV=9.0)],
+               layers=[(0, 0.3 * n[0] * dx, 0.5 * n[0] * dx), (1, 0.5 * n[0] * dx, 0.62 * n[0] * dx)],
+               ppc=2, T_K=300.0, shape_order=order, keldysh_terms=500, seed=11,
+               laser=dict(lambda_m=W.LAMBDA, fwhm_s=W.cycles(2), peak_Wcm2=1e12, envelope="gauss",
+                          pol_axis=1), particle_capacity=0, preionize_eV=0.0)
+    st = _state_f32(W.random_state(cfg, 3000, seed=100 + 10 * ndim + order, e_scale=1e9, u_scale=0.6))
+    ctx = P.Context(cfg)
+    ctx.set_state(0, st["E"], st["b"], _records(P, st, ndim))
+    ctx.step(1)
+    E_g, b_g = ctx.fields()
+    parts = ctx.particles()
+    sim = OP.Sim(cfg)
+    _to_oracle_state(sim, st)
+    sim.step()
+    scale = 1e9
+    for c in range(3):
+        Eo = sim.interior_field("E", c)
+        bo = sim.interior_field("b", c)
+        assert E_g[c].shape == Eo.shape and b_g[c].shape == bo.shape
+        assert np.max(np.abs(E_g[c] - Eo)) < 2e-6 * scale, ("E", c)
+        assert np.max(np.abs(b_g[c] - bo)) < 2e-6 * scale, ("b", c)
+    # no births from these weak fields; all particles stay in the box
+    assert len(sim.events) == 0
+    assert len(parts) == len(sim.px)
+    pos_g = parts["cell"][:, :ndim] + parts["off"][:, :ndim].astype(np.float64)
+    if bc == "periodic":
+        d = pos_g - sim.px[:, :ndim]
+        for k in range(1, ndim):
+            d[:, k] -= n[k] * np.round(d[:, k] / n[k])
+    else:
+        d = pos_g - sim.px[:, :ndim]
+    assert np.max(np.abs(d)) < 2e-5
+    assert np.max(np.abs(parts["u"] - sim.pu)) < 2e-6 * max(1.0, np.max(np.abs(sim.pu)))
+    assert np.array_equal(parts["kind"], sim.pk)
+    ctx.close()
+
+
+@pytest.mark.parametrize("cfg", [W.config_2d(), W.config_3d()])
+def test_device_rate_table(P, cfg):
+    small = dict(cfg, n=[64, 8, 8][:cfg["ndim"]], layers=[(m, 20 * cfg["dx"][0] + i * 1e-9,
+                                                         30 * cfg["dx"][0] + i * 1e-9)
+                                                        for i, (m, _, _) in enumerate(cfg["layers"][:2])])
+    ctx = P.Context(small)
+    o = Problem(small)
+    for mi, mt in enumerate(o.mats):
+        A = np.geomspace(1e9, 9e10, 50000).astype(np.float32)
+        Pd = ctx.table_probe_device(mi, A)
+        Wo = K.keldysh_rate(A.astype(np.float64), mt.gap_eV, mt.mred, o.laser.lam)
+        Po = -np.expm1(-Wo * o.dt / mt.n0)
+        assert not np.any((Pd == 0) & (Po >= 2.0 ** -33))
+        sel = Po >= 2.0 ** -33
+        assert np.max(np.abs(Pd[sel] / Po[sel] - 1)) < 1e-6
+        # the device lookup equals the host lookup up to libm rounding
+        Ph = P.table_probe(small, mi, A)
+        assert np.max(np.abs(Pd[sel] / Ph[sel] - 1)) < 3e-7
+    ctx.close()
+
+
+def _run_both(P, cfg, nsteps):
+    ctx = P.Context(cfg)
+    ctx.step(nsteps)
+    sim = OP.Sim(cfg)
+    sim.run(nsteps)
+    return ctx, sim
+
+
+def _field_l2(ctx, sim):
+    E_g, b_g = ctx.fields()
+    num = den = 0.0
+    for c in range(3):
+        for g_, o_ in ((E_g[c], sim.interior_field("E", c)), (b_g[c], sim.interior_field("b", c))):
+            num += np.sum((g_ - o_) ** 2)
+            den += np.sum(o_ ** 2)
+    return math.sqrt(num / den)
+
+
+def _compare_run(P, ctx, sim, l2_tol=1e-5, rel_tol=5e-3, min_events=1):
+    l2 = _field_l2(ctx, sim)
+    assert l2 < l2_tol, l2
+    sc = ctx.scalars()
+    ev_g = set(map(tuple, ctx.events().tolist()))
+    ev_o = sim.event_set()
+    assert len(ev_o) >= min_events
+    inter = len(ev_g & ev_o)
+    union = len(ev_g | ev_o)
+    # identical event sets (a difference needs a draw within the FP32 rounding of P)
+    assert union - inter <= max(1, int(1e-4 * union)), (len(ev_g), len(ev_o), inter)
+    assert sc["events"] == len(ev_g)
+    ne_o = float(np.sum(sim.pk % 2 == 0))
+    assert abs(sc["n_e"] - ne_o) <= max(1.0, rel_tol * ne_o)
+    eabs_o = sim.kinetic_energy() + sim.energy_gap
+    if eabs_o > 0:
+        assert abs(sc["e_abs"] / eabs_o - 1) < rel_tol, (sc["e_abs"], eabs_o)
+    # the device Gauss residual stays at FP32 roundoff of the charge density
+    assert sc["gauss_max"] <= 1e-4 * max(sc["rho_max"], 1.0)
+    return l2, sc
+
+
+def test_run_1d_slab_high_intensity(P):
+    cfg = W.config_1d(hi=True, ppc=10, nsteps=1400)
+    ctx, sim = _run_both(P, cfg, 1400)
+    l2, sc = _compare_run(P, ctx, sim, min_events=20)
+    # amplitude window against the oracle's brute-force maximum
+    A_g = ctx.amp()[:, 0, 0].astype(np.float64)
+    A_o = sim.A[OP.G:OP.G + cfg["n"][0] + 1, 0, 0]
+    mat = np.nonzero(sim.P.mat_node >= 0)[0]
+    rng = slice(mat[0] - 1, mat[-1] + 2)
+    assert np.max(np.abs(A_g[rng] - A_o[rng])) <= 2e-5 * np.max(A_o[rng])
+    # electron density grid
+    ne_g = ctx.ne_grid()[:, 0, 0]
+    ne_o = sim.density_grid("e")[OP.G:OP.G + cfg["n"][0] + 1, 0, 0]
+    assert np.max(np.abs(ne_g - ne_o)) <= 1e-3 * max(np.max(ne_o), 1.0)
+    ctx.close()
+
+
+def test_run_2d_slab_gaussian_beam(P):
+    cfg = W.config_2d(nx=192, ny=48, nsteps=520, ppc=2, peak=3e14, slab_cells=12, waist=0.6e-6)
+    ctx, sim = _run_both(P, cfg, 520)
+    _compare_run(P, ctx, sim, min_events=20)
+    ctx.close()
+
+
+def test_run_3d_mirror_periodic(P):
+    dx = W.LAMBDA / 24
+    cfg = W.config_3d(nx=96, ny=8, nz=8, nsteps=380, ppc=2, fluence=1.5, front=24)
+    ctx, sim = _run_both(P, cfg, 380)
+    _compare_run(P, ctx, sim, min_events=20)
+    ctx.close()
+
+
+def test_stress_preionized_2d(P):
+    cfg = W.config_stress(W.config_2d(nx=96, ny=32, nsteps=60, ppc=4, slab_cells=20, peak=1e13,
+                                      bc="periodic", waist=0.0), eV=3.0)
+    ctx, sim = _run_both(P, cfg, 60)
+    sc = ctx.scalars()
+    assert sc["n_e"] == np.sum(sim.pk % 2 == 0)
+    l2 = _field_l2(ctx, sim)
+    assert l2 < 1e-4, l2
+    ke_o = sim.kinetic_energy("e")
+    assert abs(sc["ke_e"] / ke_o - 1) < 1e-4
+    assert sc["gauss_max"] <= 1e-4 * sc["rho_max"]
+    ctx.close()
+
+
+def test_batch_matches_single_runs(P):
+    cfgs = [W.config_2d(nx=128, ny=32, nsteps=200, ppc=2, peak=3e14, slab_cells=10, waist=0.6e-6, seed=s)
+            for s in (5, 6)]
+    cfgs.append(W.config_1d(hi=True, ppc=4, nsteps=200, n=256))
+    singles = []
+    for c in cfgs:
+        x = P.Context(c)
+        x.step(200)
+        singles.append((x.fields(), x.scalars(), set(map(tuple, x.events().tolist()))))
+        x.close()
+    ctxs = [P.Context(c) for c in cfgs]
+    b = P.Batch(ctxs[:2])
+    b.step(120)
+    b.add(ctxs[2])          # joins at a step boundary, its own step counter
+    b.step(80)
+    b.remove(ctxs[2])
+    ctxs[2].step(120)
+    b.step(0)
+    for x, (f_s, sc_s, ev_s), in zip(ctxs, singles):
+        f_b = x.fields()
+        num = sum(np.sum((a - c) ** 2) for a, c in zip(f_b[0] + f_b[1], f_s[0] + f_s[1]))
+        den = sum(np.sum(c ** 2) for c in f_s[0] + f_s[1])
+        assert math.sqrt(num / den) < 1e-5
+        assert set(map(tuple, x.events().tolist())) == ev_s
+    b.close()
+    for x in ctxs:
+        x.close()

@@ -1,0 +1,131 @@
+"""Host-side checks of the native library (no GPU compute): the C ABI exports
+every symbol include/pic.h declares, the canonical discrete problem equals the
+oracle's bit for bit, the C++ Keldysh rate and the FP32 rate table agree with
+the oracle's in-situ FP64 evaluation (Sec. 2.1, Eq. 1-3), including both sides
+of every channel closing, and invalid configurations are rejected."""
+
+import os
+import re
+
+import numpy as np
+import pytest
+from scipy.optimize import brentq
+
+import workloads as W
+from oracle import keldysh as K
+from oracle.problem import Problem
+
+P = pytest.importorskip("paper_2502_13695_amd.pic")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib_or_skip():
+    if not os.path.exists(P.LIB_PATH):
+        pytest.skip("libpic.so not built")
+    return P.lib()
+
+
+def test_exports_every_declared_symbol():
+    import subprocess
+    _lib_or_skip()
+    hdr = open(os.path.join(ROOT, "include", "pic.h")).read()
+    declared = set(re.findall(r"\b(pic_[a-z_]+)\s*\(", hdr))
+    assert len(declared) >= 15
+    out = subprocess.run(["nm", "-D", "--defined-only", P.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (pic_\w+)", out))
+    assert declared <= exported, declared - exported
+    assert set(P.SYMBOLS) == declared
+
+
+@pytest.mark.parametrize("cfg", [W.config_1d(), W.config_1d(hi=True), W.config_2d(), W.config_3d(),
+                                 W.batch_scan(4)[3], W.config_2d(nx=100, ny=37)])
+def test_canonical_problem_bitwise_equal(cfg):
+    _lib_or_skip()
+    p = P.canonical(cfg)
+    o = Problem(cfg)
+    assert p.dt == o.dt
+    assert list(p.Cd)[:o.D] == o.Cd[:o.D]
+    assert list(p.kmur)[:o.D] == o.kmur[:o.D]
+    assert p.nwin == o.nwin
+    assert [p.ie[m] for m in range(len(o.mats))] == [m.ie for m in o.mats]
+    assert abs(p.E0 / o.laser.E0 - 1) < 1e-15
+    nmat_cells = int(np.sum(o.mat_cell >= 0)) * o.n[1] * o.n[2]
+    assert p.n_neutral == nmat_cells * o.ppc
+
+
+def test_keldysh_rate_cpp_equals_oracle():
+    _lib_or_skip()
+    for m in (W.silica_like(), W.high_index(), W.table1_sio2(), W.table1_hfo2()):
+        A = np.geomspace(1e9, 1e11, 300)
+        mr = 1 / (1 / m["me_star"] + 1 / m["mh_star"])
+        w1 = P.keldysh_rate(m, 800e-9, A)
+        w2 = K.keldysh_rate(A, m["gap_eV"], mr, 800e-9)
+        assert np.max(np.abs(w1 / w2 - 1)) < 1e-13
+
+
+def _closings(mt, lam, lo, hi):
+    f0 = lambda A, k: K.keldysh_parts(np.array([A]), mt.gap_eV, mt.mred, lam)["x"][0] - k
+    out = []
+    x_lo = K.keldysh_parts(np.array([lo]), mt.gap_eV, mt.mred, lam)["x"][0]
+    x_hi = K.keldysh_parts(np.array([hi]), mt.gap_eV, mt.mred, lam)["x"][0]
+    for k in range(int(np.floor(x_lo)) + 1, int(np.floor(x_hi)) + 1):
+        out.append(brentq(lambda A: f0(A, k), lo, hi, xtol=1e-6, rtol=1e-15))
+    return out
+
+
+@pytest.mark.parametrize("cfg", [W.config_2d(), W.config_3d()])
+def test_rate_table_against_insitu_fp64(cfg):
+    """P(A) from the FP32 table vs 1 - exp(-W dt/n0) in FP64 at the same FP32 A,
+    over [A_cut, A_sat] and at the FP32 neighbours of every channel closing."""
+    _lib_or_skip()
+    o = Problem(cfg)
+    for mi, mt in enumerate(o.mats):
+        A = np.geomspace(1e9, 9e10, 30000).astype(np.float32)
+        for Ak in _closings(mt, o.laser.lam, 1e9, 9e10):
+            f = np.float32(Ak)
+            nb = [f]
+            lo = hi = f
+            for _ in range(3):
+                lo = np.nextafter(lo, np.float32(0))
+                hi = np.nextafter(hi, np.float32(np.inf))
+                nb += [lo, hi]
+            A = np.concatenate([A, np.array(nb, dtype=np.float32),
+                                (np.float64(Ak) * (1 + np.linspace(-1e-3, 1e-3, 41))).astype(np.float32)])
+        Pt = P.table_probe(cfg, mi, A)
+        Wo = K.keldysh_rate(A.astype(np.float64), mt.gap_eV, mt.mred, o.laser.lam)
+        Po = -np.expm1(-Wo * o.dt / mt.n0)
+        # anything that could fire against a 32-bit draw is tabulated
+        assert not np.any((Pt == 0) & (Po >= 2.0 ** -33))
+        sel = Po >= 2.0 ** -33
+        rel = np.abs(Pt[sel] / Po[sel] - 1)
+        assert np.max(rel) < 1e-6
+        assert np.all(Pt[~sel] < 2.0 ** -32)
+
+
+def test_invalid_configs_rejected():
+    _lib_or_skip()
+    import ctypes as C
+    c, keep = P.make_config(W.config_1d())
+    c.abi_version = 99
+    h = C.c_void_p()
+    assert P.lib().pic_init(C.byref(c), C.byref(h)) == -7
+    c, keep = P.make_config(W.config_1d())
+    c.ndim = 4
+    assert P.lib().pic_init(C.byref(c), C.byref(h)) == -1
+    c, keep = P.make_config(W.config_1d())
+    c.shape_order = 3
+    assert P.lib().pic_init(C.byref(c), C.byref(h)) == -1
+    with pytest.raises(P.PicError):
+        P.canonical(dict(W.config_1d(), cfl=1.5))
+    with pytest.raises(P.PicError):
+        P.canonical(dict(W.config_2d(), n=[2, 512]))
+    assert P.lib().pic_status_str(-6) == b"charged-particle capacity exceeded"
+
+
+def test_footprint_scales_with_problem():
+    _lib_or_skip()
+    f2 = P.footprint(W.config_2d())
+    f3 = P.footprint(W.config_3d())
+    assert 50e6 < f2 < 2e9
+    assert f3 > f2
