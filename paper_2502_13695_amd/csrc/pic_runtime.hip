@@ -78,7 +78,11 @@ pic_status plan(const pic_config* cfg, const Canon& c, const std::vector<TableHo
   if (cfg->preionize_eV > 0) cap = std::max<int64_t>(cap, 2 * L->nneut);
   if (cap > INT_MAX - 16 || L->nneut > ((int64_t)1 << 40)) return PIC_E_INVAL;
   L->capacity = cap;
-  L->nsrc = (int)std::min<int64_t>(cfg->nsteps + 2, 1 << 26);
+  // source samples cover the planned steps and the whole pulse (Gaussian: to
+  // t0 + 8 fwhm, where the envelope is below 1e-38; sin^2: its full length)
+  const double t_end = c.env == PIC_ENV_GAUSS ? c.t0 + 8.0 * c.fwhm : c.t0 + 0.5 * c.T;
+  const int64_t pulse_steps = (int64_t)std::ceil(t_end / c.dt) + 2;
+  L->nsrc = (int)std::min<int64_t>(std::max<int64_t>(cfg->nsteps + 2, pulse_steps), 1 << 26);
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t r = o;
@@ -306,6 +310,7 @@ pic_status pic_footprint(const pic_config* cfg, size_t* bytes) {
 pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
   if (!cfg_in || !out) return PIC_E_INVAL;
   *out = nullptr;
+  (void)hipGetLastError();   // launch errors are checked below; drop stale ones
   pic_ctx* c = new (std::nothrow) pic_ctx();
   if (!c) return PIC_E_NOMEM;
   c->cfg = *cfg_in;
@@ -538,6 +543,7 @@ pic_status pic_set_timing(pic_ctx* c, int32_t on) {
 pic_status pic_step(pic_ctx* c, int64_t nsteps) {
   if (!c || nsteps < 0) return PIC_E_INVAL;
   if (c->latched != PIC_OK) return PIC_E_STATE;
+  (void)hipGetLastError();
   for (int64_t s = 0; s < nsteps; ++s) enqueue_step(c);
   c->step += nsteps;
   if (hipGetLastError() != hipSuccess) return PIC_E_DEVICE;
@@ -746,6 +752,7 @@ pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size
     return PIC_OK;
   }
   // ---- SCALARS
+  (void)hipGetLastError();
   double* o = (double*)host_out;
   std::memset(o, 0, sizeof(double) * PIC_SC_COUNT);
   HIP_OK(hipMemsetAsync(c->d_ctr->acc, 0, sizeof(c->d_ctr->acc), s));
@@ -877,6 +884,7 @@ pic_status pic_batch_step(pic_batch* b, int64_t nsteps) {
     if (st != PIC_OK) return st;
   }
   hipStream_t s = b->stream;
+  (void)hipGetLastError();
   for (int64_t t = 0; t < nsteps; ++t) {
     for (auto& cl : b->classes) {
       const int np1 = cl.n + 1;

@@ -100,6 +100,12 @@ def lib():
     if _LIB is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2502_13695_amd.build")
+        # torch ships its own HIP runtime; load it first so that libpic.so binds
+        # to the same runtime (one device context, torch-allocated memory valid)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
         sig = {

@@ -90,26 +90,32 @@ def test_one_step_fields_and_particles(P, ndim, order, bc):
     sim = OP.Sim(cfg)
     _to_oracle_state(sim, st)
     sim.step()
-    scale = 1e9
+    # FP32 against FP64: a few ulp of the largest field (the deposited
+    # current dominates E after the step)
+    scale = max(1e9, max(np.max(np.abs(sim.interior_field(w, c))) for w in "Eb" for c in range(3)))
     for c in range(3):
         Eo = sim.interior_field("E", c)
         bo = sim.interior_field("b", c)
         assert E_g[c].shape == Eo.shape and b_g[c].shape == bo.shape
         assert np.max(np.abs(E_g[c] - Eo)) < 2e-6 * scale, ("E", c)
         assert np.max(np.abs(b_g[c] - bo)) < 2e-6 * scale, ("b", c)
-    # no births from these weak fields; all particles stay in the box
-    assert len(sim.events) == 0
+    # the deposited current is strong enough to ionize: same events, same births
+    ev_g = set(map(tuple, ctx.events().tolist()))
+    assert ev_g == sim.event_set()
     assert len(parts) == len(sim.px)
+    npre = len(st["kind"])
     pos_g = parts["cell"][:, :ndim] + parts["off"][:, :ndim].astype(np.float64)
+    d = pos_g[:npre] - sim.px[:npre, :ndim]
     if bc == "periodic":
-        d = pos_g - sim.px[:, :ndim]
         for k in range(1, ndim):
             d[:, k] -= n[k] * np.round(d[:, k] / n[k])
-    else:
-        d = pos_g - sim.px[:, :ndim]
     assert np.max(np.abs(d)) < 2e-5
-    assert np.max(np.abs(parts["u"] - sim.pu)) < 2e-6 * max(1.0, np.max(np.abs(sim.pu)))
-    assert np.array_equal(parts["kind"], sim.pk)
+    assert np.max(np.abs(parts["u"][:npre] - sim.pu[:npre])) < 2e-6 * max(1.0, np.max(np.abs(sim.pu)))
+    assert np.array_equal(parts["kind"][:npre], sim.pk[:npre])
+    # births: identical (position, kind) multisets, thermal u at FP32 accuracy
+    key_g = sorted(zip(np.round(pos_g[npre:], 6).tolist(), parts["kind"][npre:].tolist()))
+    key_o = sorted(zip(np.round(sim.px[npre:, :ndim], 6).tolist(), sim.pk[npre:].tolist()))
+    assert key_g == key_o
     ctx.close()
 
 
@@ -152,8 +158,27 @@ def _field_l2(ctx, sim):
     return math.sqrt(num / den)
 
 
-def _compare_run(P, ctx, sim, l2_tol=1e-5, rel_tol=5e-3, min_events=1):
+def _record(name, **kv):
+    """Append measured parity figures to gpurun_out/parity_metrics.jsonl (if present)."""
+    import json
+    import os
+    d = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+    if os.path.isdir(d):
+        with open(os.path.join(d, "parity_metrics.jsonl"), "a") as f:
+            f.write(json.dumps(dict(test=name, **kv)) + "\n")
+
+
+def _compare_run(P, ctx, sim, l2_tol=1e-5, rel_tol=5e-3, min_events=1, name=""):
     l2 = _field_l2(ctx, sim)
+    sc0 = ctx.scalars()
+    ev_g0 = set(map(tuple, ctx.events().tolist()))
+    ev_o0 = sim.event_set()
+    ne_o0 = float(np.sum(sim.pk % 2 == 0))
+    eabs_o0 = sim.kinetic_energy() + sim.energy_gap
+    _record(name, field_l2=l2, events_gpu=len(ev_g0), events_oracle=len(ev_o0),
+            events_common=len(ev_g0 & ev_o0), n_e_gpu=sc0["n_e"], n_e_oracle=ne_o0,
+            e_abs_gpu=sc0["e_abs"], e_abs_oracle=eabs_o0, gauss_max=sc0["gauss_max"],
+            rho_max=sc0["rho_max"])
     assert l2 < l2_tol, l2
     sc = ctx.scalars()
     ev_g = set(map(tuple, ctx.events().tolist()))
@@ -177,7 +202,7 @@ def _compare_run(P, ctx, sim, l2_tol=1e-5, rel_tol=5e-3, min_events=1):
 def test_run_1d_slab_high_intensity(P):
     cfg = W.config_1d(hi=True, ppc=10, nsteps=1400)
     ctx, sim = _run_both(P, cfg, 1400)
-    l2, sc = _compare_run(P, ctx, sim, min_events=20)
+    l2, sc = _compare_run(P, ctx, sim, min_events=20, name="run_1d")
     # amplitude window against the oracle's brute-force maximum
     A_g = ctx.amp()[:, 0, 0].astype(np.float64)
     A_o = sim.A[OP.G:OP.G + cfg["n"][0] + 1, 0, 0]
@@ -194,15 +219,16 @@ def test_run_1d_slab_high_intensity(P):
 def test_run_2d_slab_gaussian_beam(P):
     cfg = W.config_2d(nx=192, ny=48, nsteps=520, ppc=2, peak=3e14, slab_cells=12, waist=0.6e-6)
     ctx, sim = _run_both(P, cfg, 520)
-    _compare_run(P, ctx, sim, min_events=20)
+    _compare_run(P, ctx, sim, min_events=20, name="run_2d")
     ctx.close()
 
 
 def test_run_3d_mirror_periodic(P):
-    dx = W.LAMBDA / 24
-    cfg = W.config_3d(nx=96, ny=8, nz=8, nsteps=380, ppc=2, fluence=1.5, front=24)
+    # the mirror share of the 3D workload (1 J/cm^2, 8 neutrals per cell),
+    # transversely reduced to 8 x 8 cells (periodic, plane wave)
+    cfg = W.config_3d(nx=96, ny=8, nz=8, nsteps=380, ppc=8, fluence=1.0, front=24)
     ctx, sim = _run_both(P, cfg, 380)
-    _compare_run(P, ctx, sim, min_events=20)
+    _compare_run(P, ctx, sim, min_events=20, name="run_3d")
     ctx.close()
 
 
