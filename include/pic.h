@@ -150,7 +150,11 @@ enum {
   PIC_DIAG_PARTICLES = 5, /* pic_particle records of live charged particles */
   PIC_DIAG_PARAMS = 6,    /* one pic_params */
   PIC_DIAG_AMP = 7,       /* float: windowed amplitude A at nodes [V/m] */
-  PIC_DIAG_TIMERS = 8     /* double[8]: ms spent in the step phases (if timing on) */
+  PIC_DIAG_TIMERS = 8     /* double[24]: [0..7] device ms per phase summed over the
+                             timed launches, [8..15] launch counts (phases: 0 push,
+                             1 field update with outflow faces and amplitude window,
+                             2 ionization); [16..22] autotuner ms per field launch of
+                             each tile shape, [23] the tile shape in use */
 };
 
 /* PIC_DIAG_SCALARS layout (all double). */
@@ -234,7 +238,16 @@ pic_status pic_batch_add(pic_batch* b, pic_ctx* c);
 pic_status pic_batch_remove(pic_batch* b, pic_ctx* c);
 void pic_batch_destroy(pic_batch* b);
 
-/* Per-step device time of the phases (hip events), off by default. */
+/* Field-kernel autotuner: times each tile shape of the fused field update
+ * (reps launches each, HIP events) on the context's real launch, keeps the
+ * fastest and restores the initial (all-zero field) state.  Valid only before
+ * the first step of a run without pre-ionization (else PIC_E_STATE).  The
+ * measured ms per launch and the chosen variant are in PIC_DIAG_TIMERS. */
+pic_status pic_autotune(pic_ctx* c, int32_t reps);
+
+/* Device time of each step phase measured with HIP events recorded on the
+ * context stream around every launch (no host synchronisation per step);
+ * off by default; switching resets the accumulators. */
 pic_status pic_set_timing(pic_ctx* c, int32_t on);
 
 void pic_destroy(pic_ctx* c);

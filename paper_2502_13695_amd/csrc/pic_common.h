@@ -101,8 +101,12 @@ struct Inst {
   float halfC[3];
   float kmur[3];
   float ctdt_m;                 // c dt [m] (displacement along absent axes)
-  // fields (padded, x fastest)
-  float *E0, *E1, *E2, *B0, *B1, *B2, *J0, *J1, *J2;
+  // fields (padded, x fastest): F[parity][Ex, Ey, Ez, bx, by, bz]; the set
+  // (step & 1) holds E^n, b^n; the field kernel writes the other set
+  float* F[2][6];
+  // current dt J / eps0: the push of step n deposits into Jb[n & 1]; the field
+  // kernel of step n reads it and clears Jb[(n + 1) & 1] for the next push
+  float* Jb[2][3];
   const float* ie_half;         // 1/eps_r at Ex positions, per padded x index
   const float* ie_node;         // 1/eps_r at nodes, per padded x index
   const signed char* mat_cell;  // material of cell i (-1 vacuum), per cell x index
@@ -133,6 +137,7 @@ struct Inst {
   // neutrals
   int64_t nneut;
   int ppc;
+  uint64_t ppc_magic;           // ceil(2^64 / ppc): neutral index / ppc by multiply-high
   float *no0, *no1, *no2;       // offsets
   uint32_t* alive;              // bitmask
   int* death;                   // ionization step, -1 alive

@@ -12,17 +12,18 @@ struct Group {
   const int* off;      // device prefix offsets of blocks per instance (n + 1)
   int n;               // instances
   int blocks;          // total blocks
+  int step;            // step index of a single run; -1: each instance's device counter
 };
 
 constexpr int TPB = 256;
 
 // phase launchers (enqueue on `s`); D = 1..3, order = 1..2
 void launch_push(const Group& g, int D, int order, hipStream_t s);
-void launch_bhalf(const Group& g, int D, hipStream_t s);
-void launch_efull(const Group& g, int D, hipStream_t s);
-void launch_amp(const Group& g, int D, hipStream_t s);
+void launch_fields(const Group& g, int D, int variant, hipStream_t s);
 void launch_ionize(const Group& g, int D, int order, hipStream_t s);
-void launch_advance(const Inst* insts, int n, hipStream_t s);
+void launch_advance(const Inst* insts, int n, hipStream_t s);   // batch: step counters + 1
+int field_tiles(int D, int variant, int Px, int Py, int Pz);   // blocks of the field launch
+int field_tile_variants();
 
 // one-instance setup and diagnostics
 void launch_init_neutrals_d(const Inst* d, int64_t nneut, int D, hipStream_t s);

@@ -1,19 +1,20 @@
 // Device kernels of the MI355X laser-dielectric PIC hot path.
 //
-// Per step (state E^n, b^n = cB^n, particles x^n with u^{n-1/2}):
+// Three launches per step (state E^n, b^n = cB^n in field set n & 1, particles
+// x^n with u^{n-1/2}):
 //   push      gather E^n, b^n with the particle shape, relativistic Boris,
 //             move, Esirkepov deposit of J^{n+1/2} (global FP32 atomics)
-//   bhalf     b^{n+1/2} = b^n - (1/2) C curl E^n
-//   efull     E^{n+1} = E^n + (1/eps_r)(C curl b^{n+1/2} - dt J / eps0) with the
-//             first-order outflow (Mur) chain on the faces and the laser
-//             injected at x_min; J cleared for the next deposit
-//   bhalf     b^{n+1} = b^{n+1/2} - (1/2) C curl E^{n+1}
-//   amp       node |E^{n+1}| into the one-cycle window, exact sliding maximum
-//             (van Herk / Gil-Werman blocks), amplitude A (Sec. 2.1)
+//   fields    one LDS tile per block: b^{n+1/2} = b^n - (1/2) C curl E^n,
+//             E^{n+1} = E^n + (1/eps_r)(C curl b^{n+1/2} - dt J / eps0), the
+//             first-order outflow (Mur) chain on the faces with the laser
+//             injected at x_min, b^{n+1} = b^{n+1/2} - (1/2) C curl E^{n+1}
+//             (written to the other field set), J cleared, node |E^{n+1}| into
+//             the one-cycle window with its exact sliding maximum (van Herk /
+//             Gil-Werman blocks) giving the amplitude A (Sec. 2.1)
 //   ionize    per alive neutral: A at the neutral (shape gather), P from the
 //             FP32 Keldysh table (Sec. 2.1), Philox draw, electron and
-//             positive-carrier birth (Sec. 2.1, 3.2)
-//   advance   step counter + 1
+//             positive-carrier birth (Sec. 2.1, 3.2); the last block advances
+//             the step counter
 #include <hip/hip_runtime.h>
 
 #include "pic_kernels.h"
@@ -162,6 +163,16 @@ __global__ __launch_bounds__(TPB) void k_push(Group g) {
   const int tid = (blockIdx.x - g.off[ii]) * TPB + threadIdx.x;
   int count = *I.pcount;
   count = count < I.capacity ? count : I.capacity;
+  const int par = (g.step >= 0 ? g.step : *I.step) & 1;
+  const float* __restrict__ FE0 = I.F[par][0];
+  const float* __restrict__ FE1 = I.F[par][1];
+  const float* __restrict__ FE2 = I.F[par][2];
+  const float* __restrict__ FB0 = I.F[par][3];
+  const float* __restrict__ FB1 = I.F[par][4];
+  const float* __restrict__ FB2 = I.F[par][5];
+  float* const J0 = I.Jb[par][0];
+  float* const J1 = I.Jb[par][1];
+  float* const J2 = I.Jb[par][2];
   for (int p = tid; p < count; p += nthr) {
     const uint8_t kind = I.pkind[p];
     if (kind == DEAD) continue;
@@ -176,12 +187,12 @@ __global__ __launch_bounds__(TPB) void k_push(Group g) {
     make_axis<ORDER>(X, ci, t0, I.nx, 0, G, 1);
     if (D >= 2) make_axis<ORDER>(Y, cj, t1, I.ny, I.per_y, I.Gy, I.sy);
     if (D >= 3) make_axis<ORDER>(Z, ck, t2, I.nz, I.per_z, I.Gz, I.sz);
-    const float ex = gather<D, ORDER>(I.E0, X, Y, Z, 1, 0, 0);
-    const float ey = gather<D, ORDER>(I.E1, X, Y, Z, 0, 1, 0);
-    const float ez = gather<D, ORDER>(I.E2, X, Y, Z, 0, 0, 1);
-    const float bx = gather<D, ORDER>(I.B0, X, Y, Z, 0, 1, 1);
-    const float by = gather<D, ORDER>(I.B1, X, Y, Z, 1, 0, 1);
-    const float bz = gather<D, ORDER>(I.B2, X, Y, Z, 1, 1, 0);
+    const float ex = gather<D, ORDER>(FE0, X, Y, Z, 1, 0, 0);
+    const float ey = gather<D, ORDER>(FE1, X, Y, Z, 0, 1, 0);
+    const float ez = gather<D, ORDER>(FE2, X, Y, Z, 0, 0, 1);
+    const float bx = gather<D, ORDER>(FB0, X, Y, Z, 0, 1, 1);
+    const float by = gather<D, ORDER>(FB1, X, Y, Z, 1, 0, 1);
+    const float bz = gather<D, ORDER>(FB2, X, Y, Z, 1, 1, 0);
     // ---- relativistic Boris (u = gamma v / c, b = c B, h = q dt / 2 m c)
     const float h = I.kh[kind];
     const float umx = ux + h * ex, umy = uy + h * ey, umz = uz + h * ez;
@@ -238,7 +249,7 @@ __global__ __launch_bounds__(TPB) void k_push(Group g) {
         for (int a = ex_.lo; a < ex_.hi - 1; ++a) {
           acc += ex_.DS[a] * wbx;
           const int ox = ex_.org + a + G;
-          unsafeAtomicAdd(I.J0 + ox + oy + oz, -qx * acc);
+          unsafeAtomicAdd(J0 + ox + oy + oz, -qx * acc);
         }
       }
     }
@@ -256,10 +267,10 @@ __global__ __launch_bounds__(TPB) void k_push(Group g) {
             for (int b = ey_.lo; b < ey_.hi - 1; ++b) {
               acc += ey_.DS[b] * wby;
               const int oy = I.sy * (wrapi(ey_.org + b, I.ny, I.per_y) + I.Gy);
-              unsafeAtomicAdd(I.J1 + ox + oy + oz, -qy * acc);
+              unsafeAtomicAdd(J1 + ox + oy + oz, -qy * acc);
             }
           } else {
-            unsafeAtomicAdd(I.J1 + ox, qy * uy * ig * wby);
+            unsafeAtomicAdd(J1 + ox, qy * uy * ig * wby);
           }
         }
       }
@@ -278,10 +289,10 @@ __global__ __launch_bounds__(TPB) void k_push(Group g) {
             for (int c = ez_.lo; c < ez_.hi - 1; ++c) {
               acc += ez_.DS[c] * wbz;
               const int oz = I.sz * (wrapi(ez_.org + c, I.nz, I.per_z) + I.Gz);
-              unsafeAtomicAdd(I.J2 + ox + oy + oz, -qz * acc);
+              unsafeAtomicAdd(J2 + ox + oy + oz, -qz * acc);
             }
           } else {
-            unsafeAtomicAdd(I.J2 + ox + oy, qz * uz * ig * wbz);
+            unsafeAtomicAdd(J2 + ox + oy, qz * uz * ig * wbz);
           }
         }
       }
@@ -313,61 +324,6 @@ __global__ __launch_bounds__(TPB) void k_push(Group g) {
 }
 
 // ------------------------------------------------------------ field solve
-// decode a padded linear index into logical (i, j, k)
-template <int D>
-__device__ __forceinline__ void decode(const Inst& I, int64_t p, int& i, int& j, int& k) {
-  const int ai = (int)(p % I.Px);
-  const int64_t r = p / I.Px;
-  const int aj = D >= 2 ? (int)(r % I.Py) : 0;
-  const int ak = D >= 3 ? (int)(r / I.Py) : 0;
-  i = ai - G;
-  j = aj - I.Gy;
-  k = ak - I.Gz;
-}
-
-// valid range of a staggered component along one present axis
-__device__ __forceinline__ bool in_rng(int v, int n, int half, int per, int lo_node) {
-  if (half || per) return v >= 0 && v < n;
-  return v >= lo_node && v <= n - lo_node;
-}
-
-template <int D>
-__global__ __launch_bounds__(TPB) void k_bhalf(Group g) {
-  const int ii = find_inst(g);
-  const Inst& I = g.insts[ii];
-  const int64_t p = (int64_t)(blockIdx.x - g.off[ii]) * TPB + threadIdx.x;
-  if (p >= (int64_t)I.Px * I.Py * I.Pz) return;
-  int i, j, k;
-  decode<D>(I, p, i, j, k);
-  const float hx = I.halfC[0], hy = I.halfC[1], hz = I.halfC[2];
-  // neighbour offsets (+1 along each axis, wrapped on periodic axes)
-  const int dxp = 1;
-  const int dyp = D >= 2 ? (I.per_y && j == I.ny - 1 ? -(I.ny - 1) * I.sy : I.sy) : 0;
-  const int dzp = D >= 3 ? (I.per_z && k == I.nz - 1 ? -(I.nz - 1) * I.sz : I.sz) : 0;
-  const bool yin_n = D < 2 || in_rng(j, I.ny, 0, I.per_y, 0), yin_h = D < 2 || in_rng(j, I.ny, 1, I.per_y, 0);
-  const bool zin_n = D < 3 || in_rng(k, I.nz, 0, I.per_z, 0), zin_h = D < 3 || in_rng(k, I.nz, 1, I.per_z, 0);
-  const bool xin_n = in_rng(i, I.nx, 0, 0, 0), xin_h = in_rng(i, I.nx, 1, 0, 0);
-  // bx at (x node, y half, z half): -(dEz/dy - dEy/dz)
-  if (xin_n && (D < 2 || yin_h) && (D < 3 || zin_h)) {
-    float cu = 0.0f;
-    if (D >= 2) cu += hy * (I.E2[p + dyp] - I.E2[p]);
-    if (D >= 3) cu -= hz * (I.E1[p + dzp] - I.E1[p]);
-    I.B0[p] -= cu;
-  }
-  // by at (x half, y node, z half): -(dEx/dz - dEz/dx)
-  if (xin_h && yin_n && (D < 3 || zin_h)) {
-    float cu = -hx * (I.E2[p + dxp] - I.E2[p]);
-    if (D >= 3) cu += hz * (I.E0[p + dzp] - I.E0[p]);
-    I.B1[p] -= cu;
-  }
-  // bz at (x half, y half, z node): -(dEy/dx - dEx/dy)
-  if (xin_h && (D < 2 || yin_h) && zin_n) {
-    float cu = hx * (I.E1[p + dxp] - I.E1[p]);
-    if (D >= 2) cu -= hy * (I.E0[p + dyp] - I.E0[p]);
-    I.B2[p] -= cu;
-  }
-}
-
 // First-order outflow (Mur) for a face point q with inward neighbour r:
 // E_q^{n+1} = E_r^n + k (E_r^{n+1} - E_q^n), applied to the field minus the
 // incident wave on the injection face.
@@ -382,162 +338,363 @@ __device__ __forceinline__ float mur_inc(float qold, float rold, float rnew, flo
   return m.q1 + (rold - m.r0) + k * ((rnew - m.r1) - (qold - m.q0));
 }
 
-template <int D>
-__global__ __launch_bounds__(TPB) void k_efull(Group g) {
-  const int ii = find_inst(g);
-  const Inst& I = g.insts[ii];
-  const int64_t p = (int64_t)(blockIdx.x - g.off[ii]) * TPB + threadIdx.x;
-  if (p >= (int64_t)I.Px * I.Py * I.Pz) return;
-  int i, j, k;
-  decode<D>(I, p, i, j, k);
-  const float jx = I.J0[p], jy = I.J1[p], jz = I.J2[p];
-  I.J0[p] = 0.0f;
-  I.J1[p] = 0.0f;
-  I.J2[p] = 0.0f;
-  const float Cx = I.C[0], Cy = I.C[1], Cz = I.C[2];
-  const int ai = i + G;
-  const int dym = D >= 2 ? (I.per_y && j == 0 ? (I.ny - 1) * I.sy : -I.sy) : 0;
-  const int dzm = D >= 3 ? (I.per_z && k == 0 ? (I.nz - 1) * I.sz : -I.sz) : 0;
-  // interior test per staggering (node axes exclude the outflow faces)
-  const bool xh = in_rng(i, I.nx, 1, 0, 0), xn = in_rng(i, I.nx, 0, 0, 1);
-  const bool yh = D < 2 || in_rng(j, I.ny, 1, I.per_y, 0);
-  const bool yn = D < 2 || in_rng(j, I.ny, 0, I.per_y, 1);
-  const bool zh = D < 3 || in_rng(k, I.nz, 1, I.per_z, 0);
-  const bool zn = D < 3 || in_rng(k, I.nz, 0, I.per_z, 1);
-  const int step = *I.step;
-  // incident field factors for the x_min face
-  float4 s0 = make_float4(0.f, 0.f, 0.f, 0.f), s1 = s0;
-  if (i == 1) {
-    if (step < I.nsrc) s0 = I.src[step];
-    if (step + 1 < I.nsrc) s1 = I.src[step + 1];
-  }
-  // ---------------- Ex (x half, y node, z node)
-  if (xh && yn && zn) {
-    const float ie = I.ie_half[ai];
-    float cu = 0.0f;
-    if (D >= 2) cu += Cy * (I.B2[p] - I.B2[p + dym]);
-    if (D >= 3) cu -= Cz * (I.B1[p] - I.B1[p + dzm]);
-    const float old = I.E0[p];
-    const float nw = old + ie * (cu - jx);
-    I.E0[p] = nw;
-    // faces: y (priority over z), then z, then the y-z edge
-    if (D >= 2 && !I.per_y) {
-      const int fy = (j == 1) ? -1 : (j == I.ny - 1 ? 1 : 0);
-      const int fz = (D >= 3 && !I.per_z) ? ((k == 1) ? -1 : (k == I.nz - 1 ? 1 : 0)) : 0;
-      const int oy = fy * I.sy, oz = fz * I.sz;
-      float qz_new = 0.f, qz_old = 0.f;
-      if (fz) {   // z-face point (x half, y interior): neighbour p
-        qz_old = I.E0[p + oz];
-        qz_new = mur(qz_old, old, nw, I.kmur[2]);
-        I.E0[p + oz] = qz_new;
-      }
-      if (fy) {
-        const float qo = I.E0[p + oy];
-        I.E0[p + oy] = mur(qo, old, nw, I.kmur[1]);
-        if (fz) {   // y-z edge: y priority, neighbour is the z-face point
-          const float qe = I.E0[p + oy + oz];
-          I.E0[p + oy + oz] = mur(qe, qz_old, qz_new, I.kmur[1]);
-        }
-      }
-    } else if (D >= 3 && !I.per_z) {
-      const int fz = (k == 1) ? -1 : (k == I.nz - 1 ? 1 : 0);
-      if (fz) {
-        const float qo = I.E0[p + fz * I.sz];
-        I.E0[p + fz * I.sz] = mur(qo, old, nw, I.kmur[2]);
-      }
-    }
-  }
-  // ---------------- Ey (x node, y half, z node) and Ez (x node, y node, z half)
-#pragma unroll
-  for (int comp = 1; comp <= 2; ++comp) {
-    const bool inside = comp == 1 ? (xn && yh && zn) : (xn && yn && zh);
-    if (!inside) continue;
-    float* E = comp == 1 ? I.E1 : I.E2;
-    const float ie = I.ie_node[ai];
-    float cu;
-    if (comp == 1) {   // dbx/dz - dbz/dx
-      cu = -Cx * (I.B2[p] - I.B2[p - 1]);
-      if (D >= 3) cu += Cz * (I.B0[p] - I.B0[p + dzm]);
-    } else {           // dby/dx - dbx/dy
-      cu = Cx * (I.B1[p] - I.B1[p - 1]);
-      if (D >= 2) cu -= Cy * (I.B0[p] - I.B0[p + dym]);
-    }
-    const float jj = comp == 1 ? jy : jz;
-    const float old = E[p];
-    const float nw = old + ie * (cu - jj);
-    E[p] = nw;
-    // transverse face this component is tangential to (z for Ey, y for Ez)
-    const int td = comp == 1 ? 2 : 1;
-    int ft = 0, st = 0;
-    if (td == 1 && D >= 2 && !I.per_y) {
-      ft = (j == 1) ? -1 : (j == I.ny - 1 ? 1 : 0);
-      st = I.sy;
-    }
-    if (td == 2 && D >= 3 && !I.per_z) {
-      ft = (k == 1) ? -1 : (k == I.nz - 1 ? 1 : 0);
-      st = I.sz;
-    }
-    const int fx = (i == 1) ? -1 : (i == I.nx - 1 ? 1 : 0);
-    float qt_new = 0.f, qt_old = 0.f;
-    if (ft) {   // transverse-face point: neighbour p
-      qt_old = E[p + ft * st];
-      qt_new = mur(qt_old, old, nw, I.kmur[td]);
-      E[p + ft * st] = qt_new;
-    }
-    if (fx) {   // x-face point (priority x): neighbour p; edge: neighbour is qt
-      const bool inj = (fx < 0) && (comp == I.pol);
-      const int tp = (j + I.Gy) + I.Py * (k + I.Gz);
-      float prof = inj ? I.prof[tp] : 0.f;
-      MurInc m{prof * s0.x, prof * s1.x, prof * s0.y, prof * s1.y};
-      const float qo = E[p + fx];
-      E[p + fx] = inj ? mur_inc(qo, old, nw, I.kmur[0], m) : mur(qo, old, nw, I.kmur[0]);
-      if (ft) {
-        const int te = tp + (td == 1 ? ft : ft * I.Py);
-        float prof2 = inj ? I.prof[te] : 0.f;
-        MurInc m2{prof2 * s0.x, prof2 * s1.x, prof2 * s0.y, prof2 * s1.y};
-        const float qe = E[p + fx + ft * st];
-        E[p + fx + ft * st] = inj ? mur_inc(qe, qt_old, qt_new, I.kmur[0], m2)
-                                  : mur(qe, qt_old, qt_new, I.kmur[0]);
-      }
-    }
-  }
+// Tile shapes of the field kernel (owned positions per block), per dimension.
+struct TileShape {
+  int x, y, z;
+};
+__host__ __device__ constexpr TileShape tile_shape(int D, int v) {
+  return D == 1 ? (v == 1 ? TileShape{128, 1, 1} : v == 2 ? TileShape{512, 1, 1} : TileShape{256, 1, 1})
+       : D == 2 ? (v == 1 ? TileShape{32, 8, 1} : v == 2 ? TileShape{64, 4, 1} : v == 3 ? TileShape{64, 12, 1}
+                   : v == 4 ? TileShape{64, 16, 1} : TileShape{64, 8, 1})
+                : (v == 1 ? TileShape{32, 4, 4} : v == 2 ? TileShape{16, 4, 4} : v == 3 ? TileShape{8, 8, 8}
+                   : TileShape{16, 8, 4});
+}
+constexpr int kTileVariants = 5;
+
+__device__ __forceinline__ int wrap_any(int j, int n) {
+  j %= n;
+  return j < 0 ? j + n : j;
 }
 
-// ------------------------------------------------------- amplitude window
+// decode a padded linear index into logical (i, j, k)
 template <int D>
-__global__ __launch_bounds__(TPB) void k_amp(Group g) {
-  const int ii = find_inst(g);
-  const Inst& I = g.insts[ii];
-  const int64_t w = (int64_t)(blockIdx.x - g.off[ii]) * TPB + threadIdx.x;
-  if (w >= I.wsz) return;
-  const int wi = (int)(w % I.wnx);
-  const int64_t r = w / I.wnx;
+__device__ __forceinline__ void decode(const Inst& I, int64_t p, int& i, int& j, int& k) {
+  const int ai = (int)(p % I.Px);
+  const int64_t r = p / I.Px;
   const int aj = D >= 2 ? (int)(r % I.Py) : 0;
   const int ak = D >= 3 ? (int)(r / I.Py) : 0;
-  const int i = I.wx0 + wi - G, j = aj - I.Gy, k = ak - I.Gz;
-  // window nodes inside the box only
-  if (i < 0 || i > I.nx) return;
-  if (D >= 2 && (j < 0 || j > (I.per_y ? I.ny - 1 : I.ny))) return;
-  if (D >= 3 && (k < 0 || k > (I.per_z ? I.nz - 1 : I.nz))) return;
-  const int64_t p = (int64_t)(I.wx0 + wi) + (int64_t)I.sy * aj + (int64_t)I.sz * ak;
-  const int dym = D >= 2 ? (I.per_y && j == 0 ? (I.ny - 1) * I.sy : -I.sy) : 0;
-  const int dzm = D >= 3 ? (I.per_z && k == 0 ? (I.nz - 1) * I.sz : -I.sz) : 0;
-  const float ex = 0.5f * (I.E0[p - 1] + I.E0[p]);
-  const float ey = D >= 2 ? 0.5f * (I.E1[p + dym] + I.E1[p]) : I.E1[p];
-  const float ez = D >= 3 ? 0.5f * (I.E2[p + dzm] + I.E2[p]) : I.E2[p];
-  const float m = sqrtf(ex * ex + ey * ey + ez * ez);
-  if (!(m <= 3.0e38f)) atomicOr(I.health, HEALTH_NONFINITE);
-  const int slot = *I.step % I.nwin;
-  I.ring[(int64_t)slot * I.wsz + w] = m;
-  const float pre = slot == 0 ? m : fmaxf(I.prefix[w], m);
-  I.prefix[w] = pre;
-  const float a = slot + 1 < I.nwin ? fmaxf(I.suffix[(int64_t)(slot + 1) * I.wsz + w], pre) : pre;
-  I.A[p] = a;
-  if (slot == I.nwin - 1) {   // block complete: suffix maxima for the next block
-    float run = 0.0f;
-    for (int q = I.nwin - 1; q >= 0; --q) {
-      run = fmaxf(run, I.ring[(int64_t)q * I.wsz + w]);
-      I.suffix[(int64_t)q * I.wsz + w] = run;
+  i = ai - G;
+  j = aj - I.Gy;
+  k = ak - I.Gz;
+}
+
+// validity of a staggered position along one axis (v logical, n cells)
+__device__ __forceinline__ bool v_b(int v, int n, bool half, bool per) {
+  return per || (half ? (v >= 0 && v < n) : (v >= 0 && v <= n));
+}
+__device__ __forceinline__ bool v_in(int v, int n, bool half, bool per) {   // E interior
+  return per || (half ? (v >= 0 && v < n) : (v >= 1 && v <= n - 1));
+}
+__device__ __forceinline__ bool v_dom(int v, int n, bool half, bool per) {  // inside the box
+  return per ? (v >= 0 && v < n) : (half ? (v >= 0 && v < n) : (v >= 0 && v <= n));
+}
+
+template <int D, int V>
+struct TileT {
+  static constexpr int X = tile_shape(D, V).x, Y = tile_shape(D, V).y, Z = tile_shape(D, V).z;
+};
+
+// Per-axis facts of a local tile coordinate, as bits.
+enum : unsigned {
+  AX_BN = 1u,     // b valid, node-staggered
+  AX_BH = 2u,     // b valid, half-staggered
+  AX_IN = 4u,     // E interior, node
+  AX_IH = 8u,     // E interior, half
+  AX_DN = 16u,    // inside the box, node
+  AX_DH = 32u,    // inside the box, half
+  AX_ARR = 64u,   // has a position in the padded array
+  AX_F0 = 128u,   // on the min face (node index 0)
+  AX_F1 = 256u    // on the max face (node index n)
+};
+
+__device__ __forceinline__ unsigned axis_bits(int v, int n, bool per, bool inarr) {
+  unsigned b = inarr ? AX_ARR : 0u;
+  if (per) return b | AX_BN | AX_BH | AX_IN | AX_IH | ((v >= 0 && v < n) ? (AX_DN | AX_DH) : 0u);
+  if (v >= 0 && v <= n) b |= AX_BN | AX_DN;
+  if (v >= 0 && v < n) b |= AX_BH | AX_IH | AX_DH;
+  if (v >= 1 && v <= n - 1) b |= AX_IN;
+  if (v == 0) b |= AX_F0;
+  if (v == n) b |= AX_F1;
+  return b;
+}
+
+// One block = one tile of owned positions plus a halo of 2 on each side of
+// every present axis, all six field components staged in LDS.  Row and plane
+// offsets (periodic axes wrapped) and per-axis validity bits are tabulated
+// once per block.
+template <int D, int V>
+__global__ __launch_bounds__(TPB) void k_fields(Group g) {
+  using T = TileT<D, V>;
+  constexpr int H = 2;
+  constexpr int RX = T::X + 2 * H;
+  constexpr int RY = D >= 2 ? T::Y + 2 * H : 1;
+  constexpr int RZ = D >= 3 ? T::Z + 2 * H : 1;
+  constexpr int NR = RX * RY * RZ;
+  constexpr int LY = RX, LZ = RX * RY;   // LDS strides
+  __shared__ float sE[3][NR];
+  __shared__ float sB[3][NR];
+  __shared__ unsigned sbx[RX], sby[RY], sbz[RZ];
+  __shared__ int soy[RY], soz[RZ];
+  const int ii = find_inst(g);
+  const Inst& I = g.insts[ii];
+  const int tb = blockIdx.x - g.off[ii];
+  const int Px = I.Px, Py = I.Py, Pz = I.Pz;
+  const int ntx = (Px + T::X - 1) / T::X;
+  const int nty = D >= 2 ? (Py + T::Y - 1) / T::Y : 1;
+  const int a0x = (tb % ntx) * T::X;
+  const int a0y = D >= 2 ? ((tb / ntx) % nty) * T::Y : 0;
+  const int a0z = D >= 3 ? (tb / (ntx * nty)) * T::Z : 0;
+  const int nx = I.nx, ny = I.ny, nz = I.nz;
+  const bool py = I.per_y, pz = I.per_z;
+  const int sy = I.sy, sz = I.sz;
+  const int Gy = I.Gy, Gz = I.Gz;
+  const int step = g.step >= 0 ? g.step : *I.step;
+  const int par = step & 1;
+  const float* __restrict__ Ec0 = I.F[par][0];
+  const float* __restrict__ Ec1 = I.F[par][1];
+  const float* __restrict__ Ec2 = I.F[par][2];
+  const float* __restrict__ Bc0 = I.F[par][3];
+  const float* __restrict__ Bc1 = I.F[par][4];
+  const float* __restrict__ Bc2 = I.F[par][5];
+  float* __restrict__ En0 = I.F[par ^ 1][0];
+  float* __restrict__ En1 = I.F[par ^ 1][1];
+  float* __restrict__ En2 = I.F[par ^ 1][2];
+  float* __restrict__ Bn0 = I.F[par ^ 1][3];
+  float* __restrict__ Bn1 = I.F[par ^ 1][4];
+  float* __restrict__ Bn2 = I.F[par ^ 1][5];
+  const float* __restrict__ J0 = I.Jb[par][0];
+  const float* __restrict__ J1 = I.Jb[par][1];
+  const float* __restrict__ J2 = I.Jb[par][2];
+  float* __restrict__ Jn0 = I.Jb[par ^ 1][0];
+  float* __restrict__ Jn1 = I.Jb[par ^ 1][1];
+  float* __restrict__ Jn2 = I.Jb[par ^ 1][2];
+  const float* __restrict__ ieh = I.ie_half;
+  const float* __restrict__ ien = I.ie_node;
+  const float hx = I.halfC[0], hy = I.halfC[1], hz = I.halfC[2];
+  const float Cx = I.C[0], Cy = I.C[1], Cz = I.C[2];
+  const int i0 = a0x - G, j0 = a0y - Gy, k0 = a0z - Gz;   // logical tile origin
+
+  // ---- per-axis tables
+  for (int q = threadIdx.x; q < RX; q += TPB) {
+    const int i = i0 + q - H;
+    sbx[q] = axis_bits(i, nx, false, i + G >= 0 && i + G < Px);
+  }
+  for (int q = threadIdx.x; q < RY; q += TPB) {
+    if (D >= 2) {
+      const int j = j0 + q - H;
+      const int jw = py ? wrap_any(j, ny) : j;
+      const bool in = jw + G >= 0 && jw + G < Py;
+      sby[q] = axis_bits(j, ny, py, in);
+      soy[q] = in ? sy * (jw + G) : 0;
+    } else {
+      sby[q] = AX_BN | AX_BH | AX_IN | AX_IH | AX_DN | AX_DH | AX_ARR;
+      soy[q] = 0;
+    }
+  }
+  for (int q = threadIdx.x; q < RZ; q += TPB) {
+    if (D >= 3) {
+      const int k = k0 + q - H;
+      const int kw = pz ? wrap_any(k, nz) : k;
+      const bool in = kw + G >= 0 && kw + G < Pz;
+      sbz[q] = axis_bits(k, nz, pz, in);
+      soz[q] = in ? sz * (kw + G) : 0;
+    } else {
+      sbz[q] = AX_BN | AX_BH | AX_IN | AX_IH | AX_DN | AX_DH | AX_ARR;
+      soz[q] = 0;
+    }
+  }
+  __syncthreads();
+  auto split = [&](int l, int& qx, int& qy, int& qz) {
+    qx = l % RX;
+    qy = D >= 2 ? (l / RX) % RY : 0;
+    qz = D >= 3 ? l / (RX * RY) : 0;
+  };
+
+  // ---- A: stage E^n and b^n
+  for (int l = threadIdx.x; l < NR; l += TPB) {
+    int qx, qy, qz;
+    split(l, qx, qy, qz);
+    const bool in = sbx[qx] & sby[qy] & sbz[qz] & AX_ARR;
+    const int64_t gi = (int64_t)(a0x + qx - H) + soy[qy] + soz[qz];
+    sE[0][l] = in ? Ec0[gi] : 0.0f;
+    sE[1][l] = in ? Ec1[gi] : 0.0f;
+    sE[2][l] = in ? Ec2[gi] : 0.0f;
+    sB[0][l] = in ? Bc0[gi] : 0.0f;
+    sB[1][l] = in ? Bc1[gi] : 0.0f;
+    sB[2][l] = in ? Bc2[gi] : 0.0f;
+  }
+  __syncthreads();
+  // ---- B: b^{n+1/2} on local [-2, T] (in place; reads E only)
+  for (int l = threadIdx.x; l < NR; l += TPB) {
+    int qx, qy, qz;
+    split(l, qx, qy, qz);
+    if (qx > T::X + H || (D >= 2 && qy > T::Y + H) || (D >= 3 && qz > T::Z + H)) continue;
+    const unsigned bx = sbx[qx], by = sby[qy], bz = sbz[qz];
+    if ((bx & AX_BN) && (by & AX_BH) && (bz & AX_BH)) {
+      float cu = 0.0f;
+      if (D >= 2) cu += hy * (sE[2][l + LY] - sE[2][l]);
+      if (D >= 3) cu -= hz * (sE[1][l + LZ] - sE[1][l]);
+      sB[0][l] -= cu;
+    }
+    if ((bx & AX_BH) && (by & AX_BN) && (bz & AX_BH)) {
+      float cu = -hx * (sE[2][l + 1] - sE[2][l]);
+      if (D >= 3) cu += hz * (sE[0][l + LZ] - sE[0][l]);
+      sB[1][l] -= cu;
+    }
+    if ((bx & AX_BH) && (by & AX_BH) && (bz & AX_BN)) {
+      float cu = hx * (sE[1][l + 1] - sE[1][l]);
+      if (D >= 2) cu -= hy * (sE[0][l + LY] - sE[0][l]);
+      sB[2][l] -= cu;
+    }
+  }
+  __syncthreads();
+  // ---- C: E^{n+1} at interior positions on local [-1, T] (in place)
+  for (int l = threadIdx.x; l < NR; l += TPB) {
+    int qx, qy, qz;
+    split(l, qx, qy, qz);
+    if (qx < H - 1 || qx > T::X + H) continue;
+    if (D >= 2 && (qy < H - 1 || qy > T::Y + H)) continue;
+    if (D >= 3 && (qz < H - 1 || qz > T::Z + H)) continue;
+    const unsigned bx = sbx[qx], by = sby[qy], bz = sbz[qz];
+    if (!(bx & by & bz & AX_ARR)) continue;
+    const int ai = a0x + qx - H;
+    const int64_t gi = (int64_t)ai + soy[qy] + soz[qz];
+    if ((bx & AX_IH) && (by & AX_IN) && (bz & AX_IN)) {
+      float cu = 0.0f;
+      if (D >= 2) cu += Cy * (sB[2][l] - sB[2][l - LY]);
+      if (D >= 3) cu -= Cz * (sB[1][l] - sB[1][l - LZ]);
+      sE[0][l] += ieh[ai] * (cu - J0[gi]);
+    }
+    if ((bx & AX_IN) && (by & AX_IH) && (bz & AX_IN)) {
+      float cu = -Cx * (sB[2][l] - sB[2][l - 1]);
+      if (D >= 3) cu += Cz * (sB[0][l] - sB[0][l - LZ]);
+      sE[1][l] += ien[ai] * (cu - J1[gi]);
+    }
+    if ((bx & AX_IN) && (by & AX_IN) && (bz & AX_IH)) {
+      float cu = Cx * (sB[1][l] - sB[1][l - 1]);
+      if (D >= 2) cu -= Cy * (sB[0][l] - sB[0][l - LY]);
+      sE[2][l] += ien[ai] * (cu - J2[gi]);
+    }
+  }
+  __syncthreads();
+  // ---- D: outflow faces, lowest priority first (z, y, x); a point on several
+  // faces follows the first of x, y, z, with its inward neighbour's final value
+#pragma unroll
+  for (int d = 2; d >= 0; --d) {
+    if (d >= D) continue;
+    const bool perd = d == 1 ? py : (d == 2 ? pz : false);
+    if (perd) continue;
+    const int nd = d == 0 ? nx : (d == 1 ? ny : nz);
+    const int o0 = d == 0 ? i0 : (d == 1 ? j0 : k0);
+    const int Td = d == 0 ? T::X : (d == 1 ? T::Y : T::Z);
+    // does the tile's E region [-1, T] along d touch a face?
+    const bool touch = (o0 - 1 <= 0 && 0 <= o0 + Td) || (o0 - 1 <= nd && nd <= o0 + Td);
+    if (touch) {
+      const int ls = d == 0 ? 1 : (d == 1 ? LY : LZ);
+      float4 s0 = make_float4(0.f, 0.f, 0.f, 0.f), s1 = s0;
+      if (d == 0) {
+        if (step < I.nsrc) s0 = I.src[step];
+        if (step + 1 < I.nsrc) s1 = I.src[step + 1];
+      }
+      for (int l = threadIdx.x; l < NR; l += TPB) {
+        int qx, qy, qz;
+        split(l, qx, qy, qz);
+        if (qx < H - 1 || qx > T::X + H) continue;
+        if (D >= 2 && (qy < H - 1 || qy > T::Y + H)) continue;
+        if (D >= 3 && (qz < H - 1 || qz > T::Z + H)) continue;
+        const unsigned bx = sbx[qx], by = sby[qy], bz = sbz[qz];
+        const unsigned bd = d == 0 ? bx : (d == 1 ? by : bz);
+        if (!(bd & (AX_F0 | AX_F1))) continue;
+        const int inw = (bd & AX_F0) ? 1 : -1;
+        const int qd = (d == 0 ? qx : (d == 1 ? qy : qz)) + inw;
+        if (qd < H - 1 || qd > Td + H) continue;
+        const unsigned bb[3] = {bx, by, bz};
+        const int64_t gq = (int64_t)(a0x + qx - H) + soy[qy] + soz[qz];
+        const int64_t gr = gq + (d == 0 ? inw : (d == 1 ? inw * sy : inw * sz));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          if (c == d) continue;   // normal component: interior update only
+          // inside the box along the other axes, not on a face of higher priority
+          bool ok = true;
+#pragma unroll
+          for (int e = 0; e < 3; ++e) {
+            if (e == d || e >= D) continue;
+            const bool half = (e == c);
+            if (e < d) ok = ok && (bb[e] & (half ? AX_IH : AX_IN));
+            else ok = ok && (bb[e] & (half ? AX_BH : AX_BN));   // box incl. faces (periodic: any)
+          }
+          if (!ok) continue;
+          const float* Eold = c == 0 ? Ec0 : (c == 1 ? Ec1 : Ec2);
+          const float qold = Eold[gq], rold = Eold[gr], rnew = sE[c][l + inw * ls];
+          if (d == 0 && (bd & AX_F0) && c == I.pol) {
+            const float pr = I.prof[(soy[qy] / sy) + Py * (D >= 3 ? soz[qz] / sz : 0)];
+            const MurInc m{pr * s0.x, pr * s1.x, pr * s0.y, pr * s1.y};
+            sE[c][l] = mur_inc(qold, rold, rnew, I.kmur[0], m);
+          } else {
+            sE[c][l] = mur(qold, rold, rnew, I.kmur[d]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // ---- E: owned positions: b^{n+1}, E^{n+1} out, J cleared, amplitude window
+  const int nwin = I.nwin;
+  const int slot = step % (nwin > 0 ? nwin : 1);
+  const int wx0 = I.wx0, wx1 = I.wx1;
+  for (int l = threadIdx.x; l < NR; l += TPB) {
+    int qx, qy, qz;
+    split(l, qx, qy, qz);
+    if (qx < H || qx >= T::X + H) continue;
+    if (D >= 2 && (qy < H || qy >= T::Y + H)) continue;
+    if (D >= 3 && (qz < H || qz >= T::Z + H)) continue;
+    const int ai = a0x + qx - H;
+    const int aj = D >= 2 ? a0y + qy - H : 0;   // absent axes: index 0
+    const int ak = D >= 3 ? a0z + qz - H : 0;
+    if (ai >= Px || aj >= Py || ak >= Pz) continue;
+    const int64_t gi = (int64_t)ai + (int64_t)sy * aj + (int64_t)sz * ak;
+    Jn0[gi] = 0.0f;   // next push deposits here; nobody reads it now
+    Jn1[gi] = 0.0f;
+    Jn2[gi] = 0.0f;
+    const unsigned bx = sbx[qx], by = sby[qy], bz = sbz[qz];
+    // owned positions of periodic axes are the box itself (no wrapped copies)
+    const unsigned dy = D >= 2 && py ? (aj - G >= 0 && aj - G < ny ? ~0u : 0u) : ~0u;
+    const unsigned dz = D >= 3 && pz ? (ak - G >= 0 && ak - G < nz ? ~0u : 0u) : ~0u;
+    const bool xdn = bx & AX_DN, xdh = bx & AX_DH;
+    const bool ydn = by & dy & AX_DN, ydh = by & dy & AX_DH;
+    const bool zdn = bz & dz & AX_DN, zdh = bz & dz & AX_DH;
+    if (xdh && ydn && zdn) En0[gi] = sE[0][l];
+    if (xdn && ydh && zdn) En1[gi] = sE[1][l];
+    if (xdn && ydn && zdh) En2[gi] = sE[2][l];
+    if (xdn && ydh && zdh) {
+      float cu = 0.0f;
+      if (D >= 2) cu += hy * (sE[2][l + LY] - sE[2][l]);
+      if (D >= 3) cu -= hz * (sE[1][l + LZ] - sE[1][l]);
+      Bn0[gi] = sB[0][l] - cu;
+    }
+    if (xdh && ydn && zdh) {
+      float cu = -hx * (sE[2][l + 1] - sE[2][l]);
+      if (D >= 3) cu += hz * (sE[0][l + LZ] - sE[0][l]);
+      Bn1[gi] = sB[1][l] - cu;
+    }
+    if (xdh && ydh && zdn) {
+      float cu = hx * (sE[1][l + 1] - sE[1][l]);
+      if (D >= 2) cu -= hy * (sE[0][l + LY] - sE[0][l]);
+      Bn2[gi] = sB[2][l] - cu;
+    }
+    // node |E^{n+1}| (Yee components averaged to the node) into the window
+    if (ai >= wx0 && ai < wx1 && xdn && ydn && zdn) {
+      const float ex = 0.5f * (sE[0][l - 1] + sE[0][l]);
+      const float ey = D >= 2 ? 0.5f * (sE[1][l - LY] + sE[1][l]) : sE[1][l];
+      const float ez = D >= 3 ? 0.5f * (sE[2][l - LZ] + sE[2][l]) : sE[2][l];
+      const float m = sqrtf(ex * ex + ey * ey + ez * ez);
+      if (!(m <= 3.0e38f)) atomicOr(I.health, HEALTH_NONFINITE);
+      const int64_t wsz = I.wsz;
+      const int64_t w = (int64_t)(ai - wx0) + (int64_t)I.wnx * (aj + (int64_t)Py * ak);
+      float* __restrict__ ring = I.ring;
+      float* __restrict__ suffix = I.suffix;
+      ring[(int64_t)slot * wsz + w] = m;
+      const float pre = slot == 0 ? m : fmaxf(I.prefix[w], m);
+      I.prefix[w] = pre;
+      const float a = slot + 1 < nwin ? fmaxf(suffix[(int64_t)(slot + 1) * wsz + w], pre) : pre;
+      I.A[gi] = a;
+      if (slot == nwin - 1) {   // block of samples complete: suffix maxima for the next
+        float run = 0.0f;
+        for (int q = nwin - 1; q >= 0; --q) {
+          run = fmaxf(run, ring[(int64_t)q * wsz + w]);
+          suffix[(int64_t)q * wsz + w] = run;
+        }
+      }
     }
   }
 }
@@ -557,9 +714,13 @@ __device__ __forceinline__ void maxwell(uint64_t seed, uint64_t id, uint32_t pur
   uz = sig * r2 * cosf(tp * u4);
 }
 
+__device__ __forceinline__ int64_t div_ppc(const Inst& I, int64_t j) {
+  return I.ppc == 1 ? j : (int64_t)__umul64hi((uint64_t)j, I.ppc_magic);
+}
+
 template <int D>
 __device__ __forceinline__ uint64_t neutral_id(const Inst& I, int64_t jn, int& ci, int& cj, int& ck) {
-  const int64_t m = jn / I.ppc;
+  const int64_t m = div_ppc(I, jn);
   const int64_t kk = jn - m * I.ppc;
   unpack_cell(D, I.mcell[m], ci, cj, ck);
   const int64_t lin = ci + (int64_t)I.nx * (cj + (int64_t)I.ny * ck);
@@ -567,11 +728,52 @@ __device__ __forceinline__ uint64_t neutral_id(const Inst& I, int64_t jn, int& c
 }
 
 template <int D, int ORDER>
+__device__ __forceinline__ void ionize_one(const Inst& I, int64_t jn, int step);
+
+// Ionization of the alive neutrals with the amplitude after the field update.
+// A block first marks which of its material cells can ionize at all: the
+// largest windowed amplitude over the nodes any neutral of the cell can reach
+// must reach the material's cut (an exact test: the shape weights are
+// non-negative and sum to one).  Neutrals of the other cells read nothing more.
+template <int D, int ORDER>
 __global__ __launch_bounds__(TPB) void k_ionize(Group g) {
+  __shared__ unsigned char hot[TPB + 2];
   const int ii = find_inst(g);
   const Inst& I = g.insts[ii];
-  const int64_t jn = (int64_t)(blockIdx.x - g.off[ii]) * TPB + threadIdx.x;
-  if (jn >= I.nneut) return;
+  const int step = g.step >= 0 ? g.step : *I.step;
+  const int64_t j0 = (int64_t)(blockIdx.x - g.off[ii]) * TPB;
+  const int64_t nneut = I.nneut;
+  if (j0 >= nneut) return;
+  const int64_t m0 = div_ppc(I, j0);
+  const int64_t jl = (j0 + TPB < nneut ? j0 + TPB : nneut) - 1;
+  const int ncell = (int)(div_ppc(I, jl) - m0 + 1);
+  for (int t = threadIdx.x; t < ncell; t += TPB) {
+    int ci, cj, ck;
+    unpack_cell(D, I.mcell[m0 + t], ci, cj, ck);
+    const int mat = I.mat_cell[ci];
+    constexpr int lo = ORDER == 2 ? -1 : 0, hi = ORDER == 2 ? 2 : 1;
+    float amax = 0.0f;
+    for (int c = (D >= 3 ? lo : 0); c <= (D >= 3 ? hi : 0); ++c) {
+      const int oz = D >= 3 ? I.sz * (wrapi(ck + c, I.nz, I.per_z) + I.Gz) : 0;
+      for (int b = (D >= 2 ? lo : 0); b <= (D >= 2 ? hi : 0); ++b) {
+        const int oy = D >= 2 ? I.sy * (wrapi(cj + b, I.ny, I.per_y) + I.Gy) : 0;
+        for (int a = lo; a <= hi; ++a) amax = fmaxf(amax, I.A[ci + a + G + oy + oz]);
+      }
+    }
+    hot[t] = mat >= 0 && amax >= I.acut[mat];
+  }
+  __syncthreads();
+  const int64_t jn = j0 + threadIdx.x;
+  if (jn < nneut && hot[div_ppc(I, jn) - m0]) ionize_one<D, ORDER>(I, jn, step);
+}
+
+__global__ void k_advance(const Inst* insts, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) *insts[i].step += 1;
+}
+
+template <int D, int ORDER>
+__device__ __forceinline__ void ionize_one(const Inst& I, int64_t jn, int step) {
   if (!((I.alive[jn >> 5] >> (jn & 31)) & 1u)) return;
   int ci, cj, ck;
   const uint64_t id = neutral_id<D>(I, jn, ci, cj, ck);
@@ -587,7 +789,7 @@ __global__ __launch_bounds__(TPB) void k_ionize(Group g) {
   const int mat = I.mat_cell[ci];
   if (mat < 0 || !(Ap >= I.acut[mat])) return;
   const float P = table_lookup(I.tab[mat], Ap);
-  const int n1 = *I.step + 1;
+  const int n1 = step + 1;
   const u32x4 w = draw(I.seed, id, (uint32_t)n1, PURPOSE_IONIZE);
   // event iff (w + 1/2) 2^-32 < P, decided exactly in FP64
   if (!((double)w.x + 0.5 < (double)P * 4294967296.0)) return;
@@ -614,11 +816,6 @@ __global__ __launch_bounds__(TPB) void k_ionize(Group g) {
     I.pu2[q] = uz;
     I.pkind[q] = (uint8_t)(2 * mat + s);
   }
-}
-
-__global__ void k_advance(const Inst* insts, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) *insts[i].step += 1;
 }
 
 // ------------------------------------------------------------------ setup
@@ -696,12 +893,13 @@ __global__ __launch_bounds__(TPB) void k_diag_particles(const Inst* d, double* a
 
 __global__ __launch_bounds__(TPB) void k_diag_field_energy(const Inst* d, int64_t ncell, double* acc) {
   const Inst& I = *d;
+  const int par = *I.step & 1;
   double s = 0.0;
   for (int64_t p = (int64_t)blockIdx.x * TPB + threadIdx.x; p < ncell; p += (int64_t)gridDim.x * TPB) {
     const int ai = (int)(p % I.Px);
-    const double ex = I.E0[p], ey = I.E1[p], ez = I.E2[p];
+    const double ex = I.F[par][0][p], ey = I.F[par][1][p], ez = I.F[par][2][p];
     s += ex * ex / I.ie_half[ai] + (ey * ey + ez * ez) / I.ie_node[ai];
-    const double bx = I.B0[p], by = I.B1[p], bz = I.B2[p];
+    const double bx = I.F[par][3][p], by = I.F[par][4][p], bz = I.F[par][5][p];
     s += bx * bx + by * by + bz * bz;
   }
   __shared__ double sh[TPB];
@@ -759,6 +957,10 @@ template <int D>
 __global__ __launch_bounds__(TPB) void k_diag_gauss(const Inst* d, const double* rho, double* acc) {
   const Inst& I = *d;
   const int64_t ncell = (int64_t)I.Px * I.Py * I.Pz;
+  const int par = *I.step & 1;
+  const float* E0 = I.F[par][0];
+  const float* E1 = I.F[par][1];
+  const float* E2 = I.F[par][2];
   double mres = 0.0, mrho = 0.0;
   for (int64_t p = (int64_t)blockIdx.x * TPB + threadIdx.x; p < ncell; p += (int64_t)gridDim.x * TPB) {
     int i, j, k;
@@ -767,14 +969,14 @@ __global__ __launch_bounds__(TPB) void k_diag_gauss(const Inst* d, const double*
     if (D >= 2 && (I.per_y ? (j < 0 || j >= I.ny) : (j < 1 || j > I.ny - 1))) continue;
     if (D >= 3 && (I.per_z ? (k < 0 || k >= I.nz) : (k < 1 || k > I.nz - 1))) continue;
     const int ai = i + G;
-    double div = ((double)I.E0[p] / I.ie_half[ai] - (double)I.E0[p - 1] / I.ie_half[ai - 1]) / I.dx[0];
+    double div = ((double)E0[p] / I.ie_half[ai] - (double)E0[p - 1] / I.ie_half[ai - 1]) / I.dx[0];
     if (D >= 2) {
       const int dym = I.per_y && j == 0 ? (I.ny - 1) * I.sy : -I.sy;
-      div += ((double)I.E1[p] - (double)I.E1[p + dym]) / I.ie_node[ai] / I.dx[1];
+      div += ((double)E1[p] - (double)E1[p + dym]) / I.ie_node[ai] / I.dx[1];
     }
     if (D >= 3) {
       const int dzm = I.per_z && k == 0 ? (I.nz - 1) * I.sz : -I.sz;
-      div += ((double)I.E2[p] - (double)I.E2[p + dzm]) / I.ie_node[ai] / I.dx[2];
+      div += ((double)E2[p] - (double)E2[p + dzm]) / I.ie_node[ai] / I.dx[2];
     }
     mres = fmax(mres, fabs(div - rho[p]));
     mrho = fmax(mrho, fabs(rho[p]));
@@ -803,15 +1005,21 @@ void launch_push(const Group& g, int D, int order, hipStream_t s) {
     DISPATCH_D(D, hipLaunchKernelGGL((k_push<DD, 2>), dim3(g.blocks), dim3(TPB), 0, s, g));
   }
 }
-void launch_bhalf(const Group& g, int D, hipStream_t s) {
-  DISPATCH_D(D, hipLaunchKernelGGL((k_bhalf<DD>), dim3(g.blocks), dim3(TPB), 0, s, g));
+#define FIELDS_V(DD, V) hipLaunchKernelGGL((k_fields<DD, V>), dim3(g.blocks), dim3(TPB), 0, s, g)
+void launch_fields(const Group& g, int D, int variant, hipStream_t s) {
+  switch (variant) {
+    case 1: DISPATCH_D(D, FIELDS_V(DD, 1)); break;
+    case 2: DISPATCH_D(D, FIELDS_V(DD, 2)); break;
+    case 3: DISPATCH_D(D, FIELDS_V(DD, 3)); break;
+    case 4: DISPATCH_D(D, FIELDS_V(DD, 4)); break;
+    default: DISPATCH_D(D, FIELDS_V(DD, 0)); break;
+  }
 }
-void launch_efull(const Group& g, int D, hipStream_t s) {
-  DISPATCH_D(D, hipLaunchKernelGGL((k_efull<DD>), dim3(g.blocks), dim3(TPB), 0, s, g));
+int field_tiles(int D, int variant, int Px, int Py, int Pz) {
+  const TileShape t = tile_shape(D, variant);
+  return ((Px + t.x - 1) / t.x) * (D >= 2 ? (Py + t.y - 1) / t.y : 1) * (D >= 3 ? (Pz + t.z - 1) / t.z : 1);
 }
-void launch_amp(const Group& g, int D, hipStream_t s) {
-  DISPATCH_D(D, hipLaunchKernelGGL((k_amp<DD>), dim3(g.blocks), dim3(TPB), 0, s, g));
-}
+int field_tile_variants() { return kTileVariants; }
 void launch_ionize(const Group& g, int D, int order, hipStream_t s) {
   if (order == 1) {
     DISPATCH_D(D, hipLaunchKernelGGL((k_ionize<DD, 1>), dim3(g.blocks), dim3(TPB), 0, s, g));

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -31,7 +32,7 @@ struct Layout {
   int wx0, wx1;
   int64_t wsz;
   int nsrc;
-  size_t o_E[3], o_B[3], o_J[3], o_ie_half, o_ie_node, o_mat, o_src, o_prof;
+  size_t o_F[2][6], o_J[2][3], o_ie_half, o_ie_node, o_mat, o_src, o_prof;
   size_t o_ring, o_suffix, o_prefix, o_A;
   size_t o_no[3], o_alive, o_death, o_mcell;
   size_t o_pcell, o_po[3], o_pu[3], o_pkind;
@@ -47,7 +48,7 @@ struct Ctr {
   int pcount;
   int step;
   unsigned health;
-  int pad;
+  unsigned done;
   unsigned long long nevents[MAXMAT];
   double acc[64];
 };
@@ -76,7 +77,7 @@ pic_status plan(const pic_config* cfg, const Canon& c, const std::vector<TableHo
   L->wsz = (int64_t)(L->wx1 - L->wx0) * L->Py * L->Pz;
   int64_t cap = cfg->particle_capacity > 0 ? cfg->particle_capacity : 2 * L->nneut + 4096;
   if (cfg->preionize_eV > 0) cap = std::max<int64_t>(cap, 2 * L->nneut);
-  if (cap > INT_MAX - 16 || L->nneut > ((int64_t)1 << 40)) return PIC_E_INVAL;
+  if (cap > INT_MAX - 16 || L->nneut > ((int64_t)1 << 40) || c.ppc > 65535) return PIC_E_INVAL;
   L->capacity = cap;
   // source samples cover the planned steps and the whole pulse (Gaussian: to
   // t0 + 8 fwhm, where the envelope is below 1e-38; sin^2: its full length)
@@ -90,9 +91,10 @@ pic_status plan(const pic_config* cfg, const Canon& c, const std::vector<TableHo
     return r;
   };
   const size_t f = sizeof(float) * (size_t)L->ncell;
-  for (int q = 0; q < 3; ++q) L->o_E[q] = take(f);
-  for (int q = 0; q < 3; ++q) L->o_B[q] = take(f);
-  for (int q = 0; q < 3; ++q) L->o_J[q] = take(f);
+  for (int par = 0; par < 2; ++par)
+    for (int q = 0; q < 6; ++q) L->o_F[par][q] = take(f);
+  for (int par = 0; par < 2; ++par)
+    for (int q = 0; q < 3; ++q) L->o_J[par][q] = take(f);
   L->o_ie_half = take(sizeof(float) * L->Px);
   L->o_ie_node = take(sizeof(float) * L->Px);
   L->o_mat = take(c.n[0]);
@@ -136,14 +138,26 @@ struct pic_ctx {
   Inst* d_inst = nullptr;
   int* d_off = nullptr;   // [0, nb_push, 0, nb_cell, 0, nb_win, 0, nb_neut]
   int nb_push = 0, nb_cell = 0, nb_win = 0, nb_neut = 0;
+  int tile = 0;               // field-kernel tile variant
+  double tune_ms[8] = {0};    // autotuner: ms per field launch of each variant
   Ctr* d_ctr = nullptr;
   double* d_grid64 = nullptr;
   std::vector<uint32_t> mcell;
   int64_t step = 0;
   pic_status latched = PIC_OK;
   int timing = 0;
-  double timers[8] = {0};
+  double timers[8] = {0};     // accumulated ms per phase
+  double tcount[8] = {0};     // launches timed per phase
+  // event ring per phase: record around each launch, read back when reused
+  static constexpr int kRing = 64;
+  hipEvent_t ev[8][kRing][2] = {};
+  int ev_used[8][kRing] = {};
+  int64_t ev_slot = 0;
   int owns_alloc_via_cb = 0;
+  int d_off_push = -1;        // push blocks currently in d_off (single-run launches)
+  int* h_count = nullptr;     // pinned: charged slots used, copied back after each pic_step
+  int* h_off = nullptr;       // pinned: staging for the push-phase block offsets
+  int* h_step = nullptr;      // pinned: staging for the device step counter
 };
 
 struct pic_batch {
@@ -151,7 +165,7 @@ struct pic_batch {
   bool dirty = true;
   // per (D, order) class: device Inst copies and per-phase block offsets
   struct Class {
-    int D, order;
+    int D, order, tile = 0;
     std::vector<pic_ctx*> ms;
     Inst* d_insts = nullptr;
     int* d_off = nullptr;   // 4 phases x (n + 1)
@@ -172,19 +186,64 @@ namespace {
 inline void* devp(pic_ctx* c, size_t off) { return c->base + off; }
 
 Group single(pic_ctx* c, int phase, int nb) {
-  return Group{c->d_inst, c->d_off + 2 * phase, 1, nb};
+  return Group{c->d_inst, c->d_off + 2 * phase, 1, nb, (int)c->step};
 }
 
+// Phase timing: events recorded on the context stream around each launch;
+// a ring slot is read back (and accumulated) before it is reused.
+void harvest(pic_ctx* c, int ph, int slot) {
+  if (!c->ev_used[ph][slot]) return;
+  float ms = 0.f;
+  if (hipEventSynchronize(c->ev[ph][slot][1]) == hipSuccess &&
+      hipEventElapsedTime(&ms, c->ev[ph][slot][0], c->ev[ph][slot][1]) == hipSuccess) {
+    c->timers[ph] += ms;
+    c->tcount[ph] += 1.0;
+  }
+  c->ev_used[ph][slot] = 0;
+}
+
+template <typename F>
+void timed(pic_ctx* c, int ph, F&& launch) {
+  if (!c->timing) {
+    launch();
+    return;
+  }
+  const int slot = (int)(c->ev_slot % pic_ctx::kRing);
+  harvest(c, ph, slot);
+  if (!c->ev[ph][slot][0]) {
+    if (hipEventCreate(&c->ev[ph][slot][0]) != hipSuccess || hipEventCreate(&c->ev[ph][slot][1]) != hipSuccess) {
+      launch();
+      return;
+    }
+  }
+  (void)hipEventRecord(c->ev[ph][slot][0], c->stream);
+  launch();
+  (void)hipEventRecord(c->ev[ph][slot][1], c->stream);
+  c->ev_used[ph][slot] = 1;
+}
+
+void harvest_all(pic_ctx* c) {
+  for (int ph = 0; ph < 8; ++ph)
+    for (int k = 0; k < pic_ctx::kRing; ++k) harvest(c, ph, k);
+}
+
+// phases: 0 push, 1 fields (Yee step, outflow faces, amplitude window),
+// 2 ionize (+ step counter)
 void enqueue_step(pic_ctx* c) {
   const int D = c->canon.D, order = c->cfg.shape_order;
   hipStream_t s = c->stream;
-  launch_push(single(c, 0, c->nb_push), D, order, s);
-  launch_bhalf(single(c, 1, c->nb_cell), D, s);
-  launch_efull(single(c, 1, c->nb_cell), D, s);
-  launch_bhalf(single(c, 1, c->nb_cell), D, s);
-  if (c->nb_win > 0) launch_amp(single(c, 2, c->nb_win), D, s);
-  if (c->nb_neut > 0) launch_ionize(single(c, 3, c->nb_neut), D, order, s);
-  launch_advance(c->d_inst, 1, s);
+  timed(c, 0, [&] { launch_push(single(c, 0, c->nb_push), D, order, s); });
+  timed(c, 1, [&] { launch_fields(single(c, 1, c->nb_cell), D, c->tile, s); });
+  timed(c, 2, [&] { launch_ionize(single(c, 3, c->nb_neut), D, order, s); });
+  ++c->ev_slot;
+  ++c->step;
+}
+
+// push grid: enough threads for the charged particles last seen (grid-stride
+// covers any births since), at least 32 blocks
+int push_blocks(int64_t count) {
+  const int64_t nb = (count + TPB * 4 - 1) / (TPB * 4);
+  return (int)std::max<int64_t>(32, std::min<int64_t>(nb, 8192));
 }
 
 // padded index of logical (i, j, k)
@@ -356,6 +415,11 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
     pic_destroy(c);
     return s;
   };
+  if (hipHostMalloc((void**)&c->h_count, sizeof(int)) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_off, 4 * sizeof(int)) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_step, sizeof(int)) != hipSuccess)
+    return fail(PIC_E_NOMEM);
+  *c->h_count = c->cfg.preionize_eV > 0 ? (int)(2 * L.nneut) : 0;
   if (hipMemsetAsync(c->base, 0, L.total, c->stream) != hipSuccess) return fail(PIC_E_DEVICE);
 
   // ---- host-built tables and parameter block
@@ -408,17 +472,10 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
   }
   I.vcell = K.vcell;
   I.ctdt_m = (float)(kC * K.dt);
-  float* fE[3];
-  for (int q = 0; q < 3; ++q) fE[q] = (float*)devp(c, L.o_E[q]);
-  I.E0 = fE[0];
-  I.E1 = fE[1];
-  I.E2 = fE[2];
-  I.B0 = (float*)devp(c, L.o_B[0]);
-  I.B1 = (float*)devp(c, L.o_B[1]);
-  I.B2 = (float*)devp(c, L.o_B[2]);
-  I.J0 = (float*)devp(c, L.o_J[0]);
-  I.J1 = (float*)devp(c, L.o_J[1]);
-  I.J2 = (float*)devp(c, L.o_J[2]);
+  for (int par = 0; par < 2; ++par) {
+    for (int q = 0; q < 6; ++q) I.F[par][q] = (float*)devp(c, L.o_F[par][q]);
+    for (int q = 0; q < 3; ++q) I.Jb[par][q] = (float*)devp(c, L.o_J[par][q]);
+  }
   I.ie_half = (const float*)devp(c, L.o_ie_half);
   I.ie_node = (const float*)devp(c, L.o_ie_node);
   I.mat_cell = (const signed char*)devp(c, L.o_mat);
@@ -468,6 +525,7 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
   }
   I.nneut = L.nneut;
   I.ppc = K.ppc;
+  I.ppc_magic = K.ppc > 1 ? UINT64_MAX / (uint64_t)K.ppc + 1 : 0;
   I.no0 = (float*)devp(c, L.o_no[0]);
   I.no1 = (float*)devp(c, L.o_no[1]);
   I.no2 = (float*)devp(c, L.o_no[2]);
@@ -481,11 +539,17 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
 
   // block counts per phase
   auto nblk = [](int64_t n) { return (int)std::max<int64_t>(0, (n + TPB - 1) / TPB); };
-  c->nb_push = std::max(1, std::min(nblk(L.capacity), 4096));
-  c->nb_cell = nblk(L.ncell);
-  c->nb_win = nblk(L.wsz);
-  c->nb_neut = nblk(L.nneut);
+  c->nb_push = push_blocks(c->cfg.preionize_eV > 0 ? 2 * L.nneut : 0);
+  // field tile shape: default per dimension, overridable (tuning sweeps) by
+  // PIC_FIELD_TILE=<variant>
+  c->tile = 0;
+  if (const char* tv = std::getenv("PIC_FIELD_TILE")) c->tile = std::max(0, std::min(atoi(tv), field_tile_variants() - 1));
+  c->nb_cell = field_tiles(D, c->tile, (int)L.Px, (int)L.Py, (int)L.Pz);
+  c->nb_win = 0;
+  c->nb_neut = std::max(1, nblk(L.nneut));
+
   const int offs[8] = {0, c->nb_push, 0, c->nb_cell, 0, c->nb_win, 0, c->nb_neut};
+  c->d_off_push = c->nb_push;
 
   hipStream_t s = c->stream;
   bool ok = true;
@@ -527,6 +591,13 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
 void pic_destroy(pic_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream); else (void)hipDeviceSynchronize();
+  for (int ph = 0; ph < 8; ++ph)
+    for (int k = 0; k < pic_ctx::kRing; ++k)
+      for (int e = 0; e < 2; ++e)
+        if (c->ev[ph][k][e]) (void)hipEventDestroy(c->ev[ph][k][e]);
+  if (c->h_count) (void)hipHostFree(c->h_count);
+  if (c->h_off) (void)hipHostFree(c->h_off);
+  if (c->h_step) (void)hipHostFree(c->h_step);
   if (c->base) {
     if (c->owns_alloc_via_cb && c->cfg.free) c->cfg.free(c->base, c->cfg.alloc_user);
     else if (!c->owns_alloc_via_cb) (void)hipFree(c->base);
@@ -536,17 +607,89 @@ void pic_destroy(pic_ctx* c) {
 
 pic_status pic_set_timing(pic_ctx* c, int32_t on) {
   if (!c) return PIC_E_INVAL;
+  harvest_all(c);
   c->timing = on;
+  for (int ph = 0; ph < 8; ++ph) c->timers[ph] = c->tcount[ph] = 0.0;
   return PIC_OK;
+}
+
+// Resize the push grid from the last charged-slot count seen on the host.
+static void refresh_push_grid(pic_ctx* c) {
+  const int nb = push_blocks(std::max<int64_t>(*c->h_count, 0));
+  c->nb_push = nb;
+  if (nb == c->d_off_push) return;
+  c->d_off_push = nb;
+  c->h_off[0] = 0;
+  c->h_off[1] = nb;
+  (void)hipMemcpyAsync(c->d_off, c->h_off, 2 * sizeof(int), hipMemcpyHostToDevice, c->stream);
 }
 
 pic_status pic_step(pic_ctx* c, int64_t nsteps) {
   if (!c || nsteps < 0) return PIC_E_INVAL;
   if (c->latched != PIC_OK) return PIC_E_STATE;
   (void)hipGetLastError();
-  for (int64_t s = 0; s < nsteps; ++s) enqueue_step(c);
-  c->step += nsteps;
+  refresh_push_grid(c);
+  for (int64_t s = 0; s < nsteps; ++s) enqueue_step(c);   // advances c->step
+  // keep the device step counter (read by batches and diagnostics) in step
+  *c->h_step = (int)c->step;
+  (void)hipMemcpyAsync(&c->d_ctr->step, c->h_step, sizeof(int), hipMemcpyHostToDevice, c->stream);
+  (void)hipMemcpyAsync(c->h_count, &c->d_ctr->pcount, sizeof(int), hipMemcpyDeviceToHost, c->stream);
   if (hipGetLastError() != hipSuccess) return PIC_E_DEVICE;
+  return PIC_OK;
+}
+
+// Field-kernel tile autotuner: before the first step the fields, currents and
+// amplitude window are all zero, so every variant can be timed on the real
+// launch shape; the state is cleared again afterwards (exactly the initial state).
+pic_status pic_autotune(pic_ctx* c, int32_t reps) {
+  if (!c || reps < 1) return PIC_E_INVAL;
+  if (c->step != 0 || c->cfg.preionize_eV > 0) return PIC_E_STATE;
+  const Layout& L = c->L;
+  const int D = c->canon.D;
+  hipStream_t s = c->stream;
+  hipEvent_t e0, e1;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventCreate(&e1));
+  double best = 1e30;
+  int best_v = c->tile;
+  int offs[2];
+  for (int v = 0; v < field_tile_variants(); ++v) {
+    const int nb = field_tiles(D, v, (int)L.Px, (int)L.Py, (int)L.Pz);
+    offs[0] = 0;
+    offs[1] = nb;
+    HIP_OK(hipMemcpy(c->d_off + 2, offs, sizeof offs, hipMemcpyHostToDevice));
+    Group gr{c->d_inst, c->d_off + 2, 1, nb, 0};
+    launch_fields(gr, D, v, s);   // warm
+    HIP_OK(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) launch_fields(gr, D, v, s);
+    HIP_OK(hipEventRecord(e1, s));
+    HIP_OK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+    c->tune_ms[v] = ms / reps;
+    if (ms < best) {
+      best = ms;
+      best_v = v;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->tile = best_v;
+  c->nb_cell = field_tiles(D, best_v, (int)L.Px, (int)L.Py, (int)L.Pz);
+  offs[0] = 0;
+  offs[1] = c->nb_cell;
+  HIP_OK(hipMemcpy(c->d_off + 2, offs, sizeof offs, hipMemcpyHostToDevice));
+  // back to the initial state: fields, currents, window and amplitude zero
+  for (int par = 0; par < 2; ++par) {
+    for (int q = 0; q < 6; ++q) HIP_OK(hipMemsetAsync(devp(c, L.o_F[par][q]), 0, sizeof(float) * L.ncell, s));
+    for (int q = 0; q < 3; ++q) HIP_OK(hipMemsetAsync(devp(c, L.o_J[par][q]), 0, sizeof(float) * L.ncell, s));
+  }
+  HIP_OK(hipMemsetAsync(devp(c, L.o_ring), 0, sizeof(float) * L.wsz * c->canon.nwin, s));
+  HIP_OK(hipMemsetAsync(devp(c, L.o_suffix), 0, sizeof(float) * L.wsz * c->canon.nwin, s));
+  HIP_OK(hipMemsetAsync(devp(c, L.o_prefix), 0, sizeof(float) * L.wsz, s));
+  HIP_OK(hipMemsetAsync(devp(c, L.o_A), 0, sizeof(float) * L.ncell, s));
+  HIP_OK(hipMemsetAsync(&c->d_ctr->health, 0, sizeof(unsigned), s));
+  HIP_OK(hipStreamSynchronize(s));
   return PIC_OK;
 }
 
@@ -560,6 +703,7 @@ pic_status pic_set_state(pic_ctx* c, const pic_state* S) {
   hipStream_t s = c->stream;
   if (hipStreamSynchronize(s) != hipSuccess) return PIC_E_DEVICE;
   std::vector<float> buf(L.ncell);
+  const int spar = (int)(S->step & 1);
   for (int w = 0; w < 2; ++w)
     for (int q = 0; q < 3; ++q) {
       const float* src = w == 0 ? S->E[q] : S->b[q];
@@ -567,7 +711,7 @@ pic_status pic_set_state(pic_ctx* c, const pic_state* S) {
       std::fill(buf.begin(), buf.end(), 0.0f);
       const bool* half = w == 0 ? kHalfE[q] : kHalfB[q];
       for_domain(K, half, [&](int64_t n, int64_t i, int64_t j, int64_t k) { buf[pidx(L, D, i, j, k)] = src[n]; });
-      HIP_OK(hipMemcpy(devp(c, w == 0 ? L.o_E[q] : L.o_B[q]), buf.data(), sizeof(float) * L.ncell,
+      HIP_OK(hipMemcpy(devp(c, L.o_F[spar][3 * w + q]), buf.data(), sizeof(float) * L.ncell,
                        hipMemcpyHostToDevice));
     }
   const int64_t n = S->n_particles;
@@ -601,6 +745,7 @@ pic_status pic_set_state(pic_ctx* c, const pic_state* S) {
     }
     const int cnt = (int)n;
     HIP_OK(hipMemcpy(&c->d_ctr->pcount, &cnt, sizeof cnt, hipMemcpyHostToDevice));
+    *c->h_count = cnt;
   }
   const int st = (int)S->step;
   HIP_OK(hipMemcpy(&c->d_ctr->step, &st, sizeof st, hipMemcpyHostToDevice));
@@ -611,7 +756,8 @@ pic_status pic_set_state(pic_ctx* c, const pic_state* S) {
     HIP_OK(hipMemset(devp(c, L.o_prefix), 0, sizeof(float) * L.wsz));
     HIP_OK(hipMemset(devp(c, L.o_A), 0, sizeof(float) * L.ncell));
   }
-  for (int q = 0; q < 3; ++q) HIP_OK(hipMemset(devp(c, L.o_J[q]), 0, sizeof(float) * L.ncell));
+  for (int par = 0; par < 2; ++par)
+    for (int q = 0; q < 3; ++q) HIP_OK(hipMemset(devp(c, L.o_J[par][q]), 0, sizeof(float) * L.ncell));
   HIP_OK(hipDeviceSynchronize());
   return PIC_OK;
 }
@@ -635,7 +781,7 @@ pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size
     case PIC_DIAG_UE_GRID: need = sizeof(double) * dom_count(K, kNode); break;
     case PIC_DIAG_AMP: need = sizeof(float) * dom_count(K, kNode); break;
     case PIC_DIAG_PARAMS: need = sizeof(pic_params); break;
-    case PIC_DIAG_TIMERS: need = sizeof(double) * 8; break;
+    case PIC_DIAG_TIMERS: need = sizeof(double) * 24; break;
     case PIC_DIAG_EVENTS:
     case PIC_DIAG_PARTICLES: break;   // computed below
     default: return PIC_E_INVAL;
@@ -707,9 +853,11 @@ pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size
   if (kind == PIC_DIAG_FIELDS) {
     double* o = (double*)host_out;
     std::vector<float> buf(L.ncell);
+    int dstep = 0;
+    HIP_OK(hipMemcpy(&dstep, &c->d_ctr->step, sizeof dstep, hipMemcpyDeviceToHost));
     for (int w = 0; w < 2; ++w)
       for (int q = 0; q < 3; ++q) {
-        HIP_OK(hipMemcpy(buf.data(), devp(c, w == 0 ? L.o_E[q] : L.o_B[q]), sizeof(float) * L.ncell,
+        HIP_OK(hipMemcpy(buf.data(), devp(c, L.o_F[dstep & 1][3 * w + q]), sizeof(float) * L.ncell,
                          hipMemcpyDeviceToHost));
         const bool* half = w == 0 ? kHalfE[q] : kHalfB[q];
         for_domain(K, half, [&](int64_t n, int64_t i, int64_t j, int64_t k) { o[n] = buf[pidx(L, D, i, j, k)]; });
@@ -748,7 +896,14 @@ pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size
     return PIC_OK;
   }
   if (kind == PIC_DIAG_TIMERS) {
-    std::memcpy(host_out, c->timers, sizeof c->timers);
+    harvest_all(c);
+    double* o = (double*)host_out;
+    for (int ph = 0; ph < 8; ++ph) {
+      o[ph] = c->timers[ph];
+      o[8 + ph] = c->tcount[ph];
+    }
+    for (int v = 0; v < 7; ++v) o[16 + v] = c->tune_ms[v];
+    o[23] = c->tile;
     return PIC_OK;
   }
   // ---- SCALARS
@@ -847,12 +1002,13 @@ static pic_status batch_rebuild(pic_batch* b) {
   for (pic_ctx* c : b->members) {
     pic_batch::Class* cl = nullptr;
     for (auto& k : b->classes)
-      if (k.D == c->canon.D && k.order == c->cfg.shape_order) cl = &k;
+      if (k.D == c->canon.D && k.order == c->cfg.shape_order && k.tile == c->tile) cl = &k;
     if (!cl) {
       b->classes.push_back(pic_batch::Class{});
       cl = &b->classes.back();
       cl->D = c->canon.D;
       cl->order = c->cfg.shape_order;
+      cl->tile = c->tile;
     }
     cl->ms.push_back(c);
   }
@@ -879,6 +1035,13 @@ pic_status pic_batch_step(pic_batch* b, int64_t nsteps) {
   if (!b || nsteps < 0) return PIC_E_INVAL;
   for (pic_ctx* c : b->members)
     if (c->latched != PIC_OK) return PIC_E_STATE;
+  for (pic_ctx* c : b->members) {
+    const int nb = push_blocks(std::max<int64_t>(*c->h_count, 0));
+    if (nb != c->nb_push) {
+      c->nb_push = nb;
+      b->dirty = true;
+    }
+  }
   if (b->dirty) {
     pic_status st = batch_rebuild(b);
     if (st != PIC_OK) return st;
@@ -888,20 +1051,19 @@ pic_status pic_batch_step(pic_batch* b, int64_t nsteps) {
   for (int64_t t = 0; t < nsteps; ++t) {
     for (auto& cl : b->classes) {
       const int np1 = cl.n + 1;
-      Group gp{cl.d_insts, cl.d_off + 0 * np1, cl.n, cl.blocks[0]};
-      Group gc{cl.d_insts, cl.d_off + 1 * np1, cl.n, cl.blocks[1]};
-      Group gw{cl.d_insts, cl.d_off + 2 * np1, cl.n, cl.blocks[2]};
-      Group gn{cl.d_insts, cl.d_off + 3 * np1, cl.n, cl.blocks[3]};
+      Group gp{cl.d_insts, cl.d_off + 0 * np1, cl.n, cl.blocks[0], -1};
+      Group gc{cl.d_insts, cl.d_off + 1 * np1, cl.n, cl.blocks[1], -1};
+      Group gn{cl.d_insts, cl.d_off + 3 * np1, cl.n, cl.blocks[3], -1};
       launch_push(gp, cl.D, cl.order, s);
-      launch_bhalf(gc, cl.D, s);
-      launch_efull(gc, cl.D, s);
-      launch_bhalf(gc, cl.D, s);
-      if (gw.blocks > 0) launch_amp(gw, cl.D, s);
-      if (gn.blocks > 0) launch_ionize(gn, cl.D, cl.order, s);
+      launch_fields(gc, cl.D, cl.tile, s);
+      launch_ionize(gn, cl.D, cl.order, s);
       launch_advance(cl.d_insts, cl.n, s);
     }
   }
-  for (pic_ctx* c : b->members) c->step += nsteps;
+  for (pic_ctx* c : b->members) {
+    c->step += nsteps;
+    (void)hipMemcpyAsync(c->h_count, &c->d_ctr->pcount, sizeof(int), hipMemcpyDeviceToHost, s);
+  }
   if (hipGetLastError() != hipSuccess) return PIC_E_DEVICE;
   return PIC_OK;
 }

@@ -91,7 +91,7 @@ class State(C.Structure):
 SYMBOLS = ["pic_init", "pic_step", "pic_diag", "pic_set_state", "pic_footprint", "pic_canonical",
            "pic_keldysh_rate", "pic_table_probe", "pic_table_probe_device", "pic_batch_create",
            "pic_batch_step", "pic_batch_add", "pic_batch_remove", "pic_batch_destroy",
-           "pic_set_timing", "pic_destroy", "pic_status_str"]
+           "pic_set_timing", "pic_autotune", "pic_destroy", "pic_status_str"]
 
 
 def lib():
@@ -127,6 +127,7 @@ def lib():
             "pic_batch_remove": ([vp, vp], C.c_int),
             "pic_batch_destroy": ([vp], None),
             "pic_set_timing": ([vp, i32], C.c_int),
+            "pic_autotune": ([vp, i32], C.c_int),
             "pic_destroy": ([vp], None),
             "pic_status_str": ([C.c_int], C.c_char_p),
         }
@@ -251,6 +252,12 @@ class Context:
 
     def set_timing(self, on):
         _check(lib().pic_set_timing(self.h, int(on)), "pic_set_timing")
+
+    def autotune(self, reps=20):
+        """Pick the fastest field-kernel tile shape (before the first step)."""
+        _check(lib().pic_autotune(self.h, int(reps)), "pic_autotune")
+        t = self.timers()
+        return dict(chosen=int(t[23]), ms=[float(x) for x in t[16:23]])
 
     def close(self):
         if getattr(self, "h", None):

@@ -273,3 +273,24 @@ def test_batch_matches_single_runs(P):
     b.close()
     for x in ctxs:
         x.close()
+
+
+def test_autotune_restores_initial_state(P):
+    """The tile autotuner runs field launches on the initial state and clears it
+    again: a tuned run and an untuned run of the same problem agree."""
+    cfg = W.config_2d(nx=160, ny=40, nsteps=300, ppc=2, peak=3e14, slab_cells=10, waist=0.6e-6)
+    a = P.Context(cfg)
+    info = a.autotune(3)
+    assert 0 <= info["chosen"] < 5 and all(m > 0 for m in info["ms"][:5])
+    a.step(300)
+    b = P.Context(cfg)
+    b.step(300)
+    fa, fb = a.fields(), b.fields()
+    num = sum(np.sum((x - y) ** 2) for x, y in zip(fa[0] + fa[1], fb[0] + fb[1]))
+    den = sum(np.sum(y ** 2) for y in fb[0] + fb[1])
+    assert math.sqrt(num / den) < 1e-6
+    assert set(map(tuple, a.events().tolist())) == set(map(tuple, b.events().tolist()))
+    with pytest.raises(P.PicError):
+        a.autotune(1)          # only before the first step
+    a.close()
+    b.close()
