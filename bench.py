@@ -144,6 +144,8 @@ def main():
                                                              "stress2d", "stress3d"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="copy 256 MiB once before the run (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); multi-GPU runs are not "
@@ -172,6 +174,14 @@ def main():
         wl = dict(workload="3D3V mirror share, all neutrals pre-ionized (charged-loop stress)",
                   cells=[256, 128, 128], ppc=8, seed=2)
     cfg = dict(cfg, nsteps=max(cfg["nsteps"], args.steps))
+    if args.calib_copy:
+        import torch
+        a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     r = run_gpu(cfg, args.steps, args.warmup)
     value = r["particle_steps"] / r["wall"]
     timers = r["timers"]
