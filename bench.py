@@ -29,7 +29,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 
 # phases of the step (index into the library's timers)
-PHASES = {0: "push", 1: "fields", 2: "ionize"}
+PHASES = {0: "push", 1: "fields", 2: "ionize", 3: "sort"}
 
 
 def window_nodes(cfg):
@@ -89,6 +89,7 @@ def run_gpu(cfg, steps, warmup):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     timers = ctx.timers()
+    sort_state = ctx.sort_state()
     sc = ctx.scalars()
     ev = ctx.events()
     nneut = ctx.params().n_neutral
@@ -106,7 +107,7 @@ def run_gpu(cfg, steps, warmup):
     ps = neutral_steps + births
     wall = t1 - t0
     return dict(wall=wall, particle_steps=ps, neutral_steps=neutral_steps, charged_steps=births,
-                timers=timers, scalars=sc, nneut=nneut, tune=tune)
+                timers=timers, scalars=sc, nneut=nneut, tune=tune, sort_state=sort_state)
 
 
 def cpu_baseline(cfg, budget_s=20.0):
@@ -187,7 +188,7 @@ def main():
     timers = r["timers"]
     # dominant kernel by device time
     tot = {ph: timers[ph] for ph in PHASES if timers[8 + ph] > 0}
-    dom = max(tot, key=tot.get)
+    dom = max((ph for ph in tot if ph != 3), key=tot.get)
     n_launch = timers[8 + dom]
     avg_ms = timers[dom] / n_launch
     n_charged_avg = r["charged_steps"] / args.steps
@@ -213,8 +214,10 @@ def main():
         "roofline": {"bound": "hbm", "kernel": PHASES[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_launch": bytes_launch, "avg_launch_us": avg_ms * 1e3},
-        "phases_us_per_step": {PHASES[ph]: timers[ph] / max(timers[8 + ph], 1) * 1e3 for ph in tot},
+        "phases_us_per_step": {PHASES[ph]: timers[ph] / args.steps * 1e3 for ph in tot},
+        "phases_us_per_launch": {PHASES[ph]: timers[ph] / max(timers[8 + ph], 1) * 1e3 for ph in tot},
         "field_tile_autotune": r["tune"],
+        "tile_sort": r["sort_state"],
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_budget)

@@ -150,11 +150,15 @@ enum {
   PIC_DIAG_PARTICLES = 5, /* pic_particle records of live charged particles */
   PIC_DIAG_PARAMS = 6,    /* one pic_params */
   PIC_DIAG_AMP = 7,       /* float: windowed amplitude A at nodes [V/m] */
-  PIC_DIAG_TIMERS = 8     /* double[24]: [0..7] device ms per phase summed over the
+  PIC_DIAG_TIMERS = 8,    /* double[24]: [0..7] device ms per phase summed over the
                              timed launches, [8..15] launch counts (phases: 0 push,
                              1 field update with outflow faces and amplitude window,
                              2 ionization); [16..22] autotuner ms per field launch of
                              each tile shape, [23] the tile shape in use */
+  PIC_DIAG_SORT = 9       /* double[4]: charged slots held in tile order, tile
+                             chunks, drifter-steps (a particle that deposited outside
+                             its tile's window, counted per step) since the last
+                             sort, sorts performed */
 };
 
 /* PIC_DIAG_SCALARS layout (all double). */
@@ -249,6 +253,16 @@ pic_status pic_autotune(pic_ctx* c, int32_t reps);
  * context stream around every launch (no host synchronisation per step);
  * off by default; switching resets the accumulators. */
 pic_status pic_set_timing(pic_ctx* c, int32_t on);
+
+/* Tile sort of the charged particles (the resort of the particle loop): every
+ * `period` steps (default 8; 0 = never) the device checks whether births
+ * since the last sort exceed 1/32 of the slots in use, or particles that left
+ * their tile exceed 1/64 (at least 256 either way), and if so counting-sorts
+ * the charged particles by tile of the deposit (compacting dead slots).  The
+ * order of the slots returned by PIC_DIAG_PARTICLES changes with each sort;
+ * physics results do not (only the summation order of the current).  A batch
+ * checks every 8 batch steps. */
+pic_status pic_set_resort(pic_ctx* c, int32_t period);
 
 void pic_destroy(pic_ctx* c);
 const char* pic_status_str(pic_status s);

@@ -89,6 +89,40 @@ __host__ __device__ inline float table_lookup(const TabHdr* __restrict__ h, floa
   return -expm1f(-r);
 }
 
+// ------------------------------------------------------- particle tiles
+// The charged particles are kept sorted by tile of the deposit (counting sort,
+// redone when enough births or drifters have accumulated).  A particle that
+// starts a step in cell c deposits its current on nodes c - 2 .. c + 3 of each
+// present axis (Esirkepov, shape order <= 2, at most one cell per step), so
+// the deposit of a whole tile of T cells fits a window of T + 5 nodes held in
+// LDS.  Each tile is split into groups of 64 cells (x fastest: 3D one 8 x 8
+// plane, 2D four 16-cell rows, 1D 64 cells); inside a group the particles are
+// ordered level by level -- the first particle of every cell, in cell order,
+// then the second, ... -- so the lanes of a wave sit in distinct, neighbouring
+// cells (distinct LDS addresses for the deposit, few cache lines per gather).
+__host__ __device__ constexpr int ptile_ext(int D, int axis) {
+  return axis >= D ? 1 : (D == 1 ? 128 : (D == 2 ? 16 : 8));
+}
+__host__ __device__ constexpr int ptile_cells(int D) {
+  return ptile_ext(D, 0) * ptile_ext(D, 1) * ptile_ext(D, 2);
+}
+constexpr int PT_GROUP = 64;        // cells per group
+constexpr int PT_LO = 2;            // window starts PT_LO nodes below the tile
+constexpr int PT_PAD = 5;           // window = tile + PT_PAD nodes per present axis
+constexpr int SORT_CHUNK = 4096;    // particles per block-sized piece of a tile
+constexpr int SORT_GMAX = 16384;    // larger groups are copied without the level order
+constexpr int SORT_LMAX = 2048;     // (or with more than this many particles in one cell)
+// LDS deposit in 64-bit fixed point: a contribution v (|v| <= max |kq|) is
+// added as trunc(v * jscale) with jscale = 2^40 / 2^ceil(log2 max |kq|), so a
+// node's sum over one chunk stays below 2^52; the sum is exact and does not
+// depend on the order of the atomics.
+constexpr int JFIX_BITS = 40;
+
+// sort control words (device): [0] sorted slots, [1] chunks, [2] drifters
+// deposited outside their tile's window since the sort (per step), [3] sort
+// decision, [4] sorts performed
+constexpr int SC_NSORTED = 0, SC_NCHUNKS = 1, SC_NDRIFT = 2, SC_GO = 3, SC_NSORTS = 4, SC_WORDS = 8;
+
 // ----------------------------------------------------- instance parameters
 struct Inst {
   // grid
@@ -125,6 +159,16 @@ struct Inst {
   uint8_t* pkind;
   int* pcount;                  // used slots
   int capacity;
+  // tile sort: [0, sctl[SC_NSORTED]) holds the groups in order (tile-major);
+  // births since the sort follow up to *pcount
+  int ntile[3], ntiles;
+  int *gcnt, *gn, *gstart, *gfill;  // per group: count (zero between sorts), count, first slot, fill
+  int4* chunks;                 // {tile, first slot, end slot, 0}
+  float jscale, jscale_inv;     // LDS fixed-point scale of the deposit and its inverse
+  int* sctl;                    // SC_* words
+  uint32_t* scell;              // scatter targets (same layout as the particle arrays)
+  float *so0, *so1, *so2, *su0, *su1, *su2;
+  uint8_t* skind;
   // particle kinds: 2m electron, 2m+1 positive carrier
   float kh[MAXKIND];            // q dt / (2 m c)
   float kq[MAXKIND][3];         // qhat dx_d (present axes) or qhat c dt (absent)

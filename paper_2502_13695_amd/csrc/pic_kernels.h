@@ -19,6 +19,9 @@ constexpr int TPB = 256;
 
 // phase launchers (enqueue on `s`); D = 1..3, order = 1..2
 void launch_push(const Group& g, int D, int order, hipStream_t s);
+// tile sort of the charged particles (gp: the push grid; gscan: one block per
+// instance); each instance decides on the device whether a sort is due
+void launch_sort(const Group& gp, const Group& gscan, int D, hipStream_t s);
 void launch_fields(const Group& g, int D, int variant, hipStream_t s);
 void launch_ionize(const Group& g, int D, int order, hipStream_t s);
 void launch_advance(const Inst* insts, int n, hipStream_t s);   // batch: step counters + 1

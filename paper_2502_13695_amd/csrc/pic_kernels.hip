@@ -37,6 +37,29 @@ __device__ __forceinline__ int wrapi(int j, int n, int per) {
   return j < 0 ? j + n : (j >= n ? j - n : j);
 }
 
+// Global-memory views of device pointers: loads, stores and atomics through
+// them compile to global_* instructions (scalar base + 32-bit offset) instead
+// of flat ones, which would also wait on LDS traffic.
+template <class T>
+using gmem = __attribute__((address_space(1))) T;
+template <class T>
+__device__ __forceinline__ gmem<T>* gp(T* p) {
+  return (gmem<T>*)p;
+}
+template <class T>
+__device__ __forceinline__ const gmem<T>* gp(const T* p) {
+  return (const gmem<T>*)p;
+}
+// A pointer every lane holds the same value of, made visibly wave-uniform (kept
+// in scalar registers: loads through it use a scalar base + 32-bit offset).
+template <class T>
+__device__ __forceinline__ T* uniform(T* p) {
+  const unsigned long long v = (unsigned long long)p;
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return (T*)(((unsigned long long)hi << 32) | lo);
+}
+
 // shape weights on the integer grid for a particle at cell c + offset t
 // (t in [0,1)); half = 1 for a half-integer staggered component.
 // Returns the first grid index; weights w[0..ORDER].
@@ -97,229 +120,630 @@ __device__ __forceinline__ void make_axis(Axis<ORDER>& a, int c, float t, int n,
 }
 
 template <int D, int ORDER>
-__device__ __forceinline__ float gather(const float* __restrict__ F, const Axis<ORDER>& X,
+__device__ __forceinline__ float gather(const float* __restrict__ Fp, const Axis<ORDER>& X,
                                         const Axis<ORDER>& Y, const Axis<ORDER>& Z, int hx, int hy,
                                         int hz) {
   constexpr int SY = D >= 2 ? ORDER + 1 : 1;
   constexpr int SZ = D >= 3 ? ORDER + 1 : 1;
+  constexpr int SX = ORDER + 1;
+  const gmem<float>* __restrict__ F = gp(Fp);
+  // all loads first (independent, in flight together), then the weighted sum;
+  // x is never periodic, so the x nodes are consecutive
+  const int ox = hx ? X.oh[0] : X.on[0];
+  float v[SZ][SY][SX];
+#pragma unroll
+  for (int c = 0; c < SZ; ++c) {
+    const int oz = D >= 3 ? (hz ? Z.oh[c] : Z.on[c]) : 0;
+#pragma unroll
+    for (int b = 0; b < SY; ++b) {
+      const int oy = D >= 2 ? (hy ? Y.oh[b] : Y.on[b]) : 0;
+      const gmem<float>* __restrict__ r = F + (ox + oy + oz);
+#pragma unroll
+      for (int a = 0; a < SX; ++a) v[c][b][a] = r[a];
+    }
+  }
   float acc = 0.0f;
 #pragma unroll
   for (int c = 0; c < SZ; ++c) {
     const float wz = D >= 3 ? (hz ? Z.wh[c] : Z.wn[c]) : 1.0f;
-    const int oz = D >= 3 ? (hz ? Z.oh[c] : Z.on[c]) : 0;
 #pragma unroll
     for (int b = 0; b < SY; ++b) {
       const float wy = D >= 2 ? (hy ? Y.wh[b] : Y.wn[b]) : 1.0f;
-      const int oy = D >= 2 ? (hy ? Y.oh[b] : Y.on[b]) : 0;
       float row = 0.0f;
 #pragma unroll
-      for (int a = 0; a <= ORDER; ++a) {
-        const float wx = hx ? X.wh[a] : X.wn[a];
-        const int ox = hx ? X.oh[a] : X.on[a];
-        row += wx * F[ox + oy + oz];
-      }
+      for (int a = 0; a < SX; ++a) row += (hx ? X.wh[a] : X.wn[a]) * v[c][b][a];
       acc += wz * wy * row;
     }
   }
   return acc;
 }
 
-// Esirkepov local arrays along one axis: L = 5 (order 2) or 4 (order 1)
-// nodes starting at `org`; S0 and DS = S1 - S0; [lo, hi) = nonzero range.
+// Esirkepov arrays along one axis, compacted to the W = ORDER + 2 nodes a
+// move of at most one cell can touch, from `org` = the lower of the start and
+// end shape bases: S0 = start weights, DS = end - start weights.  A move that
+// keeps its shape base leaves node W - 1 zero.
 template <int ORDER>
 struct Esk {
-  static constexpr int L = ORDER == 2 ? 5 : 4;
-  float S0[L], DS[L];
-  int org, lo, hi;
+  static constexpr int W = ORDER + 2;
+  float S0[W], DS[W];
+  int org;
+  int moved;   // the shape base changed along this axis
 };
+
+template <int ORDER>
+__device__ __forceinline__ float esk_pick(const float* w, int o, int q) {
+  // weight at compact node q of a shape whose first weight sits at node o
+  if (q == 0) return o ? 0.0f : w[0];
+  if (q == ORDER + 1) return o ? w[ORDER] : 0.0f;
+  return o ? w[q - 1] : w[q];
+}
 
 template <int ORDER>
 __device__ __forceinline__ void esk_axis(Esk<ORDER>& e, int c0, float t0, int c1, float t1) {
   float w0[ORDER + 1], w1[ORDER + 1];
   const int b0 = shape<ORDER>(c0, t0, 0, w0);
   const int b1 = shape<ORDER>(c1, t1, 0, w1);
-  constexpr int L = Esk<ORDER>::L;
-  e.org = b0 - 1;   // S0 occupies local 1 .. ORDER + 1
   const int sh = b1 - b0;   // -1, 0, 1
+  e.org = sh < 0 ? b1 : b0;
+  e.moved = sh != 0;
+  const int o0 = sh < 0 ? 1 : 0, o1 = sh > 0 ? 1 : 0;
 #pragma unroll
-  for (int q = 0; q < L; ++q) e.S0[q] = 0.0f;
-#pragma unroll
-  for (int q = 0; q <= ORDER; ++q) e.S0[q + 1] = w0[q];
-#pragma unroll
-  for (int q = 0; q < L; ++q) {
-    const int r = q - 1 - sh;
-    const float s1 = (r >= 0 && r <= ORDER) ? w1[r] : 0.0f;
-    e.DS[q] = s1 - e.S0[q];
+  for (int q = 0; q < Esk<ORDER>::W; ++q) {
+    const float a0 = esk_pick<ORDER>(w0, o0, q);
+    e.S0[q] = a0;
+    e.DS[q] = esk_pick<ORDER>(w1, o1, q) - a0;
   }
-  e.lo = sh < 0 ? 0 : 1;
-  e.hi = sh > 0 ? ORDER + 3 : ORDER + 2;
 }
 
+// Nodes visited along an axis: W if any lane of the wave changed its shape
+// base along it, else W - 1.  Wave-uniform, so the unrolled deposit loops
+// below branch on scalars; a lane that did not move adds zeros (or the
+// rounding residue of its vanishing cumulative sum) on the extra node.
+template <int ORDER>
+__device__ __forceinline__ int wave_extent(int moved) {
+  return __any(moved) ? ORDER + 2 : ORDER + 1;
+}
+
+// Current sinks.  x/y/z map an (unwrapped) node index to an offset, add()
+// accumulates component `comp`.
+struct GSink {   // the padded HBM arrays, FP32 atomics, periodic wrap
+  float* J0;
+  float* J1;
+  float* J2;
+  int ny, nz, per_y, per_z, sy, sz, Gy, Gz;
+  __device__ __forceinline__ int x(int i) const { return i + G; }
+  __device__ __forceinline__ int y(int j) const { return sy * (wrapi(j, ny, per_y) + Gy); }
+  __device__ __forceinline__ int z(int k) const { return sz * (wrapi(k, nz, per_z) + Gz); }
+  __device__ __forceinline__ void add(int comp, int o, float v) const {
+    gmem<float>* J = gp(comp == 0 ? J0 : comp == 1 ? J1 : J2);
+    __hip_atomic_fetch_add(J + (unsigned)o, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+};
+
+// round(v * scale) as a two's-complement 64-bit integer (|v * scale| < 2^51):
+// adding 1.5 * 2^52 in FP64 leaves the integer in the low mantissa bits, and
+// the constant's low word is zero, so removing it touches the high word only
+__device__ __forceinline__ unsigned long long fix64(float v, double scale) {
+  const double d = fma((double)v, scale, 6755399441055744.0);
+  return (unsigned long long)__double_as_longlong(d) - 0x4338000000000000ull;
+}
+
+template <int D>
+struct PWin {   // LDS deposit window of a particle tile
+  static constexpr int X = ptile_ext(D, 0) + PT_PAD;
+  static constexpr int Y = D >= 2 ? ptile_ext(D, 1) + PT_PAD : 1;
+  static constexpr int Z = D >= 3 ? ptile_ext(D, 2) + PT_PAD : 1;
+  static constexpr int N = X * Y * Z;
+};
+
+template <int D>
+struct LSink {   // the block's LDS window, origin (x0, y0, z0) in unwrapped nodes;
+                 // 64-bit fixed point (integer LDS atomics run at full rate)
+  unsigned long long* s;
+  int x0, y0, z0;
+  double scale;
+  __device__ __forceinline__ int x(int i) const { return i - x0; }
+  __device__ __forceinline__ int y(int j) const { return (j - y0) * PWin<D>::X; }
+  __device__ __forceinline__ int z(int k) const { return (k - z0) * (PWin<D>::X * PWin<D>::Y); }
+  __device__ __forceinline__ void add(int comp, int o, float v) const {
+    atomicAdd(s + comp * PWin<D>::N + o, fix64(v, scale));
+  }
+};
+
+// Esirkepov deposit of dt J^{n+1/2} / eps0 for one particle.  Components
+// along present axes accumulate -q dx (dW/dt) along their axis; components
+// along absent axes take q v times the path-averaged shape.
+template <int D, int ORDER, class S>
+__device__ __forceinline__ void deposit(const S& s, const Esk<ORDER>& ex, const Esk<ORDER>& ey,
+                                        const Esk<ORDER>& ez, float qx, float qy, float qz, float vy,
+                                        float vz) {
+  constexpr int W = ORDER + 2;
+  constexpr int WY = D >= 2 ? W : 1;
+  constexpr int WZ = D >= 3 ? W : 1;
+  const int nx = wave_extent<ORDER>(ex.moved);
+  const int ny = D >= 2 ? wave_extent<ORDER>(ey.moved) : 1;
+  const int nz = D >= 3 ? wave_extent<ORDER>(ez.moved) : 1;
+  constexpr float third = 1.0f / 3.0f;
+  // Jx: cumulative sum of Wx along x
+#pragma unroll
+  for (int c = 0; c < WZ; ++c) {
+    if (c >= nz) break;
+    const float s0z = D >= 3 ? ez.S0[c] : 1.0f, dsz = D >= 3 ? ez.DS[c] : 0.0f;
+    const int oz = D >= 3 ? s.z(ez.org + c) : 0;
+#pragma unroll
+    for (int b = 0; b < WY; ++b) {
+      if (b >= ny) break;
+      const float s0y = D >= 2 ? ey.S0[b] : 1.0f, dsy = D >= 2 ? ey.DS[b] : 0.0f;
+      const int oy = D >= 2 ? s.y(ey.org + b) : 0;
+      const float wb = s0y * s0z + 0.5f * dsy * s0z + 0.5f * s0y * dsz + third * dsy * dsz;
+      float acc = 0.0f;
+#pragma unroll
+      for (int a = 0; a < W - 1; ++a) {
+        if (a >= nx - 1) break;
+        acc += ex.DS[a] * wb;
+        s.add(0, s.x(ex.org + a) + oy + oz, -qx * acc);
+      }
+    }
+  }
+  // Jy
+#pragma unroll
+  for (int c = 0; c < WZ; ++c) {
+    if (c >= nz) break;
+    const float s0z = D >= 3 ? ez.S0[c] : 1.0f, dsz = D >= 3 ? ez.DS[c] : 0.0f;
+    const int oz = D >= 3 ? s.z(ez.org + c) : 0;
+#pragma unroll
+    for (int a = 0; a < W; ++a) {
+      if (a >= nx) break;
+      const float s0x = ex.S0[a], dsx = ex.DS[a];
+      const float wb = s0x * s0z + 0.5f * dsx * s0z + 0.5f * s0x * dsz + third * dsx * dsz;
+      const int ox = s.x(ex.org + a);
+      if (D >= 2) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int b = 0; b < W - 1; ++b) {
+          if (b >= ny - 1) break;
+          acc += ey.DS[b] * wb;
+          s.add(1, ox + s.y(ey.org + b) + oz, -qy * acc);
+        }
+      } else {
+        s.add(1, ox, qy * vy * wb);
+      }
+    }
+  }
+  // Jz
+#pragma unroll
+  for (int b = 0; b < WY; ++b) {
+    if (b >= ny) break;
+    const float s0y = D >= 2 ? ey.S0[b] : 1.0f, dsy = D >= 2 ? ey.DS[b] : 0.0f;
+    const int oy = D >= 2 ? s.y(ey.org + b) : 0;
+#pragma unroll
+    for (int a = 0; a < W; ++a) {
+      if (a >= nx) break;
+      const float s0x = ex.S0[a], dsx = ex.DS[a];
+      const float wb = s0x * s0y + 0.5f * dsx * s0y + 0.5f * s0x * dsy + third * dsx * dsy;
+      const int ox = s.x(ex.org + a);
+      if (D >= 3) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int c = 0; c < W - 1; ++c) {
+          if (c >= nz - 1) break;
+          acc += ez.DS[c] * wb;
+          s.add(2, ox + oy + s.z(ez.org + c), -qz * acc);
+        }
+      } else {
+        s.add(2, ox + oy, qz * vz * wb);
+      }
+    }
+  }
+}
+
+// Field sets read by the push of one step.
+struct PushFields {
+  const float* __restrict__ E0;
+  const float* __restrict__ E1;
+  const float* __restrict__ E2;
+  const float* __restrict__ B0;
+  const float* __restrict__ B1;
+  const float* __restrict__ B2;
+};
+
+// One charged particle: gather E^n, b^n, relativistic Boris, move, deposit,
+// boundary.  TILED: the block holds the LDS window of tile origin
+// (tx0, ty0, tz0); a particle that started the step inside that tile
+// deposits there, any other one in HBM (and is counted as a drifter).
+template <int D, int ORDER, bool TILED>
+__device__ __forceinline__ void push_one(const Inst& I, const PushFields& f, const GSink& gs,
+                                         const LSink<D>& ls, int tx0, int ty0, int tz0, int p,
+                                         bool valid) {
+  const unsigned q = (unsigned)p;
+  const uint8_t kind = valid ? gp(I.pkind)[q] : DEAD;
+  if (kind == DEAD) return;
+  int ci, cj, ck;
+  unpack_cell(D, gp(I.pcell)[q], ci, cj, ck);
+  const float t0 = gp(I.po0)[q];
+  const float t1 = D >= 2 ? gp(I.po1)[q] : 0.0f;
+  const float t2 = D >= 3 ? gp(I.po2)[q] : 0.0f;
+  float ux = gp(I.pu0)[q], uy = gp(I.pu1)[q], uz = gp(I.pu2)[q];
+  // ---- gather E^n, b^n
+  Axis<ORDER> X, Y, Z;
+  make_axis<ORDER>(X, ci, t0, I.nx, 0, G, 1);
+  if (D >= 2) make_axis<ORDER>(Y, cj, t1, I.ny, I.per_y, I.Gy, I.sy);
+  if (D >= 3) make_axis<ORDER>(Z, ck, t2, I.nz, I.per_z, I.Gz, I.sz);
+  const float ex = gather<D, ORDER>(f.E0, X, Y, Z, 1, 0, 0);
+  const float ey = gather<D, ORDER>(f.E1, X, Y, Z, 0, 1, 0);
+  const float ez = gather<D, ORDER>(f.E2, X, Y, Z, 0, 0, 1);
+  const float bx = gather<D, ORDER>(f.B0, X, Y, Z, 0, 1, 1);
+  const float by = gather<D, ORDER>(f.B1, X, Y, Z, 1, 0, 1);
+  const float bz = gather<D, ORDER>(f.B2, X, Y, Z, 1, 1, 0);
+  // ---- relativistic Boris (u = gamma v / c, b = c B, h = q dt / 2 m c)
+  const float h = I.kh[kind];
+  const float umx = ux + h * ex, umy = uy + h * ey, umz = uz + h * ez;
+  const float gm = sqrtf(1.0f + umx * umx + umy * umy + umz * umz);
+  const float hg = h / gm;
+  const float tx = hg * bx, ty = hg * by, tz = hg * bz;
+  const float sf = 2.0f / (1.0f + tx * tx + ty * ty + tz * tz);
+  const float vx = umx + (umy * tz - umz * ty);
+  const float vy = umy + (umz * tx - umx * tz);
+  const float vz = umz + (umx * ty - umy * tx);
+  ux = umx + sf * (vy * tz - vz * ty) + h * ex;
+  uy = umy + sf * (vz * tx - vx * tz) + h * ey;
+  uz = umz + sf * (vx * ty - vy * tx) + h * ez;
+  const float ig = 1.0f / sqrtf(1.0f + ux * ux + uy * uy + uz * uz);
+  // ---- move: integer cell + FP32 offset, at most one cell per step
+  int ni = ci, nj = cj, nk = ck;
+  float n0 = t0, n1 = t1, n2 = t2;
+  auto move = [&](float& t, int& c, float disp) {
+    float xn = t + disp;
+    if (xn >= 1.0f) {
+      xn -= 1.0f;
+      c += 1;
+    } else if (xn < 0.0f) {
+      xn += 1.0f;
+      c -= 1;
+      if (xn >= 1.0f) { xn = 0.0f; c += 1; }
+    }
+    t = xn;
+  };
+  move(n0, ni, I.C[0] * ux * ig);
+  if (D >= 2) move(n1, nj, I.C[1] * uy * ig);
+  if (D >= 3) move(n2, nk, I.C[2] * uz * ig);
+  // ---- Esirkepov deposit of J^{n+1/2} (scaled: dt J / eps0, V/m)
+  Esk<ORDER> exk, eyk, ezk;
+  esk_axis<ORDER>(exk, ci, t0, ni, n0);
+  if (D >= 2) esk_axis<ORDER>(eyk, cj, t1, nj, n1);
+  if (D >= 3) esk_axis<ORDER>(ezk, ck, t2, nk, n2);
+  const float qx = I.kq[kind][0], qy = I.kq[kind][1], qz = I.kq[kind][2];
+  const float wy = uy * ig, wz = uz * ig;
+  if (TILED) {
+    bool in = ci >= tx0 && ci < tx0 + ptile_ext(D, 0);
+    if (D >= 2) in = in && cj >= ty0 && cj < ty0 + ptile_ext(D, 1);
+    if (D >= 3) in = in && ck >= tz0 && ck < tz0 + ptile_ext(D, 2);
+    if (in) {
+      deposit<D, ORDER>(ls, exk, eyk, ezk, qx, qy, qz, wy, wz);
+    } else {
+      deposit<D, ORDER>(gs, exk, eyk, ezk, qx, qy, qz, wy, wz);
+      const unsigned long long m = __ballot(1);
+      if ((threadIdx.x & 63) == __ffsll((long long)m) - 1) atomicAdd(I.sctl + SC_NDRIFT, __popcll(m));
+    }
+  } else {
+    deposit<D, ORDER>(gs, exk, eyk, ezk, qx, qy, qz, wy, wz);
+  }
+  // ---- boundaries: outflow removes, periodic wraps
+  int dead = 0;
+  if (ni < 0 || ni >= I.nx) dead = 1;
+  if (D >= 2) {
+    if (I.per_y) nj = wrapi(nj, I.ny, 1);
+    else if (nj < 0 || nj >= I.ny) dead = 1;
+  }
+  if (D >= 3) {
+    if (I.per_z) nk = wrapi(nk, I.nz, 1);
+    else if (nk < 0 || nk >= I.nz) dead = 1;
+  }
+  if (dead) {
+    gp(I.pkind)[q] = DEAD;
+    return;
+  }
+  gp(I.pcell)[q] = pack_cell(D, ni, nj, nk);
+  gp(I.po0)[q] = n0;
+  if (D >= 2) gp(I.po1)[q] = n1;
+  if (D >= 3) gp(I.po2)[q] = n2;
+  gp(I.pu0)[q] = ux;
+  gp(I.pu1)[q] = uy;
+  gp(I.pu2)[q] = uz;
+}
+
+// Charged-particle phase.  Work units of a block (persistent grid-stride):
+// first the chunks of the sorted tiles -- the block clears its LDS window,
+// pushes the chunk's particles depositing into LDS, then adds the window's
+// nonzero nodes to HBM with one atomic each -- then the unsorted tail
+// (births since the sort) with HBM atomics.
 template <int D, int ORDER>
 __global__ __launch_bounds__(TPB) void k_push(Group g) {
+  __shared__ unsigned long long sJ[3 * PWin<D>::N];
   const int ii = find_inst(g);
   const Inst& I = g.insts[ii];
-  const int nthr = (g.off[ii + 1] - g.off[ii]) * TPB;
-  const int tid = (blockIdx.x - g.off[ii]) * TPB + threadIdx.x;
+  const int nb = g.off[ii + 1] - g.off[ii];
+  const int b0 = blockIdx.x - g.off[ii];
   int count = *I.pcount;
   count = count < I.capacity ? count : I.capacity;
   const int par = (g.step >= 0 ? g.step : *I.step) & 1;
-  const float* __restrict__ FE0 = I.F[par][0];
-  const float* __restrict__ FE1 = I.F[par][1];
-  const float* __restrict__ FE2 = I.F[par][2];
-  const float* __restrict__ FB0 = I.F[par][3];
-  const float* __restrict__ FB1 = I.F[par][4];
-  const float* __restrict__ FB2 = I.F[par][5];
-  float* const J0 = I.Jb[par][0];
-  float* const J1 = I.Jb[par][1];
-  float* const J2 = I.Jb[par][2];
-  for (int p = tid; p < count; p += nthr) {
-    const uint8_t kind = I.pkind[p];
-    if (kind == DEAD) continue;
-    int ci, cj, ck;
-    unpack_cell(D, I.pcell[p], ci, cj, ck);
-    const float t0 = I.po0[p];
-    const float t1 = D >= 2 ? I.po1[p] : 0.0f;
-    const float t2 = D >= 3 ? I.po2[p] : 0.0f;
-    float ux = I.pu0[p], uy = I.pu1[p], uz = I.pu2[p];
-    // ---- gather E^n, b^n
-    Axis<ORDER> X, Y, Z;
-    make_axis<ORDER>(X, ci, t0, I.nx, 0, G, 1);
-    if (D >= 2) make_axis<ORDER>(Y, cj, t1, I.ny, I.per_y, I.Gy, I.sy);
-    if (D >= 3) make_axis<ORDER>(Z, ck, t2, I.nz, I.per_z, I.Gz, I.sz);
-    const float ex = gather<D, ORDER>(FE0, X, Y, Z, 1, 0, 0);
-    const float ey = gather<D, ORDER>(FE1, X, Y, Z, 0, 1, 0);
-    const float ez = gather<D, ORDER>(FE2, X, Y, Z, 0, 0, 1);
-    const float bx = gather<D, ORDER>(FB0, X, Y, Z, 0, 1, 1);
-    const float by = gather<D, ORDER>(FB1, X, Y, Z, 1, 0, 1);
-    const float bz = gather<D, ORDER>(FB2, X, Y, Z, 1, 1, 0);
-    // ---- relativistic Boris (u = gamma v / c, b = c B, h = q dt / 2 m c)
-    const float h = I.kh[kind];
-    const float umx = ux + h * ex, umy = uy + h * ey, umz = uz + h * ez;
-    const float gm = sqrtf(1.0f + umx * umx + umy * umy + umz * umz);
-    const float hg = h / gm;
-    const float tx = hg * bx, ty = hg * by, tz = hg * bz;
-    const float sf = 2.0f / (1.0f + tx * tx + ty * ty + tz * tz);
-    const float vx = umx + (umy * tz - umz * ty);
-    const float vy = umy + (umz * tx - umx * tz);
-    const float vz = umz + (umx * ty - umy * tx);
-    ux = umx + sf * (vy * tz - vz * ty) + h * ex;
-    uy = umy + sf * (vz * tx - vx * tz) + h * ey;
-    uz = umz + sf * (vx * ty - vy * tx) + h * ez;
-    const float ig = 1.0f / sqrtf(1.0f + ux * ux + uy * uy + uz * uz);
-    // ---- move: integer cell + FP32 offset, at most one cell per step
-    int dead = 0;
-    int ni = ci, nj = cj, nk = ck;
-    float n0 = t0, n1 = t1, n2 = t2;
-    auto move = [&](float& t, int& c, float disp) {
-      float xn = t + disp;
-      if (xn >= 1.0f) {
-        xn -= 1.0f;
-        c += 1;
-      } else if (xn < 0.0f) {
-        xn += 1.0f;
-        c -= 1;
-        if (xn >= 1.0f) { xn = 0.0f; c += 1; }
-      }
-      t = xn;
-    };
-    move(n0, ni, I.C[0] * ux * ig);
-    if (D >= 2) move(n1, nj, I.C[1] * uy * ig);
-    if (D >= 3) move(n2, nk, I.C[2] * uz * ig);
-    // ---- Esirkepov deposit of J^{n+1/2} (scaled: dt J / eps0, V/m)
-    Esk<ORDER> ex_, ey_, ez_;
-    esk_axis<ORDER>(ex_, ci, t0, ni, n0);
-    if (D >= 2) esk_axis<ORDER>(ey_, cj, t1, nj, n1);
-    if (D >= 3) esk_axis<ORDER>(ez_, ck, t2, nk, n2);
-    constexpr int L = Esk<ORDER>::L;
-    constexpr int LY = D >= 2 ? L : 1;
-    constexpr int LZ = D >= 3 ? L : 1;
-    const float qx = I.kq[kind][0], qy = I.kq[kind][1], qz = I.kq[kind][2];
-    const int ylo = D >= 2 ? ey_.lo : 0, yhi = D >= 2 ? ey_.hi : 1;
-    const int zlo = D >= 3 ? ez_.lo : 0, zhi = D >= 3 ? ez_.hi : 1;
-    for (int c = zlo; c < zhi; ++c) {
-      const float s0z = D >= 3 ? ez_.S0[c] : 1.0f, dsz = D >= 3 ? ez_.DS[c] : 0.0f;
-      const int oz = D >= 3 ? I.sz * (wrapi(ez_.org + c, I.nz, I.per_z) + I.Gz) : 0;
-      for (int b = ylo; b < yhi; ++b) {
-        const float s0y = D >= 2 ? ey_.S0[b] : 1.0f, dsy = D >= 2 ? ey_.DS[b] : 0.0f;
-        const int oy = D >= 2 ? I.sy * (wrapi(ey_.org + b, I.ny, I.per_y) + I.Gy) : 0;
-        // Jx: cumulative sum of Wx along x
-        const float wbx = s0y * s0z + 0.5f * dsy * s0z + 0.5f * s0y * dsz + (1.0f / 3.0f) * dsy * dsz;
-        float acc = 0.0f;
-        for (int a = ex_.lo; a < ex_.hi - 1; ++a) {
-          acc += ex_.DS[a] * wbx;
-          const int ox = ex_.org + a + G;
-          unsafeAtomicAdd(J0 + ox + oy + oz, -qx * acc);
-        }
-      }
+  const PushFields f{uniform(I.F[par][0]), uniform(I.F[par][1]), uniform(I.F[par][2]),
+                     uniform(I.F[par][3]), uniform(I.F[par][4]), uniform(I.F[par][5])};
+  const GSink gs{I.Jb[par][0], I.Jb[par][1], I.Jb[par][2], I.ny, I.nz, I.per_y, I.per_z,
+                 I.sy, I.sz, I.Gy, I.Gz};
+  int nsorted = I.sctl[SC_NSORTED];
+  nsorted = nsorted < count ? nsorted : count;
+  const int nchunks = I.sctl[SC_NCHUNKS];
+  const int64_t ncell = (int64_t)I.Px * I.Py * I.Pz;
+  for (int u = b0; u < nchunks; u += nb) {
+    const int4 ch = I.chunks[u];
+    const int t = ch.x;
+    const int tx0 = (t % I.ntile[0]) * ptile_ext(D, 0);
+    const int ty0 = D >= 2 ? ((t / I.ntile[0]) % I.ntile[1]) * ptile_ext(D, 1) : 0;
+    const int tz0 = D >= 3 ? (t / (I.ntile[0] * I.ntile[1])) * ptile_ext(D, 2) : 0;
+    const LSink<D> ls{sJ, tx0 - PT_LO, D >= 2 ? ty0 - PT_LO : 0, D >= 3 ? tz0 - PT_LO : 0,
+                      (double)I.jscale};
+    for (int e = threadIdx.x; e < 3 * PWin<D>::N; e += TPB) sJ[e] = 0ull;
+    __syncthreads();
+    const int end = ch.z < count ? ch.z : count;
+    for (int p0 = ch.y; p0 < end; p0 += TPB) {
+      const int p = p0 + threadIdx.x;
+      push_one<D, ORDER, true>(I, f, gs, ls, tx0, ty0, tz0, p, p < end);
     }
-    // Jy
-    {
-      for (int c = zlo; c < zhi; ++c) {
-        const float s0z = D >= 3 ? ez_.S0[c] : 1.0f, dsz = D >= 3 ? ez_.DS[c] : 0.0f;
-        const int oz = D >= 3 ? I.sz * (wrapi(ez_.org + c, I.nz, I.per_z) + I.Gz) : 0;
-        for (int a = ex_.lo; a < ex_.hi; ++a) {
-          const float s0x = ex_.S0[a], dsx = ex_.DS[a];
-          const float wby = s0x * s0z + 0.5f * dsx * s0z + 0.5f * s0x * dsz + (1.0f / 3.0f) * dsx * dsz;
-          const int ox = ex_.org + a + G;
-          if (D >= 2) {
-            float acc = 0.0f;
-            for (int b = ey_.lo; b < ey_.hi - 1; ++b) {
-              acc += ey_.DS[b] * wby;
-              const int oy = I.sy * (wrapi(ey_.org + b, I.ny, I.per_y) + I.Gy);
-              unsafeAtomicAdd(J1 + ox + oy + oz, -qy * acc);
-            }
-          } else {
-            unsafeAtomicAdd(J1 + ox, qy * uy * ig * wby);
-          }
-        }
-      }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 3 * PWin<D>::N; e += TPB) {
+      const long long q = (long long)sJ[e];
+      if (q == 0) continue;
+      const float v = (float)q * I.jscale_inv;
+      const int comp = e / PWin<D>::N;
+      const int r = e - comp * PWin<D>::N;
+      const int a = r % PWin<D>::X;
+      const int b = (r / PWin<D>::X) % PWin<D>::Y;
+      const int c = r / (PWin<D>::X * PWin<D>::Y);
+      const int o = gs.x(ls.x0 + a) + (D >= 2 ? gs.y(ls.y0 + b) : 0) + (D >= 3 ? gs.z(ls.z0 + c) : 0);
+      if (o >= 0 && o < ncell) gs.add(comp, o, v);
     }
-    // Jz
-    {
-      for (int b = ylo; b < yhi; ++b) {
-        const float s0y = D >= 2 ? ey_.S0[b] : 1.0f, dsy = D >= 2 ? ey_.DS[b] : 0.0f;
-        const int oy = D >= 2 ? I.sy * (wrapi(ey_.org + b, I.ny, I.per_y) + I.Gy) : 0;
-        for (int a = ex_.lo; a < ex_.hi; ++a) {
-          const float s0x = ex_.S0[a], dsx = ex_.DS[a];
-          const float wbz = s0x * s0y + 0.5f * dsx * s0y + 0.5f * s0x * dsy + (1.0f / 3.0f) * dsx * dsy;
-          const int ox = ex_.org + a + G;
-          if (D >= 3) {
-            float acc = 0.0f;
-            for (int c = ez_.lo; c < ez_.hi - 1; ++c) {
-              acc += ez_.DS[c] * wbz;
-              const int oz = I.sz * (wrapi(ez_.org + c, I.nz, I.per_z) + I.Gz);
-              unsafeAtomicAdd(J2 + ox + oy + oz, -qz * acc);
-            }
-          } else {
-            unsafeAtomicAdd(J2 + ox + oy, qz * uz * ig * wbz);
-          }
-        }
-      }
+    __syncthreads();
+  }
+  const LSink<D> none{sJ, 0, 0, 0, 0.0};
+  for (int p0 = nsorted + b0 * TPB; p0 < count; p0 += nb * TPB) {
+    const int p = p0 + threadIdx.x;
+    push_one<D, ORDER, false>(I, f, gs, none, 0, 0, 0, p, p < count);
+  }
+}
+
+// ------------------------------------------------------------ tile sort
+// Counting sort of the charged particles by group (64 cells of a tile):
+// count (wave-aggregated atomics), scan (one block per instance: group ranges
+// and the chunk list of every tile), scatter into the spare arrays (dead slots
+// dropped), then one block per group writes the group back in level order.
+// The first kernel decides, identically in every block, whether a sort is
+// due; the others follow its decision.
+template <int D>
+__device__ __forceinline__ void group_of(const Inst& I, uint32_t pc, int& g, int& c) {
+  int i, j, k;
+  unpack_cell(D, pc, i, j, k);
+  constexpr int TX = ptile_ext(D, 0), TY = ptile_ext(D, 1), TZ = ptile_ext(D, 2);
+  int t = i / TX;
+  if (D >= 2) t += I.ntile[0] * (j / TY);
+  if (D >= 3) t += I.ntile[0] * I.ntile[1] * (k / TZ);
+  const int lc = (i % TX) + TX * ((D >= 2 ? j % TY : 0) + TY * (D >= 3 ? k % TZ : 0));
+  constexpr int GPT = ptile_cells(D) / PT_GROUP;
+  g = (unsigned)t < (unsigned)I.ntiles ? t * GPT + lc / PT_GROUP : -1;   // -1 only for a corrupt cell
+  c = lc % PT_GROUP;
+}
+
+// Adds 1 to arr[t] for every lane with t >= 0, one atomic per distinct t of
+// the wave; returns the lane's rank (distinct per lane and t).
+__device__ __forceinline__ int wave_rank_add(int* arr, int t) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  unsigned long long pending = __ballot(t >= 0);
+  int rank = 0;
+  while (pending) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const int tl = __shfl(t, leader);
+    const unsigned long long m = __ballot(t == tl);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(arr + tl, __popcll(m));
+    base = __shfl(base, leader);
+    if (t == tl) rank = base + __popcll(m & below);
+    pending &= ~m;
+  }
+  return rank;
+}
+
+template <int D>
+__global__ __launch_bounds__(TPB) void k_sort_count(Group g) {
+  const int ii = find_inst(g);
+  const Inst& I = g.insts[ii];
+  const int nb = g.off[ii + 1] - g.off[ii];
+  const int b0 = blockIdx.x - g.off[ii];
+  int count = *I.pcount;
+  count = count < I.capacity ? count : I.capacity;
+  const int loose = count - I.sctl[SC_NSORTED];
+  const int drift = I.sctl[SC_NDRIFT];
+  const int lo = count >> 5, dr = count >> 6;
+  const int go = loose > (lo > 256 ? lo : 256) || drift > (dr > 256 ? dr : 256);
+  if (b0 == 0 && threadIdx.x == 0) I.sctl[SC_GO] = go;
+  if (!go) return;
+  const int lane = threadIdx.x & 63;
+  for (int p0 = b0 * TPB + (threadIdx.x - lane); p0 < count; p0 += nb * TPB) {
+    const int p = p0 + lane;
+    int gr = -1, c;
+    if (p < count && I.pkind[p] != DEAD) group_of<D>(I, I.pcell[p], gr, c);
+    (void)wave_rank_add(I.gcnt, gr);
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(TPB) void k_sort_scan(Group g) {
+  __shared__ long long sp[TPB], sc[TPB];
+  const int ii = find_inst(g);
+  const Inst& I = g.insts[ii];
+  if (!I.sctl[SC_GO]) return;
+  constexpr int GPT = ptile_cells(D) / PT_GROUP;
+  const int nt = I.ntiles;
+  const int per = (nt + TPB - 1) / TPB;
+  const int t0 = threadIdx.x * per;
+  const int t1 = t0 + per < nt ? t0 + per : nt;
+  long long np = 0, nc = 0;
+  for (int t = t0; t < t1; ++t) {
+    long long n = 0;
+    for (int q = 0; q < GPT; ++q) n += I.gcnt[t * GPT + q];
+    np += n;
+    nc += (n + SORT_CHUNK - 1) / SORT_CHUNK;
+  }
+  sp[threadIdx.x] = np;
+  sc[threadIdx.x] = nc;
+  __syncthreads();
+  for (int w = 1; w < TPB; w <<= 1) {   // inclusive scan
+    const long long a = threadIdx.x >= w ? sp[threadIdx.x - w] : 0;
+    const long long b = threadIdx.x >= w ? sc[threadIdx.x - w] : 0;
+    __syncthreads();
+    sp[threadIdx.x] += a;
+    sc[threadIdx.x] += b;
+    __syncthreads();
+  }
+  const long long total = sp[TPB - 1], tchunks = sc[TPB - 1];
+  long long pp = sp[threadIdx.x] - np, pc = sc[threadIdx.x] - nc;
+  for (int t = t0; t < t1; ++t) {
+    const long long ts = pp;
+    for (int q = 0; q < GPT; ++q) {
+      const int gi = t * GPT + q;
+      const int n = I.gcnt[gi];
+      I.gcnt[gi] = 0;
+      I.gn[gi] = n;
+      I.gstart[gi] = (int)pp;
+      I.gfill[gi] = 0;
+      pp += n;
     }
-    (void)LY;
-    (void)LZ;
-    // ---- boundaries: outflow removes, periodic wraps
-    if (ni < 0 || ni >= I.nx) dead = 1;
-    if (D >= 2) {
-      if (I.per_y) nj = wrapi(nj, I.ny, 1);
-      else if (nj < 0 || nj >= I.ny) dead = 1;
+    for (long long q = 0; ts + q * SORT_CHUNK < pp; ++q) {
+      const long long e = ts + (q + 1) * SORT_CHUNK;
+      I.chunks[pc++] = make_int4(t, (int)(ts + q * SORT_CHUNK), (int)(e < pp ? e : pp), 0);
     }
-    if (D >= 3) {
-      if (I.per_z) nk = wrapi(nk, I.nz, 1);
-      else if (nk < 0 || nk >= I.nz) dead = 1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    I.sctl[SC_NSORTED] = (int)total;   // <= the slots in use: dead ones are dropped
+    I.sctl[SC_NCHUNKS] = (int)tchunks;
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(TPB) void k_sort_scatter(Group g) {
+  const int ii = find_inst(g);
+  const Inst& I = g.insts[ii];
+  if (!I.sctl[SC_GO]) return;
+  const int nb = g.off[ii + 1] - g.off[ii];
+  const int b0 = blockIdx.x - g.off[ii];
+  int count = *I.pcount;
+  count = count < I.capacity ? count : I.capacity;
+  const int lane = threadIdx.x & 63;
+  for (int p0 = b0 * TPB + (threadIdx.x - lane); p0 < count; p0 += nb * TPB) {
+    const int p = p0 + lane;
+    int gr = -1, c;
+    uint32_t pc = 0;
+    uint8_t kd = DEAD;
+    if (p < count) {
+      kd = I.pkind[p];
+      pc = I.pcell[p];
+      if (kd != DEAD) group_of<D>(I, pc, gr, c);
     }
-    if (dead) {
-      I.pkind[p] = DEAD;
+    const int r = wave_rank_add(I.gfill, gr);
+    if (gr < 0) continue;
+    const int d = I.gstart[gr] + r;
+    I.scell[d] = pc;
+    I.skind[d] = kd;
+    I.so0[d] = I.po0[p];
+    if (D >= 2) I.so1[d] = I.po1[p];
+    if (D >= 3) I.so2[d] = I.po2[p];
+    I.su0[d] = I.pu0[p];
+    I.su1[d] = I.pu1[p];
+    I.su2[d] = I.pu2[p];
+  }
+}
+
+template <int D>
+__device__ __forceinline__ void sort_move(const Inst& I, int from, int to) {
+  I.pcell[to] = I.scell[from];
+  I.pkind[to] = I.skind[from];
+  I.po0[to] = I.so0[from];
+  if (D >= 2) I.po1[to] = I.so1[from];
+  if (D >= 3) I.po2[to] = I.so2[from];
+  I.pu0[to] = I.su0[from];
+  I.pu1[to] = I.su1[from];
+  I.pu2[to] = I.su2[from];
+}
+
+// One block per group (grid-stride): rank of every particle inside its cell
+// (LDS counters), the bit mask of the cells still holding a particle at each
+// level, and the level-order slot: first slot of the level + cells before it
+// in the level.
+template <int D>
+__global__ __launch_bounds__(TPB) void k_sort_group(Group g) {
+  __shared__ unsigned cnt[PT_GROUP];
+  __shared__ unsigned long long lmask[SORT_LMAX];
+  __shared__ unsigned lbase[SORT_LMAX];
+  __shared__ unsigned short rank[SORT_GMAX];
+  __shared__ unsigned smax;
+  const int ii = find_inst(g);
+  const Inst& I = g.insts[ii];
+  if (!I.sctl[SC_GO]) return;
+  const int nb = g.off[ii + 1] - g.off[ii];
+  const int b0 = blockIdx.x - g.off[ii];
+  const int ngr = I.ntiles * (ptile_cells(D) / PT_GROUP);
+  for (int gi = b0; gi < ngr; gi += nb) {
+    const int n = I.gn[gi];
+    if (n == 0) continue;
+    const int s0 = I.gstart[gi];
+    if (n > SORT_GMAX) {
+      for (int q = threadIdx.x; q < n; q += TPB) sort_move<D>(I, s0 + q, s0 + q);
       continue;
     }
-    I.pcell[p] = pack_cell(D, ni, nj, nk);
-    I.po0[p] = n0;
-    if (D >= 2) I.po1[p] = n1;
-    if (D >= 3) I.po2[p] = n2;
-    I.pu0[p] = ux;
-    I.pu1[p] = uy;
-    I.pu2[p] = uz;
+    if (threadIdx.x < PT_GROUP) cnt[threadIdx.x] = 0;
+    if (threadIdx.x == 0) smax = 0;
+    __syncthreads();
+    for (int q = threadIdx.x; q < n; q += TPB) {
+      int gr, c;
+      group_of<D>(I, I.scell[s0 + q], gr, c);
+      rank[q] = (unsigned short)atomicAdd(&cnt[c], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < PT_GROUP) atomicMax(&smax, cnt[threadIdx.x]);
+    __syncthreads();
+    const unsigned levels = smax;
+    if (levels > SORT_LMAX) {
+      for (int q = threadIdx.x; q < n; q += TPB) sort_move<D>(I, s0 + q, s0 + q);
+      __syncthreads();
+      continue;
+    }
+    if (threadIdx.x < 64) {   // wave 0: one lane per cell
+      const unsigned mine = cnt[threadIdx.x];
+      unsigned acc = 0;
+      for (unsigned l = 0; l < levels; ++l) {
+        const unsigned long long m = __ballot(mine > l);
+        if (threadIdx.x == 0) {
+          lmask[l] = m;
+          lbase[l] = acc;
+        }
+        acc += __popcll(m);
+      }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < n; q += TPB) {
+      int gr, c;
+      group_of<D>(I, I.scell[s0 + q], gr, c);
+      const unsigned l = rank[q];
+      const int pos = (int)lbase[l] + __popcll(lmask[l] & ((1ull << c) - 1ull));
+      sort_move<D>(I, s0 + q, s0 + pos);
+    }
+    __syncthreads();
+  }
+  if (b0 == 0 && threadIdx.x == 0) {
+    *I.pcount = I.sctl[SC_NSORTED];
+    I.sctl[SC_NDRIFT] = 0;
+    I.sctl[SC_NSORTS] += 1;
   }
 }
 
@@ -1004,6 +1428,12 @@ void launch_push(const Group& g, int D, int order, hipStream_t s) {
   } else {
     DISPATCH_D(D, hipLaunchKernelGGL((k_push<DD, 2>), dim3(g.blocks), dim3(TPB), 0, s, g));
   }
+}
+void launch_sort(const Group& gp, const Group& gscan, int D, hipStream_t s) {
+  DISPATCH_D(D, hipLaunchKernelGGL((k_sort_count<DD>), dim3(gp.blocks), dim3(TPB), 0, s, gp));
+  DISPATCH_D(D, hipLaunchKernelGGL((k_sort_scan<DD>), dim3(gscan.blocks), dim3(TPB), 0, s, gscan));
+  DISPATCH_D(D, hipLaunchKernelGGL((k_sort_scatter<DD>), dim3(gp.blocks), dim3(TPB), 0, s, gp));
+  DISPATCH_D(D, hipLaunchKernelGGL((k_sort_group<DD>), dim3(gp.blocks), dim3(TPB), 0, s, gp));
 }
 #define FIELDS_V(DD, V) hipLaunchKernelGGL((k_fields<DD, V>), dim3(g.blocks), dim3(TPB), 0, s, g)
 void launch_fields(const Group& g, int D, int variant, hipStream_t s) {

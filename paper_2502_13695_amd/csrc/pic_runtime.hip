@@ -36,6 +36,10 @@ struct Layout {
   size_t o_ring, o_suffix, o_prefix, o_A;
   size_t o_no[3], o_alive, o_death, o_mcell;
   size_t o_pcell, o_po[3], o_pu[3], o_pkind;
+  int ntile[3];
+  int64_t ntiles, ngroups, maxchunks;
+  size_t o_gcnt, o_gn, o_gstart, o_gfill, o_chunks;
+  size_t o_scell, o_so[3], o_su[3], o_skind;
   size_t o_tab[MAXMAT];
   size_t o_ctr;      // pcount, step, health, nevents[MAXMAT], diag accumulators
   size_t o_grid64;   // FP64 node grid for diagnostics
@@ -49,6 +53,7 @@ struct Ctr {
   int step;
   unsigned health;
   unsigned done;
+  int sctl[SC_WORDS];
   unsigned long long nevents[MAXMAT];
   double acc[64];
 };
@@ -77,8 +82,18 @@ pic_status plan(const pic_config* cfg, const Canon& c, const std::vector<TableHo
   L->wsz = (int64_t)(L->wx1 - L->wx0) * L->Py * L->Pz;
   int64_t cap = cfg->particle_capacity > 0 ? cfg->particle_capacity : 2 * L->nneut + 4096;
   if (cfg->preionize_eV > 0) cap = std::max<int64_t>(cap, 2 * L->nneut);
-  if (cap > INT_MAX - 16 || L->nneut > ((int64_t)1 << 40) || c.ppc > 65535) return PIC_E_INVAL;
+  // particle tiles and their 64-cell groups
+  L->ntiles = 1;
+  for (int d = 0; d < 3; ++d) {
+    const int64_t e = ptile_ext(D, d);
+    L->ntile[d] = d < D ? (int)((c.n[d] + e - 1) / e) : 1;
+    L->ntiles *= L->ntile[d];
+  }
+  L->ngroups = L->ntiles * (ptile_cells(D) / PT_GROUP);
+  if (cap > INT_MAX / 2 || L->ngroups > (1 << 28) || L->nneut > ((int64_t)1 << 40) || c.ppc > 65535)
+    return PIC_E_INVAL;
   L->capacity = cap;
+  L->maxchunks = L->ntiles + cap / SORT_CHUNK + 1;
   // source samples cover the planned steps and the whole pulse (Gaussian: to
   // t0 + 8 fwhm, where the envelope is below 1e-38; sin^2: its full length)
   const double t_end = c.env == PIC_ENV_GAUSS ? c.t0 + 8.0 * c.fwhm : c.t0 + 0.5 * c.T;
@@ -112,6 +127,15 @@ pic_status plan(const pic_config* cfg, const Canon& c, const std::vector<TableHo
   for (int q = 0; q < 3; ++q) L->o_po[q] = take(q < D ? sizeof(float) * L->capacity : 0);
   for (int q = 0; q < 3; ++q) L->o_pu[q] = take(sizeof(float) * L->capacity);
   L->o_pkind = take(L->capacity);
+  L->o_gcnt = take(sizeof(int) * L->ngroups);
+  L->o_gn = take(sizeof(int) * L->ngroups);
+  L->o_gstart = take(sizeof(int) * L->ngroups);
+  L->o_gfill = take(sizeof(int) * L->ngroups);
+  L->o_chunks = take(sizeof(int4) * L->maxchunks);
+  L->o_scell = take(sizeof(uint32_t) * L->capacity);
+  for (int q = 0; q < 3; ++q) L->o_so[q] = take(q < D ? sizeof(float) * L->capacity : 0);
+  for (int q = 0; q < 3; ++q) L->o_su[q] = take(sizeof(float) * L->capacity);
+  L->o_skind = take(L->capacity);
   for (int m = 0; m < MAXMAT; ++m) L->o_tab[m] = take(m < (int)tabs.size() ? tabs[m].bytes.size() : 0);
   L->o_ctr = take(sizeof(Ctr));
   L->o_grid64 = take(sizeof(double) * (size_t)L->ncell);
@@ -136,7 +160,7 @@ struct pic_ctx {
   hipStream_t stream = nullptr;
   Inst h{};
   Inst* d_inst = nullptr;
-  int* d_off = nullptr;   // [0, nb_push, 0, nb_cell, 0, nb_win, 0, nb_neut]
+  int* d_off = nullptr;   // [0, nb_push, 0, nb_cell, 0, 1, 0, nb_neut]
   int nb_push = 0, nb_cell = 0, nb_win = 0, nb_neut = 0;
   int tile = 0;               // field-kernel tile variant
   double tune_ms[8] = {0};    // autotuner: ms per field launch of each variant
@@ -154,10 +178,8 @@ struct pic_ctx {
   int ev_used[8][kRing] = {};
   int64_t ev_slot = 0;
   int owns_alloc_via_cb = 0;
-  int d_off_push = -1;        // push blocks currently in d_off (single-run launches)
-  int* h_count = nullptr;     // pinned: charged slots used, copied back after each pic_step
-  int* h_off = nullptr;       // pinned: staging for the push-phase block offsets
   int* h_step = nullptr;      // pinned: staging for the device step counter
+  int resort = 8;             // tile-sort check every `resort` steps (0 = never)
 };
 
 struct pic_batch {
@@ -174,6 +196,8 @@ struct pic_batch {
   };
   std::vector<Class> classes;
   hipStream_t stream = nullptr;
+  int resort = 8;     // tile-sort check every `resort` batch steps (0 = never)
+  int64_t tick = 0;   // batch steps taken
 };
 
 namespace {
@@ -228,10 +252,12 @@ void harvest_all(pic_ctx* c) {
 }
 
 // phases: 0 push, 1 fields (Yee step, outflow faces, amplitude window),
-// 2 ionize (+ step counter)
+// 2 ionize (+ step counter), 3 tile sort (when a check is due)
 void enqueue_step(pic_ctx* c) {
   const int D = c->canon.D, order = c->cfg.shape_order;
   hipStream_t s = c->stream;
+  if (c->resort > 0 && c->step % c->resort == 0)
+    timed(c, 3, [&] { launch_sort(single(c, 0, c->nb_push), single(c, 2, 1), D, s); });
   timed(c, 0, [&] { launch_push(single(c, 0, c->nb_push), D, order, s); });
   timed(c, 1, [&] { launch_fields(single(c, 1, c->nb_cell), D, c->tile, s); });
   timed(c, 2, [&] { launch_ionize(single(c, 3, c->nb_neut), D, order, s); });
@@ -239,11 +265,11 @@ void enqueue_step(pic_ctx* c) {
   ++c->step;
 }
 
-// push grid: enough threads for the charged particles last seen (grid-stride
-// covers any births since), at least 32 blocks
-int push_blocks(int64_t count) {
-  const int64_t nb = (count + TPB * 4 - 1) / (TPB * 4);
-  return (int)std::max<int64_t>(32, std::min<int64_t>(nb, 8192));
+// push and sort grid: persistent blocks (grid-stride over tile chunks and the
+// unsorted tail), sized by the slot capacity: 8 slots per thread, 16 .. 2048
+int push_blocks(int64_t capacity) {
+  const int64_t nb = (capacity + TPB * 8 - 1) / (TPB * 8);
+  return (int)std::max<int64_t>(16, std::min<int64_t>(nb, 2048));
 }
 
 // padded index of logical (i, j, k)
@@ -415,11 +441,7 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
     pic_destroy(c);
     return s;
   };
-  if (hipHostMalloc((void**)&c->h_count, sizeof(int)) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_off, 4 * sizeof(int)) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_step, sizeof(int)) != hipSuccess)
-    return fail(PIC_E_NOMEM);
-  *c->h_count = c->cfg.preionize_eV > 0 ? (int)(2 * L.nneut) : 0;
+  if (hipHostMalloc((void**)&c->h_step, sizeof(int)) != hipSuccess) return fail(PIC_E_NOMEM);
   if (hipMemsetAsync(c->base, 0, L.total, c->stream) != hipSuccess) return fail(PIC_E_DEVICE);
 
   // ---- host-built tables and parameter block
@@ -500,8 +522,24 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
   I.pu1 = (float*)devp(c, L.o_pu[1]);
   I.pu2 = (float*)devp(c, L.o_pu[2]);
   I.pkind = (uint8_t*)devp(c, L.o_pkind);
+  for (int d = 0; d < 3; ++d) I.ntile[d] = L.ntile[d];
+  I.ntiles = (int)L.ntiles;
+  I.gcnt = (int*)devp(c, L.o_gcnt);
+  I.gn = (int*)devp(c, L.o_gn);
+  I.gstart = (int*)devp(c, L.o_gstart);
+  I.gfill = (int*)devp(c, L.o_gfill);
+  I.chunks = (int4*)devp(c, L.o_chunks);
+  I.scell = (uint32_t*)devp(c, L.o_scell);
+  I.so0 = (float*)devp(c, L.o_so[0]);
+  I.so1 = (float*)devp(c, L.o_so[1]);
+  I.so2 = (float*)devp(c, L.o_so[2]);
+  I.su0 = (float*)devp(c, L.o_su[0]);
+  I.su1 = (float*)devp(c, L.o_su[1]);
+  I.su2 = (float*)devp(c, L.o_su[2]);
+  I.skind = (uint8_t*)devp(c, L.o_skind);
   c->d_ctr = (Ctr*)devp(c, L.o_ctr);
   I.pcount = &c->d_ctr->pcount;
+  I.sctl = c->d_ctr->sctl;
   I.step = &c->d_ctr->step;
   I.health = &c->d_ctr->health;
   I.nevents = c->d_ctr->nevents;
@@ -523,6 +561,13 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
     I.tab[m] = (const TabHdr*)devp(c, L.o_tab[m]);
     I.acut[m] = c->tabs[m].acut;
   }
+  // fixed-point scale of the LDS deposit: 2^JFIX_BITS per 2^ceil(log2 max |kq|)
+  float qmax = 0.0f;
+  for (int kd = 0; kd < 2 * K.nmat; ++kd)
+    for (int d = 0; d < 3; ++d) qmax = std::max(qmax, std::fabs(I.kq[kd][d]));
+  const int qexp = qmax > 0.0f ? (int)std::ceil(std::log2((double)qmax)) : 0;
+  I.jscale = std::ldexp(1.0f, JFIX_BITS - qexp);
+  I.jscale_inv = std::ldexp(1.0f, qexp - JFIX_BITS);
   I.nneut = L.nneut;
   I.ppc = K.ppc;
   I.ppc_magic = K.ppc > 1 ? UINT64_MAX / (uint64_t)K.ppc + 1 : 0;
@@ -539,17 +584,16 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
 
   // block counts per phase
   auto nblk = [](int64_t n) { return (int)std::max<int64_t>(0, (n + TPB - 1) / TPB); };
-  c->nb_push = push_blocks(c->cfg.preionize_eV > 0 ? 2 * L.nneut : 0);
+  c->nb_push = push_blocks(L.capacity);
   // field tile shape: default per dimension, overridable (tuning sweeps) by
   // PIC_FIELD_TILE=<variant>
   c->tile = 0;
   if (const char* tv = std::getenv("PIC_FIELD_TILE")) c->tile = std::max(0, std::min(atoi(tv), field_tile_variants() - 1));
   c->nb_cell = field_tiles(D, c->tile, (int)L.Px, (int)L.Py, (int)L.Pz);
-  c->nb_win = 0;
+  c->nb_win = 1;   // one block per instance (tile-sort scan)
   c->nb_neut = std::max(1, nblk(L.nneut));
 
   const int offs[8] = {0, c->nb_push, 0, c->nb_cell, 0, c->nb_win, 0, c->nb_neut};
-  c->d_off_push = c->nb_push;
 
   hipStream_t s = c->stream;
   bool ok = true;
@@ -595,8 +639,6 @@ void pic_destroy(pic_ctx* c) {
     for (int k = 0; k < pic_ctx::kRing; ++k)
       for (int e = 0; e < 2; ++e)
         if (c->ev[ph][k][e]) (void)hipEventDestroy(c->ev[ph][k][e]);
-  if (c->h_count) (void)hipHostFree(c->h_count);
-  if (c->h_off) (void)hipHostFree(c->h_off);
   if (c->h_step) (void)hipHostFree(c->h_step);
   if (c->base) {
     if (c->owns_alloc_via_cb && c->cfg.free) c->cfg.free(c->base, c->cfg.alloc_user);
@@ -613,27 +655,20 @@ pic_status pic_set_timing(pic_ctx* c, int32_t on) {
   return PIC_OK;
 }
 
-// Resize the push grid from the last charged-slot count seen on the host.
-static void refresh_push_grid(pic_ctx* c) {
-  const int nb = push_blocks(std::max<int64_t>(*c->h_count, 0));
-  c->nb_push = nb;
-  if (nb == c->d_off_push) return;
-  c->d_off_push = nb;
-  c->h_off[0] = 0;
-  c->h_off[1] = nb;
-  (void)hipMemcpyAsync(c->d_off, c->h_off, 2 * sizeof(int), hipMemcpyHostToDevice, c->stream);
+pic_status pic_set_resort(pic_ctx* c, int32_t period) {
+  if (!c || period < 0) return PIC_E_INVAL;
+  c->resort = period;
+  return PIC_OK;
 }
 
 pic_status pic_step(pic_ctx* c, int64_t nsteps) {
   if (!c || nsteps < 0) return PIC_E_INVAL;
   if (c->latched != PIC_OK) return PIC_E_STATE;
   (void)hipGetLastError();
-  refresh_push_grid(c);
   for (int64_t s = 0; s < nsteps; ++s) enqueue_step(c);   // advances c->step
   // keep the device step counter (read by batches and diagnostics) in step
   *c->h_step = (int)c->step;
   (void)hipMemcpyAsync(&c->d_ctr->step, c->h_step, sizeof(int), hipMemcpyHostToDevice, c->stream);
-  (void)hipMemcpyAsync(c->h_count, &c->d_ctr->pcount, sizeof(int), hipMemcpyDeviceToHost, c->stream);
   if (hipGetLastError() != hipSuccess) return PIC_E_DEVICE;
   return PIC_OK;
 }
@@ -745,7 +780,8 @@ pic_status pic_set_state(pic_ctx* c, const pic_state* S) {
     }
     const int cnt = (int)n;
     HIP_OK(hipMemcpy(&c->d_ctr->pcount, &cnt, sizeof cnt, hipMemcpyHostToDevice));
-    *c->h_count = cnt;
+    // the new particles are all unsorted
+    HIP_OK(hipMemset(c->d_ctr->sctl, 0, sizeof(c->d_ctr->sctl)));
   }
   const int st = (int)S->step;
   HIP_OK(hipMemcpy(&c->d_ctr->step, &st, sizeof st, hipMemcpyHostToDevice));
@@ -782,6 +818,7 @@ pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size
     case PIC_DIAG_AMP: need = sizeof(float) * dom_count(K, kNode); break;
     case PIC_DIAG_PARAMS: need = sizeof(pic_params); break;
     case PIC_DIAG_TIMERS: need = sizeof(double) * 24; break;
+    case PIC_DIAG_SORT: need = sizeof(double) * 4; break;
     case PIC_DIAG_EVENTS:
     case PIC_DIAG_PARTICLES: break;   // computed below
     default: return PIC_E_INVAL;
@@ -893,6 +930,16 @@ pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size
       P.amp_sat[m] = c->tabs[m].asat;
     }
     std::memcpy(host_out, &P, sizeof P);
+    return PIC_OK;
+  }
+  if (kind == PIC_DIAG_SORT) {
+    int w[SC_WORDS];
+    HIP_OK(hipMemcpy(w, c->d_ctr->sctl, sizeof w, hipMemcpyDeviceToHost));
+    double* o = (double*)host_out;
+    o[0] = w[SC_NSORTED];
+    o[1] = w[SC_NCHUNKS];
+    o[2] = w[SC_NDRIFT];
+    o[3] = w[SC_NSORTS];
     return PIC_OK;
   }
   if (kind == PIC_DIAG_TIMERS) {
@@ -1035,13 +1082,6 @@ pic_status pic_batch_step(pic_batch* b, int64_t nsteps) {
   if (!b || nsteps < 0) return PIC_E_INVAL;
   for (pic_ctx* c : b->members)
     if (c->latched != PIC_OK) return PIC_E_STATE;
-  for (pic_ctx* c : b->members) {
-    const int nb = push_blocks(std::max<int64_t>(*c->h_count, 0));
-    if (nb != c->nb_push) {
-      c->nb_push = nb;
-      b->dirty = true;
-    }
-  }
   if (b->dirty) {
     pic_status st = batch_rebuild(b);
     if (st != PIC_OK) return st;
@@ -1049,21 +1089,21 @@ pic_status pic_batch_step(pic_batch* b, int64_t nsteps) {
   hipStream_t s = b->stream;
   (void)hipGetLastError();
   for (int64_t t = 0; t < nsteps; ++t) {
+    const bool sort_due = b->resort > 0 && b->tick++ % b->resort == 0;
     for (auto& cl : b->classes) {
       const int np1 = cl.n + 1;
       Group gp{cl.d_insts, cl.d_off + 0 * np1, cl.n, cl.blocks[0], -1};
       Group gc{cl.d_insts, cl.d_off + 1 * np1, cl.n, cl.blocks[1], -1};
+      Group gs{cl.d_insts, cl.d_off + 2 * np1, cl.n, cl.blocks[2], -1};
       Group gn{cl.d_insts, cl.d_off + 3 * np1, cl.n, cl.blocks[3], -1};
+      if (sort_due) launch_sort(gp, gs, cl.D, s);
       launch_push(gp, cl.D, cl.order, s);
       launch_fields(gc, cl.D, cl.tile, s);
       launch_ionize(gn, cl.D, cl.order, s);
       launch_advance(cl.d_insts, cl.n, s);
     }
   }
-  for (pic_ctx* c : b->members) {
-    c->step += nsteps;
-    (void)hipMemcpyAsync(c->h_count, &c->d_ctr->pcount, sizeof(int), hipMemcpyDeviceToHost, s);
-  }
+  for (pic_ctx* c : b->members) c->step += nsteps;
   if (hipGetLastError() != hipSuccess) return PIC_E_DEVICE;
   return PIC_OK;
 }

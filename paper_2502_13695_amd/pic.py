@@ -23,7 +23,7 @@ ABI_VERSION = 1
 ENV = {"gauss": 0, "sin2": 1}
 BC = {"outflow": 0, "periodic": 1}
 DIAG_SCALARS, DIAG_FIELDS, DIAG_NE, DIAG_UE, DIAG_EVENTS, DIAG_PARTICLES, DIAG_PARAMS, DIAG_AMP, \
-    DIAG_TIMERS = range(9)
+    DIAG_TIMERS, DIAG_SORT = range(10)
 SC = dict(step=0, time=1, n_neutral=2, n_e=3, n_pos=4, events=5, u_field=6, ke_e=7, ke_pos=8,
           e_gap=9, e_abs=10, gauss_max=11, rho_max=12, health=13, slots=14)
 
@@ -91,7 +91,7 @@ class State(C.Structure):
 SYMBOLS = ["pic_init", "pic_step", "pic_diag", "pic_set_state", "pic_footprint", "pic_canonical",
            "pic_keldysh_rate", "pic_table_probe", "pic_table_probe_device", "pic_batch_create",
            "pic_batch_step", "pic_batch_add", "pic_batch_remove", "pic_batch_destroy",
-           "pic_set_timing", "pic_autotune", "pic_destroy", "pic_status_str"]
+           "pic_set_timing", "pic_autotune", "pic_set_resort", "pic_destroy", "pic_status_str"]
 
 
 def lib():
@@ -128,6 +128,7 @@ def lib():
             "pic_batch_destroy": ([vp], None),
             "pic_set_timing": ([vp, i32], C.c_int),
             "pic_autotune": ([vp, i32], C.c_int),
+            "pic_set_resort": ([vp, i32], C.c_int),
             "pic_destroy": ([vp], None),
             "pic_status_str": ([C.c_int], C.c_char_p),
         }
@@ -253,6 +254,10 @@ class Context:
     def set_timing(self, on):
         _check(lib().pic_set_timing(self.h, int(on)), "pic_set_timing")
 
+    def set_resort(self, period):
+        """Tile-sort check period in steps (0 = never sort the charged particles)."""
+        _check(lib().pic_set_resort(self.h, int(period)), "pic_set_resort")
+
     def autotune(self, reps=20):
         """Pick the fastest field-kernel tile shape (before the first step)."""
         _check(lib().pic_autotune(self.h, int(reps)), "pic_autotune")
@@ -341,6 +346,11 @@ class Context:
 
     def timers(self):
         return self._diag(DIAG_TIMERS, np.float64)
+
+    def sort_state(self):
+        """Tile-sort state: sorted slots, chunks, drifter-steps since the sort, sorts done."""
+        v = self._diag(DIAG_SORT, np.float64)
+        return dict(sorted=int(v[0]), chunks=int(v[1]), drift=int(v[2]), sorts=int(v[3]))
 
     def set_state(self, step, E=None, b=None, particles=None, reset_window=True):
         """Overwrite fields ([i, j, k] arrays on their own positions), charged
