@@ -153,7 +153,7 @@ enum {
   PIC_DIAG_TIMERS = 8,    /* double[24]: [0..7] device ms per phase summed over the
                              timed launches, [8..15] launch counts (phases: 0 push,
                              1 field update with outflow faces and amplitude window,
-                             2 ionization); [16..22] autotuner ms per field launch of
+                             2 ionization, 3 tile sort); [16..22] autotuner ms per field launch of
                              each tile shape, [23] the tile shape in use */
   PIC_DIAG_SORT = 9       /* double[4]: charged slots held in tile order, tile
                              chunks, drifter-steps (a particle that deposited outside
@@ -250,8 +250,10 @@ void pic_batch_destroy(pic_batch* b);
 pic_status pic_autotune(pic_ctx* c, int32_t reps);
 
 /* Device time of each step phase measured with HIP events recorded on the
- * context stream around every launch (no host synchronisation per step);
- * off by default; switching resets the accumulators. */
+ * context stream around the launches of every `on`-th step (1 = every step;
+ * 0 = off, the default); no host synchronisation per step.  Phases: 0 push,
+ * 1 field update, 2 ionization, 3 tile sort.  Switching resets the
+ * accumulators. */
 pic_status pic_set_timing(pic_ctx* c, int32_t on);
 
 /* Tile sort of the charged particles (the resort of the particle loop): every

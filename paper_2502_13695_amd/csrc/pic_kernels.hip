@@ -347,34 +347,94 @@ struct PushFields {
   const float* __restrict__ B2;
 };
 
-// One charged particle: gather E^n, b^n, relativistic Boris, move, deposit,
-// boundary.  TILED: the block holds the LDS window of tile origin
-// (tx0, ty0, tz0); a particle that started the step inside that tile
-// deposits there, any other one in HBM (and is counted as a drifter).
-template <int D, int ORDER, bool TILED>
-__device__ __forceinline__ void push_one(const Inst& I, const PushFields& f, const GSink& gs,
-                                         const LSink<D>& ls, int tx0, int ty0, int tz0, int p,
-                                         bool valid) {
-  const unsigned q = (unsigned)p;
-  const uint8_t kind = valid ? gp(I.pkind)[q] : DEAD;
-  if (kind == DEAD) return;
-  int ci, cj, ck;
-  unpack_cell(D, gp(I.pcell)[q], ci, cj, ck);
-  const float t0 = gp(I.po0)[q];
-  const float t1 = D >= 2 ? gp(I.po1)[q] : 0.0f;
-  const float t2 = D >= 3 ? gp(I.po2)[q] : 0.0f;
-  float ux = gp(I.pu0)[q], uy = gp(I.pu1)[q], uz = gp(I.pu2)[q];
+// Field window of a particle tile staged in LDS: the gather stencil of a
+// particle starting in cell c spans nodes c - 1 .. c + 2 (both staggerings,
+// order <= 2), so a tile of T cells needs T + 3 nodes per present axis.
+template <int D>
+struct FWin {
+  static constexpr int X = ptile_ext(D, 0) + 3;
+  static constexpr int Y = D >= 2 ? ptile_ext(D, 1) + 3 : 1;
+  static constexpr int Z = D >= 3 ? ptile_ext(D, 2) + 3 : 1;
+  static constexpr int N = X * Y * Z;
+};
+
+// threads per block of the push: the 3D windows (current and fields) take
+// most of a CU's LDS, so one larger block per CU shares them
+__host__ __device__ constexpr int push_tpb(int D) { return D == 3 ? 512 : 256; }
+
+template <int ORDER>
+__device__ __forceinline__ void make_axis_l(Axis<ORDER>& a, int c, float t, int origin, int stride) {
+  const int bn = shape<ORDER>(c, t, 0, a.wn);
+  const int bh = shape<ORDER>(c, t, 1, a.wh);
+#pragma unroll
+  for (int q = 0; q <= ORDER; ++q) {
+    a.on[q] = stride * (bn + q - origin);
+    a.oh[q] = stride * (bh + q - origin);
+  }
+}
+
+template <int D, int ORDER>
+__device__ __forceinline__ float gather_l(const float* __restrict__ S, const Axis<ORDER>& X,
+                                          const Axis<ORDER>& Y, const Axis<ORDER>& Z, int hx, int hy,
+                                          int hz) {
+  constexpr int SY = D >= 2 ? ORDER + 1 : 1;
+  constexpr int SZ = D >= 3 ? ORDER + 1 : 1;
+  constexpr int SX = ORDER + 1;
+  const int ox = hx ? X.oh[0] : X.on[0];
+  float acc = 0.0f;
+#pragma unroll
+  for (int c = 0; c < SZ; ++c) {
+    const float wz = D >= 3 ? (hz ? Z.wh[c] : Z.wn[c]) : 1.0f;
+    const int oz = D >= 3 ? (hz ? Z.oh[c] : Z.on[c]) : 0;
+#pragma unroll
+    for (int b = 0; b < SY; ++b) {
+      const float wy = D >= 2 ? (hy ? Y.wh[b] : Y.wn[b]) : 1.0f;
+      const int oy = D >= 2 ? (hy ? Y.oh[b] : Y.on[b]) : 0;
+      const float* r = S + (ox + oy + oz);
+      float row = 0.0f;
+#pragma unroll
+      for (int a = 0; a < SX; ++a) row += (hx ? X.wh[a] : X.wn[a]) * r[a];
+      acc += wz * wy * row;
+    }
+  }
+  return acc;
+}
+
+// Boris, move, deposit and write-back of one charged particle.  LOCAL: the
+// particle started inside the block's tile -- fields from the LDS window
+// (origin fx0, fy0, fz0), current into the LDS sink; else HBM for both.
+template <int D, int ORDER, bool LOCAL>
+__device__ __forceinline__ void push_body(const Inst& I, const PushFields& f, const float* sF, int fx0,
+                                          int fy0, int fz0, const GSink& gs, const LSink<D>& ls,
+                                          unsigned q, uint8_t kind, int ci, int cj, int ck, float t0,
+                                          float t1, float t2, float ux, float uy, float uz) {
   // ---- gather E^n, b^n
-  Axis<ORDER> X, Y, Z;
-  make_axis<ORDER>(X, ci, t0, I.nx, 0, G, 1);
-  if (D >= 2) make_axis<ORDER>(Y, cj, t1, I.ny, I.per_y, I.Gy, I.sy);
-  if (D >= 3) make_axis<ORDER>(Z, ck, t2, I.nz, I.per_z, I.Gz, I.sz);
-  const float ex = gather<D, ORDER>(f.E0, X, Y, Z, 1, 0, 0);
-  const float ey = gather<D, ORDER>(f.E1, X, Y, Z, 0, 1, 0);
-  const float ez = gather<D, ORDER>(f.E2, X, Y, Z, 0, 0, 1);
-  const float bx = gather<D, ORDER>(f.B0, X, Y, Z, 0, 1, 1);
-  const float by = gather<D, ORDER>(f.B1, X, Y, Z, 1, 0, 1);
-  const float bz = gather<D, ORDER>(f.B2, X, Y, Z, 1, 1, 0);
+  float ex, ey, ez, bx, by, bz;
+  {
+    Axis<ORDER> X, Y, Z;
+    if (LOCAL) {
+      constexpr int N = FWin<D>::N;
+      make_axis_l<ORDER>(X, ci, t0, fx0, 1);
+      if (D >= 2) make_axis_l<ORDER>(Y, cj, t1, fy0, FWin<D>::X);
+      if (D >= 3) make_axis_l<ORDER>(Z, ck, t2, fz0, FWin<D>::X * FWin<D>::Y);
+      ex = gather_l<D, ORDER>(sF + 0 * N, X, Y, Z, 1, 0, 0);
+      ey = gather_l<D, ORDER>(sF + 1 * N, X, Y, Z, 0, 1, 0);
+      ez = gather_l<D, ORDER>(sF + 2 * N, X, Y, Z, 0, 0, 1);
+      bx = gather_l<D, ORDER>(sF + 3 * N, X, Y, Z, 0, 1, 1);
+      by = gather_l<D, ORDER>(sF + 4 * N, X, Y, Z, 1, 0, 1);
+      bz = gather_l<D, ORDER>(sF + 5 * N, X, Y, Z, 1, 1, 0);
+    } else {
+      make_axis<ORDER>(X, ci, t0, I.nx, 0, G, 1);
+      if (D >= 2) make_axis<ORDER>(Y, cj, t1, I.ny, I.per_y, I.Gy, I.sy);
+      if (D >= 3) make_axis<ORDER>(Z, ck, t2, I.nz, I.per_z, I.Gz, I.sz);
+      ex = gather<D, ORDER>(f.E0, X, Y, Z, 1, 0, 0);
+      ey = gather<D, ORDER>(f.E1, X, Y, Z, 0, 1, 0);
+      ez = gather<D, ORDER>(f.E2, X, Y, Z, 0, 0, 1);
+      bx = gather<D, ORDER>(f.B0, X, Y, Z, 0, 1, 1);
+      by = gather<D, ORDER>(f.B1, X, Y, Z, 1, 0, 1);
+      bz = gather<D, ORDER>(f.B2, X, Y, Z, 1, 1, 0);
+    }
+  }
   // ---- relativistic Boris (u = gamma v / c, b = c B, h = q dt / 2 m c)
   const float h = I.kh[kind];
   const float umx = ux + h * ex, umy = uy + h * ey, umz = uz + h * ez;
@@ -408,25 +468,14 @@ __device__ __forceinline__ void push_one(const Inst& I, const PushFields& f, con
   if (D >= 2) move(n1, nj, I.C[1] * uy * ig);
   if (D >= 3) move(n2, nk, I.C[2] * uz * ig);
   // ---- Esirkepov deposit of J^{n+1/2} (scaled: dt J / eps0, V/m)
-  Esk<ORDER> exk, eyk, ezk;
-  esk_axis<ORDER>(exk, ci, t0, ni, n0);
-  if (D >= 2) esk_axis<ORDER>(eyk, cj, t1, nj, n1);
-  if (D >= 3) esk_axis<ORDER>(ezk, ck, t2, nk, n2);
-  const float qx = I.kq[kind][0], qy = I.kq[kind][1], qz = I.kq[kind][2];
-  const float wy = uy * ig, wz = uz * ig;
-  if (TILED) {
-    bool in = ci >= tx0 && ci < tx0 + ptile_ext(D, 0);
-    if (D >= 2) in = in && cj >= ty0 && cj < ty0 + ptile_ext(D, 1);
-    if (D >= 3) in = in && ck >= tz0 && ck < tz0 + ptile_ext(D, 2);
-    if (in) {
-      deposit<D, ORDER>(ls, exk, eyk, ezk, qx, qy, qz, wy, wz);
-    } else {
-      deposit<D, ORDER>(gs, exk, eyk, ezk, qx, qy, qz, wy, wz);
-      const unsigned long long m = __ballot(1);
-      if ((threadIdx.x & 63) == __ffsll((long long)m) - 1) atomicAdd(I.sctl + SC_NDRIFT, __popcll(m));
-    }
-  } else {
-    deposit<D, ORDER>(gs, exk, eyk, ezk, qx, qy, qz, wy, wz);
+  {
+    Esk<ORDER> exk, eyk, ezk;
+    esk_axis<ORDER>(exk, ci, t0, ni, n0);
+    if (D >= 2) esk_axis<ORDER>(eyk, cj, t1, nj, n1);
+    if (D >= 3) esk_axis<ORDER>(ezk, ck, t2, nk, n2);
+    const float qx = I.kq[kind][0], qy = I.kq[kind][1], qz = I.kq[kind][2];
+    if (LOCAL) deposit<D, ORDER>(ls, exk, eyk, ezk, qx, qy, qz, uy * ig, uz * ig);
+    else deposit<D, ORDER>(gs, exk, eyk, ezk, qx, qy, qz, uy * ig, uz * ig);
   }
   // ---- boundaries: outflow removes, periodic wraps
   int dead = 0;
@@ -452,14 +501,49 @@ __device__ __forceinline__ void push_one(const Inst& I, const PushFields& f, con
   gp(I.pu2)[q] = uz;
 }
 
+// One charged particle (slot p).  TILED: the block holds the LDS windows of
+// the tile with origin (tx0, ty0, tz0); a particle that started the step
+// outside that tile goes through HBM and is counted as a drifter.
+template <int D, int ORDER, bool TILED>
+__device__ __forceinline__ void push_one(const Inst& I, const PushFields& f, const float* sF,
+                                         const GSink& gs, const LSink<D>& ls, int tx0, int ty0,
+                                         int tz0, int p, bool valid) {
+  const unsigned q = (unsigned)p;
+  const uint8_t kind = valid ? gp(I.pkind)[q] : DEAD;
+  if (kind == DEAD) return;
+  int ci, cj, ck;
+  unpack_cell(D, gp(I.pcell)[q], ci, cj, ck);
+  const float t0 = gp(I.po0)[q];
+  const float t1 = D >= 2 ? gp(I.po1)[q] : 0.0f;
+  const float t2 = D >= 3 ? gp(I.po2)[q] : 0.0f;
+  const float ux = gp(I.pu0)[q], uy = gp(I.pu1)[q], uz = gp(I.pu2)[q];
+  if (TILED) {
+    bool in = ci >= tx0 && ci < tx0 + ptile_ext(D, 0);
+    if (D >= 2) in = in && cj >= ty0 && cj < ty0 + ptile_ext(D, 1);
+    if (D >= 3) in = in && ck >= tz0 && ck < tz0 + ptile_ext(D, 2);
+    if (in) {
+      push_body<D, ORDER, true>(I, f, sF, tx0 - 1, ty0 - 1, tz0 - 1, gs, ls, q, kind, ci, cj, ck, t0, t1,
+                                t2, ux, uy, uz);
+    } else {
+      const unsigned long long m = __ballot(1);
+      if ((threadIdx.x & 63) == __ffsll((long long)m) - 1) atomicAdd(I.sctl + SC_NDRIFT, __popcll(m));
+      push_body<D, ORDER, false>(I, f, sF, 0, 0, 0, gs, ls, q, kind, ci, cj, ck, t0, t1, t2, ux, uy, uz);
+    }
+  } else {
+    push_body<D, ORDER, false>(I, f, sF, 0, 0, 0, gs, ls, q, kind, ci, cj, ck, t0, t1, t2, ux, uy, uz);
+  }
+}
+
 // Charged-particle phase.  Work units of a block (persistent grid-stride):
-// first the chunks of the sorted tiles -- the block clears its LDS window,
-// pushes the chunk's particles depositing into LDS, then adds the window's
-// nonzero nodes to HBM with one atomic each -- then the unsorted tail
-// (births since the sort) with HBM atomics.
+// first the chunks of the sorted tiles -- the block stages the tile's field
+// window in LDS and clears its current window, pushes the chunk's particles,
+// then adds the current window's nonzero nodes to HBM with one atomic each --
+// then the unsorted tail (births since the sort) through HBM.
 template <int D, int ORDER>
-__global__ __launch_bounds__(TPB) void k_push(Group g) {
+__global__ __launch_bounds__(push_tpb(D)) void k_push(Group g) {
+  constexpr int NT = push_tpb(D);
   __shared__ unsigned long long sJ[3 * PWin<D>::N];
+  __shared__ float sF[6 * FWin<D>::N];
   const int ii = find_inst(g);
   const Inst& I = g.insts[ii];
   const int nb = g.off[ii + 1] - g.off[ii];
@@ -483,18 +567,47 @@ __global__ __launch_bounds__(TPB) void k_push(Group g) {
     const int tz0 = D >= 3 ? (t / (I.ntile[0] * I.ntile[1])) * ptile_ext(D, 2) : 0;
     const LSink<D> ls{sJ, tx0 - PT_LO, D >= 2 ? ty0 - PT_LO : 0, D >= 3 ? tz0 - PT_LO : 0,
                       (double)I.jscale};
-    for (int e = threadIdx.x; e < 3 * PWin<D>::N; e += TPB) sJ[e] = 0ull;
-    __syncthreads();
-    const int end = ch.z < count ? ch.z : count;
-    for (int p0 = ch.y; p0 < end; p0 += TPB) {
-      const int p = p0 + threadIdx.x;
-      push_one<D, ORDER, true>(I, f, gs, ls, tx0, ty0, tz0, p, p < end);
+    for (int e = threadIdx.x; e < 3 * PWin<D>::N; e += NT) sJ[e] = 0ull;
+    // field window: nodes tile - 1 .. tile + T + 1 (periodic axes wrapped;
+    // nodes outside the padded arrays, never read, are zero)
+    for (int e = threadIdx.x; e < FWin<D>::N; e += NT) {
+      const int a = e % FWin<D>::X;
+      const int b = (e / FWin<D>::X) % FWin<D>::Y;
+      const int c = e / (FWin<D>::X * FWin<D>::Y);
+      const int px = tx0 - 1 + a + G;
+      bool ok = px < I.Px;
+      int off = px;
+      if (D >= 2) {
+        int j = ty0 - 1 + b;
+        if (I.per_y) j = ((j % I.ny) + I.ny) % I.ny;
+        ok = ok && j + I.Gy < I.Py;
+        off += I.sy * (j + I.Gy);
+      }
+      if (D >= 3) {
+        int k = tz0 - 1 + c;
+        if (I.per_z) k = ((k % I.nz) + I.nz) % I.nz;
+        ok = ok && k + I.Gz < I.Pz;
+        off += I.sz * (k + I.Gz);
+      }
+      const unsigned o = (unsigned)off;
+      sF[0 * FWin<D>::N + e] = ok ? gp(f.E0)[o] : 0.0f;
+      sF[1 * FWin<D>::N + e] = ok ? gp(f.E1)[o] : 0.0f;
+      sF[2 * FWin<D>::N + e] = ok ? gp(f.E2)[o] : 0.0f;
+      sF[3 * FWin<D>::N + e] = ok ? gp(f.B0)[o] : 0.0f;
+      sF[4 * FWin<D>::N + e] = ok ? gp(f.B1)[o] : 0.0f;
+      sF[5 * FWin<D>::N + e] = ok ? gp(f.B2)[o] : 0.0f;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < 3 * PWin<D>::N; e += TPB) {
-      const long long q = (long long)sJ[e];
-      if (q == 0) continue;
-      const float v = (float)q * I.jscale_inv;
+    const int end = ch.z < count ? ch.z : count;
+    for (int p0 = ch.y; p0 < end; p0 += NT) {
+      const int p = p0 + threadIdx.x;
+      push_one<D, ORDER, true>(I, f, sF, gs, ls, tx0, ty0, tz0, p, p < end);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 3 * PWin<D>::N; e += NT) {
+      const long long qv = (long long)sJ[e];
+      if (qv == 0) continue;
+      const float v = (float)qv * I.jscale_inv;
       const int comp = e / PWin<D>::N;
       const int r = e - comp * PWin<D>::N;
       const int a = r % PWin<D>::X;
@@ -506,9 +619,9 @@ __global__ __launch_bounds__(TPB) void k_push(Group g) {
     __syncthreads();
   }
   const LSink<D> none{sJ, 0, 0, 0, 0.0};
-  for (int p0 = nsorted + b0 * TPB; p0 < count; p0 += nb * TPB) {
+  for (int p0 = nsorted + b0 * NT; p0 < count; p0 += nb * NT) {
     const int p = p0 + threadIdx.x;
-    push_one<D, ORDER, false>(I, f, gs, none, 0, 0, 0, p, p < count);
+    push_one<D, ORDER, false>(I, f, sF, gs, none, 0, 0, 0, p, p < count);
   }
 }
 
@@ -864,26 +977,26 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
   const int Gy = I.Gy, Gz = I.Gz;
   const int step = g.step >= 0 ? g.step : *I.step;
   const int par = step & 1;
-  const float* __restrict__ Ec0 = I.F[par][0];
-  const float* __restrict__ Ec1 = I.F[par][1];
-  const float* __restrict__ Ec2 = I.F[par][2];
-  const float* __restrict__ Bc0 = I.F[par][3];
-  const float* __restrict__ Bc1 = I.F[par][4];
-  const float* __restrict__ Bc2 = I.F[par][5];
-  float* __restrict__ En0 = I.F[par ^ 1][0];
-  float* __restrict__ En1 = I.F[par ^ 1][1];
-  float* __restrict__ En2 = I.F[par ^ 1][2];
-  float* __restrict__ Bn0 = I.F[par ^ 1][3];
-  float* __restrict__ Bn1 = I.F[par ^ 1][4];
-  float* __restrict__ Bn2 = I.F[par ^ 1][5];
-  const float* __restrict__ J0 = I.Jb[par][0];
-  const float* __restrict__ J1 = I.Jb[par][1];
-  const float* __restrict__ J2 = I.Jb[par][2];
-  float* __restrict__ Jn0 = I.Jb[par ^ 1][0];
-  float* __restrict__ Jn1 = I.Jb[par ^ 1][1];
-  float* __restrict__ Jn2 = I.Jb[par ^ 1][2];
-  const float* __restrict__ ieh = I.ie_half;
-  const float* __restrict__ ien = I.ie_node;
+  const gmem<float>* __restrict__ Ec0 = gp(uniform(I.F[par][0]));
+  const gmem<float>* __restrict__ Ec1 = gp(uniform(I.F[par][1]));
+  const gmem<float>* __restrict__ Ec2 = gp(uniform(I.F[par][2]));
+  const gmem<float>* __restrict__ Bc0 = gp(uniform(I.F[par][3]));
+  const gmem<float>* __restrict__ Bc1 = gp(uniform(I.F[par][4]));
+  const gmem<float>* __restrict__ Bc2 = gp(uniform(I.F[par][5]));
+  gmem<float>* __restrict__ En0 = gp(uniform(I.F[par ^ 1][0]));
+  gmem<float>* __restrict__ En1 = gp(uniform(I.F[par ^ 1][1]));
+  gmem<float>* __restrict__ En2 = gp(uniform(I.F[par ^ 1][2]));
+  gmem<float>* __restrict__ Bn0 = gp(uniform(I.F[par ^ 1][3]));
+  gmem<float>* __restrict__ Bn1 = gp(uniform(I.F[par ^ 1][4]));
+  gmem<float>* __restrict__ Bn2 = gp(uniform(I.F[par ^ 1][5]));
+  const gmem<float>* __restrict__ J0 = gp(uniform(I.Jb[par][0]));
+  const gmem<float>* __restrict__ J1 = gp(uniform(I.Jb[par][1]));
+  const gmem<float>* __restrict__ J2 = gp(uniform(I.Jb[par][2]));
+  gmem<float>* __restrict__ Jn0 = gp(uniform(I.Jb[par ^ 1][0]));
+  gmem<float>* __restrict__ Jn1 = gp(uniform(I.Jb[par ^ 1][1]));
+  gmem<float>* __restrict__ Jn2 = gp(uniform(I.Jb[par ^ 1][2]));
+  const gmem<float>* __restrict__ ieh = gp(I.ie_half);
+  const gmem<float>* __restrict__ ien = gp(I.ie_node);
   const float hx = I.halfC[0], hy = I.halfC[1], hz = I.halfC[2];
   const float Cx = I.C[0], Cy = I.C[1], Cz = I.C[2];
   const int i0 = a0x - G, j0 = a0y - Gy, k0 = a0z - Gz;   // logical tile origin
@@ -1038,7 +1151,7 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
             else ok = ok && (bb[e] & (half ? AX_BH : AX_BN));   // box incl. faces (periodic: any)
           }
           if (!ok) continue;
-          const float* Eold = c == 0 ? Ec0 : (c == 1 ? Ec1 : Ec2);
+          const gmem<float>* Eold = c == 0 ? Ec0 : (c == 1 ? Ec1 : Ec2);
           const float qold = Eold[gq], rold = Eold[gr], rnew = sE[c][l + inw * ls];
           if (d == 0 && (bd & AX_F0) && c == I.pol) {
             const float pr = I.prof[(soy[qy] / sy) + Py * (D >= 3 ? soz[qz] / sz : 0)];
@@ -1105,13 +1218,14 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
       if (!(m <= 3.0e38f)) atomicOr(I.health, HEALTH_NONFINITE);
       const int64_t wsz = I.wsz;
       const int64_t w = (int64_t)(ai - wx0) + (int64_t)I.wnx * (aj + (int64_t)Py * ak);
-      float* __restrict__ ring = I.ring;
-      float* __restrict__ suffix = I.suffix;
+      gmem<float>* __restrict__ ring = gp(I.ring);
+      gmem<float>* __restrict__ suffix = gp(I.suffix);
       ring[(int64_t)slot * wsz + w] = m;
-      const float pre = slot == 0 ? m : fmaxf(I.prefix[w], m);
-      I.prefix[w] = pre;
+      gmem<float>* __restrict__ prefix = gp(I.prefix);
+      const float pre = slot == 0 ? m : fmaxf(prefix[w], m);
+      prefix[w] = pre;
       const float a = slot + 1 < nwin ? fmaxf(suffix[(int64_t)(slot + 1) * wsz + w], pre) : pre;
-      I.A[gi] = a;
+      gp(I.A)[gi] = a;
       if (slot == nwin - 1) {   // block of samples complete: suffix maxima for the next
         float run = 0.0f;
         for (int q = nwin - 1; q >= 0; --q) {
@@ -1424,9 +1538,9 @@ __global__ void k_table_probe(const TabHdr* tab, const float* A, float* P, int64
 
 void launch_push(const Group& g, int D, int order, hipStream_t s) {
   if (order == 1) {
-    DISPATCH_D(D, hipLaunchKernelGGL((k_push<DD, 1>), dim3(g.blocks), dim3(TPB), 0, s, g));
+    DISPATCH_D(D, hipLaunchKernelGGL((k_push<DD, 1>), dim3(g.blocks), dim3(push_tpb(DD)), 0, s, g));
   } else {
-    DISPATCH_D(D, hipLaunchKernelGGL((k_push<DD, 2>), dim3(g.blocks), dim3(TPB), 0, s, g));
+    DISPATCH_D(D, hipLaunchKernelGGL((k_push<DD, 2>), dim3(g.blocks), dim3(push_tpb(DD)), 0, s, g));
   }
 }
 void launch_sort(const Group& gp, const Group& gscan, int D, hipStream_t s) {

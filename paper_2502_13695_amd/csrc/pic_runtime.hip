@@ -7,7 +7,10 @@
 #include <cstdlib>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "host_math.h"
@@ -24,6 +27,32 @@ constexpr double kEPS0 = 8.8541878128e-12;
 constexpr double kKB = 1.380649e-23;
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Process-wide cache of the FP64-built rate tables: a table depends only on
+// the material, the wavelength, the time step and the number of terms, which
+// runs of a scan or a serving mix share (building one takes ~0.4 s of host time).
+pic_status cached_table(const Canon& c, int mat, int terms, TableHost* out) {
+  static std::mutex mu;
+  static std::map<std::string, TableHost> cache;
+  const MatC& m = c.mats[mat];
+  const double key_v[9] = {m.gap_eV, m.n_index, m.n0, m.mred, m.mol_kg, m.e_kg, m.p_kg, c.lam, c.dt};
+  std::string key(reinterpret_cast<const char*>(key_v), sizeof key_v);
+  key.append(reinterpret_cast<const char*>(&terms), sizeof terms);
+  {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      *out = it->second;
+      return PIC_OK;
+    }
+  }
+  const pic_status st = build_table(c, mat, terms, out);
+  if (st != PIC_OK) return st;
+  std::lock_guard<std::mutex> g(mu);
+  if (cache.size() >= 256) cache.clear();
+  cache.emplace(key, *out);
+  return PIC_OK;
+}
 
 // Device memory plan of one context (offsets into one allocation).
 struct Layout {
@@ -169,7 +198,7 @@ struct pic_ctx {
   std::vector<uint32_t> mcell;
   int64_t step = 0;
   pic_status latched = PIC_OK;
-  int timing = 0;
+  int timing = 0;             // 0 off; k > 0: time the launches of every k-th step
   double timers[8] = {0};     // accumulated ms per phase
   double tcount[8] = {0};     // launches timed per phase
   // event ring per phase: record around each launch, read back when reused
@@ -228,7 +257,7 @@ void harvest(pic_ctx* c, int ph, int slot) {
 
 template <typename F>
 void timed(pic_ctx* c, int ph, F&& launch) {
-  if (!c->timing) {
+  if (!c->timing || c->step % c->timing != 0) {
     launch();
     return;
   }
@@ -261,7 +290,7 @@ void enqueue_step(pic_ctx* c) {
   timed(c, 0, [&] { launch_push(single(c, 0, c->nb_push), D, order, s); });
   timed(c, 1, [&] { launch_fields(single(c, 1, c->nb_cell), D, c->tile, s); });
   timed(c, 2, [&] { launch_ionize(single(c, 3, c->nb_neut), D, order, s); });
-  ++c->ev_slot;
+  if (c->timing && c->step % c->timing == 0) ++c->ev_slot;
   ++c->step;
 }
 
@@ -412,7 +441,7 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
   const int D = K.D;
   c->tabs.resize(K.nmat);
   for (int m = 0; m < K.nmat; ++m) {
-    st = build_table(K, m, cfg_in->keldysh_terms > 0 ? cfg_in->keldysh_terms : 500, &c->tabs[m]);
+    st = cached_table(K, m, cfg_in->keldysh_terms > 0 ? cfg_in->keldysh_terms : 500, &c->tabs[m]);
     if (st != PIC_OK) {
       delete c;
       return st;
@@ -1059,13 +1088,18 @@ static pic_status batch_rebuild(pic_batch* b) {
     }
     cl->ms.push_back(c);
   }
+  // persistent push/sort blocks: shared out over the members (every member
+  // keeps at least 16; its grid-stride loops cover any particle count)
+  const int nmem = (int)b->members.size();
+  const int push_share = std::max(16, 8192 / std::max(1, nmem));
   for (auto& cl : b->classes) {
     cl.n = (int)cl.ms.size();
     std::vector<Inst> hi(cl.n);
     std::vector<int> off(4 * (cl.n + 1), 0);
     for (int i = 0; i < cl.n; ++i) {
       hi[i] = cl.ms[i]->h;
-      const int nb[4] = {cl.ms[i]->nb_push, cl.ms[i]->nb_cell, cl.ms[i]->nb_win, cl.ms[i]->nb_neut};
+      const int nb[4] = {std::min(cl.ms[i]->nb_push, push_share), cl.ms[i]->nb_cell, cl.ms[i]->nb_win,
+                         cl.ms[i]->nb_neut};
       for (int ph = 0; ph < 4; ++ph) off[ph * (cl.n + 1) + i + 1] = off[ph * (cl.n + 1) + i] + nb[ph];
     }
     for (int ph = 0; ph < 4; ++ph) cl.blocks[ph] = off[ph * (cl.n + 1) + cl.n];
