@@ -258,8 +258,9 @@ pic_status pic_set_timing(pic_ctx* c, int32_t on);
 
 /* Tile sort of the charged particles (the resort of the particle loop): every
  * `period` steps (default 8; 0 = never) the device checks whether births
- * since the last sort exceed 1/32 of the slots in use, or particles that left
- * their tile exceed 1/64 (at least 256 either way), and if so counting-sorts
+ * since the last sort exceed 1/32 of the slots in use, or the particles that
+ * started a step outside their tile, summed over the steps since the sort,
+ * exceed 1/16 of them (at least 256 either way), and if so counting-sorts
  * the charged particles by tile of the deposit (compacting dead slots).  The
  * order of the slots returned by PIC_DIAG_PARTICLES changes with each sort;
  * physics results do not (only the summation order of the current).  A batch

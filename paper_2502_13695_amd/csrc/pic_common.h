@@ -95,11 +95,12 @@ __host__ __device__ inline float table_lookup(const TabHdr* __restrict__ h, floa
 // starts a step in cell c deposits its current on nodes c - 2 .. c + 3 of each
 // present axis (Esirkepov, shape order <= 2, at most one cell per step), so
 // the deposit of a whole tile of T cells fits a window of T + 5 nodes held in
-// LDS.  Each tile is split into groups of 64 cells (x fastest: 3D one 8 x 8
-// plane, 2D four 16-cell rows, 1D 64 cells); inside a group the particles are
-// ordered level by level -- the first particle of every cell, in cell order,
-// then the second, ... -- so the lanes of a wave sit in distinct, neighbouring
-// cells (distinct LDS addresses for the deposit, few cache lines per gather).
+// LDS.  Each tile is split into groups of 64 cells, one per parity class of
+// the cell indices inside the tile (3D: 8 classes of 4 x 4 x 4 cells, 2D: 4
+// of 8 x 8, 1D: 2 of 64); inside a group the particles are ordered level by
+// level -- the first particle of every cell, in cell order, then the second,
+// ... -- so the lanes of a wave sit in distinct cells at least two apart along
+// some axis: the deposit stencils of one instruction never share a node.
 __host__ __device__ constexpr int ptile_ext(int D, int axis) {
   return axis >= D ? 1 : (D == 1 ? 128 : (D == 2 ? 16 : 8));
 }
@@ -110,8 +111,9 @@ constexpr int PT_GROUP = 64;        // cells per group
 constexpr int PT_LO = 2;            // window starts PT_LO nodes below the tile
 constexpr int PT_PAD = 5;           // window = tile + PT_PAD nodes per present axis
 constexpr int SORT_CHUNK = 4096;    // particles per block-sized piece of a tile
-constexpr int SORT_GMAX = 16384;    // larger groups are copied without the level order
-constexpr int SORT_LMAX = 2048;     // (or with more than this many particles in one cell)
+constexpr int SPARSE_CHUNK = 128;   // pieces this small skip the LDS windows
+constexpr int SORT_LMAX = 256;      // a group with more particles in one cell keeps its
+                                    // scatter order (still sorted by group)
 // LDS deposit in 64-bit fixed point: a contribution v (|v| <= max |kq|) is
 // added as trunc(v * jscale) with jscale = 2^40 / 2^ceil(log2 max |kq|), so a
 // node's sum over one chunk stays below 2^52; the sum is exact and does not
@@ -188,6 +190,8 @@ struct Inst {
   const uint32_t* mcell;        // packed cell of each material cell (neutral / ppc)
   const TabHdr* tab[MAXMAT];
   float acut[MAXMAT];
+  float acut_min;               // smallest cut over the materials
+  int* hot;                     // [step & 1]: some node's amplitude reached acut_min
   unsigned long long* nevents;  // per material
   uint64_t seed;
   // control

@@ -32,6 +32,15 @@ __device__ __forceinline__ int find_inst(const Group& g) {
   return lo;
 }
 
+// Workgroups are dispatched to the 8 XCDs (each with its own L2) round robin,
+// block b going to XCD b mod 8.  Work index of block b of nb such that every
+// XCD walks a contiguous range of the work (neighbouring tiles share halo
+// lines in one L2).  A bijection of [0, nb).
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = b & 7, s = b >> 3;
+  return x * q + (x < r ? x : r) + s;
+}
+
 __device__ __forceinline__ int wrapi(int j, int n, int per) {
   if (!per) return j;
   return j < 0 ? j + n : (j >= n ? j - n : j);
@@ -358,9 +367,13 @@ struct FWin {
   static constexpr int N = X * Y * Z;
 };
 
-// threads per block of the push: the 3D windows (current and fields) take
-// most of a CU's LDS, so one larger block per CU shares them
-__host__ __device__ constexpr int push_tpb(int D) { return D == 3 ? 512 : 256; }
+// Push configuration per dimension: threads per block, and whether the tile's
+// field window is staged in LDS (else in-tile particles gather from HBM
+// through the caches).  In 3D the two windows (85 KB) take most of a CU's LDS,
+// so one block of 16 waves per CU shares them (measured: 1024 threads 544 us,
+// 512 646 us, 256 without the field window 735 us on the 3D stress push).
+__host__ __device__ constexpr int push_tpb(int D) { return D == 3 ? 1024 : 256; }
+__host__ __device__ constexpr bool push_stage_fields(int D) { return true; }
 
 template <int ORDER>
 __device__ __forceinline__ void make_axis_l(Axis<ORDER>& a, int c, float t, int origin, int stride) {
@@ -377,20 +390,22 @@ template <int D, int ORDER>
 __device__ __forceinline__ float gather_l(const float* __restrict__ S, const Axis<ORDER>& X,
                                           const Axis<ORDER>& Y, const Axis<ORDER>& Z, int hx, int hy,
                                           int hz) {
+  // the window's rows are consecutive nodes, so only the first node of each
+  // axis is needed: every other stencil point is a constant offset from it
   constexpr int SY = D >= 2 ? ORDER + 1 : 1;
   constexpr int SZ = D >= 3 ? ORDER + 1 : 1;
   constexpr int SX = ORDER + 1;
-  const int ox = hx ? X.oh[0] : X.on[0];
+  constexpr int LY = FWin<D>::X, LZ = FWin<D>::X * FWin<D>::Y;
+  const float* __restrict__ r0 = S + (hx ? X.oh[0] : X.on[0]) + (D >= 2 ? (hy ? Y.oh[0] : Y.on[0]) : 0) +
+                                 (D >= 3 ? (hz ? Z.oh[0] : Z.on[0]) : 0);
   float acc = 0.0f;
 #pragma unroll
   for (int c = 0; c < SZ; ++c) {
     const float wz = D >= 3 ? (hz ? Z.wh[c] : Z.wn[c]) : 1.0f;
-    const int oz = D >= 3 ? (hz ? Z.oh[c] : Z.on[c]) : 0;
 #pragma unroll
     for (int b = 0; b < SY; ++b) {
       const float wy = D >= 2 ? (hy ? Y.wh[b] : Y.wn[b]) : 1.0f;
-      const int oy = D >= 2 ? (hy ? Y.oh[b] : Y.on[b]) : 0;
-      const float* r = S + (ox + oy + oz);
+      const float* r = r0 + b * LY + c * LZ;
       float row = 0.0f;
 #pragma unroll
       for (int a = 0; a < SX; ++a) row += (hx ? X.wh[a] : X.wn[a]) * r[a];
@@ -403,7 +418,7 @@ __device__ __forceinline__ float gather_l(const float* __restrict__ S, const Axi
 // Boris, move, deposit and write-back of one charged particle.  LOCAL: the
 // particle started inside the block's tile -- fields from the LDS window
 // (origin fx0, fy0, fz0), current into the LDS sink; else HBM for both.
-template <int D, int ORDER, bool LOCAL>
+template <int D, int ORDER, bool LOCAL, bool LF = LOCAL && push_stage_fields(D)>
 __device__ __forceinline__ void push_body(const Inst& I, const PushFields& f, const float* sF, int fx0,
                                           int fy0, int fz0, const GSink& gs, const LSink<D>& ls,
                                           unsigned q, uint8_t kind, int ci, int cj, int ck, float t0,
@@ -412,7 +427,7 @@ __device__ __forceinline__ void push_body(const Inst& I, const PushFields& f, co
   float ex, ey, ez, bx, by, bz;
   {
     Axis<ORDER> X, Y, Z;
-    if (LOCAL) {
+    if (LF) {
       constexpr int N = FWin<D>::N;
       make_axis_l<ORDER>(X, ci, t0, fx0, 1);
       if (D >= 2) make_axis_l<ORDER>(Y, cj, t1, fy0, FWin<D>::X);
@@ -543,7 +558,7 @@ template <int D, int ORDER>
 __global__ __launch_bounds__(push_tpb(D)) void k_push(Group g) {
   constexpr int NT = push_tpb(D);
   __shared__ unsigned long long sJ[3 * PWin<D>::N];
-  __shared__ float sF[6 * FWin<D>::N];
+  __shared__ float sF[push_stage_fields(D) ? 6 * FWin<D>::N : 1];
   const int ii = find_inst(g);
   const Inst& I = g.insts[ii];
   const int nb = g.off[ii + 1] - g.off[ii];
@@ -559,8 +574,18 @@ __global__ __launch_bounds__(push_tpb(D)) void k_push(Group g) {
   nsorted = nsorted < count ? nsorted : count;
   const int nchunks = I.sctl[SC_NCHUNKS];
   const int64_t ncell = (int64_t)I.Px * I.Py * I.Pz;
-  for (int u = b0; u < nchunks; u += nb) {
-    const int4 ch = I.chunks[u];
+  for (int v = b0; v < nchunks; v += nb) {
+    // the same XCD keeps neighbouring chunks: nb is a multiple of 8, so the
+    // XCD of work item v is v mod 8 whatever the round
+    const int4 ch = I.chunks[(nb & 7) ? v : xcd_remap(v, nchunks)];
+    if (ch.z - ch.y <= SPARSE_CHUNK) {
+      // a sparse piece (one pass of the block): HBM atomics cost less than
+      // staging and flushing the windows
+      const int end = ch.z < count ? ch.z : count;
+      const int p = ch.y + threadIdx.x;
+      push_one<D, ORDER, false>(I, f, sF, gs, LSink<D>{sJ, 0, 0, 0, 0.0}, 0, 0, 0, p, p < end);
+      continue;
+    }
     const int t = ch.x;
     const int tx0 = (t % I.ntile[0]) * ptile_ext(D, 0);
     const int ty0 = D >= 2 ? ((t / I.ntile[0]) % I.ntile[1]) * ptile_ext(D, 1) : 0;
@@ -570,7 +595,7 @@ __global__ __launch_bounds__(push_tpb(D)) void k_push(Group g) {
     for (int e = threadIdx.x; e < 3 * PWin<D>::N; e += NT) sJ[e] = 0ull;
     // field window: nodes tile - 1 .. tile + T + 1 (periodic axes wrapped;
     // nodes outside the padded arrays, never read, are zero)
-    for (int e = threadIdx.x; e < FWin<D>::N; e += NT) {
+    for (int e = threadIdx.x; push_stage_fields(D) && e < FWin<D>::N; e += NT) {
       const int a = e % FWin<D>::X;
       const int b = (e / FWin<D>::X) % FWin<D>::Y;
       const int c = e / (FWin<D>::X * FWin<D>::Y);
@@ -640,10 +665,14 @@ __device__ __forceinline__ void group_of(const Inst& I, uint32_t pc, int& g, int
   int t = i / TX;
   if (D >= 2) t += I.ntile[0] * (j / TY);
   if (D >= 3) t += I.ntile[0] * I.ntile[1] * (k / TZ);
-  const int lc = (i % TX) + TX * ((D >= 2 ? j % TY : 0) + TY * (D >= 3 ? k % TZ : 0));
+  // group = parity class of the cell inside its tile (x, y, z parities);
+  // cells of one class are at least two apart along some axis, so their
+  // deposit stencils never meet on the same node in the same instruction
+  const int il = i % TX, jl = D >= 2 ? j % TY : 0, kl = D >= 3 ? k % TZ : 0;
+  const int cls = (il & 1) | (D >= 2 ? (jl & 1) << 1 : 0) | (D >= 3 ? (kl & 1) << 2 : 0);
   constexpr int GPT = ptile_cells(D) / PT_GROUP;
-  g = (unsigned)t < (unsigned)I.ntiles ? t * GPT + lc / PT_GROUP : -1;   // -1 only for a corrupt cell
-  c = lc % PT_GROUP;
+  g = (unsigned)t < (unsigned)I.ntiles ? t * GPT + cls : -1;   // -1 only for a corrupt cell
+  c = (il >> 1) + (TX / 2) * ((jl >> 1) + (TY > 1 ? TY / 2 : 1) * (kl >> 1));
 }
 
 // Adds 1 to arr[t] for every lane with t >= 0, one atomic per distinct t of
@@ -676,7 +705,9 @@ __global__ __launch_bounds__(TPB) void k_sort_count(Group g) {
   count = count < I.capacity ? count : I.capacity;
   const int loose = count - I.sctl[SC_NSORTED];
   const int drift = I.sctl[SC_NDRIFT];
-  const int lo = count >> 5, dr = count >> 6;
+  // births since the sort (unsorted tail) above 1/32 of the slots, or
+  // drifter-steps (per step, a particle deposited outside its tile) above 1/16
+  const int lo = count >> 5, dr = count >> 4;
   const int go = loose > (lo > 256 ? lo : 256) || drift > (dr > 256 ? dr : 256);
   if (b0 == 0 && threadIdx.x == 0) I.sctl[SC_GO] = go;
   if (!go) return;
@@ -689,8 +720,12 @@ __global__ __launch_bounds__(TPB) void k_sort_count(Group g) {
   }
 }
 
+constexpr int SCAN_TPB = 1024;
+
+
 template <int D>
-__global__ __launch_bounds__(TPB) void k_sort_scan(Group g) {
+__global__ __launch_bounds__(SCAN_TPB) void k_sort_scan(Group g) {
+  constexpr int TPB = SCAN_TPB;
   __shared__ long long sp[TPB], sc[TPB];
   const int ii = find_inst(g);
   const Inst& I = g.insts[ii];
@@ -789,69 +824,122 @@ __device__ __forceinline__ void sort_move(const Inst& I, int from, int to) {
   I.pu2[to] = I.su2[from];
 }
 
-// One block per group (grid-stride): rank of every particle inside its cell
-// (LDS counters), the bit mask of the cells still holding a particle at each
-// level, and the level-order slot: first slot of the level + cells before it
-// in the level.
+// One wave per group (grid-stride over the groups, no block barriers): count
+// the particles of every cell (LDS counters, one lane per cell), the bit mask
+// of the cells still holding a particle at each level, then each particle's
+// rank inside its cell from a second round of counters and its level-order
+// slot: first slot of the level + cells of the level before its own.  (Any
+// rank order inside a cell is as good as another.)  The permutation is applied
+// one array at a time through LDS, so HBM sees coalesced reads and writes.
+constexpr int SORT_GWAVE = 2048;   // particles of a group reordered through LDS
+
+template <int D, class T>
+__device__ __forceinline__ void permute_array(const T* __restrict__ src, T* __restrict__ dst, int n,
+                                              const unsigned short* pos, T* buf, int lane) {
+  for (int q = lane; q < n; q += 64) buf[pos[q]] = src[q];
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  for (int q = lane; q < n; q += 64) dst[q] = buf[q];
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 template <int D>
 __global__ __launch_bounds__(TPB) void k_sort_group(Group g) {
-  __shared__ unsigned cnt[PT_GROUP];
-  __shared__ unsigned long long lmask[SORT_LMAX];
-  __shared__ unsigned lbase[SORT_LMAX];
-  __shared__ unsigned short rank[SORT_GMAX];
-  __shared__ unsigned smax;
+  constexpr int WPB = TPB / 64;
+  __shared__ unsigned cnt[WPB][PT_GROUP];
+  __shared__ unsigned long long lmask[WPB][SORT_LMAX];
+  __shared__ unsigned lbase[WPB][SORT_LMAX];
+  __shared__ unsigned short spos[WPB][SORT_GWAVE];
+  __shared__ unsigned sbuf[WPB][SORT_GWAVE];
   const int ii = find_inst(g);
   const Inst& I = g.insts[ii];
   if (!I.sctl[SC_GO]) return;
   const int nb = g.off[ii + 1] - g.off[ii];
   const int b0 = blockIdx.x - g.off[ii];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int ngr = I.ntiles * (ptile_cells(D) / PT_GROUP);
-  for (int gi = b0; gi < ngr; gi += nb) {
+  auto sync_wave = [] {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  };
+  for (int gi = b0 * WPB + w; gi < ngr; gi += nb * WPB) {
     const int n = I.gn[gi];
     if (n == 0) continue;
     const int s0 = I.gstart[gi];
-    if (n > SORT_GMAX) {
-      for (int q = threadIdx.x; q < n; q += TPB) sort_move<D>(I, s0 + q, s0 + q);
+    cnt[w][lane] = 0;
+    sync_wave();
+    // four particles per lane per round keep several loads and atomics in flight
+    for (int q0 = lane; q0 < n; q0 += 256) {
+      int c[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        int gr;
+        c[k] = -1;
+        if (q0 + 64 * k < n) group_of<D>(I, I.scell[s0 + q0 + 64 * k], gr, c[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (c[k] >= 0) atomicAdd(&cnt[w][c[k]], 1u);
+    }
+    sync_wave();
+    const unsigned mine = cnt[w][lane];
+    unsigned levels = mine;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) levels = max(levels, (unsigned)__shfl_xor((int)levels, o));
+    if (levels > SORT_LMAX) {   // a crowded cell: keep the group as scattered
+      for (int q = lane; q < n; q += 64) sort_move<D>(I, s0 + q, s0 + q);
       continue;
     }
-    if (threadIdx.x < PT_GROUP) cnt[threadIdx.x] = 0;
-    if (threadIdx.x == 0) smax = 0;
-    __syncthreads();
-    for (int q = threadIdx.x; q < n; q += TPB) {
-      int gr, c;
-      group_of<D>(I, I.scell[s0 + q], gr, c);
-      rank[q] = (unsigned short)atomicAdd(&cnt[c], 1u);
+    unsigned acc = 0;
+    for (unsigned l = 0; l < levels; ++l) {
+      const unsigned long long m = __ballot(mine > l);
+      if (lane == 0) {
+        lmask[w][l] = m;
+        lbase[w][l] = acc;
+      }
+      acc += __popcll(m);
     }
-    __syncthreads();
-    if (threadIdx.x < PT_GROUP) atomicMax(&smax, cnt[threadIdx.x]);
-    __syncthreads();
-    const unsigned levels = smax;
-    if (levels > SORT_LMAX) {
-      for (int q = threadIdx.x; q < n; q += TPB) sort_move<D>(I, s0 + q, s0 + q);
-      __syncthreads();
-      continue;
-    }
-    if (threadIdx.x < 64) {   // wave 0: one lane per cell
-      const unsigned mine = cnt[threadIdx.x];
-      unsigned acc = 0;
-      for (unsigned l = 0; l < levels; ++l) {
-        const unsigned long long m = __ballot(mine > l);
-        if (threadIdx.x == 0) {
-          lmask[l] = m;
-          lbase[l] = acc;
-        }
-        acc += __popcll(m);
+    cnt[w][lane] = 0;
+    sync_wave();
+    const bool staged = n <= SORT_GWAVE;
+    for (int q0 = lane; q0 < n; q0 += 256) {
+      int c[4];
+      unsigned l[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        int gr;
+        c[k] = -1;
+        if (q0 + 64 * k < n) group_of<D>(I, I.scell[s0 + q0 + 64 * k], gr, c[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (c[k] >= 0) l[k] = atomicAdd(&cnt[w][c[k]], 1u);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (c[k] < 0) continue;
+        const int pos = (int)lbase[w][l[k]] + __popcll(lmask[w][l[k]] & ((1ull << c[k]) - 1ull));
+        if (staged) spos[w][q0 + 64 * k] = (unsigned short)pos;
+        else sort_move<D>(I, s0 + q0 + 64 * k, s0 + pos);
       }
     }
-    __syncthreads();
-    for (int q = threadIdx.x; q < n; q += TPB) {
-      int gr, c;
-      group_of<D>(I, I.scell[s0 + q], gr, c);
-      const unsigned l = rank[q];
-      const int pos = (int)lbase[l] + __popcll(lmask[l] & ((1ull << c) - 1ull));
-      sort_move<D>(I, s0 + q, s0 + pos);
+    sync_wave();
+    if (staged) {
+      unsigned* buf = sbuf[w];
+      const unsigned short* ps = spos[w];
+      permute_array<D>(I.scell + s0, I.pcell + s0, n, ps, buf, lane);
+      permute_array<D>(reinterpret_cast<const unsigned*>(I.so0) + s0, reinterpret_cast<unsigned*>(I.po0) + s0, n, ps, buf, lane);
+      if (D >= 2) permute_array<D>(reinterpret_cast<const unsigned*>(I.so1) + s0, reinterpret_cast<unsigned*>(I.po1) + s0, n, ps, buf, lane);
+      if (D >= 3) permute_array<D>(reinterpret_cast<const unsigned*>(I.so2) + s0, reinterpret_cast<unsigned*>(I.po2) + s0, n, ps, buf, lane);
+      permute_array<D>(reinterpret_cast<const unsigned*>(I.su0) + s0, reinterpret_cast<unsigned*>(I.pu0) + s0, n, ps, buf, lane);
+      permute_array<D>(reinterpret_cast<const unsigned*>(I.su1) + s0, reinterpret_cast<unsigned*>(I.pu1) + s0, n, ps, buf, lane);
+      permute_array<D>(reinterpret_cast<const unsigned*>(I.su2) + s0, reinterpret_cast<unsigned*>(I.pu2) + s0, n, ps, buf, lane);
+      // kinds are bytes: move them through the same buffer one per word
+      for (int q = lane; q < n; q += 64) buf[ps[q]] = I.skind[s0 + q];
+      sync_wave();
+      for (int q = lane; q < n; q += 64) I.pkind[s0 + q] = (uint8_t)buf[q];
+      sync_wave();
     }
-    __syncthreads();
   }
   if (b0 == 0 && threadIdx.x == 0) {
     *I.pcount = I.sctl[SC_NSORTED];
@@ -962,9 +1050,10 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
   __shared__ float sB[3][NR];
   __shared__ unsigned sbx[RX], sby[RY], sbz[RZ];
   __shared__ int soy[RY], soz[RZ];
+  __shared__ int blk_hot;
   const int ii = find_inst(g);
   const Inst& I = g.insts[ii];
-  const int tb = blockIdx.x - g.off[ii];
+  const int tb = xcd_remap(blockIdx.x - g.off[ii], g.off[ii + 1] - g.off[ii]);
   const int Px = I.Px, Py = I.Py, Pz = I.Pz;
   const int ntx = (Px + T::X - 1) / T::X;
   const int nty = D >= 2 ? (Py + T::Y - 1) / T::Y : 1;
@@ -1001,6 +1090,7 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
   const float Cx = I.C[0], Cy = I.C[1], Cz = I.C[2];
   const int i0 = a0x - G, j0 = a0y - Gy, k0 = a0z - Gz;   // logical tile origin
 
+  if (threadIdx.x == 0) blk_hot = 0;
   // ---- per-axis tables
   for (int q = threadIdx.x; q < RX; q += TPB) {
     const int i = i0 + q - H;
@@ -1226,6 +1316,7 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
       prefix[w] = pre;
       const float a = slot + 1 < nwin ? fmaxf(suffix[(int64_t)(slot + 1) * wsz + w], pre) : pre;
       gp(I.A)[gi] = a;
+      if (a >= I.acut_min) blk_hot = 1;
       if (slot == nwin - 1) {   // block of samples complete: suffix maxima for the next
         float run = 0.0f;
         for (int q = nwin - 1; q >= 0; --q) {
@@ -1235,6 +1326,8 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
       }
     }
   }
+  __syncthreads();
+  if (threadIdx.x == 0 && blk_hot) atomicOr(I.hot + par, 1);
 }
 
 // ------------------------------------------------------------- ionization
@@ -1279,7 +1372,11 @@ __global__ __launch_bounds__(TPB) void k_ionize(Group g) {
   const int ii = find_inst(g);
   const Inst& I = g.insts[ii];
   const int step = g.step >= 0 ? g.step : *I.step;
-  const int64_t j0 = (int64_t)(blockIdx.x - g.off[ii]) * TPB;
+  // the flag of the next step is raised by its field update, which runs after
+  // this kernel; a cold grid (no amplitude at any cut) ionizes nothing
+  if (blockIdx.x == g.off[ii] && threadIdx.x == 0) I.hot[(step + 1) & 1] = 0;
+  if (!I.hot[step & 1]) return;
+  const int64_t j0 = (int64_t)xcd_remap(blockIdx.x - g.off[ii], g.off[ii + 1] - g.off[ii]) * TPB;
   const int64_t nneut = I.nneut;
   if (j0 >= nneut) return;
   const int64_t m0 = div_ppc(I, j0);
@@ -1545,7 +1642,7 @@ void launch_push(const Group& g, int D, int order, hipStream_t s) {
 }
 void launch_sort(const Group& gp, const Group& gscan, int D, hipStream_t s) {
   DISPATCH_D(D, hipLaunchKernelGGL((k_sort_count<DD>), dim3(gp.blocks), dim3(TPB), 0, s, gp));
-  DISPATCH_D(D, hipLaunchKernelGGL((k_sort_scan<DD>), dim3(gscan.blocks), dim3(TPB), 0, s, gscan));
+  DISPATCH_D(D, hipLaunchKernelGGL((k_sort_scan<DD>), dim3(gscan.blocks), dim3(SCAN_TPB), 0, s, gscan));
   DISPATCH_D(D, hipLaunchKernelGGL((k_sort_scatter<DD>), dim3(gp.blocks), dim3(TPB), 0, s, gp));
   DISPATCH_D(D, hipLaunchKernelGGL((k_sort_group<DD>), dim3(gp.blocks), dim3(TPB), 0, s, gp));
 }

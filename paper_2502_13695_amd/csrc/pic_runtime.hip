@@ -83,6 +83,7 @@ struct Ctr {
   unsigned health;
   unsigned done;
   int sctl[SC_WORDS];
+  int hot[2];
   unsigned long long nevents[MAXMAT];
   double acc[64];
 };
@@ -295,10 +296,11 @@ void enqueue_step(pic_ctx* c) {
 }
 
 // push and sort grid: persistent blocks (grid-stride over tile chunks and the
-// unsorted tail), sized by the slot capacity: 8 slots per thread, 16 .. 2048
+// unsorted tail), sized by the slot capacity: 8 slots per thread, 16 .. 2048,
+// a multiple of 8 (the XCD count, so a work item keeps its XCD every round)
 int push_blocks(int64_t capacity) {
   const int64_t nb = (capacity + TPB * 8 - 1) / (TPB * 8);
-  return (int)std::max<int64_t>(16, std::min<int64_t>(nb, 2048));
+  return (int)((std::max<int64_t>(16, std::min<int64_t>(nb, 2048)) + 7) / 8 * 8);
 }
 
 // padded index of logical (i, j, k)
@@ -569,6 +571,7 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
   c->d_ctr = (Ctr*)devp(c, L.o_ctr);
   I.pcount = &c->d_ctr->pcount;
   I.sctl = c->d_ctr->sctl;
+  I.hot = c->d_ctr->hot;
   I.step = &c->d_ctr->step;
   I.health = &c->d_ctr->health;
   I.nevents = c->d_ctr->nevents;
@@ -590,6 +593,8 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
     I.tab[m] = (const TabHdr*)devp(c, L.o_tab[m]);
     I.acut[m] = c->tabs[m].acut;
   }
+  I.acut_min = 3.0e38f;
+  for (int m = 0; m < K.nmat; ++m) I.acut_min = std::min(I.acut_min, I.acut[m]);
   // fixed-point scale of the LDS deposit: 2^JFIX_BITS per 2^ceil(log2 max |kq|)
   float qmax = 0.0f;
   for (int kd = 0; kd < 2 * K.nmat; ++kd)
@@ -753,6 +758,7 @@ pic_status pic_autotune(pic_ctx* c, int32_t reps) {
   HIP_OK(hipMemsetAsync(devp(c, L.o_prefix), 0, sizeof(float) * L.wsz, s));
   HIP_OK(hipMemsetAsync(devp(c, L.o_A), 0, sizeof(float) * L.ncell, s));
   HIP_OK(hipMemsetAsync(&c->d_ctr->health, 0, sizeof(unsigned), s));
+  HIP_OK(hipMemsetAsync(c->d_ctr->hot, 0, sizeof(c->d_ctr->hot), s));
   HIP_OK(hipStreamSynchronize(s));
   return PIC_OK;
 }
@@ -1091,7 +1097,7 @@ static pic_status batch_rebuild(pic_batch* b) {
   // persistent push/sort blocks: shared out over the members (every member
   // keeps at least 16; its grid-stride loops cover any particle count)
   const int nmem = (int)b->members.size();
-  const int push_share = std::max(16, 8192 / std::max(1, nmem));
+  const int push_share = std::max(16, 8192 / std::max(1, nmem)) / 8 * 8;
   for (auto& cl : b->classes) {
     cl.n = (int)cl.ms.size();
     std::vector<Inst> hi(cl.n);
