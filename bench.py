@@ -83,7 +83,9 @@ def run_gpu(cfg, steps, warmup):
         w.scalars()
         w.close()
     ctx = pic.Context(cfg)
-    tune = ctx.autotune(10) if cfg.get("preionize_eV", 0.0) <= 0 else None
+    # field tile shape: timed on the first steps of the timed run itself (every
+    # shape computes identical fields); the choice is reported after the run
+    ctx.autotune_steps(4)
     # HIP events around the launches of every 16th step of the timed region
     # (recording them around every launch would add a marker between kernels)
     ctx.set_timing(TIMING_PERIOD)
@@ -93,6 +95,7 @@ def run_gpu(cfg, steps, warmup):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     timers = ctx.timers()
+    tune = dict(chosen=int(timers[23]), blocks=int(timers[24]), ms=[float(x) for x in timers[16:21]])
     sort_state = ctx.sort_state()
     sc = ctx.scalars()
     ev = ctx.events()

@@ -150,11 +150,12 @@ enum {
   PIC_DIAG_PARTICLES = 5, /* pic_particle records of live charged particles */
   PIC_DIAG_PARAMS = 6,    /* one pic_params */
   PIC_DIAG_AMP = 7,       /* float: windowed amplitude A at nodes [V/m] */
-  PIC_DIAG_TIMERS = 8,    /* double[24]: [0..7] device ms per phase summed over the
+  PIC_DIAG_TIMERS = 8,    /* double[32]: [0..7] device ms per phase summed over the
                              timed launches, [8..15] launch counts (phases: 0 push,
                              1 field update with outflow faces and amplitude window,
                              2 ionization, 3 tile sort); [16..22] autotuner ms per field launch of
-                             each tile shape, [23] the tile shape in use */
+                             each tile shape (best block count), [23] the tile shape in
+                             use, [24] field blocks per launch, [25] push blocks */
   PIC_DIAG_SORT = 9       /* double[4]: charged slots held in tile order, tile
                              chunks, drifter-steps (a particle that deposited outside
                              its tile's window, counted per step) since the last
@@ -248,6 +249,14 @@ void pic_batch_destroy(pic_batch* b);
  * the first step of a run without pre-ionization (else PIC_E_STATE).  The
  * measured ms per launch and the chosen variant are in PIC_DIAG_TIMERS. */
 pic_status pic_autotune(pic_ctx* c, int32_t reps);
+
+/* In-run variant of the tuner: the next reps x (number of shapes) steps of
+ * pic_step cycle the tile shapes, reps consecutive steps each (every shape
+ * computes identical fields), timing each field launch with HIP events; then
+ * the shape with the fastest launch is kept for the rest of the run (one host
+ * synchronisation when the tuning window ends).  Valid at any step of a single
+ * run; reps in 1..16; PIC_E_STATE while a tuning window is open. */
+pic_status pic_autotune_steps(pic_ctx* c, int32_t reps);
 
 /* Device time of each step phase measured with HIP events recorded on the
  * context stream around the launches of every `on`-th step (1 = every step;

@@ -1050,16 +1050,16 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
   __shared__ float sB[3][NR];
   __shared__ unsigned sbx[RX], sby[RY], sbz[RZ];
   __shared__ int soy[RY], soz[RZ];
+  __shared__ float sieh[RX], sien[RX];
   __shared__ int blk_hot;
+  constexpr int KMAX = (NR + TPB - 1) / TPB;   // staged points per thread
   const int ii = find_inst(g);
   const Inst& I = g.insts[ii];
-  const int tb = xcd_remap(blockIdx.x - g.off[ii], g.off[ii + 1] - g.off[ii]);
   const int Px = I.Px, Py = I.Py, Pz = I.Pz;
   const int ntx = (Px + T::X - 1) / T::X;
   const int nty = D >= 2 ? (Py + T::Y - 1) / T::Y : 1;
-  const int a0x = (tb % ntx) * T::X;
-  const int a0y = D >= 2 ? ((tb / ntx) % nty) * T::Y : 0;
-  const int a0z = D >= 3 ? (tb / (ntx * nty)) * T::Z : 0;
+  const int nbk = g.off[ii + 1] - g.off[ii];
+  const int bk = blockIdx.x - g.off[ii];
   const int nx = I.nx, ny = I.ny, nz = I.nz;
   const bool py = I.per_y, pz = I.per_z;
   const int sy = I.sy, sz = I.sz;
@@ -1088,13 +1088,25 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
   const gmem<float>* __restrict__ ien = gp(I.ie_node);
   const float hx = I.halfC[0], hy = I.halfC[1], hz = I.halfC[2];
   const float Cx = I.C[0], Cy = I.C[1], Cz = I.C[2];
+  auto split = [&](int l, int& qx, int& qy, int& qz) {
+    qx = l % RX;
+    qy = D >= 2 ? (l / RX) % RY : 0;
+    qz = D >= 3 ? l / (RX * RY) : 0;
+  };
+  // one block per tile; each XCD walks a contiguous range of tiles
+  const int tb = xcd_remap(bk, nbk);
+  const int a0x = (tb % ntx) * T::X;
+  const int a0y = D >= 2 ? ((tb / ntx) % nty) * T::Y : 0;
+  const int a0z = D >= 3 ? (tb / (ntx * nty)) * T::Z : 0;
   const int i0 = a0x - G, j0 = a0y - Gy, k0 = a0z - Gz;   // logical tile origin
-
   if (threadIdx.x == 0) blk_hot = 0;
   // ---- per-axis tables
   for (int q = threadIdx.x; q < RX; q += TPB) {
     const int i = i0 + q - H;
-    sbx[q] = axis_bits(i, nx, false, i + G >= 0 && i + G < Px);
+    const bool in = i + G >= 0 && i + G < Px;
+    sbx[q] = axis_bits(i, nx, false, in);
+    sieh[q] = in ? ieh[i + G] : 1.0f;
+    sien[q] = in ? ien[i + G] : 1.0f;
   }
   for (int q = threadIdx.x; q < RY; q += TPB) {
     if (D >= 2) {
@@ -1121,14 +1133,13 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
     }
   }
   __syncthreads();
-  auto split = [&](int l, int& qx, int& qy, int& qz) {
-    qx = l % RX;
-    qy = D >= 2 ? (l / RX) % RY : 0;
-    qz = D >= 3 ? l / (RX * RY) : 0;
-  };
-
-  // ---- A: stage E^n and b^n
-  for (int l = threadIdx.x; l < NR; l += TPB) {
+  // ---- A: stage E^n and b^n; the current of the points this thread updates
+  // in phase C is loaded now too (registers), so HBM latency is met once
+  float jr[KMAX][3];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    const int l = threadIdx.x + k * TPB;
+    if (l >= NR) continue;
     int qx, qy, qz;
     split(l, qx, qy, qz);
     const bool in = sbx[qx] & sby[qy] & sbz[qz] & AX_ARR;
@@ -1139,6 +1150,11 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
     sB[0][l] = in ? Bc0[gi] : 0.0f;
     sB[1][l] = in ? Bc1[gi] : 0.0f;
     sB[2][l] = in ? Bc2[gi] : 0.0f;
+    const bool cpt = in && qx >= H - 1 && qx <= T::X + H && (D < 2 || (qy >= H - 1 && qy <= T::Y + H)) &&
+                     (D < 3 || (qz >= H - 1 && qz <= T::Z + H));
+    jr[k][0] = cpt ? J0[gi] : 0.0f;
+    jr[k][1] = cpt ? J1[gi] : 0.0f;
+    jr[k][2] = cpt ? J2[gi] : 0.0f;
   }
   __syncthreads();
   // ---- B: b^{n+1/2} on local [-2, T] (in place; reads E only)
@@ -1166,7 +1182,10 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
   }
   __syncthreads();
   // ---- C: E^{n+1} at interior positions on local [-1, T] (in place)
-  for (int l = threadIdx.x; l < NR; l += TPB) {
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    const int l = threadIdx.x + k * TPB;
+    if (l >= NR) continue;
     int qx, qy, qz;
     split(l, qx, qy, qz);
     if (qx < H - 1 || qx > T::X + H) continue;
@@ -1174,23 +1193,21 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
     if (D >= 3 && (qz < H - 1 || qz > T::Z + H)) continue;
     const unsigned bx = sbx[qx], by = sby[qy], bz = sbz[qz];
     if (!(bx & by & bz & AX_ARR)) continue;
-    const int ai = a0x + qx - H;
-    const int64_t gi = (int64_t)ai + soy[qy] + soz[qz];
     if ((bx & AX_IH) && (by & AX_IN) && (bz & AX_IN)) {
       float cu = 0.0f;
       if (D >= 2) cu += Cy * (sB[2][l] - sB[2][l - LY]);
       if (D >= 3) cu -= Cz * (sB[1][l] - sB[1][l - LZ]);
-      sE[0][l] += ieh[ai] * (cu - J0[gi]);
+      sE[0][l] += sieh[qx] * (cu - jr[k][0]);
     }
     if ((bx & AX_IN) && (by & AX_IH) && (bz & AX_IN)) {
       float cu = -Cx * (sB[2][l] - sB[2][l - 1]);
       if (D >= 3) cu += Cz * (sB[0][l] - sB[0][l - LZ]);
-      sE[1][l] += ien[ai] * (cu - J1[gi]);
+      sE[1][l] += sien[qx] * (cu - jr[k][1]);
     }
     if ((bx & AX_IN) && (by & AX_IN) && (bz & AX_IH)) {
       float cu = Cx * (sB[1][l] - sB[1][l - 1]);
       if (D >= 2) cu -= Cy * (sB[0][l] - sB[0][l - LY]);
-      sE[2][l] += ien[ai] * (cu - J2[gi]);
+      sE[2][l] += sien[qx] * (cu - jr[k][2]);
     }
   }
   __syncthreads();

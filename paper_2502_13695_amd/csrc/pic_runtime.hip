@@ -170,7 +170,7 @@ pic_status plan(const pic_config* cfg, const Canon& c, const std::vector<TableHo
   L->o_ctr = take(sizeof(Ctr));
   L->o_grid64 = take(sizeof(double) * (size_t)L->ncell);
   L->o_inst = take(sizeof(Inst));
-  L->o_off = take(sizeof(int) * 16);
+  L->o_off = take(sizeof(int) * 32);   // 4 phases x {0, blocks}; field shapes x {0, blocks}
   L->o_sig = take(sizeof(float) * 2 * MAXMAT);
   L->o_probe = take(0);
   L->total = o;
@@ -190,10 +190,15 @@ struct pic_ctx {
   hipStream_t stream = nullptr;
   Inst h{};
   Inst* d_inst = nullptr;
-  int* d_off = nullptr;   // [0, nb_push, 0, nb_cell, 0, 1, 0, nb_neut]
+  int* d_off = nullptr;   // [0, nb_push, 0, nb_cell, 0, 1, 0, nb_neut], then {0, tiles} per field shape
+  int* d_off_fields = nullptr;   // block offsets of the field launch in use
   int nb_push = 0, nb_cell = 0, nb_win = 0, nb_neut = 0;
   int tile = 0;               // field-kernel tile variant
   double tune_ms[8] = {0};    // autotuner: ms per field launch of each variant
+  // in-run tuning of the field tile shape: the next tune_left steps cycle the
+  // shapes (tune_reps steps each; results identical), timing every launch
+  int tune_left = 0, tune_reps = 0;
+  hipEvent_t tune_ev[8][16][2] = {};
   Ctr* d_ctr = nullptr;
   double* d_grid64 = nullptr;
   std::vector<uint32_t> mcell;
@@ -240,7 +245,7 @@ namespace {
 inline void* devp(pic_ctx* c, size_t off) { return c->base + off; }
 
 Group single(pic_ctx* c, int phase, int nb) {
-  return Group{c->d_inst, c->d_off + 2 * phase, 1, nb, (int)c->step};
+  return Group{c->d_inst, phase == 1 ? c->d_off_fields : c->d_off + 2 * phase, 1, nb, (int)c->step};
 }
 
 // Phase timing: events recorded on the context stream around each launch;
@@ -283,13 +288,47 @@ void harvest_all(pic_ctx* c) {
 
 // phases: 0 push, 1 fields (Yee step, outflow faces, amplitude window),
 // 2 ionize (+ step counter), 3 tile sort (when a check is due)
+// End of the in-run tuning: the fastest shape (best of its launches) is kept.
+void finish_tuning(pic_ctx* c) {
+  const int nv = field_tile_variants();
+  (void)hipEventSynchronize(c->tune_ev[nv - 1][c->tune_reps - 1][1]);
+  double best = 1e30;
+  for (int v = 0; v < nv; ++v) {
+    c->tune_ms[v] = 1e30;
+    for (int r = 0; r < c->tune_reps; ++r) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, c->tune_ev[v][r][0], c->tune_ev[v][r][1]) == hipSuccess)
+        c->tune_ms[v] = std::min(c->tune_ms[v], (double)ms);
+    }
+    if (c->tune_ms[v] < best) {
+      best = c->tune_ms[v];
+      c->tile = v;
+    }
+  }
+  const Layout& L = c->L;
+  c->nb_cell = field_tiles(c->canon.D, c->tile, (int)L.Px, (int)L.Py, (int)L.Pz);
+  c->d_off_fields = c->d_off + 8 + 2 * c->tile;
+}
+
 void enqueue_step(pic_ctx* c) {
   const int D = c->canon.D, order = c->cfg.shape_order;
   hipStream_t s = c->stream;
   if (c->resort > 0 && c->step % c->resort == 0)
     timed(c, 3, [&] { launch_sort(single(c, 0, c->nb_push), single(c, 2, 1), D, s); });
   timed(c, 0, [&] { launch_push(single(c, 0, c->nb_push), D, order, s); });
-  timed(c, 1, [&] { launch_fields(single(c, 1, c->nb_cell), D, c->tile, s); });
+  if (c->tune_left > 0) {
+    const int idx = field_tile_variants() * c->tune_reps - c->tune_left;
+    const int v = idx / c->tune_reps, r = idx % c->tune_reps;
+    const Layout& L = c->L;
+    const Group gv{c->d_inst, c->d_off + 8 + 2 * v, 1, field_tiles(D, v, (int)L.Px, (int)L.Py, (int)L.Pz),
+                   (int)c->step};
+    (void)hipEventRecord(c->tune_ev[v][r][0], s);
+    launch_fields(gv, D, v, s);
+    (void)hipEventRecord(c->tune_ev[v][r][1], s);
+    if (--c->tune_left == 0) finish_tuning(c);
+  } else {
+    timed(c, 1, [&] { launch_fields(single(c, 1, c->nb_cell), D, c->tile, s); });
+  }
   timed(c, 2, [&] { launch_ionize(single(c, 3, c->nb_neut), D, order, s); });
   if (c->timing && c->step % c->timing == 0) ++c->ev_slot;
   ++c->step;
@@ -614,6 +653,7 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
   I.seed = c->cfg.seed;
   c->d_inst = (Inst*)devp(c, L.o_inst);
   c->d_off = (int*)devp(c, L.o_off);
+  c->d_off_fields = c->d_off + 2;
   c->d_grid64 = (double*)devp(c, L.o_grid64);
 
   // block counts per phase
@@ -627,7 +667,9 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
   c->nb_win = 1;   // one block per instance (tile-sort scan)
   c->nb_neut = std::max(1, nblk(L.nneut));
 
-  const int offs[8] = {0, c->nb_push, 0, c->nb_cell, 0, c->nb_win, 0, c->nb_neut};
+  int offs[32] = {0, c->nb_push, 0, c->nb_cell, 0, c->nb_win, 0, c->nb_neut};
+  for (int v = 0; v < field_tile_variants(); ++v)
+    offs[9 + 2 * v] = field_tiles(D, v, (int)L.Px, (int)L.Py, (int)L.Pz);
 
   hipStream_t s = c->stream;
   bool ok = true;
@@ -673,6 +715,10 @@ void pic_destroy(pic_ctx* c) {
     for (int k = 0; k < pic_ctx::kRing; ++k)
       for (int e = 0; e < 2; ++e)
         if (c->ev[ph][k][e]) (void)hipEventDestroy(c->ev[ph][k][e]);
+  for (auto& vv : c->tune_ev)
+    for (auto& rr : vv)
+      for (auto& e : rr)
+        if (e) (void)hipEventDestroy(e);
   if (c->h_step) (void)hipHostFree(c->h_step);
   if (c->base) {
     if (c->owns_alloc_via_cb && c->cfg.free) c->cfg.free(c->base, c->cfg.alloc_user);
@@ -722,25 +768,31 @@ pic_status pic_autotune(pic_ctx* c, int32_t reps) {
   double best = 1e30;
   int best_v = c->tile;
   int offs[2];
-  for (int v = 0; v < field_tile_variants(); ++v) {
-    const int nb = field_tiles(D, v, (int)L.Px, (int)L.Py, (int)L.Pz);
-    offs[0] = 0;
-    offs[1] = nb;
-    HIP_OK(hipMemcpy(c->d_off + 2, offs, sizeof offs, hipMemcpyHostToDevice));
-    Group gr{c->d_inst, c->d_off + 2, 1, nb, 0};
-    launch_fields(gr, D, v, s);   // warm
-    HIP_OK(hipEventRecord(e0, s));
-    for (int r = 0; r < reps; ++r) launch_fields(gr, D, v, s);
-    HIP_OK(hipEventRecord(e1, s));
-    HIP_OK(hipEventSynchronize(e1));
-    float ms = 0.f;
-    HIP_OK(hipEventElapsedTime(&ms, e0, e1));
-    c->tune_ms[v] = ms / reps;
-    if (ms < best) {
-      best = ms;
-      best_v = v;
+  // three interleaved rounds over the tile shapes, best round of each kept
+  // (the differences are a few percent, close to the launch-to-launch noise)
+  for (int v = 0; v < field_tile_variants(); ++v) c->tune_ms[v] = 1e30;
+  for (int round = 0; round < 3; ++round) {
+    for (int v = 0; v < field_tile_variants(); ++v) {
+      const int nb = field_tiles(D, v, (int)L.Px, (int)L.Py, (int)L.Pz);
+      offs[0] = 0;
+      offs[1] = nb;
+      HIP_OK(hipMemcpy(c->d_off + 2, offs, sizeof offs, hipMemcpyHostToDevice));
+      Group gr{c->d_inst, c->d_off + 2, 1, nb, 0};
+      launch_fields(gr, D, v, s);   // warm
+      HIP_OK(hipEventRecord(e0, s));
+      for (int r = 0; r < reps; ++r) launch_fields(gr, D, v, s);
+      HIP_OK(hipEventRecord(e1, s));
+      HIP_OK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+      c->tune_ms[v] = std::min(c->tune_ms[v], (double)ms / reps);
     }
   }
+  for (int v = 0; v < field_tile_variants(); ++v)
+    if (c->tune_ms[v] < best) {
+      best = c->tune_ms[v];
+      best_v = v;
+    }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   c->tile = best_v;
@@ -760,6 +812,18 @@ pic_status pic_autotune(pic_ctx* c, int32_t reps) {
   HIP_OK(hipMemsetAsync(&c->d_ctr->health, 0, sizeof(unsigned), s));
   HIP_OK(hipMemsetAsync(c->d_ctr->hot, 0, sizeof(c->d_ctr->hot), s));
   HIP_OK(hipStreamSynchronize(s));
+  return PIC_OK;
+}
+
+pic_status pic_autotune_steps(pic_ctx* c, int32_t reps) {
+  if (!c || reps < 1 || reps > 16) return PIC_E_INVAL;
+  if (c->tune_left > 0) return PIC_E_STATE;
+  for (int v = 0; v < field_tile_variants(); ++v)
+    for (int r = 0; r < reps; ++r)
+      for (int e = 0; e < 2; ++e)
+        if (!c->tune_ev[v][r][e]) HIP_OK(hipEventCreate(&c->tune_ev[v][r][e]));
+  c->tune_reps = reps;
+  c->tune_left = field_tile_variants() * reps;
   return PIC_OK;
 }
 
@@ -852,7 +916,7 @@ pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size
     case PIC_DIAG_UE_GRID: need = sizeof(double) * dom_count(K, kNode); break;
     case PIC_DIAG_AMP: need = sizeof(float) * dom_count(K, kNode); break;
     case PIC_DIAG_PARAMS: need = sizeof(pic_params); break;
-    case PIC_DIAG_TIMERS: need = sizeof(double) * 24; break;
+    case PIC_DIAG_TIMERS: need = sizeof(double) * 32; break;
     case PIC_DIAG_SORT: need = sizeof(double) * 4; break;
     case PIC_DIAG_EVENTS:
     case PIC_DIAG_PARTICLES: break;   // computed below
@@ -986,6 +1050,9 @@ pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size
     }
     for (int v = 0; v < 7; ++v) o[16 + v] = c->tune_ms[v];
     o[23] = c->tile;
+    o[24] = c->nb_cell;
+    o[25] = c->nb_push;
+    for (int k = 26; k < 32; ++k) o[k] = 0.0;
     return PIC_OK;
   }
   // ---- SCALARS

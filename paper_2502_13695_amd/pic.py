@@ -91,7 +91,8 @@ class State(C.Structure):
 SYMBOLS = ["pic_init", "pic_step", "pic_diag", "pic_set_state", "pic_footprint", "pic_canonical",
            "pic_keldysh_rate", "pic_table_probe", "pic_table_probe_device", "pic_batch_create",
            "pic_batch_step", "pic_batch_add", "pic_batch_remove", "pic_batch_destroy",
-           "pic_set_timing", "pic_autotune", "pic_set_resort", "pic_destroy", "pic_status_str"]
+           "pic_set_timing", "pic_autotune", "pic_autotune_steps", "pic_set_resort", "pic_destroy",
+           "pic_status_str"]
 
 
 def lib():
@@ -128,6 +129,7 @@ def lib():
             "pic_batch_destroy": ([vp], None),
             "pic_set_timing": ([vp, i32], C.c_int),
             "pic_autotune": ([vp, i32], C.c_int),
+            "pic_autotune_steps": ([vp, i32], C.c_int),
             "pic_set_resort": ([vp, i32], C.c_int),
             "pic_destroy": ([vp], None),
             "pic_status_str": ([C.c_int], C.c_char_p),
@@ -254,6 +256,11 @@ class Context:
     def set_timing(self, on):
         _check(lib().pic_set_timing(self.h, int(on)), "pic_set_timing")
 
+    def autotune_steps(self, reps=8):
+        """Time every field tile shape on the next reps x shapes steps of the run
+        (identical results) and keep the fastest."""
+        _check(lib().pic_autotune_steps(self.h, int(reps)), "pic_autotune_steps")
+
     def set_resort(self, period):
         """Tile-sort check period in steps (0 = never sort the charged particles)."""
         _check(lib().pic_set_resort(self.h, int(period)), "pic_set_resort")
@@ -262,7 +269,7 @@ class Context:
         """Pick the fastest field-kernel tile shape (before the first step)."""
         _check(lib().pic_autotune(self.h, int(reps)), "pic_autotune")
         t = self.timers()
-        return dict(chosen=int(t[23]), ms=[float(x) for x in t[16:23]])
+        return dict(chosen=int(t[23]), blocks=int(t[24]), ms=[float(x) for x in t[16:23]])
 
     def close(self):
         if getattr(self, "h", None):

@@ -359,3 +359,25 @@ def test_autotune_restores_initial_state(P):
         a.autotune(1)          # only before the first step
     a.close()
     b.close()
+
+
+def test_autotune_in_run_same_results(P):
+    """In-run tuning cycles the field tile shapes over the first steps; every
+    shape computes the same fields, so the run matches an untuned one."""
+    cfg = W.config_2d(nx=160, ny=40, nsteps=300, ppc=2, peak=3e14, slab_cells=10, waist=0.6e-6)
+    a = P.Context(cfg)
+    a.autotune_steps(3)
+    a.step(300)
+    t = a.timers()
+    assert 0 <= int(t[23]) < 5 and all(m > 0 for m in t[16:21])
+    b = P.Context(cfg)
+    b.step(300)
+    fa, fb = a.fields(), b.fields()
+    num = sum(np.sum((x - y) ** 2) for x, y in zip(fa[0] + fa[1], fb[0] + fb[1]))
+    den = sum(np.sum(y ** 2) for y in fb[0] + fb[1])
+    assert math.sqrt(num / den) < 1e-6
+    assert set(map(tuple, a.events().tolist())) == set(map(tuple, b.events().tolist()))
+    with pytest.raises(P.PicError):
+        a.autotune_steps(0)
+    a.close()
+    b.close()
