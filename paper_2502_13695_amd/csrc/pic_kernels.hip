@@ -1103,10 +1103,7 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
   // ---- per-axis tables
   for (int q = threadIdx.x; q < RX; q += TPB) {
     const int i = i0 + q - H;
-    const bool in = i + G >= 0 && i + G < Px;
-    sbx[q] = axis_bits(i, nx, false, in);
-    sieh[q] = in ? ieh[i + G] : 1.0f;
-    sien[q] = in ? ien[i + G] : 1.0f;
+    sbx[q] = axis_bits(i, nx, false, i + G >= 0 && i + G < Px);
   }
   for (int q = threadIdx.x; q < RY; q += TPB) {
     if (D >= 2) {
@@ -1155,6 +1152,13 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
     jr[k][0] = cpt ? J0[gi] : 0.0f;
     jr[k][1] = cpt ? J1[gi] : 0.0f;
     jr[k][2] = cpt ? J2[gi] : 0.0f;
+  }
+  // 1/eps per x (loads in flight with the staging)
+  for (int q = threadIdx.x; q < RX; q += TPB) {
+    const int ai = a0x + q - H;
+    const bool in = ai >= 0 && ai < Px;
+    sieh[q] = in ? ieh[ai] : 1.0f;
+    sien[q] = in ? ien[ai] : 1.0f;
   }
   __syncthreads();
   // ---- B: b^{n+1/2} on local [-2, T] (in place; reads E only)
