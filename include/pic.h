@@ -156,10 +156,16 @@ enum {
                              2 ionization, 3 tile sort); [16..22] autotuner ms per field launch of
                              each tile shape (best block count), [23] the tile shape in
                              use, [24] field blocks per launch, [25] push blocks */
-  PIC_DIAG_SORT = 9       /* double[4]: charged slots held in tile order, tile
+  PIC_DIAG_SORT = 9,      /* double[4]: charged slots held in tile order, tile
                              chunks, drifter-steps (a particle that deposited outside
                              its tile's window, counted per step) since the last
                              sort, sorts performed */
+  PIC_DIAG_REGION = 10    /* double[4]: charged region along x that the next step's
+                             field update uses (first and last cell that held a
+                             charged particle so far, together with the amplitude
+                             window's cells; lo > hi when empty), then the field
+                             tiles that read the current and the far tiles that
+                             skip it (see pic_set_far_tiles) */
 };
 
 /* PIC_DIAG_SCALARS layout (all double). */
@@ -258,12 +264,25 @@ pic_status pic_autotune(pic_ctx* c, int32_t reps);
  * run; reps in 1..16; PIC_E_STATE while a tuning window is open. */
 pic_status pic_autotune_steps(pic_ctx* c, int32_t reps);
 
-/* Device time of each step phase measured with HIP events recorded on the
- * context stream around the launches of every `on`-th step (1 = every step;
- * 0 = off, the default); no host synchronisation per step.  Phases: 0 push,
- * 1 field update, 2 ionization, 3 tile sort.  Switching resets the
- * accumulators. */
+/* Device time of each step phase measured with HIP events that the phase's
+ * own dispatches stamp (start of its first kernel, end of its last) on the
+ * stream it runs on, for one step in every `on` consecutive steps (1 = every
+ * step; 0 = off, the default); the sampled position inside each window of `on`
+ * steps advances by one per window, so a phase that runs every r steps with r
+ * dividing `on` (the tile sort check) is sampled in proportion.  No host synchronisation per
+ * step.  Phases: 0 push, 1 field update, 2 ionization, 3 tile sort.
+ * Switching resets the accumulators. */
 pic_status pic_set_timing(pic_ctx* c, int32_t on);
+
+/* Far field tiles (default on): the push tracks on the device every x cell
+ * that has held a charged particle at any step so far.  A field tile whose x
+ * column lies farther than 6 cells from all of them and from the amplitude
+ * window has carried no current at any step (a step's deposit stays within 3
+ * cells of the particle's cell), so its update neither reads nor clears the
+ * current: 48 instead of 72 bytes per cell.  Results are identical either way;
+ * on = 0 makes every tile read its current (for comparison).  Batches always
+ * skip. */
+pic_status pic_set_far_tiles(pic_ctx* c, int32_t on);
 
 /* Tile sort of the charged particles (the resort of the particle loop): every
  * `period` steps (default 8; 0 = never) the device checks whether births

@@ -124,6 +124,11 @@ constexpr int JFIX_BITS = 40;
 // deposited outside their tile's window since the sort (per step), [3] sort
 // decision, [4] sorts performed
 constexpr int SC_NSORTED = 0, SC_NCHUNKS = 1, SC_NDRIFT = 2, SC_GO = 3, SC_NSORTS = 4, SC_WORDS = 8;
+// Charged region along x: cells [lo, hi] that held a charged particle at some
+// step so far (never shrinks), in three rotating slots (step n reads slot n % 3,
+// its push extends slot (n + 1) % 3).  Field tiles farther than XNEAR_MARGIN
+// cells from it (and from the amplitude window) have carried no current, ever.
+constexpr int XNEAR_MARGIN = 6;
 
 // ----------------------------------------------------- instance parameters
 struct Inst {
@@ -192,6 +197,7 @@ struct Inst {
   float acut[MAXMAT];
   float acut_min;               // smallest cut over the materials
   int* hot;                     // [step & 1]: some node's amplitude reached acut_min
+  int* xext;                    // charged region, 3 slots x {lo, hi} (cells)
   unsigned long long* nevents;  // per material
   uint64_t seed;
   // control

@@ -13,20 +13,29 @@ struct Group {
   int n;               // instances
   int blocks;          // total blocks
   int step;            // step index of a single run; -1: each instance's device counter
+  int part = 0;        // field update: 1 = far tiles skip the current (0: every tile reads it)
 };
 
 constexpr int TPB = 256;
 
+// Optional events stamped by the dispatch itself (start of the phase's first
+// kernel, end of its last): kernel execution time, without the gap between a
+// separately recorded event and the dispatch that follows it.
+struct Stamp {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+
 // phase launchers (enqueue on `s`); D = 1..3, order = 1..2
-void launch_push(const Group& g, int D, int order, hipStream_t s);
+void launch_push(const Group& g, int D, int order, hipStream_t s, Stamp st = {});
 // tile sort of the charged particles (gp: the push grid; gscan: one block per
 // instance); each instance decides on the device whether a sort is due
-void launch_sort(const Group& gp, const Group& gscan, int D, hipStream_t s);
-void launch_fields(const Group& g, int D, int variant, hipStream_t s);
-void launch_ionize(const Group& g, int D, int order, hipStream_t s);
+void launch_sort(const Group& gp, const Group& gscan, int D, hipStream_t s, Stamp st = {});
+void launch_fields(const Group& g, int D, int variant, hipStream_t s, Stamp st = {});
+void launch_ionize(const Group& g, int D, int order, hipStream_t s, Stamp st = {});
 void launch_advance(const Inst* insts, int n, hipStream_t s);   // batch: step counters + 1
 int field_tiles(int D, int variant, int Px, int Py, int Pz);   // blocks of the field launch
 int field_tile_variants();
+int field_tile_x(int D, int variant);                          // owned x extent of a field tile
 
 // one-instance setup and diagnostics
 void launch_init_neutrals_d(const Inst* d, int64_t nneut, int D, hipStream_t s);

@@ -16,6 +16,7 @@
 //             positive-carrier birth (Sec. 2.1, 3.2); the last block advances
 //             the step counter
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include "pic_kernels.h"
 
@@ -422,7 +423,8 @@ template <int D, int ORDER, bool LOCAL, bool LF = LOCAL && push_stage_fields(D)>
 __device__ __forceinline__ void push_body(const Inst& I, const PushFields& f, const float* sF, int fx0,
                                           int fy0, int fz0, const GSink& gs, const LSink<D>& ls,
                                           unsigned q, uint8_t kind, int ci, int cj, int ck, float t0,
-                                          float t1, float t2, float ux, float uy, float uz) {
+                                          float t1, float t2, float ux, float uy, float uz, int& xlo,
+                                          int& xhi) {
   // ---- gather E^n, b^n
   float ex, ey, ez, bx, by, bz;
   {
@@ -507,6 +509,8 @@ __device__ __forceinline__ void push_body(const Inst& I, const PushFields& f, co
     gp(I.pkind)[q] = DEAD;
     return;
   }
+  xlo = min(xlo, ni);
+  xhi = max(xhi, ni);
   gp(I.pcell)[q] = pack_cell(D, ni, nj, nk);
   gp(I.po0)[q] = n0;
   if (D >= 2) gp(I.po1)[q] = n1;
@@ -522,7 +526,7 @@ __device__ __forceinline__ void push_body(const Inst& I, const PushFields& f, co
 template <int D, int ORDER, bool TILED>
 __device__ __forceinline__ void push_one(const Inst& I, const PushFields& f, const float* sF,
                                          const GSink& gs, const LSink<D>& ls, int tx0, int ty0,
-                                         int tz0, int p, bool valid) {
+                                         int tz0, int p, bool valid, int& xlo, int& xhi) {
   const unsigned q = (unsigned)p;
   const uint8_t kind = valid ? gp(I.pkind)[q] : DEAD;
   if (kind == DEAD) return;
@@ -538,14 +542,16 @@ __device__ __forceinline__ void push_one(const Inst& I, const PushFields& f, con
     if (D >= 3) in = in && ck >= tz0 && ck < tz0 + ptile_ext(D, 2);
     if (in) {
       push_body<D, ORDER, true>(I, f, sF, tx0 - 1, ty0 - 1, tz0 - 1, gs, ls, q, kind, ci, cj, ck, t0, t1,
-                                t2, ux, uy, uz);
+                                t2, ux, uy, uz, xlo, xhi);
     } else {
       const unsigned long long m = __ballot(1);
       if ((threadIdx.x & 63) == __ffsll((long long)m) - 1) atomicAdd(I.sctl + SC_NDRIFT, __popcll(m));
-      push_body<D, ORDER, false>(I, f, sF, 0, 0, 0, gs, ls, q, kind, ci, cj, ck, t0, t1, t2, ux, uy, uz);
+      push_body<D, ORDER, false>(I, f, sF, 0, 0, 0, gs, ls, q, kind, ci, cj, ck, t0, t1, t2, ux, uy, uz,
+                                 xlo, xhi);
     }
   } else {
-    push_body<D, ORDER, false>(I, f, sF, 0, 0, 0, gs, ls, q, kind, ci, cj, ck, t0, t1, t2, ux, uy, uz);
+    push_body<D, ORDER, false>(I, f, sF, 0, 0, 0, gs, ls, q, kind, ci, cj, ck, t0, t1, t2, ux, uy, uz,
+                               xlo, xhi);
   }
 }
 
@@ -565,7 +571,9 @@ __global__ __launch_bounds__(push_tpb(D)) void k_push(Group g) {
   const int b0 = blockIdx.x - g.off[ii];
   int count = *I.pcount;
   count = count < I.capacity ? count : I.capacity;
-  const int par = (g.step >= 0 ? g.step : *I.step) & 1;
+  const int step = g.step >= 0 ? g.step : *I.step;
+  const int par = step & 1;
+  int xlo = 1 << 30, xhi = -(1 << 30);   // x cells of this block's particles after the move
   const PushFields f{uniform(I.F[par][0]), uniform(I.F[par][1]), uniform(I.F[par][2]),
                      uniform(I.F[par][3]), uniform(I.F[par][4]), uniform(I.F[par][5])};
   const GSink gs{I.Jb[par][0], I.Jb[par][1], I.Jb[par][2], I.ny, I.nz, I.per_y, I.per_z,
@@ -583,7 +591,7 @@ __global__ __launch_bounds__(push_tpb(D)) void k_push(Group g) {
       // staging and flushing the windows
       const int end = ch.z < count ? ch.z : count;
       const int p = ch.y + threadIdx.x;
-      push_one<D, ORDER, false>(I, f, sF, gs, LSink<D>{sJ, 0, 0, 0, 0.0}, 0, 0, 0, p, p < end);
+      push_one<D, ORDER, false>(I, f, sF, gs, LSink<D>{sJ, 0, 0, 0, 0.0}, 0, 0, 0, p, p < end, xlo, xhi);
       continue;
     }
     const int t = ch.x;
@@ -626,7 +634,7 @@ __global__ __launch_bounds__(push_tpb(D)) void k_push(Group g) {
     const int end = ch.z < count ? ch.z : count;
     for (int p0 = ch.y; p0 < end; p0 += NT) {
       const int p = p0 + threadIdx.x;
-      push_one<D, ORDER, true>(I, f, sF, gs, ls, tx0, ty0, tz0, p, p < end);
+      push_one<D, ORDER, true>(I, f, sF, gs, ls, tx0, ty0, tz0, p, p < end, xlo, xhi);
     }
     __syncthreads();
     for (int e = threadIdx.x; e < 3 * PWin<D>::N; e += NT) {
@@ -646,7 +654,35 @@ __global__ __launch_bounds__(push_tpb(D)) void k_push(Group g) {
   const LSink<D> none{sJ, 0, 0, 0, 0.0};
   for (int p0 = nsorted + b0 * NT; p0 < count; p0 += nb * NT) {
     const int p = p0 + threadIdx.x;
-    push_one<D, ORDER, false>(I, f, sF, gs, none, 0, 0, 0, p, p < count);
+    push_one<D, ORDER, false>(I, f, sF, gs, none, 0, 0, 0, p, p < count, xlo, xhi);
+  }
+  // charged region of the next step: this step's region plus where this
+  // block's particles went (an atomic only where a block extends it)
+  __shared__ int sxr[2][NT / 64];
+  for (int o = 32; o > 0; o >>= 1) {
+    xlo = min(xlo, __shfl_xor(xlo, o));
+    xhi = max(xhi, __shfl_xor(xhi, o));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sxr[0][threadIdx.x >> 6] = xlo;
+    sxr[1][threadIdx.x >> 6] = xhi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < NT / 64; ++w) {
+      xlo = min(xlo, sxr[0][w]);
+      xhi = max(xhi, sxr[1][w]);
+    }
+    const int* cur = I.xext + 2 * (step % 3);
+    int* nxt = I.xext + 2 * ((step + 1) % 3);
+    const int clo = cur[0], chi = cur[1];
+    if (b0 == 0) {
+      atomicMin(nxt, min(clo, xlo));
+      atomicMax(nxt + 1, max(chi, xhi));
+    } else {
+      if (xlo < clo) atomicMin(nxt, xlo);
+      if (xhi > chi) atomicMax(nxt + 1, xhi);
+    }
   }
 }
 
@@ -1095,9 +1131,24 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
   };
   // one block per tile; each XCD walks a contiguous range of tiles
   const int tb = xcd_remap(bk, nbk);
-  const int a0x = (tb % ntx) * T::X;
-  const int a0y = D >= 2 ? ((tb / ntx) % nty) * T::Y : 0;
-  const int a0z = D >= 3 ? (tb / (ntx * nty)) * T::Z : 0;
+  const int tx = tb % ntx, rest = tb / ntx;
+  // far tiles: x columns farther than XNEAR_MARGIN cells from every cell that
+  // held a charged particle so far and from the amplitude window have carried
+  // no current, ever, so their update neither reads nor clears it
+  bool cur = true;
+  if (g.part == 1) {
+    const int* xe = I.xext + 2 * (step % 3);
+    int lo = xe[0], hi = xe[1];
+    if (I.wx1 > I.wx0) {
+      lo = min(lo, I.wx0 - G);
+      hi = max(hi, I.wx1 - 1 - G);
+    }
+    const int alo = lo - XNEAR_MARGIN + G, ahi = hi + XNEAR_MARGIN + G;
+    cur = lo <= hi && tx * T::X <= ahi && tx * T::X + T::X - 1 >= alo;
+  }
+  const int a0x = tx * T::X;
+  const int a0y = D >= 2 ? (rest % nty) * T::Y : 0;
+  const int a0z = D >= 3 ? (rest / nty) * T::Z : 0;
   const int i0 = a0x - G, j0 = a0y - Gy, k0 = a0z - Gz;   // logical tile origin
   if (threadIdx.x == 0) blk_hot = 0;
   // ---- per-axis tables
@@ -1147,7 +1198,7 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
     sB[0][l] = in ? Bc0[gi] : 0.0f;
     sB[1][l] = in ? Bc1[gi] : 0.0f;
     sB[2][l] = in ? Bc2[gi] : 0.0f;
-    const bool cpt = in && qx >= H - 1 && qx <= T::X + H && (D < 2 || (qy >= H - 1 && qy <= T::Y + H)) &&
+    const bool cpt = cur && in && qx >= H - 1 && qx <= T::X + H && (D < 2 || (qy >= H - 1 && qy <= T::Y + H)) &&
                      (D < 3 || (qz >= H - 1 && qz <= T::Z + H));
     jr[k][0] = cpt ? J0[gi] : 0.0f;
     jr[k][1] = cpt ? J1[gi] : 0.0f;
@@ -1291,9 +1342,11 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
     const int ak = D >= 3 ? a0z + qz - H : 0;
     if (ai >= Px || aj >= Py || ak >= Pz) continue;
     const int64_t gi = (int64_t)ai + (int64_t)sy * aj + (int64_t)sz * ak;
-    Jn0[gi] = 0.0f;   // next push deposits here; nobody reads it now
-    Jn1[gi] = 0.0f;
-    Jn2[gi] = 0.0f;
+    if (cur) {
+      Jn0[gi] = 0.0f;   // next push deposits here; nobody reads it now
+      Jn1[gi] = 0.0f;
+      Jn2[gi] = 0.0f;
+    }
     const unsigned bx = sbx[qx], by = sby[qy], bz = sbz[qz];
     // owned positions of periodic axes are the box itself (no wrapped copies)
     const unsigned dy = D >= 2 && py ? (aj - G >= 0 && aj - G < ny ? ~0u : 0u) : ~0u;
@@ -1654,21 +1707,31 @@ __global__ void k_table_probe(const TabHdr* tab, const float* A, float* P, int64
     default: { constexpr int DD = 3; __VA_ARGS__; break; }    \
   }
 
-void launch_push(const Group& g, int D, int order, hipStream_t s) {
+// plain launch, or one that stamps the events it is given
+#define GO(K, grid, block, s, e0, e1, ...)                                               \
+  do {                                                                                    \
+    if ((e0) || (e1))                                                                     \
+      hipExtLaunchKernelGGL(K, dim3(grid), dim3(block), 0, s, e0, e1, 0, __VA_ARGS__);    \
+    else                                                                                  \
+      hipLaunchKernelGGL(K, dim3(grid), dim3(block), 0, s, __VA_ARGS__);                  \
+  } while (0)
+
+void launch_push(const Group& g, int D, int order, hipStream_t s, Stamp st) {
   if (order == 1) {
-    DISPATCH_D(D, hipLaunchKernelGGL((k_push<DD, 1>), dim3(g.blocks), dim3(push_tpb(DD)), 0, s, g));
+    DISPATCH_D(D, GO((k_push<DD, 1>), g.blocks, push_tpb(DD), s, st.start, st.stop, g));
   } else {
-    DISPATCH_D(D, hipLaunchKernelGGL((k_push<DD, 2>), dim3(g.blocks), dim3(push_tpb(DD)), 0, s, g));
+    DISPATCH_D(D, GO((k_push<DD, 2>), g.blocks, push_tpb(DD), s, st.start, st.stop, g));
   }
 }
-void launch_sort(const Group& gp, const Group& gscan, int D, hipStream_t s) {
-  DISPATCH_D(D, hipLaunchKernelGGL((k_sort_count<DD>), dim3(gp.blocks), dim3(TPB), 0, s, gp));
-  DISPATCH_D(D, hipLaunchKernelGGL((k_sort_scan<DD>), dim3(gscan.blocks), dim3(SCAN_TPB), 0, s, gscan));
-  DISPATCH_D(D, hipLaunchKernelGGL((k_sort_scatter<DD>), dim3(gp.blocks), dim3(TPB), 0, s, gp));
-  DISPATCH_D(D, hipLaunchKernelGGL((k_sort_group<DD>), dim3(gp.blocks), dim3(TPB), 0, s, gp));
+void launch_sort(const Group& gp, const Group& gscan, int D, hipStream_t s, Stamp st) {
+  hipEvent_t none = nullptr;
+  DISPATCH_D(D, GO((k_sort_count<DD>), gp.blocks, TPB, s, st.start, none, gp));
+  DISPATCH_D(D, GO((k_sort_scan<DD>), gscan.blocks, SCAN_TPB, s, none, none, gscan));
+  DISPATCH_D(D, GO((k_sort_scatter<DD>), gp.blocks, TPB, s, none, none, gp));
+  DISPATCH_D(D, GO((k_sort_group<DD>), gp.blocks, TPB, s, none, st.stop, gp));
 }
-#define FIELDS_V(DD, V) hipLaunchKernelGGL((k_fields<DD, V>), dim3(g.blocks), dim3(TPB), 0, s, g)
-void launch_fields(const Group& g, int D, int variant, hipStream_t s) {
+#define FIELDS_V(DD, V) GO((k_fields<DD, V>), g.blocks, TPB, s, st.start, st.stop, g)
+void launch_fields(const Group& g, int D, int variant, hipStream_t s, Stamp st) {
   switch (variant) {
     case 1: DISPATCH_D(D, FIELDS_V(DD, 1)); break;
     case 2: DISPATCH_D(D, FIELDS_V(DD, 2)); break;
@@ -1682,11 +1745,12 @@ int field_tiles(int D, int variant, int Px, int Py, int Pz) {
   return ((Px + t.x - 1) / t.x) * (D >= 2 ? (Py + t.y - 1) / t.y : 1) * (D >= 3 ? (Pz + t.z - 1) / t.z : 1);
 }
 int field_tile_variants() { return kTileVariants; }
-void launch_ionize(const Group& g, int D, int order, hipStream_t s) {
+int field_tile_x(int D, int variant) { return tile_shape(D, variant).x; }
+void launch_ionize(const Group& g, int D, int order, hipStream_t s, Stamp st) {
   if (order == 1) {
-    DISPATCH_D(D, hipLaunchKernelGGL((k_ionize<DD, 1>), dim3(g.blocks), dim3(TPB), 0, s, g));
+    DISPATCH_D(D, GO((k_ionize<DD, 1>), g.blocks, TPB, s, st.start, st.stop, g));
   } else {
-    DISPATCH_D(D, hipLaunchKernelGGL((k_ionize<DD, 2>), dim3(g.blocks), dim3(TPB), 0, s, g));
+    DISPATCH_D(D, GO((k_ionize<DD, 2>), g.blocks, TPB, s, st.start, st.stop, g));
   }
 }
 void launch_advance(const Inst* insts, int n, hipStream_t s) {

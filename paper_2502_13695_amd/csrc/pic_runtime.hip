@@ -77,14 +77,18 @@ struct Layout {
   size_t total;
 };
 
+// Device counters.  Words that every block of a launch reads (the step of a
+// batch member, the charged region) sit on cache lines of their own, apart
+// from the words that blocks update with atomics while others read.
 struct Ctr {
-  int pcount;
-  int step;
+  alignas(256) int step;
+  alignas(256) int xext[6];
+  alignas(256) int pcount;
   unsigned health;
   unsigned done;
-  int sctl[SC_WORDS];
-  int hot[2];
-  unsigned long long nevents[MAXMAT];
+  alignas(256) int sctl[SC_WORDS];
+  alignas(256) int hot[2];
+  alignas(256) unsigned long long nevents[MAXMAT];
   double acc[64];
 };
 
@@ -215,6 +219,8 @@ struct pic_ctx {
   int owns_alloc_via_cb = 0;
   int* h_step = nullptr;      // pinned: staging for the device step counter
   int resort = 8;             // tile-sort check every `resort` steps (0 = never)
+  int far_skip = 1;           // far field tiles skip the current (pic_set_far_tiles)
+  int h_xext[6] = {};         // host source of the charged-region slots
 };
 
 struct pic_batch {
@@ -248,7 +254,11 @@ Group single(pic_ctx* c, int phase, int nb) {
   return Group{c->d_inst, phase == 1 ? c->d_off_fields : c->d_off + 2 * phase, 1, nb, (int)c->step};
 }
 
-// Phase timing: events recorded on the context stream around each launch;
+// Timing events: no system-scope fence when they complete, so stamping a
+// launch adds no cache write-back and invalidation around it.
+hipError_t timing_event(hipEvent_t* e) { return hipEventCreateWithFlags(e, hipEventDisableSystemFence); }
+
+// Phase timing: events stamped by the phase's dispatches on the context stream;
 // a ring slot is read back (and accumulated) before it is reused.
 void harvest(pic_ctx* c, int ph, int slot) {
   if (!c->ev_used[ph][slot]) return;
@@ -261,24 +271,42 @@ void harvest(pic_ctx* c, int ph, int slot) {
   c->ev_used[ph][slot] = 0;
 }
 
+// one step in every window of `timing` steps, at an offset that advances by one
+// per window (every residue of the step index is sampled equally often)
+bool sampled(const pic_ctx* c) {
+  return c->timing && c->step % c->timing == (c->step / c->timing) % c->timing;
+}
+
 template <typename F>
 void timed(pic_ctx* c, int ph, F&& launch) {
-  if (!c->timing || c->step % c->timing != 0) {
-    launch();
+  if (!sampled(c)) {
+    launch(Stamp{});
     return;
   }
   const int slot = (int)(c->ev_slot % pic_ctx::kRing);
   harvest(c, ph, slot);
   if (!c->ev[ph][slot][0]) {
-    if (hipEventCreate(&c->ev[ph][slot][0]) != hipSuccess || hipEventCreate(&c->ev[ph][slot][1]) != hipSuccess) {
-      launch();
+    if (timing_event(&c->ev[ph][slot][0]) != hipSuccess || timing_event(&c->ev[ph][slot][1]) != hipSuccess) {
+      launch(Stamp{});
       return;
     }
   }
-  (void)hipEventRecord(c->ev[ph][slot][0], c->stream);
-  launch();
-  (void)hipEventRecord(c->ev[ph][slot][1], c->stream);
+  launch(Stamp{c->ev[ph][slot][0], c->ev[ph][slot][1]});
   c->ev_used[ph][slot] = 1;
+}
+
+// Charged region of every slot: cells [lo, hi] (with the amplitude window's
+// cells); lo > hi = empty.
+void set_region(pic_ctx* c, int lo, int hi) {
+  const Layout& L = c->L;
+  if (L.wx1 > L.wx0) {
+    lo = std::min(lo, L.wx0 - G);
+    hi = std::max(hi, L.wx1 - 1 - G);
+  }
+  for (int k = 0; k < 3; ++k) {
+    c->h_xext[2 * k] = lo;
+    c->h_xext[2 * k + 1] = hi;
+  }
 }
 
 void harvest_all(pic_ctx* c) {
@@ -314,23 +342,25 @@ void enqueue_step(pic_ctx* c) {
   const int D = c->canon.D, order = c->cfg.shape_order;
   hipStream_t s = c->stream;
   if (c->resort > 0 && c->step % c->resort == 0)
-    timed(c, 3, [&] { launch_sort(single(c, 0, c->nb_push), single(c, 2, 1), D, s); });
-  timed(c, 0, [&] { launch_push(single(c, 0, c->nb_push), D, order, s); });
+    timed(c, 3, [&](Stamp st) { launch_sort(single(c, 0, c->nb_push), single(c, 2, 1), D, s, st); });
+  timed(c, 0, [&](Stamp st) { launch_push(single(c, 0, c->nb_push), D, order, s, st); });
   if (c->tune_left > 0) {
     const int idx = field_tile_variants() * c->tune_reps - c->tune_left;
     const int v = idx / c->tune_reps, r = idx % c->tune_reps;
     const Layout& L = c->L;
     const Group gv{c->d_inst, c->d_off + 8 + 2 * v, 1, field_tiles(D, v, (int)L.Px, (int)L.Py, (int)L.Pz),
-                   (int)c->step};
-    (void)hipEventRecord(c->tune_ev[v][r][0], s);
-    launch_fields(gv, D, v, s);
-    (void)hipEventRecord(c->tune_ev[v][r][1], s);
+                   (int)c->step, c->far_skip};
+    launch_fields(gv, D, v, s, Stamp{c->tune_ev[v][r][0], c->tune_ev[v][r][1]});
     if (--c->tune_left == 0) finish_tuning(c);
   } else {
-    timed(c, 1, [&] { launch_fields(single(c, 1, c->nb_cell), D, c->tile, s); });
+    timed(c, 1, [&](Stamp st) {
+      Group g = single(c, 1, c->nb_cell);
+      g.part = c->far_skip;
+      launch_fields(g, D, c->tile, s, st);
+    });
   }
-  timed(c, 2, [&] { launch_ionize(single(c, 3, c->nb_neut), D, order, s); });
-  if (c->timing && c->step % c->timing == 0) ++c->ev_slot;
+  timed(c, 2, [&](Stamp st) { launch_ionize(single(c, 3, c->nb_neut), D, order, s, st); });
+  if (sampled(c)) ++c->ev_slot;
   ++c->step;
 }
 
@@ -611,6 +641,7 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
   I.pcount = &c->d_ctr->pcount;
   I.sctl = c->d_ctr->sctl;
   I.hot = c->d_ctr->hot;
+  I.xext = c->d_ctr->xext;
   I.step = &c->d_ctr->step;
   I.health = &c->d_ctr->health;
   I.nevents = c->d_ctr->nevents;
@@ -695,6 +726,11 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
     ok &= hipMemcpyAsync(devp(c, L.o_sig), sig, sizeof sig, hipMemcpyHostToDevice, s) == hipSuccess;
   }
   if (!ok) return fail(PIC_E_DEVICE);
+  // charged region: the amplitude window (births and preionized carriers are
+  // all inside it)
+  set_region(c, 1 << 30, -(1 << 30));
+  ok &= hipMemcpyAsync(c->d_ctr->xext, c->h_xext, sizeof c->h_xext, hipMemcpyHostToDevice, s) == hipSuccess;
+  if (!ok) return fail(PIC_E_DEVICE);
   launch_init_neutrals_d(c->d_inst, L.nneut, D, s);
   if (c->cfg.preionize_eV > 0 && L.nneut > 0) {
     const float* sg = (const float*)devp(c, L.o_sig);
@@ -732,6 +768,12 @@ pic_status pic_set_timing(pic_ctx* c, int32_t on) {
   harvest_all(c);
   c->timing = on;
   for (int ph = 0; ph < 8; ++ph) c->timers[ph] = c->tcount[ph] = 0.0;
+  return PIC_OK;
+}
+
+pic_status pic_set_far_tiles(pic_ctx* c, int32_t on) {
+  if (!c) return PIC_E_INVAL;
+  c->far_skip = on ? 1 : 0;
   return PIC_OK;
 }
 
@@ -821,7 +863,7 @@ pic_status pic_autotune_steps(pic_ctx* c, int32_t reps) {
   for (int v = 0; v < field_tile_variants(); ++v)
     for (int r = 0; r < reps; ++r)
       for (int e = 0; e < 2; ++e)
-        if (!c->tune_ev[v][r][e]) HIP_OK(hipEventCreate(&c->tune_ev[v][r][e]));
+        if (!c->tune_ev[v][r][e]) HIP_OK(timing_event(&c->tune_ev[v][r][e]));
   c->tune_reps = reps;
   c->tune_left = field_tile_variants() * reps;
   return PIC_OK;
@@ -879,6 +921,13 @@ pic_status pic_set_state(pic_ctx* c, const pic_state* S) {
     }
     const int cnt = (int)n;
     HIP_OK(hipMemcpy(&c->d_ctr->pcount, &cnt, sizeof cnt, hipMemcpyHostToDevice));
+    int lo = 1 << 30, hi = -(1 << 30);
+    for (int64_t p = 0; p < n; ++p) {
+      lo = std::min(lo, S->particles[p].cell[0]);
+      hi = std::max(hi, S->particles[p].cell[0]);
+    }
+    set_region(c, lo, hi);
+    HIP_OK(hipMemcpy(c->d_ctr->xext, c->h_xext, sizeof c->h_xext, hipMemcpyHostToDevice));
     // the new particles are all unsorted
     HIP_OK(hipMemset(c->d_ctr->sctl, 0, sizeof(c->d_ctr->sctl)));
   }
@@ -918,6 +967,7 @@ pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size
     case PIC_DIAG_PARAMS: need = sizeof(pic_params); break;
     case PIC_DIAG_TIMERS: need = sizeof(double) * 32; break;
     case PIC_DIAG_SORT: need = sizeof(double) * 4; break;
+    case PIC_DIAG_REGION: need = sizeof(double) * 4; break;
     case PIC_DIAG_EVENTS:
     case PIC_DIAG_PARTICLES: break;   // computed below
     default: return PIC_E_INVAL;
@@ -1039,6 +1089,32 @@ pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size
     o[1] = w[SC_NCHUNKS];
     o[2] = w[SC_NDRIFT];
     o[3] = w[SC_NSORTS];
+    return PIC_OK;
+  }
+  if (kind == PIC_DIAG_REGION) {
+    // the slot the next step reads, with the tile split the field kernel derives from it
+    int x[6];
+    HIP_OK(hipMemcpy(x, c->d_ctr->xext, sizeof x, hipMemcpyDeviceToHost));
+    int lo = x[2 * (c->step % 3)], hi = x[2 * (c->step % 3) + 1];
+    if (L.wx1 > L.wx0) {
+      lo = std::min(lo, L.wx0 - G);
+      hi = std::max(hi, L.wx1 - 1 - G);
+    }
+    const int TX = field_tile_x(D, c->tile);
+    const int ntx = (int)((L.Px + TX - 1) / TX);
+    int nnx = 0;
+    if (lo <= hi) {
+      const int alo = std::max(0, lo - XNEAR_MARGIN + G);
+      const int ahi = std::min((int)L.Px - 1, hi + XNEAR_MARGIN + G);
+      if (alo <= ahi) nnx = ahi / TX - alo / TX + 1;
+    }
+    if (!c->far_skip) nnx = ntx;
+    const int rows = c->nb_cell / ntx;
+    double* o = (double*)host_out;
+    o[0] = lo;
+    o[1] = hi;
+    o[2] = (double)nnx * rows;
+    o[3] = (double)(ntx - nnx) * rows;
     return PIC_OK;
   }
   if (kind == PIC_DIAG_TIMERS) {
@@ -1200,12 +1276,12 @@ pic_status pic_batch_step(pic_batch* b, int64_t nsteps) {
     for (auto& cl : b->classes) {
       const int np1 = cl.n + 1;
       Group gp{cl.d_insts, cl.d_off + 0 * np1, cl.n, cl.blocks[0], -1};
-      Group gc{cl.d_insts, cl.d_off + 1 * np1, cl.n, cl.blocks[1], -1};
+      Group gc{cl.d_insts, cl.d_off + 1 * np1, cl.n, cl.blocks[1], -1, 1};
       Group gs{cl.d_insts, cl.d_off + 2 * np1, cl.n, cl.blocks[2], -1};
       Group gn{cl.d_insts, cl.d_off + 3 * np1, cl.n, cl.blocks[3], -1};
       if (sort_due) launch_sort(gp, gs, cl.D, s);
       launch_push(gp, cl.D, cl.order, s);
-      launch_fields(gc, cl.D, cl.tile, s);
+      launch_fields(gc, cl.D, cl.tile, s);   // far tiles skip the current
       launch_ionize(gn, cl.D, cl.order, s);
       launch_advance(cl.d_insts, cl.n, s);
     }

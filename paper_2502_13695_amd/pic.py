@@ -23,7 +23,7 @@ ABI_VERSION = 1
 ENV = {"gauss": 0, "sin2": 1}
 BC = {"outflow": 0, "periodic": 1}
 DIAG_SCALARS, DIAG_FIELDS, DIAG_NE, DIAG_UE, DIAG_EVENTS, DIAG_PARTICLES, DIAG_PARAMS, DIAG_AMP, \
-    DIAG_TIMERS, DIAG_SORT = range(10)
+    DIAG_TIMERS, DIAG_SORT, DIAG_REGION = range(11)
 SC = dict(step=0, time=1, n_neutral=2, n_e=3, n_pos=4, events=5, u_field=6, ke_e=7, ke_pos=8,
           e_gap=9, e_abs=10, gauss_max=11, rho_max=12, health=13, slots=14)
 
@@ -91,8 +91,8 @@ class State(C.Structure):
 SYMBOLS = ["pic_init", "pic_step", "pic_diag", "pic_set_state", "pic_footprint", "pic_canonical",
            "pic_keldysh_rate", "pic_table_probe", "pic_table_probe_device", "pic_batch_create",
            "pic_batch_step", "pic_batch_add", "pic_batch_remove", "pic_batch_destroy",
-           "pic_set_timing", "pic_autotune", "pic_autotune_steps", "pic_set_resort", "pic_destroy",
-           "pic_status_str"]
+           "pic_set_timing", "pic_autotune", "pic_autotune_steps", "pic_set_resort", "pic_set_far_tiles",
+           "pic_destroy", "pic_status_str"]
 
 
 def lib():
@@ -131,6 +131,7 @@ def lib():
             "pic_autotune": ([vp, i32], C.c_int),
             "pic_autotune_steps": ([vp, i32], C.c_int),
             "pic_set_resort": ([vp, i32], C.c_int),
+            "pic_set_far_tiles": ([vp, i32], C.c_int),
             "pic_destroy": ([vp], None),
             "pic_status_str": ([C.c_int], C.c_char_p),
         }
@@ -353,6 +354,16 @@ class Context:
 
     def timers(self):
         return self._diag(DIAG_TIMERS, np.float64)
+
+    def set_far_tiles(self, on):
+        """Field tiles far from every charged particle so far skip the current."""
+        _check(lib().pic_set_far_tiles(self.h, int(on)), "pic_set_far_tiles")
+
+    def region(self):
+        """Charged region along x of the next step (cells lo..hi, with the
+        amplitude window) and the field tiles that read / skip the current."""
+        v = self._diag(DIAG_REGION, np.float64)
+        return dict(lo=int(v[0]), hi=int(v[1]), near_tiles=int(v[2]), far_tiles=int(v[3]))
 
     def sort_state(self):
         """Tile-sort state: sorted slots, chunks, drifter-steps since the sort, sorts done."""

@@ -361,6 +361,94 @@ def test_autotune_restores_initial_state(P):
     b.close()
 
 
+def test_phase_timing_samples_in_proportion(P):
+    """Sampled phase timing: one step per window of 16, at an offset that moves
+    by one per window, so over 256 steps 16 steps are timed and 2 of them (the
+    offsets 0 and 8) carry the tile sort check that runs every 8 steps."""
+    cfg = W.config_2d(nx=160, ny=40, nsteps=300, ppc=2, peak=3e14, slab_cells=10, waist=0.6e-6)
+    a = P.Context(cfg)
+    a.set_resort(8)
+    a.set_timing(16)
+    a.step(256)
+    t = a.timers()
+    assert [int(t[8 + ph]) for ph in range(4)] == [16, 16, 16, 2]
+    assert all(t[ph] > 0 for ph in range(4))
+    a.close()
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_far_tiles_skip_only_zero_current(P, ndim):
+    """Field tiles farther than the margin from every cell that ever held a
+    charged particle update without reading or clearing the current.
+    Electrons launched out of the slab towards both x faces (each from the spot
+    of a hole at rest, so the start is charge neutral) widen that region as
+    they go.  The Gauss law holds to roundoff (a current skipped where it was
+    not zero breaks it), and fields, carriers and ionization events match runs
+    where every tile reads its current, within the noise floor of two such
+    runs (FP32 atomics add in varying order)."""
+    # no carrier reaches a face in the 60 steps (its removal there would leave
+    # its charge's imprint on the first interior nodes): periodic transverse
+    # faces, and the fast electrons stop short of the x faces
+    if ndim == 2:
+        cfg = W.config_2d(nx=320, ny=40, nsteps=400, ppc=2, peak=3e14, slab_cells=10, waist=0.6e-6,
+                          bc="periodic")
+    else:
+        cfg = W.config_3d(nx=128, ny=8, nz=8, nsteps=400, ppc=4, fluence=1.5, front=40)
+    rng = np.random.default_rng(3)
+    n = 32
+    rec = np.zeros(2 * n, dtype=P.PARTICLE_DTYPE)
+    dx = cfg["dx"][0]
+    front, back = int(cfg["layers"][0][1] / dx), int(cfg["layers"][-1][2] / dx) - 4
+    out = np.arange(n) % 2 == 0                          # these go to +x from the back
+    rec["cell"][:n, 0] = np.where(out, back, front) + rng.integers(0, 4, n)
+    if ndim == 2:
+        rec["cell"][:n, 1] = rng.integers(10, 30, n)
+    else:
+        rec["cell"][:n, 1:] = rng.integers(0, 8, (n, 2))
+    rec["off"][:n, :ndim] = rng.uniform(0.0, 1.0, (n, ndim))
+    rec[n:] = rec[:n]
+    rec["kind"][:n] = 0                                  # electrons of the first material
+    rec["kind"][n:] = 1                                  # holes at rest on the same spots
+    rec["u"][:n, 0] = np.where(out, 3.0, -3.0)
+    runs = []
+    for skip in (0, 0, 1):
+        c = P.Context(cfg)
+        c.set_far_tiles(skip)
+        c.set_state(0, particles=rec)
+        r0 = c.region()
+        c.step(60)
+        sc = c.scalars()
+        assert sc["gauss_max"] <= 1e-4 * sc["rho_max"], (skip, sc["gauss_max"], sc["rho_max"])
+        p = c.particles()
+        runs.append(dict(f=c.fields(), ev=set(map(tuple, c.events().tolist())), r0=r0, r=c.region(),
+                         x=np.sort(p["cell"][:, 0] + p["off"][:, 0].astype(np.float64)), sc=sc))
+        c.close()
+
+    def l2(fa, fb):
+        num = sum(np.sum((x - y) ** 2) for x, y in zip(fa[0] + fa[1], fb[0] + fb[1]))
+        den = sum(np.sum(y ** 2) for y in fb[0] + fb[1])
+        return math.sqrt(num / den)
+
+    u0, u1, sp = runs
+    r0, r = sp["r0"], sp["r"]
+    assert r["lo"] <= r0["lo"] - 20 and r["hi"] >= r0["hi"] + 20, (r0, r)
+    assert r["near_tiles"] + r["far_tiles"] == r0["near_tiles"] + r0["far_tiles"]
+    if ndim == 2:
+        assert r["far_tiles"] > 0
+    # every live carrier lies inside the region the next step uses
+    assert r["lo"] <= sp["x"].min() and sp["x"].max() < r["hi"] + 1
+    floor = l2(u1["f"], u0["f"])
+    d = l2(sp["f"], u0["f"])
+    _record(f"far_tiles_{ndim}d", l2_skip=d, l2_noskip_pair=floor)
+    assert d < max(2e-6, 10 * floor), (d, floor)
+    assert len(u0["ev"]) > 0
+    assert len(sp["ev"] ^ u0["ev"]) <= max(1, 10 * len(u1["ev"] ^ u0["ev"]), int(1e-4 * len(u0["ev"])))
+    dn = abs(len(sp["x"]) - len(u0["x"]))
+    assert dn <= 2 * len(sp["ev"] ^ u0["ev"])
+    if dn == 0 and len(u1["x"]) == len(u0["x"]):
+        assert np.max(np.abs(sp["x"] - u0["x"])) < max(1e-3, 10 * np.max(np.abs(u1["x"] - u0["x"])))
+
+
 def test_autotune_in_run_same_results(P):
     """In-run tuning cycles the field tile shapes over the first steps; every
     shape computes the same fields, so the run matches an untuned one."""
