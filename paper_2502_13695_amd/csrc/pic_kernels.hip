@@ -17,6 +17,7 @@
 //             the step counter
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
+#include <type_traits>
 
 #include "pic_kernels.h"
 
@@ -1151,10 +1152,19 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
   const int a0z = D >= 3 ? (rest / nty) * T::Z : 0;
   const int i0 = a0x - G, j0 = a0y - Gy, k0 = a0z - Gz;   // logical tile origin
   if (threadIdx.x == 0) blk_hot = 0;
-  // ---- per-axis tables
+  // ---- per-axis tables; an interior tile (every staged position valid for
+  // both updates and on no face, every owned position inside the box) runs
+  // the phases below without any per-position test
+  constexpr unsigned REQ = AX_ARR | AX_BN | AX_BH | AX_IN | AX_IH;
+  auto interior = [](unsigned b, int q, int t) {
+    return (b & REQ) == REQ && !(b & (AX_F0 | AX_F1)) &&
+           (q < H || q >= t + H || (b & (AX_DN | AX_DH)) == (AX_DN | AX_DH));
+  };
+  bool ok = true;
   for (int q = threadIdx.x; q < RX; q += TPB) {
     const int i = i0 + q - H;
     sbx[q] = axis_bits(i, nx, false, i + G >= 0 && i + G < Px);
+    ok = ok && interior(sbx[q], q, T::X);
   }
   for (int q = threadIdx.x; q < RY; q += TPB) {
     if (D >= 2) {
@@ -1163,6 +1173,7 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
       const bool in = jw + G >= 0 && jw + G < Py;
       sby[q] = axis_bits(j, ny, py, in);
       soy[q] = in ? sy * (jw + G) : 0;
+      ok = ok && interior(sby[q], q, T::Y);
     } else {
       sby[q] = AX_BN | AX_BH | AX_IN | AX_IH | AX_DN | AX_DH | AX_ARR;
       soy[q] = 0;
@@ -1175,12 +1186,13 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
       const bool in = kw + G >= 0 && kw + G < Pz;
       sbz[q] = axis_bits(k, nz, pz, in);
       soz[q] = in ? sz * (kw + G) : 0;
+      ok = ok && interior(sbz[q], q, T::Z);
     } else {
       sbz[q] = AX_BN | AX_BH | AX_IN | AX_IH | AX_DN | AX_DH | AX_ARR;
       soz[q] = 0;
     }
   }
-  __syncthreads();
+  const bool inner = __syncthreads_and(ok);
   // ---- A: stage E^n and b^n; the current of the points this thread updates
   // in phase C is loaded now too (registers), so HBM latency is met once
   float jr[KMAX][3];
@@ -1190,7 +1202,7 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
     if (l >= NR) continue;
     int qx, qy, qz;
     split(l, qx, qy, qz);
-    const bool in = sbx[qx] & sby[qy] & sbz[qz] & AX_ARR;
+    const bool in = inner || (sbx[qx] & sby[qy] & sbz[qz] & AX_ARR);
     const int64_t gi = (int64_t)(a0x + qx - H) + soy[qy] + soz[qz];
     sE[0][l] = in ? Ec0[gi] : 0.0f;
     sE[1][l] = in ? Ec1[gi] : 0.0f;
@@ -1213,11 +1225,12 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
   }
   __syncthreads();
   // ---- B: b^{n+1/2} on local [-2, T] (in place; reads E only)
+  auto phase_b = [&](auto INNER) {
   for (int l = threadIdx.x; l < NR; l += TPB) {
     int qx, qy, qz;
     split(l, qx, qy, qz);
     if (qx > T::X + H || (D >= 2 && qy > T::Y + H) || (D >= 3 && qz > T::Z + H)) continue;
-    const unsigned bx = sbx[qx], by = sby[qy], bz = sbz[qz];
+    const unsigned bx = INNER ? ~0u : sbx[qx], by = INNER ? ~0u : sby[qy], bz = INNER ? ~0u : sbz[qz];
     if ((bx & AX_BN) && (by & AX_BH) && (bz & AX_BH)) {
       float cu = 0.0f;
       if (D >= 2) cu += hy * (sE[2][l + LY] - sE[2][l]);
@@ -1235,8 +1248,12 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
       sB[2][l] -= cu;
     }
   }
+  };
+  if (inner) phase_b(std::true_type{});
+  else phase_b(std::false_type{});
   __syncthreads();
   // ---- C: E^{n+1} at interior positions on local [-1, T] (in place)
+  auto phase_c = [&](auto INNER) {
 #pragma unroll
   for (int k = 0; k < KMAX; ++k) {
     const int l = threadIdx.x + k * TPB;
@@ -1246,8 +1263,8 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
     if (qx < H - 1 || qx > T::X + H) continue;
     if (D >= 2 && (qy < H - 1 || qy > T::Y + H)) continue;
     if (D >= 3 && (qz < H - 1 || qz > T::Z + H)) continue;
-    const unsigned bx = sbx[qx], by = sby[qy], bz = sbz[qz];
-    if (!(bx & by & bz & AX_ARR)) continue;
+    const unsigned bx = INNER ? ~0u : sbx[qx], by = INNER ? ~0u : sby[qy], bz = INNER ? ~0u : sbz[qz];
+    if (!INNER && !(bx & by & bz & AX_ARR)) continue;
     if ((bx & AX_IH) && (by & AX_IN) && (bz & AX_IN)) {
       float cu = 0.0f;
       if (D >= 2) cu += Cy * (sB[2][l] - sB[2][l - LY]);
@@ -1265,6 +1282,9 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
       sE[2][l] += sien[qx] * (cu - jr[k][2]);
     }
   }
+  };
+  if (inner) phase_c(std::true_type{});
+  else phase_c(std::false_type{});
   __syncthreads();
   // ---- D: outflow faces, lowest priority first (z, y, x); a point on several
   // faces follows the first of x, y, z, with its inward neighbour's final value
@@ -1331,6 +1351,7 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
   const int nwin = I.nwin;
   const int slot = step % (nwin > 0 ? nwin : 1);
   const int wx0 = I.wx0, wx1 = I.wx1;
+  auto phase_e = [&](auto INNER) {
   for (int l = threadIdx.x; l < NR; l += TPB) {
     int qx, qy, qz;
     split(l, qx, qy, qz);
@@ -1340,17 +1361,17 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
     const int ai = a0x + qx - H;
     const int aj = D >= 2 ? a0y + qy - H : 0;   // absent axes: index 0
     const int ak = D >= 3 ? a0z + qz - H : 0;
-    if (ai >= Px || aj >= Py || ak >= Pz) continue;
+    if (!INNER && (ai >= Px || aj >= Py || ak >= Pz)) continue;
     const int64_t gi = (int64_t)ai + (int64_t)sy * aj + (int64_t)sz * ak;
     if (cur) {
       Jn0[gi] = 0.0f;   // next push deposits here; nobody reads it now
       Jn1[gi] = 0.0f;
       Jn2[gi] = 0.0f;
     }
-    const unsigned bx = sbx[qx], by = sby[qy], bz = sbz[qz];
+    const unsigned bx = INNER ? ~0u : sbx[qx], by = INNER ? ~0u : sby[qy], bz = INNER ? ~0u : sbz[qz];
     // owned positions of periodic axes are the box itself (no wrapped copies)
-    const unsigned dy = D >= 2 && py ? (aj - G >= 0 && aj - G < ny ? ~0u : 0u) : ~0u;
-    const unsigned dz = D >= 3 && pz ? (ak - G >= 0 && ak - G < nz ? ~0u : 0u) : ~0u;
+    const unsigned dy = !INNER && D >= 2 && py ? (aj - G >= 0 && aj - G < ny ? ~0u : 0u) : ~0u;
+    const unsigned dz = !INNER && D >= 3 && pz ? (ak - G >= 0 && ak - G < nz ? ~0u : 0u) : ~0u;
     const bool xdn = bx & AX_DN, xdh = bx & AX_DH;
     const bool ydn = by & dy & AX_DN, ydh = by & dy & AX_DH;
     const bool zdn = bz & dz & AX_DN, zdh = bz & dz & AX_DH;
@@ -1400,6 +1421,9 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
       }
     }
   }
+  };
+  if (inner) phase_e(std::true_type{});
+  else phase_e(std::false_type{});
   __syncthreads();
   if (threadIdx.x == 0 && blk_hot) atomicOr(I.hot + par, 1);
 }
