@@ -120,7 +120,7 @@ def run_gpu(cfg, steps, warmup):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     timers = ctx.timers()
-    tune = dict(chosen=int(timers[23]), blocks=int(timers[24]), ms=[float(x) for x in timers[16:21]])
+    tune = dict(chosen=int(timers[23]), blocks=int(timers[24]), ms=[float(x) for x in timers[16:23]])
     sort_state = ctx.sort_state()
     region = ctx.region()
     sc = ctx.scalars()

