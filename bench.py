@@ -130,9 +130,10 @@ def run_gpu(cfg, steps, warmup):
     # particle-steps: each neutral counts until its ionization step, each birth
     # pair from its step to the end (carriers leaving the box are not subtracted)
     if len(ev):
-        death = ev[:, 1]
-        dead_steps = float(sum(min(int(s), steps) for s in death))
-        births = float(sum(2 * max(0, steps - int(s)) for s in death))
+        import numpy as np
+        death = np.asarray(ev[:, 1], dtype=np.int64)
+        dead_steps = float(np.minimum(death, steps).sum())
+        births = float(2 * np.maximum(0, steps - death).sum())
         neutral_steps = dead_steps + (nneut - len(death)) * steps
     else:
         births = 0.0
@@ -296,7 +297,8 @@ def main():
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="slab2d", choices=["slab2d", "mirror3d", "slab1d",
-                                                             "stress2d", "stress3d", "scan", "serve"])
+                                                             "stress2d", "stress3d", "stress2d-cap",
+                                                             "stress3d-cap", "scan", "serve"])
     ap.add_argument("--instances", type=int, default=32, help="scan: fluence-scan instances")
     ap.add_argument("--requests", type=int, default=400, help="serve: requests")
     ap.add_argument("--scale", type=float, default=1.0, help="serve: grid/step scale of the mix")
@@ -335,6 +337,16 @@ def main():
         cfg = W.config_stress(W.config_2d(), eV=2.0)
         wl = dict(workload="2D3V slab, all neutrals pre-ionized (charged-loop stress)", cells=[2048, 512],
                   ppc=16, seed=1)
+    elif args.workload == "stress2d-cap":
+        # 488 neutrals per slab cell, all pre-ionized: 2 x 40960 x 488 = 4.0e7 charged
+        cfg = W.config_stress(W.config_2d(ppc=488), eV=2.0)
+        wl = dict(workload="2D3V slab grid, 4.0e7 pre-ionized carriers (charged-loop stress at the "
+                           "particle cap)", cells=[2048, 512], ppc=488, seed=1)
+    elif args.workload == "stress3d-cap":
+        # 272 neutrals per material cell, all pre-ionized: 2 x 458752 x 272 = 2.5e8 charged
+        cfg = W.config_stress(W.config_3d(ppc=272), eV=2.0)
+        wl = dict(workload="3D3V mirror-share grid, 2.5e8 pre-ionized carriers (charged-loop stress at "
+                           "the particle cap)", cells=[256, 128, 128], ppc=272, seed=2)
     else:
         cfg = W.config_stress(W.config_3d(), eV=2.0)
         wl = dict(workload="3D3V mirror share, all neutrals pre-ionized (charged-loop stress)",

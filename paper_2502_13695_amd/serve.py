@@ -25,12 +25,12 @@ def particle_steps(events, nneut, steps):
     t = 0, from its ionization events (neutral id, step): each neutral counts
     until its ionization step, each birth pair from that step on (carriers
     leaving the box are not subtracted)."""
-    ev = events
-    if len(ev) == 0:
+    import numpy as np
+    if len(events) == 0:
         return float(nneut) * steps, 0.0
-    death = ev[:, 1]
-    dead = float(sum(min(int(s), steps) for s in death))
-    births = float(sum(2 * max(0, steps - int(s)) for s in death))
+    death = np.asarray(events[:, 1], dtype=np.int64)
+    dead = float(np.minimum(death, steps).sum())
+    births = float(2 * np.maximum(0, steps - death).sum())
     return dead + (nneut - len(death)) * steps, births
 
 
