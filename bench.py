@@ -96,6 +96,26 @@ def measured_traffic(workload, kernel):
     return None
 
 
+def stream_copy_gbs(mib=1024, reps=5):
+    """Device-to-device copy bandwidth on this GPU (read + write bytes / s),
+    the practical ceiling a streaming kernel is also compared with."""
+    import torch
+    n = mib * 1024 * 1024 // 4
+    a = torch.empty(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * n * 4 / (ms * 1e-3) / 1e9
+
+
 def run_gpu(cfg, steps, warmup):
     import torch
     from paper_2502_13695_amd import pic
@@ -379,6 +399,7 @@ def main():
     far_frac, far_frac_end = share(reg0), share(reg)
     bytes_launch = phase_bytes(cfg, dom, n_charged_avg, n_alive_avg, far_frac)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    copy_gbs = stream_copy_gbs()
     step_ms = r["wall"] / args.steps * 1e3
     out = {
         "metric": "particle-steps/sec (gather+push+deposit+ionize) at 1 GPU",
@@ -398,7 +419,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": PHASES[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.workload, PHASES[dom]),
-                     "bytes_per_launch": bytes_launch, "avg_launch_us": avg_ms * 1e3},
+                     "bytes_per_launch": bytes_launch, "avg_launch_us": avg_ms * 1e3,
+                     "stream_copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "phases_us_per_step": {PHASES[ph]: timers[ph] / max(timers[8], 1) * 1e3 for ph in tot},
         "phases_us_per_launch": {PHASES[ph]: timers[ph] / max(timers[8 + ph], 1) * 1e3 for ph in tot},
         "field_tile_autotune": r["tune"],

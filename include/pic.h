@@ -202,7 +202,9 @@ typedef struct {
 /* Create a context: canonicalise the configuration, build the FP64 Keldysh
  * rate table per material (Sec. 2.1, Eq. 1-3), allocate device state, load the
  * neutrals (Sec. 3.1).  Returns PIC_E_VERSION on a struct_size/abi_version
- * mismatch, PIC_E_INVAL on a bad configuration, PIC_E_NOMEM / PIC_E_DEVICE. */
+ * mismatch, PIC_E_INVAL on a bad configuration (including a guarded grid of
+ * 2^30 points or more, or a charged capacity above 2^30), PIC_E_NOMEM /
+ * PIC_E_DEVICE. */
 pic_status pic_init(const pic_config* cfg, pic_ctx** out);
 
 /* Enqueue nsteps time steps (Sec. 1-2 loop: gather, push, deposit, field

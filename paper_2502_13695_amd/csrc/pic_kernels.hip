@@ -71,6 +71,18 @@ __device__ __forceinline__ T* uniform(T* p) {
   return (T*)(((unsigned long long)hi << 32) | lo);
 }
 
+// Element i of an array through a 32-bit byte offset from a wave-uniform
+// base: the scalar-base addressing form, one VALU shift per offset shared by
+// every array indexed with it (grids hold fewer than 2^30 points).
+template <class T>
+__device__ __forceinline__ const gmem<T>& at(const gmem<T>* b, unsigned i) {
+  return *(const gmem<T>*)((const gmem<char>*)b + i * (unsigned)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ gmem<T>& at(gmem<T>* b, unsigned i) {
+  return *(gmem<T>*)((gmem<char>*)b + i * (unsigned)sizeof(T));
+}
+
 // shape weights on the integer grid for a particle at cell c + offset t
 // (t in [0,1)); half = 1 for a half-integer staggered component.
 // Returns the first grid index; weights w[0..ORDER].
@@ -1207,18 +1219,19 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
     int qx, qy, qz;
     split(l, qx, qy, qz);
     const bool in = inner || (sbx[qx] & sby[qy] & sbz[qz] & AX_ARR);
-    const int64_t gi = (int64_t)(a0x + qx - H) + soy[qy] + soz[qz];
-    sE[0][l] = in ? Ec0[gi] : 0.0f;
-    sE[1][l] = in ? Ec1[gi] : 0.0f;
-    sE[2][l] = in ? Ec2[gi] : 0.0f;
-    sB[0][l] = in ? Bc0[gi] : 0.0f;
-    sB[1][l] = in ? Bc1[gi] : 0.0f;
-    sB[2][l] = in ? Bc2[gi] : 0.0f;
+    // 32-bit element offsets from uniform bases (every grid has < 2^31 points)
+    const unsigned gi = (unsigned)(a0x + qx - H + soy[qy] + soz[qz]);
+    sE[0][l] = in ? at(Ec0, gi) : 0.0f;
+    sE[1][l] = in ? at(Ec1, gi) : 0.0f;
+    sE[2][l] = in ? at(Ec2, gi) : 0.0f;
+    sB[0][l] = in ? at(Bc0, gi) : 0.0f;
+    sB[1][l] = in ? at(Bc1, gi) : 0.0f;
+    sB[2][l] = in ? at(Bc2, gi) : 0.0f;
     const bool cpt = cur && in && qx >= H - 1 && qx <= T::X + H && (D < 2 || (qy >= H - 1 && qy <= T::Y + H)) &&
                      (D < 3 || (qz >= H - 1 && qz <= T::Z + H));
-    jr[k][0] = cpt ? J0[gi] : 0.0f;
-    jr[k][1] = cpt ? J1[gi] : 0.0f;
-    jr[k][2] = cpt ? J2[gi] : 0.0f;
+    jr[k][0] = cpt ? at(J0, gi) : 0.0f;
+    jr[k][1] = cpt ? at(J1, gi) : 0.0f;
+    jr[k][2] = cpt ? at(J2, gi) : 0.0f;
   }
   // 1/eps per x (loads in flight with the staging)
   for (int q = threadIdx.x; q < RX; q += TPB) {
@@ -1322,8 +1335,8 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
         const int qd = (d == 0 ? qx : (d == 1 ? qy : qz)) + inw;
         if (qd < H - 1 || qd > Td + H) continue;
         const unsigned bb[3] = {bx, by, bz};
-        const int64_t gq = (int64_t)(a0x + qx - H) + soy[qy] + soz[qz];
-        const int64_t gr = gq + (d == 0 ? inw : (d == 1 ? inw * sy : inw * sz));
+        const unsigned gq = (unsigned)(a0x + qx - H + soy[qy] + soz[qz]);
+        const unsigned gr = gq + (d == 0 ? inw : (d == 1 ? inw * sy : inw * sz));
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           if (c == d) continue;   // normal component: interior update only
@@ -1338,7 +1351,7 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
           }
           if (!ok) continue;
           const gmem<float>* Eold = c == 0 ? Ec0 : (c == 1 ? Ec1 : Ec2);
-          const float qold = Eold[gq], rold = Eold[gr], rnew = sE[c][l + inw * ls];
+          const float qold = at(Eold, gq), rold = at(Eold, gr), rnew = sE[c][l + inw * ls];
           if (d == 0 && (bd & AX_F0) && c == I.pol) {
             const float pr = I.prof[(soy[qy] / sy) + Py * (D >= 3 ? soz[qz] / sz : 0)];
             const MurInc m{pr * s0.x, pr * s1.x, pr * s0.y, pr * s1.y};
@@ -1366,11 +1379,11 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
     const int aj = D >= 2 ? a0y + qy - H : 0;   // absent axes: index 0
     const int ak = D >= 3 ? a0z + qz - H : 0;
     if (!INNER && (ai >= Px || aj >= Py || ak >= Pz)) continue;
-    const int64_t gi = (int64_t)ai + (int64_t)sy * aj + (int64_t)sz * ak;
+    const unsigned gi = (unsigned)(ai + sy * aj + sz * ak);
     if (cur) {
-      Jn0[gi] = 0.0f;   // next push deposits here; nobody reads it now
-      Jn1[gi] = 0.0f;
-      Jn2[gi] = 0.0f;
+      at(Jn0, gi) = 0.0f;   // next push deposits here; nobody reads it now
+      at(Jn1, gi) = 0.0f;
+      at(Jn2, gi) = 0.0f;
     }
     const unsigned bx = INNER ? ~0u : sbx[qx], by = INNER ? ~0u : sby[qy], bz = INNER ? ~0u : sbz[qz];
     // owned positions of periodic axes are the box itself (no wrapped copies)
@@ -1379,24 +1392,24 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
     const bool xdn = bx & AX_DN, xdh = bx & AX_DH;
     const bool ydn = by & dy & AX_DN, ydh = by & dy & AX_DH;
     const bool zdn = bz & dz & AX_DN, zdh = bz & dz & AX_DH;
-    if (xdh && ydn && zdn) En0[gi] = sE[0][l];
-    if (xdn && ydh && zdn) En1[gi] = sE[1][l];
-    if (xdn && ydn && zdh) En2[gi] = sE[2][l];
+    if (xdh && ydn && zdn) at(En0, gi) = sE[0][l];
+    if (xdn && ydh && zdn) at(En1, gi) = sE[1][l];
+    if (xdn && ydn && zdh) at(En2, gi) = sE[2][l];
     if (xdn && ydh && zdh) {
       float cu = 0.0f;
       if (D >= 2) cu += hy * (sE[2][l + LY] - sE[2][l]);
       if (D >= 3) cu -= hz * (sE[1][l + LZ] - sE[1][l]);
-      Bn0[gi] = sB[0][l] - cu;
+      at(Bn0, gi) = sB[0][l] - cu;
     }
     if (xdh && ydn && zdh) {
       float cu = -hx * (sE[2][l + 1] - sE[2][l]);
       if (D >= 3) cu += hz * (sE[0][l + LZ] - sE[0][l]);
-      Bn1[gi] = sB[1][l] - cu;
+      at(Bn1, gi) = sB[1][l] - cu;
     }
     if (xdh && ydh && zdn) {
       float cu = hx * (sE[1][l + 1] - sE[1][l]);
       if (D >= 2) cu -= hy * (sE[0][l + LY] - sE[0][l]);
-      Bn2[gi] = sB[2][l] - cu;
+      at(Bn2, gi) = sB[2][l] - cu;
     }
     // node |E^{n+1}| (Yee components averaged to the node) into the window
     if (ai >= wx0 && ai < wx1 && xdn && ydn && zdn) {
@@ -1414,7 +1427,7 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
       const float pre = slot == 0 ? m : fmaxf(prefix[w], m);
       prefix[w] = pre;
       const float a = slot + 1 < nwin ? fmaxf(suffix[(int64_t)(slot + 1) * wsz + w], pre) : pre;
-      gp(I.A)[gi] = a;
+      at(gp(uniform(I.A)), gi) = a;
       if (a >= I.acut_min) blk_hot = 1;
       if (slot == nwin - 1) {   // block of samples complete: suffix maxima for the next
         float run = 0.0f;

@@ -124,7 +124,9 @@ pic_status plan(const pic_config* cfg, const Canon& c, const std::vector<TableHo
     L->ntiles *= L->ntile[d];
   }
   L->ngroups = L->ntiles * (ptile_cells(D) / PT_GROUP);
-  if (cap > INT_MAX / 2 || L->ngroups > (1 << 28) || L->nneut > ((int64_t)1 << 40) || c.ppc > 65535)
+  // grid byte offsets are 32-bit in the kernels
+  if (cap > INT_MAX / 2 || L->ngroups > (1 << 28) || L->nneut > ((int64_t)1 << 40) || c.ppc > 65535 ||
+      L->ncell >= (1 << 30))
     return PIC_E_INVAL;
   L->capacity = cap;
   L->maxchunks = L->ntiles + cap / SORT_CHUNK + 1;
