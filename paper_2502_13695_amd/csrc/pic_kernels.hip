@@ -1016,16 +1016,18 @@ __device__ __forceinline__ float mur_inc(float qold, float rold, float rnew, flo
 struct TileShape {
   int x, y, z;
 };
-// Shapes 5 and 6 make the staged row (x extent plus the 2 + 2 halo) a power
-// of two, so a thread's staged index splits into coordinates by shifts.
+// Shapes 3 to 6 (2D, 3D) and 5, 6 (1D) make the staged row (x extent plus
+// the 2 + 2 halo) a power of two, so a thread's staged index splits into
+// coordinates by shifts.
 __host__ __device__ constexpr TileShape tile_shape(int D, int v) {
   return D == 1 ? (v == 1 ? TileShape{128, 1, 1} : v == 2 ? TileShape{512, 1, 1} : v == 5 ? TileShape{252, 1, 1}
                    : v == 6 ? TileShape{508, 1, 1} : TileShape{256, 1, 1})
-       : D == 2 ? (v == 1 ? TileShape{32, 8, 1} : v == 2 ? TileShape{64, 4, 1} : v == 3 ? TileShape{64, 12, 1}
-                   : v == 4 ? TileShape{64, 16, 1} : v == 5 ? TileShape{60, 8, 1} : v == 6 ? TileShape{60, 12, 1}
+       : D == 2 ? (v == 1 ? TileShape{32, 8, 1} : v == 2 ? TileShape{64, 4, 1} : v == 3 ? TileShape{124, 4, 1}
+                   : v == 4 ? TileShape{60, 4, 1} : v == 5 ? TileShape{60, 8, 1} : v == 6 ? TileShape{60, 12, 1}
                    : TileShape{64, 8, 1})
-                : (v == 1 ? TileShape{32, 4, 4} : v == 2 ? TileShape{16, 4, 4} : v == 3 ? TileShape{8, 8, 8}
-                   : v == 5 ? TileShape{12, 4, 4} : v == 6 ? TileShape{12, 8, 4} : TileShape{16, 8, 4});
+                : (v == 1 ? TileShape{12, 4, 8} : v == 2 ? TileShape{16, 4, 4} : v == 3 ? TileShape{28, 4, 4}
+                   : v == 4 ? TileShape{12, 12, 4} : v == 5 ? TileShape{12, 4, 4} : v == 6 ? TileShape{12, 8, 4}
+                   : TileShape{16, 8, 4});
 }
 constexpr int kTileVariants = 7;
 
