@@ -116,7 +116,7 @@ def stream_copy_gbs(mib=1024, reps=5):
     return 2.0 * n * 4 / (ms * 1e-3) / 1e9
 
 
-def run_gpu(cfg, steps, warmup):
+def run_gpu(cfg, steps, warmup, field_tile=None):
     import torch
     from paper_2502_13695_amd import pic
     torch.cuda.set_device(0)
@@ -129,7 +129,8 @@ def run_gpu(cfg, steps, warmup):
     region0 = ctx.region()
     # field tile shape: timed on the first steps of the timed run itself (every
     # shape computes identical fields); the choice is reported after the run
-    ctx.autotune_steps(4)
+    if field_tile is None:
+        ctx.autotune_steps(4)
     # HIP events stamped by the dispatches of one step in every 16 of the timed
     # region (the sampled position cycles through the window, so the tile sort
     # check, due every 8 steps, is sampled in proportion)
@@ -324,6 +325,8 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="serve: grid/step scale of the mix")
     ap.add_argument("--burst", action="store_true",
                     help="serve: every request arrives at t = 0 (capacity, not latency, is measured)")
+    ap.add_argument("--field-tile", type=int, default=None,
+                    help="fixed field tile shape (default: timed in-run over the first steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--calib-copy", action="store_true",
@@ -380,7 +383,10 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    r = run_gpu(cfg, args.steps, args.warmup)
+    if args.field_tile is not None:
+        # fixed field tile shape, read by the library when a context is created
+        os.environ["PIC_FIELD_TILE"] = str(args.field_tile)
+    r = run_gpu(cfg, args.steps, args.warmup, args.field_tile)
     value = r["particle_steps"] / r["wall"]
     timers = r["timers"]
     # dominant kernel by device time
