@@ -2,7 +2,8 @@
 
 * one step from a seeded random state (fields, relativistic particles) in
   1D / 2D / 3D, shape order 1 and 2, outflow and periodic transverse
-  boundaries: fields and every particle element by element;
+  boundaries: fields and every particle element by element; the same at the
+  full benchmark grids in the benchmark's launch configuration;
 * the device rate table against the oracle's in-situ Keldysh probability;
 * whole runs (laser through a slab, ionization births): fields (relative L2),
   ionization events (id, step), electron count and absorbed energy, the
@@ -141,6 +142,55 @@ def test_one_step_fields_and_particles(P, ndim, order, bc, sort):
     key_o = sorted(zip(np.round(sim.px[npre:, :ndim], 6).tolist(), sim.pk[npre:].tolist()))
     assert key_g == key_o
     ctx.close()
+
+
+@pytest.mark.parametrize("which", ["slab2d_2048x512", "mirror3d_256x128x128"])
+def test_one_step_at_benchmark_size(P, which, monkeypatch):
+    """One step at the full benchmark grids (the 2D slab and the 3D mirror
+    share, with their materials, neutrals and laser), in the launch
+    configuration the benchmark times (the field tile shape the in-run tuning
+    picks on MI355X, tile sort and far-tile skip on), from a seeded random
+    state: every field value against the oracle, every pre-existing carrier
+    (matched by position: the tile sort reorders the slots), and the
+    ionization events of the step."""
+    cfg = W.config_2d() if which.startswith("slab2d") else W.config_3d()
+    ndim = cfg["ndim"]
+    monkeypatch.setenv("PIC_FIELD_TILE", "5" if ndim == 2 else "6")
+    st = _state_f32(W.random_state(cfg, 30000, seed=900 + ndim, e_scale=3e8, u_scale=0.3))
+    ctx = P.Context(cfg)
+    ctx.set_state(0, st["E"], st["b"], _records(P, st, ndim))
+    ctx.step(1)
+    assert int(ctx.timers()[23]) == (5 if ndim == 2 else 6)
+    E_g, b_g = ctx.fields()
+    parts = ctx.particles()
+    ev_g = set(map(tuple, ctx.events().tolist()))
+    ctx.close()
+    sim = OP.Sim(cfg)
+    _to_oracle_state(sim, st)
+    sim.step()
+    scale = max(3e8, max(np.max(np.abs(sim.interior_field(w, c))) for w in "Eb" for c in range(3)))
+    for c in range(3):
+        Eo, bo = sim.interior_field("E", c), sim.interior_field("b", c)
+        assert E_g[c].shape == Eo.shape and b_g[c].shape == bo.shape
+        assert np.max(np.abs(E_g[c] - Eo)) < 2e-6 * scale, ("E", c)
+        assert np.max(np.abs(b_g[c] - bo)) < 2e-6 * scale, ("b", c)
+    ev_o = sim.event_set()
+    assert len(ev_o) > 0 and len(ev_g ^ ev_o) <= max(1, int(1e-4 * len(ev_o)))
+    npre = len(st["kind"])
+    n = cfg["n"]
+    per = cfg["transverse_bc"] == "periodic"
+    period = [None] + [n[k] if per else None for k in range(1, ndim)]
+    pos_g = parts["cell"][:, :ndim] + parts["off"][:, :ndim].astype(np.float64)
+    pre_g, u_g, k_g = _match_particles(pos_g, parts["u"], parts["kind"].astype(np.int64),
+                                       sim.px[:npre, :ndim], sim.pk[:npre], period)
+    d = pre_g - sim.px[:npre, :ndim]
+    for k in range(1, ndim):
+        if per:
+            d[:, k] -= n[k] * np.round(d[:, k] / n[k])
+    assert np.max(np.abs(d)) < 2e-5
+    assert np.max(np.abs(u_g - sim.pu[:npre])) < 2e-6 * max(1.0, np.max(np.abs(sim.pu)))
+    assert np.array_equal(k_g, sim.pk[:npre])
+    assert abs(len(parts) - len(sim.px)) <= 2 * len(ev_g ^ ev_o)   # births
 
 
 @pytest.mark.parametrize("cfg", [W.config_2d(), W.config_3d()])
