@@ -306,6 +306,44 @@ def test_run_3d_mirror_periodic(P):
     ctx.close()
 
 
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_run_without_material(P, ndim):
+    """Degenerate target: no material, hence no neutrals, no amplitude window
+    and no carriers ever (every field tile is far from any charge); the pulse
+    crosses vacuum and leaves.  Fields match the oracle; every count is zero;
+    nothing is sorted."""
+    base = {1: W.config_1d(n=256, ppc=4, nsteps=300),
+            2: W.config_2d(nx=96, ny=24, nsteps=300, ppc=2, waist=0.6e-6),
+            3: W.config_3d(nx=48, ny=8, nz=8, nsteps=300, ppc=2)}[ndim]
+    cfg = dict(base, layers=[])
+    ctx, sim = _run_both(P, cfg, 160)
+    sc = ctx.scalars()
+    assert sc["n_neutral"] == 0 and sc["n_e"] == 0 and sc["events"] == 0
+    assert len(ctx.events()) == 0 and len(ctx.particles()) == 0
+    r = ctx.region()
+    assert r["near_tiles"] == 0 and r["far_tiles"] > 0
+    assert ctx.sort_state()["sorts"] == 0
+    l2 = _field_l2(ctx, sim)
+    assert 0.0 < l2 < 1e-5, l2
+    ctx.close()
+
+
+def test_zero_amplitude_pulse_keeps_everything_zero(P):
+    """A pulse of zero amplitude: the fields stay exactly zero, the window stays
+    cold, no neutral ionizes, and the step counter advances."""
+    cfg = W.config_2d(nx=96, ny=24, nsteps=200, ppc=4, peak=0.0, slab_cells=10, waist=0.6e-6)
+    cfg["laser"] = dict(cfg["laser"], peak_Wcm2=0.0, fluence_Jcm2=0.0)
+    ctx = P.Context(cfg)
+    ctx.step(200)
+    sc = ctx.scalars()
+    E, b = ctx.fields()
+    assert all(np.all(a == 0) for a in E + b)
+    assert sc["step"] == 200 and sc["events"] == 0 and sc["n_e"] == 0
+    assert sc["n_neutral"] == 10 * 24 * 4        # slab of 10 cells across all 24 rows
+    assert np.all(ctx.amp() == 0)
+    ctx.close()
+
+
 def test_stress_preionized_2d(P):
     cfg = W.config_stress(W.config_2d(nx=96, ny=32, nsteps=60, ppc=4, slab_cells=20, peak=1e13,
                                       bc="periodic", waist=0.0), eV=3.0)

@@ -123,6 +123,20 @@ def test_invalid_configs_rejected():
     assert P.lib().pic_status_str(-6) == b"charged-particle capacity exceeded"
 
 
+def test_size_limits_rejected():
+    """The kernels address grids with 32-bit byte offsets and particles with
+    32-bit slots: a guarded grid of 2^30 points or more, or a charged capacity
+    above 2^30, is refused before anything is allocated."""
+    _lib_or_skip()
+    big = dict(W.config_3d(), n=[1100, 1000, 1000])             # 1.1e9 guarded points
+    with pytest.raises(P.PicError):
+        P.footprint(big)
+    ok = dict(W.config_3d(), n=[1000, 1000, 1000])              # just below 2^30 with guards
+    assert P.footprint(ok) > 0
+    with pytest.raises(P.PicError):
+        P.footprint(dict(W.config_2d(), particle_capacity=(1 << 30) + 2))
+
+
 def test_footprint_scales_with_problem():
     _lib_or_skip()
     f2 = P.footprint(W.config_2d())
