@@ -160,12 +160,14 @@ enum {
                              chunks, drifter-steps (a particle that deposited outside
                              its tile's window, counted per step) since the last
                              sort, sorts performed */
-  PIC_DIAG_REGION = 10    /* double[4]: charged region along x that the next step's
+  PIC_DIAG_REGION = 10    /* double[5]: charged region along x that the next step's
                              field update uses (first and last cell that held a
                              charged particle so far, together with the amplitude
                              window's cells; lo > hi when empty), then the field
                              tiles that read the current and the far tiles that
-                             skip it (see pic_set_far_tiles) */
+                             skip it (see pic_set_far_tiles), then the field front:
+                             the last x node of a field tile that has held a
+                             nonzero E or b */
 };
 
 /* PIC_DIAG_SCALARS layout (all double). */
@@ -281,9 +283,12 @@ pic_status pic_set_timing(pic_ctx* c, int32_t on);
  * column lies farther than 6 cells from all of them and from the amplitude
  * window has carried no current at any step (a step's deposit stays within 3
  * cells of the particle's cell), so its update neither reads nor clears the
- * current: 48 instead of 72 bytes per cell.  Results are identical either way;
- * on = 0 makes every tile read its current (for comparison).  Batches always
- * skip. */
+ * current: 48 instead of 72 bytes per cell.  A far tile whose staged x range
+ * (tile plus 2 cells) also lies beyond the field front (the last x column of
+ * a tile that has stored a nonzero E or b) has only zero inputs; it is not
+ * updated at all, its outputs being zero already.  Results are identical
+ * either way; on = 0 makes every tile read its current and be updated (for
+ * comparison).  Batches always skip. */
 pic_status pic_set_far_tiles(pic_ctx* c, int32_t on);
 
 /* Tile sort of the charged particles (the resort of the particle loop): every

@@ -13,7 +13,10 @@ struct Group {
   int n;               // instances
   int blocks;          // total blocks
   int step;            // step index of a single run; -1: each instance's device counter
-  int part = 0;        // field update: 1 = far tiles skip the current (0: every tile reads it)
+  // field update: 0 every tile reads its current; 1 far tiles skip the current
+  // and far tiles beyond the field front are not updated; 2 far tiles skip the
+  // current but every tile is updated (the in-run timing of the tile shapes)
+  int part = 0;
 };
 
 constexpr int TPB = 256;

@@ -1155,7 +1155,7 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
   // held a charged particle so far and from the amplitude window have carried
   // no current, ever, so their update neither reads nor clears it
   bool cur = true;
-  if (g.part == 1) {
+  if (g.part >= 1) {
     const int* xe = I.xext + 2 * (step % 3);
     int lo = xe[0], hi = xe[1];
     if (I.wx1 > I.wx0) {
@@ -1165,6 +1165,9 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
     const int alo = lo - XNEAR_MARGIN + G, ahi = hi + XNEAR_MARGIN + G;
     cur = lo <= hi && tx * T::X <= ahi && tx * T::X + T::X - 1 >= alo;
   }
+  // the field front: the last x column of a tile that has stored a nonzero E
+  // or b (loaded now, tested after the axis tables)
+  const int front = *I.front;
   const int a0x = tx * T::X;
   const int a0y = D >= 2 ? (rest % nty) * T::Y : 0;
   const int a0z = D >= 3 ? (rest / nty) * T::Z : 0;
@@ -1210,6 +1213,11 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
       soz[q] = 0;
     }
   }
+  // a far tile whose staged x range lies beyond the front has zero inputs
+  // (the update moves the front by at most two cells per step): its outputs
+  // are zero and already stored, as it was skipped or wrote zeros at every
+  // earlier step, so it is not updated
+  if (g.part == 1 && !cur && a0x - H > front) return;
   const bool inner = __syncthreads_and(ok);
   // ---- A: stage E^n and b^n; the current of the points this thread updates
   // in phase C is loaded now too (registers), so HBM latency is met once
@@ -1370,6 +1378,8 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
   const int nwin = I.nwin;
   const int slot = step % (nwin > 0 ? nwin : 1);
   const int wx0 = I.wx0, wx1 = I.wx1;
+  bool stored_nz = false;   // this thread stored a nonzero E or b (tiles reaching past the front)
+  const bool track = a0x + T::X - 1 > front;
   auto phase_e = [&](auto INNER) {
   for (int l = threadIdx.x; l < NR; l += TPB) {
     int qx, qy, qz;
@@ -1394,24 +1404,39 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
     const bool xdn = bx & AX_DN, xdh = bx & AX_DH;
     const bool ydn = by & dy & AX_DN, ydh = by & dy & AX_DH;
     const bool zdn = bz & dz & AX_DN, zdh = bz & dz & AX_DH;
-    if (xdh && ydn && zdn) at(En0, gi) = sE[0][l];
-    if (xdn && ydh && zdn) at(En1, gi) = sE[1][l];
-    if (xdn && ydn && zdh) at(En2, gi) = sE[2][l];
+    if (xdh && ydn && zdn) {
+      at(En0, gi) = sE[0][l];
+      stored_nz = stored_nz || (track && sE[0][l] != 0.0f);
+    }
+    if (xdn && ydh && zdn) {
+      at(En1, gi) = sE[1][l];
+      stored_nz = stored_nz || (track && sE[1][l] != 0.0f);
+    }
+    if (xdn && ydn && zdh) {
+      at(En2, gi) = sE[2][l];
+      stored_nz = stored_nz || (track && sE[2][l] != 0.0f);
+    }
     if (xdn && ydh && zdh) {
       float cu = 0.0f;
       if (D >= 2) cu += hy * (sE[2][l + LY] - sE[2][l]);
       if (D >= 3) cu -= hz * (sE[1][l + LZ] - sE[1][l]);
-      at(Bn0, gi) = sB[0][l] - cu;
+      const float v = sB[0][l] - cu;
+      at(Bn0, gi) = v;
+      stored_nz = stored_nz || (track && v != 0.0f);
     }
     if (xdh && ydn && zdh) {
       float cu = -hx * (sE[2][l + 1] - sE[2][l]);
       if (D >= 3) cu += hz * (sE[0][l + LZ] - sE[0][l]);
-      at(Bn1, gi) = sB[1][l] - cu;
+      const float v = sB[1][l] - cu;
+      at(Bn1, gi) = v;
+      stored_nz = stored_nz || (track && v != 0.0f);
     }
     if (xdh && ydh && zdn) {
       float cu = hx * (sE[1][l + 1] - sE[1][l]);
       if (D >= 2) cu -= hy * (sE[0][l + LY] - sE[0][l]);
-      at(Bn2, gi) = sB[2][l] - cu;
+      const float v = sB[2][l] - cu;
+      at(Bn2, gi) = v;
+      stored_nz = stored_nz || (track && v != 0.0f);
     }
     // node |E^{n+1}| (Yee components averaged to the node) into the window
     if (ai >= wx0 && ai < wx1 && xdn && ydn && zdn) {
@@ -1443,7 +1468,12 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
   };
   if (inner) phase_e(std::true_type{});
   else phase_e(std::false_type{});
-  __syncthreads();
+  // a tile reaching past the field front moves it if it stored a nonzero value
+  if (track) {
+    if (__syncthreads_or(stored_nz) && threadIdx.x == 0) atomicMax(I.front, a0x + T::X - 1);
+  } else {
+    __syncthreads();
+  }
   if (threadIdx.x == 0 && blk_hot) atomicOr(I.hot + par, 1);
 }
 

@@ -83,6 +83,7 @@ struct Layout {
 struct Ctr {
   alignas(256) int step;
   alignas(256) int xext[6];
+  alignas(256) int front;
   alignas(256) int pcount;
   unsigned health;
   unsigned done;
@@ -350,8 +351,10 @@ void enqueue_step(pic_ctx* c) {
     const int idx = field_tile_variants() * c->tune_reps - c->tune_left;
     const int v = idx / c->tune_reps, r = idx % c->tune_reps;
     const Layout& L = c->L;
+    // every tile is updated while the shapes are timed (with tiles beyond the
+    // field front skipped, the first steps would time an unrepresentative load)
     const Group gv{c->d_inst, c->d_off + 8 + 2 * v, 1, field_tiles(D, v, (int)L.Px, (int)L.Py, (int)L.Pz),
-                   (int)c->step, c->far_skip};
+                   (int)c->step, c->far_skip ? 2 : 0};
     launch_fields(gv, D, v, s, Stamp{c->tune_ev[v][r][0], c->tune_ev[v][r][1]});
     if (--c->tune_left == 0) finish_tuning(c);
   } else {
@@ -644,6 +647,7 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
   I.sctl = c->d_ctr->sctl;
   I.hot = c->d_ctr->hot;
   I.xext = c->d_ctr->xext;
+  I.front = &c->d_ctr->front;
   I.step = &c->d_ctr->step;
   I.health = &c->d_ctr->health;
   I.nevents = c->d_ctr->nevents;
@@ -855,6 +859,7 @@ pic_status pic_autotune(pic_ctx* c, int32_t reps) {
   HIP_OK(hipMemsetAsync(devp(c, L.o_A), 0, sizeof(float) * L.ncell, s));
   HIP_OK(hipMemsetAsync(&c->d_ctr->health, 0, sizeof(unsigned), s));
   HIP_OK(hipMemsetAsync(c->d_ctr->hot, 0, sizeof(c->d_ctr->hot), s));
+  HIP_OK(hipMemsetAsync(&c->d_ctr->front, 0, sizeof(int), s));
   HIP_OK(hipStreamSynchronize(s));
   return PIC_OK;
 }
@@ -930,6 +935,9 @@ pic_status pic_set_state(pic_ctx* c, const pic_state* S) {
     }
     set_region(c, lo, hi);
     HIP_OK(hipMemcpy(c->d_ctr->xext, c->h_xext, sizeof c->h_xext, hipMemcpyHostToDevice));
+    // the new fields may be nonzero anywhere: no tile is beyond the field front
+    const int fr = (int)L.Px;
+    HIP_OK(hipMemcpy(&c->d_ctr->front, &fr, sizeof fr, hipMemcpyHostToDevice));
     // the new particles are all unsorted
     HIP_OK(hipMemset(c->d_ctr->sctl, 0, sizeof(c->d_ctr->sctl)));
   }
@@ -969,7 +977,7 @@ pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size
     case PIC_DIAG_PARAMS: need = sizeof(pic_params); break;
     case PIC_DIAG_TIMERS: need = sizeof(double) * 32; break;
     case PIC_DIAG_SORT: need = sizeof(double) * 4; break;
-    case PIC_DIAG_REGION: need = sizeof(double) * 4; break;
+    case PIC_DIAG_REGION: need = sizeof(double) * 5; break;
     case PIC_DIAG_EVENTS:
     case PIC_DIAG_PARTICLES: break;   // computed below
     default: return PIC_E_INVAL;
@@ -1095,8 +1103,9 @@ pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size
   }
   if (kind == PIC_DIAG_REGION) {
     // the slot the next step reads, with the tile split the field kernel derives from it
-    int x[6];
+    int x[6], fr = 0;
     HIP_OK(hipMemcpy(x, c->d_ctr->xext, sizeof x, hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(&fr, &c->d_ctr->front, sizeof fr, hipMemcpyDeviceToHost));
     int lo = x[2 * (c->step % 3)], hi = x[2 * (c->step % 3) + 1];
     if (L.wx1 > L.wx0) {
       lo = std::min(lo, L.wx0 - G);
@@ -1117,6 +1126,7 @@ pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size
     o[1] = hi;
     o[2] = (double)nnx * rows;
     o[3] = (double)(ntx - nnx) * rows;
+    o[4] = fr - G;
     return PIC_OK;
   }
   if (kind == PIC_DIAG_TIMERS) {

@@ -537,6 +537,37 @@ def test_far_tiles_skip_only_zero_current(P, ndim):
         assert np.max(np.abs(sp["x"] - u0["x"])) < max(1e-3, 10 * np.max(np.abs(u1["x"] - u0["x"])))
 
 
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_field_front_skip_is_exact(P, ndim):
+    """Far tiles beyond the field front (every input zero) are not updated:
+    while the pulse crosses the box the front trails the update's reach, the
+    skipped part shrinks, and every field value equals the update of every
+    tile bit for bit (no carriers yet, so no atomic-order noise)."""
+    cfg = {1: W.config_1d(n=2048, ppc=4, nsteps=400),
+           2: W.config_2d(nx=480, ny=32, nsteps=400, ppc=2, waist=0.6e-6),
+           3: W.config_3d(nx=160, ny=8, nz=8, nsteps=400, ppc=2, front=120)}[ndim]
+    runs = []
+    for skip in (1, 0):
+        c = P.Context(cfg)
+        c.set_far_tiles(skip)
+        fronts = []
+        for _ in range(3):
+            c.step(150 if ndim == 1 else 40)
+            fronts.append(c.region()["front"])
+        runs.append((c.fields(), fronts, c.scalars()))
+        c.close()
+    (fa, fr, sa), (fb, _, sb) = runs
+    assert sa["events"] == 0 and sb["events"] == 0
+    # the front only advances, and tiles beyond it were skipped (a tile spans
+    # up to 256 cells in 1D, so the front can stay put for a while)
+    assert fr[0] <= fr[1] <= fr[2] < cfg["n"][0] - 14 and fr[2] > fr[0]
+    for x, y in zip(fa[0] + fa[1], fb[0] + fb[1]):
+        assert np.array_equal(x, y)
+    # nothing beyond the front
+    for a in fa[0] + fa[1]:
+        assert not np.any(a[fr[2] + 2:])
+
+
 @pytest.mark.parametrize("case", ["1d", "2d", "3d_periodic"])
 def test_autotune_in_run_same_results(P, case):
     """In-run tuning cycles the field tile shapes (3 steps each, started while
