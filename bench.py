@@ -52,10 +52,12 @@ def window_nodes(cfg):
     return int(np.int64(wx) * t)
 
 
-def phase_bytes(cfg, phase, n_charged_avg, n_alive_avg, far_frac=0.0):
+def phase_bytes(cfg, phase, n_charged_avg, n_alive_avg, far_frac=0.0, far_updated=None):
     """Algorithmic HBM bytes of one launch of a phase (FP32 SoA layout).
     far_frac: share of the field tiles that skip the current (no charged
-    particle has come within their margin)."""
+    particle has come within their margin); far_updated: share of the field
+    tiles that skip the current and are updated (the rest lie beyond the
+    field front and move nothing), default all of them."""
     D = cfg["ndim"]
     per = cfg.get("transverse_bc", "outflow") == "periodic"
     cells = 1
@@ -66,7 +68,8 @@ def phase_bytes(cfg, phase, n_charged_avg, n_alive_avg, far_frac=0.0):
         # far tiles: no current to read or clear (48 B);
         # window node: ring write, prefix read+write, suffix read, A write (20 B)
         # plus the once-per-cycle suffix rebuild (8 B amortised)
-        return (72.0 * (1.0 - far_frac) + 48.0 * far_frac) * cells + 28.0 * window_nodes(cfg)
+        fu = far_frac if far_updated is None else far_updated
+        return (72.0 * (1.0 - far_frac) + 48.0 * fu) * cells + 28.0 * window_nodes(cfg)
     if phase == 0:           # charged particle: read cell, offsets, u, kind; write back
         rd = 4 + 4 * D + 12 + 1
         wr = 4 + 4 * D + 12
@@ -403,7 +406,13 @@ def main():
     share = lambda g: g["far_tiles"] / max(1, g["near_tiles"] + g["far_tiles"])
     reg, reg0 = r["region"], r["region0"]
     far_frac, far_frac_end = share(reg0), share(reg)
-    bytes_launch = phase_bytes(cfg, dom, n_charged_avg, n_alive_avg, far_frac)
+    # far tiles beyond the field front are not updated: the device counts the
+    # tiles every field launch updated; the mean over the timed launches,
+    # less the near tiles, is the share of far tiles that moved bytes
+    ntiles = max(1, reg["near_tiles"] + reg["far_tiles"])
+    upd = (reg["tiles_updated"] - reg0["tiles_updated"]) / max(1, args.steps)
+    far_updated = min(far_frac, max(0.0, upd - reg0["near_tiles"]) / ntiles)
+    bytes_launch = phase_bytes(cfg, dom, n_charged_avg, n_alive_avg, far_frac, far_updated)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
     copy_gbs = stream_copy_gbs()
     step_ms = r["wall"] / args.steps * 1e3
@@ -431,6 +440,7 @@ def main():
         "phases_us_per_launch": {PHASES[ph]: timers[ph] / max(timers[8 + ph], 1) * 1e3 for ph in tot},
         "field_tile_autotune": r["tune"],
         "far_tiles": dict(start=reg0, end=reg, far_frac_start=far_frac, far_frac_end=far_frac_end,
+                          tiles_updated_per_launch=upd, far_updated_frac=far_updated,
                           bytes_per_launch_end=phase_bytes(cfg, 1, 0, 0, far_frac_end)),
         "tile_sort": r["sort_state"],
     }

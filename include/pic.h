@@ -160,14 +160,15 @@ enum {
                              chunks, drifter-steps (a particle that deposited outside
                              its tile's window, counted per step) since the last
                              sort, sorts performed */
-  PIC_DIAG_REGION = 10    /* double[5]: charged region along x that the next step's
+  PIC_DIAG_REGION = 10    /* double[6]: charged region along x that the next step's
                              field update uses (first and last cell that held a
                              charged particle so far, together with the amplitude
                              window's cells; lo > hi when empty), then the field
                              tiles that read the current and the far tiles that
                              skip it (see pic_set_far_tiles), then the field front:
                              the last x node of a field tile that has held a
-                             nonzero E or b */
+                             nonzero E or b, then the field tiles updated so far,
+                             summed over the field launches */
 };
 
 /* PIC_DIAG_SCALARS layout (all double). */

@@ -199,6 +199,7 @@ struct Inst {
   int* hot;                     // [step & 1]: some node's amplitude reached acut_min
   int* xext;                    // charged region, 3 slots x {lo, hi} (cells)
   int* front;                   // last padded x index of a tile that stored a nonzero E or b
+  unsigned long long* tiles_done;   // field tiles updated, one counter per XCD (stride 32)
   unsigned long long* nevents;  // per material
   uint64_t seed;
   // control

@@ -1475,6 +1475,7 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
     __syncthreads();
   }
   if (threadIdx.x == 0 && blk_hot) atomicOr(I.hot + par, 1);
+  if (threadIdx.x == 0) atomicAdd(I.tiles_done + 32 * (blockIdx.x & 7), 1ull);
 }
 
 // ------------------------------------------------------------- ionization

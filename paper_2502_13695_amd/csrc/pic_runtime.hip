@@ -84,6 +84,7 @@ struct Ctr {
   alignas(256) int step;
   alignas(256) int xext[6];
   alignas(256) int front;
+  alignas(256) unsigned long long tiles_done[8 * 32];   // one 256-byte line per XCD
   alignas(256) int pcount;
   unsigned health;
   unsigned done;
@@ -648,6 +649,7 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
   I.hot = c->d_ctr->hot;
   I.xext = c->d_ctr->xext;
   I.front = &c->d_ctr->front;
+  I.tiles_done = c->d_ctr->tiles_done;
   I.step = &c->d_ctr->step;
   I.health = &c->d_ctr->health;
   I.nevents = c->d_ctr->nevents;
@@ -977,7 +979,7 @@ pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size
     case PIC_DIAG_PARAMS: need = sizeof(pic_params); break;
     case PIC_DIAG_TIMERS: need = sizeof(double) * 32; break;
     case PIC_DIAG_SORT: need = sizeof(double) * 4; break;
-    case PIC_DIAG_REGION: need = sizeof(double) * 5; break;
+    case PIC_DIAG_REGION: need = sizeof(double) * 6; break;
     case PIC_DIAG_EVENTS:
     case PIC_DIAG_PARTICLES: break;   // computed below
     default: return PIC_E_INVAL;
@@ -1104,8 +1106,12 @@ pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size
   if (kind == PIC_DIAG_REGION) {
     // the slot the next step reads, with the tile split the field kernel derives from it
     int x[6], fr = 0;
+    unsigned long long td[8 * 32];
     HIP_OK(hipMemcpy(x, c->d_ctr->xext, sizeof x, hipMemcpyDeviceToHost));
     HIP_OK(hipMemcpy(&fr, &c->d_ctr->front, sizeof fr, hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(td, c->d_ctr->tiles_done, sizeof td, hipMemcpyDeviceToHost));
+    double done = 0.0;
+    for (int k = 0; k < 8; ++k) done += (double)td[32 * k];
     int lo = x[2 * (c->step % 3)], hi = x[2 * (c->step % 3) + 1];
     if (L.wx1 > L.wx0) {
       lo = std::min(lo, L.wx0 - G);
@@ -1127,6 +1133,7 @@ pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size
     o[2] = (double)nnx * rows;
     o[3] = (double)(ntx - nnx) * rows;
     o[4] = fr - G;
+    o[5] = done;
     return PIC_OK;
   }
   if (kind == PIC_DIAG_TIMERS) {

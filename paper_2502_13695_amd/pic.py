@@ -361,11 +361,12 @@ class Context:
 
     def region(self):
         """Charged region along x of the next step (cells lo..hi, with the
-        amplitude window), the field tiles that read / skip the current, and
-        the field front (last x node of a tile that held a nonzero field)."""
+        amplitude window), the field tiles that read / skip the current, the
+        field front (last x node of a tile that held a nonzero field) and the
+        field tiles updated so far over all field launches."""
         v = self._diag(DIAG_REGION, np.float64)
         return dict(lo=int(v[0]), hi=int(v[1]), near_tiles=int(v[2]), far_tiles=int(v[3]),
-                    front=int(v[4]))
+                    front=int(v[4]), tiles_updated=int(v[5]))
 
     def sort_state(self):
         """Tile-sort state: sorted slots, chunks, drifter-steps since the sort, sorts done."""
