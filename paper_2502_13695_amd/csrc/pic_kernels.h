@@ -17,6 +17,9 @@ struct Group {
   // and far tiles beyond the field front are not updated; 2 far tiles skip the
   // current but every tile is updated (the in-run timing of the tile shapes)
   int part = 0;
+  // batches: the instance of every block (one load instead of a binary search
+  // over `off`); null for a single run
+  const unsigned short* map = nullptr;
 };
 
 constexpr int TPB = 256;

@@ -25,6 +25,7 @@ namespace pic {
 
 // ------------------------------------------------------------------ helpers
 __device__ __forceinline__ int find_inst(const Group& g) {
+  if (g.map) return g.map[blockIdx.x];
   const int b = blockIdx.x;
   int lo = 0, hi = g.n;
   while (hi - lo > 1) {

@@ -236,6 +236,8 @@ struct pic_batch {
     std::vector<pic_ctx*> ms;
     Inst* d_insts = nullptr;
     int* d_off = nullptr;   // 4 phases x (n + 1)
+    unsigned short* d_map = nullptr;   // per phase: member of every block
+    int map_off[4] = {0, 0, 0, 0};
     int n = 0;
     int blocks[4] = {0, 0, 0, 0};
   };
@@ -698,9 +700,10 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
   // block counts per phase
   auto nblk = [](int64_t n) { return (int)std::max<int64_t>(0, (n + TPB - 1) / TPB); };
   c->nb_push = push_blocks(L.capacity);
-  // field tile shape: default per dimension, overridable (tuning sweeps) by
-  // PIC_FIELD_TILE=<variant>
-  c->tile = 0;
+  // field tile shape: default per dimension (the shapes the in-run timing
+  // picks on MI355X for the benchmark grids: 60x8 in 2D, 12x8x4 in 3D),
+  // overridable (tuning sweeps) by PIC_FIELD_TILE=<variant>
+  c->tile = D == 2 ? 5 : (D == 3 ? 6 : 0);
   if (const char* tv = std::getenv("PIC_FIELD_TILE")) c->tile = std::max(0, std::min(atoi(tv), field_tile_variants() - 1));
   c->nb_cell = field_tiles(D, c->tile, (int)L.Px, (int)L.Py, (int)L.Pz);
   c->nb_win = 1;   // one block per instance (tile-sort scan)
@@ -1236,6 +1239,7 @@ static void batch_free_classes(pic_batch* b) {
   for (auto& cl : b->classes) {
     if (cl.d_insts) (void)hipFree(cl.d_insts);
     if (cl.d_off) (void)hipFree(cl.d_off);
+    if (cl.d_map) (void)hipFree(cl.d_map);
   }
   b->classes.clear();
 }
@@ -1271,10 +1275,19 @@ static pic_status batch_rebuild(pic_batch* b) {
       for (int ph = 0; ph < 4; ++ph) off[ph * (cl.n + 1) + i + 1] = off[ph * (cl.n + 1) + i] + nb[ph];
     }
     for (int ph = 0; ph < 4; ++ph) cl.blocks[ph] = off[ph * (cl.n + 1) + cl.n];
+    if (cl.n > 65535) return PIC_E_INVAL;
+    std::vector<unsigned short> map;
+    for (int ph = 0; ph < 4; ++ph) {
+      cl.map_off[ph] = (int)map.size();
+      for (int i = 0; i < cl.n; ++i)
+        map.insert(map.end(), off[ph * (cl.n + 1) + i + 1] - off[ph * (cl.n + 1) + i], (unsigned short)i);
+    }
     HIP_OK(hipMalloc(&cl.d_insts, sizeof(Inst) * cl.n));
     HIP_OK(hipMalloc(&cl.d_off, sizeof(int) * off.size()));
+    HIP_OK(hipMalloc(&cl.d_map, sizeof(unsigned short) * map.size()));
     HIP_OK(hipMemcpy(cl.d_insts, hi.data(), sizeof(Inst) * cl.n, hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(cl.d_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(cl.d_map, map.data(), sizeof(unsigned short) * map.size(), hipMemcpyHostToDevice));
   }
   b->dirty = false;
   return PIC_OK;
@@ -1294,10 +1307,10 @@ pic_status pic_batch_step(pic_batch* b, int64_t nsteps) {
     const bool sort_due = b->resort > 0 && b->tick++ % b->resort == 0;
     for (auto& cl : b->classes) {
       const int np1 = cl.n + 1;
-      Group gp{cl.d_insts, cl.d_off + 0 * np1, cl.n, cl.blocks[0], -1};
-      Group gc{cl.d_insts, cl.d_off + 1 * np1, cl.n, cl.blocks[1], -1, 1};
-      Group gs{cl.d_insts, cl.d_off + 2 * np1, cl.n, cl.blocks[2], -1};
-      Group gn{cl.d_insts, cl.d_off + 3 * np1, cl.n, cl.blocks[3], -1};
+      Group gp{cl.d_insts, cl.d_off + 0 * np1, cl.n, cl.blocks[0], -1, 0, cl.d_map + cl.map_off[0]};
+      Group gc{cl.d_insts, cl.d_off + 1 * np1, cl.n, cl.blocks[1], -1, 1, cl.d_map + cl.map_off[1]};
+      Group gs{cl.d_insts, cl.d_off + 2 * np1, cl.n, cl.blocks[2], -1, 0, cl.d_map + cl.map_off[2]};
+      Group gn{cl.d_insts, cl.d_off + 3 * np1, cl.n, cl.blocks[3], -1, 0, cl.d_map + cl.map_off[3]};
       if (sort_due) launch_sort(gp, gs, cl.D, s);
       launch_push(gp, cl.D, cl.order, s);
       launch_fields(gc, cl.D, cl.tile, s);   // far tiles skip the current
