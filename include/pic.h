@@ -247,9 +247,17 @@ pic_status pic_table_probe_device(pic_ctx* c, int32_t mat, const float* A, int64
 
 /* Batching of independent instances (fluence scans): one launch per phase
  * advances every member.  Members keep their own step counters; a member
- * added with pic_batch_add joins at the next step boundary. */
+ * added with pic_batch_add joins at the next step boundary.  pic_batch_step
+ * replays one sort period of batch steps (8) as a HIP graph, captured on a
+ * private stream at the first full period after a change of membership and
+ * launched on the members' stream; the steps before the next period boundary
+ * and the remainder run eagerly.  Results are those of eager stepping. */
 pic_status pic_batch_create(pic_ctx* const* members, int32_t n, pic_batch** out);
 pic_status pic_batch_step(pic_batch* b, int64_t nsteps);
+/* Graph replay of batch steps on (default) or off; off steps eagerly. */
+pic_status pic_batch_set_graph(pic_batch* b, int32_t on);
+/* Graph replays launched so far (each is one sort period of batch steps). */
+int64_t pic_batch_graph_replays(const pic_batch* b);
 pic_status pic_batch_add(pic_batch* b, pic_ctx* c);
 pic_status pic_batch_remove(pic_batch* b, pic_ctx* c);
 void pic_batch_destroy(pic_batch* b);

@@ -245,6 +245,13 @@ struct pic_batch {
   hipStream_t stream = nullptr;
   int resort = 8;     // tile-sort check every `resort` batch steps (0 = never)
   int64_t tick = 0;   // batch steps taken
+  // one sort period of batch steps captured as a HIP graph (recaptured after
+  // every change of membership), replayed on `stream`
+  int graph_on = 1;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int64_t replays = 0;
 };
 
 namespace {
@@ -1235,7 +1242,15 @@ pic_status pic_batch_create(pic_ctx* const* members, int32_t n, pic_batch** out)
   return PIC_OK;
 }
 
+static void batch_drop_graph(pic_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
 static void batch_free_classes(pic_batch* b) {
+  batch_drop_graph(b);
   for (auto& cl : b->classes) {
     if (cl.d_insts) (void)hipFree(cl.d_insts);
     if (cl.d_off) (void)hipFree(cl.d_off);
@@ -1293,17 +1308,9 @@ static pic_status batch_rebuild(pic_batch* b) {
   return PIC_OK;
 }
 
-pic_status pic_batch_step(pic_batch* b, int64_t nsteps) {
-  if (!b || nsteps < 0) return PIC_E_INVAL;
-  for (pic_ctx* c : b->members)
-    if (c->latched != PIC_OK) return PIC_E_STATE;
-  if (b->dirty) {
-    pic_status st = batch_rebuild(b);
-    if (st != PIC_OK) return st;
-  }
-  hipStream_t s = b->stream;
-  (void)hipGetLastError();
-  for (int64_t t = 0; t < nsteps; ++t) {
+// Enqueue k batch steps on stream s (the tick decides the sort checks).
+static void batch_enqueue(pic_batch* b, int64_t k, hipStream_t s) {
+  for (int64_t t = 0; t < k; ++t) {
     const bool sort_due = b->resort > 0 && b->tick++ % b->resort == 0;
     for (auto& cl : b->classes) {
       const int np1 = cl.n + 1;
@@ -1318,10 +1325,68 @@ pic_status pic_batch_step(pic_batch* b, int64_t nsteps) {
       launch_advance(cl.d_insts, cl.n, s);
     }
   }
+}
+
+// Capture `period` batch steps, starting at a tick that is a multiple of the
+// period (the first of them checks the sort), as a graph; false if capture is
+// not possible (the batch then steps eagerly).
+static bool batch_capture(pic_batch* b, int period) {
+  if (!b->cap && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) return false;
+  const int64_t tick = b->tick;
+  if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
+  batch_enqueue(b, period, b->cap);
+  b->tick = tick;   // nothing ran: the capture only recorded the launches
+  hipGraph_t g = nullptr;
+  if (hipStreamEndCapture(b->cap, &g) != hipSuccess || !g) return false;
+  b->graph = g;
+  if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    batch_drop_graph(b);
+    return false;
+  }
+  return true;
+}
+
+pic_status pic_batch_step(pic_batch* b, int64_t nsteps) {
+  if (!b || nsteps < 0) return PIC_E_INVAL;
+  for (pic_ctx* c : b->members)
+    if (c->latched != PIC_OK) return PIC_E_STATE;
+  if (b->dirty) {
+    pic_status st = batch_rebuild(b);
+    if (st != PIC_OK) return st;
+  }
+  hipStream_t s = b->stream;
+  (void)hipGetLastError();
+  int64_t left = nsteps;
+  const int period = b->resort > 0 ? b->resort : 8;
+  if (b->graph_on && !b->classes.empty() && period <= 64 && left >= period) {
+    // eager steps up to the next multiple of the sort period, then replays
+    const int64_t lead = std::min<int64_t>(left, (period - b->tick % period) % period);
+    batch_enqueue(b, lead, s);
+    left -= lead;
+    if (left >= period && !b->exec && !batch_capture(b, period)) {
+      (void)hipGetLastError();
+      b->graph_on = 0;   // capture unavailable: step eagerly from now on
+    }
+    while (b->exec && left >= period) {
+      if (hipGraphLaunch(b->exec, s) != hipSuccess) return PIC_E_DEVICE;
+      b->tick += period;
+      left -= period;
+      ++b->replays;
+    }
+  }
+  batch_enqueue(b, left, s);
   for (pic_ctx* c : b->members) c->step += nsteps;
   if (hipGetLastError() != hipSuccess) return PIC_E_DEVICE;
   return PIC_OK;
 }
+
+pic_status pic_batch_set_graph(pic_batch* b, int32_t on) {
+  if (!b) return PIC_E_INVAL;
+  b->graph_on = on ? 1 : 0;
+  return PIC_OK;
+}
+
+int64_t pic_batch_graph_replays(const pic_batch* b) { return b ? b->replays : 0; }
 
 pic_status pic_batch_add(pic_batch* b, pic_ctx* c) {
   if (!b || !c) return PIC_E_INVAL;
@@ -1346,6 +1411,7 @@ void pic_batch_destroy(pic_batch* b) {
   if (!b) return;
   if (b->stream) (void)hipStreamSynchronize(b->stream); else (void)hipDeviceSynchronize();
   batch_free_classes(b);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
   delete b;
 }
 

@@ -90,7 +90,8 @@ class State(C.Structure):
 
 SYMBOLS = ["pic_init", "pic_step", "pic_diag", "pic_set_state", "pic_footprint", "pic_canonical",
            "pic_keldysh_rate", "pic_table_probe", "pic_table_probe_device", "pic_batch_create",
-           "pic_batch_step", "pic_batch_add", "pic_batch_remove", "pic_batch_destroy",
+           "pic_batch_step", "pic_batch_add", "pic_batch_remove", "pic_batch_destroy", "pic_batch_set_graph",
+           "pic_batch_graph_replays",
            "pic_set_timing", "pic_autotune", "pic_autotune_steps", "pic_set_resort", "pic_set_far_tiles",
            "pic_destroy", "pic_status_str"]
 
@@ -132,6 +133,8 @@ def lib():
             "pic_autotune_steps": ([vp, i32], C.c_int),
             "pic_set_resort": ([vp, i32], C.c_int),
             "pic_set_far_tiles": ([vp, i32], C.c_int),
+            "pic_batch_set_graph": ([vp, i32], C.c_int),
+            "pic_batch_graph_replays": ([vp], C.c_int64),
             "pic_destroy": ([vp], None),
             "pic_status_str": ([C.c_int], C.c_char_p),
         }
@@ -414,6 +417,13 @@ class Batch:
 
     def step(self, n=1):
         _check(lib().pic_batch_step(self.h, int(n)), "pic_batch_step")
+
+    def set_graph(self, on):
+        """Replay sort periods of batch steps as a HIP graph (default) or step eagerly."""
+        _check(lib().pic_batch_set_graph(self.h, int(on)), "pic_batch_set_graph")
+
+    def graph_replays(self):
+        return int(lib().pic_batch_graph_replays(self.h))
 
     def add(self, ctx):
         _check(lib().pic_batch_add(self.h, ctx.h), "pic_batch_add")

@@ -428,6 +428,60 @@ def test_batch_matches_single_runs(P):
         x.close()
 
 
+def test_batch_graph_replays_match_eager(P):
+    """Batch steps replayed as a captured HIP graph (one sort period per
+    replay) against the same members stepped eagerly: after every replay
+    chunk, with eager work and synchronisation on the stream in between (a
+    diagnostic of every member), fields, events and counts agree (FP32
+    atomic-order noise only); then a member joins, the graph is captured
+    again, and the replays still agree."""
+    cfgs = [W.config_2d(nx=128, ny=32, nsteps=400, ppc=2, peak=3e14, slab_cells=10, waist=0.6e-6, seed=s)
+            for s in (5, 6)]
+    cfgs.append(W.config_1d(hi=True, ppc=4, nsteps=400, n=256))
+    late = W.config_2d(nx=96, ny=24, nsteps=400, ppc=2, peak=3e14, slab_cells=8, waist=0.6e-6, seed=7)
+
+    def l2(fa, fb):
+        num = sum(np.sum((a - c) ** 2) for a, c in zip(fa[0] + fa[1], fb[0] + fb[1]))
+        den = sum(np.sum(c ** 2) for c in fb[0] + fb[1])
+        return math.sqrt(num / den) if den > 0 else math.sqrt(num)
+
+    sets = []
+    for graph in (1, 0):
+        ctxs = [P.Context(c) for c in cfgs]
+        b = P.Batch(ctxs)
+        b.set_graph(graph)
+        sets.append((ctxs, b))
+    (cg, bg), (ce, be) = sets
+    def compare():
+        for xg, xe in zip(cg, ce):
+            sg, se = xg.scalars(), xe.scalars()       # eager work + sync between replays
+            assert sg["step"] == se["step"]
+            assert l2(xg.fields(), xe.fields()) < 1e-5
+            eg, ee = set(map(tuple, xg.events().tolist())), set(map(tuple, xe.events().tolist()))
+            assert len(eg ^ ee) <= max(1, int(1e-4 * len(eg | ee)))
+    bg.step(3)          # eager lead-in, then the first full period is captured
+    be.step(3)
+    for chunk in (21, 16, 40):
+        bg.step(chunk)
+        be.step(chunk)
+        compare()
+    assert bg.graph_replays() >= 8 and be.graph_replays() == 0
+    cg.append(P.Context(late))
+    ce.append(P.Context(late))
+    bg.add(cg[-1])
+    be.add(ce[-1])
+    before = bg.graph_replays()
+    for chunk in (13, 32):
+        bg.step(chunk)
+        be.step(chunk)
+        compare()
+    assert bg.graph_replays() >= before + 4
+    for ctxs, b in sets:
+        b.close()
+        for x in ctxs:
+            x.close()
+
+
 def test_autotune_restores_initial_state(P):
     """The tile autotuner runs field launches on the initial state and clears it
     again: a tuned run and an untuned run of the same problem agree."""
