@@ -20,6 +20,14 @@ struct Group {
   // batches: the instance of every block (one load instead of a binary search
   // over `off`); null for a single run
   const unsigned short* map = nullptr;
+  // a single run's field front and charged-region slots, read directly so
+  // they load alongside the instance block instead of after it; null in
+  // batches (each instance's own, through its parameter block)
+  int* front = nullptr;
+  const int* xext = nullptr;
+  // host copy of a single run's parameter block: the field launch passes it
+  // by value, so its fields load from the kernel arguments
+  const Inst* host = nullptr;
 };
 
 constexpr int TPB = 256;

@@ -35,6 +35,24 @@ __device__ __forceinline__ int find_inst(const Group& g) {
   return lo;
 }
 
+// Instance of this block, the block's index within the instance's range and
+// the range's length.  A single run (one instance, offsets {0, blocks}) needs
+// no memory access for this.
+struct Slot {
+  int ii, bk, nbk;
+};
+__device__ __forceinline__ Slot block_slot(const Group& g) {
+  if (g.n == 1) return {0, (int)blockIdx.x, g.blocks};
+  const int ii = find_inst(g);
+  return {ii, (int)blockIdx.x - g.off[ii], g.off[ii + 1] - g.off[ii]};
+}
+
+// The parameter block of a kernel launched either for a single run (the
+// block itself passed by value) or for a batch (an array indexed per block).
+struct NoInst {};
+__device__ __forceinline__ const Inst& inst_of(const Group&, int, const Inst& one) { return one; }
+__device__ __forceinline__ const Inst& inst_of(const Group& g, int ii, NoInst) { return g.insts[ii]; }
+
 // Workgroups are dispatched to the 8 XCDs (each with its own L2) round robin,
 // block b going to XCD b mod 8.  Work index of block b of nb such that every
 // XCD walks a contiguous range of the work (neighbouring tiles share halo
@@ -1092,9 +1110,11 @@ __device__ __forceinline__ unsigned axis_bits(int v, int n, bool per, bool inarr
 // One block = one tile of owned positions plus a halo of 2 on each side of
 // every present axis, all six field components staged in LDS.  Row and plane
 // offsets (periodic axes wrapped) and per-axis validity bits are tabulated
-// once per block.
-template <int D, int V>
-__global__ __launch_bounds__(TPB) void k_fields(Group g) {
+// once per block.  ONE: a single run whose parameter block, step index and
+// front and charged-range addresses come in the launch, so that the first
+// loads of a block are one round trip instead of a chain of dependent ones.
+template <int D, int V, bool ONE>
+__global__ __launch_bounds__(TPB) void k_fields(Group g, std::conditional_t<ONE, Inst, NoInst> one) {
   using T = TileT<D, V>;
   constexpr int H = 2;
   constexpr int RX = T::X + 2 * H;
@@ -1109,19 +1129,21 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
   __shared__ float sieh[RX], sien[RX];
   __shared__ int blk_hot;
   constexpr int KMAX = (NR + TPB - 1) / TPB;   // staged points per thread
-  const int ii = find_inst(g);
-  const Inst& I = g.insts[ii];
-  const int Px = I.Px, Py = I.Py, Pz = I.Pz;
-  const int ntx = (Px + T::X - 1) / T::X;
-  const int nty = D >= 2 ? (Py + T::Y - 1) / T::Y : 1;
-  const int nbk = g.off[ii + 1] - g.off[ii];
-  const int bk = blockIdx.x - g.off[ii];
-  const int nx = I.nx, ny = I.ny, nz = I.nz;
-  const bool py = I.per_y, pz = I.per_z;
-  const int sy = I.sy, sz = I.sz;
-  const int Gy = I.Gy, Gz = I.Gz;
-  const int step = g.step >= 0 ? g.step : *I.step;
+  const Slot sl = ONE ? Slot{0, (int)blockIdx.x, g.blocks} : block_slot(g);
+  const Inst& I = inst_of(g, sl.ii, one);
+  // step parity in a scalar register, so the field pointers load as scalars
+  const int step = ONE || g.step >= 0 ? g.step : __builtin_amdgcn_readfirstlane(*gp(I.step));
   const int par = step & 1;
+  // the field front (the last x column of a tile that has stored a nonzero E
+  // or b) and the charged x range, first used after the axis tables.  Relaxed
+  // atomic loads (plain loads in the instruction stream) are issued here and
+  // not moved down to their first use; another tile raising the front during
+  // this launch only makes the test below more conservative.
+  int* const frontp = ONE ? g.front : I.front;
+  gmem<int>* const xe = gp(const_cast<int*>(ONE ? g.xext : I.xext) + 2 * (step % 3));
+  const int front = __hip_atomic_load(gp(frontp), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  const int xlo = __hip_atomic_load(xe, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  const int xhi = __hip_atomic_load(xe + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   const gmem<float>* __restrict__ Ec0 = gp(uniform(I.F[par][0]));
   const gmem<float>* __restrict__ Ec1 = gp(uniform(I.F[par][1]));
   const gmem<float>* __restrict__ Ec2 = gp(uniform(I.F[par][2]));
@@ -1144,6 +1166,14 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
   const gmem<float>* __restrict__ ien = gp(I.ie_node);
   const float hx = I.halfC[0], hy = I.halfC[1], hz = I.halfC[2];
   const float Cx = I.C[0], Cy = I.C[1], Cz = I.C[2];
+  const int Px = I.Px, Py = I.Py, Pz = I.Pz;
+  const int ntx = (Px + T::X - 1) / T::X;
+  const int nty = D >= 2 ? (Py + T::Y - 1) / T::Y : 1;
+  const int nbk = sl.nbk, bk = sl.bk;
+  const int nx = I.nx, ny = I.ny, nz = I.nz;
+  const bool py = I.per_y, pz = I.per_z;
+  const int sy = I.sy, sz = I.sz;
+  const int Gy = I.Gy, Gz = I.Gz;
   auto split = [&](int l, int& qx, int& qy, int& qz) {
     qx = l % RX;
     qy = D >= 2 ? (l / RX) % RY : 0;
@@ -1152,23 +1182,6 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
   // one block per tile; each XCD walks a contiguous range of tiles
   const int tb = xcd_remap(bk, nbk);
   const int tx = tb % ntx, rest = tb / ntx;
-  // far tiles: x columns farther than XNEAR_MARGIN cells from every cell that
-  // held a charged particle so far and from the amplitude window have carried
-  // no current, ever, so their update neither reads nor clears it
-  bool cur = true;
-  if (g.part >= 1) {
-    const int* xe = I.xext + 2 * (step % 3);
-    int lo = xe[0], hi = xe[1];
-    if (I.wx1 > I.wx0) {
-      lo = min(lo, I.wx0 - G);
-      hi = max(hi, I.wx1 - 1 - G);
-    }
-    const int alo = lo - XNEAR_MARGIN + G, ahi = hi + XNEAR_MARGIN + G;
-    cur = lo <= hi && tx * T::X <= ahi && tx * T::X + T::X - 1 >= alo;
-  }
-  // the field front: the last x column of a tile that has stored a nonzero E
-  // or b (loaded now, tested after the axis tables)
-  const int front = *I.front;
   const int a0x = tx * T::X;
   const int a0y = D >= 2 ? (rest % nty) * T::Y : 0;
   const int a0z = D >= 3 ? (rest / nty) * T::Z : 0;
@@ -1213,6 +1226,19 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
       sbz[q] = AX_BN | AX_BH | AX_IN | AX_IH | AX_DN | AX_DH | AX_ARR;
       soz[q] = 0;
     }
+  }
+  // far tiles: x columns farther than XNEAR_MARGIN cells from every cell that
+  // held a charged particle so far and from the amplitude window have carried
+  // no current, ever, so their update neither reads nor clears it
+  bool cur = true;
+  if (g.part >= 1) {
+    int lo = xlo, hi = xhi;
+    if (I.wx1 > I.wx0) {
+      lo = min(lo, I.wx0 - G);
+      hi = max(hi, I.wx1 - 1 - G);
+    }
+    const int alo = lo - XNEAR_MARGIN + G, ahi = hi + XNEAR_MARGIN + G;
+    cur = lo <= hi && tx * T::X <= ahi && tx * T::X + T::X - 1 >= alo;
   }
   // a far tile whose staged x range lies beyond the front has zero inputs
   // (the update moves the front by at most two cells per step): its outputs
@@ -1471,7 +1497,7 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g) {
   else phase_e(std::false_type{});
   // a tile reaching past the field front moves it if it stored a nonzero value
   if (track) {
-    if (__syncthreads_or(stored_nz) && threadIdx.x == 0) atomicMax(I.front, a0x + T::X - 1);
+    if (__syncthreads_or(stored_nz) && threadIdx.x == 0) atomicMax(frontp, a0x + T::X - 1);
   } else {
     __syncthreads();
   }
@@ -1805,8 +1831,15 @@ void launch_sort(const Group& gp, const Group& gscan, int D, hipStream_t s, Stam
   DISPATCH_D(D, GO((k_sort_scatter<DD>), gp.blocks, TPB, s, none, none, gp));
   DISPATCH_D(D, GO((k_sort_group<DD>), gp.blocks, TPB, s, none, st.stop, gp));
 }
-#define FIELDS_V(DD, V) GO((k_fields<DD, V>), g.blocks, TPB, s, st.start, st.stop, g)
+#define FIELDS_V(DD, V)                                                               \
+  do {                                                                                \
+    if (one)                                                                          \
+      GO((k_fields<DD, V, true>), g.blocks, TPB, s, st.start, st.stop, g, *g.host);   \
+    else                                                                              \
+      GO((k_fields<DD, V, false>), g.blocks, TPB, s, st.start, st.stop, g, NoInst{}); \
+  } while (0)
 void launch_fields(const Group& g, int D, int variant, hipStream_t s, Stamp st) {
+  const bool one = g.n == 1 && g.host && g.front && g.xext && g.step >= 0;
   switch (variant) {
     case 1: DISPATCH_D(D, FIELDS_V(DD, 1)); break;
     case 2: DISPATCH_D(D, FIELDS_V(DD, 2)); break;

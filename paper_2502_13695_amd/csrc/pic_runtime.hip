@@ -264,7 +264,11 @@ namespace {
 inline void* devp(pic_ctx* c, size_t off) { return c->base + off; }
 
 Group single(pic_ctx* c, int phase, int nb) {
-  return Group{c->d_inst, phase == 1 ? c->d_off_fields : c->d_off + 2 * phase, 1, nb, (int)c->step};
+  Group g{c->d_inst, phase == 1 ? c->d_off_fields : c->d_off + 2 * phase, 1, nb, (int)c->step};
+  g.front = &c->d_ctr->front;
+  g.xext = c->d_ctr->xext;
+  g.host = &c->h;
+  return g;
 }
 
 // Timing events: no system-scope fence when they complete, so stamping a
@@ -363,8 +367,11 @@ void enqueue_step(pic_ctx* c) {
     const Layout& L = c->L;
     // every tile is updated while the shapes are timed (with tiles beyond the
     // field front skipped, the first steps would time an unrepresentative load)
-    const Group gv{c->d_inst, c->d_off + 8 + 2 * v, 1, field_tiles(D, v, (int)L.Px, (int)L.Py, (int)L.Pz),
-                   (int)c->step, c->far_skip ? 2 : 0};
+    Group gv{c->d_inst, c->d_off + 8 + 2 * v, 1, field_tiles(D, v, (int)L.Px, (int)L.Py, (int)L.Pz),
+             (int)c->step, c->far_skip ? 2 : 0};
+    gv.front = &c->d_ctr->front;
+    gv.xext = c->d_ctr->xext;
+    gv.host = &c->h;
     launch_fields(gv, D, v, s, Stamp{c->tune_ev[v][r][0], c->tune_ev[v][r][1]});
     if (--c->tune_left == 0) finish_tuning(c);
   } else {
