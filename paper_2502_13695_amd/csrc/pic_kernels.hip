@@ -592,18 +592,19 @@ __device__ __forceinline__ void push_one(const Inst& I, const PushFields& f, con
 // window in LDS and clears its current window, pushes the chunk's particles,
 // then adds the current window's nonzero nodes to HBM with one atomic each --
 // then the unsorted tail (births since the sort) through HBM.
-template <int D, int ORDER>
-__global__ __launch_bounds__(push_tpb(D)) void k_push(Group g) {
+// ONE: a single run, its parameter block passed by value.
+template <int D, int ORDER, bool ONE>
+__global__ __launch_bounds__(push_tpb(D)) void k_push(Group g, std::conditional_t<ONE, Inst, NoInst> one) {
   constexpr int NT = push_tpb(D);
   __shared__ unsigned long long sJ[3 * PWin<D>::N];
   __shared__ float sF[push_stage_fields(D) ? 6 * FWin<D>::N : 1];
-  const int ii = find_inst(g);
-  const Inst& I = g.insts[ii];
-  const int nb = g.off[ii + 1] - g.off[ii];
-  const int b0 = blockIdx.x - g.off[ii];
+  const Slot sl = ONE ? Slot{0, (int)blockIdx.x, g.blocks} : block_slot(g);
+  const Inst& I = inst_of(g, sl.ii, one);
+  const int nb = sl.nbk;
+  const int b0 = sl.bk;
   int count = *I.pcount;
   count = count < I.capacity ? count : I.capacity;
-  const int step = g.step >= 0 ? g.step : *I.step;
+  const int step = ONE || g.step >= 0 ? g.step : *I.step;
   const int par = step & 1;
   int xlo = 1 << 30, xhi = -(1 << 30);   // x cells of this block's particles after the move
   const PushFields f{uniform(I.F[par][0]), uniform(I.F[par][1]), uniform(I.F[par][2]),
@@ -1541,17 +1542,17 @@ __device__ __forceinline__ void ionize_one(const Inst& I, int64_t jn, int step);
 // largest windowed amplitude over the nodes any neutral of the cell can reach
 // must reach the material's cut (an exact test: the shape weights are
 // non-negative and sum to one).  Neutrals of the other cells read nothing more.
-template <int D, int ORDER>
-__global__ __launch_bounds__(TPB) void k_ionize(Group g) {
+template <int D, int ORDER, bool ONE>
+__global__ __launch_bounds__(TPB) void k_ionize(Group g, std::conditional_t<ONE, Inst, NoInst> one) {
   __shared__ unsigned char hot[TPB + 2];
-  const int ii = find_inst(g);
-  const Inst& I = g.insts[ii];
-  const int step = g.step >= 0 ? g.step : *I.step;
+  const Slot sl = ONE ? Slot{0, (int)blockIdx.x, g.blocks} : block_slot(g);
+  const Inst& I = inst_of(g, sl.ii, one);
+  const int step = ONE || g.step >= 0 ? g.step : *I.step;
   // the flag of the next step is raised by its field update, which runs after
   // this kernel; a cold grid (no amplitude at any cut) ionizes nothing
-  if (blockIdx.x == g.off[ii] && threadIdx.x == 0) I.hot[(step + 1) & 1] = 0;
+  if (sl.bk == 0 && threadIdx.x == 0) I.hot[(step + 1) & 1] = 0;
   if (!I.hot[step & 1]) return;
-  const int64_t j0 = (int64_t)xcd_remap(blockIdx.x - g.off[ii], g.off[ii + 1] - g.off[ii]) * TPB;
+  const int64_t j0 = (int64_t)xcd_remap(sl.bk, sl.nbk) * TPB;
   const int64_t nneut = I.nneut;
   if (j0 >= nneut) return;
   const int64_t m0 = div_ppc(I, j0);
@@ -1817,11 +1818,21 @@ __global__ void k_table_probe(const TabHdr* tab, const float* A, float* P, int64
       hipLaunchKernelGGL(K, dim3(grid), dim3(block), 0, s, __VA_ARGS__);                  \
   } while (0)
 
+// a single run passes its parameter block by value (see k_fields)
+#define ONE_OR_GROUP(KT, tpb, ...)                                                    \
+  do {                                                                                \
+    if (one)                                                                          \
+      GO((KT<__VA_ARGS__, true>), g.blocks, tpb, s, st.start, st.stop, g, *g.host);   \
+    else                                                                              \
+      GO((KT<__VA_ARGS__, false>), g.blocks, tpb, s, st.start, st.stop, g, NoInst{}); \
+  } while (0)
 void launch_push(const Group& g, int D, int order, hipStream_t s, Stamp st) {
+  // not in 3D: the parameter block in scalar registers makes that push spill
+  const bool one = D < 3 && g.n == 1 && g.host && g.step >= 0;
   if (order == 1) {
-    DISPATCH_D(D, GO((k_push<DD, 1>), g.blocks, push_tpb(DD), s, st.start, st.stop, g));
+    DISPATCH_D(D, ONE_OR_GROUP(k_push, push_tpb(DD), DD, 1));
   } else {
-    DISPATCH_D(D, GO((k_push<DD, 2>), g.blocks, push_tpb(DD), s, st.start, st.stop, g));
+    DISPATCH_D(D, ONE_OR_GROUP(k_push, push_tpb(DD), DD, 2));
   }
 }
 void launch_sort(const Group& gp, const Group& gscan, int D, hipStream_t s, Stamp st) {
@@ -1831,13 +1842,7 @@ void launch_sort(const Group& gp, const Group& gscan, int D, hipStream_t s, Stam
   DISPATCH_D(D, GO((k_sort_scatter<DD>), gp.blocks, TPB, s, none, none, gp));
   DISPATCH_D(D, GO((k_sort_group<DD>), gp.blocks, TPB, s, none, st.stop, gp));
 }
-#define FIELDS_V(DD, V)                                                               \
-  do {                                                                                \
-    if (one)                                                                          \
-      GO((k_fields<DD, V, true>), g.blocks, TPB, s, st.start, st.stop, g, *g.host);   \
-    else                                                                              \
-      GO((k_fields<DD, V, false>), g.blocks, TPB, s, st.start, st.stop, g, NoInst{}); \
-  } while (0)
+#define FIELDS_V(DD, V) ONE_OR_GROUP(k_fields, TPB, DD, V)
 void launch_fields(const Group& g, int D, int variant, hipStream_t s, Stamp st) {
   const bool one = g.n == 1 && g.host && g.front && g.xext && g.step >= 0;
   switch (variant) {
@@ -1857,10 +1862,11 @@ int field_tiles(int D, int variant, int Px, int Py, int Pz) {
 int field_tile_variants() { return kTileVariants; }
 int field_tile_x(int D, int variant) { return tile_shape(D, variant).x; }
 void launch_ionize(const Group& g, int D, int order, hipStream_t s, Stamp st) {
+  const bool one = g.n == 1 && g.host && g.step >= 0;
   if (order == 1) {
-    DISPATCH_D(D, GO((k_ionize<DD, 1>), g.blocks, TPB, s, st.start, st.stop, g));
+    DISPATCH_D(D, ONE_OR_GROUP(k_ionize, TPB, DD, 1));
   } else {
-    DISPATCH_D(D, GO((k_ionize<DD, 2>), g.blocks, TPB, s, st.start, st.stop, g));
+    DISPATCH_D(D, ONE_OR_GROUP(k_ionize, TPB, DD, 2));
   }
 }
 void launch_advance(const Inst* insts, int n, hipStream_t s) {

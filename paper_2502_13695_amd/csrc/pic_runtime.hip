@@ -845,6 +845,9 @@ pic_status pic_autotune(pic_ctx* c, int32_t reps) {
       offs[1] = nb;
       HIP_OK(hipMemcpy(c->d_off + 2, offs, sizeof offs, hipMemcpyHostToDevice));
       Group gr{c->d_inst, c->d_off + 2, 1, nb, 0};
+      gr.front = &c->d_ctr->front;
+      gr.xext = c->d_ctr->xext;
+      gr.host = &c->h;
       launch_fields(gr, D, v, s);   // warm
       HIP_OK(hipEventRecord(e0, s));
       for (int r = 0; r < reps; ++r) launch_fields(gr, D, v, s);
