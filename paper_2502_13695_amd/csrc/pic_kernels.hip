@@ -51,7 +51,10 @@ __device__ __forceinline__ Slot block_slot(const Group& g) {
 // block itself passed by value) or for a batch (an array indexed per block).
 struct NoInst {};
 __device__ __forceinline__ const Inst& inst_of(const Group&, int, const Inst& one) { return one; }
-__device__ __forceinline__ const Inst& inst_of(const Group& g, int ii, NoInst) { return g.insts[ii]; }
+// Batches: no kernel writes the array, so it is read through the constant
+// address space (its fields are not reloaded after every other store).
+using CInst = const __attribute__((address_space(4))) Inst;
+__device__ __forceinline__ CInst& inst_of(const Group& g, int ii, NoInst) { return *(CInst*)(g.insts + ii); }
 
 // Workgroups are dispatched to the 8 XCDs (each with its own L2) round robin,
 // block b going to XCD b mod 8.  Work index of block b of nb such that every
@@ -451,8 +454,8 @@ __device__ __forceinline__ float gather_l(const float* __restrict__ S, const Axi
 // Boris, move, deposit and write-back of one charged particle.  LOCAL: the
 // particle started inside the block's tile -- fields from the LDS window
 // (origin fx0, fy0, fz0), current into the LDS sink; else HBM for both.
-template <int D, int ORDER, bool LOCAL, bool LF = LOCAL && push_stage_fields(D)>
-__device__ __forceinline__ void push_body(const Inst& I, const PushFields& f, const float* sF, int fx0,
+template <int D, int ORDER, bool LOCAL, bool LF = LOCAL && push_stage_fields(D), class IT = Inst>
+__device__ __forceinline__ void push_body(const IT& I, const PushFields& f, const float* sF, int fx0,
                                           int fy0, int fz0, const GSink& gs, const LSink<D>& ls,
                                           unsigned q, uint8_t kind, int ci, int cj, int ck, float t0,
                                           float t1, float t2, float ux, float uy, float uz, int& xlo,
@@ -555,8 +558,8 @@ __device__ __forceinline__ void push_body(const Inst& I, const PushFields& f, co
 // One charged particle (slot p).  TILED: the block holds the LDS windows of
 // the tile with origin (tx0, ty0, tz0); a particle that started the step
 // outside that tile goes through HBM and is counted as a drifter.
-template <int D, int ORDER, bool TILED>
-__device__ __forceinline__ void push_one(const Inst& I, const PushFields& f, const float* sF,
+template <int D, int ORDER, bool TILED, class IT>
+__device__ __forceinline__ void push_one(const IT& I, const PushFields& f, const float* sF,
                                          const GSink& gs, const LSink<D>& ls, int tx0, int ty0,
                                          int tz0, int p, bool valid, int& xlo, int& xhi) {
   const unsigned q = (unsigned)p;
@@ -599,7 +602,7 @@ __global__ __launch_bounds__(push_tpb(D)) void k_push(Group g, std::conditional_
   __shared__ unsigned long long sJ[3 * PWin<D>::N];
   __shared__ float sF[push_stage_fields(D) ? 6 * FWin<D>::N : 1];
   const Slot sl = ONE ? Slot{0, (int)blockIdx.x, g.blocks} : block_slot(g);
-  const Inst& I = inst_of(g, sl.ii, one);
+  auto& I = inst_of(g, sl.ii, one);
   const int nb = sl.nbk;
   const int b0 = sl.bk;
   int count = *I.pcount;
@@ -1131,7 +1134,7 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g, std::conditional_t<ONE,
   __shared__ int blk_hot;
   constexpr int KMAX = (NR + TPB - 1) / TPB;   // staged points per thread
   const Slot sl = ONE ? Slot{0, (int)blockIdx.x, g.blocks} : block_slot(g);
-  const Inst& I = inst_of(g, sl.ii, one);
+  auto& I = inst_of(g, sl.ii, one);
   // step parity in a scalar register, so the field pointers load as scalars
   const int step = ONE || g.step >= 0 ? g.step : __builtin_amdgcn_readfirstlane(*gp(I.step));
   const int par = step & 1;
@@ -1521,12 +1524,13 @@ __device__ __forceinline__ void maxwell(uint64_t seed, uint64_t id, uint32_t pur
   uz = sig * r2 * cosf(tp * u4);
 }
 
-__device__ __forceinline__ int64_t div_ppc(const Inst& I, int64_t j) {
+template <class IT>
+__device__ __forceinline__ int64_t div_ppc(const IT& I, int64_t j) {
   return I.ppc == 1 ? j : (int64_t)__umul64hi((uint64_t)j, I.ppc_magic);
 }
 
-template <int D>
-__device__ __forceinline__ uint64_t neutral_id(const Inst& I, int64_t jn, int& ci, int& cj, int& ck) {
+template <int D, class IT>
+__device__ __forceinline__ uint64_t neutral_id(const IT& I, int64_t jn, int& ci, int& cj, int& ck) {
   const int64_t m = div_ppc(I, jn);
   const int64_t kk = jn - m * I.ppc;
   unpack_cell(D, I.mcell[m], ci, cj, ck);
@@ -1534,8 +1538,8 @@ __device__ __forceinline__ uint64_t neutral_id(const Inst& I, int64_t jn, int& c
   return (uint64_t)(lin * I.ppc + kk);
 }
 
-template <int D, int ORDER>
-__device__ __forceinline__ void ionize_one(const Inst& I, int64_t jn, int step);
+template <int D, int ORDER, class IT>
+__device__ __forceinline__ void ionize_one(const IT& I, int64_t jn, int step);
 
 // Ionization of the alive neutrals with the amplitude after the field update.
 // A block first marks which of its material cells can ionize at all: the
@@ -1546,7 +1550,7 @@ template <int D, int ORDER, bool ONE>
 __global__ __launch_bounds__(TPB) void k_ionize(Group g, std::conditional_t<ONE, Inst, NoInst> one) {
   __shared__ unsigned char hot[TPB + 2];
   const Slot sl = ONE ? Slot{0, (int)blockIdx.x, g.blocks} : block_slot(g);
-  const Inst& I = inst_of(g, sl.ii, one);
+  auto& I = inst_of(g, sl.ii, one);
   const int step = ONE || g.step >= 0 ? g.step : *I.step;
   // the flag of the next step is raised by its field update, which runs after
   // this kernel; a cold grid (no amplitude at any cut) ionizes nothing
@@ -1583,8 +1587,8 @@ __global__ void k_advance(const Inst* insts, int n) {
   if (i < n) *insts[i].step += 1;
 }
 
-template <int D, int ORDER>
-__device__ __forceinline__ void ionize_one(const Inst& I, int64_t jn, int step) {
+template <int D, int ORDER, class IT>
+__device__ __forceinline__ void ionize_one(const IT& I, int64_t jn, int step) {
   if (!((I.alive[jn >> 5] >> (jn & 31)) & 1u)) return;
   int ci, cj, ck;
   const uint64_t id = neutral_id<D>(I, jn, ci, cj, ck);
@@ -1827,8 +1831,7 @@ __global__ void k_table_probe(const TabHdr* tab, const float* A, float* P, int64
       GO((KT<__VA_ARGS__, false>), g.blocks, tpb, s, st.start, st.stop, g, NoInst{}); \
   } while (0)
 void launch_push(const Group& g, int D, int order, hipStream_t s, Stamp st) {
-  // not in 3D: the parameter block in scalar registers makes that push spill
-  const bool one = D < 3 && g.n == 1 && g.host && g.step >= 0;
+  const bool one = g.n == 1 && g.host && g.step >= 0;
   if (order == 1) {
     DISPATCH_D(D, ONE_OR_GROUP(k_push, push_tpb(DD), DD, 1));
   } else {
