@@ -729,8 +729,8 @@ __global__ __launch_bounds__(push_tpb(D)) void k_push(Group g, std::conditional_
 // dropped), then one block per group writes the group back in level order.
 // The first kernel decides, identically in every block, whether a sort is
 // due; the others follow its decision.
-template <int D>
-__device__ __forceinline__ void group_of(const Inst& I, uint32_t pc, int& g, int& c) {
+template <int D, class IT>
+__device__ __forceinline__ void group_of(const IT& I, uint32_t pc, int& g, int& c) {
   int i, j, k;
   unpack_cell(D, pc, i, j, k);
   constexpr int TX = ptile_ext(D, 0), TY = ptile_ext(D, 1), TZ = ptile_ext(D, 2);
@@ -770,7 +770,7 @@ __device__ __forceinline__ int wave_rank_add(int* arr, int t) {
 template <int D>
 __global__ __launch_bounds__(TPB) void k_sort_count(Group g) {
   const int ii = find_inst(g);
-  const Inst& I = g.insts[ii];
+  auto& I = inst_of(g, ii, NoInst{});
   const int nb = g.off[ii + 1] - g.off[ii];
   const int b0 = blockIdx.x - g.off[ii];
   int count = *I.pcount;
@@ -800,7 +800,7 @@ __global__ __launch_bounds__(SCAN_TPB) void k_sort_scan(Group g) {
   constexpr int TPB = SCAN_TPB;
   __shared__ long long sp[TPB], sc[TPB];
   const int ii = find_inst(g);
-  const Inst& I = g.insts[ii];
+  auto& I = inst_of(g, ii, NoInst{});
   if (!I.sctl[SC_GO]) return;
   constexpr int GPT = ptile_cells(D) / PT_GROUP;
   const int nt = I.ntiles;
@@ -853,7 +853,7 @@ __global__ __launch_bounds__(SCAN_TPB) void k_sort_scan(Group g) {
 template <int D>
 __global__ __launch_bounds__(TPB) void k_sort_scatter(Group g) {
   const int ii = find_inst(g);
-  const Inst& I = g.insts[ii];
+  auto& I = inst_of(g, ii, NoInst{});
   if (!I.sctl[SC_GO]) return;
   const int nb = g.off[ii + 1] - g.off[ii];
   const int b0 = blockIdx.x - g.off[ii];
@@ -884,8 +884,8 @@ __global__ __launch_bounds__(TPB) void k_sort_scatter(Group g) {
   }
 }
 
-template <int D>
-__device__ __forceinline__ void sort_move(const Inst& I, int from, int to) {
+template <int D, class IT>
+__device__ __forceinline__ void sort_move(const IT& I, int from, int to) {
   I.pcell[to] = I.scell[from];
   I.pkind[to] = I.skind[from];
   I.po0[to] = I.so0[from];
@@ -925,7 +925,7 @@ __global__ __launch_bounds__(TPB) void k_sort_group(Group g) {
   __shared__ unsigned short spos[WPB][SORT_GWAVE];
   __shared__ unsigned sbuf[WPB][SORT_GWAVE];
   const int ii = find_inst(g);
-  const Inst& I = g.insts[ii];
+  auto& I = inst_of(g, ii, NoInst{});
   if (!I.sctl[SC_GO]) return;
   const int nb = g.off[ii + 1] - g.off[ii];
   const int b0 = blockIdx.x - g.off[ii];
@@ -1060,8 +1060,8 @@ __device__ __forceinline__ int wrap_any(int j, int n) {
 }
 
 // decode a padded linear index into logical (i, j, k)
-template <int D>
-__device__ __forceinline__ void decode(const Inst& I, int64_t p, int& i, int& j, int& k) {
+template <int D, class IT>
+__device__ __forceinline__ void decode(const IT& I, int64_t p, int& i, int& j, int& k) {
   const int ai = (int)(p % I.Px);
   const int64_t r = p / I.Px;
   const int aj = D >= 2 ? (int)(r % I.Py) : 0;
