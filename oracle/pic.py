@@ -38,7 +38,10 @@ per-particle discrete continuity of the deposit and the Gauss law through whole
 runs with births, the Yee vacuum dispersion relation and the discrete field
 energy invariant, Fresnel reflection at a dielectric interface, the cold-plasma
 oscillation frequency, brute-force sliding maximum, the binomial statistics of
-ionization at a fixed amplitude.
+ionization at a fixed amplitude; for the paper-style diagnostics, kinetic
+energies of particles built from a chosen gamma, the particle and range
+bookkeeping of the energy histogram, and the maximum accumulated intensity of a
+plane wave crossing vacuum against the peak of its incident field.
 """
 
 import math
@@ -46,7 +49,7 @@ from collections import deque
 
 import numpy as np
 
-from .constants import C, KB, EPS0
+from .constants import C, KB, EPS0, QE
 from . import keldysh, philox
 from .problem import Problem
 
@@ -96,6 +99,9 @@ class Sim:
         self.pu = np.zeros((0, 3))
         self.pk = np.zeros(0, dtype=np.int64)
         self.step_index = 0
+        # maximum accumulated intensity: node |E|^2 after every imax_every-th step
+        self.imax_every = 0
+        self.imax = z()
         self.events = []          # list of (id array, step)
         self.energy_gap = 0.0     # sum over events of w * Delta  [J]
         self.acut = [self._amp_cut(m) for m in P.mats]
@@ -552,8 +558,11 @@ class Sim:
         self._b_half()
         self._e_full(n)
         self._b_half()
-        self.win.append(self.node_emag())
+        em = self.node_emag()
+        self.win.append(em)
         self.A = np.max(np.stack(self.win), axis=0)
+        if self.imax_every > 0 and (n + 1) % self.imax_every == 0:
+            self.imax = np.maximum(self.imax, em * em)
         self.ionize(n + 1)
         self.step_index = n + 1
 
@@ -630,6 +639,53 @@ class Sim:
                     np.add.at(out, (ix[:, a], iy[:, b_], iz[:, c]), w * wx[:, a] * wy[:, b_] * wz[:, c])
         self._fold_periodic(out)
         return out / self.P.vcell
+
+    def set_imax(self, every):
+        """Maximum accumulated intensity (Sec. 5, multilayer mirror: the
+        intensity recorded at fixed intervals and the largest value over all of
+        them kept per point).  From now on, after the field update of every step
+        whose new step index is a multiple of `every`, each node's |E|^2 (the
+        Yee components averaged to the node, as for the amplitude window) raises
+        the node's running maximum; 0 switches it off.  The maximum restarts
+        from zero."""
+        self.imax_every = int(every)
+        self.imax = np.zeros(self.S)
+
+    def imax_nodes(self):
+        """The running maximum of |E|^2 [V^2/m^2] on the domain nodes."""
+        return self.imax[self._domain_slices([False] * 3)].copy()
+
+    def kinetic_energy_eV(self):
+        """Kinetic energy of every charged particle [eV]:
+        m c^2 |u|^2 / (gamma + 1) = m c^2 (gamma - 1) with gamma = sqrt(1 + |u|^2),
+        u = gamma v / c; |u|^2 summed x, y, z in that order."""
+        if len(self.px) == 0:
+            return np.zeros(0)
+        u = self.pu
+        u2 = u[:, 0] * u[:, 0] + u[:, 1] * u[:, 1] + u[:, 2] * u[:, 2]
+        mc2 = np.array([k["mass"] * C * C / QE for k in self.P.kinds])[self.pk]
+        return mc2 * u2 / (np.sqrt(1.0 + u2) + 1.0)
+
+    def energy_spectrum(self, edges_eV, x_lo_cell=0, x_hi_cell=0):
+        """Energy histogram of the charged macroparticles (Sec. 5: histograms of
+        the electrons' energy in one layer at a given time, fitted with a chi^2
+        law).  Counts per kind (row = kind index, 2 m electron, 2 m + 1 positive
+        carrier of material m) of the particles whose x cell lies in
+        [x_lo_cell, x_hi_cell) (every cell when x_hi_cell <= x_lo_cell), by
+        kinetic energy against the increasing bin edges: column 0 below the
+        first edge, column j in [edges[j-1], edges[j]), the last column at or
+        above the last edge."""
+        edges = np.asarray(edges_eV, dtype=np.float64)
+        out = np.zeros((len(self.P.kinds), len(edges) + 1), dtype=np.int64)
+        if len(self.px) == 0:
+            return out
+        cell = np.floor(self.px[:, 0]).astype(np.int64)
+        sel = np.ones(len(cell), dtype=bool)
+        if x_hi_cell > x_lo_cell:
+            sel = (cell >= x_lo_cell) & (cell < x_hi_cell)
+        col = np.searchsorted(edges, self.kinetic_energy_eV()[sel], side="right")
+        np.add.at(out, (self.pk[sel], col), 1)
+        return out
 
     def event_set(self):
         s = set()
