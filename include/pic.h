@@ -160,7 +160,7 @@ enum {
                              chunks, drifter-steps (a particle that deposited outside
                              its tile's window, counted per step) since the last
                              sort, sorts performed */
-  PIC_DIAG_REGION = 10    /* double[6]: charged region along x that the next step's
+  PIC_DIAG_REGION = 10,   /* double[6]: charged region along x that the next step's
                              field update uses (first and last cell that held a
                              charged particle so far, together with the amplitude
                              window's cells; lo > hi when empty), then the field
@@ -169,6 +169,9 @@ enum {
                              the last x node of a field tile that has held a
                              nonzero E or b, then the field tiles updated so far,
                              summed over the field launches */
+  PIC_DIAG_IMAX = 11      /* float: maximum accumulated intensity at nodes, the
+                             largest node |E|^2 [V^2/m^2] over the samples taken
+                             since pic_set_imax (zero when never enabled) */
 };
 
 /* PIC_DIAG_SCALARS layout (all double). */
@@ -286,6 +289,45 @@ pic_status pic_autotune_steps(pic_ctx* c, int32_t reps);
  * step.  Phases: 0 push, 1 field update, 2 ionization, 3 tile sort.
  * Switching resets the accumulators. */
 pic_status pic_set_timing(pic_ctx* c, int32_t on);
+
+/* Maximum accumulated intensity (Sec. 5, multilayer mirror: the intensity is
+ * recorded at fixed intervals, 0.5 fs in the paper, and each point keeps its
+ * largest value over the run).  every > 0: after the field update of each
+ * step whose new step index is a multiple of `every`, every domain node's
+ * |E|^2 raises the node's running maximum.  The node |E| is the one the
+ * amplitude window uses: Yee components averaged to the node, positions
+ * outside the box counted as zero, periodic axes wrapped; FP32.  Enabling
+ * (again) clears the maximum; every = 0 stops sampling and keeps it.  Read with
+ * PIC_DIAG_IMAX.  The maximum takes 4 bytes per padded grid point, allocated on
+ * the first enable (through the configuration's allocator when it has one).
+ * A batch does not sample: pic_batch_step returns PIC_E_STATE while a member
+ * has sampling on.  Errors: PIC_E_INVAL (every < 0), PIC_E_NOMEM,
+ * PIC_E_STATE (latched error). */
+pic_status pic_set_imax(pic_ctx* c, int32_t every);
+
+/* Energy histogram of the charged macroparticles (Sec. 5: histograms of the
+ * electrons' energy in one layer at a given time, fitted with a chi^2 law).
+ * The particles whose x cell lies in [x_lo_cell, x_hi_cell) (every cell when
+ * x_hi_cell <= x_lo_cell) are counted per kind by kinetic energy
+ * KE = m c^2 |u|^2 / (gamma + 1) [eV], gamma = sqrt(1 + |u|^2), evaluated in
+ * FP64 from the FP32 u with every operation rounded on its own, in the order
+ * written (|u|^2 summed x, y, z).  Bin edges are the caller's (strictly
+ * increasing, finite, 2 .. 4097 of them). */
+typedef struct {
+  int32_t nedges;
+  const double* edges_eV;    /* host array of nedges bin edges [eV] */
+  int64_t x_lo_cell, x_hi_cell;
+} pic_spectrum;
+
+/* Synchronous.  out (host, out_count = 2 * nmat * (nedges + 1) entries): one
+ * row per kind (2 m electron, 2 m + 1 positive carrier of material m); column 0
+ * counts KE below the first edge, column j (1 .. nedges - 1) KE in
+ * [edge j-1, edge j), column nedges KE at or above the last edge.  The counts
+ * are exact (integers).  Edges and counts use a 0.5 MB device buffer allocated
+ * on the first call (through the configuration's allocator when it has one).
+ * Errors: PIC_E_INVAL (bad edges, range beyond int32 or out_count),
+ * PIC_E_NOMEM, PIC_E_DEVICE. */
+pic_status pic_spectrum_counts(pic_ctx* c, const pic_spectrum* s, uint64_t* out, size_t out_count);
 
 /* Far field tiles (default on): the push tracks on the device every x cell
  * that has held a charged particle at any step so far.  A field tile whose x

@@ -55,6 +55,26 @@ int field_tile_x(int D, int variant);                          // owned x extent
 void launch_init_neutrals_d(const Inst* d, int64_t nneut, int D, hipStream_t s);
 void launch_preionize_d(const Inst* d, int64_t nneut, int D, const float* sig_e, const float* sig_p,
                         hipStream_t s);
+// energy histogram of the charged particles (per kind, over caller edges)
+struct SpecArgs {
+  int nkinds, nedges;      // rows; increasing edges (columns = nedges + 1)
+  int x_lo, x_hi;          // x cells counted (x_hi <= x_lo: every cell)
+  int lds;                 // counts fit in LDS (nkinds * columns <= kSpecLds)
+  double mc2_eV[MAXKIND];  // rest energy per kind [eV]
+};
+constexpr int kSpecLds = 8192;
+void launch_spectrum(const Inst* d, int D, int capacity, const SpecArgs& a, const double* edges,
+                     unsigned long long* out, hipStream_t s);
+// running maximum of the node |E|^2 over the domain nodes
+struct ImaxArgs {
+  const float *E0, *E1, *E2;   // E after the step's field update (padded layout)
+  int64_t nodes;               // domain nodes: mx * my * mz
+  int mx, my;
+  int D, nx, ny, nz, per_y, per_z;
+  int Gy, Gz;                  // guard layers of y and z (x: G)
+  int64_t sy, sz;
+};
+void launch_imax(const ImaxArgs& a, float* imax, hipStream_t s);
 void launch_diag_particles(const Inst* d, int capacity, double* acc, hipStream_t s);
 void launch_diag_field_energy(const Inst* d, int64_t ncell, double* acc, hipStream_t s);
 void launch_diag_deposit(const Inst* d, int D, int order, int capacity, double* grid, int what,

@@ -1706,6 +1706,87 @@ __global__ __launch_bounds__(TPB) void k_diag_particles(const Inst* d, double* a
     if (sh[q] != 0.0) atomicAdd(&acc[q], sh[q]);
 }
 
+// Energy histogram (Sec. 5: the electrons' energy distribution in one layer,
+// fitted with a chi^2 law).  Kinetic energy m c^2 |u|^2 / (gamma + 1) in FP64,
+// every operation rounded on its own in the order written (no contraction), so
+// the bin a particle falls in is the one the same formula gives anywhere; the
+// bin is found by bisection over the caller's edges: column 0 below the first
+// edge, column j in [edge j-1, edge j), the last column at or above the last.
+// Counts per kind in LDS (when they fit) or straight to HBM.
+template <int D>
+__global__ __launch_bounds__(TPB) void k_spectrum(const Inst* d, SpecArgs a, const double* edges,
+                                                  unsigned long long* out) {
+  extern __shared__ unsigned int sc[];
+  const Inst& I = *d;
+  const int ncol = a.nedges + 1, ncnt = a.nkinds * ncol;
+  if (a.lds) {
+    for (int q = threadIdx.x; q < ncnt; q += TPB) sc[q] = 0u;
+    __syncthreads();
+  }
+  int count = *I.pcount;
+  count = count < I.capacity ? count : I.capacity;
+  for (int p = blockIdx.x * TPB + threadIdx.x; p < count; p += gridDim.x * TPB) {
+    const int kd = I.pkind[p];
+    if (kd == DEAD || kd >= a.nkinds) continue;
+    if (a.x_hi > a.x_lo) {
+      int ci, cj, ck;
+      unpack_cell(D, I.pcell[p], ci, cj, ck);
+      if (ci < a.x_lo || ci >= a.x_hi) continue;
+    }
+    double ke;
+    {
+#pragma clang fp contract(off)
+      const double ux = I.pu0[p], uy = I.pu1[p], uz = I.pu2[p];
+      const double u2 = ux * ux + uy * uy + uz * uz;
+      ke = a.mc2_eV[kd] * u2 / (sqrt(1.0 + u2) + 1.0);
+    }
+    // first edge above ke (upper bound): lo = number of edges <= ke
+    int lo = 0, hi = a.nedges;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (edges[mid] <= ke) lo = mid + 1; else hi = mid;
+    }
+    const int q = kd * ncol + lo;
+    if (a.lds) atomicAdd(&sc[q], 1u);
+    else atomicAdd(&out[q], 1ull);
+  }
+  if (a.lds) {
+    __syncthreads();
+    for (int q = threadIdx.x; q < ncnt; q += TPB)
+      if (sc[q]) atomicAdd(&out[q], (unsigned long long)sc[q]);
+  }
+}
+
+// Maximum accumulated intensity (Sec. 5, multilayer mirror): each domain
+// node's |E|^2, the Yee components averaged to the node (positions outside the
+// box count as zero, periodic axes wrap), raises the node's running maximum.
+// One thread per domain node, x fastest.
+__global__ __launch_bounds__(TPB) void k_imax(ImaxArgs a, float* __restrict__ imax) {
+  const int64_t n = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (n >= a.nodes) return;
+  const int i = (int)(n % a.mx);
+  const int j = (int)((n / a.mx) % a.my);
+  const int k = (int)(n / ((int64_t)a.mx * a.my));
+  const int64_t o = (int64_t)(i + G) + (int64_t)a.sy * (j + a.Gy) + (int64_t)a.sz * (k + a.Gz);
+  // component c at node (i, j, k): mean of its two half-integer neighbours
+  // along axis c when c is a present axis, else its value at the node
+  auto node = [&](const float* F, int c) -> float {
+    if (c >= a.D) return F[o];
+    const int v = c == 0 ? i : c == 1 ? j : k;
+    const int nv = c == 0 ? a.nx : c == 1 ? a.ny : a.nz;
+    const bool per = c == 1 ? a.per_y : c == 2 ? a.per_z : false;
+    const int64_t st = c == 0 ? 1 : c == 1 ? a.sy : a.sz;
+    const float hiv = v < nv ? F[o] : 0.0f;
+    float lov;
+    if (v >= 1) lov = F[o - st];
+    else lov = per ? F[o + (int64_t)(nv - 1) * st] : 0.0f;
+    return 0.5f * (lov + hiv);
+  };
+  const float ex = node(a.E0, 0), ey = node(a.E1, 1), ez = node(a.E2, 2);
+  const float v = ex * ex + ey * ey + ez * ez;
+  if (v > imax[o]) imax[o] = v;
+}
+
 __global__ __launch_bounds__(TPB) void k_diag_field_energy(const Inst* d, int64_t ncell, double* acc) {
   const Inst& I = *d;
   const int par = *I.step & 1;
@@ -1890,6 +1971,17 @@ void launch_diag_particles(const Inst* d, int capacity, double* acc, hipStream_t
   unsigned nb = (unsigned)((capacity + TPB - 1) / TPB);
   nb = nb < 1 ? 1 : (nb > 2048 ? 2048 : nb);
   hipLaunchKernelGGL(k_diag_particles, dim3(nb), dim3(TPB), 0, s, d, acc);
+}
+void launch_spectrum(const Inst* d, int D, int capacity, const SpecArgs& a, const double* edges,
+                     unsigned long long* out, hipStream_t s) {
+  unsigned nb = (unsigned)((capacity + TPB - 1) / TPB);
+  nb = nb < 1 ? 1 : (nb > 2048 ? 2048 : nb);
+  const size_t lds = a.lds ? sizeof(unsigned) * a.nkinds * (a.nedges + 1) : 0;
+  DISPATCH_D(D, hipLaunchKernelGGL((k_spectrum<DD>), dim3(nb), dim3(TPB), lds, s, d, a, edges, out));
+}
+void launch_imax(const ImaxArgs& a, float* imax, hipStream_t s) {
+  if (a.nodes <= 0) return;
+  hipLaunchKernelGGL(k_imax, dim3((unsigned)((a.nodes + TPB - 1) / TPB)), dim3(TPB), 0, s, a, imax);
 }
 void launch_diag_field_energy(const Inst* d, int64_t ncell, double* acc, hipStream_t s) {
   int64_t nb = (ncell + TPB - 1) / TPB;

@@ -225,6 +225,9 @@ struct pic_ctx {
   int resort = 8;             // tile-sort check every `resort` steps (0 = never)
   int far_skip = 1;           // far field tiles skip the current (pic_set_far_tiles)
   int h_xext[6] = {};         // host source of the charged-region slots
+  int imax_every = 0;         // node |E|^2 maximum sampled every k steps (0 off)
+  float* d_imax = nullptr;    // its running maximum (padded grid), allocated on demand
+  void* d_spec = nullptr;     // energy histogram: edges and counts, allocated on demand
 };
 
 struct pic_batch {
@@ -263,6 +266,25 @@ namespace {
 
 inline void* devp(pic_ctx* c, size_t off) { return c->base + off; }
 
+// device memory beyond the state block, from the caller's allocator when given
+void* dev_alloc(pic_ctx* c, size_t bytes) {
+  if (c->cfg.alloc) return c->cfg.alloc(bytes, c->cfg.alloc_user);
+  void* p = nullptr;
+  return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+}
+void dev_free(pic_ctx* c, void* p) {
+  if (!p) return;
+  if (c->cfg.alloc) {
+    if (c->cfg.free) c->cfg.free(p, c->cfg.alloc_user);
+  } else {
+    (void)hipFree(p);
+  }
+}
+
+// Energy histogram buffer: up to kSpecEdges edges, then MAXKIND rows of counts.
+constexpr int kSpecEdges = 4097;
+constexpr size_t kSpecBytes = sizeof(double) * kSpecEdges + sizeof(unsigned long long) * MAXKIND * (kSpecEdges + 1);
+
 Group single(pic_ctx* c, int phase, int nb) {
   Group g{c->d_inst, phase == 1 ? c->d_off_fields : c->d_off + 2 * phase, 1, nb, (int)c->step};
   g.front = &c->d_ctr->front;
@@ -292,6 +314,32 @@ void harvest(pic_ctx* c, int ph, int slot) {
 // per window (every residue of the step index is sampled equally often)
 bool sampled(const pic_ctx* c) {
   return c->timing && c->step % c->timing == (c->step / c->timing) % c->timing;
+}
+
+// the node |E|^2 maximum after the field update of the current step (its new
+// E is the parity the update wrote)
+ImaxArgs imax_args(const pic_ctx* c) {
+  const Inst& I = c->h;
+  const int np = (int)((c->step & 1) ^ 1);
+  ImaxArgs a{};
+  a.E0 = I.F[np][0];
+  a.E1 = I.F[np][1];
+  a.E2 = I.F[np][2];
+  a.D = I.D;
+  a.nx = I.nx;
+  a.ny = I.ny;
+  a.nz = I.nz;
+  a.per_y = I.per_y;
+  a.per_z = I.per_z;
+  a.Gy = I.Gy;
+  a.Gz = I.Gz;
+  a.sy = I.sy;
+  a.sz = I.sz;
+  a.mx = I.nx + 1;
+  a.my = I.D >= 2 ? (I.per_y ? I.ny : I.ny + 1) : 1;
+  const int mz = I.D >= 3 ? (I.per_z ? I.nz : I.nz + 1) : 1;
+  a.nodes = (int64_t)a.mx * a.my * mz;
+  return a;
 }
 
 template <typename F>
@@ -381,6 +429,7 @@ void enqueue_step(pic_ctx* c) {
       launch_fields(g, D, c->tile, s, st);
     });
   }
+  if (c->imax_every > 0 && (c->step + 1) % c->imax_every == 0) launch_imax(imax_args(c), c->d_imax, s);
   timed(c, 2, [&](Stamp st) { launch_ionize(single(c, 3, c->nb_neut), D, order, s, st); });
   if (sampled(c)) ++c->ev_slot;
   ++c->step;
@@ -781,11 +830,65 @@ void pic_destroy(pic_ctx* c) {
       for (auto& e : rr)
         if (e) (void)hipEventDestroy(e);
   if (c->h_step) (void)hipHostFree(c->h_step);
+  dev_free(c, c->d_imax);
+  dev_free(c, c->d_spec);
   if (c->base) {
     if (c->owns_alloc_via_cb && c->cfg.free) c->cfg.free(c->base, c->cfg.alloc_user);
     else if (!c->owns_alloc_via_cb) (void)hipFree(c->base);
   }
   delete c;
+}
+
+pic_status pic_set_imax(pic_ctx* c, int32_t every) {
+  if (!c || every < 0) return PIC_E_INVAL;
+  if (c->latched != PIC_OK) return PIC_E_STATE;
+  if (every > 0) {
+    const size_t bytes = sizeof(float) * c->L.ncell;
+    if (!c->d_imax) {
+      c->d_imax = (float*)dev_alloc(c, bytes);
+      if (!c->d_imax) return PIC_E_NOMEM;
+    }
+    HIP_OK(hipMemsetAsync(c->d_imax, 0, bytes, c->stream));
+  }
+  c->imax_every = every;
+  return PIC_OK;
+}
+
+pic_status pic_spectrum_counts(pic_ctx* c, const pic_spectrum* sp, uint64_t* out, size_t out_count) {
+  if (!c || !sp || !out) return PIC_E_INVAL;
+  const int ne = sp->nedges;
+  const int nk = 2 * c->canon.nmat;
+  if (ne < 2 || ne > kSpecEdges || !sp->edges_eV) return PIC_E_INVAL;
+  if (out_count != (size_t)nk * (size_t)(ne + 1)) return PIC_E_INVAL;
+  for (int q = 0; q < ne; ++q) {
+    if (!std::isfinite(sp->edges_eV[q])) return PIC_E_INVAL;
+    if (q > 0 && !(sp->edges_eV[q] > sp->edges_eV[q - 1])) return PIC_E_INVAL;
+  }
+  if (sp->x_hi_cell > sp->x_lo_cell && (sp->x_lo_cell < INT32_MIN || sp->x_hi_cell > INT32_MAX)) return PIC_E_INVAL;
+  hipStream_t s = c->stream;
+  if (hipStreamSynchronize(s) != hipSuccess) return PIC_E_DEVICE;
+  check_health(c);
+  if (!c->d_spec) {
+    c->d_spec = dev_alloc(c, kSpecBytes);
+    if (!c->d_spec) return PIC_E_NOMEM;
+  }
+  double* d_edges = (double*)c->d_spec;
+  unsigned long long* d_cnt = (unsigned long long*)(d_edges + kSpecEdges);
+  SpecArgs a{};
+  a.nkinds = nk;
+  a.nedges = ne;
+  a.x_lo = sp->x_hi_cell > sp->x_lo_cell ? (int)sp->x_lo_cell : 0;
+  a.x_hi = sp->x_hi_cell > sp->x_lo_cell ? (int)sp->x_hi_cell : 0;
+  a.lds = (int)(nk * (ne + 1) <= kSpecLds);
+  // rest energy per kind [eV]: m c^2 / e
+  for (int k = 0; k < nk; ++k) a.mc2_eV[k] = c->h.kmass[k] * kC * kC / kQE;
+  HIP_OK(hipMemcpyAsync(d_edges, sp->edges_eV, sizeof(double) * ne, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemsetAsync(d_cnt, 0, sizeof(unsigned long long) * out_count, s));
+  launch_spectrum(c->d_inst, c->canon.D, (int)c->L.capacity, a, d_edges, d_cnt, s);
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipMemcpyAsync(out, d_cnt, sizeof(unsigned long long) * out_count, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  return PIC_OK;
 }
 
 pic_status pic_set_timing(pic_ctx* c, int32_t on) {
@@ -995,7 +1098,8 @@ pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size
     }
     case PIC_DIAG_NE_GRID:
     case PIC_DIAG_UE_GRID: need = sizeof(double) * dom_count(K, kNode); break;
-    case PIC_DIAG_AMP: need = sizeof(float) * dom_count(K, kNode); break;
+    case PIC_DIAG_AMP:
+    case PIC_DIAG_IMAX: need = sizeof(float) * dom_count(K, kNode); break;
     case PIC_DIAG_PARAMS: need = sizeof(pic_params); break;
     case PIC_DIAG_TIMERS: need = sizeof(double) * 32; break;
     case PIC_DIAG_SORT: need = sizeof(double) * 4; break;
@@ -1083,9 +1187,10 @@ pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size
       }
     return PIC_OK;
   }
-  if (kind == PIC_DIAG_AMP) {
-    std::vector<float> buf(L.ncell);
-    HIP_OK(hipMemcpy(buf.data(), devp(c, L.o_A), sizeof(float) * L.ncell, hipMemcpyDeviceToHost));
+  if (kind == PIC_DIAG_AMP || kind == PIC_DIAG_IMAX) {
+    std::vector<float> buf(L.ncell, 0.0f);
+    const void* src = kind == PIC_DIAG_AMP ? devp(c, L.o_A) : (const void*)c->d_imax;
+    if (src) HIP_OK(hipMemcpy(buf.data(), src, sizeof(float) * L.ncell, hipMemcpyDeviceToHost));
     float* o = (float*)host_out;
     for_domain(K, kNode, [&](int64_t n, int64_t i, int64_t j, int64_t k) { o[n] = buf[pidx(L, D, i, j, k)]; });
     return PIC_OK;
@@ -1359,7 +1464,7 @@ static bool batch_capture(pic_batch* b, int period) {
 pic_status pic_batch_step(pic_batch* b, int64_t nsteps) {
   if (!b || nsteps < 0) return PIC_E_INVAL;
   for (pic_ctx* c : b->members)
-    if (c->latched != PIC_OK) return PIC_E_STATE;
+    if (c->latched != PIC_OK || c->imax_every > 0) return PIC_E_STATE;
   if (b->dirty) {
     pic_status st = batch_rebuild(b);
     if (st != PIC_OK) return st;

@@ -23,7 +23,7 @@ ABI_VERSION = 1
 ENV = {"gauss": 0, "sin2": 1}
 BC = {"outflow": 0, "periodic": 1}
 DIAG_SCALARS, DIAG_FIELDS, DIAG_NE, DIAG_UE, DIAG_EVENTS, DIAG_PARTICLES, DIAG_PARAMS, DIAG_AMP, \
-    DIAG_TIMERS, DIAG_SORT, DIAG_REGION = range(11)
+    DIAG_TIMERS, DIAG_SORT, DIAG_REGION, DIAG_IMAX = range(12)
 SC = dict(step=0, time=1, n_neutral=2, n_e=3, n_pos=4, events=5, u_field=6, ke_e=7, ke_pos=8,
           e_gap=9, e_abs=10, gauss_max=11, rho_max=12, health=13, slots=14)
 
@@ -93,7 +93,12 @@ SYMBOLS = ["pic_init", "pic_step", "pic_diag", "pic_set_state", "pic_footprint",
            "pic_batch_step", "pic_batch_add", "pic_batch_remove", "pic_batch_destroy", "pic_batch_set_graph",
            "pic_batch_graph_replays",
            "pic_set_timing", "pic_autotune", "pic_autotune_steps", "pic_set_resort", "pic_set_far_tiles",
-           "pic_destroy", "pic_status_str"]
+           "pic_set_imax", "pic_spectrum_counts", "pic_destroy", "pic_status_str"]
+
+
+class Spectrum(C.Structure):
+    _fields_ = [("nedges", C.c_int32), ("edges_eV", C.POINTER(C.c_double)),
+                ("x_lo_cell", C.c_int64), ("x_hi_cell", C.c_int64)]
 
 
 def lib():
@@ -133,6 +138,8 @@ def lib():
             "pic_autotune_steps": ([vp, i32], C.c_int),
             "pic_set_resort": ([vp, i32], C.c_int),
             "pic_set_far_tiles": ([vp, i32], C.c_int),
+            "pic_set_imax": ([vp, i32], C.c_int),
+            "pic_spectrum_counts": ([vp, C.POINTER(Spectrum), C.POINTER(C.c_uint64), C.c_size_t], C.c_int),
             "pic_batch_set_graph": ([vp, i32], C.c_int),
             "pic_batch_graph_replays": ([vp], C.c_int64),
             "pic_destroy": ([vp], None),
@@ -252,6 +259,7 @@ class Context:
         self.ndim = int(cfg["ndim"])
         self.n = [int(cfg["n"][d]) if d < self.ndim else 1 for d in range(3)]
         self.periodic_t = cfg.get("transverse_bc", "outflow") == "periodic"
+        self.nmat = len(cfg["materials"])
 
     # -------------------------------------------------------------- control
     def step(self, n=1):
@@ -335,6 +343,26 @@ class Context:
 
     def amp(self):
         return self._node_grid(DIAG_AMP, np.float32)
+
+    def set_imax(self, every):
+        """Sample the node |E|^2 into its running maximum after every
+        `every`-th step (0 = off); enabling clears the maximum."""
+        _check(lib().pic_set_imax(self.h, int(every)), "pic_set_imax")
+
+    def imax(self):
+        """Maximum accumulated intensity: the largest node |E|^2 [V^2/m^2]."""
+        return self._node_grid(DIAG_IMAX, np.float32)
+
+    def spectrum(self, edges_eV, x_lo_cell=0, x_hi_cell=0):
+        """Macroparticle counts per kind (rows) by kinetic energy over the bin
+        edges [eV]: below the first edge, each bin, at or above the last edge."""
+        e = np.ascontiguousarray(edges_eV, dtype=np.float64)
+        nk = 2 * self.nmat
+        out = np.zeros((nk, len(e) + 1), dtype=np.uint64)
+        sp = Spectrum(len(e), e.ctypes.data_as(C.POINTER(C.c_double)), int(x_lo_cell), int(x_hi_cell))
+        _check(lib().pic_spectrum_counts(self.h, C.byref(sp), out.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                         out.size), "pic_spectrum_counts")
+        return out
 
     def events(self):
         v = self._diag(DIAG_EVENTS, np.int64)
