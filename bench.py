@@ -315,6 +315,68 @@ def bench_serve(args):
     }
 
 
+def bench_diag(args):
+    """Sec. 5 diagnostics at the 2D slab grid (2048 x 512): the energy
+    histogram of 1.2e6 charged particles (a seeded synthetic state, |u| log-
+    uniform from 1e-4 to 3) over 200 log bins, for the whole box and for one
+    80-cell layer, and the node |E|^2 maximum sampled every step.  Reported:
+    the wall time of one histogram call (host edges in, counts out, synchronous)
+    and the added step time of the sampling; kernel durations come from a kernel
+    trace of this command."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2502_13695_amd import pic
+    cfg = W.config_2d()
+    npart = 1_200_000
+    st = W.random_state(cfg, npart, seed=77, e_scale=1e8)
+    rng = np.random.default_rng(78)
+    d = st["u"] / np.linalg.norm(st["u"], axis=1, keepdims=True)
+    st["u"] = (d * (10.0 ** rng.uniform(-4.0, 0.5, npart))[:, None]).astype(np.float32)
+    rec = np.zeros(npart, dtype=pic.PARTICLE_DTYPE)
+    rec["cell"][:, :2] = st["cell"][:, :2]
+    rec["off"] = st["off"]
+    rec["u"] = st["u"]
+    rec["kind"] = st["kind"]
+    ctx = pic.Context(cfg)
+    ctx.set_state(0, st["E"], st["b"], rec)
+    edges = np.geomspace(1e-4, 3e6, 201)
+    out = {}
+    for name, (lo, hi) in (("box", (0, 0)), ("layer", (512, 592))):
+        for _ in range(3):
+            ctx.spectrum(edges, lo, hi)
+        ts = []
+        for _ in range(args.steps if args.steps < 200 else 50):
+            t0 = time.perf_counter()
+            ctx.spectrum(edges, lo, hi)
+            ts.append(time.perf_counter() - t0)
+        out[name] = dict(call_us=1e6 * float(np.median(ts)), counted=int(ctx.spectrum(edges, lo, hi).sum()))
+    torch.cuda.synchronize()
+    nstep = 400
+
+    def steps_s(every):
+        ctx.set_imax(every)
+        ctx.step(20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.step(nstep)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / nstep
+
+    off1 = steps_s(0)
+    on = steps_s(1)
+    off2 = steps_s(0)
+    nodes = (cfg["n"][0] + 1) * (cfg["n"][1] + 1)
+    ctx.close()
+    return {"metric": "Sec. 5 diagnostics at the 2D slab grid", "unit": "us", "data": "synthetic",
+            "config": {"workload": "2048x512 slab, 1.2e6 charged particles (seeded state), 200 log bins",
+                       "particles": npart, "nodes": nodes},
+            "spectrum": out,
+            # algorithmic bytes: kind 1 + cell 4 + u 12 per slot; E 12 + maximum read and write 8 per node
+            "spectrum_bytes": 17 * npart, "imax_bytes_per_sample": 20 * nodes,
+            "step_us_without_sampling": 1e6 * 0.5 * (off1 + off2), "step_us_sampling_every_step": 1e6 * on}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -322,7 +384,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="slab2d", choices=["slab2d", "mirror3d", "slab1d",
                                                              "stress2d", "stress3d", "stress2d-cap",
-                                                             "stress3d-cap", "scan", "serve"])
+                                                             "stress3d-cap", "scan", "serve", "diag"])
     ap.add_argument("--instances", type=int, default=32, help="scan: fluence-scan instances")
     ap.add_argument("--requests", type=int, default=400, help="serve: requests")
     ap.add_argument("--scale", type=float, default=1.0, help="serve: grid/step scale of the mix")
@@ -345,6 +407,9 @@ def main():
         return
     if args.workload == "serve":
         print(json.dumps(bench_serve(args)), flush=True)
+        return
+    if args.workload == "diag":
+        print(json.dumps(bench_diag(args)), flush=True)
         return
     if args.workload == "slab2d":
         cfg = W.config_2d()

@@ -59,10 +59,14 @@ void launch_preionize_d(const Inst* d, int64_t nneut, int D, const float* sig_e,
 struct SpecArgs {
   int nkinds, nedges;      // rows; increasing edges (columns = nedges + 1)
   int x_lo, x_hi;          // x cells counted (x_hi <= x_lo: every cell)
-  int lds;                 // counts fit in LDS (nkinds * columns <= kSpecLds)
+  int lds;                 // counts fit in LDS beside the edges (spec_lds_counts)
   double mc2_eV[MAXKIND];  // rest energy per kind [eV]
 };
-constexpr int kSpecLds = 8192;
+// LDS per block: the edges (8 B each) and, when they fit in 64 KB with them,
+// the counts (4 B per kind and column)
+inline bool spec_lds_counts(int nkinds, int nedges) {
+  return 8u * nedges + 4u * nkinds * (nedges + 1) <= 65536u - 1024u;
+}
 void launch_spectrum(const Inst* d, int D, int capacity, const SpecArgs& a, const double* edges,
                      unsigned long long* out, hipStream_t s);
 // running maximum of the node |E|^2 over the domain nodes

@@ -1710,22 +1710,26 @@ __global__ __launch_bounds__(TPB) void k_diag_particles(const Inst* d, double* a
 // fitted with a chi^2 law).  Kinetic energy m c^2 |u|^2 / (gamma + 1) in FP64,
 // every operation rounded on its own in the order written (no contraction), so
 // the bin a particle falls in is the one the same formula gives anywhere; the
-// bin is found by bisection over the caller's edges: column 0 below the first
-// edge, column j in [edge j-1, edge j), the last column at or above the last.
-// Counts per kind in LDS (when they fit) or straight to HBM.
+// bin is found by bisection over the caller's edges (staged in LDS): column 0
+// below the first edge, column j in [edge j-1, edge j), the last column at or
+// above the last.  Counts per kind in LDS (when they fit) or straight to HBM.
+// One 1024-thread block per CU at most: each block adds its counts to HBM
+// once, so a column takes at most one atomic per CU.
+constexpr int SPEC_TPB = 1024;
 template <int D>
-__global__ __launch_bounds__(TPB) void k_spectrum(const Inst* d, SpecArgs a, const double* edges,
-                                                  unsigned long long* out) {
-  extern __shared__ unsigned int sc[];
+__global__ __launch_bounds__(SPEC_TPB) void k_spectrum(const Inst* d, SpecArgs a, const double* edges,
+                                                       unsigned long long* out) {
+  extern __shared__ double se[];   // nedges edges, then (a.lds) the counts
+  unsigned int* sc = (unsigned int*)(se + a.nedges);
   const Inst& I = *d;
   const int ncol = a.nedges + 1, ncnt = a.nkinds * ncol;
-  if (a.lds) {
-    for (int q = threadIdx.x; q < ncnt; q += TPB) sc[q] = 0u;
-    __syncthreads();
-  }
+  for (int q = threadIdx.x; q < a.nedges; q += SPEC_TPB) se[q] = edges[q];
+  if (a.lds)
+    for (int q = threadIdx.x; q < ncnt; q += SPEC_TPB) sc[q] = 0u;
+  __syncthreads();
   int count = *I.pcount;
   count = count < I.capacity ? count : I.capacity;
-  for (int p = blockIdx.x * TPB + threadIdx.x; p < count; p += gridDim.x * TPB) {
+  for (int p = blockIdx.x * SPEC_TPB + threadIdx.x; p < count; p += gridDim.x * SPEC_TPB) {
     const int kd = I.pkind[p];
     if (kd == DEAD || kd >= a.nkinds) continue;
     if (a.x_hi > a.x_lo) {
@@ -1740,11 +1744,11 @@ __global__ __launch_bounds__(TPB) void k_spectrum(const Inst* d, SpecArgs a, con
       const double u2 = ux * ux + uy * uy + uz * uz;
       ke = a.mc2_eV[kd] * u2 / (sqrt(1.0 + u2) + 1.0);
     }
-    // first edge above ke (upper bound): lo = number of edges <= ke
+    // number of edges at or below ke
     int lo = 0, hi = a.nedges;
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
-      if (edges[mid] <= ke) lo = mid + 1; else hi = mid;
+      if (se[mid] <= ke) lo = mid + 1; else hi = mid;
     }
     const int q = kd * ncol + lo;
     if (a.lds) atomicAdd(&sc[q], 1u);
@@ -1752,7 +1756,7 @@ __global__ __launch_bounds__(TPB) void k_spectrum(const Inst* d, SpecArgs a, con
   }
   if (a.lds) {
     __syncthreads();
-    for (int q = threadIdx.x; q < ncnt; q += TPB)
+    for (int q = threadIdx.x; q < ncnt; q += SPEC_TPB)
       if (sc[q]) atomicAdd(&out[q], (unsigned long long)sc[q]);
   }
 }
@@ -1974,10 +1978,10 @@ void launch_diag_particles(const Inst* d, int capacity, double* acc, hipStream_t
 }
 void launch_spectrum(const Inst* d, int D, int capacity, const SpecArgs& a, const double* edges,
                      unsigned long long* out, hipStream_t s) {
-  unsigned nb = (unsigned)((capacity + TPB - 1) / TPB);
-  nb = nb < 1 ? 1 : (nb > 2048 ? 2048 : nb);
-  const size_t lds = a.lds ? sizeof(unsigned) * a.nkinds * (a.nedges + 1) : 0;
-  DISPATCH_D(D, hipLaunchKernelGGL((k_spectrum<DD>), dim3(nb), dim3(TPB), lds, s, d, a, edges, out));
+  unsigned nb = (unsigned)((capacity + SPEC_TPB - 1) / SPEC_TPB);
+  nb = nb < 1 ? 1 : (nb > 256 ? 256 : nb);
+  const size_t lds = sizeof(double) * a.nedges + (a.lds ? sizeof(unsigned) * a.nkinds * (a.nedges + 1) : 0);
+  DISPATCH_D(D, hipLaunchKernelGGL((k_spectrum<DD>), dim3(nb), dim3(SPEC_TPB), lds, s, d, a, edges, out));
 }
 void launch_imax(const ImaxArgs& a, float* imax, hipStream_t s) {
   if (a.nodes <= 0) return;

@@ -879,7 +879,7 @@ pic_status pic_spectrum_counts(pic_ctx* c, const pic_spectrum* sp, uint64_t* out
   a.nedges = ne;
   a.x_lo = sp->x_hi_cell > sp->x_lo_cell ? (int)sp->x_lo_cell : 0;
   a.x_hi = sp->x_hi_cell > sp->x_lo_cell ? (int)sp->x_hi_cell : 0;
-  a.lds = (int)(nk * (ne + 1) <= kSpecLds);
+  a.lds = (int)spec_lds_counts(nk, ne);
   // rest energy per kind [eV]: m c^2 / e
   for (int k = 0; k < nk; ++k) a.mc2_eV[k] = c->h.kmass[k] * kC * kC / kQE;
   HIP_OK(hipMemcpyAsync(d_edges, sp->edges_eV, sizeof(double) * ne, hipMemcpyHostToDevice, s));
