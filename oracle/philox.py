@@ -27,6 +27,7 @@ PURPOSE_VEL = 2      # thermal velocity of a neutral (handed to its children)
 PURPOSE_IONIZE = 3   # ionization decision
 PURPOSE_STRESS_E = 4  # pre-ionized stress variant: electron velocity
 PURPOSE_STRESS_P = 5  # pre-ionized stress variant: positive-carrier velocity
+PURPOSE_TRACK = 6     # trajectory sampling: whether a particle's track is recorded
 
 
 def _mulhilo(a, b, W):

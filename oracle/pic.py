@@ -98,7 +98,15 @@ class Sim:
         self.px = np.zeros((0, 3))
         self.pu = np.zeros((0, 3))
         self.pk = np.zeros(0, dtype=np.int64)
+        # particle id: the id of the neutral it was born from (an electron and
+        # its positive carrier share it); particles placed directly get
+        # cells x ppc + their index, above every neutral id
+        self.pid = np.zeros(0, dtype=np.int64)
         self.step_index = 0
+        # trajectory sampling (off when track_every == 0)
+        self.track_every = 0
+        self.track_thr = 0
+        self.tracks = []
         # maximum accumulated intensity: node |E|^2 after every imax_every-th step
         self.imax_every = 0
         self.imax = z()
@@ -228,6 +236,7 @@ class Sim:
         self.px = np.concatenate([pos, pos])
         self.pu = np.concatenate([ue, up])
         self.pk = np.concatenate([2 * mats, 2 * mats + 1])
+        self.pid = np.concatenate([self.nid, self.nid])
 
     # ------------------------------------------------------------ field solve
     def _fill_periodic(self, a):
@@ -412,6 +421,7 @@ class Sim:
 
     def push_and_deposit(self):
         P = self.P
+        self._ensure_ids()
         for Jc in self.J:
             Jc[...] = 0.0
         n = len(self.px)
@@ -448,6 +458,7 @@ class Sim:
         self.px = x1[keep]
         self.pu = u_new[keep]
         self.pk = self.pk[keep]
+        self.pid = self.pid[keep]
 
     def _esirkepov(self, x0, x1, u, g, qhat):
         P = self.P
@@ -550,8 +561,18 @@ class Sim:
         self.px = np.concatenate([self.px, pos, pos])
         self.pu = np.concatenate([self.pu, u, u])
         self.pk = np.concatenate([self.pk, 2 * mats_e, 2 * mats_e + 1])
+        self.pid = np.concatenate([self.pid, self.nid[eidx], self.nid[eidx]])
 
     # ------------------------------------------------------------------ step
+    def placed_id_base(self):
+        """First id of particles placed directly: cells x ppc (every neutral
+        id, cell index x ppc + k, is below it)."""
+        return int(np.prod([self.P.n[d] for d in range(self.D)])) * int(self.P.ppc)
+
+    def _ensure_ids(self):
+        if len(self.pid) != len(self.pk):
+            self.pid = self.placed_id_base() + np.arange(len(self.pk), dtype=np.int64)
+
     def step(self):
         n = self.step_index
         self.push_and_deposit()
@@ -565,6 +586,8 @@ class Sim:
             self.imax = np.maximum(self.imax, em * em)
         self.ionize(n + 1)
         self.step_index = n + 1
+        if self.track_every > 0 and (n + 1) % self.track_every == 0:
+            self._record_tracks(n + 1)
 
     def run(self, nsteps):
         for _ in range(nsteps):
@@ -650,6 +673,28 @@ class Sim:
         from zero."""
         self.imax_every = int(every)
         self.imax = np.zeros(self.S)
+
+    def set_tracks(self, fraction, every):
+        """Trajectory sampling (Sec. 5: tracks of a random 2 % of the
+        electrons).  A particle is sampled iff the first word of the Philox
+        block (seed; particle id, 0, TRACK) is below floor(fraction 2^32), so an
+        electron and its positive carrier are sampled together and the choice
+        does not depend on the particle's slot.  After every step whose new step
+        index is a multiple of `every` (0 = off), each sampled live particle's
+        (id, kind, step, position in cells) is recorded."""
+        self.track_every = int(every)
+        self.track_thr = int(math.floor(float(fraction) * 2.0 ** 32))
+        self.tracks = []
+
+    def _record_tracks(self, step):
+        self._ensure_ids()
+        if len(self.pid) == 0:
+            return
+        w = philox.draw32(self.P.seed, self.pid, 0, philox.PURPOSE_TRACK)[0]
+        sel = np.nonzero(w.astype(np.int64) < self.track_thr)[0]
+        for q in sel:
+            self.tracks.append((int(self.pid[q]), int(self.pk[q]), int(step),
+                                float(self.px[q, 0]), float(self.px[q, 1]), float(self.px[q, 2])))
 
     def imax_nodes(self):
         """The running maximum of |E|^2 [V^2/m^2] on the domain nodes."""

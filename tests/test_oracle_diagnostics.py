@@ -11,6 +11,11 @@ histogram and the maximum accumulated intensity.
   node it passed the square of the peak incident field, I = c eps0 E0^2 / 2,
   to within the sampling of the carrier; nodes it has not reached stay zero;
   sampling a subset of the steps never gives more.
+* Trajectory sampling: the sampled fraction is the stated one (5 sigma of the
+  binomial) and follows the particle id, not its slot; through a run with
+  births every record equals the particle's state after the recorded step,
+  every sampled live particle is recorded at every record step, and a birth
+  enters at its neutral's position.
 """
 
 import math
@@ -145,3 +150,59 @@ def test_max_intensity_of_a_plane_wave_in_vacuum():
     # worst; the 6-cycle envelope varies by < 0.3 % within a quarter period
     assert np.all(ratio > 0.985) and np.all(ratio < 1.005), (ratio.min(), ratio.max())
     assert np.all(s3.imax_nodes()[20:200] / E0sq > 0.9)
+
+
+# ---------------------------------------------------------------- trajectories
+def test_track_selection_is_the_stated_fraction():
+    s = pic.Sim(_cfg(), load_neutrals=False)
+    n = 200_000
+    s.px = np.column_stack([np.full(n, 10.5), np.zeros(n), np.zeros(n)])
+    s.pu = np.zeros((n, 3))
+    s.pk = np.zeros(n, dtype=np.int64)
+    s.pid = np.arange(n, dtype=np.int64) * 7 + 3
+    s.set_tracks(0.02, 1)
+    s._record_tracks(1)
+    k = len(s.tracks)
+    sd = math.sqrt(n * 0.02 * 0.98)
+    assert abs(k - 0.02 * n) < 5 * sd
+    # the selection follows the id, not the slot: shuffling the slots selects
+    # the same ids
+    ids0 = {t[0] for t in s.tracks}
+    s.pid = s.pid[np.random.default_rng(1).permutation(n)]
+    s.tracks = []
+    s._record_tracks(1)
+    assert {t[0] for t in s.tracks} == ids0
+
+
+def test_tracks_record_sampled_particles_at_their_steps():
+    """A run with births: every record equals the particle's state after the
+    recorded step (brute force over the steps), births enter at their neutral's
+    position, particles that left the box stop being recorded."""
+    cfg = W.config_1d(hi=True, ppc=4, n=256, nsteps=700)
+    s = pic.Sim(cfg)
+    s.set_tracks(0.25, 5)
+    snaps = {}
+    for k in range(700):
+        s.step()
+        if (k + 1) % 5 == 0:
+            snaps[k + 1] = {(int(i), int(kd)): x for i, kd, x in zip(s.pid, s.pk, s.px[:, 0])}
+    assert len(s.events) > 0 and len(s.tracks) > 0
+    w = {}
+    for pid, kd, st, x, _, _ in s.tracks:
+        assert st % 5 == 0
+        assert snaps[st][(pid, kd)] == x
+        w.setdefault((pid, kd), []).append(st)
+    # every sampled live particle at a record step has its record
+    sel = {i for i, *_ in s.tracks}
+    for st, snap in snaps.items():
+        for (pid, kd) in snap:
+            if pid in sel:
+                assert st in w[(pid, kd)]
+    # births: the neutral's position at the first record after the birth step
+    # (the particle is recorded from its birth on)
+    death = {int(i): int(d) for i, d in zip(s.nid, s.ndeath) if d >= 0}
+    npos = {int(i): float(x) for i, x in zip(s.nid, s.npos[:, 0])}
+    born_at_record = [(pid, kd) for (pid, kd), sts in w.items() if death.get(pid, -1) == sts[0]]
+    assert len(born_at_record) > 0
+    for pid, kd in born_at_record:
+        assert snaps[w[(pid, kd)][0]][(pid, kd)] == npos[pid]
