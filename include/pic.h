@@ -169,9 +169,11 @@ enum {
                              the last x node of a field tile that has held a
                              nonzero E or b, then the field tiles updated so far,
                              summed over the field launches */
-  PIC_DIAG_IMAX = 11      /* float: maximum accumulated intensity at nodes, the
+  PIC_DIAG_IMAX = 11,     /* float: maximum accumulated intensity at nodes, the
                              largest node |E|^2 [V^2/m^2] over the samples taken
                              since pic_set_imax (zero when never enabled) */
+  PIC_DIAG_TRACKS = 12    /* pic_track records taken since pic_set_tracks, sorted
+                             by (id, kind, step) */
 };
 
 /* PIC_DIAG_SCALARS layout (all double). */
@@ -179,7 +181,7 @@ enum {
   PIC_SC_STEP = 0, PIC_SC_TIME = 1, PIC_SC_N_NEUTRAL = 2, PIC_SC_N_E = 3, PIC_SC_N_POS = 4,
   PIC_SC_EVENTS = 5, PIC_SC_U_FIELD = 6, PIC_SC_KE_E = 7, PIC_SC_KE_POS = 8,
   PIC_SC_E_GAP = 9, PIC_SC_E_ABS = 10, PIC_SC_GAUSS_MAX = 11, PIC_SC_RHO_MAX = 12,
-  PIC_SC_HEALTH = 13, PIC_SC_SLOTS = 14, PIC_SC_COUNT = 16
+  PIC_SC_HEALTH = 13, PIC_SC_SLOTS = 14, PIC_SC_TRACKS_DROPPED = 15, PIC_SC_COUNT = 16
 };
 
 /* A charged macroparticle: cell indices, FP32 offsets in [0, 1) (position =
@@ -328,6 +330,35 @@ typedef struct {
  * Errors: PIC_E_INVAL (bad edges, range beyond int32 or out_count),
  * PIC_E_NOMEM, PIC_E_DEVICE. */
 pic_status pic_spectrum_counts(pic_ctx* c, const pic_spectrum* s, uint64_t* out, size_t out_count);
+
+/* A recorded position of a sampled particle: id (the parent neutral's id,
+ * cell index x ppc + k; particles placed by pic_set_state: cells x ppc + their
+ * index), kind, the step index after which it was taken, and the position
+ * (cell + offset, as in pic_particle; absent axes 0). */
+typedef struct {
+  uint32_t id;
+  int32_t kind;
+  int32_t step;
+  int32_t cell[3];
+  float off[3];
+  int32_t reserved;
+} pic_track;
+
+/* Trajectory sampling (Sec. 5: tracks of a random 2 % of the electrons).  A
+ * particle is sampled iff the first 32-bit word of the Philox-4x32-10 block
+ * with key (seed) and counter (id, 0, 6) is below `threshold` (fraction x 2^32):
+ * an electron and its positive carrier, which share the id, go together, and
+ * the choice does not depend on where the particle sits.  every > 0: after
+ * each step whose new step index is a multiple of `every`, every sampled live
+ * particle appends one pic_track; records beyond max_records are dropped and
+ * counted (PIC_SC_TRACKS_DROPPED).  Enabling clears the records; every = 0
+ * stops recording and keeps them.  Read with PIC_DIAG_TRACKS.  The records take
+ * 40 B each plus 256 B, allocated here (through the configuration's allocator
+ * when it has one).  A batch does not record: pic_batch_step returns
+ * PIC_E_STATE while a member records.  Errors: PIC_E_INVAL (negative
+ * arguments, or ids that do not fit 32 bits: cells x ppc + capacity >= 2^32),
+ * PIC_E_NOMEM, PIC_E_STATE (latched error). */
+pic_status pic_set_tracks(pic_ctx* c, uint32_t threshold, int32_t every, int64_t max_records);
 
 /* Far field tiles (default on): the push tracks on the device every x cell
  * that has held a charged particle at any step so far.  A field tile whose x

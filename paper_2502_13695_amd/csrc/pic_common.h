@@ -19,7 +19,7 @@ constexpr unsigned HEALTH_NONFINITE = 2u;
 
 // Philox draw purposes (fourth counter word)
 constexpr uint32_t PURPOSE_POS = 1, PURPOSE_VEL = 2, PURPOSE_IONIZE = 3,
-                   PURPOSE_STRESS_E = 4, PURPOSE_STRESS_P = 5;
+                   PURPOSE_STRESS_E = 4, PURPOSE_STRESS_P = 5, PURPOSE_TRACK = 6;
 
 // ---------------------------------------------------------------- Philox
 // Philox4x32-10 (Salmon et al., SC'11): counter (id_lo, id_hi, step, purpose),
@@ -164,6 +164,7 @@ struct Inst {
   uint32_t* pcell;              // packed cell indices
   float *po0, *po1, *po2, *pu0, *pu1, *pu2;
   uint8_t* pkind;
+  uint32_t* pid;                // id of the parent neutral (placed particles: cells * ppc + index)
   int* pcount;                  // used slots
   int capacity;
   // tile sort: [0, sctl[SC_NSORTED]) holds the groups in order (tile-major);
@@ -176,6 +177,7 @@ struct Inst {
   uint32_t* scell;              // scatter targets (same layout as the particle arrays)
   float *so0, *so1, *so2, *su0, *su1, *su2;
   uint8_t* skind;
+  uint32_t* spid;
   // particle kinds: 2m electron, 2m+1 positive carrier
   float kh[MAXKIND];            // q dt / (2 m c)
   float kq[MAXKIND][3];         // qhat dx_d (present axes) or qhat c dt (absent)

@@ -79,6 +79,16 @@ struct ImaxArgs {
   int64_t sy, sz;
 };
 void launch_imax(const ImaxArgs& a, float* imax, hipStream_t s);
+// one record of a sampled particle (the layout of pic_track)
+struct TrackRec {
+  uint32_t id;
+  int32_t kind, step;
+  int32_t cell[3];
+  float off[3];
+  int32_t pad;
+};
+void launch_tracks(const Inst* d, int D, int capacity, uint32_t thr, int step, TrackRec* rec,
+                   unsigned long long* n, int64_t max_records, hipStream_t s);
 void launch_diag_particles(const Inst* d, int capacity, double* acc, hipStream_t s);
 void launch_diag_field_energy(const Inst* d, int64_t ncell, double* acc, hipStream_t s);
 void launch_diag_deposit(const Inst* d, int D, int order, int capacity, double* grid, int what,

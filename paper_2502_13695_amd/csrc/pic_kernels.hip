@@ -881,6 +881,7 @@ __global__ __launch_bounds__(TPB) void k_sort_scatter(Group g) {
     I.su0[d] = I.pu0[p];
     I.su1[d] = I.pu1[p];
     I.su2[d] = I.pu2[p];
+    I.spid[d] = I.pid[p];
   }
 }
 
@@ -894,6 +895,7 @@ __device__ __forceinline__ void sort_move(const IT& I, int from, int to) {
   I.pu0[to] = I.su0[from];
   I.pu1[to] = I.su1[from];
   I.pu2[to] = I.su2[from];
+  I.pid[to] = I.spid[from];
 }
 
 // One wave per group (grid-stride over the groups, no block barriers): count
@@ -1006,6 +1008,7 @@ __global__ __launch_bounds__(TPB) void k_sort_group(Group g) {
       permute_array<D>(reinterpret_cast<const unsigned*>(I.su0) + s0, reinterpret_cast<unsigned*>(I.pu0) + s0, n, ps, buf, lane);
       permute_array<D>(reinterpret_cast<const unsigned*>(I.su1) + s0, reinterpret_cast<unsigned*>(I.pu1) + s0, n, ps, buf, lane);
       permute_array<D>(reinterpret_cast<const unsigned*>(I.su2) + s0, reinterpret_cast<unsigned*>(I.pu2) + s0, n, ps, buf, lane);
+      permute_array<D>(I.spid + s0, I.pid + s0, n, ps, buf, lane);
       // kinds are bytes: move them through the same buffer one per word
       for (int q = lane; q < n; q += 64) buf[ps[q]] = I.skind[s0 + q];
       sync_wave();
@@ -1630,6 +1633,7 @@ __device__ __forceinline__ void ionize_one(const IT& I, int64_t jn, int step) {
     I.pu1[q] = uy;
     I.pu2[q] = uz;
     I.pkind[q] = (uint8_t)(2 * mat + s);
+    I.pid[q] = (uint32_t)id;
   }
 }
 
@@ -1679,6 +1683,7 @@ __global__ __launch_bounds__(TPB) void k_preionize(const Inst* d, const float* s
     I.pu1[q] = uy;
     I.pu2[q] = uz;
     I.pkind[q] = (uint8_t)(2 * mat + s);
+    I.pid[q] = (uint32_t)id;
   }
 }
 
@@ -1758,6 +1763,42 @@ __global__ __launch_bounds__(SPEC_TPB) void k_spectrum(const Inst* d, SpecArgs a
     __syncthreads();
     for (int q = threadIdx.x; q < ncnt; q += SPEC_TPB)
       if (sc[q]) atomicAdd(&out[q], (unsigned long long)sc[q]);
+  }
+}
+
+// Trajectory sampling (Sec. 5: tracks of a random 2 % of the electrons): a
+// live particle is sampled iff the first word of the Philox block
+// (seed; id, 0, TRACK) is below thr, so an electron and its positive carrier
+// (one id) go together and the choice does not depend on the slot.  Each
+// sampled particle appends one record; records beyond max_records are counted
+// but not written.
+template <int D>
+__global__ __launch_bounds__(TPB) void k_tracks(const Inst* d, uint32_t thr, int step, TrackRec* rec,
+                                                unsigned long long* n, int64_t max_records) {
+  const Inst& I = *d;
+  int count = *I.pcount;
+  count = count < I.capacity ? count : I.capacity;
+  for (int p = blockIdx.x * TPB + threadIdx.x; p < count; p += gridDim.x * TPB) {
+    const int kd = I.pkind[p];
+    if (kd == DEAD) continue;
+    const uint32_t id = I.pid[p];
+    if (draw(I.seed, (uint64_t)id, 0u, PURPOSE_TRACK).x >= thr) continue;
+    const unsigned long long q = atomicAdd(n, 1ull);
+    if ((int64_t)q >= max_records) continue;
+    int ci, cj, ck;
+    unpack_cell(D, I.pcell[p], ci, cj, ck);
+    TrackRec r;
+    r.id = id;
+    r.kind = kd;
+    r.step = step;
+    r.cell[0] = ci;
+    r.cell[1] = cj;
+    r.cell[2] = ck;
+    r.off[0] = I.po0[p];
+    r.off[1] = D >= 2 ? I.po1[p] : 0.0f;
+    r.off[2] = D >= 3 ? I.po2[p] : 0.0f;
+    r.pad = 0;
+    rec[q] = r;
   }
 }
 
@@ -1982,6 +2023,12 @@ void launch_spectrum(const Inst* d, int D, int capacity, const SpecArgs& a, cons
   nb = nb < 1 ? 1 : (nb > 256 ? 256 : nb);
   const size_t lds = sizeof(double) * a.nedges + (a.lds ? sizeof(unsigned) * a.nkinds * (a.nedges + 1) : 0);
   DISPATCH_D(D, hipLaunchKernelGGL((k_spectrum<DD>), dim3(nb), dim3(SPEC_TPB), lds, s, d, a, edges, out));
+}
+void launch_tracks(const Inst* d, int D, int capacity, uint32_t thr, int step, TrackRec* rec,
+                   unsigned long long* n, int64_t max_records, hipStream_t s) {
+  unsigned nb = (unsigned)((capacity + TPB - 1) / TPB);
+  nb = nb < 1 ? 1 : (nb > 2048 ? 2048 : nb);
+  DISPATCH_D(D, hipLaunchKernelGGL((k_tracks<DD>), dim3(nb), dim3(TPB), 0, s, d, thr, step, rec, n, max_records));
 }
 void launch_imax(const ImaxArgs& a, float* imax, hipStream_t s) {
   if (a.nodes <= 0) return;

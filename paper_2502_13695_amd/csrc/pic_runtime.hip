@@ -64,11 +64,11 @@ struct Layout {
   size_t o_F[2][6], o_J[2][3], o_ie_half, o_ie_node, o_mat, o_src, o_prof;
   size_t o_ring, o_suffix, o_prefix, o_A;
   size_t o_no[3], o_alive, o_death, o_mcell;
-  size_t o_pcell, o_po[3], o_pu[3], o_pkind;
+  size_t o_pcell, o_po[3], o_pu[3], o_pkind, o_pid;
   int ntile[3];
   int64_t ntiles, ngroups, maxchunks;
   size_t o_gcnt, o_gn, o_gstart, o_gfill, o_chunks;
-  size_t o_scell, o_so[3], o_su[3], o_skind;
+  size_t o_scell, o_so[3], o_su[3], o_skind, o_spid;
   size_t o_tab[MAXMAT];
   size_t o_ctr;      // pcount, step, health, nevents[MAXMAT], diag accumulators
   size_t o_grid64;   // FP64 node grid for diagnostics
@@ -165,6 +165,7 @@ pic_status plan(const pic_config* cfg, const Canon& c, const std::vector<TableHo
   for (int q = 0; q < 3; ++q) L->o_po[q] = take(q < D ? sizeof(float) * L->capacity : 0);
   for (int q = 0; q < 3; ++q) L->o_pu[q] = take(sizeof(float) * L->capacity);
   L->o_pkind = take(L->capacity);
+  L->o_pid = take(sizeof(uint32_t) * L->capacity);
   L->o_gcnt = take(sizeof(int) * L->ngroups);
   L->o_gn = take(sizeof(int) * L->ngroups);
   L->o_gstart = take(sizeof(int) * L->ngroups);
@@ -174,6 +175,7 @@ pic_status plan(const pic_config* cfg, const Canon& c, const std::vector<TableHo
   for (int q = 0; q < 3; ++q) L->o_so[q] = take(q < D ? sizeof(float) * L->capacity : 0);
   for (int q = 0; q < 3; ++q) L->o_su[q] = take(sizeof(float) * L->capacity);
   L->o_skind = take(L->capacity);
+  L->o_spid = take(sizeof(uint32_t) * L->capacity);
   for (int m = 0; m < MAXMAT; ++m) L->o_tab[m] = take(m < (int)tabs.size() ? tabs[m].bytes.size() : 0);
   L->o_ctr = take(sizeof(Ctr));
   L->o_grid64 = take(sizeof(double) * (size_t)L->ncell);
@@ -228,6 +230,10 @@ struct pic_ctx {
   int imax_every = 0;         // node |E|^2 maximum sampled every k steps (0 off)
   float* d_imax = nullptr;    // its running maximum (padded grid), allocated on demand
   void* d_spec = nullptr;     // energy histogram: edges and counts, allocated on demand
+  int track_every = 0;        // trajectory records every k steps (0 off)
+  uint32_t track_thr = 0;     // sampled iff the id's Philox word is below this
+  int64_t track_max = 0;      // records kept
+  void* d_tracks = nullptr;   // record counter (256 B), then the records
 };
 
 struct pic_batch {
@@ -265,6 +271,14 @@ namespace {
   } while (0)
 
 inline void* devp(pic_ctx* c, size_t off) { return c->base + off; }
+
+// first id of particles placed by pic_set_state: cells x ppc (every neutral
+// id, cell index x ppc + k, lies below it)
+int64_t placed_id_base(const pic_ctx* c) {
+  int64_t cells = 1;
+  for (int d = 0; d < c->canon.D; ++d) cells *= c->canon.n[d];
+  return cells * (c->canon.ppc > 0 ? c->canon.ppc : 1);
+}
 
 // device memory beyond the state block, from the caller's allocator when given
 void* dev_alloc(pic_ctx* c, size_t bytes) {
@@ -431,6 +445,10 @@ void enqueue_step(pic_ctx* c) {
   }
   if (c->imax_every > 0 && (c->step + 1) % c->imax_every == 0) launch_imax(imax_args(c), c->d_imax, s);
   timed(c, 2, [&](Stamp st) { launch_ionize(single(c, 3, c->nb_neut), D, order, s, st); });
+  if (c->track_every > 0 && (c->step + 1) % c->track_every == 0)
+    launch_tracks(c->d_inst, D, (int)c->L.capacity, c->track_thr, (int)(c->step + 1),
+                  (TrackRec*)((unsigned char*)c->d_tracks + 256), (unsigned long long*)c->d_tracks,
+                  c->track_max, s);
   if (sampled(c)) ++c->ev_slot;
   ++c->step;
 }
@@ -693,6 +711,7 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
   I.pu1 = (float*)devp(c, L.o_pu[1]);
   I.pu2 = (float*)devp(c, L.o_pu[2]);
   I.pkind = (uint8_t*)devp(c, L.o_pkind);
+  I.pid = (uint32_t*)devp(c, L.o_pid);
   for (int d = 0; d < 3; ++d) I.ntile[d] = L.ntile[d];
   I.ntiles = (int)L.ntiles;
   I.gcnt = (int*)devp(c, L.o_gcnt);
@@ -708,6 +727,7 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
   I.su1 = (float*)devp(c, L.o_su[1]);
   I.su2 = (float*)devp(c, L.o_su[2]);
   I.skind = (uint8_t*)devp(c, L.o_skind);
+  I.spid = (uint32_t*)devp(c, L.o_spid);
   c->d_ctr = (Ctr*)devp(c, L.o_ctr);
   I.pcount = &c->d_ctr->pcount;
   I.sctl = c->d_ctr->sctl;
@@ -832,6 +852,7 @@ void pic_destroy(pic_ctx* c) {
   if (c->h_step) (void)hipHostFree(c->h_step);
   dev_free(c, c->d_imax);
   dev_free(c, c->d_spec);
+  dev_free(c, c->d_tracks);
   if (c->base) {
     if (c->owns_alloc_via_cb && c->cfg.free) c->cfg.free(c->base, c->cfg.alloc_user);
     else if (!c->owns_alloc_via_cb) (void)hipFree(c->base);
@@ -888,6 +909,31 @@ pic_status pic_spectrum_counts(pic_ctx* c, const pic_spectrum* sp, uint64_t* out
   HIP_OK(hipGetLastError());
   HIP_OK(hipMemcpyAsync(out, d_cnt, sizeof(unsigned long long) * out_count, hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
+  return PIC_OK;
+}
+
+pic_status pic_set_tracks(pic_ctx* c, uint32_t threshold, int32_t every, int64_t max_records) {
+  if (!c || every < 0 || max_records < 0) return PIC_E_INVAL;
+  if (c->latched != PIC_OK) return PIC_E_STATE;
+  if (every > 0) {
+    // ids are stored in 32 bits: neutral ids and placed particles' ids must fit
+    if ((double)placed_id_base(c) + (double)c->L.capacity > 4294967295.0) return PIC_E_INVAL;
+    if (max_records > ((int64_t)1 << 40) / (int64_t)sizeof(TrackRec)) return PIC_E_INVAL;
+    const size_t bytes = 256 + sizeof(TrackRec) * (size_t)max_records;
+    if (c->d_tracks && c->track_max != max_records) {
+      if (hipStreamSynchronize(c->stream) != hipSuccess) return PIC_E_DEVICE;
+      dev_free(c, c->d_tracks);
+      c->d_tracks = nullptr;
+    }
+    if (!c->d_tracks) {
+      c->d_tracks = dev_alloc(c, bytes);
+      if (!c->d_tracks) return PIC_E_NOMEM;
+    }
+    c->track_max = max_records;
+    HIP_OK(hipMemsetAsync(c->d_tracks, 0, 256, c->stream));
+  }
+  c->track_every = every;
+  c->track_thr = threshold;
   return PIC_OK;
 }
 
@@ -1031,7 +1077,10 @@ pic_status pic_set_state(pic_ctx* c, const pic_state* S) {
       pu[q].resize(n);
     }
     std::vector<uint8_t> pk(n);
+    std::vector<uint32_t> pid(n);
+    const int64_t id0 = placed_id_base(c);
     for (int64_t p = 0; p < n; ++p) {
+      pid[p] = (uint32_t)(id0 + p);
       const pic_particle& r = S->particles[p];
       for (int d = 0; d < D; ++d)
         if (r.cell[d] < 0 || r.cell[d] >= K.n[d] || !(r.off[d] >= 0.0f && r.off[d] < 1.0f)) return PIC_E_INVAL;
@@ -1050,6 +1099,7 @@ pic_status pic_set_state(pic_ctx* c, const pic_state* S) {
         HIP_OK(hipMemcpy(devp(c, L.o_pu[q]), pu[q].data(), 4 * n, hipMemcpyHostToDevice));
       }
       HIP_OK(hipMemcpy(devp(c, L.o_pkind), pk.data(), n, hipMemcpyHostToDevice));
+      HIP_OK(hipMemcpy(devp(c, L.o_pid), pid.data(), 4 * n, hipMemcpyHostToDevice));
     }
     const int cnt = (int)n;
     HIP_OK(hipMemcpy(&c->d_ctr->pcount, &cnt, sizeof cnt, hipMemcpyHostToDevice));
@@ -1105,6 +1155,7 @@ pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size
     case PIC_DIAG_SORT: need = sizeof(double) * 4; break;
     case PIC_DIAG_REGION: need = sizeof(double) * 6; break;
     case PIC_DIAG_EVENTS:
+    case PIC_DIAG_TRACKS:
     case PIC_DIAG_PARTICLES: break;   // computed below
     default: return PIC_E_INVAL;
   }
@@ -1126,6 +1177,25 @@ pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size
     if (!host_out) return PIC_OK;
     if (out_bytes < need) return PIC_E_INVAL;
     if (need) std::memcpy(host_out, pairs.data(), need);
+    return PIC_OK;
+  }
+  if (kind == PIC_DIAG_TRACKS) {
+    unsigned long long nrec = 0;
+    if (c->d_tracks) HIP_OK(hipMemcpy(&nrec, c->d_tracks, sizeof nrec, hipMemcpyDeviceToHost));
+    const int64_t keep = std::min<int64_t>((int64_t)nrec, c->track_max);
+    need = sizeof(TrackRec) * (size_t)keep;
+    if (written) *written = need;
+    if (!host_out) return PIC_OK;
+    if (out_bytes < need) return PIC_E_INVAL;
+    if (keep > 0) {
+      TrackRec* o = (TrackRec*)host_out;
+      HIP_OK(hipMemcpy(o, (unsigned char*)c->d_tracks + 256, need, hipMemcpyDeviceToHost));
+      std::sort(o, o + keep, [](const TrackRec& a, const TrackRec& b) {
+        if (a.id != b.id) return a.id < b.id;
+        if (a.kind != b.kind) return a.kind < b.kind;
+        return a.step < b.step;
+      });
+    }
     return PIC_OK;
   }
   if (kind == PIC_DIAG_PARTICLES) {
@@ -1317,6 +1387,9 @@ pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size
   o[PIC_SC_RHO_MAX] = h.acc[45];
   o[PIC_SC_HEALTH] = (double)h.health;
   o[PIC_SC_SLOTS] = (double)h.pcount;
+  unsigned long long nrec = 0;
+  if (c->d_tracks) HIP_OK(hipMemcpy(&nrec, c->d_tracks, sizeof nrec, hipMemcpyDeviceToHost));
+  o[PIC_SC_TRACKS_DROPPED] = (double)std::max<int64_t>(0, (int64_t)nrec - c->track_max);
   return PIC_OK;
 }
 
@@ -1464,7 +1537,7 @@ static bool batch_capture(pic_batch* b, int period) {
 pic_status pic_batch_step(pic_batch* b, int64_t nsteps) {
   if (!b || nsteps < 0) return PIC_E_INVAL;
   for (pic_ctx* c : b->members)
-    if (c->latched != PIC_OK || c->imax_every > 0) return PIC_E_STATE;
+    if (c->latched != PIC_OK || c->imax_every > 0 || c->track_every > 0) return PIC_E_STATE;
   if (b->dirty) {
     pic_status st = batch_rebuild(b);
     if (st != PIC_OK) return st;

@@ -23,9 +23,9 @@ ABI_VERSION = 1
 ENV = {"gauss": 0, "sin2": 1}
 BC = {"outflow": 0, "periodic": 1}
 DIAG_SCALARS, DIAG_FIELDS, DIAG_NE, DIAG_UE, DIAG_EVENTS, DIAG_PARTICLES, DIAG_PARAMS, DIAG_AMP, \
-    DIAG_TIMERS, DIAG_SORT, DIAG_REGION, DIAG_IMAX = range(12)
+    DIAG_TIMERS, DIAG_SORT, DIAG_REGION, DIAG_IMAX, DIAG_TRACKS = range(13)
 SC = dict(step=0, time=1, n_neutral=2, n_e=3, n_pos=4, events=5, u_field=6, ke_e=7, ke_pos=8,
-          e_gap=9, e_abs=10, gauss_max=11, rho_max=12, health=13, slots=14)
+          e_gap=9, e_abs=10, gauss_max=11, rho_max=12, health=13, slots=14, tracks_dropped=15)
 
 
 class PicError(RuntimeError):
@@ -80,6 +80,10 @@ class Particle(C.Structure):
 
 PARTICLE_DTYPE = np.dtype([("cell", "<i4", 3), ("kind", "<i4"), ("off", "<f4", 3), ("u", "<f4", 3)])
 assert PARTICLE_DTYPE.itemsize == C.sizeof(Particle)
+# pic_track: a recorded position of a sampled particle
+TRACK_DTYPE = np.dtype([("id", "<u4"), ("kind", "<i4"), ("step", "<i4"), ("cell", "<i4", 3),
+                        ("off", "<f4", 3), ("reserved", "<i4")])
+assert TRACK_DTYPE.itemsize == 40
 
 
 class State(C.Structure):
@@ -93,7 +97,7 @@ SYMBOLS = ["pic_init", "pic_step", "pic_diag", "pic_set_state", "pic_footprint",
            "pic_batch_step", "pic_batch_add", "pic_batch_remove", "pic_batch_destroy", "pic_batch_set_graph",
            "pic_batch_graph_replays",
            "pic_set_timing", "pic_autotune", "pic_autotune_steps", "pic_set_resort", "pic_set_far_tiles",
-           "pic_set_imax", "pic_spectrum_counts", "pic_destroy", "pic_status_str"]
+           "pic_set_imax", "pic_spectrum_counts", "pic_set_tracks", "pic_destroy", "pic_status_str"]
 
 
 class Spectrum(C.Structure):
@@ -139,6 +143,7 @@ def lib():
             "pic_set_resort": ([vp, i32], C.c_int),
             "pic_set_far_tiles": ([vp, i32], C.c_int),
             "pic_set_imax": ([vp, i32], C.c_int),
+            "pic_set_tracks": ([vp, C.c_uint32, i32, i64], C.c_int),
             "pic_spectrum_counts": ([vp, C.POINTER(Spectrum), C.POINTER(C.c_uint64), C.c_size_t], C.c_int),
             "pic_batch_set_graph": ([vp, i32], C.c_int),
             "pic_batch_graph_replays": ([vp], C.c_int64),
@@ -352,6 +357,23 @@ class Context:
     def imax(self):
         """Maximum accumulated intensity: the largest node |E|^2 [V^2/m^2]."""
         return self._node_grid(DIAG_IMAX, np.float32)
+
+    def set_tracks(self, fraction, every, max_records=1 << 20):
+        """Record the position of a sampled `fraction` of the particles (by
+        Philox draw on their id) after every `every`-th step (0 = off)."""
+        thr = int(min(max(float(fraction), 0.0), 1.0) * 2.0 ** 32)
+        _check(lib().pic_set_tracks(self.h, min(thr, 2 ** 32 - 1), int(every), int(max_records)),
+               "pic_set_tracks")
+
+    def tracks(self):
+        """Recorded positions (TRACK_DTYPE), sorted by (id, kind, step)."""
+        nb = self._diag_bytes(DIAG_TRACKS)
+        buf = np.zeros(nb // TRACK_DTYPE.itemsize, dtype=TRACK_DTYPE)
+        w = C.c_size_t()
+        if nb:
+            _check(lib().pic_diag(self.h, DIAG_TRACKS, buf.ctypes.data_as(C.c_void_p), buf.nbytes,
+                                  C.byref(w)), "pic_diag(tracks)")
+        return buf
 
     def spectrum(self, edges_eV, x_lo_cell=0, x_hi_cell=0):
         """Macroparticle counts per kind (rows) by kinetic energy over the bin

@@ -171,3 +171,82 @@ def test_batch_refuses_sampling_member(P):
     bt.close()
     a.close()
     b.close()
+
+
+def _tracks_oracle(sim):
+    return {(i, k, s): np.array([x, y, z]) for i, k, s, x, y, z in sim.tracks}
+
+
+def _tracks_gpu(recs, ndim):
+    pos = recs["cell"].astype(np.float64) + recs["off"].astype(np.float64)
+    return {(int(r["id"]), int(r["kind"]), int(r["step"])): pos[q] for q, r in enumerate(recs)}
+
+
+@pytest.mark.parametrize("ndim,n,bc", [(1, [300], "outflow"), (2, [60, 24], "periodic"),
+                                       (3, [20, 12, 10], "periodic")])
+def test_tracks_from_seeded_state(P, ndim, n, bc):
+    """Placed particles (ids cells x ppc + index) sampled at 1/4, recorded every
+    other step for 10 steps, then the tile sort reorders the slots: the same
+    (id, kind, step) records as the oracle, positions to FP32 accuracy."""
+    cfg = dict(_cfg(ndim, n), transverse_bc=bc)
+    st = W.random_state(cfg, 3000, seed=700 + ndim, e_scale=3e8, u_scale=0.05)
+    ctx = P.Context(cfg)
+    ctx.set_resort(1)
+    ctx.set_state(0, st["E"], st["b"], _records(P, st, ndim))
+    ctx.set_tracks(0.25, 2)
+    sim = _oracle_with(cfg, st, load_neutrals=True)
+    sim.set_tracks(0.25, 2)
+    for _ in range(10):
+        sim.step()
+    ctx.step(10)
+    g, o = _tracks_gpu(ctx.tracks(), ndim), _tracks_oracle(sim)
+    assert len(o) > 500
+    assert set(g) == set(o)
+    err = max(np.max(np.abs(g[k][:ndim] - o[k][:ndim])) for k in o)
+    assert err < 2e-4, err
+    assert ctx.scalars()["tracks_dropped"] == 0
+    ctx.close()
+
+
+def test_tracks_through_slab_run(P):
+    """A 1D slab run with ionization: births sampled by their neutral's id; the
+    same records as the oracle (electron and positive carrier together)."""
+    nsteps = 1400
+    cfg = W.config_1d(hi=True, ppc=10, nsteps=nsteps)
+    ctx = P.Context(cfg)
+    ctx.set_tracks(0.5, 5)
+    ctx.step(nsteps)
+    sim = OP.Sim(cfg)
+    sim.set_tracks(0.5, 5)
+    sim.run(nsteps)
+    g, o = _tracks_gpu(ctx.tracks(), 1), _tracks_oracle(sim)
+    assert len(o) > 100
+    assert set(g) == set(o)
+    err = max(abs(g[k][0] - o[k][0]) for k in o)
+    assert err < 1e-3, err
+    ids = {k[0] for k in g}
+    kinds = {(k[0], k[1]) for k in g}
+    assert len(kinds) == 2 * len(ids)           # both carriers of every sampled birth
+    # a small record budget keeps that many and counts the rest
+    ctx2 = P.Context(cfg)
+    ctx2.set_tracks(0.5, 5, max_records=50)
+    ctx2.step(nsteps)
+    kept = _tracks_gpu(ctx2.tracks(), 1)
+    assert len(kept) == 50 and set(kept) <= set(o)
+    assert ctx2.scalars()["tracks_dropped"] == len(o) - 50
+    ctx.close()
+    ctx2.close()
+
+
+def test_batch_refuses_recording_member(P):
+    cfg = _cfg(1, [100])
+    a, b = P.Context(cfg), P.Context(cfg)
+    a.set_tracks(0.5, 3)
+    bt = P.Batch([a, b])
+    with pytest.raises(P.PicError):
+        bt.step(1)
+    a.set_tracks(0.5, 0)
+    bt.step(1)
+    bt.close()
+    a.close()
+    b.close()
