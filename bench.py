@@ -316,13 +316,15 @@ def bench_serve(args):
 
 
 def bench_diag(args):
-    """Sec. 5 diagnostics at the 2D slab grid (2048 x 512): the energy
+    """Sec. 5 diagnostics at the 2D slab grid (2048 x 512).  The energy
     histogram of 1.2e6 charged particles (a seeded synthetic state, |u| log-
-    uniform from 1e-4 to 3) over 200 log bins, for the whole box and for one
-    80-cell layer, and the node |E|^2 maximum sampled every step.  Reported:
-    the wall time of one histogram call (host edges in, counts out, synchronous)
-    and the added step time of the sampling; kernel durations come from a kernel
-    trace of this command."""
+    uniform from 1e-4 to 3, not stepped) over 200 log bins, for the whole box
+    and for one 80-cell layer.  On the 2D stress run (the slab pre-ionized at
+    2 eV, 1.31e6 carriers): the node |E|^2 maximum sampled every step, and
+    trajectory records of 2 % of the particles every 10th step.  Reported: the
+    wall time of one histogram call (host edges in, counts out, synchronous)
+    and the step times with each sampling on; kernel durations come from a
+    kernel trace of this command."""
     import numpy as np
     import torch
     import workloads as W
@@ -346,35 +348,50 @@ def bench_diag(args):
         for _ in range(3):
             ctx.spectrum(edges, lo, hi)
         ts = []
-        for _ in range(args.steps if args.steps < 200 else 50):
+        for _ in range(50):
             t0 = time.perf_counter()
             ctx.spectrum(edges, lo, hi)
             ts.append(time.perf_counter() - t0)
         out[name] = dict(call_us=1e6 * float(np.median(ts)), counted=int(ctx.spectrum(edges, lo, hi).sum()))
-    torch.cuda.synchronize()
+    ctx.close()
+
+    scfg = W.config_stress(W.config_2d())
+    ctx = pic.Context(scfg)
+    ncharged = int(ctx.scalars()["slots"])
     nstep = 400
 
-    def steps_s(every):
-        ctx.set_imax(every)
-        ctx.step(20)
+    def timed_steps():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ctx.step(nstep)
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / nstep
 
-    off1 = steps_s(0)
-    on = steps_s(1)
-    off2 = steps_s(0)
+    ctx.step(40)
+    off1 = timed_steps()
+    ctx.set_imax(1)
+    on = timed_steps()
+    ctx.set_imax(0)
+    off2 = timed_steps()
+    # trajectory records of 2 % of the particles every 10th step
+    ctx.set_tracks(0.02, 10, max_records=1 << 21)
+    timed_steps()
+    nrec = len(ctx.tracks())
+    ctx.set_tracks(0.02, 0)
+    assert ctx.scalars()["health"] == 0
     nodes = (cfg["n"][0] + 1) * (cfg["n"][1] + 1)
     ctx.close()
     return {"metric": "Sec. 5 diagnostics at the 2D slab grid", "unit": "us", "data": "synthetic",
-            "config": {"workload": "2048x512 slab, 1.2e6 charged particles (seeded state), 200 log bins",
-                       "particles": npart, "nodes": nodes},
+            "config": {"workload": "2048x512 slab; histogram of 1.2e6 charged particles (seeded state), "
+                                   "200 log bins; sampling on the 2 eV pre-ionized slab",
+                       "particles": npart, "nodes": nodes, "stress_charged": ncharged},
             "spectrum": out,
             # algorithmic bytes: kind 1 + cell 4 + u 12 per slot; E 12 + maximum read and write 8 per node
             "spectrum_bytes": 17 * npart, "imax_bytes_per_sample": 20 * nodes,
-            "step_us_without_sampling": 1e6 * 0.5 * (off1 + off2), "step_us_sampling_every_step": 1e6 * on}
+            "step_us_without_sampling": 1e6 * 0.5 * (off1 + off2), "step_us_sampling_every_step": 1e6 * on,
+            "track_records": nrec,
+            # kind 1 + id 4 per slot; a sampled one reads cell 4 + offsets 8 and writes 40
+            "tracks_bytes_per_launch": 5 * ncharged + int(0.02 * ncharged) * 52}
 
 
 def main():

@@ -1769,36 +1769,63 @@ __global__ __launch_bounds__(SPEC_TPB) void k_spectrum(const Inst* d, SpecArgs a
 // Trajectory sampling (Sec. 5: tracks of a random 2 % of the electrons): a
 // live particle is sampled iff the first word of the Philox block
 // (seed; id, 0, TRACK) is below thr, so an electron and its positive carrier
-// (one id) go together and the choice does not depend on the slot.  Each
-// sampled particle appends one record; records beyond max_records are counted
-// but not written.
+// (one id) go together and the choice does not depend on the slot.  A block
+// takes chunks of TRACK_CHUNK slots: the sampled slots of a chunk are listed
+// in LDS (one LDS atomic per wave), the chunk reserves its records with one
+// HBM atomic, then writes them.  Records beyond max_records are counted but
+// not written.
+constexpr int TRACK_CHUNK = 4096, TRACK_TPB = 1024;
 template <int D>
-__global__ __launch_bounds__(TPB) void k_tracks(const Inst* d, uint32_t thr, int step, TrackRec* rec,
+__global__ __launch_bounds__(TRACK_TPB) void k_tracks(const Inst* d, uint32_t thr, int step, TrackRec* rec,
                                                 unsigned long long* n, int64_t max_records) {
+  __shared__ unsigned slist[TRACK_CHUNK];
+  __shared__ unsigned scount;
+  __shared__ unsigned long long sbase;
   const Inst& I = *d;
   int count = *I.pcount;
   count = count < I.capacity ? count : I.capacity;
-  for (int p = blockIdx.x * TPB + threadIdx.x; p < count; p += gridDim.x * TPB) {
-    const int kd = I.pkind[p];
-    if (kd == DEAD) continue;
-    const uint32_t id = I.pid[p];
-    if (draw(I.seed, (uint64_t)id, 0u, PURPOSE_TRACK).x >= thr) continue;
-    const unsigned long long q = atomicAdd(n, 1ull);
-    if ((int64_t)q >= max_records) continue;
-    int ci, cj, ck;
-    unpack_cell(D, I.pcell[p], ci, cj, ck);
-    TrackRec r;
-    r.id = id;
-    r.kind = kd;
-    r.step = step;
-    r.cell[0] = ci;
-    r.cell[1] = cj;
-    r.cell[2] = ck;
-    r.off[0] = I.po0[p];
-    r.off[1] = D >= 2 ? I.po1[p] : 0.0f;
-    r.off[2] = D >= 3 ? I.po2[p] : 0.0f;
-    r.pad = 0;
-    rec[q] = r;
+  const int lane = threadIdx.x & 63;
+  for (int c0 = blockIdx.x * TRACK_CHUNK; c0 < count; c0 += gridDim.x * TRACK_CHUNK) {
+    if (threadIdx.x == 0) scount = 0u;
+    __syncthreads();
+#pragma unroll 4
+    for (int k = 0; k < TRACK_CHUNK / TRACK_TPB; ++k) {
+      const int p = c0 + k * TRACK_TPB + threadIdx.x;
+      bool sel = false;
+      if (p < count && I.pkind[p] != DEAD) sel = draw(I.seed, (uint64_t)I.pid[p], 0u, PURPOSE_TRACK).x < thr;
+      const unsigned long long m = __ballot(sel);
+      if (m) {
+        const int leader = __ffsll((long long)m) - 1;
+        unsigned wb = 0u;
+        if (lane == leader) wb = atomicAdd(&scount, (unsigned)__popcll(m));
+        wb = (unsigned)__shfl((int)wb, leader);
+        if (sel) slist[wb + (unsigned)__popcll(m & ((1ull << lane) - 1ull))] = (unsigned)p;
+      }
+    }
+    __syncthreads();
+    const unsigned cnt = scount;
+    if (threadIdx.x == 0) sbase = cnt ? atomicAdd(n, (unsigned long long)cnt) : 0ull;
+    __syncthreads();
+    const unsigned long long base = sbase;
+    for (unsigned i = threadIdx.x; i < cnt; i += TRACK_TPB) {
+      if ((int64_t)(base + i) >= max_records) break;
+      const int p = (int)slist[i];
+      int ci, cj, ck;
+      unpack_cell(D, I.pcell[p], ci, cj, ck);
+      TrackRec r;
+      r.id = I.pid[p];
+      r.kind = I.pkind[p];
+      r.step = step;
+      r.cell[0] = ci;
+      r.cell[1] = cj;
+      r.cell[2] = ck;
+      r.off[0] = I.po0[p];
+      r.off[1] = D >= 2 ? I.po1[p] : 0.0f;
+      r.off[2] = D >= 3 ? I.po2[p] : 0.0f;
+      r.pad = 0;
+      rec[base + i] = r;
+    }
+    __syncthreads();
   }
 }
 
@@ -2026,9 +2053,9 @@ void launch_spectrum(const Inst* d, int D, int capacity, const SpecArgs& a, cons
 }
 void launch_tracks(const Inst* d, int D, int capacity, uint32_t thr, int step, TrackRec* rec,
                    unsigned long long* n, int64_t max_records, hipStream_t s) {
-  unsigned nb = (unsigned)((capacity + TPB - 1) / TPB);
-  nb = nb < 1 ? 1 : (nb > 2048 ? 2048 : nb);
-  DISPATCH_D(D, hipLaunchKernelGGL((k_tracks<DD>), dim3(nb), dim3(TPB), 0, s, d, thr, step, rec, n, max_records));
+  unsigned nb = (unsigned)((capacity + TRACK_CHUNK - 1) / TRACK_CHUNK);
+  nb = nb < 1 ? 1 : (nb > 1024 ? 1024 : nb);
+  DISPATCH_D(D, hipLaunchKernelGGL((k_tracks<DD>), dim3(nb), dim3(TRACK_TPB), 0, s, d, thr, step, rec, n, max_records));
 }
 void launch_imax(const ImaxArgs& a, float* imax, hipStream_t s) {
   if (a.nodes <= 0) return;
