@@ -1541,8 +1541,15 @@ __device__ __forceinline__ uint64_t neutral_id(const IT& I, int64_t jn, int& ci,
   return (uint64_t)(lin * I.ppc + kk);
 }
 
+// the ionization decision of one alive neutral (no side effects)
+struct Birth {
+  bool ev;
+  int mat, ci, cj, ck;
+  uint64_t id;
+  float t0, t1, t2;
+};
 template <int D, int ORDER, class IT>
-__device__ __forceinline__ void ionize_one(const IT& I, int64_t jn, int step);
+__device__ __forceinline__ Birth ionize_decide(const IT& I, int64_t jn, int step);
 
 // Ionization of the alive neutrals with the amplitude after the field update.
 // A block first marks which of its material cells can ionize at all: the
@@ -1582,7 +1589,51 @@ __global__ __launch_bounds__(TPB) void k_ionize(Group g, std::conditional_t<ONE,
   }
   __syncthreads();
   const int64_t jn = j0 + threadIdx.x;
-  if (jn < nneut && hot[div_ppc(I, jn) - m0]) ionize_one<D, ORDER>(I, jn, step);
+  Birth b{};
+  if (jn < nneut && hot[div_ppc(I, jn) - m0]) b = ionize_decide<D, ORDER>(I, jn, step);
+  // the wave's events: one slot reservation, one event count per material, one
+  // alive-mask update per 32-neutral word (a wave holds 64 consecutive
+  // neutrals starting at a multiple of 64)
+  const unsigned long long m = __ballot(b.ev);
+  if (!m) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)m) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(I.pcount, 2 * __popcll(m));
+  base = __shfl(base, leader);
+  if (lane == 0 && (unsigned)m) atomicAnd(&I.alive[jn >> 5], ~(unsigned)m);
+  if (lane == 32 && (unsigned)(m >> 32)) atomicAnd(&I.alive[jn >> 5], ~(unsigned)(m >> 32));
+  for (unsigned long long left = m; left;) {
+    const int l0 = __ffsll((long long)left) - 1;
+    const int mt = __shfl(b.mat, l0);
+    const unsigned long long same = __ballot(b.ev && b.mat == mt);
+    if (lane == l0) atomicAdd(&I.nevents[mt], (unsigned long long)__popcll(same));
+    left &= ~same;
+  }
+  if (!b.ev) return;
+  const int n1 = step + 1;
+  I.death[jn] = n1;
+  const int slot = base + 2 * __popcll(m & ((1ull << lane) - 1ull));
+  if (slot + 2 > I.capacity) {
+    atomicOr(I.health, HEALTH_CAPACITY);
+    return;
+  }
+  float ux, uy, uz;
+  maxwell(I.seed, b.id, PURPOSE_VEL, I.ksig[b.mat], ux, uy, uz);
+  const uint32_t pc = pack_cell(D, b.ci, b.cj, b.ck);
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int q = slot + s;
+    I.pcell[q] = pc;
+    I.po0[q] = b.t0;
+    if (D >= 2) I.po1[q] = b.t1;
+    if (D >= 3) I.po2[q] = b.t2;
+    I.pu0[q] = ux;
+    I.pu1[q] = uy;
+    I.pu2[q] = uz;
+    I.pkind[q] = (uint8_t)(2 * b.mat + s);
+    I.pid[q] = (uint32_t)b.id;
+  }
 }
 
 __global__ void k_advance(const Inst* insts, int n) {
@@ -1591,50 +1642,26 @@ __global__ void k_advance(const Inst* insts, int n) {
 }
 
 template <int D, int ORDER, class IT>
-__device__ __forceinline__ void ionize_one(const IT& I, int64_t jn, int step) {
-  if (!((I.alive[jn >> 5] >> (jn & 31)) & 1u)) return;
-  int ci, cj, ck;
-  const uint64_t id = neutral_id<D>(I, jn, ci, cj, ck);
-  const float t0 = I.no0[jn];
-  const float t1 = D >= 2 ? I.no1[jn] : 0.f;
-  const float t2 = D >= 3 ? I.no2[jn] : 0.f;
+__device__ __forceinline__ Birth ionize_decide(const IT& I, int64_t jn, int step) {
+  Birth b{};
+  if (!((I.alive[jn >> 5] >> (jn & 31)) & 1u)) return b;
+  b.id = neutral_id<D>(I, jn, b.ci, b.cj, b.ck);
+  b.t0 = I.no0[jn];
+  b.t1 = D >= 2 ? I.no1[jn] : 0.f;
+  b.t2 = D >= 3 ? I.no2[jn] : 0.f;
   // amplitude at the neutral: node-shape gather of A
   Axis<ORDER> X, Y, Z;
-  make_axis<ORDER>(X, ci, t0, I.nx, 0, G, 1);
-  if (D >= 2) make_axis<ORDER>(Y, cj, t1, I.ny, I.per_y, I.Gy, I.sy);
-  if (D >= 3) make_axis<ORDER>(Z, ck, t2, I.nz, I.per_z, I.Gz, I.sz);
+  make_axis<ORDER>(X, b.ci, b.t0, I.nx, 0, G, 1);
+  if (D >= 2) make_axis<ORDER>(Y, b.cj, b.t1, I.ny, I.per_y, I.Gy, I.sy);
+  if (D >= 3) make_axis<ORDER>(Z, b.ck, b.t2, I.nz, I.per_z, I.Gz, I.sz);
   const float Ap = gather<D, ORDER>(I.A, X, Y, Z, 0, 0, 0);
-  const int mat = I.mat_cell[ci];
-  if (mat < 0 || !(Ap >= I.acut[mat])) return;
-  const float P = table_lookup(I.tab[mat], Ap);
-  const int n1 = step + 1;
-  const u32x4 w = draw(I.seed, id, (uint32_t)n1, PURPOSE_IONIZE);
+  b.mat = I.mat_cell[b.ci];
+  if (b.mat < 0 || !(Ap >= I.acut[b.mat])) return b;
+  const float P = table_lookup(I.tab[b.mat], Ap);
+  const u32x4 w = draw(I.seed, b.id, (uint32_t)(step + 1), PURPOSE_IONIZE);
   // event iff (w + 1/2) 2^-32 < P, decided exactly in FP64
-  if (!((double)w.x + 0.5 < (double)P * 4294967296.0)) return;
-  atomicAnd(&I.alive[jn >> 5], ~(1u << (jn & 31)));
-  I.death[jn] = n1;
-  atomicAdd(&I.nevents[mat], 1ull);
-  const int slot = atomicAdd(I.pcount, 2);
-  if (slot + 2 > I.capacity) {
-    atomicOr(I.health, HEALTH_CAPACITY);
-    return;
-  }
-  float ux, uy, uz;
-  maxwell(I.seed, id, PURPOSE_VEL, I.ksig[mat], ux, uy, uz);
-  const uint32_t pc = pack_cell(D, ci, cj, ck);
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    const int q = slot + s;
-    I.pcell[q] = pc;
-    I.po0[q] = t0;
-    if (D >= 2) I.po1[q] = t1;
-    if (D >= 3) I.po2[q] = t2;
-    I.pu0[q] = ux;
-    I.pu1[q] = uy;
-    I.pu2[q] = uz;
-    I.pkind[q] = (uint8_t)(2 * mat + s);
-    I.pid[q] = (uint32_t)id;
-  }
+  b.ev = (double)w.x + 0.5 < (double)P * 4294967296.0;
+  return b;
 }
 
 // ------------------------------------------------------------------ setup
