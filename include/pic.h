@@ -106,7 +106,11 @@ typedef struct {
   int32_t shape_order;         /* 1 or 2 (B-spline order of the particle shape) */
   double T_K;                  /* neutral temperature (Sec. 3.1: 300 K) */
   int32_t keldysh_terms;       /* terms of the Eq. (3) series (Sec. 2.1: 500) */
-  int32_t reserved0;
+  int32_t keldysh_tol_bits;    /* the series stops early once a bound of its
+                                  remaining tail is below 2^-bits of the partial
+                                  sum (the adaptive tolerance the paper names as
+                                  future work); 0 = 60 (full FP64 accuracy);
+                                  1 .. 60, else PIC_E_INVAL */
   uint64_t seed;               /* Philox key */
   pic_laser laser;
   int64_t particle_capacity;   /* charged-particle slots; 0 = 2 x neutrals + 4096 */

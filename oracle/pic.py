@@ -154,7 +154,7 @@ class Sim:
         draw is at least 2^-33.  Used only to avoid evaluating W there."""
         P = self.P
         A = np.geomspace(1e5, 1e13, 20001)
-        W = keldysh.keldysh_rate(A, mt.gap_eV, mt.mred, P.laser.lam, terms=P.terms)
+        W = keldysh.keldysh_rate(A, mt.gap_eV, mt.mred, P.laser.lam, terms=P.terms, tol_bits=P.tol_bits)
         Pp = -np.expm1(-W * P.dt / mt.n0)
         hit = np.nonzero(Pp >= 2.0 ** -34)[0]
         if len(hit) == 0:
@@ -542,7 +542,8 @@ class Sim:
         for mi, mt in enumerate(P.mats):
             sel = self.nmat[idx] == mi
             if np.any(sel):
-                W = keldysh.keldysh_rate(Aa[sel], mt.gap_eV, mt.mred, P.laser.lam, terms=P.terms)
+                W = keldysh.keldysh_rate(Aa[sel], mt.gap_eV, mt.mred, P.laser.lam, terms=P.terms,
+                                         tol_bits=P.tol_bits)
                 Pp[sel] = -np.expm1(-W * P.dt / mt.n0)
         w = philox.draw32(P.seed, self.nid[idx], step, philox.PURPOSE_IONIZE)[0]
         # event iff (w + 1/2) 2^-32 < P, decided exactly in FP64

@@ -125,6 +125,7 @@ class Problem:
         self.T_K = float(cfg.get("T_K", 300.0))
         self.order = int(cfg.get("shape_order", 2))
         self.terms = int(cfg.get("keldysh_terms", 500))
+        self.tol_bits = int(cfg.get("keldysh_tol_bits", 0)) or 60
         self.seed = int(cfg["seed"])
 
         # time step: cfl / (c sqrt(sum_d 1/dx_d^2)), Sec. 3.1; canonicalised

@@ -122,26 +122,29 @@ KP kparts(const MatC& m, double lam, double A) {
 }
 
 // sum_{n = n0}^{terms-1} exp(-n alpha) Dawson(sqrt(beta (d + n))), stopping once
-// the tail bound max(Dawson) e^{-n alpha}/(1 - e^{-alpha}) is below 2^-60 of the sum
-double qseries(const KP& p, double d, int n0, int terms) {
+// the bound of the remaining tail, max(Dawson) e^{-m alpha}/(1 - e^{-alpha}) from
+// the next index m, is below 2^-tol_bits of the partial sum of the whole series
+// (s_before: the terms below n0, counted in that test only)
+double qseries(const KP& p, double d, int n0, int terms, int tol_bits, double s_before = 0.0) {
   const double q = std::exp(-p.alpha);
   const double tailf = 0.5410442246 / (-std::expm1(-p.alpha));
+  const double tol = std::ldexp(1.0, -tol_bits);
   double s = 0.0, qn = std::exp(-n0 * p.alpha);
   for (int n = n0; n < terms; ++n) {
     const double a = p.beta * (d + n);
     s += qn * dawson(std::sqrt(a > 0 ? a : 0.0));
     qn *= q;
-    if (qn * tailf < 0x1p-60 * s) break;
+    if (qn * tailf < tol * (s_before + s)) break;
   }
   return s;
 }
 
 }  // namespace
 
-double keldysh_W(const MatC& m, double lam, int terms, double A) {
+double keldysh_W(const MatC& m, double lam, int terms, double A, int tol_bits) {
   const KP p = kparts(m, lam, A);
   const double N = std::floor(p.x + 1.0);
-  return p.pref * std::exp(-N * p.alpha) * qseries(p, N - p.x, 0, terms);
+  return p.pref * std::exp(-N * p.alpha) * qseries(p, N - p.x, 0, terms, tol_bits);
 }
 
 pic_status canonicalize(const pic_config* cfg, Canon* c) {
@@ -153,6 +156,7 @@ pic_status canonicalize(const pic_config* cfg, Canon* c) {
   if (cfg->nlayer < 0 || (cfg->nlayer > 0 && !cfg->layers)) return PIC_E_INVAL;
   if (cfg->shape_order != 1 && cfg->shape_order != 2) return PIC_E_INVAL;
   if (cfg->ppc < 0 || !(cfg->cfl > 0 && cfg->cfl < 1)) return PIC_E_INVAL;
+  if (cfg->keldysh_tol_bits < 0 || cfg->keldysh_tol_bits > 60) return PIC_E_INVAL;
   c->D = cfg->ndim;
   const int64_t maxn[3][3] = {{1 << 30, 1, 1}, {65535, 65535, 1}, {4095, 1023, 1023}};
   for (int d = 0; d < 3; ++d) {
@@ -253,10 +257,10 @@ namespace {
 struct Ctx {
   const MatC* m;
   double lam, dt;
-  int terms;
+  int terms, tol_bits;
 };
 
-double rate_r(const Ctx& k, double A) { return keldysh_W(*k.m, k.lam, k.terms, A) * k.dt / k.m->n0; }
+double rate_r(const Ctx& k, double A) { return keldysh_W(*k.m, k.lam, k.terms, A, k.tol_bits) * k.dt / k.m->n0; }
 double xof(const Ctx& k, double A) { return kparts(*k.m, k.lam, A).x; }
 
 // One channel (floor(x+1) = N held fixed): r = pre [Dawson(sqrt(beta d)) + sum_{n>=1}],
@@ -272,8 +276,13 @@ Split split_r(const Ctx& k, double A, double N) {
   s.pre = p.pref * std::exp(-N * p.alpha) * k.dt / k.m->n0;
   s.d = N - p.x;
   s.beta = p.beta;
-  s.S1 = s.pre * qseries(p, s.d, 1, k.terms);
-  s.T0 = s.pre * dawson(std::sqrt(s.d > 0 ? p.beta * s.d : 0.0));
+  const double t0 = dawson(std::sqrt(s.d > 0 ? p.beta * s.d : 0.0));
+  // the n >= 1 part stops where the whole series would: the n = 0 term counts
+  // in each stopping test, and the test after n = 0 alone may end the series
+  const double tail1 = std::exp(-p.alpha) * (0.5410442246 / (-std::expm1(-p.alpha)));
+  const bool stop0 = k.terms <= 1 || tail1 < std::ldexp(1.0, -k.tol_bits) * t0;
+  s.S1 = stop0 ? 0.0 : s.pre * qseries(p, s.d, 1, k.terms, k.tol_bits, t0);
+  s.T0 = s.pre * t0;
   return s;
 }
 
@@ -304,9 +313,9 @@ void cubic_fit(const double* t, const double* y, double* c) {
 
 }  // namespace
 
-pic_status build_table(const Canon& c, int mat, int terms, TableHost* out) {
-  if (mat < 0 || mat >= c.nmat || terms < 1) return PIC_E_INVAL;
-  Ctx k{&c.mats[mat], c.lam, c.dt, terms};
+pic_status build_table(const Canon& c, int mat, int terms, TableHost* out, int tol_bits) {
+  if (mat < 0 || mat >= c.nmat || terms < 1 || tol_bits < 1 || tol_bits > 60) return PIC_E_INVAL;
+  Ctx k{&c.mats[mat], c.lam, c.dt, terms, tol_bits};
   // 1. scan: amplitude cut (P < 2^-34 below) and saturation (r >= 40 above)
   const double Alo = 1e5, Ahi = 1e12, ratio = 1.0005;
   double acut = -1.0, asat = Ahi, prev = Alo;

@@ -38,13 +38,14 @@ double laser_field(const Canon& c, double t);
 double transverse_profile(const Canon& c, double y, double z);
 
 // Keldysh volumetric rate W(A) [m^-3 s^-1], FP64, `terms` terms of Eq. (3).
-double keldysh_W(const MatC& m, double lam, int terms, double A);
+// The series stops once a bound of its tail is below 2^-tol_bits of the sum.
+double keldysh_W(const MatC& m, double lam, int terms, double A, int tol_bits = 60);
 
 struct TableHost {
   std::vector<unsigned char> bytes;   // TabHdr, TabSeg[], coefficients
   float acut = 0.f, asat = 0.f;
 };
 // Table of P(A) = 1 - exp(-W dt / n0) for material `mat`.
-pic_status build_table(const Canon& c, int mat, int terms, TableHost* out);
+pic_status build_table(const Canon& c, int mat, int terms, TableHost* out, int tol_bits = 60);
 
 }  // namespace pic

@@ -31,13 +31,14 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 // Process-wide cache of the FP64-built rate tables: a table depends only on
 // the material, the wavelength, the time step and the number of terms, which
 // runs of a scan or a serving mix share (building one takes ~0.4 s of host time).
-pic_status cached_table(const Canon& c, int mat, int terms, TableHost* out) {
+pic_status cached_table(const Canon& c, int mat, int terms, int tol_bits, TableHost* out) {
   static std::mutex mu;
   static std::map<std::string, TableHost> cache;
   const MatC& m = c.mats[mat];
   const double key_v[9] = {m.gap_eV, m.n_index, m.n0, m.mred, m.mol_kg, m.e_kg, m.p_kg, c.lam, c.dt};
   std::string key(reinterpret_cast<const char*>(key_v), sizeof key_v);
   key.append(reinterpret_cast<const char*>(&terms), sizeof terms);
+  key.append(reinterpret_cast<const char*>(&tol_bits), sizeof tol_bits);
   {
     std::lock_guard<std::mutex> g(mu);
     auto it = cache.find(key);
@@ -46,7 +47,7 @@ pic_status cached_table(const Canon& c, int mat, int terms, TableHost* out) {
       return PIC_OK;
     }
   }
-  const pic_status st = build_table(c, mat, terms, out);
+  const pic_status st = build_table(c, mat, terms, out, tol_bits);
   if (st != PIC_OK) return st;
   std::lock_guard<std::mutex> g(mu);
   if (cache.size() >= 256) cache.clear();
@@ -559,7 +560,7 @@ pic_status pic_table_probe(const pic_config* cfg, int32_t mat, const float* A, i
   pic_status st = canonicalize(cfg, &c);
   if (st != PIC_OK) return st;
   TableHost T;
-  st = build_table(c, mat, cfg->keldysh_terms, &T);
+  st = build_table(c, mat, cfg->keldysh_terms, &T, cfg->keldysh_tol_bits > 0 ? cfg->keldysh_tol_bits : 60);
   if (st != PIC_OK) return st;
   const TabHdr* h = reinterpret_cast<const TabHdr*>(T.bytes.data());
   for (int64_t i = 0; i < n; ++i) P_out[i] = table_lookup(h, A[i]);
@@ -601,7 +602,8 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
   const int D = K.D;
   c->tabs.resize(K.nmat);
   for (int m = 0; m < K.nmat; ++m) {
-    st = cached_table(K, m, cfg_in->keldysh_terms > 0 ? cfg_in->keldysh_terms : 500, &c->tabs[m]);
+    st = cached_table(K, m, cfg_in->keldysh_terms > 0 ? cfg_in->keldysh_terms : 500,
+                      cfg_in->keldysh_tol_bits > 0 ? cfg_in->keldysh_tol_bits : 60, &c->tabs[m]);
     if (st != PIC_OK) {
       delete c;
       return st;

@@ -60,7 +60,7 @@ class Config(C.Structure):
                 ("cfl", C.c_double), ("nsteps", C.c_int64), ("nmat", C.c_int32),
                 ("nlayer", C.c_int32), ("mats", C.POINTER(Material)), ("layers", C.POINTER(Layer)),
                 ("ppc", C.c_int32), ("shape_order", C.c_int32), ("T_K", C.c_double),
-                ("keldysh_terms", C.c_int32), ("reserved0", C.c_int32), ("seed", C.c_uint64),
+                ("keldysh_terms", C.c_int32), ("keldysh_tol_bits", C.c_int32), ("seed", C.c_uint64),
                 ("laser", Laser), ("particle_capacity", C.c_int64), ("preionize_eV", C.c_double),
                 ("stream", C.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN),
                 ("alloc_user", C.c_void_p)]
@@ -193,6 +193,7 @@ def make_config(cfg, stream=None, alloc=None, free=None):
     c.shape_order = int(cfg.get("shape_order", 2))
     c.T_K = float(cfg.get("T_K", 300.0))
     c.keldysh_terms = int(cfg.get("keldysh_terms", 500))
+    c.keldysh_tol_bits = int(cfg.get("keldysh_tol_bits", 0))
     c.seed = int(cfg["seed"])
     L = cfg["laser"]
     for k in ("lambda_m", "fwhm_s", "cep_rad", "waist_m", "t_peak_s"):

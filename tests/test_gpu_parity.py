@@ -193,7 +193,8 @@ def test_one_step_at_benchmark_size(P, which, monkeypatch):
     assert abs(len(parts) - len(sim.px)) <= 2 * len(ev_g ^ ev_o)   # births
 
 
-@pytest.mark.parametrize("cfg", [W.config_2d(), W.config_3d()])
+@pytest.mark.parametrize("cfg", [W.config_2d(), W.config_3d(), dict(W.config_2d(), keldysh_tol_bits=16)],
+                         ids=["2d", "3d", "2d_tol16"])
 def test_device_rate_table(P, cfg):
     small = dict(cfg, n=[64, 8, 8][:cfg["ndim"]], layers=[(m, 20 * cfg["dx"][0] + i * 1e-9,
                                                          30 * cfg["dx"][0] + i * 1e-9)
@@ -203,11 +204,14 @@ def test_device_rate_table(P, cfg):
     for mi, mt in enumerate(o.mats):
         A = np.geomspace(1e9, 9e10, 50000).astype(np.float32)
         Pd = ctx.table_probe_device(mi, A)
-        Wo = K.keldysh_rate(A.astype(np.float64), mt.gap_eV, mt.mred, o.laser.lam)
+        Wo = K.keldysh_rate(A.astype(np.float64), mt.gap_eV, mt.mred, o.laser.lam, tol_bits=o.tol_bits)
         Po = -np.expm1(-Wo * o.dt / mt.n0)
         assert not np.any((Pd == 0) & (Po >= 2.0 ** -33))
         sel = Po >= 2.0 ** -33
-        assert np.max(np.abs(Pd[sel] / Po[sel] - 1)) < 1e-6
+        # a coarse series tolerance makes the rate step where the stopping
+        # term changes; the cubic table agrees within that tolerance
+        tol = 1e-6 if o.tol_bits >= 60 else 2.0 ** -o.tol_bits + 1e-6
+        assert np.max(np.abs(Pd[sel] / Po[sel] - 1)) < tol
         # the device lookup equals the host lookup up to libm rounding
         Ph = P.table_probe(small, mi, A)
         assert np.max(np.abs(Pd[sel] / Ph[sel] - 1)) < 3e-7

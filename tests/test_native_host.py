@@ -74,10 +74,14 @@ def _closings(mt, lam, lo, hi):
     return out
 
 
-@pytest.mark.parametrize("cfg", [W.config_2d(), W.config_3d()])
+@pytest.mark.parametrize("cfg", [W.config_2d(), W.config_3d(), dict(W.config_2d(), keldysh_tol_bits=12)],
+                         ids=["2d", "3d", "2d_tol12"])
 def test_rate_table_against_insitu_fp64(cfg):
     """P(A) from the FP32 table vs 1 - exp(-W dt/n0) in FP64 at the same FP32 A,
-    over [A_cut, A_sat] and at the FP32 neighbours of every channel closing."""
+    over [A_cut, A_sat] and at the FP32 neighbours of every channel closing.  With
+    the series stopped at a coarse tolerance (2^-12) the rate jumps where the
+    stopping term changes, which the cubic table smooths: there the table must
+    agree with the stopped and with the full series within that tolerance."""
     _lib_or_skip()
     o = Problem(cfg)
     for mi, mt in enumerate(o.mats):
@@ -93,13 +97,19 @@ def test_rate_table_against_insitu_fp64(cfg):
             A = np.concatenate([A, np.array(nb, dtype=np.float32),
                                 (np.float64(Ak) * (1 + np.linspace(-1e-3, 1e-3, 41))).astype(np.float32)])
         Pt = P.table_probe(cfg, mi, A)
-        Wo = K.keldysh_rate(A.astype(np.float64), mt.gap_eV, mt.mred, o.laser.lam)
+        Wo = K.keldysh_rate(A.astype(np.float64), mt.gap_eV, mt.mred, o.laser.lam, tol_bits=o.tol_bits)
         Po = -np.expm1(-Wo * o.dt / mt.n0)
         # anything that could fire against a 32-bit draw is tabulated
         assert not np.any((Pt == 0) & (Po >= 2.0 ** -33))
         sel = Po >= 2.0 ** -33
         rel = np.abs(Pt[sel] / Po[sel] - 1)
-        assert np.max(rel) < 1e-6
+        if o.tol_bits >= 60:
+            assert np.max(rel) < 1e-6
+        else:
+            Wf = K.keldysh_rate(A.astype(np.float64), mt.gap_eV, mt.mred, o.laser.lam)
+            Pf = -np.expm1(-Wf * o.dt / mt.n0)
+            assert np.max(rel) < 2.0 ** -o.tol_bits
+            assert np.max(np.abs(Pt[sel] / Pf[sel] - 1)) < 2.0 ** -o.tol_bits + 1e-6
         assert np.all(Pt[~sel] < 2.0 ** -32)
 
 

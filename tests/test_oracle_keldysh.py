@@ -9,7 +9,9 @@ import numpy as np
 import pytest
 import scipy.special as sp
 
+import workloads as W
 from oracle import keldysh as K
+from oracle.problem import Problem
 from oracle.constants import C, QE, ME, HBAR, EPS0
 
 LAM = 800e-9
@@ -149,3 +151,21 @@ def test_rate_increases_with_field_between_closings():
     # steep growth over one decade of field: between A^4 (tunneling side) and
     # A^(2N) with N ~ 7 (multiphoton side)
     assert 1e4 < W[-1] / W[0] < 1e14
+
+
+@pytest.mark.parametrize("bits", [4, 8, 16, 30])
+def test_series_tolerance_bound(bits):
+    """The series stopped at tolerance 2^-bits: the terms are positive, so the
+    stopped sum is at most the full one and, by the tail bound, within 2^-bits of
+    it; coarser tolerances never sum more terms; at 4 bits the stop bites."""
+    mt = Problem(W.config_2d()).mats[0]
+    lam = W.LAMBDA
+    A = np.geomspace(3e8, 3e11, 400)                  # gamma from ~0.1 to ~100
+    full = K.keldysh_rate(A, mt.gap_eV, mt.mred, lam, tol_bits=60)
+    cut = K.keldysh_rate(A, mt.gap_eV, mt.mred, lam, tol_bits=bits)
+    assert np.all(cut <= full * (1 + 1e-15))
+    assert np.all((full - cut) / full <= 2.0 ** -bits)
+    coarser = K.keldysh_rate(A, mt.gap_eV, mt.mred, lam, tol_bits=max(1, bits // 2))
+    assert np.all(coarser <= cut * (1 + 1e-15))
+    if bits == 4:
+        assert np.max((full - cut) / full) > 1e-6
