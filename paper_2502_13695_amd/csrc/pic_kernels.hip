@@ -1549,7 +1549,8 @@ struct Birth {
   float t0, t1, t2;
 };
 template <int D, int ORDER, class IT>
-__device__ __forceinline__ Birth ionize_decide(const IT& I, int64_t jn, int step);
+__device__ __forceinline__ Birth ionize_decide(const IT& I, int64_t jn, int64_t m, uint32_t pcell, int mat,
+                                               int step);
 
 // Ionization of the alive neutrals with the amplitude after the field update.
 // A block first marks which of its material cells can ionize at all: the
@@ -1559,6 +1560,8 @@ __device__ __forceinline__ Birth ionize_decide(const IT& I, int64_t jn, int step
 template <int D, int ORDER, bool ONE>
 __global__ __launch_bounds__(TPB) void k_ionize(Group g, std::conditional_t<ONE, Inst, NoInst> one) {
   __shared__ unsigned char hot[TPB + 2];
+  __shared__ uint32_t scell[TPB + 2];   // packed cell and material of each cell of the block
+  __shared__ signed char smat[TPB + 2];
   const Slot sl = ONE ? Slot{0, (int)blockIdx.x, g.blocks} : block_slot(g);
   auto& I = inst_of(g, sl.ii, one);
   const int step = ONE || g.step >= 0 ? g.step : *I.step;
@@ -1574,8 +1577,11 @@ __global__ __launch_bounds__(TPB) void k_ionize(Group g, std::conditional_t<ONE,
   const int ncell = (int)(div_ppc(I, jl) - m0 + 1);
   for (int t = threadIdx.x; t < ncell; t += TPB) {
     int ci, cj, ck;
-    unpack_cell(D, I.mcell[m0 + t], ci, cj, ck);
+    const uint32_t pc = I.mcell[m0 + t];
+    unpack_cell(D, pc, ci, cj, ck);
     const int mat = I.mat_cell[ci];
+    scell[t] = pc;
+    smat[t] = (signed char)mat;
     constexpr int lo = ORDER == 2 ? -1 : 0, hi = ORDER == 2 ? 2 : 1;
     float amax = 0.0f;
     for (int c = (D >= 3 ? lo : 0); c <= (D >= 3 ? hi : 0); ++c) {
@@ -1585,12 +1591,25 @@ __global__ __launch_bounds__(TPB) void k_ionize(Group g, std::conditional_t<ONE,
         for (int a = lo; a <= hi; ++a) amax = fmaxf(amax, I.A[ci + a + G + oy + oz]);
       }
     }
-    hot[t] = mat >= 0 && amax >= I.acut[mat];
+    // a cell whose neutrals have all been ionized needs no per-neutral pass
+    const int64_t a0 = (m0 + t) * I.ppc, a1 = a0 + I.ppc;
+    bool alive = false;
+    for (int64_t w = a0 >> 5; w <= ((a1 - 1) >> 5) && !alive; ++w) {
+      const int lo_b = (int)((a0 > 32 * w ? a0 : 32 * w) - 32 * w);
+      const int hi_b = (int)((a1 < 32 * w + 32 ? a1 : 32 * w + 32) - 32 * w);
+      const uint32_t mask = hi_b - lo_b == 32 ? ~0u : ((1u << (hi_b - lo_b)) - 1u) << lo_b;
+      alive = (I.alive[w] & mask) != 0u;
+    }
+    hot[t] = alive && mat >= 0 && amax >= I.acut[mat];
   }
   __syncthreads();
   const int64_t jn = j0 + threadIdx.x;
   Birth b{};
-  if (jn < nneut && hot[div_ppc(I, jn) - m0]) b = ionize_decide<D, ORDER>(I, jn, step);
+  if (jn < nneut) {
+    const int64_t mn = div_ppc(I, jn);
+    const int t = (int)(mn - m0);
+    if (hot[t]) b = ionize_decide<D, ORDER>(I, jn, mn, scell[t], smat[t], step);
+  }
   // the wave's events: one slot reservation, one event count per material, one
   // alive-mask update per 32-neutral word (a wave holds 64 consecutive
   // neutrals starting at a multiple of 64)
@@ -1641,23 +1660,29 @@ __global__ void k_advance(const Inst* insts, int n) {
   if (i < n) *insts[i].step += 1;
 }
 
+// The cell and its material come from the block's per-cell pass; the alive
+// bit and the offsets are loaded together (one round trip).
 template <int D, int ORDER, class IT>
-__device__ __forceinline__ Birth ionize_decide(const IT& I, int64_t jn, int step) {
+__device__ __forceinline__ Birth ionize_decide(const IT& I, int64_t jn, int64_t m, uint32_t pcell, int mat,
+                                               int step) {
   Birth b{};
-  if (!((I.alive[jn >> 5] >> (jn & 31)) & 1u)) return b;
-  b.id = neutral_id<D>(I, jn, b.ci, b.cj, b.ck);
+  const uint32_t aw = I.alive[jn >> 5];
   b.t0 = I.no0[jn];
   b.t1 = D >= 2 ? I.no1[jn] : 0.f;
   b.t2 = D >= 3 ? I.no2[jn] : 0.f;
+  if (!((aw >> (jn & 31)) & 1u)) return b;
+  unpack_cell(D, pcell, b.ci, b.cj, b.ck);
+  const int64_t lin = b.ci + (int64_t)I.nx * (b.cj + (int64_t)I.ny * b.ck);
+  b.id = (uint64_t)(lin * I.ppc + (jn - m * I.ppc));
   // amplitude at the neutral: node-shape gather of A
   Axis<ORDER> X, Y, Z;
   make_axis<ORDER>(X, b.ci, b.t0, I.nx, 0, G, 1);
   if (D >= 2) make_axis<ORDER>(Y, b.cj, b.t1, I.ny, I.per_y, I.Gy, I.sy);
   if (D >= 3) make_axis<ORDER>(Z, b.ck, b.t2, I.nz, I.per_z, I.Gz, I.sz);
   const float Ap = gather<D, ORDER>(I.A, X, Y, Z, 0, 0, 0);
-  b.mat = I.mat_cell[b.ci];
-  if (b.mat < 0 || !(Ap >= I.acut[b.mat])) return b;
-  const float P = table_lookup(I.tab[b.mat], Ap);
+  b.mat = mat;
+  if (mat < 0 || !(Ap >= I.acut[mat])) return b;
+  const float P = table_lookup(I.tab[mat], Ap);
   const u32x4 w = draw(I.seed, b.id, (uint32_t)(step + 1), PURPOSE_IONIZE);
   // event iff (w + 1/2) 2^-32 < P, decided exactly in FP64
   b.ev = (double)w.x + 0.5 < (double)P * 4294967296.0;
