@@ -11,6 +11,11 @@
   ionization, sampled at 0.5 fs intervals (relative L2 2e-5, twice the field
   tolerance since the quantity is squared); stopping keeps the maximum; a batch
   refuses a member that samples.
+* Trajectory sampling: from a seeded state through sorts and through a slab
+  run with births, the same (id, kind, step) records as the oracle, positions
+  to FP32 accuracy; a record budget keeps that many and counts the rest.
+* Edge cases: no charged particles, a zero record budget, sampling that never
+  reaches its step, the largest edge count.
 """
 
 import numpy as np
@@ -250,3 +255,34 @@ def test_batch_refuses_recording_member(P):
     bt.close()
     a.close()
     b.close()
+
+
+def test_diagnostics_edge_cases(P):
+    """Empty and degenerate inputs: no charged particles, a zero record budget,
+    sampling that never reaches its step, the largest edge count."""
+    cfg = _cfg(1, [200])
+    ctx = P.Context(cfg)
+    edges = np.geomspace(1e-3, 1e3, 4097)                 # the largest edge count
+    h = ctx.spectrum(edges)
+    assert h.shape == (4, 4098) and not h.any()           # no charged particles yet
+    assert not ctx.imax().any()                           # never enabled
+    ctx.set_imax(1000)
+    ctx.step(5)
+    assert not ctx.imax().any()                           # no sampled step yet
+    ctx.set_tracks(1.0, 1, max_records=0)
+    ctx.step(2)
+    assert len(ctx.tracks()) == 0 and ctx.scalars()["tracks_dropped"] == 0
+    # particles placed, every one sampled, none kept: all counted as dropped
+    st = W.random_state(cfg, 500, seed=9, e_scale=1e7, u_scale=0.01)
+    ctx.set_state(ctx.scalars()["step"], st["E"], st["b"], _records(P, st, 1))
+    ctx.set_tracks(1.0, 1, max_records=0)
+    ctx.step(1)
+    n_live = int(ctx.scalars()["n_e"] + ctx.scalars()["n_pos"])
+    assert len(ctx.tracks()) == 0 and ctx.scalars()["tracks_dropped"] == n_live > 0
+    # the largest edge count, against the oracle, from the placed state
+    sim = _oracle_with(cfg, st)
+    ctx2 = P.Context(cfg)
+    ctx2.set_state(0, st["E"], st["b"], _records(P, st, 1))
+    assert np.array_equal(ctx2.spectrum(edges).astype(np.int64), sim.energy_spectrum(edges))
+    ctx.close()
+    ctx2.close()
