@@ -296,6 +296,23 @@ pic_status pic_autotune_steps(pic_ctx* c, int32_t reps);
  * Switching resets the accumulators. */
 pic_status pic_set_timing(pic_ctx* c, int32_t on);
 
+/* Checkpoint and resume.  pic_snapshot writes the whole simulation state:
+ * fields, currents, the amplitude window, the charged particles (with their
+ * ids), the neutrals' alive bits and death steps, the device counters and the
+ * step index, after an 80-byte header.  host_out = NULL: size query (written =
+ * bytes needed).  Synchronous.  The maximum accumulated intensity and the
+ * trajectory records are diagnostics, not part of it.  pic_restore loads such a
+ * snapshot into a context created from the same configuration (the header
+ * carries a key of the problem and the state layout), so that stepping
+ * continues from it.  The random draws are keyed by (id, step) and carry no
+ * state, so the continuation takes the same decisions; the fields agree with
+ * an uninterrupted run to the rounding of FP32 atomic additions.  A restore
+ * clears a latched error unless the snapshot itself carries one.  Errors:
+ * PIC_E_INVAL (short buffer, another configuration), PIC_E_VERSION (not a
+ * snapshot of this format), PIC_E_DEVICE. */
+pic_status pic_snapshot(pic_ctx* c, void* host_out, size_t out_bytes, size_t* written);
+pic_status pic_restore(pic_ctx* c, const void* host_in, size_t in_bytes);
+
 /* Maximum accumulated intensity (Sec. 5, multilayer mirror: the intensity is
  * recorded at fixed intervals, 0.5 fs in the paper, and each point keeps its
  * largest value over the run).  every > 0: after the field update of each

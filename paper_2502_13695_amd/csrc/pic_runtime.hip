@@ -862,6 +862,89 @@ void pic_destroy(pic_ctx* c) {
   delete c;
 }
 
+// ------------------------------------------------------------ checkpoints
+namespace {
+struct SnapHdr {
+  uint64_t magic;      // "PICSNAP1"
+  uint32_t version, hdr_bytes;
+  uint64_t total;      // bytes of the device state block that follow
+  uint64_t key;        // hash of the layout and the canonical problem
+  int64_t step;
+  int32_t tile, nb_cell, far_skip, resort;
+  int32_t xext[6];
+};
+constexpr uint64_t kSnapMagic = 0x31504e5350434950ull;   // "PICSNAP1"
+
+// FNV-1a over the quantities that fix the state block's layout and meaning
+uint64_t snap_key(const pic_ctx* c) {
+  const Layout& L = c->L;
+  const Canon& K = c->canon;
+  const double v[] = {(double)L.total, (double)L.ncell, (double)L.nneut, (double)L.capacity,
+                      (double)L.Px, (double)L.Py, (double)L.Pz, (double)L.nmcell, (double)L.o_inst,
+                      K.dt, K.dx[0], K.dx[1], K.dx[2], (double)K.ppc, (double)K.nmat,
+                      (double)c->cfg.seed, (double)c->cfg.shape_order};
+  uint64_t h = 1469598103934665603ull;
+  const unsigned char* p = reinterpret_cast<const unsigned char*>(v);
+  for (size_t i = 0; i < sizeof v; ++i) h = (h ^ p[i]) * 1099511628211ull;
+  return h;
+}
+}  // namespace
+
+pic_status pic_snapshot(pic_ctx* c, void* host_out, size_t out_bytes, size_t* written) {
+  if (!c) return PIC_E_INVAL;
+  const Layout& L = c->L;
+  const size_t need = sizeof(SnapHdr) + (size_t)L.total;
+  if (written) *written = need;
+  if (!host_out) return PIC_OK;
+  if (out_bytes < need) return PIC_E_INVAL;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return PIC_E_DEVICE;
+  SnapHdr h{};
+  h.magic = kSnapMagic;
+  h.version = 1;
+  h.hdr_bytes = sizeof(SnapHdr);
+  h.total = (uint64_t)L.total;
+  h.key = snap_key(c);
+  h.step = c->step;
+  h.tile = c->tile;
+  h.nb_cell = c->nb_cell;
+  h.far_skip = c->far_skip;
+  h.resort = c->resort;
+  for (int q = 0; q < 6; ++q) h.xext[q] = c->h_xext[q];
+  std::memcpy(host_out, &h, sizeof h);
+  HIP_OK(hipMemcpy((unsigned char*)host_out + sizeof h, c->base, (size_t)L.total, hipMemcpyDeviceToHost));
+  return PIC_OK;
+}
+
+pic_status pic_restore(pic_ctx* c, const void* host_in, size_t in_bytes) {
+  if (!c || !host_in || in_bytes < sizeof(SnapHdr)) return PIC_E_INVAL;
+  SnapHdr h;
+  std::memcpy(&h, host_in, sizeof h);
+  if (h.magic != kSnapMagic || h.version != 1 || h.hdr_bytes != sizeof(SnapHdr)) return PIC_E_VERSION;
+  const Layout& L = c->L;
+  if (h.total != (uint64_t)L.total || h.key != snap_key(c) || in_bytes < sizeof h + (size_t)L.total ||
+      h.tile < 0 || h.tile >= field_tile_variants())
+    return PIC_E_INVAL;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return PIC_E_DEVICE;
+  harvest_all(c);
+  // every byte of the state block except this context's own parameter block,
+  // which holds its device addresses
+  const unsigned char* src = (const unsigned char*)host_in + sizeof h;
+  const size_t i0 = L.o_inst, i1 = L.o_inst + sizeof(Inst);
+  HIP_OK(hipMemcpy(c->base, src, i0, hipMemcpyHostToDevice));
+  if ((size_t)L.total > i1) HIP_OK(hipMemcpy(c->base + i1, src + i1, (size_t)L.total - i1, hipMemcpyHostToDevice));
+  c->step = h.step;
+  c->tile = h.tile;
+  c->nb_cell = h.nb_cell;
+  c->d_off_fields = c->d_off + 8 + 2 * c->tile;
+  c->tune_left = 0;
+  c->far_skip = h.far_skip;
+  c->resort = h.resort;
+  for (int q = 0; q < 6; ++q) c->h_xext[q] = h.xext[q];
+  c->latched = PIC_OK;
+  check_health(c);
+  return PIC_OK;
+}
+
 pic_status pic_set_imax(pic_ctx* c, int32_t every) {
   if (!c || every < 0) return PIC_E_INVAL;
   if (c->latched != PIC_OK) return PIC_E_STATE;

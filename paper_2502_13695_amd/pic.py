@@ -97,7 +97,8 @@ SYMBOLS = ["pic_init", "pic_step", "pic_diag", "pic_set_state", "pic_footprint",
            "pic_batch_step", "pic_batch_add", "pic_batch_remove", "pic_batch_destroy", "pic_batch_set_graph",
            "pic_batch_graph_replays",
            "pic_set_timing", "pic_autotune", "pic_autotune_steps", "pic_set_resort", "pic_set_far_tiles",
-           "pic_set_imax", "pic_spectrum_counts", "pic_set_tracks", "pic_destroy", "pic_status_str"]
+           "pic_set_imax", "pic_spectrum_counts", "pic_set_tracks", "pic_snapshot", "pic_restore",
+           "pic_destroy", "pic_status_str"]
 
 
 class Spectrum(C.Structure):
@@ -144,6 +145,8 @@ def lib():
             "pic_set_far_tiles": ([vp, i32], C.c_int),
             "pic_set_imax": ([vp, i32], C.c_int),
             "pic_set_tracks": ([vp, C.c_uint32, i32, i64], C.c_int),
+            "pic_snapshot": ([vp, vp, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
+            "pic_restore": ([vp, vp, C.c_size_t], C.c_int),
             "pic_spectrum_counts": ([vp, C.POINTER(Spectrum), C.POINTER(C.c_uint64), C.c_size_t], C.c_int),
             "pic_batch_set_graph": ([vp, i32], C.c_int),
             "pic_batch_graph_replays": ([vp], C.c_int64),
@@ -358,6 +361,19 @@ class Context:
     def imax(self):
         """Maximum accumulated intensity: the largest node |E|^2 [V^2/m^2]."""
         return self._node_grid(DIAG_IMAX, np.float32)
+
+    def snapshot(self):
+        """The whole simulation state as bytes (pic_snapshot)."""
+        w = C.c_size_t()
+        _check(lib().pic_snapshot(self.h, None, 0, C.byref(w)), "pic_snapshot(size)")
+        buf = np.empty(w.value, dtype=np.uint8)
+        _check(lib().pic_snapshot(self.h, buf.ctypes.data_as(C.c_void_p), buf.nbytes, C.byref(w)), "pic_snapshot")
+        return buf
+
+    def restore(self, snap):
+        """Load a snapshot of a context with the same configuration."""
+        b = np.ascontiguousarray(snap, dtype=np.uint8)
+        _check(lib().pic_restore(self.h, b.ctypes.data_as(C.c_void_p), b.nbytes), "pic_restore")
 
     def set_tracks(self, fraction, every, max_records=1 << 20):
         """Record the position of a sampled `fraction` of the particles (by
