@@ -206,6 +206,7 @@ struct Inst {
   uint64_t seed;
   // control
   int* step;                    // device step counter
+  int step_now;                 // batches: the step index, kept by k_advance beside the counter
   unsigned* health;
 };
 

@@ -46,7 +46,7 @@ void launch_push(const Group& g, int D, int order, hipStream_t s, Stamp st = {})
 void launch_sort(const Group& gp, const Group& gscan, int D, hipStream_t s, Stamp st = {});
 void launch_fields(const Group& g, int D, int variant, hipStream_t s, Stamp st = {});
 void launch_ionize(const Group& g, int D, int order, hipStream_t s, Stamp st = {});
-void launch_advance(const Inst* insts, int n, hipStream_t s);   // batch: step counters + 1
+void launch_advance(Inst* insts, int n, hipStream_t s);   // batch: step counters + 1
 int field_tiles(int D, int variant, int Px, int Py, int Pz);   // blocks of the field launch
 int field_tile_variants();
 int field_tile_x(int D, int variant);                          // owned x extent of a field tile

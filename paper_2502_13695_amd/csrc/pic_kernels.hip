@@ -607,7 +607,7 @@ __global__ __launch_bounds__(push_tpb(D)) void k_push(Group g, std::conditional_
   const int b0 = sl.bk;
   int count = *I.pcount;
   count = count < I.capacity ? count : I.capacity;
-  const int step = ONE || g.step >= 0 ? g.step : *I.step;
+  const int step = ONE || g.step >= 0 ? g.step : I.step_now;
   const int par = step & 1;
   int xlo = 1 << 30, xhi = -(1 << 30);   // x cells of this block's particles after the move
   const PushFields f{uniform(I.F[par][0]), uniform(I.F[par][1]), uniform(I.F[par][2]),
@@ -1139,7 +1139,7 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g, std::conditional_t<ONE,
   const Slot sl = ONE ? Slot{0, (int)blockIdx.x, g.blocks} : block_slot(g);
   auto& I = inst_of(g, sl.ii, one);
   // step parity in a scalar register, so the field pointers load as scalars
-  const int step = ONE || g.step >= 0 ? g.step : __builtin_amdgcn_readfirstlane(*gp(I.step));
+  const int step = ONE || g.step >= 0 ? g.step : I.step_now;
   const int par = step & 1;
   // the field front (the last x column of a tile that has stored a nonzero E
   // or b) and the charged x range, first used after the axis tables.  Relaxed
@@ -1564,7 +1564,7 @@ __global__ __launch_bounds__(TPB) void k_ionize(Group g, std::conditional_t<ONE,
   __shared__ signed char smat[TPB + 2];
   const Slot sl = ONE ? Slot{0, (int)blockIdx.x, g.blocks} : block_slot(g);
   auto& I = inst_of(g, sl.ii, one);
-  const int step = ONE || g.step >= 0 ? g.step : *I.step;
+  const int step = ONE || g.step >= 0 ? g.step : I.step_now;
   // the flag of the next step is raised by its field update, which runs after
   // this kernel; a cold grid (no amplitude at any cut) ionizes nothing
   if (sl.bk == 0 && threadIdx.x == 0) I.hot[(step + 1) & 1] = 0;
@@ -1655,9 +1655,13 @@ __global__ __launch_bounds__(TPB) void k_ionize(Group g, std::conditional_t<ONE,
   }
 }
 
-__global__ void k_advance(const Inst* insts, int n) {
+__global__ void k_advance(Inst* insts, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) *insts[i].step += 1;
+  if (i < n) {
+    const int s = *insts[i].step + 1;
+    *insts[i].step = s;
+    insts[i].step_now = s;
+  }
 }
 
 // The cell and its material come from the block's per-cell pass; the alive
@@ -2077,7 +2081,7 @@ void launch_ionize(const Group& g, int D, int order, hipStream_t s, Stamp st) {
     DISPATCH_D(D, ONE_OR_GROUP(k_ionize, TPB, DD, 2));
   }
 }
-void launch_advance(const Inst* insts, int n, hipStream_t s) {
+void launch_advance(Inst* insts, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_advance, dim3((n + 63) / 64), dim3(64), 0, s, insts, n);
 }
 void launch_init_neutrals_d(const Inst* d, int64_t nneut, int D, hipStream_t s) {

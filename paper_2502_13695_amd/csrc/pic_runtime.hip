@@ -262,6 +262,7 @@ struct pic_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int64_t replays = 0;
+  std::vector<int64_t> expect;   // each member's step index as the batch's blocks hold it
 };
 
 namespace {
@@ -1558,6 +1559,7 @@ static pic_status batch_rebuild(pic_batch* b) {
     std::vector<int> off(4 * (cl.n + 1), 0);
     for (int i = 0; i < cl.n; ++i) {
       hi[i] = cl.ms[i]->h;
+      hi[i].step_now = (int)cl.ms[i]->step;
       const int nb[4] = {std::min(cl.ms[i]->nb_push, push_share), cl.ms[i]->nb_cell, cl.ms[i]->nb_win,
                          cl.ms[i]->nb_neut};
       for (int ph = 0; ph < 4; ++ph) off[ph * (cl.n + 1) + i + 1] = off[ph * (cl.n + 1) + i] + nb[ph];
@@ -1577,6 +1579,8 @@ static pic_status batch_rebuild(pic_batch* b) {
     HIP_OK(hipMemcpy(cl.d_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(cl.d_map, map.data(), sizeof(unsigned short) * map.size(), hipMemcpyHostToDevice));
   }
+  b->expect.clear();
+  for (pic_ctx* c : b->members) b->expect.push_back(c->step);
   b->dirty = false;
   return PIC_OK;
 }
@@ -1623,6 +1627,10 @@ pic_status pic_batch_step(pic_batch* b, int64_t nsteps) {
   if (!b || nsteps < 0) return PIC_E_INVAL;
   for (pic_ctx* c : b->members)
     if (c->latched != PIC_OK || c->imax_every > 0 || c->track_every > 0) return PIC_E_STATE;
+  // a member stepped, restored or given a state outside the batch: its step
+  // index in the batch's parameter blocks is stale
+  for (size_t i = 0; !b->dirty && i < b->members.size(); ++i)
+    if (i >= b->expect.size() || b->members[i]->step != b->expect[i]) b->dirty = true;
   if (b->dirty) {
     pic_status st = batch_rebuild(b);
     if (st != PIC_OK) return st;
@@ -1649,6 +1657,7 @@ pic_status pic_batch_step(pic_batch* b, int64_t nsteps) {
   }
   batch_enqueue(b, left, s);
   for (pic_ctx* c : b->members) c->step += nsteps;
+  for (auto& e : b->expect) e += nsteps;
   if (hipGetLastError() != hipSuccess) return PIC_E_DEVICE;
   return PIC_OK;
 }

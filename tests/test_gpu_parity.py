@@ -432,6 +432,35 @@ def test_batch_matches_single_runs(P):
         x.close()
 
 
+def test_batch_member_stepped_alone_between_batch_steps(P):
+    """A member stepped on its own, and another given a new state, between
+    batch steps: the batch resumes each from its own step index (the batch's
+    copy of it is refreshed), matching the same runs stepped alone."""
+    cfgs = [W.config_2d(nx=128, ny=32, nsteps=200, ppc=2, peak=3e14, slab_cells=10, waist=0.6e-6, seed=s)
+            for s in (7, 8)]
+    ref = []
+    for c, n in zip(cfgs, (180, 160)):
+        x = P.Context(c)
+        x.step(n)
+        ref.append((x.fields(), set(map(tuple, x.events().tolist()))))
+        x.close()
+    a, bb = P.Context(cfgs[0]), P.Context(cfgs[1])
+    batch = P.Batch([a, bb])
+    batch.step(80)          # both at 80 (eager steps and graph replays)
+    a.step(20)              # a alone: 100
+    batch.step(80)          # a 180, b 160
+    for x, (f_s, ev_s) in zip((a, bb), ref):
+        f_b = x.fields()
+        num = sum(np.sum((p - q) ** 2) for p, q in zip(f_b[0] + f_b[1], f_s[0] + f_s[1]))
+        den = sum(np.sum(q ** 2) for q in f_s[0] + f_s[1])
+        assert math.sqrt(num / den) < 1e-5
+        assert set(map(tuple, x.events().tolist())) == ev_s
+    assert a.scalars()["step"] == 180 and bb.scalars()["step"] == 160
+    batch.close()
+    a.close()
+    bb.close()
+
+
 def test_batch_graph_replays_match_eager(P):
     """Batch steps replayed as a captured HIP graph (one sort period per
     replay) against the same members stepped eagerly: after every replay
