@@ -144,7 +144,7 @@ typedef struct {
 /* Diagnostic kinds for pic_diag.  Grids are FP64 unless stated, on the
  * positions inside the box, x fastest. */
 enum {
-  PIC_DIAG_SCALARS = 0,   /* double[16], see PIC_SC_* */
+  PIC_DIAG_SCALARS = 0,   /* double[PIC_SC_COUNT], see PIC_SC_* */
   PIC_DIAG_FIELDS = 1,    /* double: Ex, Ey, Ez, bx, by, bz (b = cB) on their own
                              staggered positions; per component the shape is
                              n_d (half-integer or periodic axis) or n_d + 1 */
@@ -185,7 +185,9 @@ enum {
   PIC_SC_STEP = 0, PIC_SC_TIME = 1, PIC_SC_N_NEUTRAL = 2, PIC_SC_N_E = 3, PIC_SC_N_POS = 4,
   PIC_SC_EVENTS = 5, PIC_SC_U_FIELD = 6, PIC_SC_KE_E = 7, PIC_SC_KE_POS = 8,
   PIC_SC_E_GAP = 9, PIC_SC_E_ABS = 10, PIC_SC_GAUSS_MAX = 11, PIC_SC_RHO_MAX = 12,
-  PIC_SC_HEALTH = 13, PIC_SC_SLOTS = 14, PIC_SC_TRACKS_DROPPED = 15, PIC_SC_COUNT = 16
+  PIC_SC_HEALTH = 13, PIC_SC_SLOTS = 14, PIC_SC_TRACKS_DROPPED = 15,
+  PIC_SC_GAUSS_L2 = 16,   /* root mean square of the Gauss-law residual over the interior nodes [V/m^2] */
+  PIC_SC_COUNT = 17
 };
 
 /* A charged macroparticle: cell indices, FP32 offsets in [0, 1) (position =

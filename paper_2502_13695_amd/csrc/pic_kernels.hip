@@ -1985,7 +1985,7 @@ __global__ __launch_bounds__(TPB) void k_diag_gauss(const Inst* d, const double*
   const float* E0 = I.F[par][0];
   const float* E1 = I.F[par][1];
   const float* E2 = I.F[par][2];
-  double mres = 0.0, mrho = 0.0;
+  double mres = 0.0, mrho = 0.0, sres = 0.0, nres = 0.0;
   for (int64_t p = (int64_t)blockIdx.x * TPB + threadIdx.x; p < ncell; p += (int64_t)gridDim.x * TPB) {
     int i, j, k;
     decode<D>(I, p, i, j, k);
@@ -2002,11 +2002,19 @@ __global__ __launch_bounds__(TPB) void k_diag_gauss(const Inst* d, const double*
       const int dzm = I.per_z && k == 0 ? (I.nz - 1) * I.sz : -I.sz;
       div += ((double)E2[p] - (double)E2[p + dzm]) / I.ie_node[ai] / I.dx[2];
     }
-    mres = fmax(mres, fabs(div - rho[p]));
+    const double r = div - rho[p];
+    mres = fmax(mres, fabs(r));
     mrho = fmax(mrho, fabs(rho[p]));
+    sres += r * r;
+    nres += 1.0;
   }
   atomicMax(reinterpret_cast<unsigned long long*>(acc), __double_as_longlong(mres));
   atomicMax(reinterpret_cast<unsigned long long*>(acc) + 1, __double_as_longlong(mrho));
+  // sum of squares and count of the interior nodes (root mean square on the host)
+  if (nres > 0.0) {
+    atomicAdd(acc + 2, sres);
+    atomicAdd(acc + 3, nres);
+  }
 }
 
 __global__ void k_table_probe(const TabHdr* tab, const float* A, float* P, int64_t n) {

@@ -1471,6 +1471,7 @@ pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size
   o[PIC_SC_E_ABS] = kee + kep + egap;
   o[PIC_SC_GAUSS_MAX] = h.acc[44];
   o[PIC_SC_RHO_MAX] = h.acc[45];
+  o[PIC_SC_GAUSS_L2] = h.acc[47] > 0 ? std::sqrt(h.acc[46] / h.acc[47]) : 0.0;
   o[PIC_SC_HEALTH] = (double)h.health;
   o[PIC_SC_SLOTS] = (double)h.pcount;
   unsigned long long nrec = 0;

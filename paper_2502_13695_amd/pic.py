@@ -25,7 +25,8 @@ BC = {"outflow": 0, "periodic": 1}
 DIAG_SCALARS, DIAG_FIELDS, DIAG_NE, DIAG_UE, DIAG_EVENTS, DIAG_PARTICLES, DIAG_PARAMS, DIAG_AMP, \
     DIAG_TIMERS, DIAG_SORT, DIAG_REGION, DIAG_IMAX, DIAG_TRACKS = range(13)
 SC = dict(step=0, time=1, n_neutral=2, n_e=3, n_pos=4, events=5, u_field=6, ke_e=7, ke_pos=8,
-          e_gap=9, e_abs=10, gauss_max=11, rho_max=12, health=13, slots=14, tracks_dropped=15)
+          e_gap=9, e_abs=10, gauss_max=11, rho_max=12, health=13, slots=14, tracks_dropped=15,
+          gauss_l2=16)
 
 
 class PicError(RuntimeError):

@@ -272,8 +272,12 @@ def _compare_run(P, ctx, sim, l2_tol=1e-5, rel_tol=5e-3, min_events=1, name=""):
     eabs_o = sim.kinetic_energy() + sim.energy_gap
     if eabs_o > 0:
         assert abs(sc["e_abs"] / eabs_o - 1) < rel_tol, (sc["e_abs"], eabs_o)
-    # the device Gauss residual stays at FP32 roundoff of the charge density
+    # the device Gauss residual stays at FP32 roundoff of the charge density;
+    # its root mean square lies between zero and its maximum
     assert sc["gauss_max"] <= 1e-4 * max(sc["rho_max"], 1.0)
+    assert 0.0 <= sc["gauss_l2"] <= sc["gauss_max"] * (1 + 1e-12)
+    if sc["gauss_max"] > 0:
+        assert sc["gauss_l2"] > 0
     return l2, sc
 
 
