@@ -237,12 +237,13 @@ def _field_l2(ctx, sim):
 
 
 def _record(name, **kv):
-    """Append measured parity figures to gpurun_out/parity_metrics.jsonl (if present)."""
+    """Append measured parity figures (one JSON line) to the file named by the
+    PIC_PARITY_LOG environment variable, when it is set."""
     import json
     import os
-    d = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
-    if os.path.isdir(d):
-        with open(os.path.join(d, "parity_metrics.jsonl"), "a") as f:
+    path = os.environ.get("PIC_PARITY_LOG")
+    if path:
+        with open(path, "a") as f:
             f.write(json.dumps(dict(test=name, **kv)) + "\n")
 
 
