@@ -415,8 +415,8 @@ def main():
                     help="copy 256 MiB once before the run (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}); multi-GPU runs are not "
-              f"part of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the library has no "
+              f"multi-GPU path", file=sys.stderr)
         sys.exit(2)
     import workloads as W
     if args.workload == "scan":
