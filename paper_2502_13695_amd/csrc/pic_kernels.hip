@@ -1193,6 +1193,24 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g, std::conditional_t<ONE,
   const int a0y = D >= 2 ? (rest % nty) * T::Y : 0;
   const int a0z = D >= 3 ? (rest / nty) * T::Z : 0;
   const int i0 = a0x - G, j0 = a0y - Gy, k0 = a0z - Gz;   // logical tile origin
+  // far tiles: x columns farther than XNEAR_MARGIN cells from every cell that
+  // held a charged particle so far and from the amplitude window have carried
+  // no current, ever, so their update neither reads nor clears it
+  bool cur = true;
+  if (g.part >= 1) {
+    int lo = xlo, hi = xhi;
+    if (I.wx1 > I.wx0) {
+      lo = min(lo, I.wx0 - G);
+      hi = max(hi, I.wx1 - 1 - G);
+    }
+    const int alo = lo - XNEAR_MARGIN + G, ahi = hi + XNEAR_MARGIN + G;
+    cur = lo <= hi && tx * T::X <= ahi && tx * T::X + T::X - 1 >= alo;
+  }
+  // a far tile whose staged x range lies beyond the front has zero inputs
+  // (the update moves the front by at most two cells per step): its outputs
+  // are zero and already stored, as it was skipped or wrote zeros at every
+  // earlier step, so it is not updated (decided before the axis tables)
+  if (g.part == 1 && !cur && a0x - H > front) return;
   if (threadIdx.x == 0) blk_hot = 0;
   // ---- per-axis tables; an interior tile (every staged position valid for
   // both updates and on no face, every owned position inside the box) runs
@@ -1234,24 +1252,6 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g, std::conditional_t<ONE,
       soz[q] = 0;
     }
   }
-  // far tiles: x columns farther than XNEAR_MARGIN cells from every cell that
-  // held a charged particle so far and from the amplitude window have carried
-  // no current, ever, so their update neither reads nor clears it
-  bool cur = true;
-  if (g.part >= 1) {
-    int lo = xlo, hi = xhi;
-    if (I.wx1 > I.wx0) {
-      lo = min(lo, I.wx0 - G);
-      hi = max(hi, I.wx1 - 1 - G);
-    }
-    const int alo = lo - XNEAR_MARGIN + G, ahi = hi + XNEAR_MARGIN + G;
-    cur = lo <= hi && tx * T::X <= ahi && tx * T::X + T::X - 1 >= alo;
-  }
-  // a far tile whose staged x range lies beyond the front has zero inputs
-  // (the update moves the front by at most two cells per step): its outputs
-  // are zero and already stored, as it was skipped or wrote zeros at every
-  // earlier step, so it is not updated
-  if (g.part == 1 && !cur && a0x - H > front) return;
   const bool inner = __syncthreads_and(ok);
   // ---- A: stage E^n and b^n; the current of the points this thread updates
   // in phase C is loaded now too (registers), so HBM latency is met once
