@@ -1,24 +1,47 @@
 """Benchmark of the laser-dielectric PIC hot path on one MI355X.
 
-Workload (default): the 2D3V slab run -- 2048 x 512 cells at lambda/32, a 2 um
-silica-like slab (n = 1.45, 9 eV) across y with 16 neutral macroparticles per
-cell, a 3-cycle 800 nm pulse with a 3 um waist at 5e13 W/cm^2, seed 1.  One
-step is one pass of the whole hot path (gather, Boris push, Esirkepov deposit,
-Yee update with the dielectric, amplitude window, Keldysh ionization and
-births).  The timed region is K steps from t = 0 of a fresh run, inputs
-resident in HBM; W warmup steps run first on a separate instance.
+Workload (default, ``--workload mirror3d``): the 3D3V one-GPU share of the
+multi-layer mirror -- 256 x 128 x 128 cells at lambda/24, eight alternating
+quarter-wave layers (n = 1.45 with a 9 eV gap, n = 2.1 with a 4 eV gap) from
+x = 64 cells, 8 neutral macroparticles per material cell (3.67e6), a 2-cycle
+800 nm plane-wave pulse of 1 J/cm^2, periodic transverse boundaries, seed 2.
 
-Metric: particle-steps/s = sum over steps of (charged + alive neutral
-macroparticles) / wall time.  Prints one JSON line.  Extra objects:
-  roofline     -- the dominant kernel's algorithmic HBM bytes per launch over
-                  its mean launch time (HIP events on the kernel's stream)
-  cpu_baseline -- the FP64 oracle on a bounded sample of the same workload
+One step is one pass of the whole hot path: gather, Boris push, Esirkepov
+deposit, Yee update with the dielectric, outflow faces and laser injection,
+amplitude window, Keldysh ionization and births, and the tile sort when due.
+
+Timed window: K = --steps steps starting at the interaction step S, the step
+at which the pulse peak reaches the front of the first layer
+(t_peak + x_front / c; reported as config.start_step, --start overrides).
+Untimed before it: context set-up, the in-run timing of the field tile shapes
+over the first 28 steps, the advance to step S - W and then W = --warmup more
+steps.  Inputs are resident in HBM; the timed region is the K steps bracketed
+by device synchronisations.
+
+Metric: particle-steps/s = sum over the K steps of (charged + alive neutral
+macroparticles at the start of the step) / wall time of the K steps.
+
+Extra objects in the JSON line:
+  roofline     -- the kernel with the most device time in the window: its
+                  algorithmic bytes per launch (the per-unit bytes below times
+                  the units one launch processes) over its mean launch time,
+                  from HIP events stamped by the dispatches of every step of
+                  the window on the context's stream
+  cpu_baseline -- the FP64 oracle pinned to one host core, on the same window
+                  of the workload's transverse share (see cpu_baseline)
+
+Per-unit algorithmic bytes (FP32 SoA layout): a charged particle-step 60
+(32 read, 28 written); an alive neutral-step 16, plus 64 per ionization event
+(two births); a grid cell-step 73 (E, B, J and the material read; E, B
+written; J cleared), 49 where no current can exist; plus 24 per amplitude-
+window node-step; a sorted charged particle 120 (read and written once).
 """
 
 import argparse
+import ctypes
 import json
-import math
 import os
+import subprocess
 import sys
 import time
 
@@ -26,17 +49,51 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+METRIC = "particle-steps/sec (gather+push+deposit+ionize) at 1 GPU"
 HBM_PEAK_GBS = 8000.0
-
-TIMING_PERIOD = 16
+FP32_PEAK_TFLOPS = 157.3
+C_LIGHT = 299792458.0
 
 # phases of the step (index into the library's timers)
 PHASES = {0: "push", 1: "fields", 2: "ionize", 3: "sort"}
+# algorithmic bytes per unit of work
+B_CHARGED, B_NEUTRAL, B_EVENT = 60.0, 16.0, 64.0
+B_CELL, B_CELL_NO_J, B_WINDOW, B_SORTED = 73.0, 49.0, 24.0, 120.0
+# algorithmic flops per charged particle-step of the 3D order-2 push: gather
+# 160, Boris 60, Esirkepov deposit 770
+FLOP_PUSH_3D2 = 990.0
+# steps of the in-run timing of the field tile shapes (7 shapes x 4 launches)
+TUNE_REPS = 4
+TUNE_STEPS = 7 * TUNE_REPS
+
+
+class Roctx:
+    """roctxProfilerResume / Pause around the timed region, so that a profiler
+    run with --selected-regions (which starts paused; a pause before the first
+    resume is an error there) sees exactly the window's dispatches.  No-ops
+    without a profiler; absent library: nothing happens."""
+
+    def __init__(self):
+        self.lib = None
+        for name in ("librocprofiler-sdk-roctx.so.1", "librocprofiler-sdk-roctx.so",
+                     "/opt/rocm/lib/librocprofiler-sdk-roctx.so"):
+            try:
+                self.lib = ctypes.CDLL(name)
+                break
+            except OSError:
+                continue
+
+    def resume(self):
+        if self.lib is not None:
+            self.lib.roctxProfilerResume(ctypes.c_uint64(0))
+
+    def pause(self):
+        if self.lib is not None:
+            self.lib.roctxProfilerPause(ctypes.c_uint64(0))
 
 
 def window_nodes(cfg):
     """Nodes of the amplitude window: material x-range +-1 node, whole transverse."""
-    import numpy as np
     D = cfg["ndim"]
     dx = cfg["dx"][0]
     nx = cfg["n"][0]
@@ -49,34 +106,24 @@ def window_nodes(cfg):
     t = 1
     for d in range(1, D):
         t *= cfg["n"][d] + (0 if per else 1)
-    return int(np.int64(wx) * t)
+    return int(wx * t)
 
 
-def phase_bytes(cfg, phase, n_charged_avg, n_alive_avg, far_frac=0.0, far_updated=None):
-    """Algorithmic HBM bytes of one launch of a phase (FP32 SoA layout).
-    far_frac: share of the field tiles that skip the current (no charged
-    particle has come within their margin); far_updated: share of the field
-    tiles that skip the current and are updated (the rest lie beyond the
-    field front and move nothing), default all of them."""
-    D = cfg["ndim"]
+def domain_cells(cfg):
+    """Grid cells of the field update (nodes along outflow axes, cells along periodic ones)."""
     per = cfg.get("transverse_bc", "outflow") == "periodic"
     cells = 1
-    for d in range(D):
+    for d in range(cfg["ndim"]):
         cells *= cfg["n"][d] + (0 if (per and d > 0) else 1)
-    if phase == 1:
-        # Yee step: read E, b, J (36 B), write E, b (24 B), clear J (12 B);
-        # far tiles: no current to read or clear (48 B);
-        # window node: ring write, prefix read+write, suffix read, A write (20 B)
-        # plus the once-per-cycle suffix rebuild (8 B amortised)
-        fu = far_frac if far_updated is None else far_updated
-        return (72.0 * (1.0 - far_frac) + 48.0 * fu) * cells + 28.0 * window_nodes(cfg)
-    if phase == 0:           # charged particle: read cell, offsets, u, kind; write back
-        rd = 4 + 4 * D + 12 + 1
-        wr = 4 + 4 * D + 12
-        return float(rd + wr) * n_charged_avg
-    if phase == 2:           # alive neutral: offsets (+ alive bit)
-        return (4.0 * D + 0.125) * n_alive_avg
-    return 0.0
+    return cells
+
+
+def interaction_start(cfg, params):
+    """Step at which the pulse peak reaches the front of the first layer."""
+    if not cfg["layers"]:
+        return 0
+    x0 = min(lo for (_, lo, _) in cfg["layers"])
+    return int(round((params.t_peak + x0 / C_LIGHT) / params.dt))
 
 
 def measured_traffic(workload, kernel):
@@ -119,80 +166,311 @@ def stream_copy_gbs(mib=1024, reps=5):
     return 2.0 * n * 4 / (ms * 1e-3) / 1e9
 
 
-def run_gpu(cfg, steps, warmup, field_tile=None):
+def window_counts(sc0, sc1, ev, start, steps):
+    """Charged and alive-neutral particle-steps of steps start .. start+steps-1.
+    A step counts the particles present when it starts; an event recorded with
+    step index s (the ionization of step s - 1) adds two carriers from step s
+    on.  Carriers that left the box during the window (rare: the layers are far
+    from the outflow faces) are taken off at half the window."""
+    import numpy as np
+    charged0 = sc0["n_e"] + sc0["n_pos"]
+    alive0 = sc0["n_neutral"]
+    st = np.asarray(ev[:, 1], dtype=np.int64) if len(ev) else np.zeros(0, dtype=np.int64)
+    win = st[(st > start) & (st <= start + steps)]
+    later = float(np.sum(start + steps - win))      # steps each birth pair is present
+    births = len(win)
+    removed = max(0.0, charged0 + 2 * births - (sc1["n_e"] + sc1["n_pos"]))
+    charged_steps = steps * charged0 + 2.0 * later - removed * steps / 2.0
+    neutral_steps = steps * alive0 - later
+    return dict(charged_steps=charged_steps, neutral_steps=neutral_steps, events=births,
+                removed=removed, charged_start=charged0, alive_start=alive0,
+                charged_end=sc1["n_e"] + sc1["n_pos"], alive_end=sc1["n_neutral"])
+
+
+def run_window(cfg, start, steps, warmup, field_tile, roctx, resort=None):
+    """The benchmark run: one context, untimed advance to the window, K timed
+    steps with every dispatch stamped."""
     import torch
     from paper_2502_13695_amd import pic
     torch.cuda.set_device(0)
-    if warmup > 0:
-        w = pic.Context(cfg)
-        w.step(warmup)
-        w.scalars()
-        w.close()
     ctx = pic.Context(cfg)
-    region0 = ctx.region()
-    # field tile shape: timed on the first steps of the timed run itself (every
-    # shape computes identical fields); the choice is reported after the run
+    if resort is not None:
+        ctx.set_resort(resort)
+    pre = start - warmup
     if field_tile is None:
-        ctx.autotune_steps(4)
-    # HIP events stamped by the dispatches of one step in every 16 of the timed
-    # region (the sampled position cycles through the window, so the tile sort
-    # check, due every 8 steps, is sampled in proportion)
-    ctx.set_timing(TIMING_PERIOD)
+        # field tile shapes timed in-run on the first steps (identical results)
+        if pre < TUNE_STEPS:
+            raise SystemExit(f"the window starts at step {start}: at least {TUNE_STEPS + warmup} "
+                             f"steps are needed before it for the tile timing and the warmup")
+        ctx.autotune_steps(TUNE_REPS)
+    ctx.step(max(0, pre))
+    ctx.step(start - max(0, pre))          # W warmup steps
     torch.cuda.synchronize()
+    sc0 = ctx.scalars()
+    reg0 = ctx.region()
+    sort0 = ctx.sort_state()
+    ctx.set_timing(1)                      # every dispatch of the window stamped
+    torch.cuda.synchronize()
+    roctx.resume()
     t0 = time.perf_counter()
     ctx.step(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    roctx.pause()
     timers = ctx.timers()
-    tune = dict(chosen=int(timers[23]), blocks=int(timers[24]), ms=[float(x) for x in timers[16:23]])
-    sort_state = ctx.sort_state()
-    region = ctx.region()
-    sc = ctx.scalars()
+    sc1 = ctx.scalars()
+    reg1 = ctx.region()
+    sort1 = ctx.sort_state()
     ev = ctx.events()
-    nneut = ctx.params().n_neutral
+    tune = dict(chosen=int(timers[23]), blocks=int(timers[24]), ms=[float(x) for x in timers[16:23]])
     ctx.close()
-    # particle-steps: each neutral counts until its ionization step, each birth
-    # pair from its step to the end (carriers leaving the box are not subtracted)
-    if len(ev):
-        import numpy as np
-        death = np.asarray(ev[:, 1], dtype=np.int64)
-        dead_steps = float(np.minimum(death, steps).sum())
-        births = float(2 * np.maximum(0, steps - death).sum())
-        neutral_steps = dead_steps + (nneut - len(death)) * steps
-    else:
-        births = 0.0
-        neutral_steps = float(nneut) * steps
-    ps = neutral_steps + births
-    wall = t1 - t0
-    return dict(wall=wall, particle_steps=ps, neutral_steps=neutral_steps, charged_steps=births,
-                timers=timers, scalars=sc, nneut=nneut, tune=tune, sort_state=sort_state, region=region,
-                region0=region0)
+    assert sc1["health"] == 0, f"health word {sc1['health']}"
+    return dict(wall=t1 - t0, timers=timers, sc0=sc0, sc1=sc1, reg0=reg0, reg1=reg1, sort0=sort0,
+                sort1=sort1, ev=ev, tune=tune)
 
 
-def cpu_baseline(cfg, budget_s=20.0):
-    """The FP64 oracle (as it stands) on the first steps of the same run."""
+def phase_bytes(cfg, r, cnt, steps):
+    """Algorithmic bytes per launch of each phase over the window."""
+    timers = r["timers"]
+    out = {}
+    n_launch = {ph: max(1.0, timers[8 + ph]) for ph in PHASES}
+    out[0] = B_CHARGED * cnt["charged_steps"] / n_launch[0]
+    out[2] = (B_NEUTRAL * cnt["neutral_steps"] + B_EVENT * cnt["events"]) / n_launch[2]
+    # field update: tiles updated per launch (device counter), near tiles with
+    # current, the rest without; tiles beyond the field front move nothing
+    reg0, reg1 = r["reg0"], r["reg1"]
+    ntiles = max(1, reg1["near_tiles"] + reg1["far_tiles"])
+    upd = (reg1["tiles_updated"] - reg0["tiles_updated"]) / max(1.0, timers[9])
+    near = min(upd, 0.5 * (reg0["near_tiles"] + reg1["near_tiles"]))
+    far_upd = max(0.0, upd - near)
+    cells = domain_cells(cfg)
+    out[1] = cells * (B_CELL * near + B_CELL_NO_J * far_upd) / ntiles + B_WINDOW * window_nodes(cfg)
+    # tile sort: every slot read and written once per sort performed
+    nsort = r["sort1"]["sorts"] - r["sort0"]["sorts"]
+    slots = 0.5 * (cnt["charged_start"] + cnt["charged_end"])
+    out[3] = B_SORTED * slots * nsort / n_launch[3]
+    return out, dict(tiles=ntiles, updated_per_launch=upd, near=near, far_updated=far_upd,
+                     sorts=nsort)
+
+
+def _oracle_child(spec):
+    """The oracle on the window, in this (pinned, single-threaded) process."""
+    os.sched_setaffinity(0, {int(spec["cpu"])})
     from oracle import pic as OP
+    cfg = spec["cfg"]
     t0 = time.perf_counter()
     sim = OP.Sim(cfg)
     t_init = time.perf_counter() - t0
-    n = 0
-    ps = 0.0
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:
+    while sim.step_index < spec["start"]:
+        sim.step()
+    t_ff = time.perf_counter() - t0
+    n, ps = 0, 0.0
+    charged = 0.0
+    t0 = time.perf_counter()
+    K = spec["steps"]
+    while True:
+        el = time.perf_counter() - t0
+        if not ((n < K and el < 3 * spec["budget"]) or (el < spec["budget"] and n < 10 * K)):
+            break
+        c = float(len(sim.px))
+        ps += c + float(sim.nalive.sum())
+        charged += c
         sim.step()
         n += 1
-        ps += float(len(sim.px) + int(sim.nalive.sum()))
     dt = time.perf_counter() - t0
-    cores = 1
-    try:
-        import numpy as np  # noqa: F401
-        cores = len(os.sched_getaffinity(0))
-    except Exception:
-        pass
-    return dict(value=ps / dt, unit="particle-steps/s", cores=cores, kind="oracle",
-                sample=f"first {n} steps of the same run from t=0 (init {t_init:.1f} s excluded), "
-                       f"FP64 NumPy, in-situ Keldysh rate; numpy may use multiple BLAS threads "
-                       f"but the hot loops are single-threaded")
+    print(json.dumps(dict(steps=n, seconds=dt, particle_steps=ps, charged_steps=charged,
+                          init_s=t_init, advance_s=t_ff, cpus=sorted(os.sched_getaffinity(0)))), flush=True)
+
+
+def cpu_baseline(cfg, start, steps, budget_s, share_note):
+    """The FP64 oracle (as it stands, untuned) on the same window, pinned to one
+    host core with single-threaded numpy: a child process advances to `start`
+    (untimed), then times the window's steps (and more while the time budget
+    lasts, up to 10x the window)."""
+    cpus = sorted(os.sched_getaffinity(0))
+    spec = dict(cfg=cfg, start=start, budget=budget_s, steps=steps, cpu=cpus[-1])
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
+               NUMEXPR_NUM_THREADS="1")
+    p = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-child", json.dumps(spec)],
+                       env=env, capture_output=True, text=True, timeout=1800)
+    if p.returncode != 0:
+        raise RuntimeError(f"oracle child failed: {p.stderr[-2000:]}")
+    res = json.loads(p.stdout.strip().splitlines()[-1])
+    return dict(value=res["particle_steps"] / res["seconds"], unit="particle-steps/s", cores=1,
+                kind="oracle",
+                sample=f"steps {start}..{start + res['steps'] - 1} ({res['steps']} steps, "
+                       f"{res['seconds']:.1f} s, {res['particle_steps'] / res['steps']:.3g} particles per step) "
+                       f"of {share_note}; FP64 NumPy with in-situ Keldysh rates, one process pinned to "
+                       f"host CPU {res['cpus']} with single-threaded BLAS; the advance to step {start} "
+                       f"({res['advance_s']:.1f} s) and set-up ({res['init_s']:.1f} s) untimed",
+                cpus_on_host=len(cpus))
+
+
+def trace_summary(path, steps):
+    """Per-kernel statistics of the timed window from a rocprofv3 kernel trace
+    (kernel_trace.csv of a run of this script): the window is the span from
+    the start of the last `steps` push dispatches (no push follows the window)
+    to the end of the last ionization dispatch; every dispatch starting inside
+    it is counted."""
+    import csv
+    rows = list(csv.DictReader(open(path)))
+    for r in rows:
+        r["t0"], r["t1"] = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+    rows.sort(key=lambda r: r["t0"])
+    push = [r for r in rows if "k_push" in r["Kernel_Name"]]
+    ion = [r for r in rows if "k_ionize" in r["Kernel_Name"]]
+    if len(push) < steps or not ion:
+        raise SystemExit(f"{path}: {len(push)} push dispatches, fewer than the window's {steps} steps")
+    w0, w1 = push[-steps]["t0"], ion[-1]["t1"]
+    stats = {}
+    for r in rows:
+        if w0 <= r["t0"] <= w1:
+            name = r["Kernel_Name"].split("(")[0]
+            s = stats.setdefault(name, [0, 0.0, 1e30, 0.0])
+            d = (r["t1"] - r["t0"]) / 1e3
+            s[0] += 1
+            s[1] += d
+            s[2] = min(s[2], d)
+            s[3] = max(s[3], d)
+    total = sum(v[1] for v in stats.values())
+    lines = [f"window: {steps} steps, {(w1 - w0) / 1e6:.3f} ms from the first push of the window to the "
+             f"end of the last ionization",
+             "| kernel | calls | total us | avg us | min us | max us | share |", "|---|---|---|---|---|---|---|"]
+    for name, (n, tot, lo, hi) in sorted(stats.items(), key=lambda kv: -kv[1][1]):
+        lines.append(f"| {name} | {n} | {tot:.1f} | {tot / n:.2f} | {lo:.2f} | {hi:.2f} | {tot / total:.1%} |")
+    return "\n".join(lines)
+
+
+WORKLOADS = {
+    "mirror3d": "3D3V multi-layer mirror share, 256x128x128 cells at lambda/24, 8 alternating quarter-wave "
+                "layers (n 1.45 / 9 eV, n 2.1 / 4 eV), 8 ppc, 2-cycle 1 J/cm^2 plane wave, periodic transverse, "
+                "seed 2",
+    "slab2d": "2D3V silica slab, 2048x512 cells at lambda/32, 16 ppc, 3-cycle 5e13 W/cm^2 pulse, w0 3 um, seed 1",
+    "slab1d": "1D3V slab, 1024 cells at lambda/40, 100 ppc, 2-cycle 1e13 W/cm^2, seed 0",
+    "stress2d": "2D3V slab grid, every neutral pre-ionized at 2 eV (charged-loop stress), seed 1",
+    "stress3d": "3D3V mirror-share grid, every neutral pre-ionized at 2 eV (charged-loop stress), seed 2",
+    "stress2d-cap": "2D3V slab grid, 4.0e7 pre-ionized carriers (charged-loop stress at the particle cap)",
+    "stress3d-cap": "3D3V mirror-share grid, 2.5e8 pre-ionized carriers (charged-loop stress at the particle cap)",
+}
+
+
+def workload_config(name):
+    """(benchmark configuration, oracle configuration for the CPU baseline, its description)."""
+    import workloads as W
+    if name == "mirror3d":
+        cfg = W.config_3d()
+        # periodic transverse plane-wave run: every transverse column evolves
+        # alike, so a 16 x 16 share carries the same per-particle work
+        return cfg, W.config_3d(ny=16, nz=16), "the 256x16x16 transverse share of the same run"
+    if name == "slab2d":
+        cfg = W.config_2d()
+        return cfg, cfg, "the same run"
+    if name == "slab1d":
+        cfg = W.config_1d()
+        return cfg, cfg, "the same run"
+    if name == "stress2d":
+        cfg = W.config_stress(W.config_2d(), eV=2.0)
+        return cfg, W.config_stress(W.config_2d(ny=32), eV=2.0), "a 2048x32 outflow strip of the same slab"
+    if name == "stress3d":
+        cfg = W.config_stress(W.config_3d(), eV=2.0)
+        return cfg, W.config_stress(W.config_3d(ny=16, nz=16), eV=2.0), "the 256x16x16 transverse share"
+    if name == "stress2d-cap":
+        # 488 neutrals per slab cell, all pre-ionized: 2 x 40960 x 488 = 4.0e7 charged
+        return W.config_stress(W.config_2d(ppc=488), eV=2.0), None, ""
+    if name == "stress3d-cap":
+        # 272 neutrals per material cell, all pre-ionized: 2 x 458752 x 272 = 2.5e8 charged
+        return W.config_stress(W.config_3d(ppc=272), eV=2.0), None, ""
+    raise SystemExit(f"unknown workload {name}")
+
+
+def bench_window(args):
+    from paper_2502_13695_amd import pic
+    cfg, ocfg, share_note = workload_config(args.workload)
+    params = pic.canonical(cfg)
+    if args.start is not None:
+        start = args.start
+    elif cfg.get("preionize_eV", 0.0) > 0:
+        start = TUNE_STEPS + args.warmup + 12
+    else:
+        start = interaction_start(cfg, params)
+    cfg = dict(cfg, nsteps=max(cfg["nsteps"], start + args.steps + 1))
+    if args.calib_copy:
+        import torch
+        a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    if args.field_tile is not None:
+        os.environ["PIC_FIELD_TILE"] = str(args.field_tile)
+    roctx = Roctx()
+    r = run_window(cfg, start, args.steps, args.warmup, args.field_tile, roctx, args.resort)
+    cnt = window_counts(r["sc0"], r["sc1"], r["ev"], start, args.steps)
+    timers = r["timers"]
+    ps = cnt["charged_steps"] + cnt["neutral_steps"]
+    value = ps / r["wall"]
+    bytes_launch, fdetail = phase_bytes(cfg, r, cnt, args.steps)
+    tot_ms = {ph: timers[ph] for ph in PHASES if timers[8 + ph] > 0}
+    dom = max(tot_ms, key=tot_ms.get)
+    avg_ms = timers[dom] / timers[8 + dom]
+    achieved = bytes_launch[dom] / (avg_ms * 1e-3) / 1e9
+    copy_gbs = stream_copy_gbs()
+    # the other ceiling of the push: its algorithmic flops at the FP32 vector
+    # peak (3D order 2 only); bound = the larger of the two floors
+    roof = {"kernel": PHASES[dom], "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload, PHASES[dom]),
+            "bytes_per_launch": bytes_launch[dom], "avg_launch_us": avg_ms * 1e3, "launches": int(timers[8 + dom]),
+            "stream_copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs}
+    bound = "hbm"
+    if dom == 0 and cfg["ndim"] == 3 and cfg.get("shape_order", 2) == 2:
+        flops = FLOP_PUSH_3D2 * cnt["charged_steps"] / timers[8]
+        tflops = flops / (avg_ms * 1e-3) / 1e12
+        roof["alu"] = {"flop_per_launch": flops, "achieved_TFLOPs": tflops, "peak_TFLOPs": FP32_PEAK_TFLOPS,
+                       "frac": tflops / FP32_PEAK_TFLOPS}
+        if flops / (FP32_PEAK_TFLOPS * 1e12) > bytes_launch[dom] / (HBM_PEAK_GBS * 1e9):
+            bound = "alu"
+    roof = {"bound": bound, **roof}
+    steps = args.steps
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["wall"] / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload], "cells": list(cfg["n"]), "ppc": cfg["ppc"],
+                   "seed": cfg["seed"], "start_step": start,
+                   "sort_check_every": args.resort if args.resort is not None else 8,
+                   "window": f"steps {start}..{start + steps - 1}" +
+                             (" (the pulse peak reaches the first layer at the start)" if args.start is None
+                              and not cfg.get("preionize_eV", 0.0) else ""),
+                   "charged_start": cnt["charged_start"], "charged_end": cnt["charged_end"],
+                   "alive_neutrals_start": cnt["alive_start"], "alive_neutrals_end": cnt["alive_end"],
+                   "events_in_window": cnt["events"], "removed_in_window": cnt["removed"],
+                   "charged_steps": cnt["charged_steps"], "neutral_steps": cnt["neutral_steps"],
+                   "particle_steps": ps},
+        "roofline": roof,
+        "phases_us_per_step": {PHASES[ph]: timers[ph] / steps * 1e3 for ph in tot_ms},
+        "phases_us_per_launch": {PHASES[ph]: timers[ph] / timers[8 + ph] * 1e3 for ph in tot_ms},
+        "phases_GBs": {PHASES[ph]: bytes_launch[ph] / (timers[ph] / timers[8 + ph] * 1e-3) / 1e9
+                       for ph in tot_ms},
+        "field_tiles": fdetail,
+        "field_tile_autotune": r["tune"],
+        "tile_sort": dict(start=r["sort0"], end=r["sort1"]),
+        "health": r["sc1"]["health"],
+    }
+    if not args.no_cpu_baseline and ocfg is not None:
+        out["cpu_baseline"] = cpu_baseline(dict(ocfg, nsteps=cfg["nsteps"]), start, steps, args.cpu_budget,
+                                           share_note)
+    return out
 
 
 def _run_alone(cfg, steps):
@@ -218,7 +496,7 @@ def bench_scan(args):
     from paper_2502_13695_amd import pic
     from paper_2502_13695_amd.serve import particle_steps
     torch.cuda.set_device(0)
-    steps = args.steps if args.steps != 4000 else 3000
+    steps = args.scan_steps
     cfgs = [dict(c, nsteps=steps) for c in W.batch_scan(args.instances, steps)]
     # warm the kernels and the rate-table cache
     _run_alone(dict(cfgs[0], nsteps=20), 20)
@@ -397,12 +675,14 @@ def bench_diag(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4000)
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="slab2d", choices=["slab2d", "mirror3d", "slab1d",
-                                                             "stress2d", "stress3d", "stress2d-cap",
-                                                             "stress3d-cap", "scan", "serve", "diag"])
+    ap.add_argument("--steps", type=int, default=20, help="timed steps (the window)")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed steps right before the window")
+    ap.add_argument("--start", type=int, default=None,
+                    help="first step of the window (default: the pulse peak reaches the first layer)")
+    ap.add_argument("--workload", default="mirror3d",
+                    choices=list(WORKLOADS) + ["scan", "serve", "diag"])
     ap.add_argument("--instances", type=int, default=32, help="scan: fluence-scan instances")
+    ap.add_argument("--scan-steps", type=int, default=3000, help="scan: steps of every instance")
     ap.add_argument("--requests", type=int, default=400, help="serve: requests")
     ap.add_argument("--scale", type=float, default=1.0, help="serve: grid/step scale of the mix")
     ap.add_argument("--burst", action="store_true",
@@ -413,12 +693,23 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--calib-copy", action="store_true",
                     help="copy 256 MiB once before the run (HBM counter calibration)")
+    ap.add_argument("--resort", type=int, default=None,
+                    help="tile-sort check period in steps (default: the library's, 8)")
+    ap.add_argument("--trace-summary", default=None, metavar="KERNEL_TRACE_CSV",
+                    help="print the per-kernel statistics of the timed window of a rocprofv3 kernel "
+                         "trace of this script (same --steps) and exit")
+    ap.add_argument("--oracle-child", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.oracle_child is not None:
+        _oracle_child(json.loads(args.oracle_child))
+        return
+    if args.trace_summary is not None:
+        print(trace_summary(args.trace_summary, args.steps))
+        return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}); the library has no "
-              f"multi-GPU path", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}): the library has no multi-GPU "
+              f"path, and the design notes describe how a run would shard", file=sys.stderr)
         sys.exit(2)
-    import workloads as W
     if args.workload == "scan":
         print(json.dumps(bench_scan(args)), flush=True)
         return
@@ -428,107 +719,7 @@ def main():
     if args.workload == "diag":
         print(json.dumps(bench_diag(args)), flush=True)
         return
-    if args.workload == "slab2d":
-        cfg = W.config_2d()
-        wl = dict(workload="2D3V silica slab, 2048x512 cells at lambda/32, 16 ppc, 3-cycle 5e13 W/cm^2 "
-                           "pulse, w0 3 um", cells=[2048, 512], ppc=16, planned_steps=4000, seed=1)
-    elif args.workload == "mirror3d":
-        cfg = W.config_3d()
-        wl = dict(workload="3D3V multi-layer mirror share, 256x128x128 cells at lambda/24, 8 ppc, "
-                           "2-cycle 1 J/cm^2 plane wave", cells=[256, 128, 128], ppc=8,
-                  planned_steps=2000, seed=2)
-    elif args.workload == "slab1d":
-        cfg = W.config_1d()
-        wl = dict(workload="1D3V slab, 1024 cells at lambda/40, 100 ppc, 2-cycle 1e13 W/cm^2",
-                  cells=[1024], ppc=100, planned_steps=2000, seed=0)
-    elif args.workload == "stress2d":
-        cfg = W.config_stress(W.config_2d(), eV=2.0)
-        wl = dict(workload="2D3V slab, all neutrals pre-ionized (charged-loop stress)", cells=[2048, 512],
-                  ppc=16, seed=1)
-    elif args.workload == "stress2d-cap":
-        # 488 neutrals per slab cell, all pre-ionized: 2 x 40960 x 488 = 4.0e7 charged
-        cfg = W.config_stress(W.config_2d(ppc=488), eV=2.0)
-        wl = dict(workload="2D3V slab grid, 4.0e7 pre-ionized carriers (charged-loop stress at the "
-                           "particle cap)", cells=[2048, 512], ppc=488, seed=1)
-    elif args.workload == "stress3d-cap":
-        # 272 neutrals per material cell, all pre-ionized: 2 x 458752 x 272 = 2.5e8 charged
-        cfg = W.config_stress(W.config_3d(ppc=272), eV=2.0)
-        wl = dict(workload="3D3V mirror-share grid, 2.5e8 pre-ionized carriers (charged-loop stress at "
-                           "the particle cap)", cells=[256, 128, 128], ppc=272, seed=2)
-    else:
-        cfg = W.config_stress(W.config_3d(), eV=2.0)
-        wl = dict(workload="3D3V mirror share, all neutrals pre-ionized (charged-loop stress)",
-                  cells=[256, 128, 128], ppc=8, seed=2)
-    cfg = dict(cfg, nsteps=max(cfg["nsteps"], args.steps))
-    if args.calib_copy:
-        import torch
-        a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        a.fill_(1.0)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
-    if args.field_tile is not None:
-        # fixed field tile shape, read by the library when a context is created
-        os.environ["PIC_FIELD_TILE"] = str(args.field_tile)
-    r = run_gpu(cfg, args.steps, args.warmup, args.field_tile)
-    value = r["particle_steps"] / r["wall"]
-    timers = r["timers"]
-    # dominant kernel by device time
-    tot = {ph: timers[ph] for ph in PHASES if timers[8 + ph] > 0}
-    dom = max((ph for ph in tot if ph != 3), key=tot.get)
-    n_launch = timers[8 + dom]
-    avg_ms = timers[dom] / n_launch
-    n_charged_avg = r["charged_steps"] / args.steps
-    n_alive_avg = r["neutral_steps"] / args.steps
-    # share of the field tiles that skip the current: it only shrinks during a
-    # run (the charged region only grows), so the share at the start gives the
-    # fewest bytes per launch, the share at the end the most; the achieved rate
-    # uses the fewest
-    share = lambda g: g["far_tiles"] / max(1, g["near_tiles"] + g["far_tiles"])
-    reg, reg0 = r["region"], r["region0"]
-    far_frac, far_frac_end = share(reg0), share(reg)
-    # far tiles beyond the field front are not updated: the device counts the
-    # tiles every field launch updated; the mean over the timed launches,
-    # less the near tiles, is the share of far tiles that moved bytes
-    ntiles = max(1, reg["near_tiles"] + reg["far_tiles"])
-    upd = (reg["tiles_updated"] - reg0["tiles_updated"]) / max(1, args.steps)
-    far_updated = min(far_frac, max(0.0, upd - reg0["near_tiles"]) / ntiles)
-    bytes_launch = phase_bytes(cfg, dom, n_charged_avg, n_alive_avg, far_frac, far_updated)
-    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
-    copy_gbs = stream_copy_gbs()
-    step_ms = r["wall"] / args.steps * 1e3
-    out = {
-        "metric": "particle-steps/sec (gather+push+deposit+ionize) at 1 GPU",
-        "value": value,
-        "unit": "particle-steps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": step_ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": dict(wl, neutrals=r["nneut"], charged_final=r["scalars"]["n_e"] + r["scalars"]["n_pos"],
-                       events=r["scalars"]["events"], particle_steps=r["particle_steps"]),
-        "roofline": {"bound": "hbm", "kernel": PHASES[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(args.workload, PHASES[dom]),
-                     "bytes_per_launch": bytes_launch, "avg_launch_us": avg_ms * 1e3,
-                     "stream_copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
-        "phases_us_per_step": {PHASES[ph]: timers[ph] / max(timers[8], 1) * 1e3 for ph in tot},
-        "phases_us_per_launch": {PHASES[ph]: timers[ph] / max(timers[8 + ph], 1) * 1e3 for ph in tot},
-        "field_tile_autotune": r["tune"],
-        "far_tiles": dict(start=reg0, end=reg, far_frac_start=far_frac, far_frac_end=far_frac_end,
-                          tiles_updated_per_launch=upd, far_updated_frac=far_updated,
-                          bytes_per_launch_end=phase_bytes(cfg, 1, 0, 0, far_frac_end)),
-        "tile_sort": r["sort_state"],
-    }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_budget)
-    print(json.dumps(out), flush=True)
+    print(json.dumps(bench_window(args)), flush=True)
 
 
 if __name__ == "__main__":
