@@ -25,6 +25,10 @@ it changes; the inherited parts follow the textbook method named alongside:
   with the direct deposit of the velocity components along absent dimensions.
 * One-cycle rolling window of the node |E|; its maximum is the amplitude
   entering the Keldysh rate (Sec. 2.1, last paragraph).
+* Energy diagnostics: field energy, carriers' kinetic energy, the gap energy
+  paid by ionization (absorbed energy, a reading of Sec. 4.2), the number and
+  energy density grids (Sec. 4.1, 4.2), and the Poynting flux through the
+  faces of the box one cell inside the outflow faces (the field-side budget).
 * Monte-Carlo single ionization of immobile neutral molecule macroparticles
   with the per-molecule rate W/n0, probability 1 - exp(-W dt / n0) per step,
   the whole macroparticle converting into one electron (m_e*, Sec. 3.2) and
@@ -41,7 +45,14 @@ oscillation frequency, brute-force sliding maximum, the binomial statistics of
 ionization at a fixed amplitude; for the paper-style diagnostics, kinetic
 energies of particles built from a chosen gamma, the particle and range
 bookkeeping of the energy histogram, and the maximum accumulated intensity of a
-plane wave crossing vacuum against the peak of its incident field.
+plane wave crossing vacuum against the peak of its incident field
+(tests/test_oracle_diagnostics.py); the 300 K thermal draw against the
+Maxwellian variance, the exact-skip amplitude against the probability below
+it, the number and energy density grids against particle totals and uniform
+lattice loads, the field energy against uniform fields in a dielectric, the
+Poynting budget against a pulse's analytic fluence and its closure through
+transverse faces, and the gap energy against events x weight x gap
+(tests/test_oracle_budget.py).
 """
 
 import math
@@ -112,6 +123,10 @@ class Sim:
         self.imax = z()
         self.events = []          # list of (id array, step)
         self.energy_gap = 0.0     # sum over events of w * Delta  [J]
+        # field energy carried through the flux planes (one cell inside every
+        # outflow face) into and out of the box so far [J]
+        self.energy_in = 0.0
+        self.energy_out = 0.0
         self.acut = [self._amp_cut(m) for m in P.mats]
         if load_neutrals:
             self._load_neutrals()
@@ -377,6 +392,62 @@ class Sim:
                         E[c][sl_p] = ip1 + (old[c][sl_q] - iq0) + k * (
                             (E[c][sl_q] - iq1) - (old[c][sl_p] - ip0))
 
+    def _poynting(self, E_n, b_half):
+        """Energy carried through the flux surface during the step.  The surface
+        bounds the inner box whose faces are the node planes one cell inside the
+        outflow faces (periodic axes: the whole period).  On the face normal to
+        an outflow axis d, the Poynting vector S = E x H = eps0 c (E x b) (b = c B)
+        is taken with E at the half step, (E^n + E^{n+1}) / 2, and b^{n+1/2}
+        averaged to the plane from its two half-staggered neighbours along d, and
+        integrated over the face by the trapezoid rule on the inner box's extent
+        along the other axes (cell area dA; absent axes count 1 m).  Each point's
+        S dt dA adds to the energy entering (S pointing into the box) or leaving."""
+        P = self.P
+        for d in range(self.D):
+            if P.periodic[d]:
+                continue
+            a, b_ = (d + 1) % 3, (d + 2) % 3
+            area = 1.0
+            for e in range(self.D):
+                if e != d:
+                    area *= P.dx[e]
+            for plane, inward in ((1, 1.0), (P.n[d] - 1, -1.0)):
+                tot_in = tot_out = 0.0
+                for ce, cb, sign in ((a, b_, 1.0), (b_, a, -1.0)):
+                    # positions of E_ce on the face (those of b_cb coincide across it)
+                    sl, sl_lo, wts = [], [], []
+                    for e in range(3):
+                        if e == d:
+                            sl.append(slice(G + plane, G + plane + 1))
+                            sl_lo.append(slice(G + plane - 1, G + plane))
+                            wts.append(np.ones(1))
+                        elif e >= self.D:
+                            sl.append(slice(0, 1))
+                            sl_lo.append(slice(0, 1))
+                            wts.append(np.ones(1))
+                        elif P.periodic[e]:
+                            sl.append(slice(G, G + P.n[e]))
+                            sl_lo.append(slice(G, G + P.n[e]))
+                            wts.append(np.ones(P.n[e]))
+                        elif self.stE[ce][e]:            # half-staggered: j + 1/2, 1 <= j <= n - 2
+                            sl.append(slice(G + 1, G + P.n[e] - 1))
+                            sl_lo.append(slice(G + 1, G + P.n[e] - 1))
+                            wts.append(np.ones(P.n[e] - 2))
+                        else:                            # nodes 1 .. n - 1, ends weighted 1/2
+                            sl.append(slice(G + 1, G + P.n[e]))
+                            sl_lo.append(slice(G + 1, G + P.n[e]))
+                            w = np.ones(P.n[e] - 1)
+                            w[0] = w[-1] = 0.5
+                            wts.append(w)
+                    wgt = wts[0][:, None, None] * wts[1][None, :, None] * wts[2][None, None, :]
+                    e_half = 0.5 * (E_n[ce][tuple(sl)] + self.E[ce][tuple(sl)])
+                    b_node = 0.5 * (b_half[cb][tuple(sl_lo)] + b_half[cb][tuple(sl)])
+                    flux = inward * sign * EPS0 * C * e_half * b_node * wgt * area * P.dt
+                    tot_in += float(np.sum(np.maximum(flux, 0.0)))
+                    tot_out += float(np.sum(np.maximum(-flux, 0.0)))
+                self.energy_in += tot_in
+                self.energy_out += tot_out
+
     def node_emag(self):
         """|E| at grid nodes from the Yee components averaged to the node."""
         comps = []
@@ -577,8 +648,11 @@ class Sim:
     def step(self):
         n = self.step_index
         self.push_and_deposit()
+        E_n = [e.copy() for e in self.E]
         self._b_half()
+        b_half = [b.copy() for b in self.b]
         self._e_full(n)
+        self._poynting(E_n, b_half)
         self._b_half()
         em = self.node_emag()
         self.win.append(em)
@@ -661,6 +735,28 @@ class Sim:
             for b_ in range(wy.shape[1]):
                 for c in range(wz.shape[1]):
                     np.add.at(out, (ix[:, a], iy[:, b_], iz[:, c]), w * wx[:, a] * wy[:, b_] * wz[:, c])
+        self._fold_periodic(out)
+        return out / self.P.vcell
+
+    def energy_density_grid(self, species="e"):
+        """Kinetic energy density [J/m^3] at nodes (Sec. 4.2: the number density
+        times the mean energy): sum_p w_p KE_p S(x_i - x_p) / V_cell with the
+        node shape of the number density and KE = m c^2 |u|^2 / (gamma + 1)."""
+        out = np.zeros(self.S)
+        if len(self.px) == 0:
+            return out
+        sp = np.array([k["species"] for k in self.P.kinds])[self.pk]
+        sel = sp == species
+        pos = self.px[sel]
+        w = self._kind_arrays(self.pk[sel], "weight")
+        m = self._kind_arrays(self.pk[sel], "mass")
+        u2 = np.sum(self.pu[sel] * self.pu[sel], axis=1)
+        ke = m * C * C * u2 / (np.sqrt(1.0 + u2) + 1.0)
+        (ix, wx), (iy, wy), (iz, wz) = self._stencil(pos, [False] * 3)
+        for a in range(wx.shape[1]):
+            for b_ in range(wy.shape[1]):
+                for c in range(wz.shape[1]):
+                    np.add.at(out, (ix[:, a], iy[:, b_], iz[:, c]), w * ke * wx[:, a] * wy[:, b_] * wz[:, c])
         self._fold_periodic(out)
         return out / self.P.vcell
 
