@@ -176,8 +176,15 @@ enum {
   PIC_DIAG_IMAX = 11,     /* float: maximum accumulated intensity at nodes, the
                              largest node |E|^2 [V^2/m^2] over the samples taken
                              since pic_set_imax (zero when never enabled) */
-  PIC_DIAG_TRACKS = 12    /* pic_track records taken since pic_set_tracks, sorted
+  PIC_DIAG_TRACKS = 12,   /* pic_track records taken since pic_set_tracks, sorted
                              by (id, kind, step) */
+  PIC_DIAG_HEALTH = 13    /* double[4]: the device health word (bit 0 charged-slot
+                             capacity exceeded by births, bit 1 a non-finite E value
+                             stored by the field update, a non-finite particle
+                             momentum or a non-finite window amplitude), the latched
+                             pic_status, the device step index, the charged slots
+                             in use.  Valid in every state, including after a
+                             latched error. */
 };
 
 /* PIC_DIAG_SCALARS layout (all double). */
@@ -187,7 +194,17 @@ enum {
   PIC_SC_E_GAP = 9, PIC_SC_E_ABS = 10, PIC_SC_GAUSS_MAX = 11, PIC_SC_RHO_MAX = 12,
   PIC_SC_HEALTH = 13, PIC_SC_SLOTS = 14, PIC_SC_TRACKS_DROPPED = 15,
   PIC_SC_GAUSS_L2 = 16,   /* root mean square of the Gauss-law residual over the interior nodes [V/m^2] */
-  PIC_SC_COUNT = 17
+  /* Field-side energy budget (a reading of Sec. 4.2's absorbed energy): field
+   * energy carried through the flux surface since the start [J], entering and
+   * leaving.  The surface bounds the box whose faces are the node planes one
+   * cell inside the outflow faces (periodic axes: the whole period); on it the
+   * Poynting vector eps0 c (E x b) uses E at the half step, (E^n + E^{n+1})/2,
+   * and b^{n+1/2} averaged to the plane, integrated with the trapezoid rule
+   * (absent axes count 1 m).  Each staggered product E_a b_b is one term; a
+   * term's energy goes to E_IN when it points into the box, else to E_OUT.
+   * E_IN - E_OUT - U_FIELD is the energy the charges took from the field. */
+  PIC_SC_E_IN = 17, PIC_SC_E_OUT = 18,
+  PIC_SC_COUNT = 19
 };
 
 /* A charged macroparticle: cell indices, FP32 offsets in [0, 1) (position =

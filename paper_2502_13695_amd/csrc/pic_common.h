@@ -91,39 +91,36 @@ __host__ __device__ inline float table_lookup(const TabHdr* __restrict__ h, floa
 
 // ------------------------------------------------------- particle tiles
 // The charged particles are kept sorted by tile of the deposit (counting sort,
-// redone when enough births or drifters have accumulated).  A particle that
-// starts a step in cell c deposits its current on nodes c - 2 .. c + 3 of each
-// present axis (Esirkepov, shape order <= 2, at most one cell per step), so
-// the deposit of a whole tile of T cells fits a window of T + 5 nodes held in
-// LDS.  Each tile is split into groups of 64 cells, one per parity class of
-// the cell indices inside the tile (3D: 8 classes of 4 x 4 x 4 cells, 2D: 4
-// of 8 x 8, 1D: 2 of 64); inside a group the particles are ordered level by
-// level -- the first particle of every cell, in cell order, then the second,
-// ... -- so the lanes of a wave sit in distinct cells at least two apart along
-// some axis: the deposit stencils of one instruction never share a node.
+// redone when enough particles have left their tile or landed beyond the
+// layout).  A particle that starts a step in cell c deposits its current on
+// nodes c - 2 .. c + 3 of each present axis (Esirkepov, shape order <= 2, at
+// most one cell per step), so the deposit of a whole tile of T cells fits a
+// window of T + 5 nodes held in LDS.  Each tile's range is followed by room
+// for its births until the next sort: electrons and positive carriers in two
+// halves, each as large as the tile's alive neutrals (immobile, ionized once).
 __host__ __device__ constexpr int ptile_ext(int D, int axis) {
   return axis >= D ? 1 : (D == 1 ? 128 : (D == 2 ? 16 : 8));
 }
 __host__ __device__ constexpr int ptile_cells(int D) {
   return ptile_ext(D, 0) * ptile_ext(D, 1) * ptile_ext(D, 2);
 }
-constexpr int PT_GROUP = 64;        // cells per group
 constexpr int PT_LO = 2;            // window starts PT_LO nodes below the tile
 constexpr int PT_PAD = 5;           // window = tile + PT_PAD nodes per present axis
-constexpr int SORT_CHUNK = 4096;    // particles per block-sized piece of a tile
+constexpr int SORT_CHUNK = 4096;    // sorted particles per block-sized piece of a tile
 constexpr int SPARSE_CHUNK = 128;   // pieces this small skip the LDS windows
-constexpr int SORT_LMAX = 256;      // a group with more particles in one cell keeps its
-                                    // scatter order (still sorted by group)
 // LDS deposit in 64-bit fixed point: a contribution v (|v| <= max |kq|) is
-// added as trunc(v * jscale) with jscale = 2^40 / 2^ceil(log2 max |kq|), so a
-// node's sum over one chunk stays below 2^52; the sum is exact and does not
-// depend on the order of the atomics.
+// added as round(v * jscale) with jscale = 2^40 / 2^ceil(log2 max |kq|); a
+// node's sum over one work item (the particles within two cells of it) stays
+// far below 2^63; the sum is exact and does not depend on the order of the
+// atomics.
 constexpr int JFIX_BITS = 40;
 
-// sort control words (device): [0] sorted slots, [1] chunks, [2] drifters
-// deposited outside their tile's window since the sort (per step), [3] sort
-// decision, [4] sorts performed
-constexpr int SC_NSORTED = 0, SC_NCHUNKS = 1, SC_NDRIFT = 2, SC_GO = 3, SC_NSORTS = 4, SC_WORDS = 8;
+// sort control words (device): [0] end of the layout (sorted tiles and their
+// birth room), [1] chunks, [2] drifters deposited outside their tile's window
+// since the sort (per step), [3] sort decision, [4] sorts performed, [5] a
+// sort is wanted at the next check whatever the counts
+constexpr int SC_NSORTED = 0, SC_NCHUNKS = 1, SC_NDRIFT = 2, SC_GO = 3, SC_NSORTS = 4, SC_FORCE = 5,
+              SC_WORDS = 8;
 // Charged region along x: cells [lo, hi] that held a charged particle at some
 // step so far (never shrinks), in three rotating slots (step n reads slot n % 3,
 // its push extends slot (n + 1) % 3).  Field tiles farther than XNEAR_MARGIN
@@ -167,11 +164,17 @@ struct Inst {
   uint32_t* pid;                // id of the parent neutral (placed particles: cells * ppc + index)
   int* pcount;                  // used slots
   int capacity;
-  // tile sort: [0, sctl[SC_NSORTED]) holds the groups in order (tile-major);
-  // births since the sort follow up to *pcount
+  // tile sort: [0, sctl[SC_NSORTED]) holds the tiles in order, each range
+  // followed by its birth room; particles placed or born beyond it follow up
+  // to *pcount
   int ntile[3], ntiles;
-  int *gcnt, *gn, *gstart, *gfill;  // per group: count (zero between sorts), count, first slot, fill
-  int4* chunks;                 // {tile, first slot, end slot, 0}
+  int* tcnt;                    // per tile: particles counted (zero between sorts)
+  int* tstart;                  // first slot
+  int* tbirth;                  // first birth slot (electrons; positive carriers tslack later)
+  int* tslack;                  // birth room: events the tile can still take
+  int* tfill;                   // events taken since the sort
+  int* talive;                  // upper bound of the tile's alive neutrals
+  int4* chunks;                 // {tile, first slot, end slot, first birth slot or -1}
   float jscale, jscale_inv;     // LDS fixed-point scale of the deposit and its inverse
   int* sctl;                    // SC_* words
   uint32_t* scell;              // scatter targets (same layout as the particle arrays)
@@ -203,6 +206,10 @@ struct Inst {
   int* front;                   // last padded x index of a tile that stored a nonzero E or b
   unsigned long long* tiles_done;   // field tiles updated, one counter per XCD (stride 32)
   unsigned long long* nevents;  // per material
+  // field energy through the flux surface (the faces of the box one cell
+  // inside the outflow faces): [0] entering, [1] leaving, J
+  double* eflux;
+  double kflux[3];              // eps0 c dt x the transverse cell area of a plane normal to axis d
   uint64_t seed;
   // control
   int* step;                    // device step counter

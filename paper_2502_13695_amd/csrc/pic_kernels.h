@@ -40,7 +40,8 @@ struct Stamp {
 };
 
 // phase launchers (enqueue on `s`); D = 1..3, order = 1..2
-void launch_push(const Group& g, int D, int order, hipStream_t s, Stamp st = {});
+// per: periodic transverse axes (D >= 2)
+void launch_push(const Group& g, int D, int order, bool per, hipStream_t s, Stamp st = {});
 // tile sort of the charged particles (gp: the push grid; gscan: one block per
 // instance); each instance decides on the device whether a sort is due
 void launch_sort(const Group& gp, const Group& gscan, int D, hipStream_t s, Stamp st = {});

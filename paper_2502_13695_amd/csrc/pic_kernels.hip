@@ -249,29 +249,26 @@ __device__ __forceinline__ int wave_extent(int moved) {
   return __any(moved) ? ORDER + 2 : ORDER + 1;
 }
 
-// Current sinks.  x/y/z map an (unwrapped) node index to an offset, add()
-// accumulates component `comp`.
+// Current sinks.  x/y/z map an (unwrapped) node index to an offset; coef()
+// prepares a particle factor and wt() a node-pair weight in the sink's
+// arithmetic, put() adds coef x wt to component `comp` at offset o.
+template <bool PY, bool PZ>
 struct GSink {   // the padded HBM arrays, FP32 atomics, periodic wrap
   float* J0;
   float* J1;
   float* J2;
-  int ny, nz, per_y, per_z, sy, sz, Gy, Gz;
+  int ny, nz, sy, sz, Gy, Gz;
+  using C = float;
   __device__ __forceinline__ int x(int i) const { return i + G; }
-  __device__ __forceinline__ int y(int j) const { return sy * (wrapi(j, ny, per_y) + Gy); }
-  __device__ __forceinline__ int z(int k) const { return sz * (wrapi(k, nz, per_z) + Gz); }
-  __device__ __forceinline__ void add(int comp, int o, float v) const {
+  __device__ __forceinline__ int y(int j) const { return sy * (wrapi(j, ny, PY) + Gy); }
+  __device__ __forceinline__ int z(int k) const { return sz * (wrapi(k, nz, PZ) + Gz); }
+  __device__ __forceinline__ float coef(float c) const { return c; }
+  __device__ __forceinline__ float wt(float w) const { return w; }
+  __device__ __forceinline__ void put(int comp, int o, float c, float w) const {
     gmem<float>* J = gp(comp == 0 ? J0 : comp == 1 ? J1 : J2);
-    __hip_atomic_fetch_add(J + (unsigned)o, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(J + (unsigned)o, c * w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 };
-
-// round(v * scale) as a two's-complement 64-bit integer (|v * scale| < 2^51):
-// adding 1.5 * 2^52 in FP64 leaves the integer in the low mantissa bits, and
-// the constant's low word is zero, so removing it touches the high word only
-__device__ __forceinline__ unsigned long long fix64(float v, double scale) {
-  const double d = fma((double)v, scale, 6755399441055744.0);
-  return (unsigned long long)__double_as_longlong(d) - 0x4338000000000000ull;
-}
 
 template <int D>
 struct PWin {   // LDS deposit window of a particle tile
@@ -281,27 +278,42 @@ struct PWin {   // LDS deposit window of a particle tile
   static constexpr int N = X * Y * Z;
 };
 
+// The block's LDS window, origin (x0, y0, z0) in unwrapped nodes, 64-bit
+// fixed point (integer LDS atomics run at full rate; FP32 LDS atomics do not on
+// gfx950): a contribution c w (c = charge factor x scale, w = shape weight) is
+// added as round(c w) through an FP64 fma with 1.5 2^52, which leaves the
+// integer in the low mantissa bits; the constant's low word is zero, so
+// removing it touches the high word only.  Sums are exact and do not depend on
+// the order of the atomics.
 template <int D>
-struct LSink {   // the block's LDS window, origin (x0, y0, z0) in unwrapped nodes;
-                 // 64-bit fixed point (integer LDS atomics run at full rate)
+struct LSink {
   unsigned long long* s;
   int x0, y0, z0;
   double scale;
+  using C = double;
   __device__ __forceinline__ int x(int i) const { return i - x0; }
   __device__ __forceinline__ int y(int j) const { return (j - y0) * PWin<D>::X; }
   __device__ __forceinline__ int z(int k) const { return (k - z0) * (PWin<D>::X * PWin<D>::Y); }
-  __device__ __forceinline__ void add(int comp, int o, float v) const {
-    atomicAdd(s + comp * PWin<D>::N + o, fix64(v, scale));
+  __device__ __forceinline__ double coef(float c) const { return (double)c * scale; }
+  __device__ __forceinline__ double wt(float w) const { return (double)w; }
+  __device__ __forceinline__ void put(int comp, int o, double c, double w) const {
+    const double d = fma(w, c, 6755399441055744.0);
+    atomicAdd(s + comp * PWin<D>::N + o, (unsigned long long)__double_as_longlong(d) - 0x4338000000000000ull);
   }
 };
 
-// Esirkepov deposit of dt J^{n+1/2} / eps0 for one particle.  Components
-// along present axes accumulate -q dx (dW/dt) along their axis; components
-// along absent axes take q v times the path-averaged shape.
+// Esirkepov deposit of dt J^{n+1/2} / eps0 for one particle.  Components along
+// present axes are -q dx times the cumulative sum of W along their axis, and
+// Esirkepov's W_x(i, j, k) = DS_x(i) wb(j, k) with the path-averaged transverse
+// weight wb = S0_y S0_z + DS_y S0_z / 2 + S0_y DS_z / 2 + DS_y DS_z / 3, so
+// J_x(i, j, k) = (-q dx CS_x(i)) wb(j, k), CS_x the cumulative sum of DS_x;
+// wb factors as S0_z (S0_y + DS_y/2) + DS_z (S0_y/2 + DS_y/3).  Components along
+// absent axes take q v times the path-averaged shape.
 template <int D, int ORDER, class S>
 __device__ __forceinline__ void deposit(const S& s, const Esk<ORDER>& ex, const Esk<ORDER>& ey,
                                         const Esk<ORDER>& ez, float qx, float qy, float qz, float vy,
                                         float vz) {
+  using CT = typename S::C;
   constexpr int W = ORDER + 2;
   constexpr int WY = D >= 2 ? W : 1;
   constexpr int WZ = D >= 3 ? W : 1;
@@ -309,74 +321,117 @@ __device__ __forceinline__ void deposit(const S& s, const Esk<ORDER>& ex, const 
   const int ny = D >= 2 ? wave_extent<ORDER>(ey.moved) : 1;
   const int nz = D >= 3 ? wave_extent<ORDER>(ez.moved) : 1;
   constexpr float third = 1.0f / 3.0f;
-  // Jx: cumulative sum of Wx along x
+  // per-axis factors: A = S0 + DS/2, B = S0/2 + DS/3 (absent axes: S0 = 1, DS = 0)
+  float Ax[W], Bx[W], Ay[WY], By[WY];
+  CT cx[W - 1], cy[W - 1], cz[W - 1];
+  {
+    float cs = 0.0f;
+#pragma unroll
+    for (int a = 0; a < W; ++a) {
+      Ax[a] = ex.S0[a] + 0.5f * ex.DS[a];
+      Bx[a] = 0.5f * ex.S0[a] + third * ex.DS[a];
+      if (a < W - 1) {
+        cs += ex.DS[a];
+        cx[a] = s.coef(-qx * cs);
+      }
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < WY; ++b) {
+    Ay[b] = D >= 2 ? ey.S0[b] + 0.5f * ey.DS[b] : 1.0f;
+    By[b] = D >= 2 ? 0.5f * ey.S0[b] + third * ey.DS[b] : 0.5f;
+  }
+  if (D >= 2) {
+    float cs = 0.0f;
+#pragma unroll
+    for (int b = 0; b < W - 1; ++b) {
+      cs += ey.DS[b];
+      cy[b] = s.coef(-qy * cs);
+    }
+  }
+  if (D >= 3) {
+    float cs = 0.0f;
+#pragma unroll
+    for (int c = 0; c < W - 1; ++c) {
+      cs += ez.DS[c];
+      cz[c] = s.coef(-qz * cs);
+    }
+  }
+  // offsets of the nodes along each axis
+  int ox[W], oy[WY], oz[WZ];
+#pragma unroll
+  for (int a = 0; a < W; ++a) ox[a] = s.x(ex.org + a);
+#pragma unroll
+  for (int b = 0; b < WY; ++b) oy[b] = D >= 2 ? s.y(ey.org + b) : 0;
+#pragma unroll
+  for (int c = 0; c < WZ; ++c) oz[c] = D >= 3 ? s.z(ez.org + c) : 0;
+  // Jx over (j, k)
 #pragma unroll
   for (int c = 0; c < WZ; ++c) {
     if (c >= nz) break;
     const float s0z = D >= 3 ? ez.S0[c] : 1.0f, dsz = D >= 3 ? ez.DS[c] : 0.0f;
-    const int oz = D >= 3 ? s.z(ez.org + c) : 0;
+#pragma unroll
+    for (int b = 0; b < WY; ++b) {
+      if (b >= ny) break;
+      const CT w = s.wt(s0z * Ay[b] + dsz * By[b]);
+#pragma unroll
+      for (int a = 0; a < W - 1; ++a) {
+        if (a >= nx - 1) break;
+        s.put(0, ox[a] + oy[b] + oz[c], cx[a], w);
+      }
+    }
+  }
+  // Jy over (i, k)
+  if (D >= 2) {
+#pragma unroll
+    for (int c = 0; c < WZ; ++c) {
+      if (c >= nz) break;
+      const float s0z = D >= 3 ? ez.S0[c] : 1.0f, dsz = D >= 3 ? ez.DS[c] : 0.0f;
+#pragma unroll
+      for (int a = 0; a < W; ++a) {
+        if (a >= nx) break;
+        const CT w = s.wt(s0z * Ax[a] + dsz * Bx[a]);
+#pragma unroll
+        for (int b = 0; b < W - 1; ++b) {
+          if (b >= ny - 1) break;
+          s.put(1, ox[a] + oy[b] + oz[c], cy[b], w);
+        }
+      }
+    }
+  } else {
+    const CT c1 = s.coef(qy * vy);
+#pragma unroll
+    for (int a = 0; a < W; ++a) {
+      if (a >= nx) break;
+      s.put(1, ox[a], c1, s.wt(Ax[a]));
+    }
+  }
+  // Jz over (i, j)
+  if (D >= 3) {
+#pragma unroll
+    for (int b = 0; b < WY; ++b) {
+      if (b >= ny) break;
+#pragma unroll
+      for (int a = 0; a < W; ++a) {
+        if (a >= nx) break;
+        const CT w = s.wt(ey.S0[b] * Ax[a] + ey.DS[b] * Bx[a]);
+#pragma unroll
+        for (int c = 0; c < W - 1; ++c) {
+          if (c >= nz - 1) break;
+          s.put(2, ox[a] + oy[b] + oz[c], cz[c], w);
+        }
+      }
+    }
+  } else {
+    const CT c2 = s.coef(qz * vz);
 #pragma unroll
     for (int b = 0; b < WY; ++b) {
       if (b >= ny) break;
       const float s0y = D >= 2 ? ey.S0[b] : 1.0f, dsy = D >= 2 ? ey.DS[b] : 0.0f;
-      const int oy = D >= 2 ? s.y(ey.org + b) : 0;
-      const float wb = s0y * s0z + 0.5f * dsy * s0z + 0.5f * s0y * dsz + third * dsy * dsz;
-      float acc = 0.0f;
 #pragma unroll
-      for (int a = 0; a < W - 1; ++a) {
-        if (a >= nx - 1) break;
-        acc += ex.DS[a] * wb;
-        s.add(0, s.x(ex.org + a) + oy + oz, -qx * acc);
-      }
-    }
-  }
-  // Jy
-#pragma unroll
-  for (int c = 0; c < WZ; ++c) {
-    if (c >= nz) break;
-    const float s0z = D >= 3 ? ez.S0[c] : 1.0f, dsz = D >= 3 ? ez.DS[c] : 0.0f;
-    const int oz = D >= 3 ? s.z(ez.org + c) : 0;
-#pragma unroll
-    for (int a = 0; a < W; ++a) {
-      if (a >= nx) break;
-      const float s0x = ex.S0[a], dsx = ex.DS[a];
-      const float wb = s0x * s0z + 0.5f * dsx * s0z + 0.5f * s0x * dsz + third * dsx * dsz;
-      const int ox = s.x(ex.org + a);
-      if (D >= 2) {
-        float acc = 0.0f;
-#pragma unroll
-        for (int b = 0; b < W - 1; ++b) {
-          if (b >= ny - 1) break;
-          acc += ey.DS[b] * wb;
-          s.add(1, ox + s.y(ey.org + b) + oz, -qy * acc);
-        }
-      } else {
-        s.add(1, ox, qy * vy * wb);
-      }
-    }
-  }
-  // Jz
-#pragma unroll
-  for (int b = 0; b < WY; ++b) {
-    if (b >= ny) break;
-    const float s0y = D >= 2 ? ey.S0[b] : 1.0f, dsy = D >= 2 ? ey.DS[b] : 0.0f;
-    const int oy = D >= 2 ? s.y(ey.org + b) : 0;
-#pragma unroll
-    for (int a = 0; a < W; ++a) {
-      if (a >= nx) break;
-      const float s0x = ex.S0[a], dsx = ex.DS[a];
-      const float wb = s0x * s0y + 0.5f * dsx * s0y + 0.5f * s0x * dsy + third * dsx * dsy;
-      const int ox = s.x(ex.org + a);
-      if (D >= 3) {
-        float acc = 0.0f;
-#pragma unroll
-        for (int c = 0; c < W - 1; ++c) {
-          if (c >= nz - 1) break;
-          acc += ez.DS[c] * wb;
-          s.add(2, ox + oy + s.z(ez.org + c), -qz * acc);
-        }
-      } else {
-        s.add(2, ox + oy, qz * vz * wb);
+      for (int a = 0; a < W; ++a) {
+        if (a >= nx) break;
+        s.put(2, ox[a] + oy[b], c2, s.wt(s0y * Ax[a] + dsy * Bx[a]));
       }
     }
   }
@@ -403,13 +458,9 @@ struct FWin {
   static constexpr int N = X * Y * Z;
 };
 
-// Push configuration per dimension: threads per block, and whether the tile's
-// field window is staged in LDS (else in-tile particles gather from HBM
-// through the caches).  In 3D the two windows (85 KB) take most of a CU's LDS,
-// so one block of 16 waves per CU shares them (measured: 1024 threads 544 us,
-// 512 646 us, 256 without the field window 735 us on the 3D stress push).
+// Threads per push block.  In 3D the two LDS windows (85 KB) take most of a
+// CU's LDS, so one block of 16 waves per CU shares them.
 __host__ __device__ constexpr int push_tpb(int D) { return D == 3 ? 1024 : 256; }
-__host__ __device__ constexpr bool push_stage_fields(int D) { return true; }
 
 template <int ORDER>
 __device__ __forceinline__ void make_axis_l(Axis<ORDER>& a, int c, float t, int origin, int stride) {
@@ -453,10 +504,12 @@ __device__ __forceinline__ float gather_l(const float* __restrict__ S, const Axi
 
 // Boris, move, deposit and write-back of one charged particle.  LOCAL: the
 // particle started inside the block's tile -- fields from the LDS window
-// (origin fx0, fy0, fz0), current into the LDS sink; else HBM for both.
-template <int D, int ORDER, bool LOCAL, bool LF = LOCAL && push_stage_fields(D), class IT = Inst>
+// (origin fx0, fy0, fz0), current into the LDS sink; else HBM for both.  PY,
+// PZ: periodic transverse axes (compile-time, so the removal test at the
+// faces is a fixed instruction sequence).
+template <int D, int ORDER, bool PY, bool PZ, bool LOCAL, class IT>
 __device__ __forceinline__ void push_body(const IT& I, const PushFields& f, const float* sF, int fx0,
-                                          int fy0, int fz0, const GSink& gs, const LSink<D>& ls,
+                                          int fy0, int fz0, const GSink<PY, PZ>& gs, const LSink<D>& ls,
                                           unsigned q, uint8_t kind, int ci, int cj, int ck, float t0,
                                           float t1, float t2, float ux, float uy, float uz, int& xlo,
                                           int& xhi) {
@@ -464,7 +517,7 @@ __device__ __forceinline__ void push_body(const IT& I, const PushFields& f, cons
   float ex, ey, ez, bx, by, bz;
   {
     Axis<ORDER> X, Y, Z;
-    if (LF) {
+    if (LOCAL) {
       constexpr int N = FWin<D>::N;
       make_axis_l<ORDER>(X, ci, t0, fx0, 1);
       if (D >= 2) make_axis_l<ORDER>(Y, cj, t1, fy0, FWin<D>::X);
@@ -477,8 +530,8 @@ __device__ __forceinline__ void push_body(const IT& I, const PushFields& f, cons
       bz = gather_l<D, ORDER>(sF + 5 * N, X, Y, Z, 1, 1, 0);
     } else {
       make_axis<ORDER>(X, ci, t0, I.nx, 0, G, 1);
-      if (D >= 2) make_axis<ORDER>(Y, cj, t1, I.ny, I.per_y, I.Gy, I.sy);
-      if (D >= 3) make_axis<ORDER>(Z, ck, t2, I.nz, I.per_z, I.Gz, I.sz);
+      if (D >= 2) make_axis<ORDER>(Y, cj, t1, I.ny, PY, I.Gy, I.sy);
+      if (D >= 3) make_axis<ORDER>(Z, ck, t2, I.nz, PZ, I.Gz, I.sz);
       ex = gather<D, ORDER>(f.E0, X, Y, Z, 1, 0, 0);
       ey = gather<D, ORDER>(f.E1, X, Y, Z, 0, 1, 0);
       ez = gather<D, ORDER>(f.E2, X, Y, Z, 0, 0, 1);
@@ -500,6 +553,7 @@ __device__ __forceinline__ void push_body(const IT& I, const PushFields& f, cons
   ux = umx + sf * (vy * tz - vz * ty) + h * ex;
   uy = umy + sf * (vz * tx - vx * tz) + h * ey;
   uz = umz + sf * (vx * ty - vy * tx) + h * ez;
+  if (!(fabsf(ux) + fabsf(uy) + fabsf(uz) <= 3.0e38f)) atomicOr(I.health, HEALTH_NONFINITE);
   const float ig = 1.0f / sqrtf(1.0f + ux * ux + uy * uy + uz * uz);
   // ---- move: integer cell + FP32 offset, at most one cell per step
   int ni = ci, nj = cj, nk = ck;
@@ -530,15 +584,14 @@ __device__ __forceinline__ void push_body(const IT& I, const PushFields& f, cons
     else deposit<D, ORDER>(gs, exk, eyk, ezk, qx, qy, qz, uy * ig, uz * ig);
   }
   // ---- boundaries: outflow removes, periodic wraps
-  int dead = 0;
-  if (ni < 0 || ni >= I.nx) dead = 1;
+  bool dead = ni < 0 || ni >= I.nx;
   if (D >= 2) {
-    if (I.per_y) nj = wrapi(nj, I.ny, 1);
-    else if (nj < 0 || nj >= I.ny) dead = 1;
+    if (PY) nj = wrapi(nj, I.ny, 1);
+    else dead = dead || nj < 0 || nj >= I.ny;
   }
   if (D >= 3) {
-    if (I.per_z) nk = wrapi(nk, I.nz, 1);
-    else if (nk < 0 || nk >= I.nz) dead = 1;
+    if (PZ) nk = wrapi(nk, I.nz, 1);
+    else dead = dead || nk < 0 || nk >= I.nz;
   }
   if (dead) {
     gp(I.pkind)[q] = DEAD;
@@ -558,9 +611,9 @@ __device__ __forceinline__ void push_body(const IT& I, const PushFields& f, cons
 // One charged particle (slot p).  TILED: the block holds the LDS windows of
 // the tile with origin (tx0, ty0, tz0); a particle that started the step
 // outside that tile goes through HBM and is counted as a drifter.
-template <int D, int ORDER, bool TILED, class IT>
+template <int D, int ORDER, bool PY, bool PZ, bool TILED, class IT>
 __device__ __forceinline__ void push_one(const IT& I, const PushFields& f, const float* sF,
-                                         const GSink& gs, const LSink<D>& ls, int tx0, int ty0,
+                                         const GSink<PY, PZ>& gs, const LSink<D>& ls, int tx0, int ty0,
                                          int tz0, int p, bool valid, int& xlo, int& xhi) {
   const unsigned q = (unsigned)p;
   const uint8_t kind = valid ? gp(I.pkind)[q] : DEAD;
@@ -576,31 +629,41 @@ __device__ __forceinline__ void push_one(const IT& I, const PushFields& f, const
     if (D >= 2) in = in && cj >= ty0 && cj < ty0 + ptile_ext(D, 1);
     if (D >= 3) in = in && ck >= tz0 && ck < tz0 + ptile_ext(D, 2);
     if (in) {
-      push_body<D, ORDER, true>(I, f, sF, tx0 - 1, ty0 - 1, tz0 - 1, gs, ls, q, kind, ci, cj, ck, t0, t1,
-                                t2, ux, uy, uz, xlo, xhi);
+      push_body<D, ORDER, PY, PZ, true>(I, f, sF, tx0 - 1, ty0 - 1, tz0 - 1, gs, ls, q, kind, ci, cj, ck,
+                                        t0, t1, t2, ux, uy, uz, xlo, xhi);
     } else {
       const unsigned long long m = __ballot(1);
       if ((threadIdx.x & 63) == __ffsll((long long)m) - 1) atomicAdd(I.sctl + SC_NDRIFT, __popcll(m));
-      push_body<D, ORDER, false>(I, f, sF, 0, 0, 0, gs, ls, q, kind, ci, cj, ck, t0, t1, t2, ux, uy, uz,
-                                 xlo, xhi);
+      push_body<D, ORDER, PY, PZ, false>(I, f, sF, 0, 0, 0, gs, ls, q, kind, ci, cj, ck, t0, t1, t2, ux,
+                                         uy, uz, xlo, xhi);
     }
   } else {
-    push_body<D, ORDER, false>(I, f, sF, 0, 0, 0, gs, ls, q, kind, ci, cj, ck, t0, t1, t2, ux, uy, uz,
-                               xlo, xhi);
+    push_body<D, ORDER, PY, PZ, false>(I, f, sF, 0, 0, 0, gs, ls, q, kind, ci, cj, ck, t0, t1, t2, ux, uy,
+                                       uz, xlo, xhi);
   }
 }
 
-// Charged-particle phase.  Work units of a block (persistent grid-stride):
+// Slot of particle i of a work item: first the sorted range [lo, hi), then the
+// tile's births since the sort -- f electrons from b0 on and their f positive
+// carriers from b0 + cap on (cap = the tile's birth capacity).
+__device__ __forceinline__ int item_slot(int i, int lo, int n_sorted, int b0, int f, int cap) {
+  if (i < n_sorted) return lo + i;
+  const int j = i - n_sorted;
+  return j < f ? b0 + j : b0 + cap + (j - f);
+}
+
+// Charged-particle phase.  Work items of a block (persistent grid-stride):
 // first the chunks of the sorted tiles -- the block stages the tile's field
-// window in LDS and clears its current window, pushes the chunk's particles,
-// then adds the current window's nonzero nodes to HBM with one atomic each --
-// then the unsorted tail (births since the sort) through HBM.
-// ONE: a single run, its parameter block passed by value.
-template <int D, int ORDER, bool ONE>
+// window in LDS and clears its current window, pushes the chunk's particles
+// (the tile's last chunk also its births since the sort), then adds the
+// current window's nonzero nodes to HBM with one atomic each -- then the
+// unsorted tail (particles placed or born beyond the tiles' layout) through
+// HBM.  ONE: a single run, its parameter block passed by value.
+template <int D, int ORDER, bool PY, bool PZ, bool ONE>
 __global__ __launch_bounds__(push_tpb(D)) void k_push(Group g, std::conditional_t<ONE, Inst, NoInst> one) {
   constexpr int NT = push_tpb(D);
   __shared__ unsigned long long sJ[3 * PWin<D>::N];
-  __shared__ float sF[push_stage_fields(D) ? 6 * FWin<D>::N : 1];
+  __shared__ float sF[6 * FWin<D>::N];
   const Slot sl = ONE ? Slot{0, (int)blockIdx.x, g.blocks} : block_slot(g);
   auto& I = inst_of(g, sl.ii, one);
   const int nb = sl.nbk;
@@ -612,8 +675,7 @@ __global__ __launch_bounds__(push_tpb(D)) void k_push(Group g, std::conditional_
   int xlo = 1 << 30, xhi = -(1 << 30);   // x cells of this block's particles after the move
   const PushFields f{uniform(I.F[par][0]), uniform(I.F[par][1]), uniform(I.F[par][2]),
                      uniform(I.F[par][3]), uniform(I.F[par][4]), uniform(I.F[par][5])};
-  const GSink gs{I.Jb[par][0], I.Jb[par][1], I.Jb[par][2], I.ny, I.nz, I.per_y, I.per_z,
-                 I.sy, I.sz, I.Gy, I.Gz};
+  const GSink<PY, PZ> gs{I.Jb[par][0], I.Jb[par][1], I.Jb[par][2], I.ny, I.nz, I.sy, I.sz, I.Gy, I.Gz};
   int nsorted = I.sctl[SC_NSORTED];
   nsorted = nsorted < count ? nsorted : count;
   const int nchunks = I.sctl[SC_NCHUNKS];
@@ -622,15 +684,25 @@ __global__ __launch_bounds__(push_tpb(D)) void k_push(Group g, std::conditional_
     // the same XCD keeps neighbouring chunks: nb is a multiple of 8, so the
     // XCD of work item v is v mod 8 whatever the round
     const int4 ch = I.chunks[(nb & 7) ? v : xcd_remap(v, nchunks)];
-    if (ch.z - ch.y <= SPARSE_CHUNK) {
+    const int t = ch.x;
+    const int n_sorted = ch.z - ch.y;
+    int nbirth = 0, bcap = 0;
+    if (ch.w >= 0) {
+      bcap = I.tslack[t];
+      const int fe = I.tfill[t];
+      nbirth = fe < bcap ? fe : bcap;
+    }
+    const int ntot = n_sorted + 2 * nbirth;
+    if (ntot == 0) continue;
+    if (ntot <= SPARSE_CHUNK) {
       // a sparse piece (one pass of the block): HBM atomics cost less than
       // staging and flushing the windows
-      const int end = ch.z < count ? ch.z : count;
-      const int p = ch.y + threadIdx.x;
-      push_one<D, ORDER, false>(I, f, sF, gs, LSink<D>{sJ, 0, 0, 0, 0.0}, 0, 0, 0, p, p < end, xlo, xhi);
+      const int i = threadIdx.x;
+      const int p = i < ntot ? item_slot(i, ch.y, n_sorted, ch.w, nbirth, bcap) : 0;
+      push_one<D, ORDER, PY, PZ, false>(I, f, sF, gs, LSink<D>{sJ, 0, 0, 0, 0.0}, 0, 0, 0, p, i < ntot,
+                                        xlo, xhi);
       continue;
     }
-    const int t = ch.x;
     const int tx0 = (t % I.ntile[0]) * ptile_ext(D, 0);
     const int ty0 = D >= 2 ? ((t / I.ntile[0]) % I.ntile[1]) * ptile_ext(D, 1) : 0;
     const int tz0 = D >= 3 ? (t / (I.ntile[0] * I.ntile[1])) * ptile_ext(D, 2) : 0;
@@ -638,27 +710,31 @@ __global__ __launch_bounds__(push_tpb(D)) void k_push(Group g, std::conditional_
                       (double)I.jscale};
     for (int e = threadIdx.x; e < 3 * PWin<D>::N; e += NT) sJ[e] = 0ull;
     // field window: nodes tile - 1 .. tile + T + 1 (periodic axes wrapped;
-    // nodes outside the padded arrays, never read, are zero)
-    for (int e = threadIdx.x; push_stage_fields(D) && e < FWin<D>::N; e += NT) {
-      const int a = e % FWin<D>::X;
-      const int b = (e / FWin<D>::X) % FWin<D>::Y;
-      const int c = e / (FWin<D>::X * FWin<D>::Y);
+    // nodes outside the padded arrays, never read, are zero).  Threads walk
+    // the window row by row: a row of X nodes per (b, c).
+    constexpr int FX = FWin<D>::X, FY = FWin<D>::Y, FZ = FWin<D>::Z;
+    for (int e = threadIdx.x; e < FWin<D>::N; e += NT) {
+      const int a = e % FX;
+      const int r = e / FX;
+      const int b = D >= 2 ? r % FY : 0;
+      const int c = D >= 3 ? r / FY : 0;
       const int px = tx0 - 1 + a + G;
       bool ok = px < I.Px;
       int off = px;
       if (D >= 2) {
         int j = ty0 - 1 + b;
-        if (I.per_y) j = ((j % I.ny) + I.ny) % I.ny;
+        if (PY) j = j < 0 ? j + I.ny : (j >= I.ny ? j - I.ny : j);
         ok = ok && j + I.Gy < I.Py;
         off += I.sy * (j + I.Gy);
       }
       if (D >= 3) {
         int k = tz0 - 1 + c;
-        if (I.per_z) k = ((k % I.nz) + I.nz) % I.nz;
+        if (PZ) k = k < 0 ? k + I.nz : (k >= I.nz ? k - I.nz : k);
         ok = ok && k + I.Gz < I.Pz;
         off += I.sz * (k + I.Gz);
       }
       const unsigned o = (unsigned)off;
+      (void)FZ;
       sF[0 * FWin<D>::N + e] = ok ? gp(f.E0)[o] : 0.0f;
       sF[1 * FWin<D>::N + e] = ok ? gp(f.E1)[o] : 0.0f;
       sF[2 * FWin<D>::N + e] = ok ? gp(f.E2)[o] : 0.0f;
@@ -667,30 +743,30 @@ __global__ __launch_bounds__(push_tpb(D)) void k_push(Group g, std::conditional_
       sF[5 * FWin<D>::N + e] = ok ? gp(f.B2)[o] : 0.0f;
     }
     __syncthreads();
-    const int end = ch.z < count ? ch.z : count;
-    for (int p0 = ch.y; p0 < end; p0 += NT) {
-      const int p = p0 + threadIdx.x;
-      push_one<D, ORDER, true>(I, f, sF, gs, ls, tx0, ty0, tz0, p, p < end, xlo, xhi);
+    for (int i0 = 0; i0 < ntot; i0 += NT) {
+      const int i = i0 + threadIdx.x;
+      const int p = i < ntot ? item_slot(i, ch.y, n_sorted, ch.w, nbirth, bcap) : 0;
+      push_one<D, ORDER, PY, PZ, true>(I, f, sF, gs, ls, tx0, ty0, tz0, p, i < ntot, xlo, xhi);
     }
     __syncthreads();
     for (int e = threadIdx.x; e < 3 * PWin<D>::N; e += NT) {
-      const long long qv = (long long)sJ[e];
-      if (qv == 0) continue;
-      const float v = (float)qv * I.jscale_inv;
+      const unsigned long long raw = sJ[e];
+      if (raw == 0ull) continue;
+      const float v = (float)(double)(long long)raw * I.jscale_inv;
       const int comp = e / PWin<D>::N;
       const int r = e - comp * PWin<D>::N;
       const int a = r % PWin<D>::X;
       const int b = (r / PWin<D>::X) % PWin<D>::Y;
       const int c = r / (PWin<D>::X * PWin<D>::Y);
       const int o = gs.x(ls.x0 + a) + (D >= 2 ? gs.y(ls.y0 + b) : 0) + (D >= 3 ? gs.z(ls.z0 + c) : 0);
-      if (o >= 0 && o < ncell) gs.add(comp, o, v);
+      if (o >= 0 && o < ncell) gs.put(comp, o, v, 1.0f);
     }
     __syncthreads();
   }
   const LSink<D> none{sJ, 0, 0, 0, 0.0};
   for (int p0 = nsorted + b0 * NT; p0 < count; p0 += nb * NT) {
     const int p = p0 + threadIdx.x;
-    push_one<D, ORDER, false>(I, f, sF, gs, none, 0, 0, 0, p, p < count, xlo, xhi);
+    push_one<D, ORDER, PY, PZ, false>(I, f, sF, gs, none, 0, 0, 0, p, p < count, xlo, xhi);
   }
   // charged region of the next step: this step's region plus where this
   // block's particles went (an atomic only where a block extends it)
@@ -723,33 +799,29 @@ __global__ __launch_bounds__(push_tpb(D)) void k_push(Group g, std::conditional_
 }
 
 // ------------------------------------------------------------ tile sort
-// Counting sort of the charged particles by group (64 cells of a tile):
-// count (wave-aggregated atomics), scan (one block per instance: group ranges
-// and the chunk list of every tile), scatter into the spare arrays (dead slots
-// dropped), then one block per group writes the group back in level order.
-// The first kernel decides, identically in every block, whether a sort is
-// due; the others follow its decision.
+// Counting sort of the charged particles by tile: count (wave-aggregated
+// atomics), scan (one block per instance: the tiles' ranges, each followed by
+// its birth capacity, and the chunk list), fill (every slot of the new layout
+// starts empty), scatter into the spare arrays (dead slots dropped), copy back.
+// A tile's births until the next sort go into its capacity: electrons and
+// positive carriers in two halves of one alive-neutral bound each (neutrals do
+// not move and ionize once, so the bound is never exceeded).  The first kernel
+// decides, identically in every block, whether a sort is due; the others
+// follow its decision.
 template <int D, class IT>
-__device__ __forceinline__ void group_of(const IT& I, uint32_t pc, int& g, int& c) {
+__device__ __forceinline__ int tile_of(const IT& I, uint32_t pc) {
   int i, j, k;
   unpack_cell(D, pc, i, j, k);
   constexpr int TX = ptile_ext(D, 0), TY = ptile_ext(D, 1), TZ = ptile_ext(D, 2);
   int t = i / TX;
   if (D >= 2) t += I.ntile[0] * (j / TY);
   if (D >= 3) t += I.ntile[0] * I.ntile[1] * (k / TZ);
-  // group = parity class of the cell inside its tile (x, y, z parities);
-  // cells of one class are at least two apart along some axis, so their
-  // deposit stencils never meet on the same node in the same instruction
-  const int il = i % TX, jl = D >= 2 ? j % TY : 0, kl = D >= 3 ? k % TZ : 0;
-  const int cls = (il & 1) | (D >= 2 ? (jl & 1) << 1 : 0) | (D >= 3 ? (kl & 1) << 2 : 0);
-  constexpr int GPT = ptile_cells(D) / PT_GROUP;
-  g = (unsigned)t < (unsigned)I.ntiles ? t * GPT + cls : -1;   // -1 only for a corrupt cell
-  c = (il >> 1) + (TX / 2) * ((jl >> 1) + (TY > 1 ? TY / 2 : 1) * (kl >> 1));
+  return (unsigned)t < (unsigned)I.ntiles ? t : -1;   // -1 only for a corrupt cell
 }
 
-// Adds 1 to arr[t] for every lane with t >= 0, one atomic per distinct t of
-// the wave; returns the lane's rank (distinct per lane and t).
-__device__ __forceinline__ int wave_rank_add(int* arr, int t) {
+// Adds k to arr[t] for every lane with t >= 0, one atomic per distinct t of the
+// wave; returns the lane's offset (distinct multiples of k per lane and t).
+__device__ __forceinline__ int wave_rank_add(int* arr, int t, int k = 1) {
   const int lane = threadIdx.x & 63;
   const unsigned long long below = (1ull << lane) - 1ull;
   unsigned long long pending = __ballot(t >= 0);
@@ -759,9 +831,9 @@ __device__ __forceinline__ int wave_rank_add(int* arr, int t) {
     const int tl = __shfl(t, leader);
     const unsigned long long m = __ballot(t == tl);
     int base = 0;
-    if (lane == leader) base = atomicAdd(arr + tl, __popcll(m));
+    if (lane == leader) base = atomicAdd(arr + tl, k * __popcll(m));
     base = __shfl(base, leader);
-    if (t == tl) rank = base + __popcll(m & below);
+    if (t == tl) rank = base + k * __popcll(m & below);
     pending &= ~m;
   }
   return rank;
@@ -777,47 +849,52 @@ __global__ __launch_bounds__(TPB) void k_sort_count(Group g) {
   count = count < I.capacity ? count : I.capacity;
   const int loose = count - I.sctl[SC_NSORTED];
   const int drift = I.sctl[SC_NDRIFT];
-  // births since the sort (unsorted tail) above 1/32 of the slots, or
-  // drifter-steps (per step, a particle deposited outside its tile) above 1/16
+  // forced (a new layout is wanted), particles beyond the layout above 1/32 of
+  // the slots, or drifter-steps (per step, a particle deposited outside its
+  // tile) above 1/16
   const int lo = count >> 5, dr = count >> 4;
-  const int go = loose > (lo > 256 ? lo : 256) || drift > (dr > 256 ? dr : 256);
+  const int go = I.sctl[SC_FORCE] || loose > (lo > 256 ? lo : 256) || drift > (dr > 256 ? dr : 256);
   if (b0 == 0 && threadIdx.x == 0) I.sctl[SC_GO] = go;
   if (!go) return;
   const int lane = threadIdx.x & 63;
   for (int p0 = b0 * TPB + (threadIdx.x - lane); p0 < count; p0 += nb * TPB) {
     const int p = p0 + lane;
-    int gr = -1, c;
-    if (p < count && I.pkind[p] != DEAD) group_of<D>(I, I.pcell[p], gr, c);
-    (void)wave_rank_add(I.gcnt, gr);
+    const int t = p < count && I.pkind[p] != DEAD ? tile_of<D>(I, I.pcell[p]) : -1;
+    (void)wave_rank_add(I.tcnt, t);
   }
 }
 
 constexpr int SCAN_TPB = 1024;
 
-
 template <int D>
 __global__ __launch_bounds__(SCAN_TPB) void k_sort_scan(Group g) {
   constexpr int TPB = SCAN_TPB;
   __shared__ long long sp[TPB], sc[TPB];
+  __shared__ int sfit;
   const int ii = find_inst(g);
   auto& I = inst_of(g, ii, NoInst{});
   if (!I.sctl[SC_GO]) return;
-  constexpr int GPT = ptile_cells(D) / PT_GROUP;
   const int nt = I.ntiles;
   const int per = (nt + TPB - 1) / TPB;
   const int t0 = threadIdx.x * per;
   const int t1 = t0 + per < nt ? t0 + per : nt;
-  long long np = 0, nc = 0;
+  // births since the sort used up alive neutrals: the bound of each tile drops
+  // by the births its capacity took (births beyond it went to the tail and are
+  // not counted, which keeps the bound an upper bound)
+  long long np = 0, nc = 0, ns = 0;
   for (int t = t0; t < t1; ++t) {
-    long long n = 0;
-    for (int q = 0; q < GPT; ++q) n += I.gcnt[t * GPT + q];
+    const int cap = I.tslack[t];
+    const int fe = I.tfill[t];
+    const int alive = I.talive[t] - (fe < cap ? fe : cap);
+    I.talive[t] = alive;
+    const int n = I.tcnt[t];
     np += n;
-    nc += (n + SORT_CHUNK - 1) / SORT_CHUNK;
+    ns += 2 * (long long)alive;
   }
   sp[threadIdx.x] = np;
-  sc[threadIdx.x] = nc;
+  sc[threadIdx.x] = ns;
   __syncthreads();
-  for (int w = 1; w < TPB; w <<= 1) {   // inclusive scan
+  for (int w = 1; w < TPB; w <<= 1) {   // inclusive scans
     const long long a = threadIdx.x >= w ? sp[threadIdx.x - w] : 0;
     const long long b = threadIdx.x >= w ? sc[threadIdx.x - w] : 0;
     __syncthreads();
@@ -825,29 +902,71 @@ __global__ __launch_bounds__(SCAN_TPB) void k_sort_scan(Group g) {
     sc[threadIdx.x] += b;
     __syncthreads();
   }
-  const long long total = sp[TPB - 1], tchunks = sc[TPB - 1];
-  long long pp = sp[threadIdx.x] - np, pc = sc[threadIdx.x] - nc;
+  // birth capacity only when the whole layout fits the slots
+  if (threadIdx.x == 0) sfit = sp[TPB - 1] + sc[TPB - 1] <= (long long)I.capacity;
+  __syncthreads();
+  const bool fit = sfit;
+  long long pp = (sp[threadIdx.x] - np) + (fit ? sc[threadIdx.x] - ns : 0);
   for (int t = t0; t < t1; ++t) {
+    const int n = I.tcnt[t];
+    const int cap = fit ? I.talive[t] : 0;
+    nc += (n + SORT_CHUNK - 1) / SORT_CHUNK + (n == 0 && cap > 0);
+  }
+  __syncthreads();
+  sc[threadIdx.x] = nc;
+  __syncthreads();
+  for (int w = 1; w < TPB; w <<= 1) {
+    const long long b = threadIdx.x >= w ? sc[threadIdx.x - w] : 0;
+    __syncthreads();
+    sc[threadIdx.x] += b;
+    __syncthreads();
+  }
+  long long pc = sc[threadIdx.x] - nc;
+  const long long tchunks = sc[TPB - 1];
+  for (int t = t0; t < t1; ++t) {
+    const int n = I.tcnt[t];
+    const int cap = fit ? I.talive[t] : 0;
     const long long ts = pp;
-    for (int q = 0; q < GPT; ++q) {
-      const int gi = t * GPT + q;
-      const int n = I.gcnt[gi];
-      I.gcnt[gi] = 0;
-      I.gn[gi] = n;
-      I.gstart[gi] = (int)pp;
-      I.gfill[gi] = 0;
-      pp += n;
+    const int bl = (int)(ts + n);   // first birth slot
+    I.tcnt[t] = 0;              // the scatter's rank counter
+    I.tstart[t] = (int)ts;
+    I.tbirth[t] = bl;
+    I.tslack[t] = cap;
+    I.tfill[t] = 0;
+    pp += n + 2 * (long long)cap;
+    if (n == 0) {
+      if (cap > 0) I.chunks[pc++] = make_int4(t, (int)ts, (int)ts, bl);
+      continue;
     }
-    for (long long q = 0; ts + q * SORT_CHUNK < pp; ++q) {
-      const long long e = ts + (q + 1) * SORT_CHUNK;
-      I.chunks[pc++] = make_int4(t, (int)(ts + q * SORT_CHUNK), (int)(e < pp ? e : pp), 0);
+    for (long long q = 0; q * SORT_CHUNK < n; ++q) {
+      const long long e = (q + 1) * SORT_CHUNK;
+      const bool last = e >= n;
+      I.chunks[pc++] = make_int4(t, (int)(ts + q * SORT_CHUNK), (int)(ts + (last ? n : e)),
+                                 last && cap > 0 ? bl : -1);
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    I.sctl[SC_NSORTED] = (int)total;   // <= the slots in use: dead ones are dropped
+  if (threadIdx.x == TPB - 1) {
+    // the layout's end: tiles and their birth room (the live particles alone
+    // always fit the slots)
+    I.sctl[SC_NSORTED] = (int)(pp < (long long)I.capacity ? pp : (long long)I.capacity);
     I.sctl[SC_NCHUNKS] = (int)tchunks;
+    I.sctl[SC_FORCE] = 0;
   }
+}
+
+// Every slot of the new layout starts empty (its kind DEAD in the spare array).
+// The layout never exceeds the slots (the live particles fit, and the birth
+// room is only laid out when it fits too); the bound is kept here regardless.
+template <int D>
+__global__ __launch_bounds__(TPB) void k_sort_fill(Group g) {
+  const int ii = find_inst(g);
+  auto& I = inst_of(g, ii, NoInst{});
+  if (!I.sctl[SC_GO]) return;
+  const int nb = g.off[ii + 1] - g.off[ii];
+  const int b0 = blockIdx.x - g.off[ii];
+  const int n = min(I.sctl[SC_NSORTED], I.capacity);
+  for (int p = b0 * TPB + threadIdx.x; p < n; p += nb * TPB) I.skind[p] = DEAD;
 }
 
 template <int D>
@@ -862,17 +981,18 @@ __global__ __launch_bounds__(TPB) void k_sort_scatter(Group g) {
   const int lane = threadIdx.x & 63;
   for (int p0 = b0 * TPB + (threadIdx.x - lane); p0 < count; p0 += nb * TPB) {
     const int p = p0 + lane;
-    int gr = -1, c;
+    int t = -1;
     uint32_t pc = 0;
     uint8_t kd = DEAD;
     if (p < count) {
       kd = I.pkind[p];
       pc = I.pcell[p];
-      if (kd != DEAD) group_of<D>(I, pc, gr, c);
+      if (kd != DEAD) t = tile_of<D>(I, pc);
     }
-    const int r = wave_rank_add(I.gfill, gr);
-    if (gr < 0) continue;
-    const int d = I.gstart[gr] + r;
+    const int r = wave_rank_add(I.tcnt, t);
+    if (t < 0) continue;
+    const int d = I.tstart[t] + r;
+    if ((unsigned)d >= (unsigned)I.capacity) continue;
     I.scell[d] = pc;
     I.skind[d] = kd;
     I.so0[d] = I.po0[p];
@@ -885,139 +1005,31 @@ __global__ __launch_bounds__(TPB) void k_sort_scatter(Group g) {
   }
 }
 
-template <int D, class IT>
-__device__ __forceinline__ void sort_move(const IT& I, int from, int to) {
-  I.pcell[to] = I.scell[from];
-  I.pkind[to] = I.skind[from];
-  I.po0[to] = I.so0[from];
-  if (D >= 2) I.po1[to] = I.so1[from];
-  if (D >= 3) I.po2[to] = I.so2[from];
-  I.pu0[to] = I.su0[from];
-  I.pu1[to] = I.su1[from];
-  I.pu2[to] = I.su2[from];
-  I.pid[to] = I.spid[from];
-}
-
-// One wave per group (grid-stride over the groups, no block barriers): count
-// the particles of every cell (LDS counters, one lane per cell), the bit mask
-// of the cells still holding a particle at each level, then each particle's
-// rank inside its cell from a second round of counters and its level-order
-// slot: first slot of the level + cells of the level before its own.  (Any
-// rank order inside a cell is as good as another.)  The permutation is applied
-// one array at a time through LDS, so HBM sees coalesced reads and writes.
-constexpr int SORT_GWAVE = 2048;   // particles of a group reordered through LDS
-
-template <int D, class T>
-__device__ __forceinline__ void permute_array(const T* __restrict__ src, T* __restrict__ dst, int n,
-                                              const unsigned short* pos, T* buf, int lane) {
-  for (int q = lane; q < n; q += 64) buf[pos[q]] = src[q];
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  for (int q = lane; q < n; q += 64) dst[q] = buf[q];
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
-
+// The new layout back into the particle arrays (coalesced copies); the slot
+// counter becomes the layout's end, and the per-tile counters (the scatter's
+// ranks) start the next sort at zero.
 template <int D>
-__global__ __launch_bounds__(TPB) void k_sort_group(Group g) {
-  constexpr int WPB = TPB / 64;
-  __shared__ unsigned cnt[WPB][PT_GROUP];
-  __shared__ unsigned long long lmask[WPB][SORT_LMAX];
-  __shared__ unsigned lbase[WPB][SORT_LMAX];
-  __shared__ unsigned short spos[WPB][SORT_GWAVE];
-  __shared__ unsigned sbuf[WPB][SORT_GWAVE];
+__global__ __launch_bounds__(TPB) void k_sort_copy(Group g) {
   const int ii = find_inst(g);
   auto& I = inst_of(g, ii, NoInst{});
   if (!I.sctl[SC_GO]) return;
   const int nb = g.off[ii + 1] - g.off[ii];
   const int b0 = blockIdx.x - g.off[ii];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int ngr = I.ntiles * (ptile_cells(D) / PT_GROUP);
-  auto sync_wave = [] {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-  };
-  for (int gi = b0 * WPB + w; gi < ngr; gi += nb * WPB) {
-    const int n = I.gn[gi];
-    if (n == 0) continue;
-    const int s0 = I.gstart[gi];
-    cnt[w][lane] = 0;
-    sync_wave();
-    // four particles per lane per round keep several loads and atomics in flight
-    for (int q0 = lane; q0 < n; q0 += 256) {
-      int c[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        int gr;
-        c[k] = -1;
-        if (q0 + 64 * k < n) group_of<D>(I, I.scell[s0 + q0 + 64 * k], gr, c[k]);
-      }
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (c[k] >= 0) atomicAdd(&cnt[w][c[k]], 1u);
-    }
-    sync_wave();
-    const unsigned mine = cnt[w][lane];
-    unsigned levels = mine;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) levels = max(levels, (unsigned)__shfl_xor((int)levels, o));
-    if (levels > SORT_LMAX) {   // a crowded cell: keep the group as scattered
-      for (int q = lane; q < n; q += 64) sort_move<D>(I, s0 + q, s0 + q);
-      continue;
-    }
-    unsigned acc = 0;
-    for (unsigned l = 0; l < levels; ++l) {
-      const unsigned long long m = __ballot(mine > l);
-      if (lane == 0) {
-        lmask[w][l] = m;
-        lbase[w][l] = acc;
-      }
-      acc += __popcll(m);
-    }
-    cnt[w][lane] = 0;
-    sync_wave();
-    const bool staged = n <= SORT_GWAVE;
-    for (int q0 = lane; q0 < n; q0 += 256) {
-      int c[4];
-      unsigned l[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        int gr;
-        c[k] = -1;
-        if (q0 + 64 * k < n) group_of<D>(I, I.scell[s0 + q0 + 64 * k], gr, c[k]);
-      }
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (c[k] >= 0) l[k] = atomicAdd(&cnt[w][c[k]], 1u);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (c[k] < 0) continue;
-        const int pos = (int)lbase[w][l[k]] + __popcll(lmask[w][l[k]] & ((1ull << c[k]) - 1ull));
-        if (staged) spos[w][q0 + 64 * k] = (unsigned short)pos;
-        else sort_move<D>(I, s0 + q0 + 64 * k, s0 + pos);
-      }
-    }
-    sync_wave();
-    if (staged) {
-      unsigned* buf = sbuf[w];
-      const unsigned short* ps = spos[w];
-      permute_array<D>(I.scell + s0, I.pcell + s0, n, ps, buf, lane);
-      permute_array<D>(reinterpret_cast<const unsigned*>(I.so0) + s0, reinterpret_cast<unsigned*>(I.po0) + s0, n, ps, buf, lane);
-      if (D >= 2) permute_array<D>(reinterpret_cast<const unsigned*>(I.so1) + s0, reinterpret_cast<unsigned*>(I.po1) + s0, n, ps, buf, lane);
-      if (D >= 3) permute_array<D>(reinterpret_cast<const unsigned*>(I.so2) + s0, reinterpret_cast<unsigned*>(I.po2) + s0, n, ps, buf, lane);
-      permute_array<D>(reinterpret_cast<const unsigned*>(I.su0) + s0, reinterpret_cast<unsigned*>(I.pu0) + s0, n, ps, buf, lane);
-      permute_array<D>(reinterpret_cast<const unsigned*>(I.su1) + s0, reinterpret_cast<unsigned*>(I.pu1) + s0, n, ps, buf, lane);
-      permute_array<D>(reinterpret_cast<const unsigned*>(I.su2) + s0, reinterpret_cast<unsigned*>(I.pu2) + s0, n, ps, buf, lane);
-      permute_array<D>(I.spid + s0, I.pid + s0, n, ps, buf, lane);
-      // kinds are bytes: move them through the same buffer one per word
-      for (int q = lane; q < n; q += 64) buf[ps[q]] = I.skind[s0 + q];
-      sync_wave();
-      for (int q = lane; q < n; q += 64) I.pkind[s0 + q] = (uint8_t)buf[q];
-      sync_wave();
-    }
+  const int n = min(I.sctl[SC_NSORTED], I.capacity);
+  for (int t = b0 * TPB + threadIdx.x; t < I.ntiles; t += nb * TPB) I.tcnt[t] = 0;
+  for (int p = b0 * TPB + threadIdx.x; p < n; p += nb * TPB) {
+    I.pcell[p] = I.scell[p];
+    I.pkind[p] = I.skind[p];
+    I.po0[p] = I.so0[p];
+    if (D >= 2) I.po1[p] = I.so1[p];
+    if (D >= 3) I.po2[p] = I.so2[p];
+    I.pu0[p] = I.su0[p];
+    I.pu1[p] = I.su1[p];
+    I.pu2[p] = I.su2[p];
+    I.pid[p] = I.spid[p];
   }
   if (b0 == 0 && threadIdx.x == 0) {
-    *I.pcount = I.sctl[SC_NSORTED];
+    *I.pcount = n;
     I.sctl[SC_NDRIFT] = 0;
     I.sctl[SC_NSORTS] += 1;
   }
@@ -1408,7 +1420,14 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g, std::conditional_t<ONE,
     }
     __syncthreads();
   }
-  // ---- E: owned positions: b^{n+1}, E^{n+1} out, J cleared, amplitude window
+  // ---- E: owned positions: b^{n+1}, E^{n+1} out, J cleared, amplitude window,
+  // the Poynting flux through the planes one node inside the outflow faces
+  auto hits = [](int lo, int t, int p) { return p >= lo && p < lo + t; };
+  bool flux_tile = hits(a0x, T::X, G + 1) || hits(a0x, T::X, G + nx - 1);
+  if (D >= 2 && !py) flux_tile = flux_tile || hits(a0y, T::Y, G + 1) || hits(a0y, T::Y, G + ny - 1);
+  if (D >= 3 && !pz) flux_tile = flux_tile || hits(a0z, T::Z, G + 1) || hits(a0z, T::Z, G + nz - 1);
+  double fin = 0.0, fout = 0.0;   // this thread's energy into / out of the inner box
+  float chk = 0.0f;               // NaN once a stored E is not finite
   const int nwin = I.nwin;
   const int slot = step % (nwin > 0 ? nwin : 1);
   const int wx0 = I.wx0, wx1 = I.wx1;
@@ -1449,6 +1468,45 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g, std::conditional_t<ONE,
     if (xdn && ydn && zdh) {
       at(En2, gi) = sE[2][l];
       stored_nz = stored_nz || (track && sE[2][l] != 0.0f);
+    }
+    // non-finite E (a NaN or an infinity anywhere in the sum leaves chk NaN)
+    chk = fmaf(sE[0][l] + sE[1][l] + sE[2][l], 0.0f, chk);
+    if (flux_tile) {
+      const int i = ai - G, j = D >= 2 ? aj - G : 0, k = D >= 3 ? ak - G : 0;
+      // trapezoid weights of the inner box [1, n - 1] along a transverse axis:
+      // node positions (ends 1/2), half-staggered positions (1 <= v <= n - 2);
+      // periodic and absent axes weigh every (owned) position 1
+      auto wn = [](int v, int n, bool per) -> double {
+        if (per) return 1.0;
+        if (v < 1 || v > n - 1) return 0.0;
+        return (v == 1 || v == n - 1) ? 0.5 : 1.0;
+      };
+      auto wh = [](int v, int n, bool per) -> double { return per || (v >= 1 && v <= n - 2) ? 1.0 : 0.0; };
+      const bool ay = D < 2 || py, az = D < 3 || pz;   // y, z weigh 1
+      // one product E_a (at the half step) b_b (averaged to the plane along d)
+      auto term = [&](double w, float en, float eo, float b0, float b1, double coef) {
+        if (w == 0.0) return;
+        const double v = coef * w * (0.5 * ((double)en + (double)eo)) * (0.5 * ((double)b0 + (double)b1));
+        if (v > 0.0) fin += v; else fout -= v;
+      };
+      // plane normal to x: S_x = E_y b_z - E_z b_y
+      if (xdn && (i == 1 || i == nx - 1)) {
+        const double c = (i == 1 ? 1.0 : -1.0) * I.kflux[0];
+        if (ydh && zdn) term(wh(j, ny, ay) * wn(k, nz, az), sE[1][l], at(Ec1, gi), sB[2][l - 1], sB[2][l], c);
+        if (ydn && zdh) term(wn(j, ny, ay) * wh(k, nz, az), sE[2][l], at(Ec2, gi), sB[1][l - 1], sB[1][l], -c);
+      }
+      // plane normal to y: S_y = E_z b_x - E_x b_z
+      if (D >= 2 && !py && ydn && (j == 1 || j == ny - 1)) {
+        const double c = (j == 1 ? 1.0 : -1.0) * I.kflux[1];
+        if (xdn && zdh) term(wn(i, nx, false) * wh(k, nz, az), sE[2][l], at(Ec2, gi), sB[0][l - LY], sB[0][l], c);
+        if (xdh && zdn) term(wh(i, nx, false) * wn(k, nz, az), sE[0][l], at(Ec0, gi), sB[2][l - LY], sB[2][l], -c);
+      }
+      // plane normal to z: S_z = E_x b_y - E_y b_x
+      if (D >= 3 && !pz && zdn && (k == 1 || k == nz - 1)) {
+        const double c = (k == 1 ? 1.0 : -1.0) * I.kflux[2];
+        if (xdh && ydn) term(wh(i, nx, false) * wn(j, ny, py), sE[0][l], at(Ec0, gi), sB[1][l - LZ], sB[1][l], c);
+        if (xdn && ydh) term(wn(i, nx, false) * wh(j, ny, py), sE[1][l], at(Ec1, gi), sB[0][l - LZ], sB[0][l], -c);
+      }
     }
     if (xdn && ydh && zdh) {
       float cu = 0.0f;
@@ -1510,6 +1568,17 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g, std::conditional_t<ONE,
   }
   if (threadIdx.x == 0 && blk_hot) atomicOr(I.hot + par, 1);
   if (threadIdx.x == 0) atomicAdd(I.tiles_done + 32 * (blockIdx.x & 7), 1ull);
+  if (chk != 0.0f) atomicOr(I.health, HEALTH_NONFINITE);
+  if (flux_tile) {
+    for (int o = 32; o > 0; o >>= 1) {
+      fin += __shfl_xor(fin, o);
+      fout += __shfl_xor(fout, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      if (fin != 0.0) atomicAdd(I.eflux, fin);
+      if (fout != 0.0) atomicAdd(I.eflux + 1, fout);
+    }
+  }
 }
 
 // ------------------------------------------------------------- ionization
@@ -1610,16 +1679,37 @@ __global__ __launch_bounds__(TPB) void k_ionize(Group g, std::conditional_t<ONE,
     const int t = (int)(mn - m0);
     if (hot[t]) b = ionize_decide<D, ORDER>(I, jn, mn, scell[t], smat[t], step);
   }
-  // the wave's events: one slot reservation, one event count per material, one
-  // alive-mask update per 32-neutral word (a wave holds 64 consecutive
-  // neutrals starting at a multiple of 64)
+  // the wave's events: one slot reservation per tile, one event count per
+  // material, one alive-mask update per 32-neutral word (a wave holds 64
+  // consecutive neutrals starting at a multiple of 64)
   const unsigned long long m = __ballot(b.ev);
   if (!m) return;
   const int lane = threadIdx.x & 63;
-  const int leader = __ffsll((long long)m) - 1;
-  int base = 0;
-  if (lane == leader) base = atomicAdd(I.pcount, 2 * __popcll(m));
-  base = __shfl(base, leader);
+  // birth slots: the tile's birth room (electron and positive-carrier halves)
+  // while it lasts, else two slots after the layout
+  int tt = -1;
+  if (b.ev) {
+    const int t = tile_of<D>(I, pack_cell(D, b.ci, b.cj, b.ck));
+    tt = t >= 0 && I.tslack[t] > 0 ? t : -1;
+  }
+  const int r = wave_rank_add(I.tfill, tt);
+  int cap = 0;
+  if (tt >= 0) cap = I.tslack[tt];
+  const bool room = tt >= 0 && r < cap;
+  int se = 0, sp = 0;
+  if (room) {
+    se = I.tbirth[tt] + r;
+    sp = se + cap;
+  }
+  const unsigned long long mt = __ballot(b.ev && !room);
+  if (mt) {
+    const int leader = __ffsll((long long)mt) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(I.pcount, 2 * __popcll(mt));
+    base = __shfl(base, leader);
+    se = base + 2 * __popcll(mt & ((1ull << lane) - 1ull));
+    sp = se + 1;
+  }
   if (lane == 0 && (unsigned)m) atomicAnd(&I.alive[jn >> 5], ~(unsigned)m);
   if (lane == 32 && (unsigned)(m >> 32)) atomicAnd(&I.alive[jn >> 5], ~(unsigned)(m >> 32));
   for (unsigned long long left = m; left;) {
@@ -1632,8 +1722,7 @@ __global__ __launch_bounds__(TPB) void k_ionize(Group g, std::conditional_t<ONE,
   if (!b.ev) return;
   const int n1 = step + 1;
   I.death[jn] = n1;
-  const int slot = base + 2 * __popcll(m & ((1ull << lane) - 1ull));
-  if (slot + 2 > I.capacity) {
+  if (!room && se + 2 > I.capacity) {
     atomicOr(I.health, HEALTH_CAPACITY);
     return;
   }
@@ -1642,7 +1731,7 @@ __global__ __launch_bounds__(TPB) void k_ionize(Group g, std::conditional_t<ONE,
   const uint32_t pc = pack_cell(D, b.ci, b.cj, b.ck);
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
-    const int q = slot + s;
+    const int q = s == 0 ? se : sp;
     I.pcell[q] = pc;
     I.po0[q] = b.t0;
     if (D >= 2) I.po1[q] = b.t1;
@@ -2047,20 +2136,30 @@ __global__ void k_table_probe(const TabHdr* tab, const float* A, float* P, int64
     else                                                                              \
       GO((KT<__VA_ARGS__, false>), g.blocks, tpb, s, st.start, st.stop, g, NoInst{}); \
   } while (0)
-void launch_push(const Group& g, int D, int order, hipStream_t s, Stamp st) {
+void launch_push(const Group& g, int D, int order, bool per, hipStream_t s, Stamp st) {
   const bool one = g.n == 1 && g.host && g.step >= 0;
+  // periodic transverse axes are a template parameter (D >= 2)
   if (order == 1) {
-    DISPATCH_D(D, ONE_OR_GROUP(k_push, push_tpb(DD), DD, 1));
+    if (per && D >= 2) {
+      DISPATCH_D(D, ONE_OR_GROUP(k_push, push_tpb(DD), DD, 1, DD >= 2, DD >= 3));
+    } else {
+      DISPATCH_D(D, ONE_OR_GROUP(k_push, push_tpb(DD), DD, 1, false, false));
+    }
   } else {
-    DISPATCH_D(D, ONE_OR_GROUP(k_push, push_tpb(DD), DD, 2));
+    if (per && D >= 2) {
+      DISPATCH_D(D, ONE_OR_GROUP(k_push, push_tpb(DD), DD, 2, DD >= 2, DD >= 3));
+    } else {
+      DISPATCH_D(D, ONE_OR_GROUP(k_push, push_tpb(DD), DD, 2, false, false));
+    }
   }
 }
 void launch_sort(const Group& gp, const Group& gscan, int D, hipStream_t s, Stamp st) {
   hipEvent_t none = nullptr;
   DISPATCH_D(D, GO((k_sort_count<DD>), gp.blocks, TPB, s, st.start, none, gp));
   DISPATCH_D(D, GO((k_sort_scan<DD>), gscan.blocks, SCAN_TPB, s, none, none, gscan));
+  DISPATCH_D(D, GO((k_sort_fill<DD>), gp.blocks, TPB, s, none, none, gp));
   DISPATCH_D(D, GO((k_sort_scatter<DD>), gp.blocks, TPB, s, none, none, gp));
-  DISPATCH_D(D, GO((k_sort_group<DD>), gp.blocks, TPB, s, none, st.stop, gp));
+  DISPATCH_D(D, GO((k_sort_copy<DD>), gp.blocks, TPB, s, none, st.stop, gp));
 }
 #define FIELDS_V(DD, V) ONE_OR_GROUP(k_fields, TPB, DD, V)
 void launch_fields(const Group& g, int D, int variant, hipStream_t s, Stamp st) {

@@ -67,8 +67,8 @@ struct Layout {
   size_t o_no[3], o_alive, o_death, o_mcell;
   size_t o_pcell, o_po[3], o_pu[3], o_pkind, o_pid;
   int ntile[3];
-  int64_t ntiles, ngroups, maxchunks;
-  size_t o_gcnt, o_gn, o_gstart, o_gfill, o_chunks;
+  int64_t ntiles, maxchunks;
+  size_t o_tcnt, o_tstart, o_tbirth, o_tslack, o_tfill, o_talive, o_chunks;
   size_t o_scell, o_so[3], o_su[3], o_skind, o_spid;
   size_t o_tab[MAXMAT];
   size_t o_ctr;      // pcount, step, health, nevents[MAXMAT], diag accumulators
@@ -93,6 +93,7 @@ struct Ctr {
   alignas(256) int hot[2];
   alignas(256) unsigned long long nevents[MAXMAT];
   double acc[64];
+  alignas(256) double eflux[2];   // field energy into / out of the flux surface [J]
 };
 
 pic_status plan(const pic_config* cfg, const Canon& c, const std::vector<TableHost>& tabs, Layout* L) {
@@ -126,13 +127,14 @@ pic_status plan(const pic_config* cfg, const Canon& c, const std::vector<TableHo
     L->ntile[d] = d < D ? (int)((c.n[d] + e - 1) / e) : 1;
     L->ntiles *= L->ntile[d];
   }
-  L->ngroups = L->ntiles * (ptile_cells(D) / PT_GROUP);
   // grid byte offsets are 32-bit in the kernels
-  if (cap > INT_MAX / 2 || L->ngroups > (1 << 28) || L->nneut > ((int64_t)1 << 40) || c.ppc > 65535 ||
+  if (cap > INT_MAX / 2 || L->ntiles > (1 << 26) || L->nneut > ((int64_t)1 << 40) || c.ppc > 65535 ||
       L->ncell >= (1 << 30))
     return PIC_E_INVAL;
   L->capacity = cap;
-  L->maxchunks = L->ntiles + cap / SORT_CHUNK + 1;
+  // chunks: ceil(n / SORT_CHUNK) per tile with particles, one per tile with
+  // birth room only
+  L->maxchunks = 2 * L->ntiles + cap / SORT_CHUNK + 1;
   // source samples cover the planned steps and the whole pulse (Gaussian: to
   // t0 + 8 fwhm, where the envelope is below 1e-38; sin^2: its full length)
   const double t_end = c.env == PIC_ENV_GAUSS ? c.t0 + 8.0 * c.fwhm : c.t0 + 0.5 * c.T;
@@ -167,10 +169,12 @@ pic_status plan(const pic_config* cfg, const Canon& c, const std::vector<TableHo
   for (int q = 0; q < 3; ++q) L->o_pu[q] = take(sizeof(float) * L->capacity);
   L->o_pkind = take(L->capacity);
   L->o_pid = take(sizeof(uint32_t) * L->capacity);
-  L->o_gcnt = take(sizeof(int) * L->ngroups);
-  L->o_gn = take(sizeof(int) * L->ngroups);
-  L->o_gstart = take(sizeof(int) * L->ngroups);
-  L->o_gfill = take(sizeof(int) * L->ngroups);
+  L->o_tcnt = take(sizeof(int) * L->ntiles);
+  L->o_tstart = take(sizeof(int) * L->ntiles);
+  L->o_tbirth = take(sizeof(int) * L->ntiles);
+  L->o_tslack = take(sizeof(int) * L->ntiles);
+  L->o_tfill = take(sizeof(int) * L->ntiles);
+  L->o_talive = take(sizeof(int) * L->ntiles);
   L->o_chunks = take(sizeof(int4) * L->maxchunks);
   L->o_scell = take(sizeof(uint32_t) * L->capacity);
   for (int q = 0; q < 3; ++q) L->o_so[q] = take(q < D ? sizeof(float) * L->capacity : 0);
@@ -243,6 +247,7 @@ struct pic_batch {
   // per (D, order) class: device Inst copies and per-phase block offsets
   struct Class {
     int D, order, tile = 0;
+    bool per = false;   // periodic transverse axes
     std::vector<pic_ctx*> ms;
     Inst* d_insts = nullptr;
     int* d_off = nullptr;   // 4 phases x (n + 1)
@@ -424,7 +429,7 @@ void enqueue_step(pic_ctx* c) {
   hipStream_t s = c->stream;
   if (c->resort > 0 && c->step % c->resort == 0)
     timed(c, 3, [&](Stamp st) { launch_sort(single(c, 0, c->nb_push), single(c, 2, 1), D, s, st); });
-  timed(c, 0, [&](Stamp st) { launch_push(single(c, 0, c->nb_push), D, order, s, st); });
+  timed(c, 0, [&](Stamp st) { launch_push(single(c, 0, c->nb_push), D, order, c->canon.per[1], s, st); });
   if (c->tune_left > 0) {
     const int idx = field_tile_variants() * c->tune_reps - c->tune_left;
     const int v = idx / c->tune_reps, r = idx % c->tune_reps;
@@ -498,6 +503,47 @@ pic_status check_health(pic_ctx* c) {
     if (h & HEALTH_NONFINITE) c->latched = PIC_E_NUMERIC;
     else if (h & HEALTH_CAPACITY) c->latched = PIC_E_CAPACITY;
   }
+  return PIC_OK;
+}
+
+// Arguments of an energy-histogram call.
+pic_status spectrum_check(pic_ctx* c, const pic_spectrum* sp, const uint64_t* out, size_t out_count) {
+  if (!c || !sp || !out) return PIC_E_INVAL;
+  const int ne = sp->nedges;
+  const int nk = 2 * c->canon.nmat;
+  if (ne < 2 || ne > kSpecEdges || !sp->edges_eV) return PIC_E_INVAL;
+  if (out_count != (size_t)nk * (size_t)(ne + 1)) return PIC_E_INVAL;
+  for (int q = 0; q < ne; ++q) {
+    if (!std::isfinite(sp->edges_eV[q])) return PIC_E_INVAL;
+    if (q > 0 && !(sp->edges_eV[q] > sp->edges_eV[q - 1])) return PIC_E_INVAL;
+  }
+  if (sp->x_hi_cell > sp->x_lo_cell && (sp->x_lo_cell < INT32_MIN || sp->x_hi_cell > INT32_MAX)) return PIC_E_INVAL;
+  return PIC_OK;
+}
+
+// The histogram through a device buffer of kSpecBytes (edges, then counts).
+pic_status spectrum_into(pic_ctx* c, const pic_spectrum* sp, uint64_t* out, size_t out_count, void* buf) {
+  hipStream_t s = c->stream;
+  if (hipStreamSynchronize(s) != hipSuccess) return PIC_E_DEVICE;
+  check_health(c);
+  const int ne = sp->nedges;
+  const int nk = 2 * c->canon.nmat;
+  double* d_edges = (double*)buf;
+  unsigned long long* d_cnt = (unsigned long long*)(d_edges + kSpecEdges);
+  SpecArgs a{};
+  a.nkinds = nk;
+  a.nedges = ne;
+  a.x_lo = sp->x_hi_cell > sp->x_lo_cell ? (int)sp->x_lo_cell : 0;
+  a.x_hi = sp->x_hi_cell > sp->x_lo_cell ? (int)sp->x_hi_cell : 0;
+  a.lds = (int)spec_lds_counts(nk, ne);
+  // rest energy per kind [eV]: m c^2 / e
+  for (int k = 0; k < nk; ++k) a.mc2_eV[k] = c->h.kmass[k] * kC * kC / kQE;
+  HIP_OK(hipMemcpyAsync(d_edges, sp->edges_eV, sizeof(double) * ne, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemsetAsync(d_cnt, 0, sizeof(unsigned long long) * out_count, s));
+  launch_spectrum(c->d_inst, c->canon.D, (int)c->L.capacity, a, d_edges, d_cnt, s);
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipMemcpyAsync(out, d_cnt, sizeof(unsigned long long) * out_count, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
   return PIC_OK;
 }
 
@@ -717,10 +763,12 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
   I.pid = (uint32_t*)devp(c, L.o_pid);
   for (int d = 0; d < 3; ++d) I.ntile[d] = L.ntile[d];
   I.ntiles = (int)L.ntiles;
-  I.gcnt = (int*)devp(c, L.o_gcnt);
-  I.gn = (int*)devp(c, L.o_gn);
-  I.gstart = (int*)devp(c, L.o_gstart);
-  I.gfill = (int*)devp(c, L.o_gfill);
+  I.tcnt = (int*)devp(c, L.o_tcnt);
+  I.tstart = (int*)devp(c, L.o_tstart);
+  I.tbirth = (int*)devp(c, L.o_tbirth);
+  I.tslack = (int*)devp(c, L.o_tslack);
+  I.tfill = (int*)devp(c, L.o_tfill);
+  I.talive = (int*)devp(c, L.o_talive);
   I.chunks = (int4*)devp(c, L.o_chunks);
   I.scell = (uint32_t*)devp(c, L.o_scell);
   I.so0 = (float*)devp(c, L.o_so[0]);
@@ -741,6 +789,15 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
   I.step = &c->d_ctr->step;
   I.health = &c->d_ctr->health;
   I.nevents = c->d_ctr->nevents;
+  I.eflux = c->d_ctr->eflux;
+  for (int d = 0; d < 3; ++d) {
+    // a plane normal to axis d: eps0 c dt times the transverse cell area
+    // (absent axes count 1 m)
+    double area = 1.0;
+    for (int e = 0; e < D; ++e)
+      if (e != d) area *= K.dx[e];
+    I.kflux[d] = kEPS0 * kC * K.dt * area;
+  }
   I.capacity = (int)L.capacity;
   for (int m = 0; m < K.nmat; ++m) {
     const MatC& mt = K.mats[m];
@@ -823,6 +880,28 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
     ok &= hipMemcpyAsync(devp(c, L.o_sig), sig, sizeof sig, hipMemcpyHostToDevice, s) == hipSuccess;
   }
   if (!ok) return fail(PIC_E_DEVICE);
+  // alive neutrals per particle tile (the bound the birth room is sized by)
+  // and a sort at the first check, which lays the tiles and their birth room out
+  {
+    std::vector<int> talive(L.ntiles, 0);
+    if (c->cfg.preionize_eV <= 0) {
+      for (uint32_t pc : c->mcell) {
+        int ci, cj, ck;
+        unpack_cell(D, pc, ci, cj, ck);
+        int64_t t = ci / ptile_ext(D, 0);
+        if (D >= 2) t += (int64_t)L.ntile[0] * (cj / ptile_ext(D, 1));
+        if (D >= 3) t += (int64_t)L.ntile[0] * L.ntile[1] * (ck / ptile_ext(D, 2));
+        talive[t] += K.ppc;
+      }
+    }
+    ok &= hipMemcpyAsync(devp(c, L.o_talive), talive.data(), sizeof(int) * L.ntiles, hipMemcpyHostToDevice,
+                         s) == hipSuccess;
+    if (c->cfg.preionize_eV <= 0 && L.nneut > 0) {
+      static const int force = 1;
+      ok &= hipMemcpyAsync(&c->d_ctr->sctl[SC_FORCE], &force, sizeof force, hipMemcpyHostToDevice, s) ==
+            hipSuccess;
+    }
+  }
   // charged region: the amplitude window (births and preionized carriers are
   // all inside it)
   set_region(c, 1 << 30, -(1 << 30));
@@ -962,40 +1041,14 @@ pic_status pic_set_imax(pic_ctx* c, int32_t every) {
 }
 
 pic_status pic_spectrum_counts(pic_ctx* c, const pic_spectrum* sp, uint64_t* out, size_t out_count) {
-  if (!c || !sp || !out) return PIC_E_INVAL;
-  const int ne = sp->nedges;
-  const int nk = 2 * c->canon.nmat;
-  if (ne < 2 || ne > kSpecEdges || !sp->edges_eV) return PIC_E_INVAL;
-  if (out_count != (size_t)nk * (size_t)(ne + 1)) return PIC_E_INVAL;
-  for (int q = 0; q < ne; ++q) {
-    if (!std::isfinite(sp->edges_eV[q])) return PIC_E_INVAL;
-    if (q > 0 && !(sp->edges_eV[q] > sp->edges_eV[q - 1])) return PIC_E_INVAL;
-  }
-  if (sp->x_hi_cell > sp->x_lo_cell && (sp->x_lo_cell < INT32_MIN || sp->x_hi_cell > INT32_MAX)) return PIC_E_INVAL;
-  hipStream_t s = c->stream;
-  if (hipStreamSynchronize(s) != hipSuccess) return PIC_E_DEVICE;
-  check_health(c);
+  pic_status st = spectrum_check(c, sp, out, out_count);
+  if (st != PIC_OK) return st;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return PIC_E_DEVICE;
   if (!c->d_spec) {
     c->d_spec = dev_alloc(c, kSpecBytes);
     if (!c->d_spec) return PIC_E_NOMEM;
   }
-  double* d_edges = (double*)c->d_spec;
-  unsigned long long* d_cnt = (unsigned long long*)(d_edges + kSpecEdges);
-  SpecArgs a{};
-  a.nkinds = nk;
-  a.nedges = ne;
-  a.x_lo = sp->x_hi_cell > sp->x_lo_cell ? (int)sp->x_lo_cell : 0;
-  a.x_hi = sp->x_hi_cell > sp->x_lo_cell ? (int)sp->x_hi_cell : 0;
-  a.lds = (int)spec_lds_counts(nk, ne);
-  // rest energy per kind [eV]: m c^2 / e
-  for (int k = 0; k < nk; ++k) a.mc2_eV[k] = c->h.kmass[k] * kC * kC / kQE;
-  HIP_OK(hipMemcpyAsync(d_edges, sp->edges_eV, sizeof(double) * ne, hipMemcpyHostToDevice, s));
-  HIP_OK(hipMemsetAsync(d_cnt, 0, sizeof(unsigned long long) * out_count, s));
-  launch_spectrum(c->d_inst, c->canon.D, (int)c->L.capacity, a, d_edges, d_cnt, s);
-  HIP_OK(hipGetLastError());
-  HIP_OK(hipMemcpyAsync(out, d_cnt, sizeof(unsigned long long) * out_count, hipMemcpyDeviceToHost, s));
-  HIP_OK(hipStreamSynchronize(s));
-  return PIC_OK;
+  return spectrum_into(c, sp, out, out_count, c->d_spec);
 }
 
 pic_status pic_set_tracks(pic_ctx* c, uint32_t threshold, int32_t every, int64_t max_records) {
@@ -1201,6 +1254,8 @@ pic_status pic_set_state(pic_ctx* c, const pic_state* S) {
     HIP_OK(hipMemcpy(&c->d_ctr->front, &fr, sizeof fr, hipMemcpyHostToDevice));
     // the new particles are all unsorted
     HIP_OK(hipMemset(c->d_ctr->sctl, 0, sizeof(c->d_ctr->sctl)));
+    // no birth room until the next sort lays the tiles out again
+    HIP_OK(hipMemset(devp(c, L.o_tslack), 0, sizeof(int) * L.ntiles));
   }
   const int st = (int)S->step;
   HIP_OK(hipMemcpy(&c->d_ctr->step, &st, sizeof st, hipMemcpyHostToDevice));
@@ -1240,6 +1295,7 @@ pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size
     case PIC_DIAG_TIMERS: need = sizeof(double) * 32; break;
     case PIC_DIAG_SORT: need = sizeof(double) * 4; break;
     case PIC_DIAG_REGION: need = sizeof(double) * 6; break;
+    case PIC_DIAG_HEALTH: need = sizeof(double) * 4; break;
     case PIC_DIAG_EVENTS:
     case PIC_DIAG_TRACKS:
     case PIC_DIAG_PARTICLES: break;   // computed below
@@ -1417,6 +1473,19 @@ pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size
     o[5] = done;
     return PIC_OK;
   }
+  if (kind == PIC_DIAG_HEALTH) {
+    unsigned h = 0;
+    int cnt = 0, dstep = 0;
+    HIP_OK(hipMemcpy(&h, &c->d_ctr->health, sizeof h, hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(&cnt, &c->d_ctr->pcount, sizeof cnt, hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(&dstep, &c->d_ctr->step, sizeof dstep, hipMemcpyDeviceToHost));
+    double* o = (double*)host_out;
+    o[0] = (double)h;
+    o[1] = (double)c->latched;
+    o[2] = (double)dstep;
+    o[3] = (double)cnt;
+    return PIC_OK;
+  }
   if (kind == PIC_DIAG_TIMERS) {
     harvest_all(c);
     double* o = (double*)host_out;
@@ -1472,6 +1541,8 @@ pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size
   o[PIC_SC_GAUSS_MAX] = h.acc[44];
   o[PIC_SC_RHO_MAX] = h.acc[45];
   o[PIC_SC_GAUSS_L2] = h.acc[47] > 0 ? std::sqrt(h.acc[46] / h.acc[47]) : 0.0;
+  o[PIC_SC_E_IN] = h.eflux[0];
+  o[PIC_SC_E_OUT] = h.eflux[1];
   o[PIC_SC_HEALTH] = (double)h.health;
   o[PIC_SC_SLOTS] = (double)h.pcount;
   unsigned long long nrec = 0;
@@ -1540,13 +1611,15 @@ static pic_status batch_rebuild(pic_batch* b) {
   for (pic_ctx* c : b->members) {
     pic_batch::Class* cl = nullptr;
     for (auto& k : b->classes)
-      if (k.D == c->canon.D && k.order == c->cfg.shape_order && k.tile == c->tile) cl = &k;
+      if (k.D == c->canon.D && k.order == c->cfg.shape_order && k.tile == c->tile && k.per == (bool)c->canon.per[1])
+        cl = &k;
     if (!cl) {
       b->classes.push_back(pic_batch::Class{});
       cl = &b->classes.back();
       cl->D = c->canon.D;
       cl->order = c->cfg.shape_order;
       cl->tile = c->tile;
+      cl->per = c->canon.per[1];
     }
     cl->ms.push_back(c);
   }
@@ -1597,7 +1670,7 @@ static void batch_enqueue(pic_batch* b, int64_t k, hipStream_t s) {
       Group gs{cl.d_insts, cl.d_off + 2 * np1, cl.n, cl.blocks[2], -1, 0, cl.d_map + cl.map_off[2]};
       Group gn{cl.d_insts, cl.d_off + 3 * np1, cl.n, cl.blocks[3], -1, 0, cl.d_map + cl.map_off[3]};
       if (sort_due) launch_sort(gp, gs, cl.D, s);
-      launch_push(gp, cl.D, cl.order, s);
+      launch_push(gp, cl.D, cl.order, cl.per, s);
       launch_fields(gc, cl.D, cl.tile, s);   // far tiles skip the current
       launch_ionize(gn, cl.D, cl.order, s);
       launch_advance(cl.d_insts, cl.n, s);

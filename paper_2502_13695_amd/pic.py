@@ -23,10 +23,10 @@ ABI_VERSION = 1
 ENV = {"gauss": 0, "sin2": 1}
 BC = {"outflow": 0, "periodic": 1}
 DIAG_SCALARS, DIAG_FIELDS, DIAG_NE, DIAG_UE, DIAG_EVENTS, DIAG_PARTICLES, DIAG_PARAMS, DIAG_AMP, \
-    DIAG_TIMERS, DIAG_SORT, DIAG_REGION, DIAG_IMAX, DIAG_TRACKS = range(13)
+    DIAG_TIMERS, DIAG_SORT, DIAG_REGION, DIAG_IMAX, DIAG_TRACKS, DIAG_HEALTH = range(14)
 SC = dict(step=0, time=1, n_neutral=2, n_e=3, n_pos=4, events=5, u_field=6, ke_e=7, ke_pos=8,
           e_gap=9, e_abs=10, gauss_max=11, rho_max=12, health=13, slots=14, tracks_dropped=15,
-          gauss_l2=16)
+          gauss_l2=16, e_in=17, e_out=18)
 
 
 class PicError(RuntimeError):
@@ -98,7 +98,8 @@ SYMBOLS = ["pic_init", "pic_step", "pic_diag", "pic_set_state", "pic_footprint",
            "pic_batch_step", "pic_batch_add", "pic_batch_remove", "pic_batch_destroy", "pic_batch_set_graph",
            "pic_batch_graph_replays",
            "pic_set_timing", "pic_autotune", "pic_autotune_steps", "pic_set_resort", "pic_set_far_tiles",
-           "pic_set_imax", "pic_spectrum_counts", "pic_set_tracks", "pic_snapshot", "pic_restore",
+           "pic_set_imax", "pic_spectrum_counts", "pic_set_tracks",
+           "pic_snapshot", "pic_restore",
            "pic_destroy", "pic_status_str"]
 
 
@@ -321,6 +322,11 @@ class Context:
     def scalars(self):
         v = self._diag(DIAG_SCALARS, np.float64)
         return {k: float(v[i]) for k, i in SC.items()}
+
+    def health(self):
+        """Device health word, latched status, device step index, slots in use."""
+        v = self._diag(DIAG_HEALTH, np.float64)
+        return dict(bits=int(v[0]), latched=int(v[1]), step=int(v[2]), slots=int(v[3]))
 
     def _split(self, flat, which_list):
         out = []

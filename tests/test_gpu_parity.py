@@ -126,10 +126,13 @@ def test_one_step_fields_and_particles(P, ndim, order, bc, sort):
     assert len(parts) == len(sim.px)
     npre = len(st["kind"])
     pos_g = parts["cell"][:, :ndim] + parts["off"][:, :ndim].astype(np.float64)
-    pre_g, u_g, k_g = pos_g[:npre], parts["u"][:npre], parts["kind"][:npre].astype(np.int64)
+    all_u, all_k = parts["u"], parts["kind"].astype(np.int64)
     if sort:
+        # the tile sort reorders the slots and puts births in their tiles' room:
+        # pair every GPU particle with the oracle's (oracle order: placed, births)
         period = [None] + [n[k] if bc == "periodic" else None for k in range(1, ndim)]
-        pre_g, u_g, k_g = _match_particles(pre_g, u_g, k_g, sim.px[:npre, :ndim], sim.pk[:npre], period)
+        pos_g, all_u, all_k = _match_particles(pos_g, all_u, all_k, sim.px[:, :ndim], sim.pk, period)
+    pre_g, u_g, k_g = pos_g[:npre], all_u[:npre], all_k[:npre]
     d = pre_g - sim.px[:npre, :ndim]
     if bc == "periodic":
         for k in range(1, ndim):
@@ -138,10 +141,23 @@ def test_one_step_fields_and_particles(P, ndim, order, bc, sort):
     assert np.max(np.abs(u_g - sim.pu[:npre])) < 2e-6 * max(1.0, np.max(np.abs(sim.pu)))
     assert np.array_equal(k_g, sim.pk[:npre])
     # births: identical (position, kind) multisets, thermal u at FP32 accuracy
-    key_g = sorted(zip(np.round(pos_g[npre:], 6).tolist(), parts["kind"][npre:].tolist()))
-    key_o = sorted(zip(np.round(sim.px[npre:, :ndim], 6).tolist(), sim.pk[npre:].tolist()))
-    assert key_g == key_o
+    _compare_births(pos_g[npre:], all_u[npre:], all_k[npre:], sim, npre, ndim)
     ctx.close()
+
+
+def _compare_births(pos_g, u_g, k_g, sim, npre, ndim):
+    """Births of a step: the same (position, kind) pairs, and each carrier's u
+    (its neutral's 300 K velocity, Box-Muller on the Philox draw) at FP32
+    accuracy of the oracle's FP64 value."""
+    key_g = [tuple(np.round(p, 6).tolist()) + (int(k),) for p, k in zip(pos_g, k_g)]
+    key_o = [tuple(np.round(p, 6).tolist()) + (int(k),) for p, k in zip(sim.px[npre:, :ndim], sim.pk[npre:])]
+    assert sorted(key_g) == sorted(key_o)
+    ig = sorted(range(len(key_g)), key=lambda q: key_g[q])
+    io = sorted(range(len(key_o)), key=lambda q: key_o[q])
+    ug = np.asarray(u_g, dtype=np.float64)[ig]
+    uo = sim.pu[npre:][io]
+    if len(uo):
+        assert np.max(np.abs(ug - uo)) <= 1e-6 * np.max(np.abs(uo)) + 1e-12
 
 
 @pytest.mark.parametrize("which", ["slab2d_2048x512", "mirror3d_256x128x128"])
@@ -175,7 +191,7 @@ def test_one_step_at_benchmark_size(P, which, monkeypatch):
         assert np.max(np.abs(E_g[c] - Eo)) < 2e-6 * scale, ("E", c)
         assert np.max(np.abs(b_g[c] - bo)) < 2e-6 * scale, ("b", c)
     ev_o = sim.event_set()
-    assert len(ev_o) > 0 and len(ev_g ^ ev_o) <= max(1, int(1e-4 * len(ev_o)))
+    assert len(ev_o) > 0 and ev_g == ev_o
     npre = len(st["kind"])
     n = cfg["n"]
     per = cfg["transverse_bc"] == "periodic"
@@ -190,7 +206,17 @@ def test_one_step_at_benchmark_size(P, which, monkeypatch):
     assert np.max(np.abs(d)) < 2e-5
     assert np.max(np.abs(u_g - sim.pu[:npre])) < 2e-6 * max(1.0, np.max(np.abs(sim.pu)))
     assert np.array_equal(k_g, sim.pk[:npre])
-    assert abs(len(parts) - len(sim.px)) <= 2 * len(ev_g ^ ev_o)   # births
+    assert len(parts) == len(sim.px)
+    # the births: every carrier at its neutral's position with its thermal u
+    born = np.ones(len(parts), dtype=bool)
+    pos_all = parts["cell"][:, :ndim] + parts["off"][:, :ndim].astype(np.float64)
+    # pre-existing carriers were matched above; births are the records whose
+    # (position, kind) the pre-existing set does not hold
+    pre_keys = set(tuple(np.round(p, 6).tolist()) + (int(k),) for p, k in zip(pre_g, k_g))
+    for q in range(len(parts)):
+        if tuple(np.round(pos_all[q], 6).tolist()) + (int(parts["kind"][q]),) in pre_keys:
+            born[q] = False
+    _compare_births(pos_all[born], parts["u"][born], parts["kind"][born], sim, npre, ndim)
 
 
 @pytest.mark.parametrize("cfg", [W.config_2d(), W.config_3d(), dict(W.config_2d(), keldysh_tol_bits=16)],
@@ -226,14 +252,21 @@ def _run_both(P, cfg, nsteps):
     return ctx, sim
 
 
-def _field_l2(ctx, sim):
+def _field_norm(sim):
+    return math.sqrt(sum(np.sum(sim.interior_field(w, c) ** 2) for w in "Eb" for c in range(3)))
+
+
+def _field_l2(ctx, sim, norm=None):
+    """Relative L2 difference of all field components: over the oracle's own
+    norm, or over `norm` (the norm at an earlier step, once the pulse has left
+    and what remains is a small fraction of it)."""
     E_g, b_g = ctx.fields()
     num = den = 0.0
     for c in range(3):
         for g_, o_ in ((E_g[c], sim.interior_field("E", c)), (b_g[c], sim.interior_field("b", c))):
             num += np.sum((g_ - o_) ** 2)
             den += np.sum(o_ ** 2)
-    return math.sqrt(num / den)
+    return math.sqrt(num) / (norm if norm is not None else math.sqrt(den))
 
 
 def _record(name, **kv):
@@ -247,30 +280,66 @@ def _record(name, **kv):
             f.write(json.dumps(dict(test=name, **kv)) + "\n")
 
 
-def _compare_run(P, ctx, sim, l2_tol=1e-5, rel_tol=5e-3, min_events=1, name=""):
-    l2 = _field_l2(ctx, sim)
-    sc0 = ctx.scalars()
-    ev_g0 = set(map(tuple, ctx.events().tolist()))
-    ev_o0 = sim.event_set()
-    ne_o0 = float(np.sum(sim.pk % 2 == 0))
-    eabs_o0 = sim.kinetic_energy() + sim.energy_gap
-    _record(name, field_l2=l2, events_gpu=len(ev_g0), events_oracle=len(ev_o0),
-            events_common=len(ev_g0 & ev_o0), n_e_gpu=sc0["n_e"], n_e_oracle=ne_o0,
-            e_abs_gpu=sc0["e_abs"], e_abs_oracle=eabs_o0, gauss_max=sc0["gauss_max"],
-            rho_max=sc0["rho_max"])
-    assert l2 < l2_tol, l2
+def _node_slices(sim):
+    """Node positions inside the box (the layout of the device's node grids)."""
+    sl = []
+    for d in range(3):
+        if d >= sim.D:
+            sl.append(slice(0, 1))
+        else:
+            n = sim.P.n[d]
+            sl.append(slice(OP.G, OP.G + n + (0 if sim.P.periodic[d] else 1)))
+    return tuple(sl)
+
+
+def _compare_run(P, ctx, sim, l2_tol=1e-5, rel_tol=5e-3, min_events=1, name="", norm=None, amp_ref=None):
+    l2 = _field_l2(ctx, sim, norm)
     sc = ctx.scalars()
     ev_g = set(map(tuple, ctx.events().tolist()))
     ev_o = sim.event_set()
-    assert len(ev_o) >= min_events
-    inter = len(ev_g & ev_o)
-    union = len(ev_g | ev_o)
-    # identical event sets (a difference needs a draw within the FP32 rounding of P)
-    assert union - inter <= max(1, int(1e-4 * union)), (len(ev_g), len(ev_o), inter)
-    assert sc["events"] == len(ev_g)
     ne_o = float(np.sum(sim.pk % 2 == 0))
+    ke_e_o, ke_p_o = sim.kinetic_energy("e"), sim.kinetic_energy("p")
+    eabs_o = ke_e_o + ke_p_o + sim.energy_gap
+    u_o = sim.field_energy()
+    _record(name, field_l2=l2, events_gpu=len(ev_g), events_oracle=len(ev_o),
+            events_common=len(ev_g & ev_o), n_e_gpu=sc["n_e"], n_e_oracle=ne_o,
+            e_abs_gpu=sc["e_abs"], e_abs_oracle=eabs_o, ke_e_gpu=sc["ke_e"], ke_e_oracle=ke_e_o,
+            ke_pos_gpu=sc["ke_pos"], ke_pos_oracle=ke_p_o, e_gap_gpu=sc["e_gap"], e_gap_oracle=sim.energy_gap,
+            u_field_gpu=sc["u_field"], u_field_oracle=u_o, e_in_gpu=sc["e_in"], e_in_oracle=sim.energy_in,
+            e_out_gpu=sc["e_out"], e_out_oracle=sim.energy_out, gauss_max=sc["gauss_max"],
+            rho_max=sc["rho_max"])
+    assert l2 < l2_tol, l2
+    assert len(ev_o) >= min_events
+    # identical event sets (every measured run so far: a difference would need
+    # a draw within the FP32 rounding of P)
+    assert ev_g == ev_o, (len(ev_g), len(ev_o), len(ev_g & ev_o))
+    assert sc["events"] == len(ev_g)
+    # energy budget: the field energy and the Poynting flux at FP32 accuracy of
+    # the fields; kinetic and gap energies within the accuracy target
+    e_in = sim.energy_in
+    assert abs(sc["e_in"] / e_in - 1) < 2e-5, (sc["e_in"], e_in)
+    assert abs(sc["e_out"] - sim.energy_out) <= 2e-5 * e_in, (sc["e_out"], sim.energy_out)
+    # the field energy left in the box (small once the pulse has gone)
+    assert abs(sc["u_field"] - u_o) <= 2e-5 * u_o + 1e-6 * e_in, (sc["u_field"], u_o)
+    assert abs(sc["e_gap"] - sim.energy_gap) <= 1e-10 * sim.energy_gap
+    for key, ref in (("ke_e", ke_e_o), ("ke_pos", ke_p_o)):
+        if ref > 0:
+            assert abs(sc[key] / ref - 1) < rel_tol, (key, sc[key], ref)
+    # node grids: electron number and energy density (Sec. 4.1, 4.2), and the
+    # windowed amplitude over the window's nodes
+    sl = _node_slices(sim)
+    for got, want in ((ctx.ne_grid(), sim.density_grid("e")[sl]),
+                      (ctx.ue_grid(), sim.energy_density_grid("e")[sl])):
+        assert got.shape == want.shape
+        assert np.max(np.abs(got - want)) <= 1e-3 * max(np.max(np.abs(want)), 1e-300)
+    A_g = ctx.amp().astype(np.float64)
+    A_o = sim.A[sl]
+    mat = np.nonzero(sim.P.mat_node >= 0)[0]
+    if len(mat):
+        rng = slice(max(0, mat[0] - 1), mat[-1] + 2)
+        ref = max(np.max(A_o[rng]), amp_ref or 0.0)
+        assert np.max(np.abs(A_g[rng] - A_o[rng])) <= 2e-5 * ref
     assert abs(sc["n_e"] - ne_o) <= max(1.0, rel_tol * ne_o)
-    eabs_o = sim.kinetic_energy() + sim.energy_gap
     if eabs_o > 0:
         assert abs(sc["e_abs"] / eabs_o - 1) < rel_tol, (sc["e_abs"], eabs_o)
     # the device Gauss residual stays at FP32 roundoff of the charge density;
@@ -285,17 +354,29 @@ def _compare_run(P, ctx, sim, l2_tol=1e-5, rel_tol=5e-3, min_events=1, name=""):
 def test_run_1d_slab_high_intensity(P):
     cfg = W.config_1d(hi=True, ppc=10, nsteps=1400)
     ctx, sim = _run_both(P, cfg, 1400)
-    l2, sc = _compare_run(P, ctx, sim, min_events=20, name="run_1d")
-    # amplitude window against the oracle's brute-force maximum
-    A_g = ctx.amp()[:, 0, 0].astype(np.float64)
-    A_o = sim.A[OP.G:OP.G + cfg["n"][0] + 1, 0, 0]
-    mat = np.nonzero(sim.P.mat_node >= 0)[0]
-    rng = slice(mat[0] - 1, mat[-1] + 2)
-    assert np.max(np.abs(A_g[rng] - A_o[rng])) <= 2e-5 * np.max(A_o[rng])
-    # electron density grid
-    ne_g = ctx.ne_grid()[:, 0, 0]
-    ne_o = sim.density_grid("e")[OP.G:OP.G + cfg["n"][0] + 1, 0, 0]
-    assert np.max(np.abs(ne_g - ne_o)) <= 1e-3 * max(np.max(ne_o), 1.0)
+    _compare_run(P, ctx, sim, min_events=20, name="run_1d")
+    ctx.close()
+
+
+@pytest.mark.parametrize("hi", [False, True], ids=["1e13", "1e14"])
+def test_run_1d_slab_as_configured(P, hi):
+    """The 1D workload exactly as configured: 1024 cells at lambda/40, the
+    n = 1.45 slab over cells 400-600 with 100 neutrals per cell, a 2-cycle
+    pulse, 2000 steps at CFL 0.95, seed 0; at 1e13 W/cm^2 (no ionization is
+    expected: about 0.02 events) and at 1e14 W/cm^2 (hundreds of events)."""
+    cfg = W.config_1d(hi=hi)
+    assert cfg["ppc"] == 100 and cfg["nsteps"] == 2000 and cfg["n"] == [1024]
+    # step 1000: the pulse has crossed the slab and is still in the box
+    ctx, sim = _run_both(P, cfg, 1000)
+    tag = "run_1d_c1_" + ("hi" if hi else "lo")
+    _compare_run(P, ctx, sim, min_events=20 if hi else 0, name=tag + "_1000")
+    norm = _field_norm(sim)
+    amp = float(np.max(sim.A))
+    # step 2000: the pulse has left; the field left behind (reflections inside
+    # the slab, the plasma's own field) is compared against the norm at step 1000
+    ctx.step(1000)
+    sim.run(1000)
+    _compare_run(P, ctx, sim, min_events=100 if hi else 0, name=tag + "_2000", norm=norm, amp_ref=amp)
     ctx.close()
 
 
@@ -360,6 +441,7 @@ def test_stress_preionized_2d(P):
     sc = ctx.scalars()
     assert sc["n_e"] == np.sum(sim.pk % 2 == 0)
     l2 = _field_l2(ctx, sim)
+    _record("stress_2d", field_l2=l2, ke_e_gpu=sc["ke_e"], ke_e_oracle=sim.kinetic_energy("e"))
     assert l2 < 1e-4, l2
     ke_o = sim.kinetic_energy("e")
     assert abs(sc["ke_e"] / ke_o - 1) < 1e-4

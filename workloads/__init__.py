@@ -227,3 +227,37 @@ def random_state(cfg, n_particles, seed, e_scale=3e10, u_scale=0.3, margin=3.0):
     nk = 2 * len(cfg["materials"])
     kind = rng.integers(0, nk, n_particles)
     return dict(E=E, b=b, cell=cell, off=off, u=u, kind=kind)
+
+
+def face_state(cfg, n_per_face, seed, e_scale=1e9, u_out=(0.3, 2.0)):
+    """A seeded state with charged particles in the cells next to every outflow
+    face (x faces always; y, z faces when the transverse boundaries are
+    outflow), each moving outward with |u| along the face normal drawn from
+    ``u_out`` and random transverse components, so that they leave the box
+    within a few steps; E and b random on every in-box position."""
+    rng = np.random.default_rng(seed)
+    D = cfg["ndim"]
+    per = cfg.get("transverse_bc", "outflow") == "periodic"
+    E = [rng.uniform(-e_scale, e_scale, domain_shape(cfg, "E", c)) for c in range(3)]
+    b = [rng.uniform(-e_scale, e_scale, domain_shape(cfg, "b", c)) for c in range(3)]
+    cells, offs, us = [], [], []
+    for d in range(D):
+        if per and d > 0:
+            continue
+        for side in (0, 1):
+            cell = np.zeros((n_per_face, 3), dtype=np.int64)
+            for e in range(D):
+                cell[:, e] = rng.integers(0, cfg["n"][e], n_per_face)
+            cell[:, d] = 0 if side == 0 else cfg["n"][d] - 1
+            off = np.zeros((n_per_face, 3), dtype=np.float32)
+            for e in range(D):
+                off[:, e] = rng.integers(0, 2 ** 24, n_per_face).astype(np.float32) * np.float32(2.0 ** -24)
+            u = rng.normal(0.0, 0.2, (n_per_face, 3))
+            u[:, d] = rng.uniform(u_out[0], u_out[1], n_per_face) * (-1.0 if side == 0 else 1.0)
+            cells.append(cell)
+            offs.append(off)
+            us.append(u)
+    cell = np.concatenate(cells)
+    nk = 2 * len(cfg["materials"])
+    kind = rng.integers(0, nk, len(cell))
+    return dict(E=E, b=b, cell=cell, off=np.concatenate(offs), u=np.concatenate(us), kind=kind)
