@@ -371,6 +371,18 @@ typedef struct {
  * PIC_E_NOMEM, PIC_E_DEVICE. */
 pic_status pic_spectrum_counts(pic_ctx* c, const pic_spectrum* s, uint64_t* out, size_t out_count);
 
+/* The same energy histogram without any device allocation, for callers that
+ * cannot allocate device memory mid-run (code inside HIP graph capture, tight
+ * serving loops, hosts that forbid hipMalloc): the edges and counts are staged
+ * in a fixed device array of the library (557 KB, one per GPU, held until the
+ * process ends; its address is resolved once per GPU by pic_init).  Same
+ * arguments, limits (at most 4097 edges, else PIC_E_INVAL) and results as
+ * pic_spectrum_counts.  Every call on one GPU shares that array: calls that
+ * overlap in time on one GPU (from several threads, or contexts on different
+ * streams) race and must be serialised by the caller.  Errors: PIC_E_INVAL,
+ * PIC_E_DEVICE. */
+pic_status pic_spectrum_counts_noalloc(pic_ctx* c, const pic_spectrum* s, uint64_t* out, size_t out_count);
+
 /* A recorded position of a sampled particle: id (the parent neutral's id,
  * cell index x ppc + k; particles placed by pic_set_state: cells x ppc + their
  * index), kind, the step index after which it was taken, and the position

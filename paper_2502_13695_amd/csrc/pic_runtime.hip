@@ -306,6 +306,31 @@ void dev_free(pic_ctx* c, void* p) {
 constexpr int kSpecEdges = 4097;
 constexpr size_t kSpecBytes = sizeof(double) * kSpecEdges + sizeof(unsigned long long) * MAXKIND * (kSpecEdges + 1);
 
+// Staging of the allocation-free energy histogram (pic_spectrum_counts_noalloc):
+// the edges and counts of one call, up to the same maximum as the allocating
+// entry point (557 KB).  Every GPU the library runs on holds one copy until the
+// process ends; calls on one GPU share it.
+static __device__ __align__(256) unsigned char scratch[kSpecBytes];
+
+// Its device address on each GPU, resolved with that GPU current (pic_init,
+// or the entry point's first call on a GPU no context was created on).
+constexpr int kMaxDevices = 64;
+void* g_scratch[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+pic_status scratch_ptr(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return PIC_E_DEVICE;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return PIC_E_DEVICE;
+    g_scratch[dev] = p;
+  }
+  *out = g_scratch[dev];
+  return PIC_OK;
+}
+
 Group single(pic_ctx* c, int phase, int nb) {
   Group g{c->d_inst, phase == 1 ? c->d_off_fields : c->d_off + 2 * phase, 1, nb, (int)c->step};
   g.front = &c->d_ctr->front;
@@ -679,6 +704,10 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
     pic_destroy(c);
     return s;
   };
+  {
+    void* sp = nullptr;   // the allocation-free histogram's staging on this GPU
+    if (scratch_ptr(&sp) != PIC_OK) return fail(PIC_E_DEVICE);
+  }
   if (hipHostMalloc((void**)&c->h_step, sizeof(int)) != hipSuccess) return fail(PIC_E_NOMEM);
   if (hipMemsetAsync(c->base, 0, L.total, c->stream) != hipSuccess) return fail(PIC_E_DEVICE);
 
@@ -1049,6 +1078,15 @@ pic_status pic_spectrum_counts(pic_ctx* c, const pic_spectrum* sp, uint64_t* out
     if (!c->d_spec) return PIC_E_NOMEM;
   }
   return spectrum_into(c, sp, out, out_count, c->d_spec);
+}
+
+pic_status pic_spectrum_counts_noalloc(pic_ctx* c, const pic_spectrum* sp, uint64_t* out, size_t out_count) {
+  pic_status st = spectrum_check(c, sp, out, out_count);
+  if (st != PIC_OK) return st;
+  void* buf = nullptr;
+  st = scratch_ptr(&buf);
+  if (st != PIC_OK) return st;
+  return spectrum_into(c, sp, out, out_count, buf);
 }
 
 pic_status pic_set_tracks(pic_ctx* c, uint32_t threshold, int32_t every, int64_t max_records) {

@@ -98,7 +98,7 @@ SYMBOLS = ["pic_init", "pic_step", "pic_diag", "pic_set_state", "pic_footprint",
            "pic_batch_step", "pic_batch_add", "pic_batch_remove", "pic_batch_destroy", "pic_batch_set_graph",
            "pic_batch_graph_replays",
            "pic_set_timing", "pic_autotune", "pic_autotune_steps", "pic_set_resort", "pic_set_far_tiles",
-           "pic_set_imax", "pic_spectrum_counts", "pic_set_tracks",
+           "pic_set_imax", "pic_spectrum_counts", "pic_spectrum_counts_noalloc", "pic_set_tracks",
            "pic_snapshot", "pic_restore",
            "pic_destroy", "pic_status_str"]
 
@@ -150,6 +150,8 @@ def lib():
             "pic_snapshot": ([vp, vp, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
             "pic_restore": ([vp, vp, C.c_size_t], C.c_int),
             "pic_spectrum_counts": ([vp, C.POINTER(Spectrum), C.POINTER(C.c_uint64), C.c_size_t], C.c_int),
+            "pic_spectrum_counts_noalloc": ([vp, C.POINTER(Spectrum), C.POINTER(C.c_uint64), C.c_size_t],
+                                            C.c_int),
             "pic_batch_set_graph": ([vp, i32], C.c_int),
             "pic_batch_graph_replays": ([vp], C.c_int64),
             "pic_destroy": ([vp], None),
@@ -408,6 +410,18 @@ class Context:
         sp = Spectrum(len(e), e.ctypes.data_as(C.POINTER(C.c_double)), int(x_lo_cell), int(x_hi_cell))
         _check(lib().pic_spectrum_counts(self.h, C.byref(sp), out.ctypes.data_as(C.POINTER(C.c_uint64)),
                                          out.size), "pic_spectrum_counts")
+        return out
+
+    def spectrum_noalloc(self, edges_eV, x_lo_cell=0, x_hi_cell=0):
+        """The energy histogram through the library's fixed device staging (no
+        device allocation; calls on one GPU must not overlap)."""
+        e = np.ascontiguousarray(edges_eV, dtype=np.float64)
+        nk = 2 * self.nmat
+        out = np.zeros((nk, len(e) + 1), dtype=np.uint64)
+        sp = Spectrum(len(e), e.ctypes.data_as(C.POINTER(C.c_double)), int(x_lo_cell), int(x_hi_cell))
+        _check(lib().pic_spectrum_counts_noalloc(self.h, C.byref(sp),
+                                                 out.ctypes.data_as(C.POINTER(C.c_uint64)), out.size),
+               "pic_spectrum_counts_noalloc")
         return out
 
     def events(self):
