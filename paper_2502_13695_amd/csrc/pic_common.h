@@ -99,7 +99,7 @@ __host__ __device__ inline float table_lookup(const TabHdr* __restrict__ h, floa
 // for its births until the next sort: electrons and positive carriers in two
 // halves, each as large as the tile's alive neutrals (immobile, ionized once).
 __host__ __device__ constexpr int ptile_ext(int D, int axis) {
-  return axis >= D ? 1 : (D == 1 ? 128 : (D == 2 ? 16 : 8));
+  return axis >= D ? 1 : (D == 1 ? 128 : (D == 2 ? 16 : (axis == 2 ? 4 : 8)));
 }
 __host__ __device__ constexpr int ptile_cells(int D) {
   return ptile_ext(D, 0) * ptile_ext(D, 1) * ptile_ext(D, 2);
@@ -174,6 +174,7 @@ struct Inst {
   int* tslack;                  // birth room: events the tile can still take
   int* tfill;                   // events taken since the sort
   int* talive;                  // upper bound of the tile's alive neutrals
+  int* tperm;                   // slot order inside the tile: rank r goes to (r tperm) mod count
   int4* chunks;                 // {tile, first slot, end slot, first birth slot or -1}
   float jscale, jscale_inv;     // LDS fixed-point scale of the deposit and its inverse
   int* sctl;                    // SC_* words

@@ -460,7 +460,7 @@ struct FWin {
 
 // Threads per push block.  In 3D the two LDS windows (85 KB) take most of a
 // CU's LDS, so one block of 16 waves per CU shares them.
-__host__ __device__ constexpr int push_tpb(int D) { return D == 3 ? 1024 : 256; }
+__host__ __device__ constexpr int push_tpb(int D) { return D == 3 ? 512 : 256; }
 
 template <int ORDER>
 __device__ __forceinline__ void make_axis_l(Axis<ORDER>& a, int c, float t, int origin, int stride) {
@@ -660,7 +660,7 @@ __device__ __forceinline__ int item_slot(int i, int lo, int n_sorted, int b0, in
 // unsorted tail (particles placed or born beyond the tiles' layout) through
 // HBM.  ONE: a single run, its parameter block passed by value.
 template <int D, int ORDER, bool PY, bool PZ, bool ONE>
-__global__ __launch_bounds__(push_tpb(D)) void k_push(Group g, std::conditional_t<ONE, Inst, NoInst> one) {
+__global__ __launch_bounds__(push_tpb(D), D == 3 ? 4 : 1) void k_push(Group g, std::conditional_t<ONE, Inst, NoInst> one) {
   constexpr int NT = push_tpb(D);
   __shared__ unsigned long long sJ[3 * PWin<D>::N];
   __shared__ float sF[6 * FWin<D>::N];
@@ -928,6 +928,26 @@ __global__ __launch_bounds__(SCAN_TPB) void k_sort_scan(Group g) {
     const int cap = fit ? I.talive[t] : 0;
     const long long ts = pp;
     const int bl = (int)(ts + n);   // first birth slot
+    // slot order inside the tile: the particles the scatter ranks r = 0, 1, ...
+    // (arriving roughly cell by cell) go to slots (r P) mod n, P coprime with n
+    // and near n / 64, so the 64 lanes of a wave hold particles from all over
+    // the tile: few lanes share a cell, and few LDS atomics of one
+    // instruction hit the same node (same-node lanes serialise)
+    int P = 1;
+    if (n >= 128) {
+      P = (n >> 6) | 1;
+      for (;;) {
+        int a = P, b = n;
+        while (b) {
+          const int r = a % b;
+          a = b;
+          b = r;
+        }
+        if (a == 1) break;
+        P += 2;
+      }
+    }
+    I.tperm[t] = P;
     I.tcnt[t] = 0;              // the scatter's rank counter
     I.tstart[t] = (int)ts;
     I.tbirth[t] = bl;
@@ -991,7 +1011,9 @@ __global__ __launch_bounds__(TPB) void k_sort_scatter(Group g) {
     }
     const int r = wave_rank_add(I.tcnt, t);
     if (t < 0) continue;
-    const int d = I.tstart[t] + r;
+    const int ts = I.tstart[t];
+    const unsigned n = (unsigned)(I.tbirth[t] - ts);
+    const int d = ts + (int)(((unsigned long long)(unsigned)r * (unsigned)I.tperm[t]) % n);
     if ((unsigned)d >= (unsigned)I.capacity) continue;
     I.scell[d] = pc;
     I.skind[d] = kd;

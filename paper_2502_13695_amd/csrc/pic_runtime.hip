@@ -68,7 +68,7 @@ struct Layout {
   size_t o_pcell, o_po[3], o_pu[3], o_pkind, o_pid;
   int ntile[3];
   int64_t ntiles, maxchunks;
-  size_t o_tcnt, o_tstart, o_tbirth, o_tslack, o_tfill, o_talive, o_chunks;
+  size_t o_tcnt, o_tstart, o_tbirth, o_tslack, o_tfill, o_talive, o_tperm, o_chunks;
   size_t o_scell, o_so[3], o_su[3], o_skind, o_spid;
   size_t o_tab[MAXMAT];
   size_t o_ctr;      // pcount, step, health, nevents[MAXMAT], diag accumulators
@@ -175,6 +175,7 @@ pic_status plan(const pic_config* cfg, const Canon& c, const std::vector<TableHo
   L->o_tslack = take(sizeof(int) * L->ntiles);
   L->o_tfill = take(sizeof(int) * L->ntiles);
   L->o_talive = take(sizeof(int) * L->ntiles);
+  L->o_tperm = take(sizeof(int) * L->ntiles);
   L->o_chunks = take(sizeof(int4) * L->maxchunks);
   L->o_scell = take(sizeof(uint32_t) * L->capacity);
   for (int q = 0; q < 3; ++q) L->o_so[q] = take(q < D ? sizeof(float) * L->capacity : 0);
@@ -798,6 +799,7 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
   I.tslack = (int*)devp(c, L.o_tslack);
   I.tfill = (int*)devp(c, L.o_tfill);
   I.talive = (int*)devp(c, L.o_talive);
+  I.tperm = (int*)devp(c, L.o_tperm);
   I.chunks = (int4*)devp(c, L.o_chunks);
   I.scell = (uint32_t*)devp(c, L.o_scell);
   I.so0 = (float*)devp(c, L.o_so[0]);
