@@ -269,6 +269,15 @@ pic_status pic_keldysh_rate(const pic_material* m, double lambda_m, int32_t term
 pic_status pic_table_probe(const pic_config* cfg, int32_t mat, const float* A, int64_t n,
                            float* P_out);
 
+/* Bound the ionization step uses to skip a neutral before it reads the
+ * neutral's amplitude (Sec. 2.1, Eq. 1-3 through the table): for each of n
+ * FP32 amplitudes A, a value B(A) >= the table lookup of every FP32 amplitude
+ * A' <= A, nondecreasing in A, 0 below the cut and 1 from saturation on.  A
+ * draw (w + 1/2) 2^-32 >= B(A) can fire for no amplitude up to A.  Host-only;
+ * same arguments and errors as pic_table_probe. */
+pic_status pic_table_bound_probe(const pic_config* cfg, int32_t mat, const float* A, int64_t n,
+                                 float* B_out);
+
 /* The same lookup executed on the device of context c (host in/out buffers). */
 pic_status pic_table_probe_device(pic_ctx* c, int32_t mat, const float* A, int64_t n,
                                   float* P_out);

@@ -286,6 +286,27 @@ Split split_r(const Ctx& k, double A, double N) {
   return s;
 }
 
+// largest value of c0 + c1 f + c2 f^2 + c3 f^3 over [lo, hi]: the ends and
+// the stationary points inside
+double cubic_max(const double* c, double lo, double hi) {
+  auto val = [&](double f) { return c[0] + f * (c[1] + f * (c[2] + f * c[3])); };
+  double m = std::max(val(lo), val(hi));
+  const double a = 3.0 * c[3], b = 2.0 * c[2], cc = c[1];   // derivative a f^2 + b f + cc
+  if (a == 0.0) {
+    if (b != 0.0) {
+      const double f = -cc / b;
+      if (f > lo && f < hi) m = std::max(m, val(f));
+    }
+    return m;
+  }
+  const double disc = b * b - 4.0 * a * cc;
+  if (disc < 0.0) return m;
+  const double sq = std::sqrt(disc);
+  for (double f : {(-b - sq) / (2.0 * a), (-b + sq) / (2.0 * a)})
+    if (f > lo && f < hi) m = std::max(m, val(f));
+  return m;
+}
+
 // monomial coefficients of the cubic through (t_j, y_j), j = 0..3
 void cubic_fit(const double* t, const double* y, double* c) {
   double M[4][5];
@@ -373,6 +394,7 @@ pic_status build_table(const Canon& c, int mat, int terms, TableHost* out, int t
   const int nseg = (int)bounds.size() - 1;
   std::vector<TabSeg> segs(nseg);
   std::vector<float> recs;
+  double running = 0.0;   // running maximum of the per-interval lookup bounds
   int base = 0;
   for (int s = 0; s < nseg; ++s) {
     const double lo = bounds[s], hi = bounds[s + 1];
@@ -416,8 +438,27 @@ pic_status build_table(const Canon& c, int mat, int terms, TableHost* out, int t
       }
       cubic_fit(t, y1, c1);
       cubic_fit(t, y2, c2);
-      const float rec[TAB_REC] = {(float)An[i], (float)c1[0], (float)c1[1], (float)c1[2], (float)c1[3],
-                                  (float)c2[0], (float)c2[1], (float)c2[2], (float)c2[3], 0.f, 0.f, 0.f};
+      float rec[TAB_REC] = {(float)An[i], (float)c1[0], (float)c1[1], (float)c1[2], (float)c1[3],
+                            (float)c2[0], (float)c2[1], (float)c2[2], (float)c2[3], 0.f, 0.f, 0.f};
+      // bound of the lookup over this interval, from the stored FP32
+      // coefficients: the largest cubic value over a slightly widened local
+      // coordinate range, plus the closing term at its largest distance
+      const double fl = -1e-3, fh = 1.0 + 1e-3;
+      const double q1[4] = {rec[1], rec[2], rec[3], rec[4]}, q2[4] = {rec[5], rec[6], rec[7], rec[8]};
+      double rb = cubic_max(q1, fl, fh);
+      double mag = std::fabs(q1[0]) + std::fabs(q1[1]) + std::fabs(q1[2]) + std::fabs(q1[3]);
+      if (sig) {
+        const double dmax = std::max(0.0, (hi - ((double)rec[0] + fl / (double)inv_h)) - (hi - Ak));
+        const double m2 = std::max(0.0, cubic_max(q2, fl, fh));
+        rb += std::sqrt(dmax) * m2;
+        mag += std::sqrt(dmax) * (std::fabs(q2[0]) + std::fabs(q2[1]) + std::fabs(q2[2]) + std::fabs(q2[3]));
+      }
+      // FP32 evaluation of the Horner sums and of expm1f: a few ulp each
+      rb = rb * (1.0 + 1e-5) + 1e-6 * mag;
+      running = std::max(running, std::min(1.0, -std::expm1(-rb) * (1.0 + 1e-5)));
+      float rf = (float)running;
+      if ((double)rf < running) rf = std::nextafter(rf, INFINITY);
+      rec[9] = rf;
       recs.insert(recs.end(), rec, rec + TAB_REC);
     }
     segs[s] = TabSeg{(float)lo, (float)hi, inv_h, base, nint, sig ? 1 : 0, (float)(hi - Ak), 0};

@@ -89,6 +89,21 @@ __host__ __device__ inline float table_lookup(const TabHdr* __restrict__ h, floa
   return -expm1f(-r);
 }
 
+// Upper bound of table_lookup(h, A') over every A' <= A (the records hold the
+// running maximum of per-interval bounds, slot 9): a draw at or above it cannot
+// fire for any amplitude up to A, so the amplitude itself need not be known.
+__host__ __device__ inline float table_bound(const TabHdr* __restrict__ h, float A) {
+  if (!(A >= h->acut)) return 0.0f;
+  if (A >= h->asat) return 1.0f;
+  const TabSeg* seg = reinterpret_cast<const TabSeg*>(h + 1);
+  int k = 0;
+  while (k + 1 < h->nseg && A >= seg[k].hi) ++k;
+  const TabSeg s = seg[k];
+  int i = (int)((A - s.lo) * s.inv_h);
+  i = i < 0 ? 0 : (i >= s.nint ? s.nint - 1 : i);
+  return reinterpret_cast<const float*>(seg + h->nseg)[TAB_REC * (s.base + i) + 9];
+}
+
 // ------------------------------------------------------- particle tiles
 // The charged particles are kept sorted by tile of the deposit (counting sort,
 // redone when enough particles have left their tile or landed beyond the

@@ -207,6 +207,20 @@ __device__ __forceinline__ float gather(const float* __restrict__ Fp, const Axis
 // move of at most one cell can touch, from `org` = the lower of the start and
 // end shape bases: S0 = start weights, DS = end - start weights.  A move that
 // keeps its shape base leaves node W - 1 zero.
+//
+// DS is formed from the two positions' local coordinates, which are exact
+// FP32 numbers, in factored form: subtracting the two sets of rounded weights
+// would leave an absolute error of a few 1e-8 on every node whatever the move,
+// i.e. a relative error of 1e-5 on the current of a particle that moves 1e-3
+// cells per step (a thermal plasma).  Quadratic shape, start offset xi0 and
+// end offset xi1 from the centres of their own stencils:
+//   same base:   d = xi1 - xi0, s = xi0 + xi1;
+//                DS = (-d (1 - s) / 2, -d s, d (1 + s) / 2)
+//   base up:     a = xi0 - 1/2 <= 0, e = xi1 + 1/2 >= 0 (both exact near the
+//                crossing); DS = (-a^2/2, (a - e) + a^2 + e^2/2,
+//                (e - a) - e^2 - a^2/2, e^2/2)
+//   base down:   the mirror image (a = -xi0 - 1/2, e = 1/2 - xi1, reversed).
+// Linear shape: d = t1 - t0 on a kept cell, else 1 - t formed first.
 template <int ORDER>
 struct Esk {
   static constexpr int W = ORDER + 2;
@@ -216,27 +230,76 @@ struct Esk {
 };
 
 template <int ORDER>
-__device__ __forceinline__ float esk_pick(const float* w, int o, int q) {
-  // weight at compact node q of a shape whose first weight sits at node o
-  if (q == 0) return o ? 0.0f : w[0];
-  if (q == ORDER + 1) return o ? w[ORDER] : 0.0f;
-  return o ? w[q - 1] : w[q];
-}
-
-template <int ORDER>
 __device__ __forceinline__ void esk_axis(Esk<ORDER>& e, int c0, float t0, int c1, float t1) {
-  float w0[ORDER + 1], w1[ORDER + 1];
-  const int b0 = shape<ORDER>(c0, t0, 0, w0);
-  const int b1 = shape<ORDER>(c1, t1, 0, w1);
-  const int sh = b1 - b0;   // -1, 0, 1
-  e.org = sh < 0 ? b1 : b0;
-  e.moved = sh != 0;
-  const int o0 = sh < 0 ? 1 : 0, o1 = sh > 0 ? 1 : 0;
-#pragma unroll
-  for (int q = 0; q < Esk<ORDER>::W; ++q) {
-    const float a0 = esk_pick<ORDER>(w0, o0, q);
-    e.S0[q] = a0;
-    e.DS[q] = esk_pick<ORDER>(w1, o1, q) - a0;
+  if (ORDER == 2) {
+    const int up0 = t0 >= 0.5f, up1 = t1 >= 0.5f;
+    const float xi0 = t0 - (float)up0, xi1 = t1 - (float)up1;
+    const float w0 = 0.5f * (0.5f - xi0) * (0.5f - xi0);
+    const float w1 = 0.75f - xi0 * xi0;
+    const float w2 = 0.5f * (0.5f + xi0) * (0.5f + xi0);
+    const int b0 = c0 + up0 - 1;
+    const int sh = (c1 + up1 - 1) - b0;   // -1, 0, 1
+    e.moved = sh != 0;
+    if (sh < 0) {
+      const float a = -0.5f - xi0, f = 0.5f - xi1;
+      e.org = b0 - 1;
+      e.S0[0] = 0.0f;
+      e.S0[1] = w0;
+      e.S0[2] = w1;
+      e.S0[3] = w2;
+      e.DS[0] = 0.5f * f * f;
+      e.DS[1] = (f - a) - f * f - 0.5f * a * a;
+      e.DS[2] = (a - f) + a * a + 0.5f * f * f;
+      e.DS[3] = -0.5f * a * a;
+    } else {
+      e.org = b0;
+      e.S0[0] = w0;
+      e.S0[1] = w1;
+      e.S0[2] = w2;
+      e.S0[3] = 0.0f;
+      if (sh > 0) {
+        const float a = xi0 - 0.5f, f = xi1 + 0.5f;
+        e.DS[0] = -0.5f * a * a;
+        e.DS[1] = (a - f) + a * a + 0.5f * f * f;
+        e.DS[2] = (f - a) - f * f - 0.5f * a * a;
+        e.DS[3] = 0.5f * f * f;
+      } else {
+        const float d = xi1 - xi0, sm = xi0 + xi1;
+        e.DS[0] = -0.5f * d * (1.0f - sm);
+        e.DS[1] = -d * sm;
+        e.DS[2] = 0.5f * d * (1.0f + sm);
+        e.DS[3] = 0.0f;
+      }
+    }
+  } else {
+    const int sh = c1 - c0;
+    e.moved = sh != 0;
+    if (sh < 0) {
+      e.org = c0 - 1;
+      e.S0[0] = 0.0f;
+      e.S0[1] = 1.0f - t0;
+      e.S0[2] = t0;
+      const float r1 = 1.0f - t1;
+      e.DS[0] = r1;
+      e.DS[1] = t0 - r1;
+      e.DS[2] = -t0;
+    } else {
+      e.org = c0;
+      const float r0 = 1.0f - t0;
+      e.S0[0] = r0;
+      e.S0[1] = t0;
+      e.S0[2] = 0.0f;
+      if (sh > 0) {
+        e.DS[0] = -r0;
+        e.DS[1] = r0 - t1;
+        e.DS[2] = t1;
+      } else {
+        const float d = t1 - t0;
+        e.DS[0] = -d;
+        e.DS[1] = d;
+        e.DS[2] = 0.0f;
+      }
+    }
   }
 }
 
@@ -1606,16 +1669,22 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g, std::conditional_t<ONE,
 // ------------------------------------------------------------- ionization
 __device__ __forceinline__ void maxwell(uint64_t seed, uint64_t id, uint32_t purpose, float sig,
                                         float& ux, float& uy, float& uz) {
+  // Box-Muller in FP64, rounded once at the end: in FP32 the uniform next to
+  // 1 keeps only 24 bits of 1 - u, so -2 log u (hence a small radius) would
+  // carry relative errors up to 1e-3
   const u32x4 w = draw(seed, id, 0u, purpose);
-  const float u1 = (float)(((double)w.x + 0.5) * 0x1p-32);
-  const float u2 = (float)(((double)w.y + 0.5) * 0x1p-32);
-  const float u3 = (float)(((double)w.z + 0.5) * 0x1p-32);
-  const float u4 = (float)(((double)w.w + 0.5) * 0x1p-32);
-  const float r1 = sqrtf(-2.0f * logf(u1)), r2 = sqrtf(-2.0f * logf(u3));
-  const float tp = 6.2831853071795864769f;
-  ux = sig * r1 * cosf(tp * u2);
-  uy = sig * r1 * sinf(tp * u2);
-  uz = sig * r2 * cosf(tp * u4);
+  const double u1 = ((double)w.x + 0.5) * 0x1p-32;
+  const double u2 = ((double)w.y + 0.5) * 0x1p-32;
+  const double u3 = ((double)w.z + 0.5) * 0x1p-32;
+  const double u4 = ((double)w.w + 0.5) * 0x1p-32;
+  const double r1 = sqrt(-2.0 * log(u1)), r2 = sqrt(-2.0 * log(u3));
+  const double tp = 6.283185307179586476925;
+  double s2, c2;
+  sincos(tp * u2, &s2, &c2);
+  const double sg = (double)sig;
+  ux = (float)(sg * (r1 * c2));
+  uy = (float)(sg * (r1 * s2));
+  uz = (float)(sg * (r2 * cos(tp * u4)));
 }
 
 template <class IT>
@@ -1640,17 +1709,24 @@ struct Birth {
   float t0, t1, t2;
 };
 template <int D, int ORDER, class IT>
-__device__ __forceinline__ Birth ionize_decide(const IT& I, int64_t jn, int64_t m, uint32_t pcell, int mat,
-                                               int step);
+__device__ __forceinline__ Birth ionize_decide(const IT& I, int64_t jn, int ci, int cj, int ck, uint64_t id,
+                                               int mat, uint32_t wx);
 
 // Ionization of the alive neutrals with the amplitude after the field update.
 // A block first marks which of its material cells can ionize at all: the
 // largest windowed amplitude over the nodes any neutral of the cell can reach
 // must reach the material's cut (an exact test: the shape weights are
 // non-negative and sum to one).  Neutrals of the other cells read nothing more.
+// A hot cell also keeps the table's bound of P up to that amplitude: each of
+// its neutrals draws first, and only a draw below the bound (a few times the
+// step's events) loads the neutral and gathers its amplitude.  The decision
+// is the same as gathering first: the gathered amplitude never exceeds the
+// cell's largest (times 1 + 2^-16, which covers the FP32 sum of non-negative
+// weights), and the bound covers the lookup at every amplitude below it.
 template <int D, int ORDER, bool ONE>
 __global__ __launch_bounds__(TPB) void k_ionize(Group g, std::conditional_t<ONE, Inst, NoInst> one) {
   __shared__ unsigned char hot[TPB + 2];
+  __shared__ float spb[TPB + 2];        // bound of P over the cell's reachable amplitudes
   __shared__ uint32_t scell[TPB + 2];   // packed cell and material of each cell of the block
   __shared__ signed char smat[TPB + 2];
   const Slot sl = ONE ? Slot{0, (int)blockIdx.x, g.blocks} : block_slot(g);
@@ -1691,7 +1767,9 @@ __global__ __launch_bounds__(TPB) void k_ionize(Group g, std::conditional_t<ONE,
       const uint32_t mask = hi_b - lo_b == 32 ? ~0u : ((1u << (hi_b - lo_b)) - 1u) << lo_b;
       alive = (I.alive[w] & mask) != 0u;
     }
-    hot[t] = alive && mat >= 0 && amax >= I.acut[mat];
+    const bool h = alive && mat >= 0 && amax >= I.acut[mat];
+    hot[t] = h;
+    spb[t] = h ? table_bound(I.tab[mat], amax * (1.0f + 0x1p-16f)) : 0.0f;
   }
   __syncthreads();
   const int64_t jn = j0 + threadIdx.x;
@@ -1699,7 +1777,15 @@ __global__ __launch_bounds__(TPB) void k_ionize(Group g, std::conditional_t<ONE,
   if (jn < nneut) {
     const int64_t mn = div_ppc(I, jn);
     const int t = (int)(mn - m0);
-    if (hot[t]) b = ionize_decide<D, ORDER>(I, jn, mn, scell[t], smat[t], step);
+    if (hot[t]) {
+      int ci, cj, ck;
+      unpack_cell(D, scell[t], ci, cj, ck);
+      const int64_t lin = ci + (int64_t)I.nx * (cj + (int64_t)I.ny * ck);
+      const uint64_t id = (uint64_t)(lin * I.ppc + (jn - mn * I.ppc));
+      const u32x4 w = draw(I.seed, id, (uint32_t)(step + 1), PURPOSE_IONIZE);
+      if ((double)w.x + 0.5 < (double)spb[t] * 4294967296.0)
+        b = ionize_decide<D, ORDER>(I, jn, ci, cj, ck, id, smat[t], w.x);
+    }
   }
   // the wave's events: one slot reservation per tile, one event count per
   // material, one alive-mask update per 32-neutral word (a wave holds 64
@@ -1775,32 +1861,33 @@ __global__ void k_advance(Inst* insts, int n) {
   }
 }
 
-// The cell and its material come from the block's per-cell pass; the alive
-// bit and the offsets are loaded together (one round trip).
+// A neutral whose draw fell below its cell's bound: the alive bit and the
+// offsets (loaded together, one round trip), the amplitude gathered at the
+// neutral, the exact FP64 comparison of the draw with P.
 template <int D, int ORDER, class IT>
-__device__ __forceinline__ Birth ionize_decide(const IT& I, int64_t jn, int64_t m, uint32_t pcell, int mat,
-                                               int step) {
+__device__ __forceinline__ Birth ionize_decide(const IT& I, int64_t jn, int ci, int cj, int ck, uint64_t id,
+                                               int mat, uint32_t wx) {
   Birth b{};
   const uint32_t aw = I.alive[jn >> 5];
   b.t0 = I.no0[jn];
   b.t1 = D >= 2 ? I.no1[jn] : 0.f;
   b.t2 = D >= 3 ? I.no2[jn] : 0.f;
   if (!((aw >> (jn & 31)) & 1u)) return b;
-  unpack_cell(D, pcell, b.ci, b.cj, b.ck);
-  const int64_t lin = b.ci + (int64_t)I.nx * (b.cj + (int64_t)I.ny * b.ck);
-  b.id = (uint64_t)(lin * I.ppc + (jn - m * I.ppc));
+  b.ci = ci;
+  b.cj = cj;
+  b.ck = ck;
+  b.id = id;
   // amplitude at the neutral: node-shape gather of A
   Axis<ORDER> X, Y, Z;
-  make_axis<ORDER>(X, b.ci, b.t0, I.nx, 0, G, 1);
-  if (D >= 2) make_axis<ORDER>(Y, b.cj, b.t1, I.ny, I.per_y, I.Gy, I.sy);
-  if (D >= 3) make_axis<ORDER>(Z, b.ck, b.t2, I.nz, I.per_z, I.Gz, I.sz);
+  make_axis<ORDER>(X, ci, b.t0, I.nx, 0, G, 1);
+  if (D >= 2) make_axis<ORDER>(Y, cj, b.t1, I.ny, I.per_y, I.Gy, I.sy);
+  if (D >= 3) make_axis<ORDER>(Z, ck, b.t2, I.nz, I.per_z, I.Gz, I.sz);
   const float Ap = gather<D, ORDER>(I.A, X, Y, Z, 0, 0, 0);
   b.mat = mat;
   if (mat < 0 || !(Ap >= I.acut[mat])) return b;
   const float P = table_lookup(I.tab[mat], Ap);
-  const u32x4 w = draw(I.seed, b.id, (uint32_t)(step + 1), PURPOSE_IONIZE);
   // event iff (w + 1/2) 2^-32 < P, decided exactly in FP64
-  b.ev = (double)w.x + 0.5 < (double)P * 4294967296.0;
+  b.ev = (double)wx + 0.5 < (double)P * 4294967296.0;
   return b;
 }
 

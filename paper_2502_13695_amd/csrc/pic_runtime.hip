@@ -627,8 +627,9 @@ pic_status pic_keldysh_rate(const pic_material* m, double lambda_m, int32_t term
   return PIC_OK;
 }
 
-pic_status pic_table_probe(const pic_config* cfg, int32_t mat, const float* A, int64_t n, float* P_out) {
-  if (!cfg || !A || !P_out || n < 0) return PIC_E_INVAL;
+static pic_status table_probe_host(const pic_config* cfg, int32_t mat, const float* A, int64_t n, float* out,
+                                   bool bound) {
+  if (!cfg || !A || !out || n < 0) return PIC_E_INVAL;
   Canon c;
   pic_status st = canonicalize(cfg, &c);
   if (st != PIC_OK) return st;
@@ -636,8 +637,17 @@ pic_status pic_table_probe(const pic_config* cfg, int32_t mat, const float* A, i
   st = build_table(c, mat, cfg->keldysh_terms, &T, cfg->keldysh_tol_bits > 0 ? cfg->keldysh_tol_bits : 60);
   if (st != PIC_OK) return st;
   const TabHdr* h = reinterpret_cast<const TabHdr*>(T.bytes.data());
-  for (int64_t i = 0; i < n; ++i) P_out[i] = table_lookup(h, A[i]);
+  for (int64_t i = 0; i < n; ++i) out[i] = bound ? table_bound(h, A[i]) : table_lookup(h, A[i]);
   return PIC_OK;
+}
+
+pic_status pic_table_probe(const pic_config* cfg, int32_t mat, const float* A, int64_t n, float* P_out) {
+  return table_probe_host(cfg, mat, A, n, P_out, false);
+}
+
+pic_status pic_table_bound_probe(const pic_config* cfg, int32_t mat, const float* A, int64_t n,
+                                 float* B_out) {
+  return table_probe_host(cfg, mat, A, n, B_out, true);
 }
 
 pic_status pic_footprint(const pic_config* cfg, size_t* bytes) {

@@ -94,7 +94,8 @@ class State(C.Structure):
 
 
 SYMBOLS = ["pic_init", "pic_step", "pic_diag", "pic_set_state", "pic_footprint", "pic_canonical",
-           "pic_keldysh_rate", "pic_table_probe", "pic_table_probe_device", "pic_batch_create",
+           "pic_keldysh_rate", "pic_table_probe", "pic_table_bound_probe", "pic_table_probe_device",
+           "pic_batch_create",
            "pic_batch_step", "pic_batch_add", "pic_batch_remove", "pic_batch_destroy", "pic_batch_set_graph",
            "pic_batch_graph_replays",
            "pic_set_timing", "pic_autotune", "pic_autotune_steps", "pic_set_resort", "pic_set_far_tiles",
@@ -133,6 +134,8 @@ def lib():
                                   C.POINTER(C.c_double)], C.c_int),
             "pic_table_probe": ([C.POINTER(Config), i32, C.POINTER(C.c_float), i64,
                                  C.POINTER(C.c_float)], C.c_int),
+            "pic_table_bound_probe": ([C.POINTER(Config), i32, C.POINTER(C.c_float), i64,
+                                       C.POINTER(C.c_float)], C.c_int),
             "pic_table_probe_device": ([vp, i32, C.POINTER(C.c_float), i64, C.POINTER(C.c_float)],
                                        C.c_int),
             "pic_batch_create": ([C.POINTER(vp), i32, C.POINTER(vp)], C.c_int),
@@ -558,10 +561,13 @@ def keldysh_rate(material, lam, A, terms=500):
     return W
 
 
-def table_probe(cfg, mat, A):
+def table_probe(cfg, mat, A, bound=False):
+    """Host lookup of the FP32 rate table at amplitudes A; with bound=True the
+    skip bound of the ionization step instead (pic_table_bound_probe)."""
     c, keep = make_config(cfg)
     A = np.ascontiguousarray(A, dtype=np.float32)
     P = np.zeros_like(A)
-    _check(lib().pic_table_probe(C.byref(c), int(mat), A.ctypes.data_as(C.POINTER(C.c_float)), len(A),
-                                 P.ctypes.data_as(C.POINTER(C.c_float))), "pic_table_probe")
+    fn = "pic_table_bound_probe" if bound else "pic_table_probe"
+    _check(getattr(lib(), fn)(C.byref(c), int(mat), A.ctypes.data_as(C.POINTER(C.c_float)), len(A),
+                              P.ctypes.data_as(C.POINTER(C.c_float))), fn)
     return P

@@ -113,6 +113,38 @@ def test_rate_table_against_insitu_fp64(cfg):
         assert np.all(Pt[~sel] < 2.0 ** -32)
 
 
+@pytest.mark.parametrize("cfg", [W.config_2d(), W.config_3d(), dict(W.config_2d(), keldysh_tol_bits=12)],
+                         ids=["2d", "3d", "2d_tol12"])
+def test_skip_bound_covers_every_lookup_below(cfg):
+    """The bound the ionization step compares a draw with before it reads the
+    neutral's amplitude: on a dense sorted sample of FP32 amplitudes, and on
+    every FP32 number within 3000 ulp of each channel closing (where the rate
+    has its square-root edge), it is nondecreasing, never below the largest
+    lookup at any smaller amplitude, zero where nothing can fire and one from
+    saturation on; and it stays within 5 % of that running maximum wherever
+    P >= 1e-9 (the bound is held per table interval, 0.2 % of A wide, over
+    which P ~ A^(2K) rises by about 2K x 0.2 %), so the skip keeps nearly
+    every non-firing neutral out."""
+    _lib_or_skip()
+    o = Problem(cfg)
+    for mi, mt in enumerate(o.mats):
+        parts = [np.geomspace(5e8, 2e11, 400000).astype(np.float32)]
+        for Ak in _closings(mt, o.laser.lam, 5e8, 2e11):
+            f = np.float32(Ak)
+            bits = f.view(np.int32) + np.arange(-3000, 3001, dtype=np.int32)
+            parts.append(bits.view(np.float32))
+        A = np.unique(np.concatenate(parts))
+        Pt = P.table_probe(cfg, mi, A)
+        B = P.table_probe(cfg, mi, A, bound=True)
+        run = np.maximum.accumulate(Pt)
+        assert np.all(np.diff(B) >= 0)
+        assert np.all(B >= run), (A[np.argmax(run - B)], np.max(run - B))
+        assert np.all(B[Pt == 0] <= run[Pt == 0] + (2.0 ** -33))
+        assert np.all(B[Pt == 1] == 1)
+        sel = run >= 1e-9
+        assert np.max(B[sel] / run[sel]) < 1.05
+
+
 def test_invalid_configs_rejected():
     _lib_or_skip()
     import ctypes as C
