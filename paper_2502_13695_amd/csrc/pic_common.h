@@ -121,6 +121,10 @@ __host__ __device__ constexpr int ptile_cells(int D) {
 }
 constexpr int PT_LO = 2;            // window starts PT_LO nodes below the tile
 constexpr int PT_PAD = 5;           // window = tile + PT_PAD nodes per present axis
+// Ionization: a block of TPB threads takes TPB x ion_nit(ppc) consecutive
+// neutrals (each thread up to ION_NIT of them), i.e. at most TPB cells.
+constexpr int ION_NIT = 8;
+__host__ __device__ constexpr int ion_nit(int64_t ppc) { return ppc < ION_NIT ? (int)ppc : ION_NIT; }
 constexpr int SORT_CHUNK = 4096;    // sorted particles per block-sized piece of a tile
 constexpr int SPARSE_CHUNK = 128;   // pieces this small skip the LDS windows
 // LDS deposit in 64-bit fixed point: a contribution v (|v| <= max |kq|) is
@@ -221,9 +225,10 @@ struct Inst {
   int* xext;                    // charged region, 3 slots x {lo, hi} (cells)
   int* front;                   // last padded x index of a tile that stored a nonzero E or b
   unsigned long long* tiles_done;   // field tiles updated, one counter per XCD (stride 32)
-  unsigned long long* nevents;  // per material
+  unsigned long long* nevents;  // per XCD and material: [x * 32 + m]
   // field energy through the flux surface (the faces of the box one cell
-  // inside the outflow faces): [0] entering, [1] leaving, J
+  // inside the outflow faces), J, per XCD x: [x * 32] entering, [x * 32 + 1]
+  // leaving
   double* eflux;
   double kflux[3];              // eps0 c dt x the transverse cell area of a plane normal to axis d
   uint64_t seed;

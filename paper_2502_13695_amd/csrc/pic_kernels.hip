@@ -1660,8 +1660,9 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g, std::conditional_t<ONE,
       fout += __shfl_xor(fout, o);
     }
     if ((threadIdx.x & 63) == 0) {
-      if (fin != 0.0) atomicAdd(I.eflux, fin);
-      if (fout != 0.0) atomicAdd(I.eflux + 1, fout);
+      double* ef = I.eflux + (blockIdx.x & 7) * 32;   // this XCD's line
+      if (fin != 0.0) atomicAdd(ef, fin);
+      if (fout != 0.0) atomicAdd(ef + 1, fout);
     }
   }
 }
@@ -1723,6 +1724,9 @@ __device__ __forceinline__ Birth ionize_decide(const IT& I, int64_t jn, int ci, 
 // is the same as gathering first: the gathered amplitude never exceeds the
 // cell's largest (times 1 + 2^-16, which covers the FP32 sum of non-negative
 // weights), and the bound covers the lookup at every amplitude below it.
+template <int D, int ORDER, class IT>
+__device__ __forceinline__ void ionize_births(const IT& I, const Birth& b, int64_t jn, int step);
+
 template <int D, int ORDER, bool ONE>
 __global__ __launch_bounds__(TPB) void k_ionize(Group g, std::conditional_t<ONE, Inst, NoInst> one) {
   __shared__ unsigned char hot[TPB + 2];
@@ -1736,11 +1740,15 @@ __global__ __launch_bounds__(TPB) void k_ionize(Group g, std::conditional_t<ONE,
   // this kernel; a cold grid (no amplitude at any cut) ionizes nothing
   if (sl.bk == 0 && threadIdx.x == 0) I.hot[(step + 1) & 1] = 0;
   if (!I.hot[step & 1]) return;
-  const int64_t j0 = (int64_t)xcd_remap(sl.bk, sl.nbk) * TPB;
+  // a block takes TPB x nit consecutive neutrals, nit = min(ppc, ION_NIT):
+  // at most TPB cells, whose per-cell pass then keeps every thread busy
+  const int nit = ion_nit(I.ppc);
+  const int64_t span = (int64_t)TPB * nit;
+  const int64_t j0 = (int64_t)xcd_remap(sl.bk, sl.nbk) * span;
   const int64_t nneut = I.nneut;
   if (j0 >= nneut) return;
   const int64_t m0 = div_ppc(I, j0);
-  const int64_t jl = (j0 + TPB < nneut ? j0 + TPB : nneut) - 1;
+  const int64_t jl = (j0 + span < nneut ? j0 + span : nneut) - 1;
   const int ncell = (int)(div_ppc(I, jl) - m0 + 1);
   for (int t = threadIdx.x; t < ncell; t += TPB) {
     int ci, cj, ck;
@@ -1772,24 +1780,31 @@ __global__ __launch_bounds__(TPB) void k_ionize(Group g, std::conditional_t<ONE,
     spb[t] = h ? table_bound(I.tab[mat], amax * (1.0f + 0x1p-16f)) : 0.0f;
   }
   __syncthreads();
-  const int64_t jn = j0 + threadIdx.x;
-  Birth b{};
-  if (jn < nneut) {
-    const int64_t mn = div_ppc(I, jn);
-    const int t = (int)(mn - m0);
-    if (hot[t]) {
-      int ci, cj, ck;
-      unpack_cell(D, scell[t], ci, cj, ck);
-      const int64_t lin = ci + (int64_t)I.nx * (cj + (int64_t)I.ny * ck);
-      const uint64_t id = (uint64_t)(lin * I.ppc + (jn - mn * I.ppc));
-      const u32x4 w = draw(I.seed, id, (uint32_t)(step + 1), PURPOSE_IONIZE);
-      if ((double)w.x + 0.5 < (double)spb[t] * 4294967296.0)
-        b = ionize_decide<D, ORDER>(I, jn, ci, cj, ck, id, smat[t], w.x);
+  for (int it = 0; it < nit; ++it) {
+    const int64_t jn = j0 + (int64_t)it * TPB + threadIdx.x;
+    Birth b{};
+    if (jn < nneut) {
+      const int64_t mn = div_ppc(I, jn);
+      const int t = (int)(mn - m0);
+      if (hot[t]) {
+        int ci, cj, ck;
+        unpack_cell(D, scell[t], ci, cj, ck);
+        const int64_t lin = ci + (int64_t)I.nx * (cj + (int64_t)I.ny * ck);
+        const uint64_t id = (uint64_t)(lin * I.ppc + (jn - mn * I.ppc));
+        const u32x4 w = draw(I.seed, id, (uint32_t)(step + 1), PURPOSE_IONIZE);
+        if ((double)w.x + 0.5 < (double)spb[t] * 4294967296.0)
+          b = ionize_decide<D, ORDER>(I, jn, ci, cj, ck, id, smat[t], w.x);
+      }
     }
+    ionize_births<D, ORDER>(I, b, jn, step);
   }
-  // the wave's events: one slot reservation per tile, one event count per
-  // material, one alive-mask update per 32-neutral word (a wave holds 64
-  // consecutive neutrals starting at a multiple of 64)
+}
+
+// The events of one wave (64 consecutive neutrals starting at a multiple of
+// 64): one slot reservation per tile, one event count per material, one
+// alive-mask update per 32-neutral word, then each event's two carriers.
+template <int D, int ORDER, class IT>
+__device__ __forceinline__ void ionize_births(const IT& I, const Birth& b, int64_t jn, int step) {
   const unsigned long long m = __ballot(b.ev);
   if (!m) return;
   const int lane = threadIdx.x & 63;
@@ -1824,7 +1839,7 @@ __global__ __launch_bounds__(TPB) void k_ionize(Group g, std::conditional_t<ONE,
     const int l0 = __ffsll((long long)left) - 1;
     const int mt = __shfl(b.mat, l0);
     const unsigned long long same = __ballot(b.ev && b.mat == mt);
-    if (lane == l0) atomicAdd(&I.nevents[mt], (unsigned long long)__popcll(same));
+    if (lane == l0) atomicAdd(&I.nevents[(blockIdx.x & 7) * 32 + mt], (unsigned long long)__popcll(same));
     left &= ~same;
   }
   if (!b.ev) return;

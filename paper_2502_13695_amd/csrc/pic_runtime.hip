@@ -91,9 +91,11 @@ struct Ctr {
   unsigned done;
   alignas(256) int sctl[SC_WORDS];
   alignas(256) int hot[2];
-  alignas(256) unsigned long long nevents[MAXMAT];
+  // counts added from every block: one 256-byte line per XCD (slot x * 32 + m),
+  // summed when read; same-address atomics from all XCDs serialize
+  alignas(256) unsigned long long nevents[8 * 32];
   double acc[64];
-  alignas(256) double eflux[2];   // field energy into / out of the flux surface [J]
+  alignas(256) double eflux[8 * 32];   // into / out of the flux surface [J]: slots x * 32 + 0 / 1
 };
 
 pic_status plan(const pic_config* cfg, const Canon& c, const std::vector<TableHost>& tabs, Layout* L) {
@@ -891,7 +893,10 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
   if (const char* tv = std::getenv("PIC_FIELD_TILE")) c->tile = std::max(0, std::min(atoi(tv), field_tile_variants() - 1));
   c->nb_cell = field_tiles(D, c->tile, (int)L.Px, (int)L.Py, (int)L.Pz);
   c->nb_win = 1;   // one block per instance (tile-sort scan)
-  c->nb_neut = std::max(1, nblk(L.nneut));
+  {
+    const int64_t span = (int64_t)TPB * ion_nit(K.ppc);
+    c->nb_neut = (int)std::max<int64_t>(1, (L.nneut + span - 1) / span);
+  }
 
   int offs[32] = {0, c->nb_push, 0, c->nb_cell, 0, c->nb_win, 0, c->nb_neut};
   for (int v = 0; v < field_tile_variants(); ++v)
@@ -1570,8 +1575,10 @@ pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size
     kee += h.acc[2 * (2 * m) + 1];
     np += h.acc[2 * (2 * m + 1)];
     kep += h.acc[2 * (2 * m + 1) + 1];
-    nev += (double)h.nevents[m];
-    egap += (double)h.nevents[m] * c->h.kw[2 * m] * K.mats[m].gap_eV * kQE;
+    unsigned long long ev = 0;
+    for (int x = 0; x < 8; ++x) ev += h.nevents[x * 32 + m];
+    nev += (double)ev;
+    egap += (double)ev * c->h.kw[2 * m] * K.mats[m].gap_eV * kQE;
   }
   if (c->cfg.preionize_eV > 0) {
     // pre-ionized neutrals count as events of step 0
@@ -1591,8 +1598,11 @@ pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size
   o[PIC_SC_GAUSS_MAX] = h.acc[44];
   o[PIC_SC_RHO_MAX] = h.acc[45];
   o[PIC_SC_GAUSS_L2] = h.acc[47] > 0 ? std::sqrt(h.acc[46] / h.acc[47]) : 0.0;
-  o[PIC_SC_E_IN] = h.eflux[0];
-  o[PIC_SC_E_OUT] = h.eflux[1];
+  o[PIC_SC_E_IN] = o[PIC_SC_E_OUT] = 0.0;
+  for (int x = 0; x < 8; ++x) {
+    o[PIC_SC_E_IN] += h.eflux[x * 32];
+    o[PIC_SC_E_OUT] += h.eflux[x * 32 + 1];
+  }
   o[PIC_SC_HEALTH] = (double)h.health;
   o[PIC_SC_SLOTS] = (double)h.pcount;
   unsigned long long nrec = 0;
