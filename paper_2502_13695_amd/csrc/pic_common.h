@@ -104,6 +104,22 @@ __host__ __device__ inline float table_bound(const TabHdr* __restrict__ h, float
   return reinterpret_cast<const float*>(seg + h->nseg)[TAB_REC * (s.base + i) + 9];
 }
 
+// ------------------------------------------------------ particle offsets
+// A charged particle's offset in its cell is a 32-bit fraction o (t = o 2^-32,
+// uniform resolution 2.3e-10 cells; an FP32 offset has 6e-8 near 1, which is
+// 3e-5 of a thermal electron's step).  The shape weights take it as an FP32
+// number; the Esirkepov differences and the move use the integer.
+__host__ __device__ inline float off_lo(uint32_t o) {   // truncated to 24 bits, < 1
+  return (float)(o >> 8) * 0x1p-24f;
+}
+__host__ __device__ inline float off_f32(uint32_t o) {  // nearest FP32 below 1
+  const float t = (float)((double)o * 0x1p-32);
+  return t < 1.0f ? t : 0x1.fffffep-1f;
+}
+__host__ __device__ inline uint32_t off_fix(float t) {   // t in [0, 1), exact for FP32 t
+  return (uint32_t)((double)t * 0x1p32);
+}
+
 // ------------------------------------------------------- particle tiles
 // The charged particles are kept sorted by tile of the deposit (counting sort,
 // redone when enough particles have left their tile or landed beyond the
@@ -178,7 +194,8 @@ struct Inst {
   float *ring, *suffix, *prefix, *A;
   // charged particles (SoA)
   uint32_t* pcell;              // packed cell indices
-  float *po0, *po1, *po2, *pu0, *pu1, *pu2;
+  uint32_t *po0, *po1, *po2;     // offsets in the cell, 32-bit fractions (t = o 2^-32)
+  float *pu0, *pu1, *pu2;
   uint8_t* pkind;
   uint32_t* pid;                // id of the parent neutral (placed particles: cells * ppc + index)
   int* pcount;                  // used slots
@@ -198,7 +215,8 @@ struct Inst {
   float jscale, jscale_inv;     // LDS fixed-point scale of the deposit and its inverse
   int* sctl;                    // SC_* words
   uint32_t* scell;              // scatter targets (same layout as the particle arrays)
-  float *so0, *so1, *so2, *su0, *su1, *su2;
+  uint32_t *so0, *so1, *so2;
+  float *su0, *su1, *su2;
   uint8_t* skind;
   uint32_t* spid;
   // particle kinds: 2m electron, 2m+1 positive carrier

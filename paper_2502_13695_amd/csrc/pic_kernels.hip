@@ -208,19 +208,25 @@ __device__ __forceinline__ float gather(const float* __restrict__ Fp, const Axis
 // end shape bases: S0 = start weights, DS = end - start weights.  A move that
 // keeps its shape base leaves node W - 1 zero.
 //
-// DS is formed from the two positions' local coordinates, which are exact
-// FP32 numbers, in factored form: subtracting the two sets of rounded weights
-// would leave an absolute error of a few 1e-8 on every node whatever the move,
-// i.e. a relative error of 1e-5 on the current of a particle that moves 1e-3
-// cells per step (a thermal plasma).  Quadratic shape, start offset xi0 and
-// end offset xi1 from the centres of their own stencils:
+// DS is formed from the two offsets (32-bit fractions) in factored form, with
+// the small differences taken on the integers: subtracting two sets of
+// rounded weights would leave a few 1e-8 on every node whatever the move, a
+// relative error of 1e-5 on the current of a particle that moves 1e-3 cells
+// per step (a thermal plasma).  Quadratic shape, xi0 and xi1 = the offsets
+// from the centres of their own stencils (xi 2^32 = o read as a signed
+// integer):
 //   same base:   d = xi1 - xi0, s = xi0 + xi1;
 //                DS = (-d (1 - s) / 2, -d s, d (1 + s) / 2)
-//   base up:     a = xi0 - 1/2 <= 0, e = xi1 + 1/2 >= 0 (both exact near the
-//                crossing); DS = (-a^2/2, (a - e) + a^2 + e^2/2,
-//                (e - a) - e^2 - a^2/2, e^2/2)
+//   base up:     a = xi0 - 1/2 <= 0, e = xi1 + 1/2 >= 0;
+//                DS = (-a^2/2, (a - e) + a^2 + e^2/2, (e - a) - e^2 - a^2/2, e^2/2)
 //   base down:   the mirror image (a = -xi0 - 1/2, e = 1/2 - xi1, reversed).
-// Linear shape: d = t1 - t0 on a kept cell, else 1 - t formed first.
+// Linear shape: d = t1 - t0 on a kept cell, else 1 - t first.  A difference
+// below 1/4 is read off the integers (exact up to its FP32 rounding, no wrap
+// below 1/2); a larger one loses nothing in FP32.
+__device__ __forceinline__ float fix_small(uint32_t v, float approx) {
+  return fabsf(approx) < 0.25f ? (float)(int32_t)v * 0x1p-32f : approx;
+}
+
 template <int ORDER>
 struct Esk {
   static constexpr int W = ORDER + 2;
@@ -230,10 +236,10 @@ struct Esk {
 };
 
 template <int ORDER>
-__device__ __forceinline__ void esk_axis(Esk<ORDER>& e, int c0, float t0, int c1, float t1) {
+__device__ __forceinline__ void esk_axis(Esk<ORDER>& e, int c0, uint32_t o0, int c1, uint32_t o1) {
   if (ORDER == 2) {
-    const int up0 = t0 >= 0.5f, up1 = t1 >= 0.5f;
-    const float xi0 = t0 - (float)up0, xi1 = t1 - (float)up1;
+    const int up0 = o0 >= 0x80000000u, up1 = o1 >= 0x80000000u;
+    const float xi0 = (float)(int32_t)o0 * 0x1p-32f, xi1 = (float)(int32_t)o1 * 0x1p-32f;
     const float w0 = 0.5f * (0.5f - xi0) * (0.5f - xi0);
     const float w1 = 0.75f - xi0 * xi0;
     const float w2 = 0.5f * (0.5f + xi0) * (0.5f + xi0);
@@ -241,7 +247,8 @@ __device__ __forceinline__ void esk_axis(Esk<ORDER>& e, int c0, float t0, int c1
     const int sh = (c1 + up1 - 1) - b0;   // -1, 0, 1
     e.moved = sh != 0;
     if (sh < 0) {
-      const float a = -0.5f - xi0, f = 0.5f - xi1;
+      const float a = -fix_small(o0 + 0x80000000u, 0.5f + xi0);
+      const float f = -fix_small(o1 - 0x80000000u, xi1 - 0.5f);
       e.org = b0 - 1;
       e.S0[0] = 0.0f;
       e.S0[1] = w0;
@@ -258,13 +265,14 @@ __device__ __forceinline__ void esk_axis(Esk<ORDER>& e, int c0, float t0, int c1
       e.S0[2] = w2;
       e.S0[3] = 0.0f;
       if (sh > 0) {
-        const float a = xi0 - 0.5f, f = xi1 + 0.5f;
+        const float a = fix_small(o0 - 0x80000000u, xi0 - 0.5f);
+        const float f = fix_small(o1 + 0x80000000u, xi1 + 0.5f);
         e.DS[0] = -0.5f * a * a;
         e.DS[1] = (a - f) + a * a + 0.5f * f * f;
         e.DS[2] = (f - a) - f * f - 0.5f * a * a;
         e.DS[3] = 0.5f * f * f;
       } else {
-        const float d = xi1 - xi0, sm = xi0 + xi1;
+        const float d = fix_small(o1 - o0, xi1 - xi0), sm = xi0 + xi1;
         e.DS[0] = -0.5f * d * (1.0f - sm);
         e.DS[1] = -d * sm;
         e.DS[2] = 0.5f * d * (1.0f + sm);
@@ -272,6 +280,7 @@ __device__ __forceinline__ void esk_axis(Esk<ORDER>& e, int c0, float t0, int c1
       }
     }
   } else {
+    const float t0 = off_lo(o0), t1 = off_lo(o1);
     const int sh = c1 - c0;
     e.moved = sh != 0;
     if (sh < 0) {
@@ -279,22 +288,24 @@ __device__ __forceinline__ void esk_axis(Esk<ORDER>& e, int c0, float t0, int c1
       e.S0[0] = 0.0f;
       e.S0[1] = 1.0f - t0;
       e.S0[2] = t0;
-      const float r1 = 1.0f - t1;
+      const float r1 = fix_small(0u - o1, 1.0f - t1);   // 1 - t1
+      const float tt0 = fix_small(o0, t0);
       e.DS[0] = r1;
-      e.DS[1] = t0 - r1;
-      e.DS[2] = -t0;
+      e.DS[1] = tt0 - r1;
+      e.DS[2] = -tt0;
     } else {
       e.org = c0;
-      const float r0 = 1.0f - t0;
-      e.S0[0] = r0;
+      const float r0 = fix_small(0u - o0, 1.0f - t0);   // 1 - t0 (o0 > 0 when small)
+      e.S0[0] = 1.0f - t0;
       e.S0[1] = t0;
       e.S0[2] = 0.0f;
       if (sh > 0) {
+        const float tt1 = fix_small(o1, t1);
         e.DS[0] = -r0;
-        e.DS[1] = r0 - t1;
-        e.DS[2] = t1;
+        e.DS[1] = r0 - tt1;
+        e.DS[2] = tt1;
       } else {
-        const float d = t1 - t0;
+        const float d = fix_small(o1 - o0, t1 - t0);
         e.DS[0] = -d;
         e.DS[1] = d;
         e.DS[2] = 0.0f;
@@ -573,12 +584,13 @@ __device__ __forceinline__ float gather_l(const float* __restrict__ S, const Axi
 template <int D, int ORDER, bool PY, bool PZ, bool LOCAL, class IT>
 __device__ __forceinline__ void push_body(const IT& I, const PushFields& f, const float* sF, int fx0,
                                           int fy0, int fz0, const GSink<PY, PZ>& gs, const LSink<D>& ls,
-                                          unsigned q, uint8_t kind, int ci, int cj, int ck, float t0,
-                                          float t1, float t2, float ux, float uy, float uz, int& xlo,
+                                          unsigned q, uint8_t kind, int ci, int cj, int ck, uint32_t o0,
+                                          uint32_t o1, uint32_t o2, float ux, float uy, float uz, int& xlo,
                                           int& xhi) {
   // ---- gather E^n, b^n
   float ex, ey, ez, bx, by, bz;
   {
+    const float t0 = off_lo(o0), t1 = off_lo(o1), t2 = off_lo(o2);
     Axis<ORDER> X, Y, Z;
     if (LOCAL) {
       constexpr int N = FWin<D>::N;
@@ -618,20 +630,15 @@ __device__ __forceinline__ void push_body(const IT& I, const PushFields& f, cons
   uz = umz + sf * (vx * ty - vy * tx) + h * ez;
   if (!(fabsf(ux) + fabsf(uy) + fabsf(uz) <= 3.0e38f)) atomicOr(I.health, HEALTH_NONFINITE);
   const float ig = 1.0f / sqrtf(1.0f + ux * ux + uy * uy + uz * uz);
-  // ---- move: integer cell + FP32 offset, at most one cell per step
+  // ---- move: integer cell + 32-bit fraction, at most one cell per step; the
+  // displacement is rounded to 2^-31 cells (|disp| < 1 fits an int32 there)
   int ni = ci, nj = cj, nk = ck;
-  float n0 = t0, n1 = t1, n2 = t2;
-  auto move = [&](float& t, int& c, float disp) {
-    float xn = t + disp;
-    if (xn >= 1.0f) {
-      xn -= 1.0f;
-      c += 1;
-    } else if (xn < 0.0f) {
-      xn += 1.0f;
-      c -= 1;
-      if (xn >= 1.0f) { xn = 0.0f; c += 1; }
-    }
-    t = xn;
+  uint32_t n0 = o0, n1 = o1, n2 = o2;
+  auto move = [&](uint32_t& o, int& c, float disp) {
+    disp = fminf(fmaxf(disp, -0x1.fffffep-1f), 0x1.fffffep-1f);
+    const int64_t pos = (int64_t)o + 2 * (int64_t)__float2int_rn(disp * 0x1p31f);
+    c += (int)(pos >> 32);
+    o = (uint32_t)pos;
   };
   move(n0, ni, I.C[0] * ux * ig);
   if (D >= 2) move(n1, nj, I.C[1] * uy * ig);
@@ -639,9 +646,9 @@ __device__ __forceinline__ void push_body(const IT& I, const PushFields& f, cons
   // ---- Esirkepov deposit of J^{n+1/2} (scaled: dt J / eps0, V/m)
   {
     Esk<ORDER> exk, eyk, ezk;
-    esk_axis<ORDER>(exk, ci, t0, ni, n0);
-    if (D >= 2) esk_axis<ORDER>(eyk, cj, t1, nj, n1);
-    if (D >= 3) esk_axis<ORDER>(ezk, ck, t2, nk, n2);
+    esk_axis<ORDER>(exk, ci, o0, ni, n0);
+    if (D >= 2) esk_axis<ORDER>(eyk, cj, o1, nj, n1);
+    if (D >= 3) esk_axis<ORDER>(ezk, ck, o2, nk, n2);
     const float qx = I.kq[kind][0], qy = I.kq[kind][1], qz = I.kq[kind][2];
     if (LOCAL) deposit<D, ORDER>(ls, exk, eyk, ezk, qx, qy, qz, uy * ig, uz * ig);
     else deposit<D, ORDER>(gs, exk, eyk, ezk, qx, qy, qz, uy * ig, uz * ig);
@@ -683,9 +690,9 @@ __device__ __forceinline__ void push_one(const IT& I, const PushFields& f, const
   if (kind == DEAD) return;
   int ci, cj, ck;
   unpack_cell(D, gp(I.pcell)[q], ci, cj, ck);
-  const float t0 = gp(I.po0)[q];
-  const float t1 = D >= 2 ? gp(I.po1)[q] : 0.0f;
-  const float t2 = D >= 3 ? gp(I.po2)[q] : 0.0f;
+  const uint32_t t0 = gp(I.po0)[q];
+  const uint32_t t1 = D >= 2 ? gp(I.po1)[q] : 0u;
+  const uint32_t t2 = D >= 3 ? gp(I.po2)[q] : 0u;
   const float ux = gp(I.pu0)[q], uy = gp(I.pu1)[q], uz = gp(I.pu2)[q];
   if (TILED) {
     bool in = ci >= tx0 && ci < tx0 + ptile_ext(D, 0);
@@ -1856,9 +1863,9 @@ __device__ __forceinline__ void ionize_births(const IT& I, const Birth& b, int64
   for (int s = 0; s < 2; ++s) {
     const int q = s == 0 ? se : sp;
     I.pcell[q] = pc;
-    I.po0[q] = b.t0;
-    if (D >= 2) I.po1[q] = b.t1;
-    if (D >= 3) I.po2[q] = b.t2;
+    I.po0[q] = off_fix(b.t0);
+    if (D >= 2) I.po1[q] = off_fix(b.t1);
+    if (D >= 3) I.po2[q] = off_fix(b.t2);
     I.pu0[q] = ux;
     I.pu1[q] = uy;
     I.pu2[q] = uz;
@@ -1945,9 +1952,9 @@ __global__ __launch_bounds__(TPB) void k_preionize(const Inst* d, const float* s
     // every neutral's pair sits in slots 2j, 2j + 1 (cell order kept)
     const int64_t q = 2 * jn + s;
     I.pcell[q] = pc;
-    I.po0[q] = I.no0[jn];
-    if (D >= 2) I.po1[q] = I.no1[jn];
-    if (D >= 3) I.po2[q] = I.no2[jn];
+    I.po0[q] = off_fix(I.no0[jn]);
+    if (D >= 2) I.po1[q] = off_fix(I.no1[jn]);
+    if (D >= 3) I.po2[q] = off_fix(I.no2[jn]);
     I.pu0[q] = ux;
     I.pu1[q] = uy;
     I.pu2[q] = uz;
@@ -2088,9 +2095,9 @@ __global__ __launch_bounds__(TRACK_TPB) void k_tracks(const Inst* d, uint32_t th
       r.cell[0] = ci;
       r.cell[1] = cj;
       r.cell[2] = ck;
-      r.off[0] = I.po0[p];
-      r.off[1] = D >= 2 ? I.po1[p] : 0.0f;
-      r.off[2] = D >= 3 ? I.po2[p] : 0.0f;
+      r.off[0] = off_f32(I.po0[p]);
+      r.off[1] = D >= 2 ? off_f32(I.po1[p]) : 0.0f;
+      r.off[2] = D >= 3 ? off_f32(I.po2[p]) : 0.0f;
       r.pad = 0;
       rec[base + i] = r;
     }
@@ -2174,9 +2181,9 @@ __global__ __launch_bounds__(TPB) void k_diag_deposit(const Inst* d, double* gri
     int ci, cj, ck;
     unpack_cell(D, I.pcell[p], ci, cj, ck);
     Axis<ORDER> X, Y, Z;
-    make_axis<ORDER>(X, ci, I.po0[p], I.nx, 0, G, 1);
-    if (D >= 2) make_axis<ORDER>(Y, cj, I.po1[p], I.ny, I.per_y, I.Gy, I.sy);
-    if (D >= 3) make_axis<ORDER>(Z, ck, I.po2[p], I.nz, I.per_z, I.Gz, I.sz);
+    make_axis<ORDER>(X, ci, off_f32(I.po0[p]), I.nx, 0, G, 1);
+    if (D >= 2) make_axis<ORDER>(Y, cj, off_f32(I.po1[p]), I.ny, I.per_y, I.Gy, I.sy);
+    if (D >= 3) make_axis<ORDER>(Z, ck, off_f32(I.po2[p]), I.nz, I.per_z, I.Gz, I.sz);
     constexpr int SY = D >= 2 ? ORDER + 1 : 1;
     constexpr int SZ = D >= 3 ? ORDER + 1 : 1;
     for (int c = 0; c < SZ; ++c)

@@ -167,7 +167,7 @@ pic_status plan(const pic_config* cfg, const Canon& c, const std::vector<TableHo
   L->o_death = take(sizeof(int) * L->nneut);
   L->o_mcell = take(sizeof(uint32_t) * L->nmcell);
   L->o_pcell = take(sizeof(uint32_t) * L->capacity);
-  for (int q = 0; q < 3; ++q) L->o_po[q] = take(q < D ? sizeof(float) * L->capacity : 0);
+  for (int q = 0; q < 3; ++q) L->o_po[q] = take(q < D ? sizeof(uint32_t) * L->capacity : 0);
   for (int q = 0; q < 3; ++q) L->o_pu[q] = take(sizeof(float) * L->capacity);
   L->o_pkind = take(L->capacity);
   L->o_pid = take(sizeof(uint32_t) * L->capacity);
@@ -180,7 +180,7 @@ pic_status plan(const pic_config* cfg, const Canon& c, const std::vector<TableHo
   L->o_tperm = take(sizeof(int) * L->ntiles);
   L->o_chunks = take(sizeof(int4) * L->maxchunks);
   L->o_scell = take(sizeof(uint32_t) * L->capacity);
-  for (int q = 0; q < 3; ++q) L->o_so[q] = take(q < D ? sizeof(float) * L->capacity : 0);
+  for (int q = 0; q < 3; ++q) L->o_so[q] = take(q < D ? sizeof(uint32_t) * L->capacity : 0);
   for (int q = 0; q < 3; ++q) L->o_su[q] = take(sizeof(float) * L->capacity);
   L->o_skind = take(L->capacity);
   L->o_spid = take(sizeof(uint32_t) * L->capacity);
@@ -795,9 +795,9 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
   I.prefix = (float*)devp(c, L.o_prefix);
   I.A = (float*)devp(c, L.o_A);
   I.pcell = (uint32_t*)devp(c, L.o_pcell);
-  I.po0 = (float*)devp(c, L.o_po[0]);
-  I.po1 = (float*)devp(c, L.o_po[1]);
-  I.po2 = (float*)devp(c, L.o_po[2]);
+  I.po0 = (uint32_t*)devp(c, L.o_po[0]);
+  I.po1 = (uint32_t*)devp(c, L.o_po[1]);
+  I.po2 = (uint32_t*)devp(c, L.o_po[2]);
   I.pu0 = (float*)devp(c, L.o_pu[0]);
   I.pu1 = (float*)devp(c, L.o_pu[1]);
   I.pu2 = (float*)devp(c, L.o_pu[2]);
@@ -814,9 +814,9 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
   I.tperm = (int*)devp(c, L.o_tperm);
   I.chunks = (int4*)devp(c, L.o_chunks);
   I.scell = (uint32_t*)devp(c, L.o_scell);
-  I.so0 = (float*)devp(c, L.o_so[0]);
-  I.so1 = (float*)devp(c, L.o_so[1]);
-  I.so2 = (float*)devp(c, L.o_so[2]);
+  I.so0 = (uint32_t*)devp(c, L.o_so[0]);
+  I.so1 = (uint32_t*)devp(c, L.o_so[1]);
+  I.so2 = (uint32_t*)devp(c, L.o_so[2]);
   I.su0 = (float*)devp(c, L.o_su[0]);
   I.su1 = (float*)devp(c, L.o_su[1]);
   I.su2 = (float*)devp(c, L.o_su[2]);
@@ -1265,7 +1265,8 @@ pic_status pic_set_state(pic_ctx* c, const pic_state* S) {
   const int64_t n = S->n_particles;
   if (n > 0 || true) {
     std::vector<uint32_t> pc(n);
-    std::vector<float> po[3], pu[3];
+    std::vector<uint32_t> po[3];
+    std::vector<float> pu[3];
     for (int q = 0; q < 3; ++q) {
       po[q].resize(n);
       pu[q].resize(n);
@@ -1281,7 +1282,7 @@ pic_status pic_set_state(pic_ctx* c, const pic_state* S) {
       if (r.kind < 0 || r.kind >= 2 * K.nmat) return PIC_E_INVAL;
       pc[p] = pack_cell(D, r.cell[0], D >= 2 ? r.cell[1] : 0, D >= 3 ? r.cell[2] : 0);
       for (int q = 0; q < 3; ++q) {
-        po[q][p] = r.off[q];
+        po[q][p] = q < D ? off_fix(r.off[q]) : 0u;
         pu[q][p] = r.u[q];
       }
       pk[p] = (uint8_t)r.kind;
@@ -1400,14 +1401,15 @@ pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size
     HIP_OK(hipMemcpy(&cnt, &c->d_ctr->pcount, sizeof cnt, hipMemcpyDeviceToHost));
     cnt = std::min<int64_t>(cnt, L.capacity);
     std::vector<uint32_t> pc(cnt);
-    std::vector<float> po[3], pu[3];
+    std::vector<uint32_t> po[3];
+    std::vector<float> pu[3];
     std::vector<uint8_t> pk(cnt);
     if (cnt) {
       HIP_OK(hipMemcpy(pc.data(), devp(c, L.o_pcell), 4 * cnt, hipMemcpyDeviceToHost));
       HIP_OK(hipMemcpy(pk.data(), devp(c, L.o_pkind), cnt, hipMemcpyDeviceToHost));
     }
     for (int q = 0; q < 3; ++q) {
-      po[q].assign(cnt, 0.0f);
+      po[q].assign(cnt, 0u);
       pu[q].resize(cnt);
       if (cnt && q < D) HIP_OK(hipMemcpy(po[q].data(), devp(c, L.o_po[q]), 4 * cnt, hipMemcpyDeviceToHost));
       if (cnt) HIP_OK(hipMemcpy(pu[q].data(), devp(c, L.o_pu[q]), 4 * cnt, hipMemcpyDeviceToHost));
@@ -1423,7 +1425,7 @@ pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size
       r.cell[2] = ck;
       r.kind = pk[p];
       for (int q = 0; q < 3; ++q) {
-        r.off[q] = po[q][p];
+        r.off[q] = q < D ? off_f32(po[q][p]) : 0.0f;
         r.u[q] = pu[q][p];
       }
       recs.push_back(r);

@@ -508,7 +508,10 @@ def test_stress_preionized_2d(P):
     assert sc["n_e"] == np.sum(sim.pk % 2 == 0)
     l2 = _field_l2(ctx, sim)
     _record("stress_2d", field_l2=l2, ke_e_gpu=sc["ke_e"], ke_e_oracle=sim.kinetic_energy("e"))
-    assert l2 < 1e-4, l2
+    # a 3 eV plasma moves 1e-3 cells per step: the current rests on the
+    # differences of the offsets, held as 32-bit fractions (FP32 offsets left
+    # 2e-5 here, the oracle's own figure with its deposit positions rounded so)
+    assert l2 < 1e-5, l2
     ke_o = sim.kinetic_energy("e")
     assert abs(sc["ke_e"] / ke_o - 1) < 1e-4
     assert sc["gauss_max"] <= 1e-4 * sc["rho_max"]
