@@ -141,7 +141,7 @@ constexpr int PT_PAD = 5;           // window = tile + PT_PAD nodes per present 
 // neutrals (each thread up to ION_NIT of them), i.e. at most TPB cells.
 constexpr int ION_NIT = 8;
 __host__ __device__ constexpr int ion_nit(int64_t ppc) { return ppc < ION_NIT ? (int)ppc : ION_NIT; }
-constexpr int SORT_CHUNK = 4096;    // sorted particles per block-sized piece of a tile
+constexpr int SORT_CHUNK = 1024;    // sorted particles per work item (piece of a tile)
 constexpr int SPARSE_CHUNK = 128;   // pieces this small skip the LDS windows
 // LDS deposit in 64-bit fixed point: a contribution v (|v| <= max |kq|) is
 // added as round(v * jscale) with jscale = 2^40 / 2^ceil(log2 max |kq|); a
@@ -244,6 +244,7 @@ struct Inst {
   int* front;                   // last padded x index of a tile that stored a nonzero E or b
   unsigned long long* tiles_done;   // field tiles updated, one counter per XCD (stride 32)
   unsigned long long* nevents;  // per XCD and material: [x * 32 + m]
+  int* pq;                      // push work queues: next item of XCD x's range at [64 x], blocks done at [512]
   // field energy through the flux surface (the faces of the box one cell
   // inside the outflow faces), J, per XCD x: [x * 32] entering, [x * 32 + 1]
   // leaving

@@ -41,6 +41,9 @@ struct Stamp {
 
 // phase launchers (enqueue on `s`); D = 1..3, order = 1..2
 // per: periodic transverse axes (D >= 2)
+// Blocks of the push grid: as many as are resident at once on this GPU (a
+// multiple of 8; the blocks take their work from queues).  0 on error.
+int push_grid(int D);
 void launch_push(const Group& g, int D, int order, bool per, hipStream_t s, Stamp st = {});
 // tile sort of the charged particles (gp: the push grid; gscan: one block per
 // instance); each instance decides on the device whether a sort is due

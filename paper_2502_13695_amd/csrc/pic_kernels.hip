@@ -750,10 +750,9 @@ __global__ __launch_bounds__(push_tpb(D), D == 3 ? 4 : 1) void k_push(Group g, s
   nsorted = nsorted < count ? nsorted : count;
   const int nchunks = I.sctl[SC_NCHUNKS];
   const int64_t ncell = (int64_t)I.Px * I.Py * I.Pz;
-  for (int v = b0; v < nchunks; v += nb) {
-    // the same XCD keeps neighbouring chunks: nb is a multiple of 8, so the
-    // XCD of work item v is v mod 8 whatever the round
-    const int4 ch = I.chunks[(nb & 7) ? v : xcd_remap(v, nchunks)];
+  // one work item: a chunk of a sorted tile
+  auto work = [&](int v) {
+    const int4 ch = I.chunks[v];
     const int t = ch.x;
     const int n_sorted = ch.z - ch.y;
     int nbirth = 0, bcap = 0;
@@ -763,7 +762,7 @@ __global__ __launch_bounds__(push_tpb(D), D == 3 ? 4 : 1) void k_push(Group g, s
       nbirth = fe < bcap ? fe : bcap;
     }
     const int ntot = n_sorted + 2 * nbirth;
-    if (ntot == 0) continue;
+    if (ntot == 0) return;
     if (ntot <= SPARSE_CHUNK) {
       // a sparse piece (one pass of the block): HBM atomics cost less than
       // staging and flushing the windows
@@ -771,7 +770,7 @@ __global__ __launch_bounds__(push_tpb(D), D == 3 ? 4 : 1) void k_push(Group g, s
       const int p = i < ntot ? item_slot(i, ch.y, n_sorted, ch.w, nbirth, bcap) : 0;
       push_one<D, ORDER, PY, PZ, false>(I, f, sF, gs, LSink<D>{sJ, 0, 0, 0, 0.0}, 0, 0, 0, p, i < ntot,
                                         xlo, xhi);
-      continue;
+      return;
     }
     const int tx0 = (t % I.ntile[0]) * ptile_ext(D, 0);
     const int ty0 = D >= 2 ? ((t / I.ntile[0]) % I.ntile[1]) * ptile_ext(D, 1) : 0;
@@ -782,7 +781,7 @@ __global__ __launch_bounds__(push_tpb(D), D == 3 ? 4 : 1) void k_push(Group g, s
     // field window: nodes tile - 1 .. tile + T + 1 (periodic axes wrapped;
     // nodes outside the padded arrays, never read, are zero).  Threads walk
     // the window row by row: a row of X nodes per (b, c).
-    constexpr int FX = FWin<D>::X, FY = FWin<D>::Y, FZ = FWin<D>::Z;
+    constexpr int FX = FWin<D>::X, FY = FWin<D>::Y;
     for (int e = threadIdx.x; e < FWin<D>::N; e += NT) {
       const int a = e % FX;
       const int r = e / FX;
@@ -804,7 +803,6 @@ __global__ __launch_bounds__(push_tpb(D), D == 3 ? 4 : 1) void k_push(Group g, s
         off += I.sz * (k + I.Gz);
       }
       const unsigned o = (unsigned)off;
-      (void)FZ;
       sF[0 * FWin<D>::N + e] = ok ? gp(f.E0)[o] : 0.0f;
       sF[1 * FWin<D>::N + e] = ok ? gp(f.E1)[o] : 0.0f;
       sF[2 * FWin<D>::N + e] = ok ? gp(f.E2)[o] : 0.0f;
@@ -831,7 +829,40 @@ __global__ __launch_bounds__(push_tpb(D), D == 3 ? 4 : 1) void k_push(Group g, s
       const int o = gs.x(ls.x0 + a) + (D >= 2 ? gs.y(ls.y0 + b) : 0) + (D >= 3 ? gs.z(ls.z0 + c) : 0);
       if (o >= 0 && o < ncell) gs.put(comp, o, v, 1.0f);
     }
+  };
+  // Work queues: the chunk list in 8 contiguous ranges, one per XCD (a block
+  // runs on XCD blockIdx.x mod 8), so neighbouring tiles share that XCD's L2.
+  // A block takes the next chunk of its own range (one atomic, issued while
+  // it works on the current chunk), then helps the other ranges.  The grid
+  // is the number of blocks resident at once: work goes to whichever block is
+  // free, so chunks of very different sizes leave no block idle.  The last
+  // block out clears the counters for the next launch.
+  __shared__ int s_next;
+  const int home = (int)(blockIdx.x & 7u);
+  for (int q = 0; q < 8; ++q) {
+    const int xq = (home + q) & 7;
+    const int lo = (int)((int64_t)nchunks * xq / 8), hi = (int)((int64_t)nchunks * (xq + 1) / 8);
+    int* const ctr = I.pq + 64 * xq;
+    if (threadIdx.x == 0) s_next = lo + atomicAdd(ctr, 1);
     __syncthreads();
+    int v = s_next;
+    while (v < hi) {
+      int nxt = 0;
+      if (threadIdx.x == 0) nxt = lo + atomicAdd(ctr, 1);   // the next item, in flight meanwhile
+      work(v);
+      __syncthreads();   // the windows are free again, and s_next has been read
+      if (threadIdx.x == 0) s_next = nxt;
+      __syncthreads();
+      v = s_next;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(I.pq + 64 * 8, 1) == nb - 1) {
+      for (int x = 0; x <= 8; ++x) __hip_atomic_store(I.pq + 64 * x, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __threadfence();
+    }
   }
   const LSink<D> none{sJ, 0, 0, 0, 0.0};
   for (int p0 = nsorted + b0 * NT; p0 < count; p0 += nb * NT) {
@@ -2267,6 +2298,19 @@ __global__ void k_table_probe(const TabHdr* tab, const float* A, float* P, int64
     else                                                                              \
       GO((KT<__VA_ARGS__, false>), g.blocks, tpb, s, st.start, st.stop, g, NoInst{}); \
   } while (0)
+int push_grid(int D) {
+  int dev = 0, bpc = 0;
+  hipDeviceProp_t pr{};
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&pr, dev) != hipSuccess) return 0;
+  hipError_t e = hipSuccess;
+  switch (D) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, k_push<1, 2, false, false, true>, push_tpb(1), 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, k_push<2, 2, true, false, true>, push_tpb(2), 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, k_push<3, 2, true, true, true>, push_tpb(3), 0); break;
+  }
+  if (e != hipSuccess || bpc < 1) return 0;
+  return std::max(8, bpc * pr.multiProcessorCount / 8 * 8);
+}
 void launch_push(const Group& g, int D, int order, bool per, hipStream_t s, Stamp st) {
   const bool one = g.n == 1 && g.host && g.step >= 0;
   // periodic transverse axes are a template parameter (D >= 2)

@@ -95,6 +95,7 @@ struct Ctr {
   // summed when read; same-address atomics from all XCDs serialize
   alignas(256) unsigned long long nevents[8 * 32];
   double acc[64];
+  alignas(256) int pq[9 * 64];   // push work queues (one 256-byte line each), zero between launches
   alignas(256) double eflux[8 * 32];   // into / out of the flux surface [J]: slots x * 32 + 0 / 1
 };
 
@@ -122,7 +123,7 @@ pic_status plan(const pic_config* cfg, const Canon& c, const std::vector<TableHo
   L->wsz = (int64_t)(L->wx1 - L->wx0) * L->Py * L->Pz;
   int64_t cap = cfg->particle_capacity > 0 ? cfg->particle_capacity : 2 * L->nneut + 4096;
   if (cfg->preionize_eV > 0) cap = std::max<int64_t>(cap, 2 * L->nneut);
-  // particle tiles and their 64-cell groups
+  // particle tiles
   L->ntiles = 1;
   for (int d = 0; d < 3; ++d) {
     const int64_t e = ptile_ext(D, d);
@@ -188,7 +189,7 @@ pic_status plan(const pic_config* cfg, const Canon& c, const std::vector<TableHo
   L->o_ctr = take(sizeof(Ctr));
   L->o_grid64 = take(sizeof(double) * (size_t)L->ncell);
   L->o_inst = take(sizeof(Inst));
-  L->o_off = take(sizeof(int) * 32);   // 4 phases x {0, blocks}; field shapes x {0, blocks}
+  L->o_off = take(sizeof(int) * 32);   // 4 phases x {0, blocks}; field shapes x {0, blocks}; the sort
   L->o_sig = take(sizeof(float) * 2 * MAXMAT);
   L->o_probe = take(0);
   L->total = o;
@@ -210,7 +211,7 @@ struct pic_ctx {
   Inst* d_inst = nullptr;
   int* d_off = nullptr;   // [0, nb_push, 0, nb_cell, 0, 1, 0, nb_neut], then {0, tiles} per field shape
   int* d_off_fields = nullptr;   // block offsets of the field launch in use
-  int nb_push = 0, nb_cell = 0, nb_win = 0, nb_neut = 0;
+  int nb_push = 0, nb_cell = 0, nb_win = 0, nb_neut = 0, nb_sort = 0;
   int tile = 0;               // field-kernel tile variant
   double tune_ms[8] = {0};    // autotuner: ms per field launch of each variant
   // in-run tuning of the field tile shape: the next tune_left steps cycle the
@@ -334,6 +335,11 @@ pic_status scratch_ptr(void** out) {
   return PIC_OK;
 }
 
+// offsets of the tile sort's grid in the block-offset table (after the
+// field shapes' pairs at 8 ..)
+constexpr int PH_SORT = 11;
+static_assert(2 * PH_SORT + 1 < 32, "block-offset table");
+
 Group single(pic_ctx* c, int phase, int nb) {
   Group g{c->d_inst, phase == 1 ? c->d_off_fields : c->d_off + 2 * phase, 1, nb, (int)c->step};
   g.front = &c->d_ctr->front;
@@ -456,7 +462,7 @@ void enqueue_step(pic_ctx* c) {
   const int D = c->canon.D, order = c->cfg.shape_order;
   hipStream_t s = c->stream;
   if (c->resort > 0 && c->step % c->resort == 0)
-    timed(c, 3, [&](Stamp st) { launch_sort(single(c, 0, c->nb_push), single(c, 2, 1), D, s, st); });
+    timed(c, 3, [&](Stamp st) { launch_sort(single(c, PH_SORT, c->nb_sort), single(c, 2, 1), D, s, st); });
   timed(c, 0, [&](Stamp st) { launch_push(single(c, 0, c->nb_push), D, order, c->canon.per[1], s, st); });
   if (c->tune_left > 0) {
     const int idx = field_tile_variants() * c->tune_reps - c->tune_left;
@@ -488,10 +494,9 @@ void enqueue_step(pic_ctx* c) {
   ++c->step;
 }
 
-// push and sort grid: persistent blocks (grid-stride over tile chunks and the
-// unsorted tail), sized by the slot capacity: 8 slots per thread, 16 .. 2048,
-// a multiple of 8 (the XCD count, so a work item keeps its XCD every round)
-int push_blocks(int64_t capacity) {
+// tile-sort grid: grid-stride blocks sized by the slot capacity, 8 slots per
+// thread, 16 .. 2048, a multiple of 8 (the XCD count)
+int sort_blocks(int64_t capacity) {
   const int64_t nb = (capacity + TPB * 8 - 1) / (TPB * 8);
   return (int)((std::max<int64_t>(16, std::min<int64_t>(nb, 2048)) + 7) / 8 * 8);
 }
@@ -832,6 +837,7 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
   I.step = &c->d_ctr->step;
   I.health = &c->d_ctr->health;
   I.nevents = c->d_ctr->nevents;
+  I.pq = c->d_ctr->pq;
   I.eflux = c->d_ctr->eflux;
   for (int d = 0; d < 3; ++d) {
     // a plane normal to axis d: eps0 c dt times the transverse cell area
@@ -885,7 +891,8 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
 
   // block counts per phase
   auto nblk = [](int64_t n) { return (int)std::max<int64_t>(0, (n + TPB - 1) / TPB); };
-  c->nb_push = push_blocks(L.capacity);
+  c->nb_push = push_grid(D);
+  if (c->nb_push <= 0) return fail(PIC_E_DEVICE);
   // field tile shape: default per dimension (the shapes the in-run timing
   // picks on MI355X for the benchmark grids: 60x8 in 2D, 12x8x4 in 3D),
   // overridable (tuning sweeps) by PIC_FIELD_TILE=<variant>
@@ -898,7 +905,9 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
     c->nb_neut = (int)std::max<int64_t>(1, (L.nneut + span - 1) / span);
   }
 
+  c->nb_sort = sort_blocks(L.capacity);
   int offs[32] = {0, c->nb_push, 0, c->nb_cell, 0, c->nb_win, 0, c->nb_neut};
+  offs[2 * PH_SORT + 1] = c->nb_sort;
   for (int v = 0; v < field_tile_variants(); ++v)
     offs[9 + 2 * v] = field_tiles(D, v, (int)L.Px, (int)L.Py, (int)L.Pz);
 
