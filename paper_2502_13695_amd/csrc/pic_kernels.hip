@@ -833,35 +833,57 @@ __global__ __launch_bounds__(push_tpb(D), D == 3 ? 4 : 1) void k_push(Group g, s
   // Work queues: the chunk list in 8 contiguous ranges, one per XCD (a block
   // runs on XCD blockIdx.x mod 8), so neighbouring tiles share that XCD's L2.
   // A block takes the next chunk of its own range (one atomic, issued while
-  // it works on the current chunk), then helps the other ranges.  The grid
+  // it works on the current chunk); when the range is used up it reads all
+  // eight counters at once and moves to a range with chunks left.  The grid
   // is the number of blocks resident at once: work goes to whichever block is
-  // free, so chunks of very different sizes leave no block idle.  The last
-  // block out clears the counters for the next launch.
+  // free, so chunks of very different sizes leave no block idle (blocks past
+  // the chunk count take no part).  The last block out of those taking part
+  // clears the counters for the next launch.
   __shared__ int s_next;
-  const int home = (int)(blockIdx.x & 7u);
-  for (int q = 0; q < 8; ++q) {
-    const int xq = (home + q) & 7;
-    const int lo = (int)((int64_t)nchunks * xq / 8), hi = (int)((int64_t)nchunks * (xq + 1) / 8);
-    int* const ctr = I.pq + 64 * xq;
-    if (threadIdx.x == 0) s_next = lo + atomicAdd(ctr, 1);
-    __syncthreads();
-    int v = s_next;
-    while (v < hi) {
-      int nxt = 0;
-      if (threadIdx.x == 0) nxt = lo + atomicAdd(ctr, 1);   // the next item, in flight meanwhile
-      work(v);
-      __syncthreads();   // the windows are free again, and s_next has been read
-      if (threadIdx.x == 0) s_next = nxt;
+  __shared__ int s_left[8];
+  auto range = [&](int x, int& lo, int& hi) {
+    lo = (int)((int64_t)nchunks * x / 8);
+    hi = (int)((int64_t)nchunks * (x + 1) / 8);
+  };
+  if (b0 < nchunks) {
+    int xq = (int)(blockIdx.x & 7u);
+    while (true) {
+      int lo, hi;
+      range(xq, lo, hi);
+      int* const ctr = I.pq + 64 * xq;
+      if (threadIdx.x == 0) s_next = lo < hi ? lo + atomicAdd(ctr, 1) : hi;
       __syncthreads();
-      v = s_next;
+      int v = s_next;
+      while (v < hi) {
+        int nxt = 0;
+        if (threadIdx.x == 0) nxt = lo + atomicAdd(ctr, 1);   // the next item, in flight meanwhile
+        work(v);
+        __syncthreads();   // the windows are free again, and s_next has been read
+        if (threadIdx.x == 0) s_next = nxt;
+        __syncthreads();
+        v = s_next;
+      }
+      if (threadIdx.x < 8) {
+        int l, h;
+        range((int)threadIdx.x, l, h);
+        s_left[threadIdx.x] = (h - l) - __hip_atomic_load(I.pq + 64 * threadIdx.x, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+      }
+      __syncthreads();
+      int pick = -1;
+      for (int k = 1; k <= 8 && pick < 0; ++k)
+        if (s_left[(xq + k) & 7] > 0) pick = (xq + k) & 7;
+      __syncthreads();
+      if (pick < 0) break;
+      xq = pick;
     }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    __threadfence();
-    if (atomicAdd(I.pq + 64 * 8, 1) == nb - 1) {
-      for (int x = 0; x <= 8; ++x) __hip_atomic_store(I.pq + 64 * x, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // the last of the min(nb, nchunks) taking part clears the counters
+    if (threadIdx.x == 0) {
       __threadfence();
+      if (atomicAdd(I.pq + 64 * 8, 1) == min(nb, nchunks) - 1) {
+        for (int x = 0; x <= 8; ++x) __hip_atomic_store(I.pq + 64 * x, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+      }
     }
   }
   const LSink<D> none{sJ, 0, 0, 0, 0.0};
