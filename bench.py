@@ -64,7 +64,7 @@ B_CELL, B_CELL_NO_J, B_WINDOW, B_SORTED = 73.0, 49.0, 24.0, 120.0
 FLOP_PUSH_3D2 = 990.0
 # steps of the in-run timing of the field tile shapes (7 shapes x 4 launches)
 TUNE_REPS = 4
-TUNE_STEPS = 7 * TUNE_REPS
+TUNE_STEPS = 8 * TUNE_REPS          # at most 8 field tile shapes, TUNE_REPS steps each
 
 
 class Roctx:
@@ -222,7 +222,8 @@ def run_window(cfg, start, steps, warmup, field_tile, roctx, resort=None):
     reg1 = ctx.region()
     sort1 = ctx.sort_state()
     ev = ctx.events()
-    tune = dict(chosen=int(timers[23]), blocks=int(timers[24]), ms=[float(x) for x in timers[16:23]])
+    tune = dict(chosen=int(timers[23]), blocks=int(timers[24]),
+                ms=[float(x) for x in timers[16:23]] + ([float(timers[26])] if timers[27] > 7 else []))
     ctx.close()
     assert sc1["health"] == 0, f"health word {sc1['health']}"
     return dict(wall=t1 - t0, timers=timers, sc0=sc0, sc1=sc1, reg0=reg0, reg1=reg1, sort0=sort0,

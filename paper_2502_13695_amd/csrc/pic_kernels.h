@@ -52,7 +52,9 @@ void launch_fields(const Group& g, int D, int variant, hipStream_t s, Stamp st =
 void launch_ionize(const Group& g, int D, int order, hipStream_t s, Stamp st = {});
 void launch_advance(Inst* insts, int n, hipStream_t s);   // batch: step counters + 1
 int field_tiles(int D, int variant, int Px, int Py, int Pz);   // blocks of the field launch
-int field_tile_variants();
+// field tile shapes of a run: the tiled shapes, plus the z-marching update in
+// 3D when y and z are periodic
+int field_tile_variants(int D, bool periodic_yz);
 int field_tile_x(int D, int variant);                          // owned x extent of a field tile
 
 // one-instance setup and diagnostics

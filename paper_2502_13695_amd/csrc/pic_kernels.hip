@@ -1210,9 +1210,13 @@ __host__ __device__ constexpr TileShape tile_shape(int D, int v) {
                    : TileShape{64, 8, 1})
                 : (v == 1 ? TileShape{12, 4, 8} : v == 2 ? TileShape{16, 4, 4} : v == 3 ? TileShape{28, 4, 4}
                    : v == 4 ? TileShape{12, 12, 4} : v == 5 ? TileShape{12, 4, 4} : v == 6 ? TileShape{12, 8, 4}
-                   : TileShape{16, 8, 4});
+                   : v == 7 ? TileShape{60, 8, 1} : TileShape{16, 8, 4});
 }
-constexpr int kTileVariants = 7;
+// Variant 7 (3D with periodic y and z only) is the z-marching update: x-y
+// tiles of 60 x 8 positions over the box, z in segments (as many as fill the
+// GPU's resident blocks).
+constexpr int kTileVariants = 8;
+constexpr int kMarchVariant = 7;
 
 __device__ __forceinline__ int wrap_any(int j, int n) {
   j %= n;
@@ -1708,6 +1712,409 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g, std::conditional_t<ONE,
   // a tile reaching past the field front moves it if it stored a nonzero value
   if (track) {
     if (__syncthreads_or(stored_nz) && threadIdx.x == 0) atomicMax(frontp, a0x + T::X - 1);
+  } else {
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && blk_hot) atomicOr(I.hot + par, 1);
+  if (threadIdx.x == 0) atomicAdd(I.tiles_done + 32 * (blockIdx.x & 7), 1ull);
+  if (chk != 0.0f) atomicOr(I.health, HEALTH_NONFINITE);
+  if (flux_tile) {
+    for (int o = 32; o > 0; o >>= 1) {
+      fin += __shfl_xor(fin, o);
+      fout += __shfl_xor(fout, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      double* ef = I.eflux + (blockIdx.x & 7) * 32;   // this XCD's line
+      if (fin != 0.0) atomicAdd(ef, fin);
+      if (fout != 0.0) atomicAdd(ef + 1, fout);
+    }
+  }
+}
+
+// ------------------------------------------------- field update, z-marching
+// The 3D update for periodic y and z as a march along z: a block owns an x-y
+// tile of ZX x ZY positions (x over the padded array, y over the box) and a
+// segment of ZS planes, and walks its planes upward with the halo of the
+// tiled update in x and y only (64 x 12 staged points per plane, 1.6x the
+// owned ones, against 5.3x for a 12 x 4 x 4 tile).  The launch's block count
+// sets the number of z segments.  Each thread keeps three
+// points of the plane; the next plane's fields and current are loaded while
+// the current plane is computed.  Plane t of the march: b^{n+1/2}(t) from
+// E^n(t) (in-plane neighbours, LDS) and E^n(t+1) (own point, registers);
+// E^{n+1}(t) from b^{n+1/2}(t) (LDS) and b^{n+1/2}(t-1) (registers); the x
+// faces of plane t; then plane t-1 is finished: b^{n+1}, the stores, the
+// current cleared, the amplitude window and the Poynting flux.  Every
+// position gets the same arithmetic as in the tiled update.
+constexpr int ZX = 60, ZY = 8, ZH = 2;
+constexpr int ZRX = ZX + 2 * ZH, ZRY = ZY + 2 * ZH;   // 64 x 12 staged
+constexpr int ZNP = ZRX * ZRY;
+constexpr int ZPT = ZNP / TPB;                        // points per thread
+static_assert(ZNP % TPB == 0 && ZRX == 64, "plane layout");
+
+template <bool ONE>
+__global__ __launch_bounds__(TPB, 4) void k_fields_z(Group g, std::conditional_t<ONE, Inst, NoInst> one) {
+  constexpr int LY = ZRX;
+  __shared__ float sEa[3][ZNP], sEb[3][ZNP], sBa[3][ZNP], sBb[3][ZNP];
+  __shared__ unsigned sbx[ZRX];
+  __shared__ float sieh[ZRX], sien[ZRX];
+  __shared__ int blk_hot;
+  const Slot sl = ONE ? Slot{0, (int)blockIdx.x, g.blocks} : block_slot(g);
+  auto& I = inst_of(g, sl.ii, one);
+  const int step = ONE || g.step >= 0 ? g.step : I.step_now;
+  const int par = step & 1;
+  int* const frontp = ONE ? g.front : I.front;
+  gmem<int>* const xe = gp(const_cast<int*>(ONE ? g.xext : I.xext) + 2 * (step % 3));
+  const int front = __hip_atomic_load(gp(frontp), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  const int xlo = __hip_atomic_load(xe, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  const int xhi = __hip_atomic_load(xe + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  const gmem<float>* __restrict__ Ec0 = gp(uniform(I.F[par][0]));
+  const gmem<float>* __restrict__ Ec1 = gp(uniform(I.F[par][1]));
+  const gmem<float>* __restrict__ Ec2 = gp(uniform(I.F[par][2]));
+  const gmem<float>* __restrict__ Bc0 = gp(uniform(I.F[par][3]));
+  const gmem<float>* __restrict__ Bc1 = gp(uniform(I.F[par][4]));
+  const gmem<float>* __restrict__ Bc2 = gp(uniform(I.F[par][5]));
+  gmem<float>* __restrict__ En0 = gp(uniform(I.F[par ^ 1][0]));
+  gmem<float>* __restrict__ En1 = gp(uniform(I.F[par ^ 1][1]));
+  gmem<float>* __restrict__ En2 = gp(uniform(I.F[par ^ 1][2]));
+  gmem<float>* __restrict__ Bn0 = gp(uniform(I.F[par ^ 1][3]));
+  gmem<float>* __restrict__ Bn1 = gp(uniform(I.F[par ^ 1][4]));
+  gmem<float>* __restrict__ Bn2 = gp(uniform(I.F[par ^ 1][5]));
+  const gmem<float>* __restrict__ J0 = gp(uniform(I.Jb[par][0]));
+  const gmem<float>* __restrict__ J1 = gp(uniform(I.Jb[par][1]));
+  const gmem<float>* __restrict__ J2 = gp(uniform(I.Jb[par][2]));
+  gmem<float>* __restrict__ Jn0 = gp(uniform(I.Jb[par ^ 1][0]));
+  gmem<float>* __restrict__ Jn1 = gp(uniform(I.Jb[par ^ 1][1]));
+  gmem<float>* __restrict__ Jn2 = gp(uniform(I.Jb[par ^ 1][2]));
+  const float hx = I.halfC[0], hy = I.halfC[1], hz = I.halfC[2];
+  const float Cx = I.C[0], Cy = I.C[1], Cz = I.C[2];
+  const int Px = I.Px, Py = I.Py;
+  const int nx = I.nx, ny = I.ny, nz = I.nz;
+  const int sy = I.sy, sz = I.sz, Gy = I.Gy, Gz = I.Gz;
+  const int ntx = (Px + ZX - 1) / ZX, nty = (ny + ZY - 1) / ZY;
+  const int tb = xcd_remap(sl.bk, sl.nbk);
+  const int tx = tb % ntx, rest = tb / ntx;
+  const int ty = rest % nty, seg = rest / nty;
+  const int nseg = sl.nbk / (ntx * nty);   // segments of z (the launch's block count decides)
+  const int zs = (nz + nseg - 1) / nseg;
+  const int a0x = tx * ZX;           // padded x of local column ZH
+  const int j0 = ty * ZY;            // y of local row ZH
+  const int k0 = seg * zs, k1 = min(k0 + zs, nz);
+  // far tiles (no current ever) and tiles beyond the field front, as in the tiled update
+  bool cur = true;
+  if (g.part >= 1) {
+    int lo = xlo, hi = xhi;
+    if (I.wx1 > I.wx0) {
+      lo = min(lo, I.wx0 - G);
+      hi = max(hi, I.wx1 - 1 - G);
+    }
+    const int alo = lo - XNEAR_MARGIN + G, ahi = hi + XNEAR_MARGIN + G;
+    cur = lo <= hi && a0x <= ahi && a0x + ZX - 1 >= alo;
+  }
+  if (g.part == 1 && !cur && a0x - ZH > front) return;
+  if (threadIdx.x == 0) blk_hot = 0;
+  for (int q = threadIdx.x; q < ZRX; q += TPB) {
+    const int i = a0x - G + q - ZH;
+    const int ai = a0x + q - ZH;
+    sbx[q] = axis_bits(i, nx, false, ai >= 0 && ai < Px);
+    const bool in = ai >= 0 && ai < Px;
+    sieh[q] = in ? I.ie_half[ai] : 1.0f;
+    sien[q] = in ? I.ie_node[ai] : 1.0f;
+  }
+  // this thread's points: row offsets (y wrapped) and per-point facts
+  int qxs[ZPT], qys[ZPT];
+  unsigned rowo[ZPT];
+  bool owny[ZPT];
+#pragma unroll
+  for (int p = 0; p < ZPT; ++p) {
+    const int l = threadIdx.x + p * TPB;
+    qxs[p] = l & (ZRX - 1);
+    qys[p] = l / ZRX;
+    const int j = j0 + qys[p] - ZH;
+    rowo[p] = (unsigned)(sy * (wrap_any(j, ny) + Gy));
+    owny[p] = qys[p] >= ZH && qys[p] < ZH + ZY && j < ny;
+  }
+  __syncthreads();
+  auto plane = [&](int k) { return (unsigned)(sz * (wrap_any(k, nz) + Gz)); };
+  auto pt_in = [&](int p) { return (sbx[qxs[p]] & AX_ARR) != 0u; };
+  auto eregion = [&](int p) {
+    return qxs[p] >= ZH - 1 && qxs[p] <= ZX + ZH && qys[p] >= ZH - 1 && qys[p] <= ZY + ZH;
+  };
+  // loads of plane k: E^n and b^n at every staged point, J at the E region
+  auto load_eb = [&](int k, float (&e)[ZPT][3], float (&b)[ZPT][3]) {
+    const unsigned pk = plane(k);
+#pragma unroll
+    for (int p = 0; p < ZPT; ++p) {
+      const bool in = pt_in(p);
+      const unsigned gi = (unsigned)(a0x + qxs[p] - ZH) + rowo[p] + pk;
+      e[p][0] = in ? at(Ec0, gi) : 0.0f;
+      e[p][1] = in ? at(Ec1, gi) : 0.0f;
+      e[p][2] = in ? at(Ec2, gi) : 0.0f;
+      b[p][0] = in ? at(Bc0, gi) : 0.0f;
+      b[p][1] = in ? at(Bc1, gi) : 0.0f;
+      b[p][2] = in ? at(Bc2, gi) : 0.0f;
+    }
+  };
+  auto load_j = [&](int k, float (&j)[ZPT][3]) {
+    const unsigned pk = plane(k);
+#pragma unroll
+    for (int p = 0; p < ZPT; ++p) {
+      const bool c = cur && pt_in(p) && eregion(p);
+      const unsigned gi = (unsigned)(a0x + qxs[p] - ZH) + rowo[p] + pk;
+      j[p][0] = c ? at(J0, gi) : 0.0f;
+      j[p][1] = c ? at(J1, gi) : 0.0f;
+      j[p][2] = c ? at(J2, gi) : 0.0f;
+    }
+  };
+  // plane buffers: c* the plane being advanced, p* the plane before it
+  float (*cE)[ZNP] = sEa;
+  float (*pE)[ZNP] = sEb;
+  float (*cB)[ZNP] = sBa;
+  float (*pB)[ZNP] = sBb;
+  float ne[ZPT][3], nb[ZPT][3];     // E^n, b^n of plane t + 1
+  float ne2[ZPT][3], nb2[ZPT][3];   // of plane t + 2 (in flight)
+  float jc[ZPT][3], jn[ZPT][3];     // J of plane t, t + 1
+  float bh0[ZPT], bh1[ZPT];         // b^{n+1/2}_x, _y of plane t - 1 at the own points
+  float e2p[ZPT], e2pp[ZPT];        // final E_z of planes t - 1, t - 2
+  {
+    float e0[ZPT][3], b0[ZPT][3];
+    load_eb(k0 - 2, e0, b0);
+    load_eb(k0 - 1, ne, nb);
+    load_j(k0 - 2, jc);
+#pragma unroll
+    for (int p = 0; p < ZPT; ++p) {
+      const int l = threadIdx.x + p * TPB;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        cE[c][l] = e0[p][c];
+        cB[c][l] = b0[p][c];
+      }
+      bh0[p] = bh1[p] = e2p[p] = e2pp[p] = 0.0f;
+    }
+  }
+  __syncthreads();
+  const bool xface = (a0x - G - ZH + 1 <= 0 && 0 <= a0x - G + ZX) || (a0x - G - ZH + 1 <= nx && nx <= a0x - G + ZX);
+  const bool flux_tile = (a0x <= G + 1 && G + 1 < a0x + ZX) || (a0x <= G + nx - 1 && G + nx - 1 < a0x + ZX);
+  const bool track = a0x + ZX - 1 > front;
+  const int nwin = I.nwin;
+  const int slot = step % (nwin > 0 ? nwin : 1);
+  const int wx0 = I.wx0, wx1 = I.wx1;
+  double fin = 0.0, fout = 0.0;
+  float chk = 0.0f;
+  bool stored_nz = false;
+  float4 s0 = make_float4(0.f, 0.f, 0.f, 0.f), s1 = s0;
+  if (step < I.nsrc) s0 = I.src[step];
+  if (step + 1 < I.nsrc) s1 = I.src[step + 1];
+  for (int t = k0 - 2; t <= k1 && k0 < k1; ++t) {
+    load_eb(t + 2, ne2, nb2);
+    load_j(t + 1, jn);
+    // ---- b^{n+1/2}(t) on local [-2, T] (in place)
+#pragma unroll
+    for (int p = 0; p < ZPT; ++p) {
+      const int l = threadIdx.x + p * TPB;
+      const int qx = qxs[p], qy = qys[p];
+      if (qx > ZX + ZH || qy > ZY + ZH) continue;
+      const unsigned bx = sbx[qx];
+      if (bx & AX_BN) {
+        float cu = 0.0f;
+        cu += hy * (cE[2][l + LY] - cE[2][l]);
+        cu -= hz * (ne[p][1] - cE[1][l]);
+        cB[0][l] -= cu;
+      }
+      if (bx & AX_BH) {
+        float cu = -hx * (cE[2][l + 1] - cE[2][l]);
+        cu += hz * (ne[p][0] - cE[0][l]);
+        cB[1][l] -= cu;
+      }
+      if (bx & AX_BH) {
+        float cu = hx * (cE[1][l + 1] - cE[1][l]);
+        cu -= hy * (cE[0][l + LY] - cE[0][l]);
+        cB[2][l] -= cu;
+      }
+    }
+    __syncthreads();
+    if (t >= k0 - 1) {
+      // ---- E^{n+1}(t) on local [-1, T] (in place)
+#pragma unroll
+      for (int p = 0; p < ZPT; ++p) {
+        const int l = threadIdx.x + p * TPB;
+        const int qx = qxs[p];
+        if (!eregion(p)) continue;
+        const unsigned bx = sbx[qx];
+        if (!(bx & AX_ARR)) continue;
+        if (bx & AX_IH) {
+          float cu = 0.0f;
+          cu += Cy * (cB[2][l] - cB[2][l - LY]);
+          cu -= Cz * (cB[1][l] - bh1[p]);
+          cE[0][l] += sieh[qx] * (cu - jc[p][0]);
+        }
+        if (bx & AX_IN) {
+          float cu = -Cx * (cB[2][l] - cB[2][l - 1]);
+          cu += Cz * (cB[0][l] - bh0[p]);
+          cE[1][l] += sien[qx] * (cu - jc[p][1]);
+        }
+        if (bx & AX_IN) {
+          float cu = Cx * (cB[1][l] - cB[1][l - 1]);
+          cu -= Cy * (cB[0][l] - cB[0][l - LY]);
+          cE[2][l] += sien[qx] * (cu - jc[p][2]);
+        }
+      }
+      __syncthreads();
+      // ---- x faces of plane t (y and z periodic: no other face)
+      if (xface) {
+        const unsigned pk = plane(t);
+#pragma unroll
+        for (int p = 0; p < ZPT; ++p) {
+          const int l = threadIdx.x + p * TPB;
+          const int qx = qxs[p];
+          if (!eregion(p)) continue;
+          const unsigned bx = sbx[qx];
+          if (!(bx & (AX_F0 | AX_F1))) continue;
+          const int inw = (bx & AX_F0) ? 1 : -1;
+          const int qd = qx + inw;
+          if (qd < ZH - 1 || qd > ZX + ZH) continue;
+          const unsigned gq = (unsigned)(a0x + qx - ZH) + rowo[p] + pk;
+          const unsigned gr = gq + inw;
+#pragma unroll
+          for (int c = 1; c < 3; ++c) {
+            const gmem<float>* Eold = c == 1 ? Ec1 : Ec2;
+            const float qold = at(Eold, gq), rold = at(Eold, gr), rnew = cE[c][l + inw];
+            if ((bx & AX_F0) && c == I.pol) {
+              const float pr = I.prof[(int)(rowo[p] / (unsigned)sy) + Py * (int)(pk / (unsigned)sz)];
+              const MurInc m{pr * s0.x, pr * s1.x, pr * s0.y, pr * s1.y};
+              cE[c][l] = mur_inc(qold, rold, rnew, I.kmur[0], m);
+            } else {
+              cE[c][l] = mur(qold, rold, rnew, I.kmur[0]);
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    // ---- finish plane f = t - 1 at the owned positions
+    if (t >= k0 + 1) {
+      const int f = t - 1;
+      const unsigned pk = plane(f);
+      const int ak = wrap_any(f, nz) + Gz;   // padded z of plane f
+#pragma unroll
+      for (int p = 0; p < ZPT; ++p) {
+        const int l = threadIdx.x + p * TPB;
+        const int qx = qxs[p];
+        if (qx < ZH || qx >= ZX + ZH || !owny[p]) continue;
+        const int ai = a0x + qx - ZH;
+        if (ai >= Px) continue;
+        const unsigned gi = (unsigned)ai + rowo[p] + pk;
+        if (cur) {
+          at(Jn0, gi) = 0.0f;
+          at(Jn1, gi) = 0.0f;
+          at(Jn2, gi) = 0.0f;
+        }
+        const unsigned bx = sbx[qx];
+        const bool xdn = bx & AX_DN, xdh = bx & AX_DH;
+        if (xdh) {
+          at(En0, gi) = pE[0][l];
+          stored_nz = stored_nz || (track && pE[0][l] != 0.0f);
+        }
+        if (xdn) {
+          at(En1, gi) = pE[1][l];
+          stored_nz = stored_nz || (track && pE[1][l] != 0.0f);
+          at(En2, gi) = pE[2][l];
+          stored_nz = stored_nz || (track && pE[2][l] != 0.0f);
+        }
+        chk = fmaf(pE[0][l] + pE[1][l] + pE[2][l], 0.0f, chk);
+        if (flux_tile) {
+          const int i = ai - G;
+          auto term = [&](float en, float eo, float b0v, float b1v, double coef) {
+            const double v = coef * 1.0 * (0.5 * ((double)en + (double)eo)) * (0.5 * ((double)b0v + (double)b1v));
+            if (v > 0.0) fin += v; else fout -= v;
+          };
+          if (xdn && (i == 1 || i == nx - 1)) {
+            const double c = (i == 1 ? 1.0 : -1.0) * I.kflux[0];
+            term(pE[1][l], at(Ec1, gi), pB[2][l - 1], pB[2][l], c);
+            term(pE[2][l], at(Ec2, gi), pB[1][l - 1], pB[1][l], -c);
+          }
+        }
+        if (xdn) {
+          float cu = 0.0f;
+          cu += hy * (pE[2][l + LY] - pE[2][l]);
+          cu -= hz * (cE[1][l] - pE[1][l]);
+          const float v = pB[0][l] - cu;
+          at(Bn0, gi) = v;
+          stored_nz = stored_nz || (track && v != 0.0f);
+        }
+        if (xdh) {
+          float cu = -hx * (pE[2][l + 1] - pE[2][l]);
+          cu += hz * (cE[0][l] - pE[0][l]);
+          const float v = pB[1][l] - cu;
+          at(Bn1, gi) = v;
+          stored_nz = stored_nz || (track && v != 0.0f);
+          float cu2 = hx * (pE[1][l + 1] - pE[1][l]);
+          cu2 -= hy * (pE[0][l + LY] - pE[0][l]);
+          const float v2 = pB[2][l] - cu2;
+          at(Bn2, gi) = v2;
+          stored_nz = stored_nz || (track && v2 != 0.0f);
+        }
+        if (ai >= wx0 && ai < wx1 && xdn) {
+          const float ex = 0.5f * (pE[0][l - 1] + pE[0][l]);
+          const float ey = 0.5f * (pE[1][l - LY] + pE[1][l]);
+          const float ez = 0.5f * (e2pp[p] + pE[2][l]);
+          const float m = sqrtf(ex * ex + ey * ey + ez * ez);
+          if (!(m <= 3.0e38f)) atomicOr(I.health, HEALTH_NONFINITE);
+          const int64_t wsz = I.wsz;
+          const int aj = (int)(rowo[p] / (unsigned)sy);
+          const int64_t w = (int64_t)(ai - wx0) + (int64_t)I.wnx * (aj + (int64_t)Py * ak);
+          gmem<float>* __restrict__ ring = gp(I.ring);
+          gmem<float>* __restrict__ suffix = gp(I.suffix);
+          ring[(int64_t)slot * wsz + w] = m;
+          gmem<float>* __restrict__ prefix = gp(I.prefix);
+          const float pre = slot == 0 ? m : fmaxf(prefix[w], m);
+          prefix[w] = pre;
+          const float a = slot + 1 < nwin ? fmaxf(suffix[(int64_t)(slot + 1) * wsz + w], pre) : pre;
+          at(gp(uniform(I.A)), gi) = a;
+          if (a >= I.acut_min) blk_hot = 1;
+          if (slot == nwin - 1) {
+            float run = 0.0f;
+            for (int q = nwin - 1; q >= 0; --q) {
+              run = fmaxf(run, ring[(int64_t)q * wsz + w]);
+              suffix[(int64_t)q * wsz + w] = run;
+            }
+          }
+        }
+      }
+    }
+    // ---- rotate: plane t becomes the previous one, plane t + 1 the current
+#pragma unroll
+    for (int p = 0; p < ZPT; ++p) {
+      const int l = threadIdx.x + p * TPB;
+      bh0[p] = cB[0][l];
+      bh1[p] = cB[1][l];
+      e2pp[p] = e2p[p];
+      e2p[p] = cE[2][l];
+    }
+    __syncthreads();
+    {
+      float (*te)[ZNP] = pE;
+      pE = cE;
+      cE = te;
+      float (*tbp)[ZNP] = pB;
+      pB = cB;
+      cB = tbp;
+    }
+#pragma unroll
+    for (int p = 0; p < ZPT; ++p) {
+      const int l = threadIdx.x + p * TPB;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        cE[c][l] = ne[p][c];
+        cB[c][l] = nb[p][c];
+        ne[p][c] = ne2[p][c];
+        nb[p][c] = nb2[p][c];
+        jc[p][c] = jn[p][c];
+      }
+    }
+    __syncthreads();
+  }
+  if (track) {
+    if (__syncthreads_or(stored_nz) && threadIdx.x == 0) atomicMax(frontp, a0x + ZX - 1);
   } else {
     __syncthreads();
   }
@@ -2368,14 +2775,42 @@ void launch_fields(const Group& g, int D, int variant, hipStream_t s, Stamp st) 
     case 4: DISPATCH_D(D, FIELDS_V(DD, 4)); break;
     case 5: DISPATCH_D(D, FIELDS_V(DD, 5)); break;
     case 6: DISPATCH_D(D, FIELDS_V(DD, 6)); break;
+    case kMarchVariant:
+      if (D == 3) {
+        if (one)
+          GO((k_fields_z<true>), g.blocks, TPB, s, st.start, st.stop, g, *g.host);
+        else
+          GO((k_fields_z<false>), g.blocks, TPB, s, st.start, st.stop, g, NoInst{});
+        break;
+      }
+      [[fallthrough]];
     default: DISPATCH_D(D, FIELDS_V(DD, 0)); break;
   }
 }
 int field_tiles(int D, int variant, int Px, int Py, int Pz) {
   const TileShape t = tile_shape(D, variant);
+  if (D == 3 && variant == kMarchVariant) {
+    // x over the padded array, y and z over the box (padded extents are
+    // n + 1 + 2 G); z cut into as many segments as fill the resident blocks
+    const int ny = Py - 1 - 2 * G, nz = Pz - 1 - 2 * G;
+    const int cols = ((Px + t.x - 1) / t.x) * ((ny + t.y - 1) / t.y);
+    static int slots = 0;
+    if (!slots) {
+      int dev = 0, bpc = 0;
+      hipDeviceProp_t pr{};
+      if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&pr, dev) == hipSuccess &&
+          hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, k_fields_z<true>, TPB, 0) == hipSuccess && bpc > 0)
+        slots = bpc * pr.multiProcessorCount;
+      else
+        slots = 1024;
+    }
+    const int want = std::max(1, std::min(nz, slots / std::max(1, cols)));
+    const int zs = (nz + want - 1) / want;
+    return cols * ((nz + zs - 1) / zs);
+  }
   return ((Px + t.x - 1) / t.x) * (D >= 2 ? (Py + t.y - 1) / t.y : 1) * (D >= 3 ? (Pz + t.z - 1) / t.z : 1);
 }
-int field_tile_variants() { return kTileVariants; }
+int field_tile_variants(int D, bool periodic_yz) { return D == 3 && periodic_yz ? kTileVariants : kTileVariants - 1; }
 int field_tile_x(int D, int variant) { return tile_shape(D, variant).x; }
 void launch_ionize(const Group& g, int D, int order, hipStream_t s, Stamp st) {
   const bool one = g.n == 1 && g.host && g.step >= 0;

@@ -217,6 +217,7 @@ struct pic_ctx {
   // in-run tuning of the field tile shape: the next tune_left steps cycle the
   // shapes (tune_reps steps each; results identical), timing every launch
   int tune_left = 0, tune_reps = 0;
+  int nvar = 7;                // field tile shapes this run can use
   hipEvent_t tune_ev[8][16][2] = {};
   Ctr* d_ctr = nullptr;
   double* d_grid64 = nullptr;
@@ -337,7 +338,7 @@ pic_status scratch_ptr(void** out) {
 
 // offsets of the tile sort's grid in the block-offset table (after the
 // field shapes' pairs at 8 ..)
-constexpr int PH_SORT = 11;
+constexpr int PH_SORT = 12;
 static_assert(2 * PH_SORT + 1 < 32, "block-offset table");
 
 Group single(pic_ctx* c, int phase, int nb) {
@@ -438,7 +439,7 @@ void harvest_all(pic_ctx* c) {
 // 2 ionize (+ step counter), 3 tile sort (when a check is due)
 // End of the in-run tuning: the fastest shape (best of its launches) is kept.
 void finish_tuning(pic_ctx* c) {
-  const int nv = field_tile_variants();
+  const int nv = c->nvar;
   (void)hipEventSynchronize(c->tune_ev[nv - 1][c->tune_reps - 1][1]);
   double best = 1e30;
   for (int v = 0; v < nv; ++v) {
@@ -465,7 +466,7 @@ void enqueue_step(pic_ctx* c) {
     timed(c, 3, [&](Stamp st) { launch_sort(single(c, PH_SORT, c->nb_sort), single(c, 2, 1), D, s, st); });
   timed(c, 0, [&](Stamp st) { launch_push(single(c, 0, c->nb_push), D, order, c->canon.per[1], s, st); });
   if (c->tune_left > 0) {
-    const int idx = field_tile_variants() * c->tune_reps - c->tune_left;
+    const int idx = c->nvar * c->tune_reps - c->tune_left;
     const int v = idx / c->tune_reps, r = idx % c->tune_reps;
     const Layout& L = c->L;
     // every tile is updated while the shapes are timed (with tiles beyond the
@@ -897,7 +898,8 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
   // picks on MI355X for the benchmark grids: 60x8 in 2D, 12x8x4 in 3D),
   // overridable (tuning sweeps) by PIC_FIELD_TILE=<variant>
   c->tile = D == 2 ? 5 : (D == 3 ? 6 : 0);
-  if (const char* tv = std::getenv("PIC_FIELD_TILE")) c->tile = std::max(0, std::min(atoi(tv), field_tile_variants() - 1));
+  c->nvar = field_tile_variants(D, c->canon.per[1] && (D < 3 || c->canon.per[2]));
+  if (const char* tv = std::getenv("PIC_FIELD_TILE")) c->tile = std::max(0, std::min(atoi(tv), c->nvar - 1));
   c->nb_cell = field_tiles(D, c->tile, (int)L.Px, (int)L.Py, (int)L.Pz);
   c->nb_win = 1;   // one block per instance (tile-sort scan)
   {
@@ -908,7 +910,7 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
   c->nb_sort = sort_blocks(L.capacity);
   int offs[32] = {0, c->nb_push, 0, c->nb_cell, 0, c->nb_win, 0, c->nb_neut};
   offs[2 * PH_SORT + 1] = c->nb_sort;
-  for (int v = 0; v < field_tile_variants(); ++v)
+  for (int v = 0; v < c->nvar; ++v)
     offs[9 + 2 * v] = field_tiles(D, v, (int)L.Px, (int)L.Py, (int)L.Pz);
 
   hipStream_t s = c->stream;
@@ -1057,7 +1059,7 @@ pic_status pic_restore(pic_ctx* c, const void* host_in, size_t in_bytes) {
   if (h.magic != kSnapMagic || h.version != 1 || h.hdr_bytes != sizeof(SnapHdr)) return PIC_E_VERSION;
   const Layout& L = c->L;
   if (h.total != (uint64_t)L.total || h.key != snap_key(c) || in_bytes < sizeof h + (size_t)L.total ||
-      h.tile < 0 || h.tile >= field_tile_variants())
+      h.tile < 0 || h.tile >= c->nvar)
     return PIC_E_INVAL;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return PIC_E_DEVICE;
   harvest_all(c);
@@ -1189,9 +1191,9 @@ pic_status pic_autotune(pic_ctx* c, int32_t reps) {
   int offs[2];
   // three interleaved rounds over the tile shapes, best round of each kept
   // (the differences are a few percent, close to the launch-to-launch noise)
-  for (int v = 0; v < field_tile_variants(); ++v) c->tune_ms[v] = 1e30;
+  for (int v = 0; v < c->nvar; ++v) c->tune_ms[v] = 1e30;
   for (int round = 0; round < 3; ++round) {
-    for (int v = 0; v < field_tile_variants(); ++v) {
+    for (int v = 0; v < c->nvar; ++v) {
       const int nb = field_tiles(D, v, (int)L.Px, (int)L.Py, (int)L.Pz);
       offs[0] = 0;
       offs[1] = nb;
@@ -1210,7 +1212,7 @@ pic_status pic_autotune(pic_ctx* c, int32_t reps) {
       c->tune_ms[v] = std::min(c->tune_ms[v], (double)ms / reps);
     }
   }
-  for (int v = 0; v < field_tile_variants(); ++v)
+  for (int v = 0; v < c->nvar; ++v)
     if (c->tune_ms[v] < best) {
       best = c->tune_ms[v];
       best_v = v;
@@ -1241,12 +1243,12 @@ pic_status pic_autotune(pic_ctx* c, int32_t reps) {
 pic_status pic_autotune_steps(pic_ctx* c, int32_t reps) {
   if (!c || reps < 1 || reps > 16) return PIC_E_INVAL;
   if (c->tune_left > 0) return PIC_E_STATE;
-  for (int v = 0; v < field_tile_variants(); ++v)
+  for (int v = 0; v < c->nvar; ++v)
     for (int r = 0; r < reps; ++r)
       for (int e = 0; e < 2; ++e)
         if (!c->tune_ev[v][r][e]) HIP_OK(timing_event(&c->tune_ev[v][r][e]));
   c->tune_reps = reps;
-  c->tune_left = field_tile_variants() * reps;
+  c->tune_left = c->nvar * reps;
   return PIC_OK;
 }
 
@@ -1564,6 +1566,8 @@ pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size
     o[24] = c->nb_cell;
     o[25] = c->nb_push;
     for (int k = 26; k < 32; ++k) o[k] = 0.0;
+    o[26] = c->nvar > 7 ? c->tune_ms[7] : 0.0;   // the z-marching update, where it applies
+    o[27] = c->nvar;
     return PIC_OK;
   }
   // ---- SCALARS

@@ -389,13 +389,53 @@ def test_run_2d_slab_gaussian_beam(P):
     ctx.close()
 
 
-def test_run_3d_mirror_periodic(P):
+@pytest.mark.parametrize("field_tile", ["tiled", "march"])
+def test_run_3d_mirror_periodic(P, field_tile, monkeypatch):
     # the mirror share of the 3D workload (1 J/cm^2, 8 neutrals per cell),
-    # transversely reduced to 8 x 8 cells (periodic, plane wave)
+    # transversely reduced to 8 x 8 cells (periodic, plane wave); the field
+    # update by its default tile shape, or marching along z
+    if field_tile == "march":
+        monkeypatch.setenv("PIC_FIELD_TILE", "7")
     cfg = W.config_3d(nx=96, ny=8, nz=8, nsteps=380, ppc=8, fluence=1.0, front=24)
     ctx, sim = _run_both(P, cfg, 380)
-    _compare_run(P, ctx, sim, min_events=20, name="run_3d")
+    if field_tile == "march":
+        assert int(ctx.timers()[23]) == 7
+    _compare_run(P, ctx, sim, min_events=20, name="run_3d" + ("_march" if field_tile == "march" else ""))
     ctx.close()
+
+
+def test_marching_field_update_matches_tiled_bitwise(P, monkeypatch):
+    """The z-marching 3D update (periodic y and z) against the tiled update:
+    random fields in a box whose y and z extents leave partial tiles and
+    segments (20 = 2.5 x 8 rows, 36 = 2.25 x 16 planes), the layers' 1/eps,
+    the pulse entering through the x_min face, both x faces, the amplitude
+    window; fields too weak to ionize, so no current and no atomics: every
+    field value and the amplitude equal bit for bit after each of 12 steps,
+    the Poynting sums to FP64 rounding."""
+    cfg = W.config_3d(nx=128, ny=20, nz=36, nsteps=200, ppc=2, fluence=1.0, front=24)
+    rng = np.random.default_rng(77)
+    E = [rng.uniform(-1e6, 1e6, W.domain_shape(cfg, "E", c)).astype(np.float32) for c in range(3)]
+    b = [rng.uniform(-1e6, 1e6, W.domain_shape(cfg, "b", c)).astype(np.float32) for c in range(3)]
+    out = {}
+    for tile in ("5", "7"):
+        monkeypatch.setenv("PIC_FIELD_TILE", tile)
+        ctx = P.Context(cfg)
+        assert int(ctx.timers()[23]) == int(tile)
+        ctx.set_state(0, E, b, None)
+        runs = []
+        for _ in range(12):
+            ctx.step(1)
+            Eg, bg = ctx.fields()
+            sc = ctx.scalars()
+            runs.append((Eg, bg, ctx.amp(), ctx.region()["front"], sc["e_in"], sc["e_out"], sc["events"]))
+        out[tile] = runs
+        ctx.close()
+    for (Ea, ba, Aa, _, ia, oa, va), (Eb, bb, Ab, _, ib, ob, vb) in zip(out["5"], out["7"]):
+        for c in range(3):
+            assert np.array_equal(Ea[c], Eb[c]) and np.array_equal(ba[c], bb[c]), c
+        # (the field front is kept per tile column, so its value follows the tile width)
+        assert np.array_equal(Aa, Ab) and va == vb == 0
+        assert abs(ia - ib) <= 1e-12 * abs(ia) and abs(oa - ob) <= 1e-12 * max(abs(ia), abs(oa))
 
 
 def test_run_3d_mirror_share_against_stored_oracle(P):
