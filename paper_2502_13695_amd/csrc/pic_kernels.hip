@@ -1755,6 +1755,10 @@ template <bool ONE>
 __global__ __launch_bounds__(TPB, 4) void k_fields_z(Group g, std::conditional_t<ONE, Inst, NoInst> one) {
   constexpr int LY = ZRX;
   __shared__ float sEa[3][ZNP], sEb[3][ZNP], sBa[3][ZNP], sBb[3][ZNP];
+  // E^n_y, E^n_z of the last two planes at the x-face columns [side][0] and
+  // their inward neighbours [side][1] (the Mur conditions' old values; the
+  // inward columns are also the flux planes), kept before E^{n+1} overwrites
+  __shared__ float sOld[2][2][2][2][ZRY];
   __shared__ unsigned sbx[ZRX];
   __shared__ float sieh[ZRX], sien[ZRX];
   __shared__ int blk_hot;
@@ -1895,6 +1899,9 @@ __global__ __launch_bounds__(TPB, 4) void k_fields_z(Group g, std::conditional_t
   const bool xface = (a0x - G - ZH + 1 <= 0 && 0 <= a0x - G + ZX) || (a0x - G - ZH + 1 <= nx && nx <= a0x - G + ZX);
   const bool flux_tile = (a0x <= G + 1 && G + 1 < a0x + ZX) || (a0x <= G + nx - 1 && G + nx - 1 < a0x + ZX);
   const bool track = a0x + ZX - 1 > front;
+  gmem<float>* __restrict__ wring = gp(I.ring);
+  gmem<float>* __restrict__ wprefix = gp(I.prefix);
+  gmem<float>* __restrict__ wsuffix = gp(I.suffix);
   const int nwin = I.nwin;
   const int slot = step % (nwin > 0 ? nwin : 1);
   const int wx0 = I.wx0, wx1 = I.wx1;
@@ -1929,6 +1936,23 @@ __global__ __launch_bounds__(TPB, 4) void k_fields_z(Group g, std::conditional_t
         float cu = hx * (cE[1][l + 1] - cE[1][l]);
         cu -= hy * (cE[0][l + LY] - cE[0][l]);
         cB[2][l] -= cu;
+      }
+    }
+    if (xface) {
+#pragma unroll
+      for (int p = 0; p < ZPT; ++p) {
+        const int l = threadIdx.x + p * TPB;
+        const int qx = qxs[p], qy = qys[p];
+        const unsigned bx = sbx[qx];
+        int side = -1, fi = 0;
+        if (bx & AX_F0) side = 0;
+        else if (bx & AX_F1) side = 1;
+        else if (qx >= 1 && (sbx[qx - 1] & AX_F0)) side = 0, fi = 1;
+        else if (qx + 1 < ZRX && (sbx[qx + 1] & AX_F1)) side = 1, fi = 1;
+        if (side >= 0) {
+          sOld[t & 1][side][fi][0][qy] = cE[1][l];
+          sOld[t & 1][side][fi][1][qy] = cE[2][l];
+        }
       }
     }
     __syncthreads();
@@ -1972,12 +1996,11 @@ __global__ __launch_bounds__(TPB, 4) void k_fields_z(Group g, std::conditional_t
           const int inw = (bx & AX_F0) ? 1 : -1;
           const int qd = qx + inw;
           if (qd < ZH - 1 || qd > ZX + ZH) continue;
-          const unsigned gq = (unsigned)(a0x + qx - ZH) + rowo[p] + pk;
-          const unsigned gr = gq + inw;
+          const int side = (bx & AX_F0) ? 0 : 1;
 #pragma unroll
           for (int c = 1; c < 3; ++c) {
-            const gmem<float>* Eold = c == 1 ? Ec1 : Ec2;
-            const float qold = at(Eold, gq), rold = at(Eold, gr), rnew = cE[c][l + inw];
+            const float qold = sOld[t & 1][side][0][c - 1][qys[p]], rold = sOld[t & 1][side][1][c - 1][qys[p]];
+            const float rnew = cE[c][l + inw];
             if ((bx & AX_F0) && c == I.pol) {
               const float pr = I.prof[(int)(rowo[p] / (unsigned)sy) + Py * (int)(pk / (unsigned)sz)];
               const MurInc m{pr * s0.x, pr * s1.x, pr * s0.y, pr * s1.y};
@@ -1987,14 +2010,45 @@ __global__ __launch_bounds__(TPB, 4) void k_fields_z(Group g, std::conditional_t
             }
           }
         }
-        __syncthreads();
+        // no barrier: a face value is read next by its own thread (b^{n+1}
+        // of plane t - 1 below), by the others only after the rotation's
       }
     }
-    // ---- finish plane f = t - 1 at the owned positions
+    // ---- finish plane f = t - 1 at the owned positions: first the loads
+    // it needs (window samples, old E on the flux planes), in flight while
+    // the fields are stored
     if (t >= k0 + 1) {
       const int f = t - 1;
       const unsigned pk = plane(f);
       const int ak = wrap_any(f, nz) + Gz;   // padded z of plane f
+      const int64_t wsz = I.wsz;
+      float wpre[ZPT], wsuf[ZPT], eo1[ZPT], eo2[ZPT];
+      int64_t wix[ZPT];
+#pragma unroll
+      for (int p = 0; p < ZPT; ++p) {
+        wpre[p] = wsuf[p] = eo1[p] = eo2[p] = 0.0f;
+        wix[p] = -1;
+        const int qx = qxs[p];
+        if (qx < ZH || qx >= ZX + ZH || !owny[p]) continue;
+        const int ai = a0x + qx - ZH;
+        if (ai >= Px) continue;
+        const unsigned gi = (unsigned)ai + rowo[p] + pk;
+        const unsigned bx = sbx[qx];
+        if (ai >= wx0 && ai < wx1 && (bx & AX_DN)) {
+          const int aj = (int)(rowo[p] / (unsigned)sy);
+          const int64_t w = (int64_t)(ai - wx0) + (int64_t)I.wnx * (aj + (int64_t)Py * ak);
+          wix[p] = w;
+          if (slot != 0) wpre[p] = wprefix[w];
+          if (slot + 1 < nwin) wsuf[p] = wsuffix[(int64_t)(slot + 1) * wsz + w];
+        }
+        const int i = ai - G;
+        if (flux_tile && (bx & AX_DN) && (i == 1 || i == nx - 1)) {
+          // the flux planes are the columns next to the x faces
+          const int side = i == 1 ? 0 : 1;
+          eo1[p] = sOld[f & 1][side][1][0][qys[p]];
+          eo2[p] = sOld[f & 1][side][1][1][qys[p]];
+        }
+      }
 #pragma unroll
       for (int p = 0; p < ZPT; ++p) {
         const int l = threadIdx.x + p * TPB;
@@ -2029,8 +2083,8 @@ __global__ __launch_bounds__(TPB, 4) void k_fields_z(Group g, std::conditional_t
           };
           if (xdn && (i == 1 || i == nx - 1)) {
             const double c = (i == 1 ? 1.0 : -1.0) * I.kflux[0];
-            term(pE[1][l], at(Ec1, gi), pB[2][l - 1], pB[2][l], c);
-            term(pE[2][l], at(Ec2, gi), pB[1][l - 1], pB[1][l], -c);
+            term(pE[1][l], eo1[p], pB[2][l - 1], pB[2][l], c);
+            term(pE[2][l], eo2[p], pB[1][l - 1], pB[1][l], -c);
           }
         }
         if (xdn) {
@@ -2053,29 +2107,24 @@ __global__ __launch_bounds__(TPB, 4) void k_fields_z(Group g, std::conditional_t
           at(Bn2, gi) = v2;
           stored_nz = stored_nz || (track && v2 != 0.0f);
         }
-        if (ai >= wx0 && ai < wx1 && xdn) {
+        if (wix[p] >= 0) {
+          const int64_t w = wix[p];
           const float ex = 0.5f * (pE[0][l - 1] + pE[0][l]);
           const float ey = 0.5f * (pE[1][l - LY] + pE[1][l]);
           const float ez = 0.5f * (e2pp[p] + pE[2][l]);
           const float m = sqrtf(ex * ex + ey * ey + ez * ez);
           if (!(m <= 3.0e38f)) atomicOr(I.health, HEALTH_NONFINITE);
-          const int64_t wsz = I.wsz;
-          const int aj = (int)(rowo[p] / (unsigned)sy);
-          const int64_t w = (int64_t)(ai - wx0) + (int64_t)I.wnx * (aj + (int64_t)Py * ak);
-          gmem<float>* __restrict__ ring = gp(I.ring);
-          gmem<float>* __restrict__ suffix = gp(I.suffix);
-          ring[(int64_t)slot * wsz + w] = m;
-          gmem<float>* __restrict__ prefix = gp(I.prefix);
-          const float pre = slot == 0 ? m : fmaxf(prefix[w], m);
-          prefix[w] = pre;
-          const float a = slot + 1 < nwin ? fmaxf(suffix[(int64_t)(slot + 1) * wsz + w], pre) : pre;
+          wring[(int64_t)slot * wsz + w] = m;
+          const float pre = slot == 0 ? m : fmaxf(wpre[p], m);
+          wprefix[w] = pre;
+          const float a = slot + 1 < nwin ? fmaxf(wsuf[p], pre) : pre;
           at(gp(uniform(I.A)), gi) = a;
           if (a >= I.acut_min) blk_hot = 1;
           if (slot == nwin - 1) {
             float run = 0.0f;
             for (int q = nwin - 1; q >= 0; --q) {
-              run = fmaxf(run, ring[(int64_t)q * wsz + w]);
-              suffix[(int64_t)q * wsz + w] = run;
+              run = fmaxf(run, wring[(int64_t)q * wsz + w]);
+              wsuffix[(int64_t)q * wsz + w] = run;
             }
           }
         }
