@@ -92,16 +92,21 @@ __host__ __device__ inline float table_lookup(const TabHdr* __restrict__ h, floa
 // Upper bound of table_lookup(h, A') over every A' <= A (the records hold the
 // running maximum of per-interval bounds, slot 9): a draw at or above it cannot
 // fire for any amplitude up to A, so the amplitude itself need not be known.
-__host__ __device__ inline float table_bound(const TabHdr* __restrict__ h, float A) {
-  if (!(A >= h->acut)) return 0.0f;
-  if (A >= h->asat) return 1.0f;
-  const TabSeg* seg = reinterpret_cast<const TabSeg*>(h + 1);
+// The same with the header fields and the segments from a copy (the records
+// stay in the table at h).
+__host__ __device__ inline float table_bound_at(const TabHdr* __restrict__ h, float acut, float asat, int nseg,
+                                                const TabSeg* __restrict__ seg, float A) {
+  if (!(A >= acut)) return 0.0f;
+  if (A >= asat) return 1.0f;
   int k = 0;
-  while (k + 1 < h->nseg && A >= seg[k].hi) ++k;
+  while (k + 1 < nseg && A >= seg[k].hi) ++k;
   const TabSeg s = seg[k];
   int i = (int)((A - s.lo) * s.inv_h);
   i = i < 0 ? 0 : (i >= s.nint ? s.nint - 1 : i);
-  return reinterpret_cast<const float*>(seg + h->nseg)[TAB_REC * (s.base + i) + 9];
+  return reinterpret_cast<const float*>(reinterpret_cast<const TabSeg*>(h + 1) + nseg)[TAB_REC * (s.base + i) + 9];
+}
+__host__ __device__ inline float table_bound(const TabHdr* __restrict__ h, float A) {
+  return table_bound_at(h, h->acut, h->asat, h->nseg, reinterpret_cast<const TabSeg*>(h + 1), A);
 }
 
 // ------------------------------------------------------ particle offsets
@@ -140,6 +145,7 @@ constexpr int PT_PAD = 5;           // window = tile + PT_PAD nodes per present 
 // Ionization: a block of TPB threads takes TPB x ion_nit(ppc) consecutive
 // neutrals (each thread up to ION_NIT of them), i.e. at most TPB cells.
 constexpr int ION_NIT = 8;
+constexpr int ION_SMAT = 2, ION_SSEG = 16;   // rate-table segments staged in LDS per block
 __host__ __device__ constexpr int ion_nit(int64_t ppc) { return ppc < ION_NIT ? (int)ppc : ION_NIT; }
 constexpr int SORT_CHUNK = 1024;    // sorted particles per work item (piece of a tile)
 constexpr int SPARSE_CHUNK = 128;   // pieces this small skip the LDS windows
@@ -237,6 +243,7 @@ struct Inst {
   int* death;                   // ionization step, -1 alive
   const uint32_t* mcell;        // packed cell of each material cell (neutral / ppc)
   const TabHdr* tab[MAXMAT];
+  int nmat;
   float acut[MAXMAT];
   float acut_min;               // smallest cut over the materials
   int* hot;                     // [step & 1]: some node's amplitude reached acut_min

@@ -2244,9 +2244,12 @@ template <int D, int ORDER, class IT>
 __device__ __forceinline__ void ionize_births(const IT& I, const Birth& b, int64_t jn, int step);
 
 template <int D, int ORDER, bool ONE>
-__global__ __launch_bounds__(TPB) void k_ionize(Group g, std::conditional_t<ONE, Inst, NoInst> one) {
+__global__ __launch_bounds__(TPB, 8) void k_ionize(Group g, std::conditional_t<ONE, Inst, NoInst> one) {
   __shared__ unsigned char hot[TPB + 2];
   __shared__ float spb[TPB + 2];        // bound of P over the cell's reachable amplitudes
+  __shared__ TabSeg sseg[ION_SMAT][ION_SSEG];   // rate-table segments (while they fit)
+  __shared__ int snseg[ION_SMAT];
+  __shared__ float sasat[ION_SMAT];
   __shared__ uint32_t scell[TPB + 2];   // packed cell and material of each cell of the block
   __shared__ signed char smat[TPB + 2];
   const Slot sl = ONE ? Slot{0, (int)blockIdx.x, g.blocks} : block_slot(g);
@@ -2266,6 +2269,19 @@ __global__ __launch_bounds__(TPB) void k_ionize(Group g, std::conditional_t<ONE,
   const int64_t m0 = div_ppc(I, j0);
   const int64_t jl = (j0 + span < nneut ? j0 + span : nneut) - 1;
   const int ncell = (int)(div_ppc(I, jl) - m0 + 1);
+  // the rate tables' segments, staged while the cells' amplitudes load
+  for (int e = threadIdx.x; e < ION_SMAT * ION_SSEG; e += TPB) {
+    const int m = e / ION_SSEG, q = e % ION_SSEG;
+    if (m < I.nmat) {
+      const TabHdr* h = I.tab[m];
+      const int ns = h->nseg;
+      if (q == 0) {
+        snseg[m] = ns;
+        sasat[m] = h->asat;
+      }
+      if (q < ns && ns <= ION_SSEG) sseg[m][q] = reinterpret_cast<const TabSeg*>(h + 1)[q];
+    }
+  }
   for (int t = threadIdx.x; t < ncell; t += TPB) {
     int ci, cj, ck;
     const uint32_t pc = I.mcell[m0 + t];
@@ -2293,7 +2309,15 @@ __global__ __launch_bounds__(TPB) void k_ionize(Group g, std::conditional_t<ONE,
     }
     const bool h = alive && mat >= 0 && amax >= I.acut[mat];
     hot[t] = h;
-    spb[t] = h ? table_bound(I.tab[mat], amax * (1.0f + 0x1p-16f)) : 0.0f;
+    spb[t] = h ? amax * (1.0f + 0x1p-16f) : 0.0f;   // the bound's amplitude, bound below
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < ncell; t += TPB) {
+    if (!hot[t]) continue;
+    const int mat = smat[t];
+    const TabHdr* h = I.tab[mat];
+    const bool st = mat < ION_SMAT && snseg[mat] <= ION_SSEG;
+    spb[t] = st ? table_bound_at(h, I.acut[mat], sasat[mat], snseg[mat], sseg[mat], spb[t]) : table_bound(h, spb[t]);
   }
   __syncthreads();
   for (int it = 0; it < nit; ++it) {

@@ -866,6 +866,7 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
     I.tab[m] = (const TabHdr*)devp(c, L.o_tab[m]);
     I.acut[m] = c->tabs[m].acut;
   }
+  I.nmat = K.nmat;
   I.acut_min = 3.0e38f;
   for (int m = 0; m < K.nmat; ++m) I.acut_min = std::min(I.acut_min, I.acut[m]);
   // fixed-point scale of the LDS deposit: 2^JFIX_BITS per 2^ceil(log2 max |kq|)
