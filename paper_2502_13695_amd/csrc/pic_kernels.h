@@ -50,6 +50,9 @@ void launch_push(const Group& g, int D, int order, bool per, hipStream_t s, Stam
 void launch_sort(const Group& gp, const Group& gscan, int D, hipStream_t s, Stamp st = {});
 void launch_fields(const Group& g, int D, int variant, hipStream_t s, Stamp st = {});
 void launch_ionize(const Group& g, int D, int order, hipStream_t s, Stamp st = {});
+// suffix maxima of the amplitude window (a single run, after the field update
+// of a step whose slot is nwin - 1)
+void launch_win_rebuild(const Inst& I, int64_t wsz, hipStream_t s, hipEvent_t stop = nullptr);
 void launch_advance(Inst* insts, int n, hipStream_t s);   // batch: step counters + 1
 int field_tiles(int D, int variant, int Px, int Py, int Pz);   // blocks of the field launch
 // field tile shapes of a run: the tiled shapes, plus the z-marching update in

@@ -1697,7 +1697,8 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g, std::conditional_t<ONE,
       const float a = slot + 1 < nwin ? fmaxf(suffix[(int64_t)(slot + 1) * wsz + w], pre) : pre;
       at(gp(uniform(I.A)), gi) = a;
       if (a >= I.acut_min) blk_hot = 1;
-      if (slot == nwin - 1) {   // block of samples complete: suffix maxima for the next
+      if (!ONE && slot == nwin - 1) {   // block of samples complete: suffix maxima for the next
+        // (a single run rebuilds them in k_win_rebuild, all nodes in parallel)
         float run = 0.0f;
         for (int q = nwin - 1; q >= 0; --q) {
           run = fmaxf(run, ring[(int64_t)q * wsz + w]);
@@ -2120,7 +2121,7 @@ __global__ __launch_bounds__(TPB, 4) void k_fields_z(Group g, std::conditional_t
           const float a = slot + 1 < nwin ? fmaxf(wsuf[p], pre) : pre;
           at(gp(uniform(I.A)), gi) = a;
           if (a >= I.acut_min) blk_hot = 1;
-          if (slot == nwin - 1) {
+          if (!ONE && slot == nwin - 1) {   // (single runs: k_win_rebuild)
             float run = 0.0f;
             for (int q = nwin - 1; q >= 0; --q) {
               run = fmaxf(run, wring[(int64_t)q * wsz + w]);
@@ -2179,6 +2180,36 @@ __global__ __launch_bounds__(TPB, 4) void k_fields_z(Group g, std::conditional_t
       double* ef = I.eflux + (blockIdx.x & 7) * 32;   // this XCD's line
       if (fin != 0.0) atomicAdd(ef, fin);
       if (fout != 0.0) atomicAdd(ef + 1, fout);
+    }
+  }
+}
+
+// Suffix maxima of the amplitude window, rebuilt after the field update of
+// the step that completes a block of nwin samples (slot nwin - 1): for every
+// window position w, suffix[q] = max of ring[q .. nwin - 1].  One thread per
+// position, eight samples loaded at a time; a single run launches it only on
+// those steps (a batch rebuilds inside the field update).
+__global__ __launch_bounds__(TPB) void k_win_rebuild(const Inst I) {
+  const int nwin = I.nwin;
+  const int64_t wsz = I.wsz;
+  const gmem<float>* __restrict__ ring = gp(I.ring);
+  gmem<float>* __restrict__ suffix = gp(I.suffix);
+  for (int64_t w = (int64_t)blockIdx.x * TPB + threadIdx.x; w < wsz; w += (int64_t)gridDim.x * TPB) {
+    float run = 0.0f;
+    int q = nwin - 1;
+    for (; q >= 7; q -= 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = ring[(int64_t)(q - u) * wsz + w];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        run = fmaxf(run, v[u]);
+        suffix[(int64_t)(q - u) * wsz + w] = run;
+      }
+    }
+    for (; q >= 0; --q) {
+      run = fmaxf(run, ring[(int64_t)q * wsz + w]);
+      suffix[(int64_t)q * wsz + w] = run;
     }
   }
 }
@@ -2885,6 +2916,12 @@ int field_tiles(int D, int variant, int Px, int Py, int Pz) {
 }
 int field_tile_variants(int D, bool periodic_yz) { return D == 3 && periodic_yz ? kTileVariants : kTileVariants - 1; }
 int field_tile_x(int D, int variant) { return tile_shape(D, variant).x; }
+void launch_win_rebuild(const Inst& I, int64_t wsz, hipStream_t s, hipEvent_t stop) {
+  if (wsz <= 0) return;
+  const int64_t nb = std::min<int64_t>((wsz + TPB - 1) / TPB, 4096);
+  hipEvent_t none = nullptr;
+  GO(k_win_rebuild, (unsigned)nb, TPB, s, none, stop, I);
+}
 void launch_ionize(const Group& g, int D, int order, hipStream_t s, Stamp st) {
   const bool one = g.n == 1 && g.host && g.step >= 0;
   if (order == 1) {

@@ -459,6 +459,13 @@ void finish_tuning(pic_ctx* c) {
   c->d_off_fields = c->d_off + 8 + 2 * c->tile;
 }
 
+// The step's field update completes a block of amplitude-window samples
+// (slot nwin - 1): the suffix maxima are rebuilt after it.
+static bool rebuild_due(const pic_ctx* c) {
+  const int nwin = c->canon.nwin;
+  return nwin > 0 && c->L.wsz > 0 && c->step % nwin == nwin - 1;
+}
+
 void enqueue_step(pic_ctx* c) {
   const int D = c->canon.D, order = c->cfg.shape_order;
   hipStream_t s = c->stream;
@@ -477,12 +484,16 @@ void enqueue_step(pic_ctx* c) {
     gv.xext = c->d_ctr->xext;
     gv.host = &c->h;
     launch_fields(gv, D, v, s, Stamp{c->tune_ev[v][r][0], c->tune_ev[v][r][1]});
+    if (rebuild_due(c)) launch_win_rebuild(c->h, c->L.wsz, s);
     if (--c->tune_left == 0) finish_tuning(c);
   } else {
     timed(c, 1, [&](Stamp st) {
       Group g = single(c, 1, c->nb_cell);
       g.part = c->far_skip;
-      launch_fields(g, D, c->tile, s, st);
+      // the window's suffix rebuild, when due, belongs to the field phase
+      const bool rb = rebuild_due(c);
+      launch_fields(g, D, c->tile, s, rb ? Stamp{st.start, nullptr} : st);
+      if (rb) launch_win_rebuild(c->h, c->L.wsz, s, st.stop);
     });
   }
   if (c->imax_every > 0 && (c->step + 1) % c->imax_every == 0) launch_imax(imax_args(c), c->d_imax, s);
