@@ -12,6 +12,13 @@ it changes; the inherited parts follow the textbook method named alongside:
   as E [V/m] and b = c B [V/m].  One step: b^{n+1/2} = b^n - (1/2) C curl E^n,
   E^{n+1} = E^n + (1/eps_r)(C curl b^{n+1/2} - dt J/eps0),
   b^{n+1} = b^{n+1/2} - (1/2) C curl E^{n+1}, where C_d = c dt / dx_d.
+* Dispersive extension of that linear response (a reading; the paper keeps it
+  static): a single-pole Lorentz medium, eps(w) = eps_inf + deps w0^2 /
+  (w0^2 - w^2 - i g w), with the polarisation P and its current J_p = dP/dt as
+  the auxiliary differential equation P'' + g P' + w0^2 P = eps0 deps w0^2 E,
+  centred at integer steps: J_p^{n+1/2} from J_p^{n-1/2}, E^n and P^n, then
+  P^{n+1} = P^n + dt J_p^{n+1/2}, and J_p^{n+1/2} enters the E update beside
+  the free current with 1/eps_inf in place of 1/eps_r.
 * "Simple outflow" boundaries (Sec. 3.1): first-order Mur on each outflow
   face for the tangential E; the laser enters as the incident field of the
   x_min face condition (Sec. 3, Fig. 1: driven from the minimum boundary).
@@ -52,7 +59,10 @@ it, the number and energy density grids against particle totals and uniform
 lattice loads, the field energy against uniform fields in a dielectric, the
 Poynting budget against a pulse's analytic fluence and its closure through
 transverse faces, and the gap energy against events x weight x gap
-(tests/test_oracle_budget.py).
+(tests/test_oracle_budget.py); for the Lorentz medium, the discrete dispersion
+relation of the coupled scheme, Fresnel reflection against the continuum
+eps(w) over the pulse's spectrum, and the Gauss law with the bound charge
+(tests/test_oracle_lorentz.py).
 """
 
 import math
@@ -99,6 +109,16 @@ class Sim:
         ie_node = np.ones(self.S[0])
         ie_node[G:G + nx + 1] = P.ie_of(P.mat_node)
         self.ieE = [ie_half.reshape(-1, 1, 1), ie_node.reshape(-1, 1, 1), ie_node.reshape(-1, 1, 1)]
+        # Lorentz oscillators (a, c, c deps) at each E component's own location,
+        # their polarisation Q = P/eps0 and current K = dt J_p/eps0 (zero where
+        # the medium is static or vacuum: the coefficients vanish there)
+        lor_half = np.zeros((self.S[0], 3))
+        lor_half[G:G + nx] = P.lor_of(P.mat_cell)
+        lor_node = np.zeros((self.S[0], 3))
+        lor_node[G:G + nx + 1] = P.lor_of(P.mat_node)
+        self.lorE = [[t[:, q].reshape(-1, 1, 1) for q in range(3)] for t in (lor_half, lor_node, lor_node)]
+        self.Q = [z(), z(), z()]
+        self.K = [z(), z(), z()]
         self.regE = [self._region(self.stE[c], True) for c in range(3)]
         self.regB = [self._region(self.stB[c], False) for c in range(3)]
         self.domain_nodes = self._domain_node_mask()
@@ -313,7 +333,12 @@ class Sim:
             r = self.regE[c]
             cc = curl[c] if np.ndim(curl[c]) else np.zeros(self.S)
             ie = np.broadcast_to(self.ieE[c], self.S)
-            self.E[c][r] += ie[r] * (cc[r] - self.J[c][r])
+            # polarisation current of the step from E^n and Q^n, then Q^{n+1}
+            la, lc, lcd = (np.broadcast_to(t, self.S)[r] for t in self.lorE[c])
+            k_new = la * self.K[c][r] + lcd * self.E[c][r] - lc * self.Q[c][r]
+            self.K[c][r] = k_new
+            self.Q[c][r] += k_new
+            self.E[c][r] += ie[r] * (cc[r] - self.J[c][r] - k_new)
         self._mur(old, n)
 
     def _face_points(self, c, d):
@@ -703,11 +728,12 @@ class Sim:
         return tuple(sl)
 
     def gauss_residual(self):
-        """div(E/ie) - rho/eps0 at interior nodes [V/m^2] (Sec. 2.3 medium)."""
+        """div(E/ie + Q) - rho/eps0 at interior nodes [V/m^2] (Sec. 2.3 medium;
+        Q = P/eps0 of a Lorentz medium, zero elsewhere)."""
         P = self.P
         div = np.zeros(self.S)
         for c in range(self.D):
-            D_ = self.E[c] / np.broadcast_to(self.ieE[c], self.S)
+            D_ = self.E[c] / np.broadcast_to(self.ieE[c], self.S) + self.Q[c]
             self._fill_periodic(D_)
             div += (D_ - np.roll(D_, 1, axis=c)) / P.dx[c]
         res = div - self.charge_density()

@@ -7,7 +7,10 @@ Sources in the paper:
 * materials: band gap, index, density, m_h*, m_e* (Sec. 3.2, Table 1); reduced
   mass m* = 1/(1/m_e* + 1/m_h*) (Sec. 3.2); electrons carry m_e* (Sec. 3.2)
 * optical region defined by the same shape that places the neutral species
-  (Sec. 2.3); permittivity eps_r = n^2, linear and static (Sec. 2.3)
+  (Sec. 2.3); permittivity eps_r = n^2, linear and static (Sec. 2.3), or, as
+  the dispersive extension of that linear response, a single-pole Lorentz
+  medium whose index at the laser wavelength is n (a reading: the paper keeps
+  the static limit; the pole's parameters come with the material)
 * pulse: sine-squared envelope with a stated intensity FWHM, spot radius w0,
   fluence F = 2 E_las / (pi w0^2) (Sec. 3); linear polarisation with
   I = c eps0 E0^2 / 2 (the convention the ponderomotive energies of Sec. 5 fix)
@@ -42,6 +45,21 @@ def f32(v):
     return float(np.float32(v))
 
 
+def lorentz_stable(ie, c, cd, s2max):
+    """Von Neumann stability of the Yee update coupled to the explicit
+    oscillator (lossless medium).  One mode gives, with w = z - 2 + 1/z,
+        f(w) = w^2 / ie + (c / ie + 4 s2 + c deps) w + 4 s2 c = 0
+    (the characteristic polynomial divided by z^2), whose roots are real and
+    negative; |z| = 1 needs both in [-4, 0]: f(-4) >= 0 with the vertex above
+    -4.  Both conditions are monotone in s2, so the largest s2 = sum_d C_d^2
+    decides; c < 4 is the oscillator's own leapfrog limit."""
+    if not (0.0 <= c < 4.0):
+        return False
+    f4 = (16.0 - 4.0 * c) / ie - 4.0 * cd - s2max * (16.0 - 4.0 * c)
+    vertex_ok = c / ie + 4.0 * s2max + cd <= 8.0 / ie
+    return f4 > 0.0 and vertex_ok
+
+
 class Material:
     def __init__(self, m):
         self.gap_eV = float(m["gap_eV"])
@@ -58,8 +76,14 @@ class Material:
         pm = float(m.get("pos_mass_kg", 0.0))
         self.pos_mass_kg = pm if pm > 0 else self.mol_mass_kg
         self.e_mass_kg = self.me_star * ME
-        # canonical inverse permittivity 1/eps_r = 1/n^2 as an FP32 number
-        self.ie = f32(1.0 / (self.n_index * self.n_index))
+        # single-pole Lorentz response (resonance wavelength > 0), else static
+        self.lor_lambda = float(m.get("lorentz_lambda_m", 0.0))
+        self.lor_gamma = float(m.get("lorentz_gamma_s", 0.0))
+        self.eps_inf = float(m.get("eps_inf", 1.0)) if self.lor_lambda > 0 else self.n_index * self.n_index
+        # canonical inverse permittivity 1/eps_r = 1/n^2 (static) or 1/eps_inf
+        # (Lorentz: the instantaneous part) as an FP32 number
+        self.ie = f32(1.0 / self.eps_inf)
+        self.lor = (0.0, 0.0, 0.0)   # (a, c, c deps) of the oscillator update; 0: none
 
 
 class Laser:
@@ -145,6 +169,9 @@ class Problem:
         self.nwin = int(math.ceil((self.laser.lam / C) / self.dt))
 
         self.mats = [Material(m) for m in cfg["materials"]]
+        for mt in self.mats:
+            if mt.lor_lambda > 0:
+                mt.lor = self._lorentz(mt)
         self.layers = [(int(L[0]), float(L[1]), float(L[2])) for L in cfg["layers"]]
         self.vcell = 1.0
         for d in range(self.D):
@@ -168,6 +195,36 @@ class Problem:
                     weight=mt.n0 * self.vcell / self.ppc,
                     mat=mt))
 
+    def _lorentz(self, mt):
+        """Coefficients of the polarisation oscillator of one Lorentz material.
+
+        Medium: eps(w) = eps_inf + deps w0^2 / (w0^2 - w^2 - i g w).  With
+        Q = P / eps0 and K = dt J_p / eps0 (J_p = dP/dt) the oscillator
+        P'' + g P' + w0^2 P = eps0 deps w0^2 E, centred at step n, reads
+            K^{n+1/2} = a K^{n-1/2} + c deps E^n - c Q^n,   Q^{n+1} = Q^n + K^{n+1/2}
+        with a = (1 - g dt/2)/(1 + g dt/2), c = (w0 dt)^2 / (1 + g dt/2).  deps is
+        fixed by Re eps(w_laser) = n^2 (n is the index at the laser wavelength);
+        the static permittivity is then eps_inf + deps.  a, c and c deps are
+        canonical FP32 numbers."""
+        w0 = 2.0 * math.pi * C / mt.lor_lambda
+        w = self.laser.omega
+        g = mt.lor_gamma
+        if not (w0 > w):
+            raise ValueError("Lorentz resonance must lie above the laser frequency")
+        re_shape = w0 * w0 * (w0 * w0 - w * w) / ((w0 * w0 - w * w) ** 2 + (g * w) ** 2)
+        mt.deps = (mt.n_index * mt.n_index - mt.eps_inf) / re_shape
+        if mt.deps < 0:
+            raise ValueError("eps_inf above n^2")
+        dt = self.dt
+        den = 1.0 + 0.5 * g * dt
+        a = (1.0 - 0.5 * g * dt) / den
+        c = (w0 * dt) ** 2 / den
+        lor = (f32(a), f32(c), f32(c * mt.deps))
+        s2max = sum(self.Cd[d] ** 2 for d in range(self.D))
+        if not lorentz_stable(mt.ie, lor[1], lor[2], s2max):
+            raise ValueError("Lorentz medium unstable at this time step")
+        return lor
+
     def material_at(self, x):
         for (m, lo, hi) in self.layers:
             if lo <= x < hi:
@@ -176,6 +233,10 @@ class Problem:
 
     def ie_of(self, mat_idx):
         return np.array([1.0 if m < 0 else self.mats[m].ie for m in mat_idx])
+
+    def lor_of(self, mat_idx):
+        """(a, c, c deps) per position; zeros where no oscillator."""
+        return np.array([(0.0, 0.0, 0.0) if m < 0 else self.mats[m].lor for m in mat_idx]).reshape(-1, 3)
 
     def transverse_profile(self, y, z):
         """Gaussian transverse field profile exp(-r^2/w0^2) at the injection plane."""

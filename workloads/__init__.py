@@ -8,7 +8,8 @@ conversion of the method happens here.
 Configuration dictionary (both sides read the same keys):
   ndim, n[ndim] (cells), dx[ndim] (m), cfl, nsteps, transverse_bc
   ("outflow" | "periodic"), materials (list of dicts: gap_eV, n_index,
-  density_gcc, molar_mass_gmol, me_star, mh_star, pos_mass_kg), layers (list
+  density_gcc, molar_mass_gmol, me_star, mh_star, pos_mass_kg, and for a
+  single-pole Lorentz response lorentz_lambda_m, eps_inf, lorentz_gamma_s), layers (list
   of (material, lo_m, hi_m) half-open along x), ppc, T_K, shape_order,
   keldysh_terms, seed, laser (lambda_m, fwhm_s, peak_Wcm2 | fluence_Jcm2,
   waist_m, t_peak_s, cep_rad, envelope "gauss" | "sin2", pol_axis),
@@ -55,6 +56,29 @@ def table1_hfo2():
                 me_star=1.09, mh_star=1.12, pos_mass_kg=0.0)
 
 
+def lorentz(mat, lambda0_m, eps_inf=1.0, gamma_s=0.0):
+    """The material with a single-pole Lorentz response: resonance at the
+    wavelength lambda0_m, instantaneous permittivity eps_inf, damping rate
+    gamma_s [1/s].  n_index stays the index at the laser wavelength."""
+    return dict(mat, lorentz_lambda_m=lambda0_m, eps_inf=eps_inf, lorentz_gamma_s=gamma_s)
+
+
+# Dispersive variants: one ultraviolet pole per material, the deeper
+# ultraviolet response folded into eps_inf (fused silica: the pole near
+# 0.116 um of its Sellmeier fit, eps_inf = 1 + the 0.068 um term's strength;
+# HfO2: a pole at 0.15 um, eps_inf = 2)
+SILICA_UV = (0.116e-6, 1.7)
+HFO2_UV = (0.15e-6, 2.0)
+
+
+def silica_dispersive():
+    return lorentz(silica_like(), SILICA_UV[0], eps_inf=SILICA_UV[1])
+
+
+def high_index_dispersive():
+    return lorentz(high_index(), HFO2_UV[0], eps_inf=HFO2_UV[1])
+
+
 def layer_stack(mats, n_indices, x0, lam=LAMBDA, first_half_wave=False):
     """Quarter-wave stack (Fig. 1): each layer lam/(4n); optionally the first
     (protective) layer lam/(2n).  Returns [(mat, lo, hi), ...] starting at x0."""
@@ -72,42 +96,51 @@ def _laser(cyc, peak=0.0, fluence=0.0, waist=0.0, env="gauss"):
                 waist_m=waist, t_peak_s=0.0, cep_rad=0.0, envelope=env, pol_axis=1)
 
 
-def config_1d(hi=False, nsteps=2000, n=1024, ppc=100, peak=None):
+def config_1d(hi=False, nsteps=2000, n=1024, ppc=100, peak=None, dispersive=False):
     """1D3V slab: 1024 cells at lambda/40, n = 1.45 slab over cells 400-600,
     2-cycle Gaussian pulse at 1e13 W/cm^2 (1e14 for the high-intensity variant,
-    which ionizes enough to exercise the Monte-Carlo step), seed 0."""
+    which ionizes enough to exercise the Monte-Carlo step), seed 0.
+    dispersive: the slab responds as a Lorentz medium (index 1.45 at 800 nm)."""
     dx = LAMBDA / 40
+    mat = silica_dispersive() if dispersive else silica_like()
     pk = peak if peak is not None else (1e14 if hi else 1e13)
     lo = int(round(n * 400 / 1024))
     hi_c = int(round(n * 600 / 1024))
     return dict(ndim=1, n=[n], dx=[dx], cfl=0.95, nsteps=nsteps, transverse_bc="outflow",
-                materials=[silica_like()], layers=[(0, lo * dx, hi_c * dx)], ppc=ppc,
+                materials=[mat], layers=[(0, lo * dx, hi_c * dx)], ppc=ppc,
                 T_K=300.0, shape_order=2, keldysh_terms=500, seed=0,
                 laser=_laser(2, peak=pk), particle_capacity=0, preionize_eV=0.0)
 
 
 def config_2d(nx=2048, ny=512, nsteps=4000, ppc=16, peak=5e13, seed=1, slab_cells=80,
-              front=None, waist=3e-6, bc="outflow"):
+              front=None, waist=3e-6, bc="outflow", dispersive=False):
     """2D3V slab: 2048 x 512 cells at lambda/32, 2 um silica-like slab filling y,
-    16 neutrals per cell, 3-cycle pulse, waist 3 um, 5e13 W/cm^2, seed 1."""
+    16 neutrals per cell, 3-cycle pulse, waist 3 um, 5e13 W/cm^2, seed 1.
+    dispersive: the slab responds as a Lorentz medium."""
     dx = LAMBDA / 32
+    mat = silica_dispersive() if dispersive else silica_like()
     f = nx // 4 if front is None else front
     return dict(ndim=2, n=[nx, ny], dx=[dx, dx], cfl=0.95, nsteps=nsteps, transverse_bc=bc,
-                materials=[silica_like()], layers=[(0, f * dx, (f + slab_cells) * dx)], ppc=ppc,
+                materials=[mat], layers=[(0, f * dx, (f + slab_cells) * dx)], ppc=ppc,
                 T_K=300.0, shape_order=2, keldysh_terms=500, seed=seed,
                 laser=_laser(3, peak=peak, waist=waist), particle_capacity=0, preionize_eV=0.0)
 
 
-def config_3d(nx=256, ny=128, nz=128, nsteps=2000, ppc=8, fluence=1.0, seed=2, front=64):
+def config_3d(nx=256, ny=128, nz=128, nsteps=2000, ppc=8, fluence=1.0, seed=2, front=64,
+              dispersive=False):
     """3D3V one-GPU share of a multi-layer mirror: 256 x 128 x 128 cells at
     lambda/24, 8 alternating quarter-wave layers (n = 1.45, 9 eV / n = 2.1,
     4 eV), 8 neutrals per cell, 2-cycle plane-wave pulse of 1 J/cm^2, periodic
-    transverse boundaries (the neighbours of this share), seed 2."""
+    transverse boundaries (the neighbours of this share), seed 2.
+    dispersive: both layer materials respond as Lorentz media."""
     dx = LAMBDA / 24
     mats = [0, 1] * 4
+    m0, m1 = silica_like(), high_index()
+    if dispersive:
+        m0, m1 = silica_dispersive(), high_index_dispersive()
     layers = layer_stack(mats, [1.45, 2.1] * 4, front * dx)
     return dict(ndim=3, n=[nx, ny, nz], dx=[dx, dx, dx], cfl=0.95, nsteps=nsteps,
-                transverse_bc="periodic", materials=[silica_like(), high_index()],
+                transverse_bc="periodic", materials=[m0, m1],
                 layers=layers, ppc=ppc, T_K=300.0, shape_order=2, keldysh_terms=500,
                 seed=seed, laser=_laser(2, fluence=fluence), particle_capacity=0,
                 preionize_eV=0.0)
