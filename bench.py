@@ -356,38 +356,43 @@ WORKLOADS = {
 }
 
 
-def workload_config(name):
-    """(benchmark configuration, oracle configuration for the CPU baseline, its description)."""
+DISPERSIVE_NOTE = "; layers as single-pole Lorentz media (index at 800 nm unchanged)"
+
+
+def workload_config(name, dispersive=False):
+    """(benchmark configuration, oracle configuration for the CPU baseline, its description).
+    dispersive: the layers respond as single-pole Lorentz media."""
     import workloads as W
+    d = dict(dispersive=dispersive)
     if name == "mirror3d":
-        cfg = W.config_3d()
+        cfg = W.config_3d(**d)
         # periodic transverse plane-wave run: every transverse column evolves
         # alike, so a 16 x 16 share carries the same per-particle work
-        return cfg, W.config_3d(ny=16, nz=16), "the 256x16x16 transverse share of the same run"
+        return cfg, W.config_3d(ny=16, nz=16, **d), "the 256x16x16 transverse share of the same run"
     if name == "slab2d":
-        cfg = W.config_2d()
+        cfg = W.config_2d(**d)
         return cfg, cfg, "the same run"
     if name == "slab1d":
-        cfg = W.config_1d()
+        cfg = W.config_1d(**d)
         return cfg, cfg, "the same run"
     if name == "stress2d":
-        cfg = W.config_stress(W.config_2d(), eV=2.0)
-        return cfg, W.config_stress(W.config_2d(ny=32), eV=2.0), "a 2048x32 outflow strip of the same slab"
+        cfg = W.config_stress(W.config_2d(**d), eV=2.0)
+        return cfg, W.config_stress(W.config_2d(ny=32, **d), eV=2.0), "a 2048x32 outflow strip of the same slab"
     if name == "stress3d":
-        cfg = W.config_stress(W.config_3d(), eV=2.0)
-        return cfg, W.config_stress(W.config_3d(ny=16, nz=16), eV=2.0), "the 256x16x16 transverse share"
+        cfg = W.config_stress(W.config_3d(**d), eV=2.0)
+        return cfg, W.config_stress(W.config_3d(ny=16, nz=16, **d), eV=2.0), "the 256x16x16 transverse share"
     if name == "stress2d-cap":
         # 488 neutrals per slab cell, all pre-ionized: 2 x 40960 x 488 = 4.0e7 charged
-        return W.config_stress(W.config_2d(ppc=488), eV=2.0), None, ""
+        return W.config_stress(W.config_2d(ppc=488, **d), eV=2.0), None, ""
     if name == "stress3d-cap":
         # 272 neutrals per material cell, all pre-ionized: 2 x 458752 x 272 = 2.5e8 charged
-        return W.config_stress(W.config_3d(ppc=272), eV=2.0), None, ""
+        return W.config_stress(W.config_3d(ppc=272, **d), eV=2.0), None, ""
     raise SystemExit(f"unknown workload {name}")
 
 
 def bench_window(args):
     from paper_2502_13695_amd import pic
-    cfg, ocfg, share_note = workload_config(args.workload)
+    cfg, ocfg, share_note = workload_config(args.workload, args.dispersive)
     params = pic.canonical(cfg)
     if args.start is not None:
         start = args.start
@@ -447,7 +452,8 @@ def bench_window(args):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload], "cells": list(cfg["n"]), "ppc": cfg["ppc"],
+        "config": {"workload": WORKLOADS[args.workload] + (DISPERSIVE_NOTE if args.dispersive else ""),
+                   "cells": list(cfg["n"]), "ppc": cfg["ppc"],
                    "seed": cfg["seed"], "start_step": start,
                    "sort_check_every": args.resort if args.resort is not None else 8,
                    "window": f"steps {start}..{start + steps - 1}" +
@@ -690,6 +696,8 @@ def main():
                     help="serve: every request arrives at t = 0 (capacity, not latency, is measured)")
     ap.add_argument("--field-tile", type=int, default=None,
                     help="fixed field tile shape (default: timed in-run over the first steps)")
+    ap.add_argument("--dispersive", action="store_true",
+                    help="the workload's layers respond as single-pole Lorentz media")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--calib-copy", action="store_true",

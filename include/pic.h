@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define PIC_ABI_VERSION 1u
+#define PIC_ABI_VERSION 2u
 
 typedef enum {
   PIC_OK = 0,
@@ -57,9 +57,25 @@ typedef struct pic_batch pic_batch;
  * molecular density n0 = rho N_A / M), effective hole and electron masses in
  * units of m_e (reduced mass m* = 1/(1/m_e* + 1/m_h*), Sec. 3.2).  Ionized
  * electrons carry m_e* (Sec. 3.2).  pos_mass_kg: mass of the positive carrier
- * born with each electron; 0 selects the molecule mass M / N_A. */
+ * born with each electron; 0 selects the molecule mass M / N_A.
+ *
+ * Dispersive response (the linear response of Sec. 2.3 made frequency
+ * dependent): lorentz_lambda_m > 0 selects a single-pole Lorentz medium,
+ *   eps(w) = eps_inf + deps w0^2 / (w0^2 - w^2 - i g w),
+ * w0 = 2 pi c / lorentz_lambda_m, g = lorentz_gamma_s [1/s], with deps chosen
+ * so that Re eps at the laser frequency is n_index^2 (n stays the index at the
+ * laser wavelength; the resonance must lie above the laser frequency and
+ * eps_inf <= n^2).  Per E position the polarisation Q = P/eps0 and its current
+ * K = dt J_p / eps0 advance as K^{n+1/2} = a K^{n-1/2} + c deps E^n - c Q^n,
+ * Q^{n+1} = Q^n + K^{n+1/2} (a = (1 - g dt/2)/(1 + g dt/2), c = (w0 dt)^2 /
+ * (1 + g dt/2)), and K enters the E update beside the free current with
+ * 1/eps_inf.  pic_init returns PIC_E_INVAL when the coupled update is unstable
+ * at the time step (lossless von Neumann bound: c < 4 and sum_d C_d^2 <=
+ * eps_inf - c deps / (4 - c), with the vertex condition of that bound).
+ * lorentz_lambda_m = 0: static eps_r = n^2 (eps_inf and lorentz_gamma_s unused). */
 typedef struct {
   double gap_eV, n_index, density_gcc, molar_mass_gmol, me_star, mh_star, pos_mass_kg;
+  double lorentz_lambda_m, eps_inf, lorentz_gamma_s;
 } pic_material;
 
 /* Optical region (Sec. 2.3): material `material` fills lo_m <= x < hi_m across
@@ -125,7 +141,9 @@ typedef struct {
 /* Canonical discrete problem derived from a configuration (host-only query).
  * dt is the largest value with c dt / dx_0 an FP32 number not above the
  * requested fraction of the CFL limit (Sec. 3.1); Cd[d] = c dt / dx_d and
- * kmur[d] = (Cd - 1)/(Cd + 1) are FP32 numbers; ie[m] = 1/n_m^2 as FP32;
+ * kmur[d] = (Cd - 1)/(Cd + 1) are FP32 numbers; ie[m] = 1/n_m^2 as FP32
+ * (a Lorentz material: 1/eps_inf); lor[m] = (a, c, c deps) of its oscillator
+ * as FP32 numbers (zeros for a static material);
  * nwin = ceil(lambda / (c dt)) samples make one laser cycle (Sec. 2.1). */
 typedef struct {
   double dt;
@@ -139,6 +157,7 @@ typedef struct {
   double amp_sat[8];           /* per material: amplitudes above ionize with P = 1 */
   int64_t n_neutral;           /* neutral macroparticles loaded */
   int64_t capacity;            /* charged slots */
+  double lor[8][3];            /* per material: Lorentz oscillator coefficients */
 } pic_params;
 
 /* Diagnostic kinds for pic_diag.  Grids are FP64 unless stated, on the
@@ -178,13 +197,18 @@ enum {
                              since pic_set_imax (zero when never enabled) */
   PIC_DIAG_TRACKS = 12,   /* pic_track records taken since pic_set_tracks, sorted
                              by (id, kind, step) */
-  PIC_DIAG_HEALTH = 13    /* double[4]: the device health word (bit 0 charged-slot
+  PIC_DIAG_HEALTH = 13,   /* double[4]: the device health word (bit 0 charged-slot
                              capacity exceeded by births, bit 1 a non-finite E value
                              stored by the field update, a non-finite particle
                              momentum or a non-finite window amplitude), the latched
                              pic_status, the device step index, the charged slots
                              in use.  Valid in every state, including after a
                              latched error. */
+  PIC_DIAG_POL = 14       /* double: Qx, Qy, Qz (P / eps0 [V/m], at step n), then
+                             Kx, Ky, Kz (dt J_p / eps0 [V/m], at step n - 1/2) of the
+                             Lorentz media, each on its E component's positions
+                             (shapes of the E part of PIC_DIAG_FIELDS); zero
+                             outside Lorentz media and everywhere in runs without one */
 };
 
 /* PIC_DIAG_SCALARS layout (all double). */
@@ -193,7 +217,8 @@ enum {
   PIC_SC_EVENTS = 5, PIC_SC_U_FIELD = 6, PIC_SC_KE_E = 7, PIC_SC_KE_POS = 8,
   PIC_SC_E_GAP = 9, PIC_SC_E_ABS = 10, PIC_SC_GAUSS_MAX = 11, PIC_SC_RHO_MAX = 12,
   PIC_SC_HEALTH = 13, PIC_SC_SLOTS = 14, PIC_SC_TRACKS_DROPPED = 15,
-  PIC_SC_GAUSS_L2 = 16,   /* root mean square of the Gauss-law residual over the interior nodes [V/m^2] */
+  PIC_SC_GAUSS_L2 = 16,   /* root mean square of the Gauss-law residual over the interior nodes [V/m^2];
+                             the residual is div(E/ie + Q) - rho/eps0, Q = P/eps0 of Lorentz media */
   /* Field-side energy budget (a reading of Sec. 4.2's absorbed energy): field
    * energy carried through the flux surface since the start [J], entering and
    * leaving.  The surface bounds the box whose faces are the node planes one
@@ -202,7 +227,9 @@ enum {
    * and b^{n+1/2} averaged to the plane, integrated with the trapezoid rule
    * (absent axes count 1 m).  Each staggered product E_a b_b is one term; a
    * term's energy goes to E_IN when it points into the box, else to E_OUT.
-   * E_IN - E_OUT - U_FIELD is the energy the charges took from the field. */
+   * E_IN - E_OUT - U_FIELD is the energy the charges took from the field (in
+   * Lorentz media U_FIELD counts eps0/2 (eps_inf E^2 + b^2) only, so the
+   * difference also holds the energy the oscillators store). */
   PIC_SC_E_IN = 17, PIC_SC_E_OUT = 18,
   PIC_SC_COUNT = 19
 };
@@ -219,7 +246,8 @@ typedef struct {
 
 /* State written by pic_set_state: E and b (FP32, layout of PIC_DIAG_FIELDS),
  * the charged particles, and the step index.  Neutrals and the amplitude
- * window keep their values unless reset_window != 0 (window cleared). */
+ * window keep their values unless reset_window != 0 (window cleared).  The
+ * polarisation of Lorentz media restarts from rest (Q = K = 0). */
 typedef struct {
   int64_t step;
   const float* E[3];

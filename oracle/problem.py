@@ -211,16 +211,17 @@ class Problem:
         g = mt.lor_gamma
         if not (w0 > w):
             raise ValueError("Lorentz resonance must lie above the laser frequency")
-        re_shape = w0 * w0 * (w0 * w0 - w * w) / ((w0 * w0 - w * w) ** 2 + (g * w) ** 2)
+        t = w0 * w0 - w * w
+        re_shape = w0 * w0 * t / (t * t + (g * w) * (g * w))
         mt.deps = (mt.n_index * mt.n_index - mt.eps_inf) / re_shape
         if mt.deps < 0:
             raise ValueError("eps_inf above n^2")
         dt = self.dt
         den = 1.0 + 0.5 * g * dt
         a = (1.0 - 0.5 * g * dt) / den
-        c = (w0 * dt) ** 2 / den
+        c = (w0 * dt) * (w0 * dt) / den
         lor = (f32(a), f32(c), f32(c * mt.deps))
-        s2max = sum(self.Cd[d] ** 2 for d in range(self.D))
+        s2max = sum(self.Cd[d] * self.Cd[d] for d in range(self.D))
         if not lorentz_stable(mt.ie, lor[1], lor[2], s2max):
             raise ValueError("Lorentz medium unstable at this time step")
         return lor

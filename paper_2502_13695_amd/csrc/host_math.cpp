@@ -223,7 +223,41 @@ pic_status canonicalize(const pic_config* cfg, Canon* c) {
     mc.mol_kg = M.molar_mass_gmol * kAMU;
     mc.e_kg = M.me_star * kME;
     mc.p_kg = M.pos_mass_kg > 0 ? M.pos_mass_kg : mc.mol_kg;
-    mc.ie = (float)(1.0 / (M.n_index * M.n_index));
+    mc.lam0 = 0.0;
+    mc.gamma = 0.0;
+    mc.eps_inf = M.n_index * M.n_index;
+    mc.deps = 0.0;
+    mc.lor[0] = mc.lor[1] = mc.lor[2] = 0.0f;
+    if (M.lorentz_lambda_m < 0) return PIC_E_INVAL;
+    if (M.lorentz_lambda_m > 0) {
+      // single pole: Re eps(omega_laser) = n^2 fixes deps; the oscillator is
+      // centred at integer steps (a, c from the damping and the pole)
+      if (!(M.eps_inf > 0) || !(M.lorentz_gamma_s >= 0)) return PIC_E_INVAL;
+      const double w0 = 2.0 * kPI * kC / M.lorentz_lambda_m;
+      const double w = c->omega;
+      if (!(w0 > w)) return PIC_E_INVAL;
+      const double g = M.lorentz_gamma_s;
+      const double t = w0 * w0 - w * w;
+      const double re_shape = w0 * w0 * t / (t * t + (g * w) * (g * w));
+      const double deps = (M.n_index * M.n_index - M.eps_inf) / re_shape;
+      if (deps < 0) return PIC_E_INVAL;
+      const double den = 1.0 + 0.5 * g * c->dt;
+      const double ca = (1.0 - 0.5 * g * c->dt) / den;
+      const double cc = (w0 * c->dt) * (w0 * c->dt) / den;
+      mc.lam0 = M.lorentz_lambda_m;
+      mc.gamma = g;
+      mc.eps_inf = M.eps_inf;
+      mc.deps = deps;
+      mc.lor[0] = (float)ca;
+      mc.lor[1] = (float)cc;
+      mc.lor[2] = (float)(cc * deps);
+    }
+    mc.ie = (float)(1.0 / mc.eps_inf);
+    if (M.lorentz_lambda_m > 0) {
+      double s2max = 0.0;
+      for (int d = 0; d < c->D; ++d) s2max += (double)c->C[d] * (double)c->C[d];
+      if (!lorentz_stable(mc.ie, mc.lor[1], mc.lor[2], s2max)) return PIC_E_INVAL;
+    }
   }
   const int64_t nx = c->n[0];
   c->mat_cell.assign(nx, -1);
@@ -231,6 +265,18 @@ pic_status canonicalize(const pic_config* cfg, Canon* c) {
   for (int64_t i = 0; i < nx; ++i) c->mat_cell[i] = (signed char)material_at(cfg, ((double)i + 0.5) * c->dx[0]);
   for (int64_t i = 0; i <= nx; ++i) c->mat_node[i] = (signed char)material_at(cfg, (double)i * c->dx[0]);
   return PIC_OK;
+}
+
+// One mode of the coupled update gives, with w = z - 2 + 1/z,
+//   f(w) = w^2 / ie + (c / ie + 4 s2 + c deps) w + 4 s2 c = 0;
+// both roots are real and negative, and |z| = 1 needs them in [-4, 0]:
+// f(-4) > 0 with the vertex above -4.  Both tests only tighten as s2 grows,
+// so the grid's largest s2 = sum_d C_d^2 decides; c < 4 is the oscillator's
+// own leapfrog bound.
+bool lorentz_stable(double ie, double c, double cd, double s2max) {
+  if (!(c >= 0.0 && c < 4.0)) return false;
+  const double f4 = (16.0 - 4.0 * c) / ie - 4.0 * cd - s2max * (16.0 - 4.0 * c);
+  return f4 > 0.0 && c / ie + 4.0 * s2max + cd <= 8.0 / ie;
 }
 
 double laser_field(const Canon& c, double t) {

@@ -11,8 +11,14 @@ namespace pic {
 
 struct MatC {
   double gap_eV, n_index, n0, mred, mol_kg, e_kg, p_kg;
-  float ie;
+  float ie;                 // 1/eps_r (static) or 1/eps_inf (Lorentz)
+  double lam0, gamma, eps_inf, deps;   // Lorentz pole (lam0 = 0: static)
+  float lor[3];             // oscillator update (a, c, c deps); zeros when static
 };
+
+// Von Neumann stability of the Yee update coupled to the explicit Lorentz
+// oscillator (lossless medium), for the largest sum_d C_d^2 of the grid.
+bool lorentz_stable(double ie, double c, double cd, double s2max);
 
 struct Canon {
   int D;

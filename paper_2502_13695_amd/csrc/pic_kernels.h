@@ -28,6 +28,9 @@ struct Group {
   // host copy of a single run's parameter block: the field launch passes it
   // by value, so its fields load from the kernel arguments
   const Inst* host = nullptr;
+  // the field update advances Lorentz oscillators (some instance has a
+  // Lorentz medium): a kernel variant of its own, so static runs keep theirs
+  bool lor = false;
 };
 
 constexpr int TPB = 256;

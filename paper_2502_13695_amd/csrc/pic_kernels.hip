@@ -1246,6 +1246,31 @@ __device__ __forceinline__ bool v_dom(int v, int n, bool half, bool per) {  // i
   return per ? (v >= 0 && v < n) : (half ? (v >= 0 && v < n) : (v >= 0 && v <= n));
 }
 
+// Lorentz oscillator at one E position: the polarisation current of the
+// step from E^n and Q^n (set n & 1), returned for the E update; the block that
+// owns the position stores K^{n+1/2} and Q^{n+1} = Q^n + K^{n+1/2} in set
+// (n + 1) & 1.  L = (a, c, c deps).
+struct LorPtrs {
+  const gmem<float>* Kc;
+  const gmem<float>* Qc;
+  gmem<float>* Kn;
+  gmem<float>* Qn;
+};
+// (a macro, not a function: the kernels' parameter block stays in the
+// kernel-argument segment instead of being copied to private memory)
+#define LOR_PTRS(I, par, c)                                                                       \
+  LorPtrs { gp(uniform((I).Kp[par][c])), gp(uniform((I).Q[par][c])), gp(uniform((I).Kp[(par) ^ 1][c])), \
+            gp(uniform((I).Q[(par) ^ 1][c])) }
+__device__ __forceinline__ float lor_step(const LorPtrs& p, unsigned gi, float4 L, float e_old, bool own) {
+  const float ko = at(p.Kc, gi), qo = at(p.Qc, gi);
+  const float kn = fmaf(L.x, ko, fmaf(L.z, e_old, -L.y * qo));
+  if (own) {
+    at(p.Kn, gi) = kn;
+    at(p.Qn, gi) = qo + kn;
+  }
+  return kn;
+}
+
 template <int D, int V>
 struct TileT {
   static constexpr int X = tile_shape(D, V).x, Y = tile_shape(D, V).y, Z = tile_shape(D, V).z;
@@ -1281,7 +1306,7 @@ __device__ __forceinline__ unsigned axis_bits(int v, int n, bool per, bool inarr
 // once per block.  ONE: a single run whose parameter block, step index and
 // front and charged-range addresses come in the launch, so that the first
 // loads of a block are one round trip instead of a chain of dependent ones.
-template <int D, int V, bool ONE>
+template <int D, int V, bool LOR, bool ONE>
 __global__ __launch_bounds__(TPB) void k_fields(Group g, std::conditional_t<ONE, Inst, NoInst> one) {
   using T = TileT<D, V>;
   constexpr int H = 2;
@@ -1373,6 +1398,8 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g, std::conditional_t<ONE,
   // earlier step, so it is not updated (decided before the axis tables)
   if (g.part == 1 && !cur && a0x - H > front) return;
   if (threadIdx.x == 0) blk_hot = 0;
+  // Lorentz media inside the staged x range
+  const bool lorT = LOR && I.lx0 < I.lx1 && a0x - H < I.lx1 && a0x + T::X + H > I.lx0;
   // ---- per-axis tables; an interior tile (every staged position valid for
   // both updates and on no face, every owned position inside the box) runs
   // the phases below without any per-position test
@@ -1487,21 +1514,42 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g, std::conditional_t<ONE,
     if (D >= 3 && (qz < H - 1 || qz > T::Z + H)) continue;
     const unsigned bx = INNER ? ~0u : sbx[qx], by = INNER ? ~0u : sby[qy], bz = INNER ? ~0u : sbz[qz];
     if (!INNER && !(bx & by & bz & AX_ARR)) continue;
+    // Lorentz media: this block owns the position (periodic axes: the box)
+    unsigned gl = 0u;
+    bool own = false;
+    float4 lh = make_float4(0.f, 0.f, 0.f, 0.f), ln = lh;   // oscillator coefficients at this x
+    if (lorT) {
+      const int ai = a0x + qx - H;
+      if (ai >= 0 && ai < Px) {
+        lh = I.lor_half[ai];
+        ln = I.lor_node[ai];
+      }
+      gl = (unsigned)(ai + soy[qy] + soz[qz]);
+      own = qx >= H && qx < T::X + H;
+      if (D >= 2) own = own && qy >= H && qy < T::Y + H && (!py || (unsigned)(a0y + qy - H - Gy) < (unsigned)ny);
+      if (D >= 3) own = own && qz >= H && qz < T::Z + H && (!pz || (unsigned)(a0z + qz - H - Gz) < (unsigned)nz);
+    }
     if ((bx & AX_IH) && (by & AX_IN) && (bz & AX_IN)) {
       float cu = 0.0f;
       if (D >= 2) cu += Cy * (sB[2][l] - sB[2][l - LY]);
       if (D >= 3) cu -= Cz * (sB[1][l] - sB[1][l - LZ]);
-      sE[0][l] += sieh[qx] * (cu - jr[k][0]);
+      float src = cu - jr[k][0];
+      if (lorT && lh.y != 0.0f) src -= lor_step(LOR_PTRS(I, par, 0), gl, lh, sE[0][l], own);
+      sE[0][l] += sieh[qx] * src;
     }
     if ((bx & AX_IN) && (by & AX_IH) && (bz & AX_IN)) {
       float cu = -Cx * (sB[2][l] - sB[2][l - 1]);
       if (D >= 3) cu += Cz * (sB[0][l] - sB[0][l - LZ]);
-      sE[1][l] += sien[qx] * (cu - jr[k][1]);
+      float src = cu - jr[k][1];
+      if (lorT && ln.y != 0.0f) src -= lor_step(LOR_PTRS(I, par, 1), gl, ln, sE[1][l], own);
+      sE[1][l] += sien[qx] * src;
     }
     if ((bx & AX_IN) && (by & AX_IN) && (bz & AX_IH)) {
       float cu = Cx * (sB[1][l] - sB[1][l - 1]);
       if (D >= 2) cu -= Cy * (sB[0][l] - sB[0][l - LY]);
-      sE[2][l] += sien[qx] * (cu - jr[k][2]);
+      float src = cu - jr[k][2];
+      if (lorT && ln.y != 0.0f) src -= lor_step(LOR_PTRS(I, par, 2), gl, ln, sE[2][l], own);
+      sE[2][l] += sien[qx] * src;
     }
   }
   };
@@ -1752,7 +1800,7 @@ constexpr int ZNP = ZRX * ZRY;
 constexpr int ZPT = ZNP / TPB;                        // points per thread
 static_assert(ZNP % TPB == 0 && ZRX == 64, "plane layout");
 
-template <bool ONE>
+template <bool ONE, bool LOR>
 __global__ __launch_bounds__(TPB, 4) void k_fields_z(Group g, std::conditional_t<ONE, Inst, NoInst> one) {
   constexpr int LY = ZRX;
   __shared__ float sEa[3][ZNP], sEb[3][ZNP], sBa[3][ZNP], sBb[3][ZNP];
@@ -1762,6 +1810,7 @@ __global__ __launch_bounds__(TPB, 4) void k_fields_z(Group g, std::conditional_t
   __shared__ float sOld[2][2][2][2][ZRY];
   __shared__ unsigned sbx[ZRX];
   __shared__ float sieh[ZRX], sien[ZRX];
+  __shared__ float4 slh[LOR ? ZRX : 1], sln[LOR ? ZRX : 1];   // Lorentz coefficients per x
   __shared__ int blk_hot;
   const Slot sl = ONE ? Slot{0, (int)blockIdx.x, g.blocks} : block_slot(g);
   auto& I = inst_of(g, sl.ii, one);
@@ -1817,6 +1866,7 @@ __global__ __launch_bounds__(TPB, 4) void k_fields_z(Group g, std::conditional_t
   }
   if (g.part == 1 && !cur && a0x - ZH > front) return;
   if (threadIdx.x == 0) blk_hot = 0;
+  const bool lorT = LOR && I.lx0 < I.lx1 && a0x - ZH < I.lx1 && a0x + ZX + ZH > I.lx0;
   for (int q = threadIdx.x; q < ZRX; q += TPB) {
     const int i = a0x - G + q - ZH;
     const int ai = a0x + q - ZH;
@@ -1824,6 +1874,10 @@ __global__ __launch_bounds__(TPB, 4) void k_fields_z(Group g, std::conditional_t
     const bool in = ai >= 0 && ai < Px;
     sieh[q] = in ? I.ie_half[ai] : 1.0f;
     sien[q] = in ? I.ie_node[ai] : 1.0f;
+    if (lorT) {
+      slh[q] = in ? I.lor_half[ai] : make_float4(0.f, 0.f, 0.f, 0.f);
+      sln[q] = in ? I.lor_node[ai] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
   }
   // this thread's points: row offsets (y wrapped) and per-point facts
   int qxs[ZPT], qys[ZPT];
@@ -1966,21 +2020,34 @@ __global__ __launch_bounds__(TPB, 4) void k_fields_z(Group g, std::conditional_t
         if (!eregion(p)) continue;
         const unsigned bx = sbx[qx];
         if (!(bx & AX_ARR)) continue;
+        // Lorentz media: this block owns the position (plane t of its segment)
+        unsigned gl = 0u;
+        bool own = false;
+        if (lorT) {
+          gl = (unsigned)(a0x + qx - ZH) + rowo[p] + plane(t);
+          own = qx >= ZH && qx < ZX + ZH && owny[p] && t >= k0 && t < k1;
+        }
         if (bx & AX_IH) {
           float cu = 0.0f;
           cu += Cy * (cB[2][l] - cB[2][l - LY]);
           cu -= Cz * (cB[1][l] - bh1[p]);
-          cE[0][l] += sieh[qx] * (cu - jc[p][0]);
+          float src = cu - jc[p][0];
+          if (lorT && slh[qx].y != 0.0f) src -= lor_step(LOR_PTRS(I, par, 0), gl, slh[qx], cE[0][l], own);
+          cE[0][l] += sieh[qx] * src;
         }
         if (bx & AX_IN) {
           float cu = -Cx * (cB[2][l] - cB[2][l - 1]);
           cu += Cz * (cB[0][l] - bh0[p]);
-          cE[1][l] += sien[qx] * (cu - jc[p][1]);
+          float src = cu - jc[p][1];
+          if (lorT && sln[qx].y != 0.0f) src -= lor_step(LOR_PTRS(I, par, 1), gl, sln[qx], cE[1][l], own);
+          cE[1][l] += sien[qx] * src;
         }
         if (bx & AX_IN) {
           float cu = Cx * (cB[1][l] - cB[1][l - 1]);
           cu -= Cy * (cB[0][l] - cB[0][l - LY]);
-          cE[2][l] += sien[qx] * (cu - jc[p][2]);
+          float src = cu - jc[p][2];
+          if (lorT && sln[qx].y != 0.0f) src -= lor_step(LOR_PTRS(I, par, 2), gl, sln[qx], cE[2][l], own);
+          cE[2][l] += sien[qx] * src;
         }
       }
       __syncthreads();
@@ -2769,6 +2836,11 @@ __global__ __launch_bounds__(TPB) void k_diag_gauss(const Inst* d, const double*
   const float* E0 = I.F[par][0];
   const float* E1 = I.F[par][1];
   const float* E2 = I.F[par][2];
+  // displacement E / ie + Q (Q = P / eps0 of Lorentz media)
+  const bool lor = I.lx0 < I.lx1;
+  auto dsp = [&](int c, const float* E, int64_t q, float ie) {
+    return (double)E[q] / ie + (lor ? (double)I.Q[par][c][q] : 0.0);
+  };
   double mres = 0.0, mrho = 0.0, sres = 0.0, nres = 0.0;
   for (int64_t p = (int64_t)blockIdx.x * TPB + threadIdx.x; p < ncell; p += (int64_t)gridDim.x * TPB) {
     int i, j, k;
@@ -2777,14 +2849,14 @@ __global__ __launch_bounds__(TPB) void k_diag_gauss(const Inst* d, const double*
     if (D >= 2 && (I.per_y ? (j < 0 || j >= I.ny) : (j < 1 || j > I.ny - 1))) continue;
     if (D >= 3 && (I.per_z ? (k < 0 || k >= I.nz) : (k < 1 || k > I.nz - 1))) continue;
     const int ai = i + G;
-    double div = ((double)E0[p] / I.ie_half[ai] - (double)E0[p - 1] / I.ie_half[ai - 1]) / I.dx[0];
+    double div = (dsp(0, E0, p, I.ie_half[ai]) - dsp(0, E0, p - 1, I.ie_half[ai - 1])) / I.dx[0];
     if (D >= 2) {
       const int dym = I.per_y && j == 0 ? (I.ny - 1) * I.sy : -I.sy;
-      div += ((double)E1[p] - (double)E1[p + dym]) / I.ie_node[ai] / I.dx[1];
+      div += (dsp(1, E1, p, I.ie_node[ai]) - dsp(1, E1, p + dym, I.ie_node[ai])) / I.dx[1];
     }
     if (D >= 3) {
       const int dzm = I.per_z && k == 0 ? (I.nz - 1) * I.sz : -I.sz;
-      div += ((double)E2[p] - (double)E2[p + dzm]) / I.ie_node[ai] / I.dx[2];
+      div += (dsp(2, E2, p, I.ie_node[ai]) - dsp(2, E2, p + dzm, I.ie_node[ai])) / I.dx[2];
     }
     const double r = div - rho[p];
     mres = fmax(mres, fabs(r));
@@ -2869,7 +2941,13 @@ void launch_sort(const Group& gp, const Group& gscan, int D, hipStream_t s, Stam
   DISPATCH_D(D, GO((k_sort_scatter<DD>), gp.blocks, TPB, s, none, none, gp));
   DISPATCH_D(D, GO((k_sort_copy<DD>), gp.blocks, TPB, s, none, st.stop, gp));
 }
-#define FIELDS_V(DD, V) ONE_OR_GROUP(k_fields, TPB, DD, V)
+#define FIELDS_V(DD, V)                                \
+  do {                                                 \
+    if (g.lor)                                         \
+      ONE_OR_GROUP(k_fields, TPB, DD, V, true);        \
+    else                                               \
+      ONE_OR_GROUP(k_fields, TPB, DD, V, false);       \
+  } while (0)
 void launch_fields(const Group& g, int D, int variant, hipStream_t s, Stamp st) {
   const bool one = g.n == 1 && g.host && g.front && g.xext && g.step >= 0;
   switch (variant) {
@@ -2881,10 +2959,14 @@ void launch_fields(const Group& g, int D, int variant, hipStream_t s, Stamp st) 
     case 6: DISPATCH_D(D, FIELDS_V(DD, 6)); break;
     case kMarchVariant:
       if (D == 3) {
-        if (one)
-          GO((k_fields_z<true>), g.blocks, TPB, s, st.start, st.stop, g, *g.host);
+        if (one && g.lor)
+          GO((k_fields_z<true, true>), g.blocks, TPB, s, st.start, st.stop, g, *g.host);
+        else if (one)
+          GO((k_fields_z<true, false>), g.blocks, TPB, s, st.start, st.stop, g, *g.host);
+        else if (g.lor)
+          GO((k_fields_z<false, true>), g.blocks, TPB, s, st.start, st.stop, g, NoInst{});
         else
-          GO((k_fields_z<false>), g.blocks, TPB, s, st.start, st.stop, g, NoInst{});
+          GO((k_fields_z<false, false>), g.blocks, TPB, s, st.start, st.stop, g, NoInst{});
         break;
       }
       [[fallthrough]];
@@ -2903,7 +2985,7 @@ int field_tiles(int D, int variant, int Px, int Py, int Pz) {
       int dev = 0, bpc = 0;
       hipDeviceProp_t pr{};
       if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&pr, dev) == hipSuccess &&
-          hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, k_fields_z<true>, TPB, 0) == hipSuccess && bpc > 0)
+          hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, k_fields_z<true, false>, TPB, 0) == hipSuccess && bpc > 0)
         slots = bpc * pr.multiProcessorCount;
       else
         slots = 1024;

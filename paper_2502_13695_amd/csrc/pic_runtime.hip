@@ -63,6 +63,11 @@ struct Layout {
   int64_t wsz;
   int nsrc;
   size_t o_F[2][6], o_J[2][3], o_ie_half, o_ie_node, o_mat, o_src, o_prof;
+  // Lorentz media: polarisation Q and its current K (two sets, as the fields),
+  // per-x oscillator coefficients; lx0 <= padded x < lx1 spans every position
+  // with an oscillator (lx0 >= lx1: none, nothing allocated)
+  size_t o_Q[2][3], o_Kp[2][3], o_lor_half, o_lor_node;
+  int lx0, lx1;
   size_t o_ring, o_suffix, o_prefix, o_A;
   size_t o_no[3], o_alive, o_death, o_mcell;
   size_t o_pcell, o_po[3], o_pu[3], o_pkind, o_pid;
@@ -156,6 +161,24 @@ pic_status plan(const pic_config* cfg, const Canon& c, const std::vector<TableHo
     for (int q = 0; q < 3; ++q) L->o_J[par][q] = take(f);
   L->o_ie_half = take(sizeof(float) * L->Px);
   L->o_ie_node = take(sizeof(float) * L->Px);
+  L->lx0 = (int)L->Px;
+  L->lx1 = 0;
+  for (int64_t i = 0; i <= c.n[0]; ++i) {
+    const bool lc = i < c.n[0] && c.mat_cell[i] >= 0 && c.mats[c.mat_cell[i]].lam0 > 0;
+    const bool ln = c.mat_node[i] >= 0 && c.mats[c.mat_node[i]].lam0 > 0;
+    if (lc || ln) {
+      L->lx0 = std::min(L->lx0, (int)(i + G));
+      L->lx1 = std::max(L->lx1, (int)(i + G + 1));
+    }
+  }
+  const size_t fq = L->lx0 < L->lx1 ? f : 0;
+  for (int par = 0; par < 2; ++par)
+    for (int q = 0; q < 3; ++q) {
+      L->o_Q[par][q] = take(fq);
+      L->o_Kp[par][q] = take(fq);
+    }
+  L->o_lor_half = take(fq ? sizeof(float4) * L->Px : 0);
+  L->o_lor_node = take(fq ? sizeof(float4) * L->Px : 0);
   L->o_mat = take(c.n[0]);
   L->o_src = take(sizeof(float) * 4 * (size_t)L->nsrc);
   L->o_prof = take(sizeof(float) * L->Py * L->Pz);
@@ -253,6 +276,7 @@ struct pic_batch {
   struct Class {
     int D, order, tile = 0;
     bool per = false;   // periodic transverse axes
+    bool lor = false;   // some member has a Lorentz medium
     std::vector<pic_ctx*> ms;
     Inst* d_insts = nullptr;
     int* d_off = nullptr;   // 4 phases x (n + 1)
@@ -346,6 +370,7 @@ Group single(pic_ctx* c, int phase, int nb) {
   g.front = &c->d_ctr->front;
   g.xext = c->d_ctr->xext;
   g.host = &c->h;
+  g.lor = c->L.lx0 < c->L.lx1;
   return g;
 }
 
@@ -483,6 +508,7 @@ void enqueue_step(pic_ctx* c) {
     gv.front = &c->d_ctr->front;
     gv.xext = c->d_ctr->xext;
     gv.host = &c->h;
+    gv.lor = c->L.lx0 < c->L.lx1;
     launch_fields(gv, D, v, s, Stamp{c->tune_ev[v][r][0], c->tune_ev[v][r][1]});
     if (rebuild_due(c)) launch_win_rebuild(c->h, c->L.wsz, s);
     if (--c->tune_left == 0) finish_tuning(c);
@@ -621,7 +647,10 @@ pic_status pic_canonical(const pic_config* cfg, pic_params* out) {
     out->Cd[d] = c.C[d];
     out->kmur[d] = c.kmur[d];
   }
-  for (int m = 0; m < c.nmat; ++m) out->ie[m] = c.mats[m].ie;
+  for (int m = 0; m < c.nmat; ++m) {
+    out->ie[m] = c.mats[m].ie;
+    for (int q = 0; q < 3; ++q) out->lor[m][q] = c.mats[m].lor[q];
+  }
   out->nwin = c.nwin;
   out->E0 = c.E0;
   out->t_peak = c.t0;
@@ -747,6 +776,17 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
     ie_half[i + G] = K.mat_cell[i] >= 0 ? K.mats[K.mat_cell[i]].ie : 1.0f;
   for (int64_t i = 0; i <= K.n[0]; ++i)
     ie_node[i + G] = K.mat_node[i] >= 0 ? K.mats[K.mat_node[i]].ie : 1.0f;
+  const bool has_lor = L.lx0 < L.lx1;
+  std::vector<float4> lor_half(has_lor ? L.Px : 0, make_float4(0.f, 0.f, 0.f, 0.f));
+  std::vector<float4> lor_node(lor_half);
+  auto lor_of = [&](int m) {
+    return m >= 0 ? make_float4(K.mats[m].lor[0], K.mats[m].lor[1], K.mats[m].lor[2], 0.f)
+                  : make_float4(0.f, 0.f, 0.f, 0.f);
+  };
+  if (has_lor) {
+    for (int64_t i = 0; i < K.n[0]; ++i) lor_half[i + G] = lor_of(K.mat_cell[i]);
+    for (int64_t i = 0; i <= K.n[0]; ++i) lor_node[i + G] = lor_of(K.mat_node[i]);
+  }
   std::vector<float> src(4 * (size_t)L.nsrc, 0.0f);
   for (int m = 0; m < L.nsrc; ++m) {
     src[4 * m + 0] = (float)laser_field(K, m * K.dt);
@@ -797,6 +837,15 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
   }
   I.ie_half = (const float*)devp(c, L.o_ie_half);
   I.ie_node = (const float*)devp(c, L.o_ie_node);
+  I.lx0 = L.lx0;
+  I.lx1 = L.lx1;
+  for (int par = 0; par < 2; ++par)
+    for (int q = 0; q < 3; ++q) {
+      I.Q[par][q] = has_lor ? (float*)devp(c, L.o_Q[par][q]) : nullptr;
+      I.Kp[par][q] = has_lor ? (float*)devp(c, L.o_Kp[par][q]) : nullptr;
+    }
+  I.lor_half = has_lor ? (const float4*)devp(c, L.o_lor_half) : nullptr;
+  I.lor_node = has_lor ? (const float4*)devp(c, L.o_lor_node) : nullptr;
   I.mat_cell = (const signed char*)devp(c, L.o_mat);
   I.pol = K.pol;
   I.nsrc = L.nsrc;
@@ -929,6 +978,12 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
   bool ok = true;
   ok &= hipMemcpyAsync(devp(c, L.o_ie_half), ie_half.data(), sizeof(float) * L.Px, hipMemcpyHostToDevice, s) == hipSuccess;
   ok &= hipMemcpyAsync(devp(c, L.o_ie_node), ie_node.data(), sizeof(float) * L.Px, hipMemcpyHostToDevice, s) == hipSuccess;
+  if (has_lor) {
+    ok &= hipMemcpyAsync(devp(c, L.o_lor_half), lor_half.data(), sizeof(float4) * L.Px, hipMemcpyHostToDevice, s) ==
+          hipSuccess;
+    ok &= hipMemcpyAsync(devp(c, L.o_lor_node), lor_node.data(), sizeof(float4) * L.Px, hipMemcpyHostToDevice, s) ==
+          hipSuccess;
+  }
   ok &= hipMemcpyAsync(devp(c, L.o_mat), K.mat_cell.data(), K.n[0], hipMemcpyHostToDevice, s) == hipSuccess;
   ok &= hipMemcpyAsync(devp(c, L.o_src), src.data(), sizeof(float) * src.size(), hipMemcpyHostToDevice, s) == hipSuccess;
   ok &= hipMemcpyAsync(devp(c, L.o_prof), prof.data(), sizeof(float) * prof.size(), hipMemcpyHostToDevice, s) == hipSuccess;
@@ -1189,6 +1244,20 @@ pic_status pic_step(pic_ctx* c, int64_t nsteps) {
 // Field-kernel tile autotuner: before the first step the fields, currents and
 // amplitude window are all zero, so every variant can be timed on the real
 // launch shape; the state is cleared again afterwards (exactly the initial state).
+// Lorentz media back at rest (Q = K = 0 in both sets); stream null: synchronous
+hipError_t clear_polarisation(pic_ctx* c, hipStream_t s) {
+  const Layout& L = c->L;
+  if (L.lx0 >= L.lx1) return hipSuccess;
+  for (int par = 0; par < 2; ++par)
+    for (int q = 0; q < 3; ++q)
+      for (void* p : {devp(c, L.o_Q[par][q]), devp(c, L.o_Kp[par][q])}) {
+        const hipError_t e = s ? hipMemsetAsync(p, 0, sizeof(float) * L.ncell, s)
+                               : hipMemset(p, 0, sizeof(float) * L.ncell);
+        if (e != hipSuccess) return e;
+      }
+  return hipSuccess;
+}
+
 pic_status pic_autotune(pic_ctx* c, int32_t reps) {
   if (!c || reps < 1) return PIC_E_INVAL;
   if (c->step != 0 || c->cfg.preionize_eV > 0) return PIC_E_STATE;
@@ -1214,6 +1283,7 @@ pic_status pic_autotune(pic_ctx* c, int32_t reps) {
       gr.front = &c->d_ctr->front;
       gr.xext = c->d_ctr->xext;
       gr.host = &c->h;
+      gr.lor = c->L.lx0 < c->L.lx1;
       launch_fields(gr, D, v, s);   // warm
       HIP_OK(hipEventRecord(e0, s));
       for (int r = 0; r < reps; ++r) launch_fields(gr, D, v, s);
@@ -1241,6 +1311,7 @@ pic_status pic_autotune(pic_ctx* c, int32_t reps) {
     for (int q = 0; q < 6; ++q) HIP_OK(hipMemsetAsync(devp(c, L.o_F[par][q]), 0, sizeof(float) * L.ncell, s));
     for (int q = 0; q < 3; ++q) HIP_OK(hipMemsetAsync(devp(c, L.o_J[par][q]), 0, sizeof(float) * L.ncell, s));
   }
+  HIP_OK(clear_polarisation(c, s));
   HIP_OK(hipMemsetAsync(devp(c, L.o_ring), 0, sizeof(float) * L.wsz * c->canon.nwin, s));
   HIP_OK(hipMemsetAsync(devp(c, L.o_suffix), 0, sizeof(float) * L.wsz * c->canon.nwin, s));
   HIP_OK(hipMemsetAsync(devp(c, L.o_prefix), 0, sizeof(float) * L.wsz, s));
@@ -1347,6 +1418,7 @@ pic_status pic_set_state(pic_ctx* c, const pic_state* S) {
   }
   for (int par = 0; par < 2; ++par)
     for (int q = 0; q < 3; ++q) HIP_OK(hipMemset(devp(c, L.o_J[par][q]), 0, sizeof(float) * L.ncell));
+  HIP_OK(clear_polarisation(c, nullptr));
   HIP_OK(hipDeviceSynchronize());
   return PIC_OK;
 }
@@ -1364,6 +1436,10 @@ pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size
     case PIC_DIAG_SCALARS: need = sizeof(double) * PIC_SC_COUNT; break;
     case PIC_DIAG_FIELDS: {
       for (int q = 0; q < 3; ++q) need += sizeof(double) * (dom_count(K, kHalfE[q]) + dom_count(K, kHalfB[q]));
+      break;
+    }
+    case PIC_DIAG_POL: {
+      for (int q = 0; q < 3; ++q) need += 2 * sizeof(double) * dom_count(K, kHalfE[q]);
       break;
     }
     case PIC_DIAG_NE_GRID:
@@ -1476,6 +1552,21 @@ pic_status pic_diag(pic_ctx* c, int kind, void* host_out, size_t out_bytes, size
         const bool* half = w == 0 ? kHalfE[q] : kHalfB[q];
         for_domain(K, half, [&](int64_t n, int64_t i, int64_t j, int64_t k) { o[n] = buf[pidx(L, D, i, j, k)]; });
         o += dom_count(K, half);
+      }
+    return PIC_OK;
+  }
+  if (kind == PIC_DIAG_POL) {
+    double* o = (double*)host_out;
+    std::vector<float> buf(L.ncell, 0.0f);
+    int dstep = 0;
+    HIP_OK(hipMemcpy(&dstep, &c->d_ctr->step, sizeof dstep, hipMemcpyDeviceToHost));
+    for (int w = 0; w < 2; ++w)
+      for (int q = 0; q < 3; ++q) {
+        if (L.lx0 < L.lx1)
+          HIP_OK(hipMemcpy(buf.data(), devp(c, w == 0 ? L.o_Q[dstep & 1][q] : L.o_Kp[dstep & 1][q]),
+                           sizeof(float) * L.ncell, hipMemcpyDeviceToHost));
+        for_domain(K, kHalfE[q], [&](int64_t n, int64_t i, int64_t j, int64_t k) { o[n] = buf[pidx(L, D, i, j, k)]; });
+        o += dom_count(K, kHalfE[q]);
       }
     return PIC_OK;
   }
@@ -1709,6 +1800,7 @@ static pic_status batch_rebuild(pic_batch* b) {
       cl->per = c->canon.per[1];
     }
     cl->ms.push_back(c);
+    cl->lor = cl->lor || c->L.lx0 < c->L.lx1;
   }
   // persistent push/sort blocks: shared out over the members (every member
   // keeps at least 16; its grid-stride loops cover any particle count)
@@ -1754,6 +1846,7 @@ static void batch_enqueue(pic_batch* b, int64_t k, hipStream_t s) {
       const int np1 = cl.n + 1;
       Group gp{cl.d_insts, cl.d_off + 0 * np1, cl.n, cl.blocks[0], -1, 0, cl.d_map + cl.map_off[0]};
       Group gc{cl.d_insts, cl.d_off + 1 * np1, cl.n, cl.blocks[1], -1, 1, cl.d_map + cl.map_off[1]};
+      gc.lor = cl.lor;
       Group gs{cl.d_insts, cl.d_off + 2 * np1, cl.n, cl.blocks[2], -1, 0, cl.d_map + cl.map_off[2]};
       Group gn{cl.d_insts, cl.d_off + 3 * np1, cl.n, cl.blocks[3], -1, 0, cl.d_map + cl.map_off[3]};
       if (sort_due) launch_sort(gp, gs, cl.D, s);

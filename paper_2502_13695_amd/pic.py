@@ -19,11 +19,11 @@ PIC_OK = 0
 STATUS = {0: "ok", -1: "invalid argument", -2: "device allocation failed", -3: "HIP runtime error",
           -4: "invalid state (latched error)", -5: "non-finite value",
           -6: "charged-particle capacity exceeded", -7: "ABI version mismatch"}
-ABI_VERSION = 1
+ABI_VERSION = 2
 ENV = {"gauss": 0, "sin2": 1}
 BC = {"outflow": 0, "periodic": 1}
 DIAG_SCALARS, DIAG_FIELDS, DIAG_NE, DIAG_UE, DIAG_EVENTS, DIAG_PARTICLES, DIAG_PARAMS, DIAG_AMP, \
-    DIAG_TIMERS, DIAG_SORT, DIAG_REGION, DIAG_IMAX, DIAG_TRACKS, DIAG_HEALTH = range(14)
+    DIAG_TIMERS, DIAG_SORT, DIAG_REGION, DIAG_IMAX, DIAG_TRACKS, DIAG_HEALTH, DIAG_POL = range(15)
 SC = dict(step=0, time=1, n_neutral=2, n_e=3, n_pos=4, events=5, u_field=6, ke_e=7, ke_pos=8,
           e_gap=9, e_abs=10, gauss_max=11, rho_max=12, health=13, slots=14, tracks_dropped=15,
           gauss_l2=16, e_in=17, e_out=18)
@@ -37,7 +37,8 @@ class PicError(RuntimeError):
 
 class Material(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("gap_eV", "n_index", "density_gcc", "molar_mass_gmol",
-                                            "me_star", "mh_star", "pos_mass_kg")]
+                                            "me_star", "mh_star", "pos_mass_kg", "lorentz_lambda_m",
+                                            "eps_inf", "lorentz_gamma_s")]
 
 
 class Layer(C.Structure):
@@ -71,7 +72,7 @@ class Params(C.Structure):
     _fields_ = [("dt", C.c_double), ("Cd", C.c_double * 3), ("kmur", C.c_double * 3),
                 ("ie", C.c_double * 8), ("nwin", C.c_int64), ("E0", C.c_double),
                 ("t_peak", C.c_double), ("amp_cut", C.c_double * 8), ("amp_sat", C.c_double * 8),
-                ("n_neutral", C.c_int64), ("capacity", C.c_int64)]
+                ("n_neutral", C.c_int64), ("capacity", C.c_int64), ("lor", (C.c_double * 3) * 8)]
 
 
 class Particle(C.Structure):
@@ -180,6 +181,9 @@ def make_config(cfg, stream=None, alloc=None, free=None):
         for k in ("gap_eV", "n_index", "density_gcc", "molar_mass_gmol", "me_star", "mh_star"):
             setattr(mats[i], k, float(m[k]))
         mats[i].pos_mass_kg = float(m.get("pos_mass_kg", 0.0))
+        mats[i].lorentz_lambda_m = float(m.get("lorentz_lambda_m", 0.0))
+        mats[i].eps_inf = float(m.get("eps_inf", 1.0))
+        mats[i].lorentz_gamma_s = float(m.get("lorentz_gamma_s", 0.0))
     layers = (Layer * max(1, len(cfg["layers"])))()
     for i, (m, lo, hi) in enumerate(cfg["layers"]):
         layers[i].material = int(m)
@@ -347,6 +351,12 @@ class Context:
         """(E, b): lists of 3 FP64 arrays indexed [i, j, k] on their own positions."""
         flat = self._diag(DIAG_FIELDS, np.float64)
         arrs = self._split(flat, [("E", 0), ("E", 1), ("E", 2), ("b", 0), ("b", 1), ("b", 2)])
+        return arrs[:3], arrs[3:]
+
+    def polarisation(self):
+        """(Q, K) of the Lorentz media: lists of 3 FP64 arrays on the E positions."""
+        flat = self._diag(DIAG_POL, np.float64)
+        arrs = self._split(flat, [("E", 0), ("E", 1), ("E", 2), ("E", 0), ("E", 1), ("E", 2)])
         return arrs[:3], arrs[3:]
 
     def _node_grid(self, kind, dtype):

@@ -39,7 +39,9 @@ def test_exports_every_declared_symbol():
 
 
 @pytest.mark.parametrize("cfg", [W.config_1d(), W.config_1d(hi=True), W.config_2d(), W.config_3d(),
-                                 W.batch_scan(4)[3], W.config_2d(nx=100, ny=37)])
+                                 W.batch_scan(4)[3], W.config_2d(nx=100, ny=37),
+                                 W.config_1d(dispersive=True), W.config_2d(dispersive=True),
+                                 W.config_3d(dispersive=True)])
 def test_canonical_problem_bitwise_equal(cfg):
     _lib_or_skip()
     p = P.canonical(cfg)
@@ -49,9 +51,37 @@ def test_canonical_problem_bitwise_equal(cfg):
     assert list(p.kmur)[:o.D] == o.kmur[:o.D]
     assert p.nwin == o.nwin
     assert [p.ie[m] for m in range(len(o.mats))] == [m.ie for m in o.mats]
+    assert [tuple(p.lor[m]) for m in range(len(o.mats))] == [tuple(m.lor) for m in o.mats]
     assert abs(p.E0 / o.laser.E0 - 1) < 1e-15
     nmat_cells = int(np.sum(o.mat_cell >= 0)) * o.n[1] * o.n[2]
     assert p.n_neutral == nmat_cells * o.ppc
+
+
+def test_lorentz_stability_check_matches_oracle():
+    """pic_init's stability test of a Lorentz medium agrees with the oracle's
+    (which its own test ties to the roots of the mode polynomial)."""
+    _lib_or_skip()
+    from oracle.problem import lorentz_stable
+    seen = {True: 0, False: 0}
+    for lam0 in (0.1e-6, 0.116e-6, 0.15e-6, 0.2e-6, 0.3e-6):
+        for eps_inf in (1.0, 1.3, 1.7, 2.0):
+            for dxfrac in (12, 20, 40):
+                cfg = W.config_1d(n=64, ppc=1)
+                cfg["dx"] = [W.LAMBDA / dxfrac]
+                cfg["materials"] = [W.lorentz(W.silica_like(), lam0, eps_inf=eps_inf)]
+                try:
+                    Problem(cfg)
+                    want = True
+                except ValueError:
+                    want = False
+                try:
+                    P.canonical(cfg)
+                    got = True
+                except P.PicError:
+                    got = False
+                assert got == want, (lam0, eps_inf, dxfrac)
+                seen[want] += 1
+    assert seen[True] > 5 and seen[False] > 5
 
 
 def test_keldysh_rate_cpp_equals_oracle():
