@@ -36,6 +36,8 @@ it changes; the inherited parts follow the textbook method named alongside:
   paid by ionization (absorbed energy, a reading of Sec. 4.2), the number and
   energy density grids (Sec. 4.1, 4.2), and the Poynting flux through the
   faces of the box one cell inside the outflow faces (the field-side budget).
+* Binary Coulomb collisions among the charged particles (Sec. 2.2, Eq. 4;
+  optional, after ionization): oracle/collide.py.
 * Monte-Carlo single ionization of immobile neutral molecule macroparticles
   with the per-molecule rate W/n0, probability 1 - exp(-W dt / n0) per step,
   the whole macroparticle converting into one electron (m_e*, Sec. 3.2) and
@@ -71,7 +73,7 @@ from collections import deque
 import numpy as np
 
 from .constants import C, KB, EPS0, QE
-from . import keldysh, philox
+from . import collide, keldysh, philox
 from .problem import Problem
 
 G = 3  # guard layers on each side of every present dimension
@@ -685,6 +687,8 @@ class Sim:
         if self.imax_every > 0 and (n + 1) % self.imax_every == 0:
             self.imax = np.maximum(self.imax, em * em)
         self.ionize(n + 1)
+        if self.P.collisions:
+            collide.collide(self, n + 1)
         self.step_index = n + 1
         if self.track_every > 0 and (n + 1) % self.track_every == 0:
             self._record_tracks(n + 1)

@@ -151,6 +151,8 @@ class Problem:
         self.terms = int(cfg.get("keldysh_terms", 500))
         self.tol_bits = int(cfg.get("keldysh_tol_bits", 0)) or 60
         self.seed = int(cfg["seed"])
+        # binary collisions among the charged particles (Sec. 2.2), off unless asked for
+        self.collisions = bool(cfg.get("collisions", False))
 
         # time step: cfl / (c sqrt(sum_d 1/dx_d^2)), Sec. 3.1; canonicalised
         s = 0.0

@@ -14,7 +14,9 @@ Configuration dictionary (both sides read the same keys):
   keldysh_terms, seed, laser (lambda_m, fwhm_s, peak_Wcm2 | fluence_Jcm2,
   waist_m, t_peak_s, cep_rad, envelope "gauss" | "sin2", pol_axis),
   particle_capacity, preionize_eV (0 = off; >0: every neutral starts ionized,
-  carriers thermal at that temperature -- the charged-loop stress variant).
+  carriers thermal at that temperature -- the charged-loop stress variant),
+  collisions (optional, default off: binary collisions among the charged
+  particles).
 
 The paper's runs (Sec. 3) are 3D with ~1e10 macroparticles and are not
 reproduced; the configurations below are the synthetic stand-ins the
