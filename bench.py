@@ -55,10 +55,15 @@ FP32_PEAK_TFLOPS = 157.3
 C_LIGHT = 299792458.0
 
 # phases of the step (index into the library's timers)
-PHASES = {0: "push", 1: "fields", 2: "ionize", 3: "sort"}
+PHASES = {0: "push", 1: "fields", 2: "ionize", 3: "sort", 4: "collide"}
 # algorithmic bytes per unit of work
 B_CHARGED, B_NEUTRAL, B_EVENT = 60.0, 16.0, 64.0
 B_CELL, B_CELL_NO_J, B_WINDOW, B_SORTED = 73.0, 49.0, 24.0, 120.0
+# binary collisions: per charged particle-step, binning (read cell and kind,
+# write slot and key: 13), the cell pass (read slot, key, kind, id: 13; read and
+# write u: 24) and 10 for the sort's moves; per cell-step the counts, fill
+# counters and their scan (16)
+B_COLLIDE, B_COLLIDE_CELL = 60.0, 16.0
 # algorithmic flops per charged particle-step of the 3D order-2 push: gather
 # 160, Boris 60, Esirkepov deposit 770
 FLOP_PUSH_3D2 = 990.0
@@ -250,6 +255,9 @@ def phase_bytes(cfg, r, cnt, steps):
     nsort = r["sort1"]["sorts"] - r["sort0"]["sorts"]
     slots = 0.5 * (cnt["charged_start"] + cnt["charged_end"])
     out[3] = B_SORTED * slots * nsort / n_launch[3]
+    # binary collisions (when on): the charged slots binned by cell and their
+    # momenta read and written, plus the per-cell counts and scan
+    out[4] = (B_COLLIDE * cnt["charged_steps"] + B_COLLIDE_CELL * domain_cells(cfg) * steps) / n_launch[4]
     return out, dict(tiles=ntiles, updated_per_launch=upd, near=near, far_updated=far_upd,
                      sorts=nsort)
 
@@ -393,6 +401,9 @@ def workload_config(name, dispersive=False):
 def bench_window(args):
     from paper_2502_13695_amd import pic
     cfg, ocfg, share_note = workload_config(args.workload, args.dispersive)
+    if args.collisions:
+        cfg = dict(cfg, collisions=True)
+        ocfg = dict(ocfg, collisions=True) if ocfg is not None else None
     params = pic.canonical(cfg)
     if args.start is not None:
         start = args.start
@@ -452,7 +463,8 @@ def bench_window(args):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload] + (DISPERSIVE_NOTE if args.dispersive else ""),
+        "config": {"workload": WORKLOADS[args.workload] + (DISPERSIVE_NOTE if args.dispersive else "")
+                   + ("; binary collisions every step" if args.collisions else ""),
                    "cells": list(cfg["n"]), "ppc": cfg["ppc"],
                    "seed": cfg["seed"], "start_step": start,
                    "sort_check_every": args.resort if args.resort is not None else 8,
@@ -698,6 +710,8 @@ def main():
                     help="fixed field tile shape (default: timed in-run over the first steps)")
     ap.add_argument("--dispersive", action="store_true",
                     help="the workload's layers respond as single-pole Lorentz media")
+    ap.add_argument("--collisions", action="store_true",
+                    help="binary collisions among the charged particles every step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--calib-copy", action="store_true",

@@ -132,6 +132,14 @@ typedef struct {
   int64_t particle_capacity;   /* charged-particle slots; 0 = 2 x neutrals + 4096 */
   double preionize_eV;         /* >0: every neutral starts ionized, carriers thermal at
                                   this temperature (charged-loop stress variant) */
+  int32_t collisions;          /* 1: binary Coulomb collisions among all charged
+                                  particles every step, after ionization (Sec. 2.2,
+                                  Eq. 4: the Perez/Nanbu model; pairing per cell and
+                                  kind, relativistic kinematics, Coulomb logarithm
+                                  per collision with a lower bound of 1, the
+                                  low-temperature cap).  0: none.  A run with
+                                  collisions cannot join a batch (PIC_E_INVAL). */
+  int32_t reserved2;
   void* stream;                /* hipStream_t, or NULL for the default stream */
   void* (*alloc)(size_t bytes, void* user);   /* optional device allocator */
   void (*free)(void* ptr, void* user);

@@ -21,6 +21,7 @@ COMMON = ["-x", "hip", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-I", IN
           "-Wno-unused-command-line-argument"]
 UNITS = [
     ("pic_kernels.hip", ["-O3", "-munsafe-fp-atomics"]),
+    ("pic_collide.hip", ["-O3"]),
     ("pic_runtime.hip", ["-O2"]),
     # canonical coefficients must be bit-reproducible: no FP contraction
     ("host_math.cpp", ["-O2", "-ffp-contract=off"]),

@@ -210,6 +210,8 @@ pic_status canonicalize(const pic_config* cfg, Canon* c) {
   c->vcell = 1.0;
   for (int d = 0; d < c->D; ++d) c->vcell *= c->dx[d];
   c->ppc = cfg->ppc;
+  if (cfg->collisions != 0 && cfg->collisions != 1) return PIC_E_INVAL;
+  c->collide = cfg->collisions == 1;
   for (int m = 0; m < cfg->nmat; ++m) {
     const pic_material& M = cfg->mats[m];
     if (!(M.n_index > 0) || !(M.density_gcc > 0) || !(M.molar_mass_gmol > 0) || !(M.me_star > 0) ||

@@ -25,6 +25,7 @@ struct Canon {
   int64_t n[3];
   double dx[3];
   bool per[3];
+  bool collide;   // binary collisions every step
   double dt;
   float C[3], kmur[3];
   int nwin;

@@ -1,0 +1,384 @@
+// Binary Coulomb collisions among the charged macroparticles (gfx950).
+//
+// The paper (Sec. 2.2, Eq. 4) collides all charged particles with the
+// Perez/Nanbu binary model of its host code: collision frequency
+// nu = (q_a q_b)^2 n_b ln(Lambda) / (4 pi (eps0 mu)^2) / v_r^3, the Coulomb
+// logarithm computed per collision with a lower bound of 1, and a
+// low-temperature extension.  The published method it names (Perez et al.
+// 2012, Nanbu 1997, Nanbu & Yonemura 1998) is restated here:
+//
+// * per step, after ionization, the particles are binned by cell (count,
+//   scan, fill), and each cell's entries ordered by (kind, Philox key, id);
+//   the order does not depend on where the particles sit in memory;
+// * one thread per cell runs the cell's collisions in a fixed sequence: each
+//   kind with itself (pairs of consecutive entries; an odd count first forms
+//   a triangle of three half-strength collisions), kinds ascending, then each
+//   pair of kinds a < b (collision i takes the (i mod Na)-th of a and the
+//   (i mod Nb)-th of b), each collision reading the momenta the previous left;
+// * per collision: the centre-of-momentum frame, the scattering parameter s
+//   (whose non-relativistic limit is nu dt of Eq. 4), the cap of one mean free
+//   path, the deflection angle from Nanbu's law through Perez's fit of A(s),
+//   a uniform azimuth, back to the lab frame; unlike weights follow Nanbu and
+//   Yonemura's rule (update with probability w_other / w_max).
+// The arithmetic is FP64; momenta are stored back as FP32.
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
+
+#include <algorithm>
+
+#include "pic_kernels.h"
+
+namespace pic {
+
+namespace {
+
+constexpr uint32_t PURPOSE_PAIR = 7, PURPOSE_SCATTER = 8;
+constexpr double kC = 299792458.0, kEPS0 = 8.8541878128e-12, kHBAR = 1.054571817e-34,
+                 kQE = 1.602176634e-19, kPI = 3.14159265358979323846;
+constexpr int SCAN_B = 1024;   // elements per block of the cell scan
+
+__device__ __forceinline__ int box_cell(const Inst& I, uint32_t pc) {
+  int i, j, k;
+  unpack_cell(I.D, pc, i, j, k);
+  return i + I.nx * (j + I.ny * k);
+}
+
+__device__ __forceinline__ int live_slots(const Inst& I) {
+  const int n = *I.pcount;
+  return n < I.capacity ? n : I.capacity;
+}
+
+__global__ void k_col_clear(ColBufs b) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i <= b.ncell) b.cnt[i] = 0;
+  if (i < b.ncell) b.fill[i] = 0;
+  if (i == 0) *b.nactive = 0;
+}
+
+// counts per cell; a cell's second particle lists the cell as one that collides
+__global__ void k_col_count(const Inst I, ColBufs b) {
+  const int n = live_slots(I);
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x)
+    if (I.pkind[p] != 0xFF) {
+      const int c = box_cell(I, I.pcell[p]);
+      if (atomicAdd(&b.cnt[c], 1) == 1) b.active[atomicAdd(b.nactive, 1)] = c;
+    }
+}
+
+// exclusive scan of cnt[0 .. n): per block in LDS, block totals, then offsets
+__global__ void k_col_scan_local(ColBufs b, int n) {
+  __shared__ int s[SCAN_B];
+  const int base = blockIdx.x * SCAN_B;
+  for (int t = threadIdx.x; t < SCAN_B; t += blockDim.x) s[t] = base + t < n ? b.cnt[base + t] : 0;
+  __syncthreads();
+  // Hillis-Steele inclusive scan over SCAN_B elements with blockDim.x = SCAN_B
+  for (int off = 1; off < SCAN_B; off <<= 1) {
+    const int t = threadIdx.x;
+    const int v = t >= off ? s[t - off] : 0;
+    __syncthreads();
+    s[t] += v;
+    __syncthreads();
+  }
+  const int t = threadIdx.x;
+  if (base + t < n) b.cnt[base + t] = t == 0 ? 0 : s[t - 1];
+  if (t == SCAN_B - 1) b.bsum[blockIdx.x] = s[t];
+}
+
+__global__ void k_col_scan_top(ColBufs b, int nb) {
+  // one block: exclusive scan of the block totals, serial per thread chunk
+  __shared__ int part[SCAN_B];
+  const int per = (nb + SCAN_B - 1) / SCAN_B;
+  const int t = threadIdx.x;
+  int sum = 0;
+  for (int q = 0; q < per; ++q) {
+    const int i = t * per + q;
+    if (i < nb) sum += b.bsum[i];
+  }
+  part[t] = sum;
+  __syncthreads();
+  if (t == 0) {
+    int run = 0;
+    for (int q = 0; q < SCAN_B; ++q) {
+      const int v = part[q];
+      part[q] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  int run = part[t];
+  for (int q = 0; q < per; ++q) {
+    const int i = t * per + q;
+    if (i < nb) {
+      const int v = b.bsum[i];
+      b.bsum[i] = run;
+      run += v;
+    }
+  }
+}
+
+__global__ void k_col_scan_add(ColBufs b, int n) {
+  const int i = blockIdx.x * SCAN_B + threadIdx.x;
+  if (i < n) b.cnt[i] += b.bsum[blockIdx.x];
+}
+
+__global__ void k_col_fill(const Inst I, ColBufs b, int step) {
+  const int n = live_slots(I);
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
+    const uint8_t kd = I.pkind[p];
+    if (kd == 0xFF) continue;
+    const int c = box_cell(I, I.pcell[p]);
+    const int q = b.cnt[c] + atomicAdd(&b.fill[c], 1);
+    b.idx[q] = p;
+    b.key[q] = draw(I.seed, (uint64_t)I.pid[p] | ((uint64_t)kd << 32), (uint32_t)step, PURPOSE_PAIR).x;
+  }
+}
+
+struct D3 {
+  double x, y, z;
+};
+__device__ __forceinline__ D3 operator+(D3 a, D3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ D3 operator*(double s, D3 a) { return {s * a.x, s * a.y, s * a.z}; }
+__device__ __forceinline__ double dot(D3 a, D3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+
+__device__ __forceinline__ double unif(uint32_t w) { return ((double)w + 0.5) * 0x1p-32; }
+
+// Nanbu's deflection: <cos chi> = coth A - 1/A = exp(-s); Perez's fit of 1/A
+// on 0.1 <= s < 3, the small-angle law below, A = 3 exp(-s) up to 6, isotropic
+// above.  FP64: small deflections take sin(chi) from 1 - cos(chi), which FP32
+// would leave with a few digits only.
+__device__ double cos_chi(double s, double U) {
+  if (s < 0.1) return fmax(-1.0, 1.0 + s * log(U));
+  if (s < 6.0) {
+    double ainv, A;
+    if (s < 3.0) {
+      ainv = 0.0056958 + s * (0.9560202 + s * (-0.508139 + s * (0.47913906 + s * (-0.12788975 + s * 0.02389567))));
+      A = 1.0 / ainv;
+    } else {
+      A = 3.0 * exp(-s);
+      ainv = 1.0 / A;
+    }
+    // exp(-A) + 2 U sinh(A) = exp(-A) (1 - U) + U exp(A)
+    const double eA = exp(A);
+    return fmin(1.0, fmax(-1.0, ainv * log((1.0 - U) / eA + U * eA)));
+  }
+  return 2.0 * U - 1.0;
+}
+
+struct CellKinds {
+  double dens[MAXKIND];   // number density [m^-3]
+  double mn13[MAXKIND];   // m n^(-1/3) of each kind present (the low-temperature cap)
+  double ld;              // Debye length of the cell (0: none)
+};
+
+// what a collision reads and writes (the kinds' masses and weights in LDS)
+struct PView {
+  float *u0, *u1, *u2;
+  const uint32_t* pid;
+  uint64_t seed;
+  const double* mass;
+  const double* w;
+};
+
+// One collision of entries a (kind ka) and b (kind kb); updates the slots' momenta.
+__device__ __forceinline__ void collide_pair(const PView& I, const CellKinds& ck, double dt, int pa, int pb, int ka,
+                                             int kb, double n, bool half, uint32_t r, int step) {
+  const double m1 = I.mass[ka], m2 = I.mass[kb];
+  const double q1 = (ka & 1) ? kQE : -kQE, q2 = (kb & 1) ? kQE : -kQE;
+  const D3 u1{I.u0[pa], I.u1[pa], I.u2[pa]};
+  const D3 u2{I.u0[pb], I.u1[pb], I.u2[pb]};
+  const double g1 = sqrt(1.0 + dot(u1, u1)), g2 = sqrt(1.0 + dot(u2, u2));
+  const D3 bc = (1.0 / (m1 * g1 + m2 * g2)) * (m1 * u1 + m2 * u2);
+  const double bc2 = dot(bc, bc);
+  const double gc = 1.0 / sqrt(1.0 - bc2);
+  const D3 b1 = (1.0 / g1) * u1, b2 = (1.0 / g2) * u2;
+  D3 p1s;   // particle 1's momentum in the centre-of-momentum frame [kg m/s]
+  if (bc2 > 0.0)
+    p1s = (m1 * kC) * (u1 + (((gc - 1.0) / bc2 * dot(bc, b1) - gc) * g1) * bc);
+  else
+    p1s = (m1 * kC) * u1;
+  const double g1s = gc * g1 * (1.0 - dot(bc, b1));
+  const double g2s = gc * g2 * (1.0 - dot(bc, b2));
+  const double P = sqrt(dot(p1s, p1s));
+  if (P == 0.0) return;
+  const double mu = m1 * m2 / (m1 + m2);
+  const double v1s = P / (m1 * g1s), v2s = P / (m2 * g2s);
+  const double vrel = (v1s + v2s) / (1.0 + v1s * v2s / (kC * kC));
+  double lnL = 1.0;
+  if (ck.ld > 0.0) {
+    const double ld = ck.ld;
+    const double bcl = fabs(q1 * q2) / (4.0 * kPI * kEPS0 * mu * vrel * vrel);
+    const double bqm = kHBAR / (2.0 * mu * vrel);
+    lnL = fmax(1.0, log(ld / fmax(bcl, bqm)));
+  }
+  const double f = m1 * g1s * m2 * g2s * kC * kC / (P * P) + 1.0;
+  double s = n * dt * lnL * (q1 * q2) * (q1 * q2) /
+             (4.0 * kPI * kEPS0 * kEPS0 * kC * kC * kC * kC * m1 * g1 * m2 * g2) * gc * P / (m1 * g1 + m2 * g2) * f * f;
+  const double cap = 1.6119919540164696 * dt * (m1 + m2) * vrel / fmax(ck.mn13[ka], ck.mn13[kb]);   // (4 pi / 3)^(1/3)
+  s = fmin(s, cap);
+  if (half) s *= 0.5;
+  const uint32_t hi = (uint32_t)ka | ((uint32_t)kb << 8) | (r << 16);
+  const u32x4 w = draw(I.seed, (uint64_t)I.pid[pa] | ((uint64_t)hi << 32), (uint32_t)step, PURPOSE_SCATTER);
+  const double cchi = cos_chi(s, unif(w.x));
+  const double schi = sqrt(fmax(0.0, 1.0 - cchi * cchi));
+  float sphf, cphf;
+  sincosf(6.2831853071795865f * (float)unif(w.y), &sphf, &cphf);
+  const double sphi = sphf, cphi = cphf;
+  const double pperp = sqrt(p1s.x * p1s.x + p1s.y * p1s.y);
+  D3 q;
+  if (pperp > 0.0) {
+    q = {p1s.x * p1s.z / pperp * schi * cphi - p1s.y * P / pperp * schi * sphi + p1s.x * cchi,
+         p1s.y * p1s.z / pperp * schi * cphi + p1s.x * P / pperp * schi * sphi + p1s.y * cchi,
+         -pperp * schi * cphi + p1s.z * cchi};
+  } else {
+    q = {P * schi * cphi, P * schi * sphi, p1s.z * cchi};
+  }
+  D3 p1n, p2n;
+  if (bc2 > 0.0) {
+    const double fq = (gc - 1.0) / bc2 * dot(bc, q);
+    p1n = q + (fq + m1 * kC * g1s * gc) * bc;
+    p2n = (-1.0) * q + (-fq + m2 * kC * g2s * gc) * bc;
+  } else {
+    p1n = q;
+    p2n = (-1.0) * q;
+  }
+  const double w1 = I.w[ka], w2 = I.w[kb], wmax = fmax(w1, w2);
+  const double U3 = unif(w.z);
+  if (U3 < w2 / wmax) {
+    const double sc = 1.0 / (m1 * kC);
+    I.u0[pa] = (float)(sc * p1n.x);
+    I.u1[pa] = (float)(sc * p1n.y);
+    I.u2[pa] = (float)(sc * p1n.z);
+  }
+  if (U3 < w1 / wmax) {
+    const double sc = 1.0 / (m2 * kC);
+    I.u0[pb] = (float)(sc * p2n.x);
+    I.u1[pb] = (float)(sc * p2n.y);
+    I.u2[pb] = (float)(sc * p2n.z);
+  }
+}
+
+// entry order inside a cell: (kind, key, id)
+__device__ __forceinline__ bool before(const uint8_t* kind, const uint32_t* pid, int pa, uint32_t ka, int pb,
+                                       uint32_t kb) {
+  const uint32_t da = kind[pa], db = kind[pb];
+  if (da != db) return da < db;
+  if (ka != kb) return ka < kb;
+  return pid[pa] < pid[pb];
+}
+
+// the collisions of one cell (at least two particles)
+__device__ __noinline__ void collide_cell(const ColBufs& b, const PView& pv, const uint8_t* kind, double vcell,
+                                          const double* smass, const double* sw, int c, int step) {
+  const int e0 = b.cnt[c], e1 = b.cnt[c + 1];
+  // insertion sort of the cell's entries
+  for (int a = e0 + 1; a < e1; ++a) {
+    const int p = b.idx[a];
+    const uint32_t k = b.key[a];
+    int j = a - 1;
+    while (j >= e0 && before(kind, pv.pid, p, k, b.idx[j], b.key[j])) {
+      b.idx[j + 1] = b.idx[j];
+      b.key[j + 1] = b.key[j];
+      --j;
+    }
+    b.idx[j + 1] = p;
+    b.key[j + 1] = k;
+  }
+  // kinds present: their entry ranges, densities and temperatures
+  int kfirst[MAXKIND], kcount[MAXKIND];
+  CellKinds ck;
+  for (int k = 0; k < MAXKIND; ++k) {
+    kcount[k] = 0;
+    kfirst[k] = 0;
+    ck.dens[k] = 0.0;
+  }
+  double ke[MAXKIND];
+  for (int k = 0; k < MAXKIND; ++k) ke[k] = 0.0;
+  for (int a = e0; a < e1; ++a) {
+    const int p = b.idx[a];
+    const int k = kind[p];
+    if (kcount[k] == 0) kfirst[k] = a;
+    ++kcount[k];
+    const double ux = pv.u0[p], uy = pv.u1[p], uz = pv.u2[p];
+    ke[k] += (sqrt(1.0 + (ux * ux + uy * uy + uz * uz)) - 1.0) * smass[k] * kC * kC;
+  }
+  double inv_ld2 = 0.0;
+  for (int k = 0; k < MAXKIND; ++k) {
+    ck.mn13[k] = 0.0;
+    if (!kcount[k]) continue;
+    ck.dens[k] = kcount[k] * sw[k] / vcell;
+    ck.mn13[k] = smass[k] / cbrt(ck.dens[k]);
+    const double T = 2.0 / 3.0 * ke[k] / kcount[k];
+    if (T > 0.0) inv_ld2 += ck.dens[k] * kQE * kQE / (kEPS0 * T);
+  }
+  ck.ld = inv_ld2 > 0.0 ? 1.0 / sqrt(inv_ld2) : 0.0;
+  // like kinds
+  for (int k = 0; k < MAXKIND; ++k) {
+    const int N = kcount[k];
+    if (N < 2) continue;
+    const int f = kfirst[k];
+    const double n = ck.dens[k];
+    int start = 0;
+    if (N & 1) {
+      collide_pair(pv, ck, b.dt, b.idx[f], b.idx[f + 1], k, k, n, true, 0, step);
+      collide_pair(pv, ck, b.dt, b.idx[f + 1], b.idx[f + 2], k, k, n, true, 0, step);
+      collide_pair(pv, ck, b.dt, b.idx[f + 2], b.idx[f], k, k, n, true, 0, step);
+      start = 3;
+    }
+    for (int a = start; a + 1 < N; a += 2) collide_pair(pv, ck, b.dt, b.idx[f + a], b.idx[f + a + 1], k, k, n, false, 0, step);
+  }
+  // unlike kinds
+  for (int ka = 0; ka < MAXKIND; ++ka) {
+    if (!kcount[ka]) continue;
+    for (int kb = ka + 1; kb < MAXKIND; ++kb) {
+      if (!kcount[kb]) continue;
+      const int Na = kcount[ka], Nb = kcount[kb];
+      const int nmin = Na < Nb ? Na : Nb, nmax = Na < Nb ? Nb : Na;
+      const double n = nmin * fmax(sw[ka], sw[kb]) / vcell;
+      for (int i = 0; i < nmax; ++i)
+        collide_pair(pv, ck, b.dt, b.idx[kfirst[ka] + i % Na], b.idx[kfirst[kb] + i % Nb], ka, kb, n, false,
+                     (uint32_t)(i / nmin), step);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_col_cells(const Inst I, ColBufs b, int step) {
+  __shared__ double smass[MAXKIND], sw[MAXKIND];
+  if (threadIdx.x < MAXKIND) {
+    smass[threadIdx.x] = I.kmass[threadIdx.x];
+    sw[threadIdx.x] = I.kw[threadIdx.x];
+  }
+  __syncthreads();
+  const PView pv{I.pu0, I.pu1, I.pu2, I.pid, I.seed, smass, sw};
+  const int nact = *b.nactive;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nact; q += gridDim.x * blockDim.x)
+    collide_cell(b, pv, I.pkind, I.vcell, smass, sw, b.active[q], step);
+}
+
+}  // namespace
+
+int col_scan_blocks(int n) { return (n + SCAN_B - 1) / SCAN_B; }
+
+void launch_collide(const Inst& I, const ColBufs& b, int step, hipStream_t s, Stamp st) {
+  const int n = b.ncell + 1;
+  const int nb = col_scan_blocks(n);
+  // grid-stride passes over the charged slots: one thread per slot up to 4096 blocks
+  const int slots = 256 * std::min(4096, std::max(1, (I.capacity + 255) / 256));
+  if (st.start)
+    hipExtLaunchKernelGGL(k_col_clear, dim3((n + 255) / 256), dim3(256), 0, s, st.start, nullptr, 0, b);
+  else
+    hipLaunchKernelGGL(k_col_clear, dim3((n + 255) / 256), dim3(256), 0, s, b);
+  hipLaunchKernelGGL(k_col_count, dim3(slots / 256), dim3(256), 0, s, I, b);
+  hipLaunchKernelGGL(k_col_scan_local, dim3(nb), dim3(SCAN_B), 0, s, b, n);
+  hipLaunchKernelGGL(k_col_scan_top, dim3(1), dim3(SCAN_B), 0, s, b, nb);
+  hipLaunchKernelGGL(k_col_scan_add, dim3(nb), dim3(SCAN_B), 0, s, b, n);
+  hipLaunchKernelGGL(k_col_fill, dim3(slots / 256), dim3(256), 0, s, I, b, step);
+  // one thread per colliding cell (at most half the slots), grid-stride
+  const int cb = std::min(4096, std::max(1, (I.capacity / 2 + 255) / 256));
+  if (st.stop)
+    hipExtLaunchKernelGGL(k_col_cells, dim3(cb), dim3(256), 0, s, nullptr, st.stop, 0, I, b, step);
+  else
+    hipLaunchKernelGGL(k_col_cells, dim3(cb), dim3(256), 0, s, I, b, step);
+}
+
+}  // namespace pic

@@ -57,6 +57,24 @@ void launch_ionize(const Group& g, int D, int order, hipStream_t s, Stamp st = {
 // of a step whose slot is nwin - 1)
 void launch_win_rebuild(const Inst& I, int64_t wsz, hipStream_t s, hipEvent_t stop = nullptr);
 void launch_advance(Inst* insts, int n, hipStream_t s);   // batch: step counters + 1
+
+// Binary collisions (a single run): device work arrays over the box cells
+// (ncell = nx ny nz) and the charged slots.
+struct ColBufs {
+  int* cnt;       // ncell + 1: particles per cell, then (scanned) each cell's first index
+  int* fill;      // ncell: particles placed per cell
+  int* bsum;      // col_scan_blocks(ncell + 1) + 1: block sums of the scan
+  int* idx;       // capacity: slots ordered by cell
+  uint32_t* key;  // capacity: pairing key of each entry of idx
+  int* active;    // capacity / 2 + 1: the cells holding at least two particles
+  int* nactive;   // their number
+  int ncell;
+  double dt;      // time step [s]
+};
+int col_scan_blocks(int n);
+// collisions of the step whose index after ionization is `step` (the state
+// after the step's push and ionization), on stream s
+void launch_collide(const Inst& I, const ColBufs& b, int step, hipStream_t s, Stamp st = {});
 int field_tiles(int D, int variant, int Px, int Py, int Pz);   // blocks of the field launch
 // field tile shapes of a run: the tiled shapes, plus the z-marching update in
 // 3D when y and z are periodic

@@ -68,6 +68,9 @@ struct Layout {
   // with an oscillator (lx0 >= lx1: none, nothing allocated)
   size_t o_Q[2][3], o_Kp[2][3], o_lor_half, o_lor_node;
   int lx0, lx1;
+  // binary collisions: per-cell counts and starts, fill counters, scan block
+  // sums, slots ordered by cell and their pairing keys (empty without collisions)
+  size_t o_ccnt, o_cfill, o_cbsum, o_cidx, o_ckey, o_cact;
   size_t o_ring, o_suffix, o_prefix, o_A;
   size_t o_no[3], o_alive, o_death, o_mcell;
   size_t o_pcell, o_po[3], o_pu[3], o_pkind, o_pid;
@@ -215,6 +218,17 @@ pic_status plan(const pic_config* cfg, const Canon& c, const std::vector<TableHo
   L->o_off = take(sizeof(int) * 32);   // 4 phases x {0, blocks}; field shapes x {0, blocks}; the sort
   L->o_sig = take(sizeof(float) * 2 * MAXMAT);
   L->o_probe = take(0);
+  {
+    const int64_t nbox = c.collide ? c.n[0] * c.n[1] * c.n[2] : 0;
+    if (nbox >= (int64_t)1 << 30) return PIC_E_INVAL;   // cell indices and their scan are int
+    const int64_t cap = c.collide ? L->capacity : 0;
+    L->o_ccnt = take(sizeof(int) * (size_t)(nbox + 1));
+    L->o_cfill = take(sizeof(int) * (size_t)nbox);
+    L->o_cbsum = take(sizeof(int) * (size_t)(c.collide ? col_scan_blocks((int)nbox + 1) + 1 : 0));
+    L->o_cidx = take(sizeof(int) * (size_t)cap);
+    L->o_ckey = take(sizeof(uint32_t) * (size_t)cap);
+    L->o_cact = take(sizeof(int) * (size_t)(c.collide ? cap / 2 + 2 : 0));   // cells, then the count
+  }
   L->total = o;
   return PIC_OK;
 }
@@ -232,6 +246,7 @@ struct pic_ctx {
   hipStream_t stream = nullptr;
   Inst h{};
   Inst* d_inst = nullptr;
+  ColBufs col{};   // binary collisions (when the run has them)
   int* d_off = nullptr;   // [0, nb_push, 0, nb_cell, 0, 1, 0, nb_neut], then {0, tiles} per field shape
   int* d_off_fields = nullptr;   // block offsets of the field launch in use
   int nb_push = 0, nb_cell = 0, nb_win = 0, nb_neut = 0, nb_sort = 0;
@@ -524,6 +539,8 @@ void enqueue_step(pic_ctx* c) {
   }
   if (c->imax_every > 0 && (c->step + 1) % c->imax_every == 0) launch_imax(imax_args(c), c->d_imax, s);
   timed(c, 2, [&](Stamp st) { launch_ionize(single(c, 3, c->nb_neut), D, order, s, st); });
+  if (c->canon.collide)
+    timed(c, 4, [&](Stamp st) { launch_collide(c->h, c->col, (int)(c->step + 1), s, st); });
   if (c->track_every > 0 && (c->step + 1) % c->track_every == 0)
     launch_tracks(c->d_inst, D, (int)c->L.capacity, c->track_thr, (int)(c->step + 1),
                   (TrackRec*)((unsigned char*)c->d_tracks + 256), (unsigned long long*)c->d_tracks,
@@ -837,6 +854,18 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
   }
   I.ie_half = (const float*)devp(c, L.o_ie_half);
   I.ie_node = (const float*)devp(c, L.o_ie_node);
+  c->col = ColBufs{};
+  if (K.collide) {
+    c->col.cnt = (int*)devp(c, L.o_ccnt);
+    c->col.fill = (int*)devp(c, L.o_cfill);
+    c->col.bsum = (int*)devp(c, L.o_cbsum);
+    c->col.idx = (int*)devp(c, L.o_cidx);
+    c->col.key = (uint32_t*)devp(c, L.o_ckey);
+    c->col.active = (int*)devp(c, L.o_cact);
+    c->col.nactive = c->col.active + L.capacity / 2 + 1;
+    c->col.ncell = (int)(K.n[0] * K.n[1] * K.n[2]);
+    c->col.dt = K.dt;
+  }
   I.lx0 = L.lx0;
   I.lx1 = L.lx1;
   for (int par = 0; par < 2; ++par)
@@ -1925,7 +1954,7 @@ pic_status pic_batch_set_graph(pic_batch* b, int32_t on) {
 int64_t pic_batch_graph_replays(const pic_batch* b) { return b ? b->replays : 0; }
 
 pic_status pic_batch_add(pic_batch* b, pic_ctx* c) {
-  if (!b || !c) return PIC_E_INVAL;
+  if (!b || !c || c->canon.collide) return PIC_E_INVAL;
   for (pic_ctx* m : b->members)
     if (m == c) return PIC_E_INVAL;
   if (b->members.empty()) b->stream = c->stream;

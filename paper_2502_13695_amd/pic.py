@@ -64,7 +64,7 @@ class Config(C.Structure):
                 ("ppc", C.c_int32), ("shape_order", C.c_int32), ("T_K", C.c_double),
                 ("keldysh_terms", C.c_int32), ("keldysh_tol_bits", C.c_int32), ("seed", C.c_uint64),
                 ("laser", Laser), ("particle_capacity", C.c_int64), ("preionize_eV", C.c_double),
-                ("stream", C.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN),
+                ("collisions", C.c_int32), ("reserved2", C.c_int32), ("stream", C.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN),
                 ("alloc_user", C.c_void_p)]
 
 
@@ -218,6 +218,7 @@ def make_config(cfg, stream=None, alloc=None, free=None):
     c.laser.pol_axis = int(L.get("pol_axis", 1))
     c.particle_capacity = int(cfg.get("particle_capacity", 0))
     c.preionize_eV = float(cfg.get("preionize_eV", 0.0))
+    c.collisions = int(bool(cfg.get("collisions", False)))
     c.stream = stream
     if alloc is not None:
         c.alloc = alloc
