@@ -404,6 +404,23 @@ def test_run_3d_mirror_periodic(P, field_tile, monkeypatch):
     ctx.close()
 
 
+@pytest.mark.parametrize("case", ["1d", "2d", "3d"])
+def test_run_linear_shape(P, case):
+    """Whole runs with the order-1 (linear, cloud-in-cell) particle shape:
+    gather, deposit and the neutrals' amplitude gather all take the two-node
+    stencil."""
+    if case == "1d":
+        cfg, n = W.config_1d(hi=True, ppc=10, nsteps=1400), 1400
+    elif case == "2d":
+        cfg, n = W.config_2d(nx=192, ny=48, nsteps=520, ppc=2, peak=3e14, slab_cells=12, waist=0.6e-6), 520
+    else:
+        cfg, n = W.config_3d(nx=96, ny=8, nz=8, nsteps=380, ppc=8, fluence=1.0, front=24), 380
+    cfg["shape_order"] = 1
+    ctx, sim = _run_both(P, cfg, n)
+    _compare_run(P, ctx, sim, min_events=20, name=f"run_{case}_order1")
+    ctx.close()
+
+
 def test_marching_field_update_matches_tiled_bitwise(P, monkeypatch):
     """The z-marching 3D update (periodic y and z) against the tiled update:
     random fields in a box whose y and z extents leave partial tiles and
