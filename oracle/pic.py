@@ -38,6 +38,8 @@ it changes; the inherited parts follow the textbook method named alongside:
   faces of the box one cell inside the outflow faces (the field-side budget).
 * Binary Coulomb collisions among the charged particles (Sec. 2.2, Eq. 4;
   optional, after ionization): oracle/collide.py.
+* Impact ionization by hot electrons (Keldysh's rate, the paper's future work,
+  Sec. 2.2; optional per material, after the collisions): oracle/impact.py.
 * Monte-Carlo single ionization of immobile neutral molecule macroparticles
   with the per-molecule rate W/n0, probability 1 - exp(-W dt / n0) per step,
   the whole macroparticle converting into one electron (m_e*, Sec. 3.2) and
@@ -73,7 +75,7 @@ from collections import deque
 import numpy as np
 
 from .constants import C, KB, EPS0, QE
-from . import collide, keldysh, philox
+from . import collide, impact, keldysh, philox
 from .problem import Problem
 
 G = 3  # guard layers on each side of every present dimension
@@ -689,6 +691,7 @@ class Sim:
         self.ionize(n + 1)
         if self.P.collisions:
             collide.collide(self, n + 1)
+        impact.impact(self, n + 1)
         self.step_index = n + 1
         if self.track_every > 0 and (n + 1) % self.track_every == 0:
             self._record_tracks(n + 1)

@@ -76,6 +76,8 @@ class Material:
         pm = float(m.get("pos_mass_kg", 0.0))
         self.pos_mass_kg = pm if pm > 0 else self.mol_mass_kg
         self.e_mass_kg = self.me_star * ME
+        # impact ionization rate constant [1/s] (Keldysh's impact rate; 0 = none)
+        self.impact_rate = float(m.get("impact_rate_s", 0.0))
         # single-pole Lorentz response (resonance wavelength > 0), else static
         self.lor_lambda = float(m.get("lorentz_lambda_m", 0.0))
         self.lor_gamma = float(m.get("lorentz_gamma_s", 0.0))

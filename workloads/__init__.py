@@ -9,7 +9,8 @@ Configuration dictionary (both sides read the same keys):
   ndim, n[ndim] (cells), dx[ndim] (m), cfl, nsteps, transverse_bc
   ("outflow" | "periodic"), materials (list of dicts: gap_eV, n_index,
   density_gcc, molar_mass_gmol, me_star, mh_star, pos_mass_kg, and for a
-  single-pole Lorentz response lorentz_lambda_m, eps_inf, lorentz_gamma_s), layers (list
+  single-pole Lorentz response lorentz_lambda_m, eps_inf, lorentz_gamma_s; for
+  impact ionization impact_rate_s), layers (list
   of (material, lo_m, hi_m) half-open along x), ppc, T_K, shape_order,
   keldysh_terms, seed, laser (lambda_m, fwhm_s, peak_Wcm2 | fluence_Jcm2,
   waist_m, t_peak_s, cep_rad, envelope "gauss" | "sin2", pol_axis),
@@ -79,6 +80,11 @@ def silica_dispersive():
 
 def high_index_dispersive():
     return lorentz(high_index(), HFO2_UV[0], eps_inf=HFO2_UV[1])
+
+
+def with_impact(mat, rate_s):
+    """The material with impact ionization at Keldysh's rate constant rate_s [1/s]."""
+    return dict(mat, impact_rate_s=rate_s)
 
 
 def layer_stack(mats, n_indices, x0, lam=LAMBDA, first_half_wave=False):
