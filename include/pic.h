@@ -72,10 +72,21 @@ typedef struct pic_batch pic_batch;
  * 1/eps_inf.  pic_init returns PIC_E_INVAL when the coupled update is unstable
  * at the time step (lossless von Neumann bound: c < 4 and sum_d C_d^2 <=
  * eps_inf - c deps / (4 - c), with the vertex condition of that bound).
- * lorentz_lambda_m = 0: static eps_r = n^2 (eps_inf and lorentz_gamma_s unused). */
+ * lorentz_lambda_m = 0: static eps_r = n^2 (eps_inf and lorentz_gamma_s unused).
+ *
+ * Impact ionization (the paper's future work, Sec. 2.2: Keldysh's impact
+ * rate): impact_rate_s = P > 0 lets every electron of this material in a cell
+ * of this material ionize, once per step at most, with probability
+ * 1 - exp(-w dt), w = P (eps / E_th - 1)^2 above E_th = E_g (1 + 2 mu)/(1 + mu),
+ * mu = m_e* / m_h*, eps its kinetic energy.  The decisions of a cell's electrons
+ * are taken in a fixed order keyed by their ids; an event consumes the cell's
+ * alive neutral of lowest index (a photoionization-like birth at its position)
+ * and takes E_g from the impacting electron.  0: none; negative: PIC_E_INVAL.
+ * Runs with impact ionization cannot join a batch. */
 typedef struct {
   double gap_eV, n_index, density_gcc, molar_mass_gmol, me_star, mh_star, pos_mass_kg;
   double lorentz_lambda_m, eps_inf, lorentz_gamma_s;
+  double impact_rate_s;
 } pic_material;
 
 /* Optical region (Sec. 2.3): material `material` fills lo_m <= x < hi_m across

@@ -207,6 +207,7 @@ pic_status canonicalize(const pic_config* cfg, Canon* c) {
   c->I0 = L.fluence_Jcm2 > 0 ? L.fluence_Jcm2 * 1e4 / c->env2 : L.peak_Wcm2 * 1e4;
   c->E0 = std::sqrt(2.0 * c->I0 / (kC * kEPS0));
   c->nmat = cfg->nmat;
+  c->impact = false;
   c->vcell = 1.0;
   for (int d = 0; d < c->D; ++d) c->vcell *= c->dx[d];
   c->ppc = cfg->ppc;
@@ -255,6 +256,13 @@ pic_status canonicalize(const pic_config* cfg, Canon* c) {
       mc.lor[2] = (float)(cc * deps);
     }
     mc.ie = (float)(1.0 / mc.eps_inf);
+    if (!(M.impact_rate_s >= 0)) return PIC_E_INVAL;
+    mc.impact_P = M.impact_rate_s;
+    {
+      const double mu = M.me_star / M.mh_star;
+      mc.impact_th = M.gap_eV * (1.0 + 2.0 * mu) / (1.0 + mu) * kQE;
+    }
+    if (mc.impact_P > 0) c->impact = true;
     if (M.lorentz_lambda_m > 0) {
       double s2max = 0.0;
       for (int d = 0; d < c->D; ++d) s2max += (double)c->C[d] * (double)c->C[d];

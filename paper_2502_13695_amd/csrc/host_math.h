@@ -14,6 +14,8 @@ struct MatC {
   float ie;                 // 1/eps_r (static) or 1/eps_inf (Lorentz)
   double lam0, gamma, eps_inf, deps;   // Lorentz pole (lam0 = 0: static)
   float lor[3];             // oscillator update (a, c, c deps); zeros when static
+  double impact_P;          // impact-ionization rate constant [1/s] (0: none)
+  double impact_th;         // its threshold energy [J]
 };
 
 // Von Neumann stability of the Yee update coupled to the explicit Lorentz
@@ -26,6 +28,7 @@ struct Canon {
   double dx[3];
   bool per[3];
   bool collide;   // binary collisions every step
+  bool impact;    // impact ionization (some material has a rate constant)
   double dt;
   float C[3], kmur[3];
   int nwin;

@@ -33,7 +33,7 @@ namespace pic {
 
 namespace {
 
-constexpr uint32_t PURPOSE_PAIR = 7, PURPOSE_SCATTER = 8;
+constexpr uint32_t PURPOSE_PAIR = 7, PURPOSE_SCATTER = 8, PURPOSE_IMPACT = 9;
 constexpr double kC = 299792458.0, kEPS0 = 8.8541878128e-12, kHBAR = 1.054571817e-34,
                  kQE = 1.602176634e-19, kPI = 3.14159265358979323846;
 constexpr int SCAN_B = 1024;   // elements per block of the cell scan
@@ -56,13 +56,21 @@ __global__ void k_col_clear(ColBufs b) {
   if (i == 0) *b.nactive = 0;
 }
 
-// counts per cell; a cell's second particle lists the cell as one that collides
+// counts per cell; the particle that makes a cell eligible lists it (the
+// first in a cell of a material with impact ionization, else the second when
+// collisions are on)
 __global__ void k_col_count(const Inst I, ColBufs b) {
   const int n = live_slots(I);
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x)
     if (I.pkind[p] != 0xFF) {
-      const int c = box_cell(I, I.pcell[p]);
-      if (atomicAdd(&b.cnt[c], 1) == 1) b.active[atomicAdd(b.nactive, 1)] = c;
+      const uint32_t pc = I.pcell[p];
+      const int c = box_cell(I, pc);
+      const int old = atomicAdd(&b.cnt[c], 1);
+      int i, j, k;
+      unpack_cell(I.D, pc, i, j, k);
+      const int m = I.mat_cell[i];
+      const bool imp = b.impact && m >= 0 && b.imp_P[m] > 0.0;
+      if (imp ? old == 0 : (b.collide && old == 1)) b.active[atomicAdd(b.nactive, 1)] = c;
     }
 }
 
@@ -165,6 +173,22 @@ __device__ double cos_chi(double s, double U) {
   return 2.0 * U - 1.0;
 }
 
+// what the impact pass writes besides the momenta: neutrals and births
+struct ImpView {
+  uint32_t* alive;
+  int* death;
+  const float *no0, *no1, *no2;
+  uint32_t* pcell;
+  uint32_t *po0, *po1, *po2;
+  uint8_t* pkind;
+  int* pcount;
+  unsigned* health;
+  unsigned long long* nevents;
+  const float* ksig;
+  const signed char* mat_cell;
+  int capacity, D, nx, ny, ppc;
+};
+
 struct CellKinds {
   double dens[MAXKIND];   // number density [m^-3]
   double mn13[MAXKIND];   // m n^(-1/3) of each kind present (the low-temperature cap)
@@ -174,7 +198,7 @@ struct CellKinds {
 // what a collision reads and writes (the kinds' masses and weights in LDS)
 struct PView {
   float *u0, *u1, *u2;
-  const uint32_t* pid;
+  uint32_t* pid;
   uint64_t seed;
   const double* mass;
   const double* w;
@@ -267,9 +291,71 @@ __device__ __forceinline__ bool before(const uint8_t* kind, const uint32_t* pid,
   return pid[pa] < pid[pb];
 }
 
-// the collisions of one cell (at least two particles)
-__device__ __noinline__ void collide_cell(const ColBufs& b, const PView& pv, const uint8_t* kind, double vcell,
-                                          const double* smass, const double* sw, int c, int step) {
+// Impact ionization in cell c (its entries ordered): each electron of the
+// cell's material decides once; an event takes the cell's alive neutral of
+// lowest index, the electron pays the gap, the pair is born at the neutral.
+__device__ void impact_cell(const ColBufs& b, const PView& pv, const ImpView& v, const uint8_t* kind,
+                            const double* smass, int c, int e0, int e1, int step) {
+  const int i = c % v.nx, j = (c / v.nx) % v.ny, k = c / (v.nx * v.ny);
+  const int m = v.mat_cell[i];
+  if (m < 0 || !(b.imp_P[m] > 0.0)) return;
+  const int64_t j0 = ((int64_t)(j + v.ny * k) * b.nmx + b.mrank[i]) * v.ppc;
+  int next = 0;   // neutrals below it are dead or taken
+  for (int a = e0; a < e1; ++a) {
+    const int p = b.idx[a];
+    const int kd = kind[p];
+    if (kd != 2 * m) continue;
+    const double ux = pv.u0[p], uy = pv.u1[p], uz = pv.u2[p];
+    const double uu = ux * ux + uy * uy + uz * uz;
+    const double mc2 = smass[kd] * kC * kC;
+    const double ke = (sqrt(1.0 + uu) - 1.0) * mc2;
+    const double x = ke / b.imp_th[m] - 1.0;
+    if (!(x > 0.0)) continue;
+    const double prob = -expm1(-b.imp_P[m] * x * x * b.dt);
+    const uint32_t w = draw(pv.seed, (uint64_t)pv.pid[p] | ((uint64_t)kd << 32), (uint32_t)step, PURPOSE_IMPACT).x;
+    if (!((double)w + 0.5 < prob * 4294967296.0)) continue;
+    while (next < v.ppc && !((v.alive[(j0 + next) >> 5] >> ((j0 + next) & 31)) & 1u)) ++next;
+    if (next >= v.ppc) continue;
+    const int64_t jn = j0 + next;
+    const uint64_t id = (uint64_t)c * (uint64_t)v.ppc + (uint64_t)next;
+    ++next;
+    atomicAnd(&v.alive[jn >> 5], ~(1u << (jn & 31)));
+    v.death[jn] = step;
+    atomicAdd(&v.nevents[(blockIdx.x & 7) * 32 + m], 1ull);
+    // the impacting electron pays the gap, direction kept
+    const double g2 = 1.0 + (ke - b.gap[m]) / mc2;
+    const double sc = sqrt(g2 * g2 - 1.0) / sqrt(uu);
+    pv.u0[p] = (float)(sc * ux);
+    pv.u1[p] = (float)(sc * uy);
+    pv.u2[p] = (float)(sc * uz);
+    const int q = atomicAdd(v.pcount, 2);
+    if (q + 2 > v.capacity) {
+      atomicOr(v.health, HEALTH_CAPACITY);
+      continue;
+    }
+    float bx, by, bz;
+    maxwell(pv.seed, id, PURPOSE_VEL, v.ksig[m], bx, by, bz);
+    const uint32_t pc = pack_cell(v.D, i, j, k);
+    for (int s = 0; s < 2; ++s) {
+      v.pcell[q + s] = pc;
+      v.po0[q + s] = off_fix(v.no0[jn]);
+      if (v.D >= 2) v.po1[q + s] = off_fix(v.no1[jn]);
+      if (v.D >= 3) v.po2[q + s] = off_fix(v.no2[jn]);
+      pv.u0[q + s] = bx;
+      pv.u1[q + s] = by;
+      pv.u2[q + s] = bz;
+      v.pkind[q + s] = (uint8_t)(2 * m + s);
+      pv.pid[q + s] = (uint32_t)id;
+    }
+  }
+}
+
+__device__ void collide_sorted(const ColBufs& b, const PView& pv, const uint8_t* kind, double vcell,
+                               const double* smass, const double* sw, int e0, int e1, int step);
+
+// the collisions (at least two particles) and the impact ionization of one cell
+__device__ __noinline__ void collide_cell(const ColBufs& b, const PView& pv, const ImpView& iv, const uint8_t* kind,
+                                          double vcell, const double* smass, const double* sw, int c, int step) {
   const int e0 = b.cnt[c], e1 = b.cnt[c + 1];
   // insertion sort of the cell's entries
   for (int a = e0 + 1; a < e1; ++a) {
@@ -284,6 +370,13 @@ __device__ __noinline__ void collide_cell(const ColBufs& b, const PView& pv, con
     b.idx[j + 1] = p;
     b.key[j + 1] = k;
   }
+  if (b.collide && e1 - e0 >= 2) collide_sorted(b, pv, kind, vcell, smass, sw, e0, e1, step);
+  if (b.impact) impact_cell(b, pv, iv, kind, smass, c, e0, e1, step);
+}
+
+// the collisions of a cell's ordered entries [e0, e1)
+__device__ void collide_sorted(const ColBufs& b, const PView& pv, const uint8_t* kind, double vcell,
+                               const double* smass, const double* sw, int e0, int e1, int step) {
   // kinds present: their entry ranges, densities and temperatures
   int kfirst[MAXKIND], kcount[MAXKIND];
   CellKinds ck;
@@ -350,9 +443,11 @@ __global__ __launch_bounds__(256) void k_col_cells(const Inst I, ColBufs b, int 
   }
   __syncthreads();
   const PView pv{I.pu0, I.pu1, I.pu2, I.pid, I.seed, smass, sw};
+  const ImpView iv{I.alive, I.death, I.no0, I.no1, I.no2, I.pcell, I.po0, I.po1, I.po2, I.pkind, I.pcount,
+                   I.health, I.nevents, I.ksig, I.mat_cell, I.capacity, I.D, I.nx, I.ny, I.ppc};
   const int nact = *b.nactive;
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nact; q += gridDim.x * blockDim.x)
-    collide_cell(b, pv, I.pkind, I.vcell, smass, sw, b.active[q], step);
+    collide_cell(b, pv, iv, I.pkind, I.vcell, smass, sw, b.active[q], step);
 }
 
 }  // namespace
@@ -373,8 +468,8 @@ void launch_collide(const Inst& I, const ColBufs& b, int step, hipStream_t s, St
   hipLaunchKernelGGL(k_col_scan_top, dim3(1), dim3(SCAN_B), 0, s, b, nb);
   hipLaunchKernelGGL(k_col_scan_add, dim3(nb), dim3(SCAN_B), 0, s, b, n);
   hipLaunchKernelGGL(k_col_fill, dim3(slots / 256), dim3(256), 0, s, I, b, step);
-  // one thread per colliding cell (at most half the slots), grid-stride
-  const int cb = std::min(4096, std::max(1, (I.capacity / 2 + 255) / 256));
+  // one thread per listed cell (at most one per slot), grid-stride
+  const int cb = std::min(4096, std::max(1, (I.capacity + 255) / 256));
   if (st.stop)
     hipExtLaunchKernelGGL(k_col_cells, dim3(cb), dim3(256), 0, s, nullptr, st.stop, 0, I, b, step);
   else

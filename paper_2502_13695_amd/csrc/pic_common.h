@@ -43,6 +43,28 @@ __host__ __device__ inline u32x4 draw(uint64_t seed, uint64_t id, uint32_t step,
                     (uint32_t)seed, (uint32_t)(seed >> 32));
 }
 
+// Thermal velocity u = gamma v / c of a particle born from neutral `id`: three
+// normal components of spread sig from one Philox block (counter (id, 0,
+// purpose)).  Box-Muller in FP64, rounded once at the end: in FP32 the uniform
+// next to 1 keeps only 24 bits of 1 - u, so -2 log u (hence a small radius)
+// would carry relative errors up to 1e-3.
+__device__ __forceinline__ void maxwell(uint64_t seed, uint64_t id, uint32_t purpose, float sig, float& ux,
+                                         float& uy, float& uz) {
+  const u32x4 w = draw(seed, id, 0u, purpose);
+  const double u1 = ((double)w.x + 0.5) * 0x1p-32;
+  const double u2 = ((double)w.y + 0.5) * 0x1p-32;
+  const double u3 = ((double)w.z + 0.5) * 0x1p-32;
+  const double u4 = ((double)w.w + 0.5) * 0x1p-32;
+  const double r1 = sqrt(-2.0 * log(u1)), r2 = sqrt(-2.0 * log(u3));
+  const double tp = 6.283185307179586476925;
+  double s2, c2;
+  sincos(tp * u2, &s2, &c2);
+  const double sg = (double)sig;
+  ux = (float)(sg * (r1 * c2));
+  uy = (float)(sg * (r1 * s2));
+  uz = (float)(sg * (r2 * cos(tp * u4)));
+}
+
 // ---------------------------------------------------------- Keldysh table
 // Per material: P(A) = 1 - exp(-r(A)), r = W(A) dt / n0.  Between consecutive
 // channel closings (x(A) crossing an integer, Eq. 1) the rate is

@@ -66,14 +66,25 @@ struct ColBufs {
   int* bsum;      // col_scan_blocks(ncell + 1) + 1: block sums of the scan
   int* idx;       // capacity: slots ordered by cell
   uint32_t* key;  // capacity: pairing key of each entry of idx
-  int* active;    // capacity / 2 + 1: the cells holding at least two particles
+  int* active;    // the cells that take part (collisions: at least two particles;
+                  // impact ionization: at least one), at most capacity + 1
   int* nactive;   // their number
   int ncell;
   double dt;      // time step [s]
+  int collide;    // binary collisions
+  int impact;     // impact ionization
+  // impact ionization: per material the rate constant [1/s], threshold [J]
+  // and gap [J]; per cell x index the rank among the material x cells (-1:
+  // none) and their count, so cell (i, j, k) holds neutrals from
+  // ((j + ny k) nmx + mrank[i]) ppc on
+  double imp_P[MAXMAT], imp_th[MAXMAT], gap[MAXMAT];
+  const int* mrank;
+  int nmx;
 };
 int col_scan_blocks(int n);
-// collisions of the step whose index after ionization is `step` (the state
-// after the step's push and ionization), on stream s
+// collisions and impact ionization of the step whose index after
+// photoionization is `step` (the state after the step's push and
+// photoionization), on stream s
 void launch_collide(const Inst& I, const ColBufs& b, int step, hipStream_t s, Stamp st = {});
 int field_tiles(int D, int variant, int Px, int Py, int Pz);   // blocks of the field launch
 // field tile shapes of a run: the tiled shapes, plus the z-marching update in

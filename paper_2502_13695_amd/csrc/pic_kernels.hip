@@ -2282,26 +2282,6 @@ __global__ __launch_bounds__(TPB) void k_win_rebuild(const Inst I) {
 }
 
 // ------------------------------------------------------------- ionization
-__device__ __forceinline__ void maxwell(uint64_t seed, uint64_t id, uint32_t purpose, float sig,
-                                        float& ux, float& uy, float& uz) {
-  // Box-Muller in FP64, rounded once at the end: in FP32 the uniform next to
-  // 1 keeps only 24 bits of 1 - u, so -2 log u (hence a small radius) would
-  // carry relative errors up to 1e-3
-  const u32x4 w = draw(seed, id, 0u, purpose);
-  const double u1 = ((double)w.x + 0.5) * 0x1p-32;
-  const double u2 = ((double)w.y + 0.5) * 0x1p-32;
-  const double u3 = ((double)w.z + 0.5) * 0x1p-32;
-  const double u4 = ((double)w.w + 0.5) * 0x1p-32;
-  const double r1 = sqrt(-2.0 * log(u1)), r2 = sqrt(-2.0 * log(u3));
-  const double tp = 6.283185307179586476925;
-  double s2, c2;
-  sincos(tp * u2, &s2, &c2);
-  const double sg = (double)sig;
-  ux = (float)(sg * (r1 * c2));
-  uy = (float)(sg * (r1 * s2));
-  uz = (float)(sg * (r2 * cos(tp * u4)));
-}
-
 template <class IT>
 __device__ __forceinline__ int64_t div_ppc(const IT& I, int64_t j) {
   return I.ppc == 1 ? j : (int64_t)__umul64hi((uint64_t)j, I.ppc_magic);

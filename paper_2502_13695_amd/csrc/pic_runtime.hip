@@ -70,7 +70,7 @@ struct Layout {
   int lx0, lx1;
   // binary collisions: per-cell counts and starts, fill counters, scan block
   // sums, slots ordered by cell and their pairing keys (empty without collisions)
-  size_t o_ccnt, o_cfill, o_cbsum, o_cidx, o_ckey, o_cact;
+  size_t o_ccnt, o_cfill, o_cbsum, o_cidx, o_ckey, o_cact, o_mrank;
   size_t o_ring, o_suffix, o_prefix, o_A;
   size_t o_no[3], o_alive, o_death, o_mcell;
   size_t o_pcell, o_po[3], o_pu[3], o_pkind, o_pid;
@@ -219,15 +219,18 @@ pic_status plan(const pic_config* cfg, const Canon& c, const std::vector<TableHo
   L->o_sig = take(sizeof(float) * 2 * MAXMAT);
   L->o_probe = take(0);
   {
-    const int64_t nbox = c.collide ? c.n[0] * c.n[1] * c.n[2] : 0;
+    // binary collisions and impact ionization share the per-step cell binning
+    const bool on = c.collide || c.impact;
+    const int64_t nbox = on ? c.n[0] * c.n[1] * c.n[2] : 0;
     if (nbox >= (int64_t)1 << 30) return PIC_E_INVAL;   // cell indices and their scan are int
-    const int64_t cap = c.collide ? L->capacity : 0;
+    const int64_t cap = on ? L->capacity : 0;
     L->o_ccnt = take(sizeof(int) * (size_t)(nbox + 1));
     L->o_cfill = take(sizeof(int) * (size_t)nbox);
-    L->o_cbsum = take(sizeof(int) * (size_t)(c.collide ? col_scan_blocks((int)nbox + 1) + 1 : 0));
+    L->o_cbsum = take(sizeof(int) * (size_t)(on ? col_scan_blocks((int)nbox + 1) + 1 : 0));
     L->o_cidx = take(sizeof(int) * (size_t)cap);
     L->o_ckey = take(sizeof(uint32_t) * (size_t)cap);
-    L->o_cact = take(sizeof(int) * (size_t)(c.collide ? cap / 2 + 2 : 0));   // cells, then the count
+    L->o_cact = take(sizeof(int) * (size_t)(on ? cap + 2 : 0));   // cells, then the count
+    L->o_mrank = take(sizeof(int) * (size_t)(on ? c.n[0] : 0));
   }
   L->total = o;
   return PIC_OK;
@@ -539,7 +542,7 @@ void enqueue_step(pic_ctx* c) {
   }
   if (c->imax_every > 0 && (c->step + 1) % c->imax_every == 0) launch_imax(imax_args(c), c->d_imax, s);
   timed(c, 2, [&](Stamp st) { launch_ionize(single(c, 3, c->nb_neut), D, order, s, st); });
-  if (c->canon.collide)
+  if (c->canon.collide || c->canon.impact)
     timed(c, 4, [&](Stamp st) { launch_collide(c->h, c->col, (int)(c->step + 1), s, st); });
   if (c->track_every > 0 && (c->step + 1) % c->track_every == 0)
     launch_tracks(c->d_inst, D, (int)c->L.capacity, c->track_thr, (int)(c->step + 1),
@@ -855,16 +858,31 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
   I.ie_half = (const float*)devp(c, L.o_ie_half);
   I.ie_node = (const float*)devp(c, L.o_ie_node);
   c->col = ColBufs{};
-  if (K.collide) {
+  std::vector<int> mrank;
+  if (K.collide || K.impact) {
     c->col.cnt = (int*)devp(c, L.o_ccnt);
     c->col.fill = (int*)devp(c, L.o_cfill);
     c->col.bsum = (int*)devp(c, L.o_cbsum);
     c->col.idx = (int*)devp(c, L.o_cidx);
     c->col.key = (uint32_t*)devp(c, L.o_ckey);
     c->col.active = (int*)devp(c, L.o_cact);
-    c->col.nactive = c->col.active + L.capacity / 2 + 1;
+    c->col.nactive = c->col.active + L.capacity + 1;
     c->col.ncell = (int)(K.n[0] * K.n[1] * K.n[2]);
     c->col.dt = K.dt;
+    c->col.collide = K.collide;
+    c->col.impact = K.impact;
+    for (int m = 0; m < K.nmat; ++m) {
+      c->col.imp_P[m] = K.mats[m].impact_P;
+      c->col.imp_th[m] = K.mats[m].impact_th;
+      c->col.gap[m] = K.mats[m].gap_eV * kQE;
+    }
+    // rank of each material x cell (the material cells run x fastest, then y, z)
+    mrank.assign(K.n[0], -1);
+    int r = 0;
+    for (int64_t i = 0; i < K.n[0]; ++i)
+      if (K.mat_cell[i] >= 0) mrank[i] = r++;
+    c->col.nmx = r;
+    c->col.mrank = (const int*)devp(c, L.o_mrank);
   }
   I.lx0 = L.lx0;
   I.lx1 = L.lx1;
@@ -1014,6 +1032,9 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
           hipSuccess;
   }
   ok &= hipMemcpyAsync(devp(c, L.o_mat), K.mat_cell.data(), K.n[0], hipMemcpyHostToDevice, s) == hipSuccess;
+  if (!mrank.empty())
+    ok &= hipMemcpyAsync(devp(c, L.o_mrank), mrank.data(), sizeof(int) * mrank.size(), hipMemcpyHostToDevice, s) ==
+          hipSuccess;
   ok &= hipMemcpyAsync(devp(c, L.o_src), src.data(), sizeof(float) * src.size(), hipMemcpyHostToDevice, s) == hipSuccess;
   ok &= hipMemcpyAsync(devp(c, L.o_prof), prof.data(), sizeof(float) * prof.size(), hipMemcpyHostToDevice, s) == hipSuccess;
   if (!c->mcell.empty())
@@ -1954,7 +1975,7 @@ pic_status pic_batch_set_graph(pic_batch* b, int32_t on) {
 int64_t pic_batch_graph_replays(const pic_batch* b) { return b ? b->replays : 0; }
 
 pic_status pic_batch_add(pic_batch* b, pic_ctx* c) {
-  if (!b || !c || c->canon.collide) return PIC_E_INVAL;
+  if (!b || !c || c->canon.collide || c->canon.impact) return PIC_E_INVAL;
   for (pic_ctx* m : b->members)
     if (m == c) return PIC_E_INVAL;
   if (b->members.empty()) b->stream = c->stream;

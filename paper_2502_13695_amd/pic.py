@@ -38,7 +38,7 @@ class PicError(RuntimeError):
 class Material(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("gap_eV", "n_index", "density_gcc", "molar_mass_gmol",
                                             "me_star", "mh_star", "pos_mass_kg", "lorentz_lambda_m",
-                                            "eps_inf", "lorentz_gamma_s")]
+                                            "eps_inf", "lorentz_gamma_s", "impact_rate_s")]
 
 
 class Layer(C.Structure):
@@ -184,6 +184,7 @@ def make_config(cfg, stream=None, alloc=None, free=None):
         mats[i].lorentz_lambda_m = float(m.get("lorentz_lambda_m", 0.0))
         mats[i].eps_inf = float(m.get("eps_inf", 1.0))
         mats[i].lorentz_gamma_s = float(m.get("lorentz_gamma_s", 0.0))
+        mats[i].impact_rate_s = float(m.get("impact_rate_s", 0.0))
     layers = (Layer * max(1, len(cfg["layers"])))()
     for i, (m, lo, hi) in enumerate(cfg["layers"]):
         layers[i].material = int(m)
