@@ -19,6 +19,10 @@ it changes; the inherited parts follow the textbook method named alongside:
   centred at integer steps: J_p^{n+1/2} from J_p^{n-1/2}, E^n and P^n, then
   P^{n+1} = P^n + dt J_p^{n+1/2}, and J_p^{n+1/2} enters the E update beside
   the free current with 1/eps_inf in place of 1/eps_r.
+* Its nonlinear extension (a reading; the paper leaves nonlinear optics out,
+  Sec. 2.3): an instantaneous Kerr term, per E component chi3 E^3 in the
+  displacement, chi3 = (4/3) n0^2 eps0 c n2; the displacement advances by the
+  curl and the currents, and E^{n+1} solves the cubic pointwise.
 * "Simple outflow" boundaries (Sec. 3.1): first-order Mur on each outflow
   face for the tangential E; the laser enters as the incident field of the
   x_min face condition (Sec. 3, Fig. 1: driven from the minimum boundary).
@@ -66,7 +70,9 @@ transverse faces, and the gap energy against events x weight x gap
 (tests/test_oracle_budget.py); for the Lorentz medium, the discrete dispersion
 relation of the coupled scheme, Fresnel reflection against the continuum
 eps(w) over the pulse's spectrum, and the Gauss law with the bound charge
-(tests/test_oracle_lorentz.py).
+(tests/test_oracle_lorentz.py); for the Kerr term, the harmonic-balance
+frequency shift of a standing wave and the Gauss law with the nonlinear
+displacement (tests/test_oracle_kerr.py).
 """
 
 import math
@@ -121,6 +127,12 @@ class Sim:
         lor_node = np.zeros((self.S[0], 3))
         lor_node[G:G + nx + 1] = P.lor_of(P.mat_node)
         self.lorE = [[t[:, q].reshape(-1, 1, 1) for q in range(3)] for t in (lor_half, lor_node, lor_node)]
+        # Kerr: chi3 at each E component's own location (x only)
+        chi_half = np.zeros(self.S[0])
+        chi_half[G:G + nx] = P.chi3_of(P.mat_cell)
+        chi_node = np.zeros(self.S[0])
+        chi_node[G:G + nx + 1] = P.chi3_of(P.mat_node)
+        self.chiE = [chi_half.reshape(-1, 1, 1), chi_node.reshape(-1, 1, 1), chi_node.reshape(-1, 1, 1)]
         self.Q = [z(), z(), z()]
         self.K = [z(), z(), z()]
         self.regE = [self._region(self.stE[c], True) for c in range(3)]
@@ -342,7 +354,22 @@ class Sim:
             k_new = la * self.K[c][r] + lcd * self.E[c][r] - lc * self.Q[c][r]
             self.K[c][r] = k_new
             self.Q[c][r] += k_new
-            self.E[c][r] += ie[r] * (cc[r] - self.J[c][r] - k_new)
+            src = cc[r] - self.J[c][r] - k_new
+            g = ie[r] * np.broadcast_to(self.chiE[c], self.S)[r]
+            if np.any(g != 0):
+                # Kerr: the displacement E/ie + chi3 E^3 (+ Q) advances by the
+                # curl and the currents; E^{n+1} solves X + g X^3 = R, g = ie chi3
+                e0 = self.E[c][r]
+                R = e0 + g * e0 ** 3 + ie[r] * src
+                X = e0 + ie[r] * src
+                for _ in range(60):       # Newton on a monotone cubic, to FP64 convergence
+                    dX = (X + g * X ** 3 - R) / (1.0 + 3.0 * g * X * X)
+                    X = X - dX
+                    if np.all(np.abs(dX) <= 1e-16 * np.abs(X)):
+                        break
+                self.E[c][r] = X
+            else:
+                self.E[c][r] += ie[r] * src
         self._mur(old, n)
 
     def _face_points(self, c, d):
@@ -735,12 +762,14 @@ class Sim:
         return tuple(sl)
 
     def gauss_residual(self):
-        """div(E/ie + Q) - rho/eps0 at interior nodes [V/m^2] (Sec. 2.3 medium;
-        Q = P/eps0 of a Lorentz medium, zero elsewhere)."""
+        """div(E/ie + Q + chi3 E^3) - rho/eps0 at interior nodes [V/m^2] (Sec. 2.3
+        medium; Q = P/eps0 of a Lorentz medium, chi3 the Kerr response, zero
+        elsewhere)."""
         P = self.P
         div = np.zeros(self.S)
         for c in range(self.D):
-            D_ = self.E[c] / np.broadcast_to(self.ieE[c], self.S) + self.Q[c]
+            D_ = (self.E[c] / np.broadcast_to(self.ieE[c], self.S) + self.Q[c]
+                  + np.broadcast_to(self.chiE[c], self.S) * self.E[c] ** 3)
             self._fill_periodic(D_)
             div += (D_ - np.roll(D_, 1, axis=c)) / P.dx[c]
         res = div - self.charge_density()

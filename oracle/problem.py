@@ -86,6 +86,14 @@ class Material:
         # (Lorentz: the instantaneous part) as an FP32 number
         self.ie = f32(1.0 / self.eps_inf)
         self.lor = (0.0, 0.0, 0.0)   # (a, c, c deps) of the oscillator update; 0: none
+        # instantaneous Kerr response: n = n0 + n2 I; per E component the
+        # displacement gains chi3 E^3 with chi3 = (4/3) n0^2 eps0 c n2 (a
+        # linearly polarised wave then sees eps + (3/4) chi3 E0^2, i.e. the
+        # index change n2 I); chi3 [m^2/V^2] as an FP32 number, 0: none
+        n2 = float(m.get("kerr_n2_m2W", 0.0))
+        if n2 < 0:
+            raise ValueError("negative n2")
+        self.chi3 = f32(4.0 / 3.0 * self.n_index * self.n_index * EPS0 * C * n2)
 
 
 class Laser:
@@ -242,6 +250,10 @@ class Problem:
     def lor_of(self, mat_idx):
         """(a, c, c deps) per position; zeros where no oscillator."""
         return np.array([(0.0, 0.0, 0.0) if m < 0 else self.mats[m].lor for m in mat_idx]).reshape(-1, 3)
+
+    def chi3_of(self, mat_idx):
+        """Kerr chi3 [m^2/V^2] per position; zero where none."""
+        return np.array([0.0 if m < 0 else self.mats[m].chi3 for m in mat_idx])
 
     def transverse_profile(self, y, z):
         """Gaussian transverse field profile exp(-r^2/w0^2) at the injection plane."""

@@ -10,7 +10,7 @@ Configuration dictionary (both sides read the same keys):
   ("outflow" | "periodic"), materials (list of dicts: gap_eV, n_index,
   density_gcc, molar_mass_gmol, me_star, mh_star, pos_mass_kg, and for a
   single-pole Lorentz response lorentz_lambda_m, eps_inf, lorentz_gamma_s; for
-  impact ionization impact_rate_s), layers (list
+  impact ionization impact_rate_s; for the Kerr response kerr_n2_m2W), layers (list
   of (material, lo_m, hi_m) half-open along x), ppc, T_K, shape_order,
   keldysh_terms, seed, laser (lambda_m, fwhm_s, peak_Wcm2 | fluence_Jcm2,
   waist_m, t_peak_s, cep_rad, envelope "gauss" | "sin2", pol_axis),
