@@ -82,11 +82,19 @@ typedef struct pic_batch pic_batch;
  * are taken in a fixed order keyed by their ids; an event consumes the cell's
  * alive neutral of lowest index (a photoionization-like birth at its position)
  * and takes E_g from the impacting electron.  0: none; negative: PIC_E_INVAL.
- * Runs with impact ionization cannot join a batch. */
+ * Runs with impact ionization cannot join a batch.
+ *
+ * Kerr response (the nonlinear extension of the linear optics, which the
+ * paper leaves out): kerr_n2_m2W = n2 > 0 adds chi3 E^3 to the displacement of
+ * each E component, chi3 = (4/3) n^2 eps0 c n2 (a linearly polarised wave
+ * then sees n + n2 I); the update advances the displacement by the curl and
+ * the currents and solves the cubic for E at every interior position of the
+ * material.  0: linear; negative: PIC_E_INVAL. */
 typedef struct {
   double gap_eV, n_index, density_gcc, molar_mass_gmol, me_star, mh_star, pos_mass_kg;
   double lorentz_lambda_m, eps_inf, lorentz_gamma_s;
   double impact_rate_s;
+  double kerr_n2_m2W;
 } pic_material;
 
 /* Optical region (Sec. 2.3): material `material` fills lo_m <= x < hi_m across
@@ -177,6 +185,7 @@ typedef struct {
   int64_t n_neutral;           /* neutral macroparticles loaded */
   int64_t capacity;            /* charged slots */
   double lor[8][3];            /* per material: Lorentz oscillator coefficients */
+  double chi3[8];              /* per material: Kerr chi3 [m^2/V^2] as FP32 (0: linear) */
 } pic_params;
 
 /* Diagnostic kinds for pic_diag.  Grids are FP64 unless stated, on the

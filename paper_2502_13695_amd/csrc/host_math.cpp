@@ -263,6 +263,8 @@ pic_status canonicalize(const pic_config* cfg, Canon* c) {
       mc.impact_th = M.gap_eV * (1.0 + 2.0 * mu) / (1.0 + mu) * kQE;
     }
     if (mc.impact_P > 0) c->impact = true;
+    if (!(M.kerr_n2_m2W >= 0)) return PIC_E_INVAL;
+    mc.chi3 = (float)(4.0 / 3.0 * M.n_index * M.n_index * kEPS0 * kC * M.kerr_n2_m2W);
     if (M.lorentz_lambda_m > 0) {
       double s2max = 0.0;
       for (int d = 0; d < c->D; ++d) s2max += (double)c->C[d] * (double)c->C[d];

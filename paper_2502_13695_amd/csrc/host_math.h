@@ -16,6 +16,7 @@ struct MatC {
   float lor[3];             // oscillator update (a, c, c deps); zeros when static
   double impact_P;          // impact-ionization rate constant [1/s] (0: none)
   double impact_th;         // its threshold energy [J]
+  float chi3;               // Kerr chi3 = (4/3) n^2 eps0 c n2 [m^2/V^2] (0: linear)
 };
 
 // Von Neumann stability of the Yee update coupled to the explicit Lorentz

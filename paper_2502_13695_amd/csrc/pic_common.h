@@ -212,9 +212,10 @@ struct Inst {
   const float* ie_node;         // 1/eps_r at nodes, per padded x index
   // Lorentz media: Q = P/eps0 (step n) and K = dt J_p/eps0 (step n - 1/2) in
   // set n & 1 at E positions, the field update writes set (n + 1) & 1; per
-  // padded x the oscillator coefficients (a, c, c deps, 0) at Ex positions and
-  // at nodes.  Positions lx0 <= padded x < lx1 hold every oscillator; null
-  // pointers and lx0 >= lx1 when the run has none.
+  // padded x the oscillator coefficients and the Kerr chi3 (a, c, c deps,
+  // chi3) at Ex positions and at nodes.  Positions lx0 <= padded x < lx1 hold
+  // every oscillator and Kerr term; null pointers and lx0 >= lx1 when the run
+  // has none.
   float* Q[2][3];
   float* Kp[2][3];
   const float4* lor_half;

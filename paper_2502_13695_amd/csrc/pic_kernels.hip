@@ -1271,6 +1271,19 @@ __device__ __forceinline__ float lor_step(const LorPtrs& p, unsigned gi, float4 
   return kn;
 }
 
+// E^{n+1} at a Kerr position: the displacement e / ie + chi3 e^3 advances by
+// src (curl and currents); X + g X^3 = R, g = ie chi3, by Newton from the
+// linear update (three steps: g X^2 is small, the start within g e^2 of it)
+__device__ __forceinline__ float kerr_update(float e, float ie, float src, float chi3) {
+  const float g = ie * chi3;
+  const float lin = e + ie * src;
+  const float R = lin + g * e * e * e;
+  float X = lin;
+#pragma unroll
+  for (int it = 0; it < 3; ++it) X -= (X + g * X * X * X - R) / (1.0f + 3.0f * g * X * X);
+  return X;
+}
+
 template <int D, int V>
 struct TileT {
   static constexpr int X = tile_shape(D, V).x, Y = tile_shape(D, V).y, Z = tile_shape(D, V).z;
@@ -1535,21 +1548,30 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g, std::conditional_t<ONE,
       if (D >= 3) cu -= Cz * (sB[1][l] - sB[1][l - LZ]);
       float src = cu - jr[k][0];
       if (lorT && lh.y != 0.0f) src -= lor_step(LOR_PTRS(I, par, 0), gl, lh, sE[0][l], own);
-      sE[0][l] += sieh[qx] * src;
+      if (lorT && lh.w != 0.0f)
+        sE[0][l] = kerr_update(sE[0][l], sieh[qx], src, lh.w);
+      else
+        sE[0][l] += sieh[qx] * src;
     }
     if ((bx & AX_IN) && (by & AX_IH) && (bz & AX_IN)) {
       float cu = -Cx * (sB[2][l] - sB[2][l - 1]);
       if (D >= 3) cu += Cz * (sB[0][l] - sB[0][l - LZ]);
       float src = cu - jr[k][1];
       if (lorT && ln.y != 0.0f) src -= lor_step(LOR_PTRS(I, par, 1), gl, ln, sE[1][l], own);
-      sE[1][l] += sien[qx] * src;
+      if (lorT && ln.w != 0.0f)
+        sE[1][l] = kerr_update(sE[1][l], sien[qx], src, ln.w);
+      else
+        sE[1][l] += sien[qx] * src;
     }
     if ((bx & AX_IN) && (by & AX_IN) && (bz & AX_IH)) {
       float cu = Cx * (sB[1][l] - sB[1][l - 1]);
       if (D >= 2) cu -= Cy * (sB[0][l] - sB[0][l - LY]);
       float src = cu - jr[k][2];
       if (lorT && ln.y != 0.0f) src -= lor_step(LOR_PTRS(I, par, 2), gl, ln, sE[2][l], own);
-      sE[2][l] += sien[qx] * src;
+      if (lorT && ln.w != 0.0f)
+        sE[2][l] = kerr_update(sE[2][l], sien[qx], src, ln.w);
+      else
+        sE[2][l] += sien[qx] * src;
     }
   }
   };
@@ -2033,21 +2055,30 @@ __global__ __launch_bounds__(TPB, 4) void k_fields_z(Group g, std::conditional_t
           cu -= Cz * (cB[1][l] - bh1[p]);
           float src = cu - jc[p][0];
           if (lorT && slh[qx].y != 0.0f) src -= lor_step(LOR_PTRS(I, par, 0), gl, slh[qx], cE[0][l], own);
-          cE[0][l] += sieh[qx] * src;
+          if (lorT && slh[qx].w != 0.0f)
+            cE[0][l] = kerr_update(cE[0][l], sieh[qx], src, slh[qx].w);
+          else
+            cE[0][l] += sieh[qx] * src;
         }
         if (bx & AX_IN) {
           float cu = -Cx * (cB[2][l] - cB[2][l - 1]);
           cu += Cz * (cB[0][l] - bh0[p]);
           float src = cu - jc[p][1];
           if (lorT && sln[qx].y != 0.0f) src -= lor_step(LOR_PTRS(I, par, 1), gl, sln[qx], cE[1][l], own);
-          cE[1][l] += sien[qx] * src;
+          if (lorT && sln[qx].w != 0.0f)
+            cE[1][l] = kerr_update(cE[1][l], sien[qx], src, sln[qx].w);
+          else
+            cE[1][l] += sien[qx] * src;
         }
         if (bx & AX_IN) {
           float cu = Cx * (cB[1][l] - cB[1][l - 1]);
           cu -= Cy * (cB[0][l] - cB[0][l - LY]);
           float src = cu - jc[p][2];
           if (lorT && sln[qx].y != 0.0f) src -= lor_step(LOR_PTRS(I, par, 2), gl, sln[qx], cE[2][l], own);
-          cE[2][l] += sien[qx] * src;
+          if (lorT && sln[qx].w != 0.0f)
+            cE[2][l] = kerr_update(cE[2][l], sien[qx], src, sln[qx].w);
+          else
+            cE[2][l] += sien[qx] * src;
         }
       }
       __syncthreads();
@@ -2816,10 +2847,14 @@ __global__ __launch_bounds__(TPB) void k_diag_gauss(const Inst* d, const double*
   const float* E0 = I.F[par][0];
   const float* E1 = I.F[par][1];
   const float* E2 = I.F[par][2];
-  // displacement E / ie + Q (Q = P / eps0 of Lorentz media)
+  // displacement E / ie + Q + chi3 E^3 (Q = P / eps0 of Lorentz media, chi3
+  // the Kerr term; ai the padded x index of the position)
   const bool lor = I.lx0 < I.lx1;
-  auto dsp = [&](int c, const float* E, int64_t q, float ie) {
-    return (double)E[q] / ie + (lor ? (double)I.Q[par][c][q] : 0.0);
+  auto dsp = [&](int c, const float* E, int64_t q, float ie, int ai) {
+    const double e = E[q];
+    if (!lor) return e / ie;
+    const double chi = c == 0 ? I.lor_half[ai].w : I.lor_node[ai].w;
+    return e / ie + (double)I.Q[par][c][q] + chi * e * e * e;
   };
   double mres = 0.0, mrho = 0.0, sres = 0.0, nres = 0.0;
   for (int64_t p = (int64_t)blockIdx.x * TPB + threadIdx.x; p < ncell; p += (int64_t)gridDim.x * TPB) {
@@ -2829,14 +2864,14 @@ __global__ __launch_bounds__(TPB) void k_diag_gauss(const Inst* d, const double*
     if (D >= 2 && (I.per_y ? (j < 0 || j >= I.ny) : (j < 1 || j > I.ny - 1))) continue;
     if (D >= 3 && (I.per_z ? (k < 0 || k >= I.nz) : (k < 1 || k > I.nz - 1))) continue;
     const int ai = i + G;
-    double div = (dsp(0, E0, p, I.ie_half[ai]) - dsp(0, E0, p - 1, I.ie_half[ai - 1])) / I.dx[0];
+    double div = (dsp(0, E0, p, I.ie_half[ai], ai) - dsp(0, E0, p - 1, I.ie_half[ai - 1], ai - 1)) / I.dx[0];
     if (D >= 2) {
       const int dym = I.per_y && j == 0 ? (I.ny - 1) * I.sy : -I.sy;
-      div += (dsp(1, E1, p, I.ie_node[ai]) - dsp(1, E1, p + dym, I.ie_node[ai])) / I.dx[1];
+      div += (dsp(1, E1, p, I.ie_node[ai], ai) - dsp(1, E1, p + dym, I.ie_node[ai], ai)) / I.dx[1];
     }
     if (D >= 3) {
       const int dzm = I.per_z && k == 0 ? (I.nz - 1) * I.sz : -I.sz;
-      div += (dsp(2, E2, p, I.ie_node[ai]) - dsp(2, E2, p + dzm, I.ie_node[ai])) / I.dx[2];
+      div += (dsp(2, E2, p, I.ie_node[ai], ai) - dsp(2, E2, p + dzm, I.ie_node[ai], ai)) / I.dx[2];
     }
     const double r = div - rho[p];
     mres = fmax(mres, fabs(r));

@@ -167,8 +167,10 @@ pic_status plan(const pic_config* cfg, const Canon& c, const std::vector<TableHo
   L->lx0 = (int)L->Px;
   L->lx1 = 0;
   for (int64_t i = 0; i <= c.n[0]; ++i) {
-    const bool lc = i < c.n[0] && c.mat_cell[i] >= 0 && c.mats[c.mat_cell[i]].lam0 > 0;
-    const bool ln = c.mat_node[i] >= 0 && c.mats[c.mat_node[i]].lam0 > 0;
+    // Lorentz oscillators or a Kerr term (both in the field update's dispersive variant)
+    auto disp = [&](int m) { return m >= 0 && (c.mats[m].lam0 > 0 || c.mats[m].chi3 != 0.0f); };
+    const bool lc = i < c.n[0] && disp(c.mat_cell[i]);
+    const bool ln = disp(c.mat_node[i]);
     if (lc || ln) {
       L->lx0 = std::min(L->lx0, (int)(i + G));
       L->lx1 = std::max(L->lx1, (int)(i + G + 1));
@@ -670,6 +672,7 @@ pic_status pic_canonical(const pic_config* cfg, pic_params* out) {
   for (int m = 0; m < c.nmat; ++m) {
     out->ie[m] = c.mats[m].ie;
     for (int q = 0; q < 3; ++q) out->lor[m][q] = c.mats[m].lor[q];
+    out->chi3[m] = c.mats[m].chi3;
   }
   out->nwin = c.nwin;
   out->E0 = c.E0;
@@ -800,7 +803,7 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
   std::vector<float4> lor_half(has_lor ? L.Px : 0, make_float4(0.f, 0.f, 0.f, 0.f));
   std::vector<float4> lor_node(lor_half);
   auto lor_of = [&](int m) {
-    return m >= 0 ? make_float4(K.mats[m].lor[0], K.mats[m].lor[1], K.mats[m].lor[2], 0.f)
+    return m >= 0 ? make_float4(K.mats[m].lor[0], K.mats[m].lor[1], K.mats[m].lor[2], K.mats[m].chi3)
                   : make_float4(0.f, 0.f, 0.f, 0.f);
   };
   if (has_lor) {

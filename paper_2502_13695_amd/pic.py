@@ -38,7 +38,7 @@ class PicError(RuntimeError):
 class Material(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("gap_eV", "n_index", "density_gcc", "molar_mass_gmol",
                                             "me_star", "mh_star", "pos_mass_kg", "lorentz_lambda_m",
-                                            "eps_inf", "lorentz_gamma_s", "impact_rate_s")]
+                                            "eps_inf", "lorentz_gamma_s", "impact_rate_s", "kerr_n2_m2W")]
 
 
 class Layer(C.Structure):
@@ -72,7 +72,8 @@ class Params(C.Structure):
     _fields_ = [("dt", C.c_double), ("Cd", C.c_double * 3), ("kmur", C.c_double * 3),
                 ("ie", C.c_double * 8), ("nwin", C.c_int64), ("E0", C.c_double),
                 ("t_peak", C.c_double), ("amp_cut", C.c_double * 8), ("amp_sat", C.c_double * 8),
-                ("n_neutral", C.c_int64), ("capacity", C.c_int64), ("lor", (C.c_double * 3) * 8)]
+                ("n_neutral", C.c_int64), ("capacity", C.c_int64), ("lor", (C.c_double * 3) * 8),
+                ("chi3", C.c_double * 8)]
 
 
 class Particle(C.Structure):
@@ -185,6 +186,7 @@ def make_config(cfg, stream=None, alloc=None, free=None):
         mats[i].eps_inf = float(m.get("eps_inf", 1.0))
         mats[i].lorentz_gamma_s = float(m.get("lorentz_gamma_s", 0.0))
         mats[i].impact_rate_s = float(m.get("impact_rate_s", 0.0))
+        mats[i].kerr_n2_m2W = float(m.get("kerr_n2_m2W", 0.0))
     layers = (Layer * max(1, len(cfg["layers"])))()
     for i, (m, lo, hi) in enumerate(cfg["layers"]):
         layers[i].material = int(m)

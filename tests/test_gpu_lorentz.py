@@ -29,11 +29,16 @@ pytestmark = pytest.mark.gpu
 SIL = W.silica_dispersive()
 
 
-def _box_cfg(ndim, n, bc, dxfrac=30):
+def _box_cfg(ndim, n, bc, dxfrac=30, kerr=0.0):
     dx = W.LAMBDA / dxfrac
+    m0, m1 = SIL, dict(W.high_index(), gap_eV=9.0)
+    if kerr:
+        # Kerr terms in both layers (n2 large enough that chi3 E^2 ~ 1e-2 at the
+        # test's 1e6 V/m fields)
+        m0, m1 = dict(m0, kerr_n2_m2W=kerr), dict(m1, kerr_n2_m2W=0.5 * kerr)
     return dict(ndim=ndim, n=n, dx=[dx] * ndim, cfl=0.95, nsteps=100, transverse_bc=bc,
                 # a Lorentz layer beside a static one (9 eV gaps: nothing ionizes)
-                materials=[SIL, dict(W.high_index(), gap_eV=9.0)],
+                materials=[m0, m1],
                 layers=[(0, 0.25 * n[0] * dx, 0.55 * n[0] * dx), (1, 0.55 * n[0] * dx, 0.7 * n[0] * dx)],
                 ppc=1, T_K=300.0, shape_order=2, keldysh_terms=500, seed=5,
                 laser=dict(lambda_m=W.LAMBDA, fwhm_s=W.cycles(2), peak_Wcm2=1e12, envelope="gauss",
@@ -55,14 +60,20 @@ def _oracle_fields(sim):
     return E, b, Q, K
 
 
-@pytest.mark.parametrize("ndim,n,bc,tile", [
-    (1, [300], "outflow", None), (2, [40, 24], "outflow", None), (2, [40, 24], "periodic", None),
-    (3, [20, 12, 10], "outflow", None), (3, [40, 20, 36], "periodic", "5"),
-    (3, [40, 20, 36], "periodic", "7")])
-def test_lorentz_random_fields_match_oracle(P, ndim, n, bc, tile, monkeypatch):
+KERR_N2 = 2.7e-12
+
+
+@pytest.mark.parametrize("ndim,n,bc,tile,kerr", [
+    (1, [300], "outflow", None, 0.0), (2, [40, 24], "outflow", None, 0.0), (2, [40, 24], "periodic", None, 0.0),
+    (3, [20, 12, 10], "outflow", None, 0.0), (3, [40, 20, 36], "periodic", "5", 0.0),
+    (3, [40, 20, 36], "periodic", "7", 0.0),
+    (1, [300], "outflow", None, KERR_N2), (2, [40, 24], "periodic", None, KERR_N2),
+    (3, [40, 20, 36], "periodic", "5", KERR_N2), (3, [40, 20, 36], "periodic", "7", KERR_N2)])
+def test_lorentz_random_fields_match_oracle(P, ndim, n, bc, tile, kerr, monkeypatch):
+    """Lorentz layer beside a static one; with kerr, both layers add a Kerr term."""
     if tile:
         monkeypatch.setenv("PIC_FIELD_TILE", tile)
-    cfg = _box_cfg(ndim, n, bc)
+    cfg = _box_cfg(ndim, n, bc, kerr=kerr)
     E, b = _random_fields(cfg, 40 + ndim)
     ctx = P.Context(cfg)
     if tile:
@@ -85,6 +96,14 @@ def test_lorentz_random_fields_match_oracle(P, ndim, n, bc, tile, monkeypatch):
             assert g_[c].shape == o_[c].shape, (name, c)
             err = np.max(np.abs(g_[c] - o_[c]))
             assert err < 1e-5 * scale, (name, c, err / scale)
+    if kerr:
+        sim_lin = OP.Sim(_box_cfg(ndim, n, bc))
+        for c in range(3):
+            sim_lin.E[c][sim_lin._domain_slices(sim_lin.stE[c])] = E[c]
+            sim_lin.b[c][sim_lin._domain_slices(sim_lin.stB[c])] = b[c]
+        sim_lin.run(nsteps)
+        # the Kerr term changed the fields far beyond the tolerance
+        assert max(np.max(np.abs(sim_lin.interior_field("E", c) - Eo[c])) for c in range(3)) > 1e-3 * scale
     # outside the Lorentz layer the polarisation stays exactly zero
     mat_node = sim.P.mat_node
     static_nodes = np.nonzero(mat_node != 0)[0]
@@ -115,6 +134,16 @@ def test_lorentz_marching_update_matches_tiled_bitwise(P, monkeypatch):
         for a, c in zip(ra, rb):
             assert np.array_equal(a, c)
     assert max(np.max(np.abs(q)) for q in out["7"][-1][6:9]) > 0
+
+
+def test_kerr_run_1d_slab(P):
+    """The 1D slab at 1e14 W/cm^2 with fused silica's Kerr index (2.5e-20 m^2/W)
+    on top of its Lorentz response."""
+    cfg = W.config_1d(hi=True, ppc=10, nsteps=1400, dispersive=True)
+    cfg["materials"] = [dict(cfg["materials"][0], kerr_n2_m2W=2.5e-20)]
+    ctx, sim = _run_both(P, cfg, 1400)
+    _compare_run(P, ctx, sim, min_events=20, name="run_1d_kerr")
+    ctx.close()
 
 
 def test_lorentz_run_1d_slab(P):

@@ -41,7 +41,8 @@ def test_exports_every_declared_symbol():
 @pytest.mark.parametrize("cfg", [W.config_1d(), W.config_1d(hi=True), W.config_2d(), W.config_3d(),
                                  W.batch_scan(4)[3], W.config_2d(nx=100, ny=37),
                                  W.config_1d(dispersive=True), W.config_2d(dispersive=True),
-                                 W.config_3d(dispersive=True)])
+                                 W.config_3d(dispersive=True),
+                                 dict(W.config_1d(), materials=[dict(W.silica_like(), kerr_n2_m2W=2.5e-20)])])
 def test_canonical_problem_bitwise_equal(cfg):
     _lib_or_skip()
     p = P.canonical(cfg)
@@ -52,6 +53,7 @@ def test_canonical_problem_bitwise_equal(cfg):
     assert p.nwin == o.nwin
     assert [p.ie[m] for m in range(len(o.mats))] == [m.ie for m in o.mats]
     assert [tuple(p.lor[m]) for m in range(len(o.mats))] == [tuple(m.lor) for m in o.mats]
+    assert [p.chi3[m] for m in range(len(o.mats))] == [m.chi3 for m in o.mats]
     assert abs(p.E0 / o.laser.E0 - 1) < 1e-15
     nmat_cells = int(np.sum(o.mat_cell >= 0)) * o.n[1] * o.n[2]
     assert p.n_neutral == nmat_cells * o.ppc
