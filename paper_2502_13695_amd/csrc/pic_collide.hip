@@ -36,7 +36,7 @@ namespace {
 constexpr uint32_t PURPOSE_PAIR = 7, PURPOSE_SCATTER = 8, PURPOSE_IMPACT = 9;
 constexpr double kC = 299792458.0, kEPS0 = 8.8541878128e-12, kHBAR = 1.054571817e-34,
                  kQE = 1.602176634e-19, kPI = 3.14159265358979323846;
-constexpr int SCAN_B = 1024;   // elements per block of the cell scan
+constexpr int SCAN_B = COL_SCAN_B;
 
 __device__ __forceinline__ int box_cell(const Inst& I, uint32_t pc) {
   int i, j, k;
@@ -53,81 +53,100 @@ __global__ void k_col_clear(ColBufs b) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i <= b.ncell) b.cnt[i] = 0;
   if (i < b.ncell) b.fill[i] = 0;
-  if (i == 0) *b.nactive = 0;
 }
 
-// counts per cell; the particle that makes a cell eligible lists it (the
-// first in a cell of a material with impact ionization, else the second when
-// collisions are on)
+// counts per cell (no return value is waited for)
 __global__ void k_col_count(const Inst I, ColBufs b) {
   const int n = live_slots(I);
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x)
-    if (I.pkind[p] != 0xFF) {
-      const uint32_t pc = I.pcell[p];
-      const int c = box_cell(I, pc);
-      const int old = atomicAdd(&b.cnt[c], 1);
-      int i, j, k;
-      unpack_cell(I.D, pc, i, j, k);
-      const int m = I.mat_cell[i];
-      const bool imp = b.impact && m >= 0 && b.imp_P[m] > 0.0;
-      if (imp ? old == 0 : (b.collide && old == 1)) b.active[atomicAdd(b.nactive, 1)] = c;
-    }
+    if (I.pkind[p] != 0xFF) atomicAdd(&b.cnt[box_cell(I, I.pcell[p])], 1);
 }
 
-// exclusive scan of cnt[0 .. n): per block in LDS, block totals, then offsets
-__global__ void k_col_scan_local(ColBufs b, int n) {
-  __shared__ int s[SCAN_B];
-  const int base = blockIdx.x * SCAN_B;
-  for (int t = threadIdx.x; t < SCAN_B; t += blockDim.x) s[t] = base + t < n ? b.cnt[base + t] : 0;
-  __syncthreads();
-  // Hillis-Steele inclusive scan over SCAN_B elements with blockDim.x = SCAN_B
-  for (int off = 1; off < SCAN_B; off <<= 1) {
-    const int t = threadIdx.x;
-    const int v = t >= off ? s[t - off] : 0;
-    __syncthreads();
-    s[t] += v;
-    __syncthreads();
+// exclusive scan of v over a block of SCAN_B threads (a scan within each
+// wave, then over the wave totals); the block's total in *total.  w holds
+// SCAN_B / 64 + 1 ints of LDS.
+__device__ __forceinline__ int block_scan(int v, int* w, int* total) {
+  constexpr int NW = SCAN_B / 64;
+  const int lane = (int)__lane_id(), wv = threadIdx.x / 64;
+  int x = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(x, off);
+    if (lane >= off) x += y;
   }
-  const int t = threadIdx.x;
-  if (base + t < n) b.cnt[base + t] = t == 0 ? 0 : s[t - 1];
-  if (t == SCAN_B - 1) b.bsum[blockIdx.x] = s[t];
+  if (lane == 63) w[wv] = x;
+  __syncthreads();
+  if (wv == 0) {
+    const int s0 = lane < NW ? w[lane] : 0;
+    int y = s0;
+    for (int off = 1; off < NW; off <<= 1) {
+      const int z = __shfl_up(y, off);
+      if (lane >= off) y += z;
+    }
+    if (lane < NW) w[lane] = y - s0;
+    if (lane == NW - 1) w[NW] = y;
+  }
+  __syncthreads();
+  const int r = w[wv] + x - v;
+  *total = w[NW];
+  __syncthreads();
+  return r;
 }
 
-__global__ void k_col_scan_top(ColBufs b, int nb) {
-  // one block: exclusive scan of the block totals, serial per thread chunk
-  __shared__ int part[SCAN_B];
+// exclusive scan of cnt[0 .. n): per block, block totals, then offsets.  The
+// local pass also lists the cells that have work, ascending, at the front of
+// the block's segment of active: a cell of a material with impact ionization
+// holding a particle, else any cell holding two when collisions are on.
+__global__ __launch_bounds__(SCAN_B) void k_col_scan_local(const Inst I, ColBufs b, int n) {
+  __shared__ int w[SCAN_B / 64 + 1];
+  const int c = blockIdx.x * SCAN_B + threadIdx.x;
+  const int cnt = c < n ? b.cnt[c] : 0;
+  bool list = false;
+  if (cnt > 0) {
+    bool imp = false;
+    if (b.impact) {
+      const int m = I.mat_cell[c % I.nx];
+      imp = m >= 0 && b.imp_P[m] > 0.0;
+    }
+    list = imp || (b.collide && cnt >= 2);
+  }
+  int tot;
+  const int off = block_scan(cnt, w, &tot);
+  if (c < n) b.cnt[c] = off;
+  if (threadIdx.x == 0) b.bsum[blockIdx.x] = tot;
+  const int r = block_scan(list ? 1 : 0, w, &tot);
+  if (list) b.active[blockIdx.x * SCAN_B + r] = c;
+  if (threadIdx.x == 0) b.bact[blockIdx.x] = tot;
+}
+
+// one block: exclusive scans of the block totals (bsum) and of the blocks'
+// listed cells (bact, whose entry nb takes the total), each thread a chunk
+__global__ __launch_bounds__(SCAN_B) void k_col_scan_top(ColBufs b, int nb) {
+  __shared__ int w[SCAN_B / 64 + 1];
   const int per = (nb + SCAN_B - 1) / SCAN_B;
-  const int t = threadIdx.x;
-  int sum = 0;
-  for (int q = 0; q < per; ++q) {
-    const int i = t * per + q;
-    if (i < nb) sum += b.bsum[i];
-  }
-  part[t] = sum;
-  __syncthreads();
-  if (t == 0) {
-    int run = 0;
-    for (int q = 0; q < SCAN_B; ++q) {
-      const int v = part[q];
-      part[q] = run;
-      run += v;
-    }
-  }
-  __syncthreads();
-  int run = part[t];
-  for (int q = 0; q < per; ++q) {
-    const int i = t * per + q;
-    if (i < nb) {
-      const int v = b.bsum[i];
-      b.bsum[i] = run;
-      run += v;
-    }
+  const int t0 = threadIdx.x * per;
+  for (int a = 0; a < 2; ++a) {
+    int* v = a ? b.bact : b.bsum;
+    int sum = 0;
+    for (int q = 0; q < per; ++q)
+      if (t0 + q < nb) sum += v[t0 + q];
+    int tot;
+    int run = block_scan(sum, w, &tot);
+    for (int q = 0; q < per; ++q)
+      if (t0 + q < nb) {
+        const int x = v[t0 + q];
+        v[t0 + q] = run;
+        run += x;
+      }
+    if (a && threadIdx.x == 0) v[nb] = tot;
   }
 }
 
-__global__ void k_col_scan_add(ColBufs b, int n) {
+// offsets of the blocks added; each block's listed cells gathered into list
+__global__ __launch_bounds__(SCAN_B) void k_col_scan_add(ColBufs b, int n) {
   const int i = blockIdx.x * SCAN_B + threadIdx.x;
   if (i < n) b.cnt[i] += b.bsum[blockIdx.x];
+  const int a0 = b.bact[blockIdx.x], na = b.bact[blockIdx.x + 1] - a0;
+  if ((int)threadIdx.x < na) b.list[a0 + threadIdx.x] = b.active[i];
 }
 
 __global__ void k_col_fill(const Inst I, ColBufs b, int step) {
@@ -294,7 +313,7 @@ __device__ __forceinline__ bool before(const uint8_t* kind, const uint32_t* pid,
 // Impact ionization in cell c (its entries ordered): each electron of the
 // cell's material decides once; an event takes the cell's alive neutral of
 // lowest index, the electron pays the gap, the pair is born at the neutral.
-__device__ void impact_cell(const ColBufs& b, const PView& pv, const ImpView& v, const uint8_t* kind,
+__device__ __forceinline__ void impact_cell(const ColBufs& b, const PView& pv, const ImpView& v, const uint8_t* kind,
                             const double* smass, int c, int e0, int e1, int step) {
   const int i = c % v.nx, j = (c / v.nx) % v.ny, k = c / (v.nx * v.ny);
   const int m = v.mat_cell[i];
@@ -350,11 +369,11 @@ __device__ void impact_cell(const ColBufs& b, const PView& pv, const ImpView& v,
   }
 }
 
-__device__ void collide_sorted(const ColBufs& b, const PView& pv, const uint8_t* kind, double vcell,
+__device__ __forceinline__ void collide_sorted(const ColBufs& b, const PView& pv, const uint8_t* kind, double vcell,
                                const double* smass, const double* sw, int e0, int e1, int step);
 
 // the collisions (at least two particles) and the impact ionization of one cell
-__device__ __noinline__ void collide_cell(const ColBufs& b, const PView& pv, const ImpView& iv, const uint8_t* kind,
+__device__ __forceinline__ void collide_cell(const ColBufs& b, const PView& pv, const ImpView& iv, const uint8_t* kind,
                                           double vcell, const double* smass, const double* sw, int c, int step) {
   const int e0 = b.cnt[c], e1 = b.cnt[c + 1];
   // insertion sort of the cell's entries
@@ -375,18 +394,18 @@ __device__ __noinline__ void collide_cell(const ColBufs& b, const PView& pv, con
 }
 
 // the collisions of a cell's ordered entries [e0, e1)
-__device__ void collide_sorted(const ColBufs& b, const PView& pv, const uint8_t* kind, double vcell,
+__device__ __forceinline__ void collide_sorted(const ColBufs& b, const PView& pv, const uint8_t* kind, double vcell,
                                const double* smass, const double* sw, int e0, int e1, int step) {
   // kinds present: their entry ranges, densities and temperatures
   int kfirst[MAXKIND], kcount[MAXKIND];
   CellKinds ck;
-  for (int k = 0; k < MAXKIND; ++k) {
+  for (int k = 0; k < b.nk; ++k) {
     kcount[k] = 0;
     kfirst[k] = 0;
     ck.dens[k] = 0.0;
   }
   double ke[MAXKIND];
-  for (int k = 0; k < MAXKIND; ++k) ke[k] = 0.0;
+  for (int k = 0; k < b.nk; ++k) ke[k] = 0.0;
   for (int a = e0; a < e1; ++a) {
     const int p = b.idx[a];
     const int k = kind[p];
@@ -396,7 +415,7 @@ __device__ void collide_sorted(const ColBufs& b, const PView& pv, const uint8_t*
     ke[k] += (sqrt(1.0 + (ux * ux + uy * uy + uz * uz)) - 1.0) * smass[k] * kC * kC;
   }
   double inv_ld2 = 0.0;
-  for (int k = 0; k < MAXKIND; ++k) {
+  for (int k = 0; k < b.nk; ++k) {
     ck.mn13[k] = 0.0;
     if (!kcount[k]) continue;
     ck.dens[k] = kcount[k] * sw[k] / vcell;
@@ -406,7 +425,7 @@ __device__ void collide_sorted(const ColBufs& b, const PView& pv, const uint8_t*
   }
   ck.ld = inv_ld2 > 0.0 ? 1.0 / sqrt(inv_ld2) : 0.0;
   // like kinds
-  for (int k = 0; k < MAXKIND; ++k) {
+  for (int k = 0; k < b.nk; ++k) {
     const int N = kcount[k];
     if (N < 2) continue;
     const int f = kfirst[k];
@@ -421,9 +440,9 @@ __device__ void collide_sorted(const ColBufs& b, const PView& pv, const uint8_t*
     for (int a = start; a + 1 < N; a += 2) collide_pair(pv, ck, b.dt, b.idx[f + a], b.idx[f + a + 1], k, k, n, false, 0, step);
   }
   // unlike kinds
-  for (int ka = 0; ka < MAXKIND; ++ka) {
+  for (int ka = 0; ka < b.nk; ++ka) {
     if (!kcount[ka]) continue;
-    for (int kb = ka + 1; kb < MAXKIND; ++kb) {
+    for (int kb = ka + 1; kb < b.nk; ++kb) {
       if (!kcount[kb]) continue;
       const int Na = kcount[ka], Nb = kcount[kb];
       const int nmin = Na < Nb ? Na : Nb, nmax = Na < Nb ? Nb : Na;
@@ -435,7 +454,7 @@ __device__ void collide_sorted(const ColBufs& b, const PView& pv, const uint8_t*
   }
 }
 
-__global__ __launch_bounds__(256) void k_col_cells(const Inst I, ColBufs b, int step) {
+__global__ __launch_bounds__(256, 2) void k_col_cells(const Inst I, ColBufs b, int step, int nb) {
   __shared__ double smass[MAXKIND], sw[MAXKIND];
   if (threadIdx.x < MAXKIND) {
     smass[threadIdx.x] = I.kmass[threadIdx.x];
@@ -445,9 +464,9 @@ __global__ __launch_bounds__(256) void k_col_cells(const Inst I, ColBufs b, int 
   const PView pv{I.pu0, I.pu1, I.pu2, I.pid, I.seed, smass, sw};
   const ImpView iv{I.alive, I.death, I.no0, I.no1, I.no2, I.pcell, I.po0, I.po1, I.po2, I.pkind, I.pcount,
                    I.health, I.nevents, I.ksig, I.mat_cell, I.capacity, I.D, I.nx, I.ny, I.ppc};
-  const int nact = *b.nactive;
+  const int nact = b.bact[nb];
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nact; q += gridDim.x * blockDim.x)
-    collide_cell(b, pv, iv, I.pkind, I.vcell, smass, sw, b.active[q], step);
+    collide_cell(b, pv, iv, I.pkind, I.vcell, smass, sw, b.list[q], step);
 }
 
 }  // namespace
@@ -464,16 +483,16 @@ void launch_collide(const Inst& I, const ColBufs& b, int step, hipStream_t s, St
   else
     hipLaunchKernelGGL(k_col_clear, dim3((n + 255) / 256), dim3(256), 0, s, b);
   hipLaunchKernelGGL(k_col_count, dim3(slots / 256), dim3(256), 0, s, I, b);
-  hipLaunchKernelGGL(k_col_scan_local, dim3(nb), dim3(SCAN_B), 0, s, b, n);
+  hipLaunchKernelGGL(k_col_scan_local, dim3(nb), dim3(SCAN_B), 0, s, I, b, n);
   hipLaunchKernelGGL(k_col_scan_top, dim3(1), dim3(SCAN_B), 0, s, b, nb);
   hipLaunchKernelGGL(k_col_scan_add, dim3(nb), dim3(SCAN_B), 0, s, b, n);
   hipLaunchKernelGGL(k_col_fill, dim3(slots / 256), dim3(256), 0, s, I, b, step);
   // one thread per listed cell (at most one per slot), grid-stride
   const int cb = std::min(4096, std::max(1, (I.capacity + 255) / 256));
   if (st.stop)
-    hipExtLaunchKernelGGL(k_col_cells, dim3(cb), dim3(256), 0, s, nullptr, st.stop, 0, I, b, step);
+    hipExtLaunchKernelGGL(k_col_cells, dim3(cb), dim3(256), 0, s, nullptr, st.stop, 0, I, b, step, nb);
   else
-    hipLaunchKernelGGL(k_col_cells, dim3(cb), dim3(256), 0, s, I, b, step);
+    hipLaunchKernelGGL(k_col_cells, dim3(cb), dim3(256), 0, s, I, b, step, nb);
 }
 
 }  // namespace pic

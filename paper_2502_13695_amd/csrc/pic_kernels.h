@@ -60,17 +60,24 @@ void launch_advance(Inst* insts, int n, hipStream_t s);   // batch: step counter
 
 // Binary collisions (a single run): device work arrays over the box cells
 // (ncell = nx ny nz) and the charged slots.
+constexpr int COL_SCAN_B = 1024;   // cells per block of the cell scan
 struct ColBufs {
   int* cnt;       // ncell + 1: particles per cell, then (scanned) each cell's first index
   int* fill;      // ncell: particles placed per cell
   int* bsum;      // col_scan_blocks(ncell + 1) + 1: block sums of the scan
   int* idx;       // capacity: slots ordered by cell
   uint32_t* key;  // capacity: pairing key of each entry of idx
-  int* active;    // the cells that take part (collisions: at least two particles;
-                  // impact ionization: at least one), at most capacity + 1
-  int* nactive;   // their number
+  // the cells that take part (collisions: at least two particles; impact
+  // ionization: at least one): listed per block of COL_SCAN_B cells at the
+  // front of that block's COL_SCAN_B entries of active, their number per
+  // block in bact (then scanned: the blocks' offsets, the total last), then
+  // gathered into list
+  int* active;    // col_scan_blocks(ncell + 1) * COL_SCAN_B
+  int* bact;      // col_scan_blocks(ncell + 1) + 1
+  int* list;      // capacity
   int ncell;
   double dt;      // time step [s]
+  int nk;         // particle kinds of the run (2 per material)
   int collide;    // binary collisions
   int impact;     // impact ionization
   // impact ionization: per material the rate constant [1/s], threshold [J]

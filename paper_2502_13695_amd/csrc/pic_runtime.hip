@@ -231,7 +231,9 @@ pic_status plan(const pic_config* cfg, const Canon& c, const std::vector<TableHo
     L->o_cbsum = take(sizeof(int) * (size_t)(on ? col_scan_blocks((int)nbox + 1) + 1 : 0));
     L->o_cidx = take(sizeof(int) * (size_t)cap);
     L->o_ckey = take(sizeof(uint32_t) * (size_t)cap);
-    L->o_cact = take(sizeof(int) * (size_t)(on ? cap + 2 : 0));   // cells, then the count
+    // listed cells per scan block, the blocks' counts and their total, the list
+    L->o_cact = take(sizeof(int) * (size_t)(on ? (int64_t)col_scan_blocks((int)nbox + 1) * (COL_SCAN_B + 1) + 1 + cap
+                                               : 0));
     L->o_mrank = take(sizeof(int) * (size_t)(on ? c.n[0] : 0));
   }
   L->total = o;
@@ -869,9 +871,12 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
     c->col.idx = (int*)devp(c, L.o_cidx);
     c->col.key = (uint32_t*)devp(c, L.o_ckey);
     c->col.active = (int*)devp(c, L.o_cact);
-    c->col.nactive = c->col.active + L.capacity + 1;
+    const int nsb = col_scan_blocks((int)(K.n[0] * K.n[1] * K.n[2]) + 1);
+    c->col.bact = c->col.active + (size_t)nsb * COL_SCAN_B;
+    c->col.list = c->col.bact + nsb + 1;
     c->col.ncell = (int)(K.n[0] * K.n[1] * K.n[2]);
     c->col.dt = K.dt;
+    c->col.nk = 2 * K.nmat;
     c->col.collide = K.collide;
     c->col.impact = K.impact;
     for (int m = 0; m < K.nmat; ++m) {
