@@ -157,7 +157,7 @@ __global__ void k_col_fill(const Inst I, ColBufs b, int step) {
     const int c = box_cell(I, I.pcell[p]);
     const int q = b.cnt[c] + atomicAdd(&b.fill[c], 1);
     b.idx[q] = p;
-    b.key[q] = draw(I.seed, (uint64_t)I.pid[p] | ((uint64_t)kd << 32), (uint32_t)step, PURPOSE_PAIR).x;
+    b.key[q] = (uint64_t)kd << 32 | draw(I.seed, (uint64_t)I.pid[p] | ((uint64_t)kd << 32), (uint32_t)step, PURPOSE_PAIR).x;
   }
 }
 
@@ -301,11 +301,8 @@ __device__ __forceinline__ void collide_pair(const PView& I, const CellKinds& ck
   }
 }
 
-// entry order inside a cell: (kind, key, id)
-__device__ __forceinline__ bool before(const uint8_t* kind, const uint32_t* pid, int pa, uint32_t ka, int pb,
-                                       uint32_t kb) {
-  const uint32_t da = kind[pa], db = kind[pb];
-  if (da != db) return da < db;
+// entry order inside a cell: (kind, key, id), the first two in one word
+__device__ __forceinline__ bool before(const uint32_t* pid, uint64_t ka, int pa, uint64_t kb, int pb) {
   if (ka != kb) return ka < kb;
   return pid[pa] < pid[pb];
 }
@@ -372,22 +369,49 @@ __device__ __forceinline__ void impact_cell(const ColBufs& b, const PView& pv, c
 __device__ __forceinline__ void collide_sorted(const ColBufs& b, const PView& pv, const uint8_t* kind, double vcell,
                                const double* smass, const double* sw, int e0, int e1, int step);
 
-// the collisions (at least two particles) and the impact ionization of one cell
+constexpr int SORT_LDS = 16;    // entries of a cell sorted in LDS (larger cells: in place)
+constexpr int CELLS_TPB = 256;  // threads per block of the cell pass
+
+// the collisions (at least two particles) and the impact ionization of one
+// cell; sk / si: this thread's SORT_LDS LDS entries, stride CELLS_TPB
 __device__ __forceinline__ void collide_cell(const ColBufs& b, const PView& pv, const ImpView& iv, const uint8_t* kind,
-                                          double vcell, const double* smass, const double* sw, int c, int step) {
+                                             double vcell, const double* smass, const double* sw, uint64_t* sk,
+                                             int* si, int c, int step) {
   const int e0 = b.cnt[c], e1 = b.cnt[c + 1];
+  const int n = e1 - e0;
+  constexpr int st = CELLS_TPB;
   // insertion sort of the cell's entries
-  for (int a = e0 + 1; a < e1; ++a) {
-    const int p = b.idx[a];
-    const uint32_t k = b.key[a];
-    int j = a - 1;
-    while (j >= e0 && before(kind, pv.pid, p, k, b.idx[j], b.key[j])) {
-      b.idx[j + 1] = b.idx[j];
-      b.key[j + 1] = b.key[j];
-      --j;
+  if (n <= SORT_LDS) {
+    for (int a = 0; a < n; ++a) {
+      sk[a * st] = b.key[e0 + a];
+      si[a * st] = b.idx[e0 + a];
     }
-    b.idx[j + 1] = p;
-    b.key[j + 1] = k;
+    for (int a = 1; a < n; ++a) {
+      const int p = si[a * st];
+      const uint64_t k = sk[a * st];
+      int j = a - 1;
+      while (j >= 0 && before(pv.pid, k, p, sk[j * st], si[j * st])) {
+        si[(j + 1) * st] = si[j * st];
+        sk[(j + 1) * st] = sk[j * st];
+        --j;
+      }
+      si[(j + 1) * st] = p;
+      sk[(j + 1) * st] = k;
+    }
+    for (int a = 0; a < n; ++a) b.idx[e0 + a] = si[a * st];
+  } else {
+    for (int a = e0 + 1; a < e1; ++a) {
+      const int p = b.idx[a];
+      const uint64_t k = b.key[a];
+      int j = a - 1;
+      while (j >= e0 && before(pv.pid, k, p, b.key[j], b.idx[j])) {
+        b.idx[j + 1] = b.idx[j];
+        b.key[j + 1] = b.key[j];
+        --j;
+      }
+      b.idx[j + 1] = p;
+      b.key[j + 1] = k;
+    }
   }
   if (b.collide && e1 - e0 >= 2) collide_sorted(b, pv, kind, vcell, smass, sw, e0, e1, step);
   if (b.impact) impact_cell(b, pv, iv, kind, smass, c, e0, e1, step);
@@ -454,8 +478,10 @@ __device__ __forceinline__ void collide_sorted(const ColBufs& b, const PView& pv
   }
 }
 
-__global__ __launch_bounds__(256, 2) void k_col_cells(const Inst I, ColBufs b, int step, int nb) {
+__global__ __launch_bounds__(CELLS_TPB, 2) void k_col_cells(const Inst I, ColBufs b, int step, int nb) {
   __shared__ double smass[MAXKIND], sw[MAXKIND];
+  __shared__ uint64_t skey[SORT_LDS * CELLS_TPB];
+  __shared__ int sidx[SORT_LDS * CELLS_TPB];
   if (threadIdx.x < MAXKIND) {
     smass[threadIdx.x] = I.kmass[threadIdx.x];
     sw[threadIdx.x] = I.kw[threadIdx.x];
@@ -466,7 +492,7 @@ __global__ __launch_bounds__(256, 2) void k_col_cells(const Inst I, ColBufs b, i
                    I.health, I.nevents, I.ksig, I.mat_cell, I.capacity, I.D, I.nx, I.ny, I.ppc};
   const int nact = b.bact[nb];
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nact; q += gridDim.x * blockDim.x)
-    collide_cell(b, pv, iv, I.pkind, I.vcell, smass, sw, b.list[q], step);
+    collide_cell(b, pv, iv, I.pkind, I.vcell, smass, sw, skey + threadIdx.x, sidx + threadIdx.x, b.list[q], step);
 }
 
 }  // namespace
@@ -488,11 +514,11 @@ void launch_collide(const Inst& I, const ColBufs& b, int step, hipStream_t s, St
   hipLaunchKernelGGL(k_col_scan_add, dim3(nb), dim3(SCAN_B), 0, s, b, n);
   hipLaunchKernelGGL(k_col_fill, dim3(slots / 256), dim3(256), 0, s, I, b, step);
   // one thread per listed cell (at most one per slot), grid-stride
-  const int cb = std::min(4096, std::max(1, (I.capacity + 255) / 256));
+  const int cb = std::min(4096, std::max(1, (I.capacity + CELLS_TPB - 1) / CELLS_TPB));
   if (st.stop)
-    hipExtLaunchKernelGGL(k_col_cells, dim3(cb), dim3(256), 0, s, nullptr, st.stop, 0, I, b, step, nb);
+    hipExtLaunchKernelGGL(k_col_cells, dim3(cb), dim3(CELLS_TPB), 0, s, nullptr, st.stop, 0, I, b, step, nb);
   else
-    hipLaunchKernelGGL(k_col_cells, dim3(cb), dim3(256), 0, s, I, b, step, nb);
+    hipLaunchKernelGGL(k_col_cells, dim3(cb), dim3(CELLS_TPB), 0, s, I, b, step, nb);
 }
 
 }  // namespace pic

@@ -66,7 +66,7 @@ struct ColBufs {
   int* fill;      // ncell: particles placed per cell
   int* bsum;      // col_scan_blocks(ncell + 1) + 1: block sums of the scan
   int* idx;       // capacity: slots ordered by cell
-  uint32_t* key;  // capacity: pairing key of each entry of idx
+  uint64_t* key;  // capacity: order key of each entry of idx (kind, then the pairing key)
   // the cells that take part (collisions: at least two particles; impact
   // ionization: at least one): listed per block of COL_SCAN_B cells at the
   // front of that block's COL_SCAN_B entries of active, their number per

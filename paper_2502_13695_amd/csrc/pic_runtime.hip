@@ -230,7 +230,7 @@ pic_status plan(const pic_config* cfg, const Canon& c, const std::vector<TableHo
     L->o_cfill = take(sizeof(int) * (size_t)nbox);
     L->o_cbsum = take(sizeof(int) * (size_t)(on ? col_scan_blocks((int)nbox + 1) + 1 : 0));
     L->o_cidx = take(sizeof(int) * (size_t)cap);
-    L->o_ckey = take(sizeof(uint32_t) * (size_t)cap);
+    L->o_ckey = take(sizeof(uint64_t) * (size_t)cap);
     // listed cells per scan block, the blocks' counts and their total, the list
     L->o_cact = take(sizeof(int) * (size_t)(on ? (int64_t)col_scan_blocks((int)nbox + 1) * (COL_SCAN_B + 1) + 1 + cap
                                                : 0));
@@ -869,7 +869,7 @@ pic_status pic_init(const pic_config* cfg_in, pic_ctx** out) {
     c->col.fill = (int*)devp(c, L.o_cfill);
     c->col.bsum = (int*)devp(c, L.o_cbsum);
     c->col.idx = (int*)devp(c, L.o_cidx);
-    c->col.key = (uint32_t*)devp(c, L.o_ckey);
+    c->col.key = (uint64_t*)devp(c, L.o_ckey);
     c->col.active = (int*)devp(c, L.o_cact);
     const int nsb = col_scan_blocks((int)(K.n[0] * K.n[1] * K.n[2]) + 1);
     c->col.bact = c->col.active + (size_t)nsb * COL_SCAN_B;
