@@ -208,12 +208,6 @@ struct ImpView {
   int capacity, D, nx, ny, ppc;
 };
 
-struct CellKinds {
-  double dens[MAXKIND];   // number density [m^-3]
-  double mn13[MAXKIND];   // m n^(-1/3) of each kind present (the low-temperature cap)
-  double ld;              // Debye length of the cell (0: none)
-};
-
 // what a collision reads and writes (the kinds' masses and weights in LDS)
 struct PView {
   float *u0, *u1, *u2;
@@ -223,8 +217,10 @@ struct PView {
   const double* w;
 };
 
-// One collision of entries a (kind ka) and b (kind kb); updates the slots' momenta.
-__device__ __forceinline__ void collide_pair(const PView& I, const CellKinds& ck, double dt, int pa, int pb, int ka,
+// One collision of entries a (kind ka) and b (kind kb); updates the slots'
+// momenta.  ld: the cell's Debye length (0: none); mn13: the larger m n^(-1/3)
+// of the two kinds (the low-temperature cap); n: the density in s.
+__device__ __forceinline__ void collide_pair(const PView& I, double ld, double mn13, double dt, int pa, int pb, int ka,
                                              int kb, double n, bool half, uint32_t r, int step) {
   const double m1 = I.mass[ka], m2 = I.mass[kb];
   const double q1 = (ka & 1) ? kQE : -kQE, q2 = (kb & 1) ? kQE : -kQE;
@@ -248,8 +244,7 @@ __device__ __forceinline__ void collide_pair(const PView& I, const CellKinds& ck
   const double v1s = P / (m1 * g1s), v2s = P / (m2 * g2s);
   const double vrel = (v1s + v2s) / (1.0 + v1s * v2s / (kC * kC));
   double lnL = 1.0;
-  if (ck.ld > 0.0) {
-    const double ld = ck.ld;
+  if (ld > 0.0) {
     const double bcl = fabs(q1 * q2) / (4.0 * kPI * kEPS0 * mu * vrel * vrel);
     const double bqm = kHBAR / (2.0 * mu * vrel);
     lnL = fmax(1.0, log(ld / fmax(bcl, bqm)));
@@ -257,7 +252,7 @@ __device__ __forceinline__ void collide_pair(const PView& I, const CellKinds& ck
   const double f = m1 * g1s * m2 * g2s * kC * kC / (P * P) + 1.0;
   double s = n * dt * lnL * (q1 * q2) * (q1 * q2) /
              (4.0 * kPI * kEPS0 * kEPS0 * kC * kC * kC * kC * m1 * g1 * m2 * g2) * gc * P / (m1 * g1 + m2 * g2) * f * f;
-  const double cap = 1.6119919540164696 * dt * (m1 + m2) * vrel / fmax(ck.mn13[ka], ck.mn13[kb]);   // (4 pi / 3)^(1/3)
+  const double cap = 1.6119919540164696 * dt * (m1 + m2) * vrel / mn13;   // (4 pi / 3)^(1/3)
   s = fmin(s, cap);
   if (half) s *= 0.5;
   const uint32_t hi = (uint32_t)ka | ((uint32_t)kb << 8) | (r << 16);
@@ -366,8 +361,10 @@ __device__ __forceinline__ void impact_cell(const ColBufs& b, const PView& pv, c
   }
 }
 
-__device__ __forceinline__ void collide_sorted(const ColBufs& b, const PView& pv, const uint8_t* kind, double vcell,
-                               const double* smass, const double* sw, int e0, int e1, int step);
+__device__ __noinline__ void collide_sorted_any(const int* idx, int nk, double dt, PView pv, const uint8_t* kind,
+                                                double vcell, int e0, int e1, int step);
+__device__ __forceinline__ bool collide_groups(const ColBufs& b, const PView& pv, const uint8_t* kind, double vcell,
+                                               const double* smass, const double* sw, int e0, int e1, int step);
 
 constexpr int SORT_LDS = 16;    // entries of a cell sorted in LDS (larger cells: in place)
 constexpr int CELLS_TPB = 256;  // threads per block of the cell pass
@@ -413,25 +410,29 @@ __device__ __forceinline__ void collide_cell(const ColBufs& b, const PView& pv, 
       b.key[j + 1] = k;
     }
   }
-  if (b.collide && e1 - e0 >= 2) collide_sorted(b, pv, kind, vcell, smass, sw, e0, e1, step);
+  if (b.collide && e1 - e0 >= 2 && !collide_groups(b, pv, kind, vcell, smass, sw, e0, e1, step))
+    collide_sorted_any(b.idx, b.nk, b.dt, pv, kind, vcell, e0, e1, step);
   if (b.impact) impact_cell(b, pv, iv, kind, smass, c, e0, e1, step);
 }
 
-// the collisions of a cell's ordered entries [e0, e1)
-__device__ __forceinline__ void collide_sorted(const ColBufs& b, const PView& pv, const uint8_t* kind, double vcell,
-                               const double* smass, const double* sw, int e0, int e1, int step) {
+// The collisions of a cell's ordered entries [e0, e1), any number of kinds:
+// per-kind tables (kept in scratch).  Cells with at most GMAX kinds take
+// collide_groups below, which gives the same results.
+__device__ __noinline__ void collide_sorted_any(const int* idx, int nk, double dt, PView pv, const uint8_t* kind,
+                                                double vcell, int e0, int e1, int step) {
+  const double* smass = pv.mass;
+  const double* sw = pv.w;
   // kinds present: their entry ranges, densities and temperatures
   int kfirst[MAXKIND], kcount[MAXKIND];
-  CellKinds ck;
-  for (int k = 0; k < b.nk; ++k) {
+  double dens[MAXKIND], mn13[MAXKIND], ke[MAXKIND];
+  for (int k = 0; k < nk; ++k) {
     kcount[k] = 0;
     kfirst[k] = 0;
-    ck.dens[k] = 0.0;
+    dens[k] = 0.0;
+    ke[k] = 0.0;
   }
-  double ke[MAXKIND];
-  for (int k = 0; k < b.nk; ++k) ke[k] = 0.0;
   for (int a = e0; a < e1; ++a) {
-    const int p = b.idx[a];
+    const int p = idx[a];
     const int k = kind[p];
     if (kcount[k] == 0) kfirst[k] = a;
     ++kcount[k];
@@ -439,43 +440,140 @@ __device__ __forceinline__ void collide_sorted(const ColBufs& b, const PView& pv
     ke[k] += (sqrt(1.0 + (ux * ux + uy * uy + uz * uz)) - 1.0) * smass[k] * kC * kC;
   }
   double inv_ld2 = 0.0;
-  for (int k = 0; k < b.nk; ++k) {
-    ck.mn13[k] = 0.0;
+  for (int k = 0; k < nk; ++k) {
+    mn13[k] = 0.0;
     if (!kcount[k]) continue;
-    ck.dens[k] = kcount[k] * sw[k] / vcell;
-    ck.mn13[k] = smass[k] / cbrt(ck.dens[k]);
+    dens[k] = kcount[k] * sw[k] / vcell;
+    mn13[k] = smass[k] / cbrt(dens[k]);
     const double T = 2.0 / 3.0 * ke[k] / kcount[k];
-    if (T > 0.0) inv_ld2 += ck.dens[k] * kQE * kQE / (kEPS0 * T);
+    if (T > 0.0) inv_ld2 += dens[k] * kQE * kQE / (kEPS0 * T);
   }
-  ck.ld = inv_ld2 > 0.0 ? 1.0 / sqrt(inv_ld2) : 0.0;
+  const double ld = inv_ld2 > 0.0 ? 1.0 / sqrt(inv_ld2) : 0.0;
   // like kinds
-  for (int k = 0; k < b.nk; ++k) {
+  for (int k = 0; k < nk; ++k) {
     const int N = kcount[k];
     if (N < 2) continue;
     const int f = kfirst[k];
-    const double n = ck.dens[k];
+    const double n = dens[k], m = mn13[k];
     int start = 0;
     if (N & 1) {
-      collide_pair(pv, ck, b.dt, b.idx[f], b.idx[f + 1], k, k, n, true, 0, step);
-      collide_pair(pv, ck, b.dt, b.idx[f + 1], b.idx[f + 2], k, k, n, true, 0, step);
-      collide_pair(pv, ck, b.dt, b.idx[f + 2], b.idx[f], k, k, n, true, 0, step);
+      collide_pair(pv, ld, m, dt, idx[f], idx[f + 1], k, k, n, true, 0, step);
+      collide_pair(pv, ld, m, dt, idx[f + 1], idx[f + 2], k, k, n, true, 0, step);
+      collide_pair(pv, ld, m, dt, idx[f + 2], idx[f], k, k, n, true, 0, step);
       start = 3;
     }
-    for (int a = start; a + 1 < N; a += 2) collide_pair(pv, ck, b.dt, b.idx[f + a], b.idx[f + a + 1], k, k, n, false, 0, step);
+    for (int a = start; a + 1 < N; a += 2) collide_pair(pv, ld, m, dt, idx[f + a], idx[f + a + 1], k, k, n, false, 0, step);
   }
   // unlike kinds
-  for (int ka = 0; ka < b.nk; ++ka) {
+  for (int ka = 0; ka < nk; ++ka) {
     if (!kcount[ka]) continue;
-    for (int kb = ka + 1; kb < b.nk; ++kb) {
+    for (int kb = ka + 1; kb < nk; ++kb) {
       if (!kcount[kb]) continue;
       const int Na = kcount[ka], Nb = kcount[kb];
       const int nmin = Na < Nb ? Na : Nb, nmax = Na < Nb ? Nb : Na;
-      const double n = nmin * fmax(sw[ka], sw[kb]) / vcell;
+      const double n = nmin * fmax(sw[ka], sw[kb]) / vcell, m = fmax(mn13[ka], mn13[kb]);
       for (int i = 0; i < nmax; ++i)
-        collide_pair(pv, ck, b.dt, b.idx[kfirst[ka] + i % Na], b.idx[kfirst[kb] + i % Nb], ka, kb, n, false,
+        collide_pair(pv, ld, m, dt, idx[kfirst[ka] + i % Na], idx[kfirst[kb] + i % Nb], ka, kb, n, false,
                      (uint32_t)(i / nmin), step);
     }
   }
+}
+
+constexpr int GMAX = 4;   // kinds of a cell whose tables stay in registers
+
+// a[g] for a wave-varying g, as a chain of selects (keeps a in registers)
+template <typename T>
+__device__ __forceinline__ T pick(const T (&a)[GMAX], int g) {
+  T r = a[0];
+#pragma unroll
+  for (int i = 1; i < GMAX; ++i) r = g == i ? a[i] : r;
+  return r;
+}
+
+// The collisions of a cell's ordered entries [e0, e1) holding at most GMAX
+// kinds: the kinds present form groups of consecutive entries, ascending; the
+// sequence, densities, temperatures and sums are those of collide_sorted_any.
+// Returns false, having changed nothing, for a cell with more kinds.
+__device__ __forceinline__ bool collide_groups(const ColBufs& b, const PView& pv, const uint8_t* kind, double vcell,
+                                               const double* smass, const double* sw, int e0, int e1, int step) {
+  int gk[GMAX], gf[GMAX], gn[GMAX];
+  double gke[GMAX];
+#pragma unroll
+  for (int g = 0; g < GMAX; ++g) {
+    gk[g] = 0;
+    gf[g] = 0;
+    gn[g] = 0;
+    gke[g] = 0.0;
+  }
+  int G = 0, last = -1;
+  for (int a = e0; a < e1; ++a) {
+    const int p = b.idx[a];
+    const int k = kind[p];
+    if (k != last) {
+      if (G == GMAX) return false;
+#pragma unroll
+      for (int g = 0; g < GMAX; ++g)
+        if (g == G) {
+          gk[g] = k;
+          gf[g] = a;
+        }
+      ++G;
+      last = k;
+    }
+    const double ux = pv.u0[p], uy = pv.u1[p], uz = pv.u2[p];
+    const double e = (sqrt(1.0 + (ux * ux + uy * uy + uz * uz)) - 1.0) * smass[k] * kC * kC;
+#pragma unroll
+    for (int g = 0; g < GMAX; ++g)
+      if (g == G - 1) {
+        ++gn[g];
+        gke[g] += e;
+      }
+  }
+  double dens[GMAX], mn13[GMAX];
+  double inv_ld2 = 0.0;
+#pragma unroll
+  for (int g = 0; g < GMAX; ++g) {
+    dens[g] = 0.0;
+    mn13[g] = 0.0;
+    if (g < G) {
+      const int k = gk[g];
+      dens[g] = gn[g] * sw[k] / vcell;
+      mn13[g] = smass[k] / cbrt(dens[g]);
+      const double T = 2.0 / 3.0 * gke[g] / gn[g];
+      if (T > 0.0) inv_ld2 += dens[g] * kQE * kQE / (kEPS0 * T);
+    }
+  }
+  const double ld = inv_ld2 > 0.0 ? 1.0 / sqrt(inv_ld2) : 0.0;
+  // like kinds
+  for (int g = 0; g < G; ++g) {
+    const int N = pick(gn, g);
+    if (N < 2) continue;
+    const int k = pick(gk, g), f = pick(gf, g);
+    const double n = pick(dens, g), m = pick(mn13, g);
+    int start = 0;
+    if (N & 1) {
+      collide_pair(pv, ld, m, b.dt, b.idx[f], b.idx[f + 1], k, k, n, true, 0, step);
+      collide_pair(pv, ld, m, b.dt, b.idx[f + 1], b.idx[f + 2], k, k, n, true, 0, step);
+      collide_pair(pv, ld, m, b.dt, b.idx[f + 2], b.idx[f], k, k, n, true, 0, step);
+      start = 3;
+    }
+    for (int a = start; a + 1 < N; a += 2)
+      collide_pair(pv, ld, m, b.dt, b.idx[f + a], b.idx[f + a + 1], k, k, n, false, 0, step);
+  }
+  // unlike kinds
+  for (int ga = 0; ga < G; ++ga) {
+    const int ka = pick(gk, ga), fa = pick(gf, ga), Na = pick(gn, ga);
+    const double ma = pick(mn13, ga);
+    for (int gb = ga + 1; gb < G; ++gb) {
+      const int kb = pick(gk, gb), fb = pick(gf, gb), Nb = pick(gn, gb);
+      const int nmin = Na < Nb ? Na : Nb, nmax = Na < Nb ? Nb : Na;
+      const double n = nmin * fmax(sw[ka], sw[kb]) / vcell, m = fmax(ma, pick(mn13, gb));
+      for (int i = 0; i < nmax; ++i)
+        collide_pair(pv, ld, m, b.dt, b.idx[fa + i % Na], b.idx[fb + i % Nb], ka, kb, n, false,
+                     (uint32_t)(i / nmin), step);
+    }
+  }
+  return true;
 }
 
 __global__ __launch_bounds__(CELLS_TPB, 2) void k_col_cells(const Inst I, ColBufs b, int step, int nb) {

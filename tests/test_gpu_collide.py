@@ -2,7 +2,8 @@
 against the FP64 oracle.
 
 * one step from a seeded random state with many particles per cell (two
-  materials, all four kinds, weak fields so nothing ionizes), 1D / 2D / 3D:
+  materials, all four kinds, weak fields so nothing ionizes), 1D / 2D / 3D,
+  and three materials in 2D (six kinds, most cells holding five or six):
   every particle's position and momentum element by element;
 * the tile sort on against off: the same momenta bit for bit (the pairing
   order is keyed by id and kind, not by the slot);
@@ -24,20 +25,25 @@ from test_gpu_parity import P, _compare_run, _records, _run_both, _state_f32, _t
 pytestmark = pytest.mark.gpu
 
 
-def _dense_cfg(ndim, n):
+def _dense_cfg(ndim, n, nmat=2):
     dx = W.LAMBDA / 30
+    mats = [dict(W.silica_like(), gap_eV=40.0), dict(W.high_index(), gap_eV=40.0),
+            dict(W.silica_like(), gap_eV=45.0, me_star=0.4, density_gcc=2.6)][:nmat]
+    L = n[0] * dx
     return dict(ndim=ndim, n=n, dx=[dx] * ndim, cfl=0.95, nsteps=10, transverse_bc="periodic",
                 # gaps far above the fields the deposit makes: nothing ionizes
-                materials=[dict(W.silica_like(), gap_eV=40.0), dict(W.high_index(), gap_eV=40.0)],
-                layers=[(0, 0.0, 0.5 * n[0] * dx), (1, 0.5 * n[0] * dx, n[0] * dx)],
+                materials=mats,
+                layers=[(m, m * L / nmat, (m + 1) * L / nmat) for m in range(nmat)],
                 ppc=2, T_K=300.0, shape_order=2, keldysh_terms=500, seed=21,
                 laser=dict(lambda_m=W.LAMBDA, fwhm_s=W.cycles(2), peak_Wcm2=1e10, envelope="gauss",
                            pol_axis=1), particle_capacity=0, preionize_eV=0.0, collisions=True)
 
 
-@pytest.mark.parametrize("ndim,n,npart", [(1, [48], 1500), (2, [16, 8], 3000), (3, [12, 6, 4], 3000)])
-def test_collisions_one_step_match_oracle(P, ndim, n, npart):
-    cfg = _dense_cfg(ndim, n)
+@pytest.mark.parametrize("ndim,n,npart,nmat", [(1, [48], 1500, 2), (2, [16, 8], 3000, 2), (3, [12, 6, 4], 3000, 2),
+                                               (2, [16, 8], 3000, 3)])
+def test_collisions_one_step_match_oracle(P, ndim, n, npart, nmat):
+    """nmat 3: six kinds, most cells hold more than four of them."""
+    cfg = _dense_cfg(ndim, n, nmat)
     st = _state_f32(W.random_state(cfg, npart, seed=300 + ndim, e_scale=1e6, u_scale=0.01, margin=3))
     ctx = P.Context(cfg)
     ctx.set_resort(0)
