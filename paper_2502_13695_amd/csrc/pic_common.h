@@ -170,7 +170,12 @@ constexpr int ION_NIT = 8;
 constexpr int ION_SMAT = 2, ION_SSEG = 16;   // rate-table segments staged in LDS per block
 __host__ __device__ constexpr int ion_nit(int64_t ppc) { return ppc < ION_NIT ? (int)ppc : ION_NIT; }
 constexpr int SORT_CHUNK = 1024;    // sorted particles per work item (piece of a tile)
-constexpr int SPARSE_CHUNK = 128;   // pieces this small skip the LDS windows
+// Pieces of at most sparse_chunk(D) particles skip the LDS windows and add
+// into HBM with FP32 atomics.  In 2D that is cheaper than staging and
+// flushing a window for a handful of particles; in 3D the HBM atomics of a
+// particle's three-dimensional stencil cost more than the window at any
+// chunk size (measured on the mirror share and the pre-ionized stress run).
+__host__ __device__ constexpr int sparse_chunk(int D) { return D == 3 ? 0 : 128; }
 // LDS deposit in 64-bit fixed point: a contribution v (|v| <= max |kq|) is
 // added as round(v * jscale) with jscale = 2^40 / 2^ceil(log2 max |kq|); a
 // node's sum over one work item (the particles within two cells of it) stays

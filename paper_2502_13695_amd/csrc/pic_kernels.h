@@ -28,9 +28,10 @@ struct Group {
   // host copy of a single run's parameter block: the field launch passes it
   // by value, so its fields load from the kernel arguments
   const Inst* host = nullptr;
-  // the field update advances Lorentz oscillators (some instance has a
-  // Lorentz medium): a kernel variant of its own, so static runs keep theirs
-  bool lor = false;
+  // dispersive media in the field update: 0 none; 1 Lorentz oscillators; 2
+  // Kerr terms too (some instance has them).  Each a kernel variant of its
+  // own, so runs without them keep their registers.
+  int lor = 0;
 };
 
 constexpr int TPB = 256;

@@ -763,7 +763,7 @@ __global__ __launch_bounds__(push_tpb(D), D == 3 ? 4 : 1) void k_push(Group g, s
     }
     const int ntot = n_sorted + 2 * nbirth;
     if (ntot == 0) return;
-    if (ntot <= SPARSE_CHUNK) {
+    if (ntot <= sparse_chunk(D)) {
       // a sparse piece (one pass of the block): HBM atomics cost less than
       // staging and flushing the windows
       const int i = threadIdx.x;
@@ -1319,7 +1319,7 @@ __device__ __forceinline__ unsigned axis_bits(int v, int n, bool per, bool inarr
 // once per block.  ONE: a single run whose parameter block, step index and
 // front and charged-range addresses come in the launch, so that the first
 // loads of a block are one round trip instead of a chain of dependent ones.
-template <int D, int V, bool LOR, bool ONE>
+template <int D, int V, int LOR, bool ONE>
 __global__ __launch_bounds__(TPB) void k_fields(Group g, std::conditional_t<ONE, Inst, NoInst> one) {
   using T = TileT<D, V>;
   constexpr int H = 2;
@@ -1548,7 +1548,7 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g, std::conditional_t<ONE,
       if (D >= 3) cu -= Cz * (sB[1][l] - sB[1][l - LZ]);
       float src = cu - jr[k][0];
       if (lorT && lh.y != 0.0f) src -= lor_step(LOR_PTRS(I, par, 0), gl, lh, sE[0][l], own);
-      if (lorT && lh.w != 0.0f)
+      if (LOR == 2 && lorT && lh.w != 0.0f)
         sE[0][l] = kerr_update(sE[0][l], sieh[qx], src, lh.w);
       else
         sE[0][l] += sieh[qx] * src;
@@ -1558,7 +1558,7 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g, std::conditional_t<ONE,
       if (D >= 3) cu += Cz * (sB[0][l] - sB[0][l - LZ]);
       float src = cu - jr[k][1];
       if (lorT && ln.y != 0.0f) src -= lor_step(LOR_PTRS(I, par, 1), gl, ln, sE[1][l], own);
-      if (lorT && ln.w != 0.0f)
+      if (LOR == 2 && lorT && ln.w != 0.0f)
         sE[1][l] = kerr_update(sE[1][l], sien[qx], src, ln.w);
       else
         sE[1][l] += sien[qx] * src;
@@ -1568,7 +1568,7 @@ __global__ __launch_bounds__(TPB) void k_fields(Group g, std::conditional_t<ONE,
       if (D >= 2) cu -= Cy * (sB[0][l] - sB[0][l - LY]);
       float src = cu - jr[k][2];
       if (lorT && ln.y != 0.0f) src -= lor_step(LOR_PTRS(I, par, 2), gl, ln, sE[2][l], own);
-      if (lorT && ln.w != 0.0f)
+      if (LOR == 2 && lorT && ln.w != 0.0f)
         sE[2][l] = kerr_update(sE[2][l], sien[qx], src, ln.w);
       else
         sE[2][l] += sien[qx] * src;
@@ -1822,7 +1822,7 @@ constexpr int ZNP = ZRX * ZRY;
 constexpr int ZPT = ZNP / TPB;                        // points per thread
 static_assert(ZNP % TPB == 0 && ZRX == 64, "plane layout");
 
-template <bool ONE, bool LOR>
+template <bool ONE, int LOR>
 __global__ __launch_bounds__(TPB, 4) void k_fields_z(Group g, std::conditional_t<ONE, Inst, NoInst> one) {
   constexpr int LY = ZRX;
   __shared__ float sEa[3][ZNP], sEb[3][ZNP], sBa[3][ZNP], sBb[3][ZNP];
@@ -2055,7 +2055,7 @@ __global__ __launch_bounds__(TPB, 4) void k_fields_z(Group g, std::conditional_t
           cu -= Cz * (cB[1][l] - bh1[p]);
           float src = cu - jc[p][0];
           if (lorT && slh[qx].y != 0.0f) src -= lor_step(LOR_PTRS(I, par, 0), gl, slh[qx], cE[0][l], own);
-          if (lorT && slh[qx].w != 0.0f)
+          if (LOR == 2 && lorT && slh[qx].w != 0.0f)
             cE[0][l] = kerr_update(cE[0][l], sieh[qx], src, slh[qx].w);
           else
             cE[0][l] += sieh[qx] * src;
@@ -2065,7 +2065,7 @@ __global__ __launch_bounds__(TPB, 4) void k_fields_z(Group g, std::conditional_t
           cu += Cz * (cB[0][l] - bh0[p]);
           float src = cu - jc[p][1];
           if (lorT && sln[qx].y != 0.0f) src -= lor_step(LOR_PTRS(I, par, 1), gl, sln[qx], cE[1][l], own);
-          if (lorT && sln[qx].w != 0.0f)
+          if (LOR == 2 && lorT && sln[qx].w != 0.0f)
             cE[1][l] = kerr_update(cE[1][l], sien[qx], src, sln[qx].w);
           else
             cE[1][l] += sien[qx] * src;
@@ -2075,7 +2075,7 @@ __global__ __launch_bounds__(TPB, 4) void k_fields_z(Group g, std::conditional_t
           cu -= Cy * (cB[0][l] - cB[0][l - LY]);
           float src = cu - jc[p][2];
           if (lorT && sln[qx].y != 0.0f) src -= lor_step(LOR_PTRS(I, par, 2), gl, sln[qx], cE[2][l], own);
-          if (lorT && sln[qx].w != 0.0f)
+          if (LOR == 2 && lorT && sln[qx].w != 0.0f)
             cE[2][l] = kerr_update(cE[2][l], sien[qx], src, sln[qx].w);
           else
             cE[2][l] += sien[qx] * src;
@@ -2958,10 +2958,12 @@ void launch_sort(const Group& gp, const Group& gscan, int D, hipStream_t s, Stam
 }
 #define FIELDS_V(DD, V)                                \
   do {                                                 \
-    if (g.lor)                                         \
-      ONE_OR_GROUP(k_fields, TPB, DD, V, true);        \
+    if (g.lor == 2)                                    \
+      ONE_OR_GROUP(k_fields, TPB, DD, V, 2);           \
+    else if (g.lor)                                    \
+      ONE_OR_GROUP(k_fields, TPB, DD, V, 1);           \
     else                                               \
-      ONE_OR_GROUP(k_fields, TPB, DD, V, false);       \
+      ONE_OR_GROUP(k_fields, TPB, DD, V, 0);           \
   } while (0)
 void launch_fields(const Group& g, int D, int variant, hipStream_t s, Stamp st) {
   const bool one = g.n == 1 && g.host && g.front && g.xext && g.step >= 0;
@@ -2974,14 +2976,18 @@ void launch_fields(const Group& g, int D, int variant, hipStream_t s, Stamp st) 
     case 6: DISPATCH_D(D, FIELDS_V(DD, 6)); break;
     case kMarchVariant:
       if (D == 3) {
-        if (one && g.lor)
-          GO((k_fields_z<true, true>), g.blocks, TPB, s, st.start, st.stop, g, *g.host);
+        if (one && g.lor == 2)
+          GO((k_fields_z<true, 2>), g.blocks, TPB, s, st.start, st.stop, g, *g.host);
+        else if (one && g.lor)
+          GO((k_fields_z<true, 1>), g.blocks, TPB, s, st.start, st.stop, g, *g.host);
         else if (one)
-          GO((k_fields_z<true, false>), g.blocks, TPB, s, st.start, st.stop, g, *g.host);
+          GO((k_fields_z<true, 0>), g.blocks, TPB, s, st.start, st.stop, g, *g.host);
+        else if (g.lor == 2)
+          GO((k_fields_z<false, 2>), g.blocks, TPB, s, st.start, st.stop, g, NoInst{});
         else if (g.lor)
-          GO((k_fields_z<false, true>), g.blocks, TPB, s, st.start, st.stop, g, NoInst{});
+          GO((k_fields_z<false, 1>), g.blocks, TPB, s, st.start, st.stop, g, NoInst{});
         else
-          GO((k_fields_z<false, false>), g.blocks, TPB, s, st.start, st.stop, g, NoInst{});
+          GO((k_fields_z<false, 0>), g.blocks, TPB, s, st.start, st.stop, g, NoInst{});
         break;
       }
       [[fallthrough]];
@@ -3000,7 +3006,7 @@ int field_tiles(int D, int variant, int Px, int Py, int Pz) {
       int dev = 0, bpc = 0;
       hipDeviceProp_t pr{};
       if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&pr, dev) == hipSuccess &&
-          hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, k_fields_z<true, false>, TPB, 0) == hipSuccess && bpc > 0)
+          hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, k_fields_z<true, 0>, TPB, 0) == hipSuccess && bpc > 0)
         slots = bpc * pr.multiProcessorCount;
       else
         slots = 1024;

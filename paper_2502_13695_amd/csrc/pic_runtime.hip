@@ -68,6 +68,7 @@ struct Layout {
   // with an oscillator (lx0 >= lx1: none, nothing allocated)
   size_t o_Q[2][3], o_Kp[2][3], o_lor_half, o_lor_node;
   int lx0, lx1;
+  bool kerr = false;   // some Kerr term inside [lx0, lx1)
   // binary collisions: per-cell counts and starts, fill counters, scan block
   // sums, slots ordered by cell and their pairing keys (empty without collisions)
   size_t o_ccnt, o_cfill, o_cbsum, o_cidx, o_ckey, o_cact, o_mrank;
@@ -85,6 +86,9 @@ struct Layout {
   size_t o_probe;    // scratch for table probes
   size_t total;
 };
+
+// the field update's dispersive variant of a layout (Group::lor)
+static int disp_mode(const Layout& L) { return L.lx0 < L.lx1 ? (L.kerr ? 2 : 1) : 0; }
 
 // Device counters.  Words that every block of a launch reads (the step of a
 // batch member, the charged region) sit on cache lines of their own, apart
@@ -175,6 +179,8 @@ pic_status plan(const pic_config* cfg, const Canon& c, const std::vector<TableHo
       L->lx0 = std::min(L->lx0, (int)(i + G));
       L->lx1 = std::max(L->lx1, (int)(i + G + 1));
     }
+    auto kerr = [&](int m) { return m >= 0 && c.mats[m].chi3 != 0.0f; };
+    if ((i < c.n[0] && kerr(c.mat_cell[i])) || kerr(c.mat_node[i])) L->kerr = true;
   }
   const size_t fq = L->lx0 < L->lx1 ? f : 0;
   for (int par = 0; par < 2; ++par)
@@ -298,7 +304,7 @@ struct pic_batch {
   struct Class {
     int D, order, tile = 0;
     bool per = false;   // periodic transverse axes
-    bool lor = false;   // some member has a Lorentz medium
+    int lor = 0;        // dispersive variant: the largest of the members' (Group::lor)
     std::vector<pic_ctx*> ms;
     Inst* d_insts = nullptr;
     int* d_off = nullptr;   // 4 phases x (n + 1)
@@ -392,7 +398,7 @@ Group single(pic_ctx* c, int phase, int nb) {
   g.front = &c->d_ctr->front;
   g.xext = c->d_ctr->xext;
   g.host = &c->h;
-  g.lor = c->L.lx0 < c->L.lx1;
+  g.lor = disp_mode(c->L);
   return g;
 }
 
@@ -530,7 +536,7 @@ void enqueue_step(pic_ctx* c) {
     gv.front = &c->d_ctr->front;
     gv.xext = c->d_ctr->xext;
     gv.host = &c->h;
-    gv.lor = c->L.lx0 < c->L.lx1;
+    gv.lor = disp_mode(c->L);
     launch_fields(gv, D, v, s, Stamp{c->tune_ev[v][r][0], c->tune_ev[v][r][1]});
     if (rebuild_due(c)) launch_win_rebuild(c->h, c->L.wsz, s);
     if (--c->tune_left == 0) finish_tuning(c);
@@ -1341,7 +1347,7 @@ pic_status pic_autotune(pic_ctx* c, int32_t reps) {
       gr.front = &c->d_ctr->front;
       gr.xext = c->d_ctr->xext;
       gr.host = &c->h;
-      gr.lor = c->L.lx0 < c->L.lx1;
+      gr.lor = disp_mode(c->L);
       launch_fields(gr, D, v, s);   // warm
       HIP_OK(hipEventRecord(e0, s));
       for (int r = 0; r < reps; ++r) launch_fields(gr, D, v, s);
@@ -1858,7 +1864,7 @@ static pic_status batch_rebuild(pic_batch* b) {
       cl->per = c->canon.per[1];
     }
     cl->ms.push_back(c);
-    cl->lor = cl->lor || c->L.lx0 < c->L.lx1;
+    cl->lor = std::max(cl->lor, disp_mode(c->L));
   }
   // persistent push/sort blocks: shared out over the members (every member
   // keeps at least 16; its grid-stride loops cover any particle count)
