@@ -600,8 +600,10 @@ int col_scan_blocks(int n) { return (n + SCAN_B - 1) / SCAN_B; }
 void launch_collide(const Inst& I, const ColBufs& b, int step, hipStream_t s, Stamp st) {
   const int n = b.ncell + 1;
   const int nb = col_scan_blocks(n);
-  // grid-stride passes over the charged slots: one thread per slot up to 4096 blocks
-  const int slots = 256 * std::min(4096, std::max(1, (I.capacity + 255) / 256));
+  // grid-stride passes over the charged slots: one thread per slot up to 65536
+  // blocks (each slot's loads and atomic are one dependent chain; more threads
+  // keep more chains in flight)
+  const int slots = 256 * std::min(65536, std::max(1, (I.capacity + 255) / 256));
   if (st.start)
     hipExtLaunchKernelGGL(k_col_clear, dim3((n + 255) / 256), dim3(256), 0, s, st.start, nullptr, 0, b);
   else
