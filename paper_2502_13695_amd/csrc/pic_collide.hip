@@ -175,20 +175,20 @@ __device__ __forceinline__ double unif(uint32_t w) { return ((double)w + 0.5) * 
 // above.  FP64: small deflections take sin(chi) from 1 - cos(chi), which FP32
 // would leave with a few digits only.
 __device__ double cos_chi(double s, double U) {
-  if (s < 0.1) return fmax(-1.0, 1.0 + s * log(U));
-  if (s < 6.0) {
-    double ainv, A;
-    if (s < 3.0) {
-      ainv = 0.0056958 + s * (0.9560202 + s * (-0.508139 + s * (0.47913906 + s * (-0.12788975 + s * 0.02389567))));
-      A = 1.0 / ainv;
-    } else {
-      A = 3.0 * exp(-s);
-      ainv = 1.0 / A;
-    }
-    // exp(-A) + 2 U sinh(A) = exp(-A) (1 - U) + U exp(A)
-    const double eA = exp(A);
-    return fmin(1.0, fmax(-1.0, ainv * log((1.0 - U) / eA + U * eA)));
-  }
+  // one exp(-s), one division, one exp(A) and one log per lane whatever its
+  // range, so that lanes of a wave in different ranges do not run each
+  // range's transcendentals in turn (same operations per range as written out)
+  const bool small = s < 0.1, fit = s < 3.0;
+  const double poly = 0.0056958 + s * (0.9560202 + s * (-0.508139 + s * (0.47913906 + s * (-0.12788975 + s * 0.02389567))));
+  const double e3 = fit ? 1.0 : 3.0 * exp(-s);
+  const double d = fit ? poly : e3;
+  const double r = 1.0 / d;
+  const double ainv = fit ? poly : r, A = fit ? r : e3;
+  const double eA = small || s >= 6.0 ? 1.0 : exp(A);
+  const double arg = small ? U : (1.0 - U) / eA + U * eA;
+  const double L = log(arg);
+  if (small) return fmax(-1.0, 1.0 + s * L);
+  if (s < 6.0) return fmin(1.0, fmax(-1.0, ainv * L));
   return 2.0 * U - 1.0;
 }
 
