@@ -678,22 +678,44 @@ __device__ __forceinline__ void push_body(const IT& I, const PushFields& f, cons
   gp(I.pu2)[q] = uz;
 }
 
-// One charged particle (slot p).  TILED: the block holds the LDS windows of
-// the tile with origin (tx0, ty0, tz0); a particle that started the step
-// outside that tile goes through HBM and is counted as a drifter.
+// A charged particle's state as the push reads it (kind DEAD: no particle).
+struct PState {
+  unsigned q;
+  uint8_t kind;
+  uint32_t pc, t0, t1, t2;
+  float ux, uy, uz;
+};
+
+template <int D, class IT>
+__device__ __forceinline__ PState load_particle(const IT& I, int p, bool valid) {
+  PState s{};
+  s.q = (unsigned)p;
+  s.kind = valid ? gp(I.pkind)[s.q] : DEAD;
+  if (s.kind == DEAD) return s;
+  s.pc = gp(I.pcell)[s.q];
+  s.t0 = gp(I.po0)[s.q];
+  s.t1 = D >= 2 ? gp(I.po1)[s.q] : 0u;
+  s.t2 = D >= 3 ? gp(I.po2)[s.q] : 0u;
+  s.ux = gp(I.pu0)[s.q];
+  s.uy = gp(I.pu1)[s.q];
+  s.uz = gp(I.pu2)[s.q];
+  return s;
+}
+
+// One charged particle (its state loaded).  TILED: the block holds the LDS
+// windows of the tile with origin (tx0, ty0, tz0); a particle that started the
+// step outside that tile goes through HBM and is counted as a drifter.
 template <int D, int ORDER, bool PY, bool PZ, bool TILED, class IT>
-__device__ __forceinline__ void push_one(const IT& I, const PushFields& f, const float* sF,
-                                         const GSink<PY, PZ>& gs, const LSink<D>& ls, int tx0, int ty0,
-                                         int tz0, int p, bool valid, int& xlo, int& xhi) {
-  const unsigned q = (unsigned)p;
-  const uint8_t kind = valid ? gp(I.pkind)[q] : DEAD;
-  if (kind == DEAD) return;
+__device__ __forceinline__ void push_loaded(const IT& I, const PushFields& f, const float* sF,
+                                            const GSink<PY, PZ>& gs, const LSink<D>& ls, int tx0, int ty0,
+                                            int tz0, const PState& st, int& xlo, int& xhi) {
+  if (st.kind == DEAD) return;
+  const unsigned q = st.q;
+  const uint8_t kind = st.kind;
   int ci, cj, ck;
-  unpack_cell(D, gp(I.pcell)[q], ci, cj, ck);
-  const uint32_t t0 = gp(I.po0)[q];
-  const uint32_t t1 = D >= 2 ? gp(I.po1)[q] : 0u;
-  const uint32_t t2 = D >= 3 ? gp(I.po2)[q] : 0u;
-  const float ux = gp(I.pu0)[q], uy = gp(I.pu1)[q], uz = gp(I.pu2)[q];
+  unpack_cell(D, st.pc, ci, cj, ck);
+  const uint32_t t0 = st.t0, t1 = st.t1, t2 = st.t2;
+  const float ux = st.ux, uy = st.uy, uz = st.uz;
   if (TILED) {
     bool in = ci >= tx0 && ci < tx0 + ptile_ext(D, 0);
     if (D >= 2) in = in && cj >= ty0 && cj < ty0 + ptile_ext(D, 1);
@@ -711,6 +733,14 @@ __device__ __forceinline__ void push_one(const IT& I, const PushFields& f, const
     push_body<D, ORDER, PY, PZ, false>(I, f, sF, 0, 0, 0, gs, ls, q, kind, ci, cj, ck, t0, t1, t2, ux, uy,
                                        uz, xlo, xhi);
   }
+}
+
+// One charged particle (slot p): load, then push.
+template <int D, int ORDER, bool PY, bool PZ, bool TILED, class IT>
+__device__ __forceinline__ void push_one(const IT& I, const PushFields& f, const float* sF,
+                                         const GSink<PY, PZ>& gs, const LSink<D>& ls, int tx0, int ty0,
+                                         int tz0, int p, bool valid, int& xlo, int& xhi) {
+  push_loaded<D, ORDER, PY, PZ, TILED>(I, f, sF, gs, ls, tx0, ty0, tz0, load_particle<D>(I, p, valid), xlo, xhi);
 }
 
 // Slot of particle i of a work item: first the sorted range [lo, hi), then the
@@ -777,6 +807,10 @@ __global__ __launch_bounds__(push_tpb(D), D == 3 ? 4 : 1) void k_push(Group g, s
     const int tz0 = D >= 3 ? (t / (I.ntile[0] * I.ntile[1])) * ptile_ext(D, 2) : 0;
     const LSink<D> ls{sJ, tx0 - PT_LO, D >= 2 ? ty0 - PT_LO : 0, D >= 3 ? tz0 - PT_LO : 0,
                       (double)I.jscale};
+    // the first pass's particles load while the windows are cleared and staged
+    const PState first = load_particle<D>(I, threadIdx.x < ntot ? item_slot(threadIdx.x, ch.y, n_sorted, ch.w, nbirth,
+                                                                                bcap) : 0,
+                                          (int)threadIdx.x < ntot);
     for (int e = threadIdx.x; e < 3 * PWin<D>::N; e += NT) sJ[e] = 0ull;
     // field window: nodes tile - 1 .. tile + T + 1 (periodic axes wrapped;
     // nodes outside the padded arrays, never read, are zero).  Threads walk
@@ -811,7 +845,8 @@ __global__ __launch_bounds__(push_tpb(D), D == 3 ? 4 : 1) void k_push(Group g, s
       sF[5 * FWin<D>::N + e] = ok ? gp(f.B2)[o] : 0.0f;
     }
     __syncthreads();
-    for (int i0 = 0; i0 < ntot; i0 += NT) {
+    push_loaded<D, ORDER, PY, PZ, true>(I, f, sF, gs, ls, tx0, ty0, tz0, first, xlo, xhi);
+    for (int i0 = NT; i0 < ntot; i0 += NT) {
       const int i = i0 + threadIdx.x;
       const int p = i < ntot ? item_slot(i, ch.y, n_sorted, ch.w, nbirth, bcap) : 0;
       push_one<D, ORDER, PY, PZ, true>(I, f, sF, gs, ls, tx0, ty0, tz0, p, i < ntot, xlo, xhi);
