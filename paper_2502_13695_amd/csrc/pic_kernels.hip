@@ -735,12 +735,43 @@ __device__ __forceinline__ void push_loaded(const IT& I, const PushFields& f, co
   }
 }
 
-// One charged particle (slot p): load, then push.
+// One charged particle (slot p): load, then push.  In 1D and 2D the loads
+// stay inside the push as one body: the split into load_particle and
+// push_loaded costs the 2D push 10 % (different registers and schedule).
 template <int D, int ORDER, bool PY, bool PZ, bool TILED, class IT>
 __device__ __forceinline__ void push_one(const IT& I, const PushFields& f, const float* sF,
                                          const GSink<PY, PZ>& gs, const LSink<D>& ls, int tx0, int ty0,
                                          int tz0, int p, bool valid, int& xlo, int& xhi) {
-  push_loaded<D, ORDER, PY, PZ, TILED>(I, f, sF, gs, ls, tx0, ty0, tz0, load_particle<D>(I, p, valid), xlo, xhi);
+  if (D == 3) {
+    push_loaded<D, ORDER, PY, PZ, TILED>(I, f, sF, gs, ls, tx0, ty0, tz0, load_particle<D>(I, p, valid), xlo, xhi);
+    return;
+  }
+  const unsigned q = (unsigned)p;
+  const uint8_t kind = valid ? gp(I.pkind)[q] : DEAD;
+  if (kind == DEAD) return;
+  int ci, cj, ck;
+  unpack_cell(D, gp(I.pcell)[q], ci, cj, ck);
+  const uint32_t t0 = gp(I.po0)[q];
+  const uint32_t t1 = D >= 2 ? gp(I.po1)[q] : 0u;
+  const uint32_t t2 = D >= 3 ? gp(I.po2)[q] : 0u;
+  const float ux = gp(I.pu0)[q], uy = gp(I.pu1)[q], uz = gp(I.pu2)[q];
+  if (TILED) {
+    bool in = ci >= tx0 && ci < tx0 + ptile_ext(D, 0);
+    if (D >= 2) in = in && cj >= ty0 && cj < ty0 + ptile_ext(D, 1);
+    if (D >= 3) in = in && ck >= tz0 && ck < tz0 + ptile_ext(D, 2);
+    if (in) {
+      push_body<D, ORDER, PY, PZ, true>(I, f, sF, tx0 - 1, ty0 - 1, tz0 - 1, gs, ls, q, kind, ci, cj, ck,
+                                        t0, t1, t2, ux, uy, uz, xlo, xhi);
+    } else {
+      const unsigned long long m = __ballot(1);
+      if ((threadIdx.x & 63) == __ffsll((long long)m) - 1) atomicAdd(I.sctl + SC_NDRIFT, __popcll(m));
+      push_body<D, ORDER, PY, PZ, false>(I, f, sF, 0, 0, 0, gs, ls, q, kind, ci, cj, ck, t0, t1, t2, ux,
+                                         uy, uz, xlo, xhi);
+    }
+  } else {
+    push_body<D, ORDER, PY, PZ, false>(I, f, sF, 0, 0, 0, gs, ls, q, kind, ci, cj, ck, t0, t1, t2, ux, uy,
+                                       uz, xlo, xhi);
+  }
 }
 
 // Slot of particle i of a work item: first the sorted range [lo, hi), then the
@@ -807,10 +838,12 @@ __global__ __launch_bounds__(push_tpb(D), D == 3 ? 4 : 1) void k_push(Group g, s
     const int tz0 = D >= 3 ? (t / (I.ntile[0] * I.ntile[1])) * ptile_ext(D, 2) : 0;
     const LSink<D> ls{sJ, tx0 - PT_LO, D >= 2 ? ty0 - PT_LO : 0, D >= 3 ? tz0 - PT_LO : 0,
                       (double)I.jscale};
-    // the first pass's particles load while the windows are cleared and staged
-    const PState first = load_particle<D>(I, threadIdx.x < ntot ? item_slot(threadIdx.x, ch.y, n_sorted, ch.w, nbirth,
-                                                                                bcap) : 0,
-                                          (int)threadIdx.x < ntot);
+    // 3D: the first pass's particles load while the windows are cleared and
+    // staged (in 2D the registers this holds cost more than the overlap gains)
+    PState first{};
+    if (D == 3)
+      first = load_particle<D>(I, (int)threadIdx.x < ntot ? item_slot(threadIdx.x, ch.y, n_sorted, ch.w, nbirth, bcap) : 0,
+                               (int)threadIdx.x < ntot);
     for (int e = threadIdx.x; e < 3 * PWin<D>::N; e += NT) sJ[e] = 0ull;
     // field window: nodes tile - 1 .. tile + T + 1 (periodic axes wrapped;
     // nodes outside the padded arrays, never read, are zero).  Threads walk
@@ -845,8 +878,8 @@ __global__ __launch_bounds__(push_tpb(D), D == 3 ? 4 : 1) void k_push(Group g, s
       sF[5 * FWin<D>::N + e] = ok ? gp(f.B2)[o] : 0.0f;
     }
     __syncthreads();
-    push_loaded<D, ORDER, PY, PZ, true>(I, f, sF, gs, ls, tx0, ty0, tz0, first, xlo, xhi);
-    for (int i0 = NT; i0 < ntot; i0 += NT) {
+    if (D == 3) push_loaded<D, ORDER, PY, PZ, true>(I, f, sF, gs, ls, tx0, ty0, tz0, first, xlo, xhi);
+    for (int i0 = D == 3 ? NT : 0; i0 < ntot; i0 += NT) {
       const int i = i0 + threadIdx.x;
       const int p = i < ntot ? item_slot(i, ch.y, n_sorted, ch.w, nbirth, bcap) : 0;
       push_one<D, ORDER, PY, PZ, true>(I, f, sF, gs, ls, tx0, ty0, tz0, p, i < ntot, xlo, xhi);
